@@ -1,0 +1,13 @@
+"""Reference CPU oracle for the D2Q9 elastic-solid lattice Boltzmann scheme.
+
+TEST INFRASTRUCTURE. Everything under ``oracle/`` exists to check the GPU
+library, never to stand in for it: only ``tests/``, the package smoke check and
+the CPU-baseline leg of ``bench.py`` may import, call, link or run it. It shares
+no code with ``paper_2009_06404_amd`` and imports nothing from it.
+
+* ``lbm_oracle.c`` / :mod:`oracle.stepper` -- the scheme itself (FP64, the
+  paper's collide-then-push-stream form of eq. LBGK, Sec. 2 and 6).
+* :mod:`oracle.theory` -- von Neumann matrix (Sec. 4), wave speeds (Sec. 2),
+  Rayleigh-wave root (Sec. 7).
+* :mod:`oracle.spectral` -- the Fourier / Crank-Nicolson reference of App. B.
+"""
