@@ -1,0 +1,157 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused D2Q9 elastic-wave LBM step on one MI355X.
+
+Workload (default): the large plain configuration -- 4096 x 4096 FP32 grid,
+free surface on top, 96-cell absorbing layers on the other three sides (rigid
+bottom behind its layer, periodic sides behind theirs), homogeneous solid with
+Poisson ratio 0.33, one vertical Gaussian x Ricker source 20 cells below the
+surface, 4096 surface receivers recording v_y. A step is one time step of the
+whole grid (pull streaming with the wall rules, moments, density gradient,
+source and sponge, collision, receivers) in one fused kernel launch.
+
+Prints ONE JSON line: GLUPS (cell updates per second / 1e9), the roofline of
+the step kernel (HBM-bound; algorithmic bytes = 9 reads + 9 writes per cell),
+and the FP64 oracle timed on this host's cores on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GLUPS (D2Q9 cell updates/s) and % HBM roofline; batched & adjoint vs plain"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("paper_2009_06404_amd/csrc/lbm_kernels.hip",
+                  "paper_2009_06404_amd/csrc/lbm_internal.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_kernel_plain_large.txt")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """Bytes per launch from the committed rocprofv3 counter summary, or None
+    when the kernel source has changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].strip()
+            if "=" in line:
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_hash") != kernel_hash():
+        return None
+    try:
+        return float(vals["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(problem, target_s: float = 15.0):
+    """The FP64 oracle as it stands, on this host's cores, on the first steps
+    of the same workload; steps chosen so the sample takes ~target_s."""
+    from oracle import stepper
+    cells = problem.nx * problem.ny
+    t = time.perf_counter()
+    stepper.run(problem, nsteps=1, want_trace=False)
+    one = max(time.perf_counter() - t, 1e-3)
+    n = max(1, min(200, int(target_s / one)))
+    t = time.perf_counter()
+    stepper.run(problem, nsteps=n, want_trace=False)
+    el = time.perf_counter() - t
+    return {"value": cells * n / el / 1e9, "unit": "GLUPS", "cores": stepper.num_threads(),
+            "kind": "oracle",
+            "sample": f"{n} steps of the full {problem.nx}x{problem.ny} grid from the rest "
+                      f"state, FP64, OpenMP over rows ({el:.1f} s incl. setup)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=11900)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--n", type=int, default=4096, help="grid side")
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--rows", type=int, default=0)
+    ap.add_argument("--graph-chunk", type=int, default=100)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the slab decomposition over xGMI is a design note); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as w
+    from paper_2009_06404_amd import Solver
+
+    torch.cuda.set_device(0)
+    p = w.plain_large(n=args.n, dtype=args.dtype)
+    total = args.warmup + args.steps
+    s = Solver(p, dtype=args.dtype, trace_steps=total)
+    if args.autotune:
+        s.autotune()
+    launch = s.launch()
+    if args.waves or args.rows:
+        launch.update({k: v for k, v in (("waves", args.waves), ("rows", args.rows)) if v})
+    launch["graph_chunk"] = args.graph_chunk
+    s.set_launch(**launch)
+    launch = s.launch()
+
+    stream = torch.cuda.current_stream()
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    s.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    ok = s.check_finite()
+    s.close()
+
+    cells = p.nx * p.ny
+    esize = 4 if args.dtype == "f32" else 8
+    ms_step = ms / args.steps
+    glups = cells * args.steps / (ms / 1e3) / 1e9
+    alg_bytes = 18 * esize * cells                 # per launch: 9 loads + 9 stores per cell
+    achieved = alg_bytes / (ms_step / 1e3) / 1e9   # GB/s
+    traffic = measured_traffic() if (args.n == 4096 and args.dtype == "f32") else None
+    out = {
+        "metric": METRIC, "value": round(glups, 3), "unit": "GLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": f"plain_large {p.nx}x{p.ny} {args.dtype.upper()}: free surface top, "
+                               f"96-cell sponges (rigid bottom, periodic sides), nu=0.33, "
+                               f"vertical Ricker source at depth 20, {p.nx} surface receivers",
+                   "nx": p.nx, "ny": p.ny, "tau": p.tau, "launch": launch,
+                   "state_finite": bool(ok)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

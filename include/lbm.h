@@ -1,0 +1,185 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) D2Q9 elastic-wave lattice Boltzmann
+ * library (liblbm.so).
+ *
+ * The library advances the single-relaxation-time D2Q9 scheme for elastic
+ * waves in isotropic linear solids of Escande, Kolluru, Cleon & Sagaut
+ * (arXiv 2009.06404): BGK collision toward the elastic equilibrium (Sec. 2,
+ * eqs. equilibrium-solid and Pn) with the source of eq. S (elastic force from
+ * the centred density gradient of eq. FDrho plus a Gaussian x Ricker body
+ * force, Sec. 5) added through eq. Si, the absorbing-layer term of eq.
+ * MomentChainAbsorbing (Sec. 6.4), fused with pull streaming (eq. LBGK) and the
+ * periodic, rigid (bounce-back, eq. BB) and free-surface (anti-bounce-back,
+ * Sec. 6.2) boundary rules.
+ *
+ * Conventions.
+ *  - Lattice units dt = dx = 1. Cell (x, y): x is the column (fast index),
+ *    y the row; row 0 is the TOP edge and y grows with depth.
+ *  - Populations are perturbations about the rest state f = 0.
+ *  - Elastic coefficient per cell: kappa = b^2 (mu - lambda) / mu, i.e. the
+ *    paper's (mu - lambda)/rho0 with mu/rho0 = b^2 = 1/3 (Sec. 4). Only the
+ *    ratio lambda/mu enters; rho0 scales the recorded velocity v = j/rho0.
+ *  - The state at time t is the post-collision population set of step t-1;
+ *    at t = 0 it is zero. lbm_step(n) runs the steps t .. t+n-1.
+ *  - All arrays passed in are CALLER-OWNED; the library keeps non-owning
+ *    pointers and never frees them. Device arrays must stay valid and
+ *    unmodified by the caller while the context uses them.
+ *  - Every call after lbm_init is asynchronous on the HIP stream given to
+ *    lbm_init, except those documented as synchronous.
+ *  - Errors: a negative return value; lbm_last_error() then describes it.
+ *    Arguments are validated on the host before anything is enqueued; a call
+ *    that fails validation has no effect.
+ */
+#ifndef LBM_H_
+#define LBM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_ABI_VERSION 1
+
+typedef struct lbm_ctx lbm_ctx; /* opaque, owned by the library */
+
+enum {
+  LBM_OK = 0,
+  LBM_E_INVALID = -1,   /* argument out of range or inconsistent */
+  LBM_E_NOMEM = -2,     /* workspace too small or host allocation failed */
+  LBM_E_DEVICE = -3,    /* a HIP call failed */
+  LBM_E_NONFINITE = -4, /* the state holds NaN or Inf */
+  LBM_E_STATE = -5      /* call not valid in the context's current state */
+};
+
+enum { LBM_F32 = 0, LBM_F64 = 1 };
+
+/* Edge types (Sec. 6). PERIODIC must be paired (top with bottom, left with
+ * right). FREE is accepted on the top and bottom edges only. */
+enum { LBM_PERIODIC = 0, LBM_FREE = 1, LBM_RIGID = 2 };
+enum { LBM_EDGE_TOP = 0, LBM_EDGE_BOTTOM = 1, LBM_EDGE_LEFT = 2, LBM_EDGE_RIGHT = 3 };
+
+typedef struct {
+  int32_t nx, ny; /* >= 3 each */
+} lbm_grid;
+
+/* Boundary rules of one grid. rigid_row = -1: none; otherwise an internal
+ * rigid wall (bounce-back from both sides) between rows rigid_row-1 and
+ * rigid_row, 2 <= rigid_row <= ny-2. The centred density gradient is not
+ * taken across non-periodic edges or the internal wall: there the neighbour
+ * density is the linear extrapolation 2 rho_b - rho_in. A link that crosses a
+ * rigid and a free edge at once bounces back as rigid. */
+typedef struct {
+  int32_t edge[4];   /* LBM_PERIODIC / LBM_FREE / LBM_RIGID per LBM_EDGE_* */
+  int32_t rigid_row;
+} lbm_bc;
+
+/* Absorbing layers (Sec. 6.4): damping A(x, y) = max over edges e with
+ * d_e < thick[e] of profile[e][d_e], d_e = cells from edge e. Host arrays of
+ * length thick[e] (0 <= thick[e] <= the extent normal to the edge), copied
+ * during lbm_init. */
+typedef struct {
+  int32_t thick[4];
+  const double *profile[4];
+} lbm_sponge;
+
+/* Gaussian-in-space, Ricker-in-time body force (Sec. 5):
+ * F(x, t) = amp exp(-r^2 / (2 sigma^2)) R(t) (dir_x, dir_y), r measured with
+ * the minimum image along periodic axes, F = 0 for r > 9 sigma;
+ * R(t) = (1 - 2 a^2) exp(-a^2), a = pi (t - t0) / period, evaluated at the
+ * integer step index t of the collision. */
+typedef struct {
+  double x, y, sigma, dir_x, dir_y, amp, period, t0;
+} lbm_source;
+
+/* Launch configuration chosen by the autotuner or set by the caller. */
+typedef struct {
+  int32_t waves;      /* wavefronts per workgroup: 1, 2 or 4 (64 columns each) */
+  int32_t rows;       /* rows marched per workgroup */
+  int32_t graph_chunk;/* steps per captured HIP graph; 0 = direct launches */
+  int32_t reserved;
+} lbm_launch;
+
+/* Bytes of device workspace lbm_init needs for nbatch grids of the given
+ * sizes and dtype. Synchronous, host only. Returns LBM_OK or LBM_E_INVALID. */
+int lbm_workspace_bytes(const lbm_grid *grids, int32_t nbatch, int32_t dtype,
+                        size_t *bytes);
+
+/* Create a context for nbatch independent grids advanced together.
+ *  grids[nbatch], bc[nbatch], sponge[nbatch]: host arrays.
+ *  lam, mu, rho: DEVICE arrays of dtype holding the grids' row-major fields
+ *    packed one after the other (grid g starts at sum_{h<g} nx_h*ny_h).
+ *    0 <= nu = lam / (2 (lam + mu)) < 5/11 (Sec. 4) and mu, rho > 0 per cell.
+ *  tau > 1/2 (Sec. 3).
+ *  workspace: DEVICE memory of at least lbm_workspace_bytes, 256-B aligned,
+ *    owned by the caller and used exclusively by this context.
+ *  hip_stream: the hipStream_t all work is enqueued on (NULL = default).
+ * Synchronous (validates the fields on the device and waits for it). On
+ * success *ctx holds a context at time t = 0 with the rest state. */
+int lbm_init(lbm_ctx **ctx, const lbm_grid *grids, int32_t nbatch,
+             int32_t dtype, const void *lam, const void *mu, const void *rho,
+             double tau, const lbm_bc *bc, const lbm_sponge *sponge,
+             void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Replace the sources of grid g (host array, copied). Synchronous on the
+ * stream. Sources must lie inside the grid; sigma > 0, period > 0. */
+int lbm_set_sources(lbm_ctx *ctx, int32_t g, const lbm_source *src, int32_t n);
+
+/* Record v = j / rho0 at n receiver cells of grid g at every step.
+ *  xy: host int32 pairs (x, y), copied; cells inside the grid.
+ *  comp_mask: bit 0 records v_x, bit 1 records v_y (ncomp = popcount).
+ *  traces: DEVICE array of dtype, layout [max_steps][n][ncomp]; row k holds
+ *    step (t_now + k), where t_now is the context time at this call. Steps
+ *    beyond max_steps are not recorded. n = 0 removes the receivers. */
+int lbm_set_receivers(lbm_ctx *ctx, int32_t g, const int32_t *xy, int32_t n,
+                      int32_t comp_mask, void *traces, int64_t max_steps);
+
+/* Advance all grids n >= 0 steps. Asynchronous. */
+int lbm_step(lbm_ctx *ctx, int64_t n);
+
+/* Macroscopic fields of grid g at the current time t: DEVICE array of dtype,
+ * layout [6][ny][nx] = rho, j_x, j_y, P_xx, P_xy, P_yy (Sec. 2: P is the
+ * second moment, the stress with the opposite sign; j = sum f c + S/2 with
+ * the sponge solved implicitly). Asynchronous. */
+int lbm_moments(lbm_ctx *ctx, int32_t g, void *out6);
+
+int lbm_get_time(const lbm_ctx *ctx, int64_t *t);
+
+/* Copy the state of grid g (post-collision populations of step t-1,
+ * DEVICE [9][ny][nx] of dtype, direction order (0,0),(1,0),(0,1),(-1,0),
+ * (0,-1),(1,1),(-1,1),(-1,-1),(1,-1)) out of / into the context. set_state
+ * with g = -1 is invalid; the context time becomes t for all grids, and when
+ * t differs from the current time every grid's receiver trace restarts (row
+ * 0 records step t). Asynchronous. */
+int lbm_get_state(lbm_ctx *ctx, int32_t g, void *dst);
+int lbm_set_state(lbm_ctx *ctx, int32_t g, const void *src, int64_t t);
+
+/* Check every grid's state for NaN/Inf. Synchronous. Returns LBM_OK or
+ * LBM_E_NONFINITE. */
+int lbm_check_finite(lbm_ctx *ctx);
+
+/* Launch configuration in use, and a way to set it (waves in {1,2,4},
+ * rows >= 1, graph_chunk >= 0). */
+int lbm_get_launch(const lbm_ctx *ctx, lbm_launch *out);
+int lbm_set_launch(lbm_ctx *ctx, const lbm_launch *cfg);
+
+/* Time each candidate launch configuration on the live context (the state is
+ * saved and restored) and keep the fastest. steps: timed steps per candidate.
+ * Synchronous. */
+int lbm_autotune(lbm_ctx *ctx, int32_t steps, lbm_launch *chosen);
+
+/* Release the context's library-owned objects (device tables, graphs). Does
+ * not touch caller-owned memory. Safe on NULL. */
+int lbm_destroy(lbm_ctx *ctx);
+
+/* Description of the last error on the calling thread ("" if none). */
+const char *lbm_last_error(void);
+
+int lbm_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H_ */

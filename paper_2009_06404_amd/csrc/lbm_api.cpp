@@ -1,0 +1,910 @@
+// C ABI of liblbm.so: argument validation, workspace layout, device tables,
+// tile lists, launches, HIP-graph capture of the time loop and the autotuner.
+// The kernels are in lbm_kernels.hip and lbm_util.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(LBM_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+constexpr int kPitchAlign = 64;     // elements; rows start on 256-B (f32) boundaries
+constexpr int kXcds = 8;            // MI355X: 8 accelerator complex dies, L2 per die
+
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+  std::vector<int32_t> pitch;
+  std::vector<int64_t> plane, f_off, k_off;
+  int64_t f_elems = 0;   // one population buffer
+  int64_t k_elems = 0;   // kappa cell planes
+  size_t esize = 4;
+  size_t bytes() const {
+    return (size_t)round_up((2 * f_elems + k_elems) * (int64_t)esize, 256) + 256;
+  }
+};
+
+Layout make_layout(const lbm_grid *grids, int n, int dtype) {
+  Layout L;
+  L.esize = dtype == LBM_F64 ? 8 : 4;
+  for (int g = 0; g < n; ++g) {
+    const int32_t p = (int32_t)round_up(grids[g].nx, kPitchAlign);
+    const int64_t pl = (int64_t)p * grids[g].ny;
+    L.pitch.push_back(p);
+    L.plane.push_back(pl);
+    L.f_off.push_back(L.f_elems);
+    L.k_off.push_back(L.k_elems);
+    L.f_elems += 9 * pl;
+    L.k_elems += pl;
+  }
+  return L;
+}
+
+struct RecHost {
+  std::vector<int32_t> xy;
+  std::vector<double> scale;   // 1/rho0 at each receiver
+  int32_t comp_mask = 0;
+  void *trace = nullptr;
+  int64_t max_steps = 0;
+  int64_t t0 = 0;
+};
+
+template <typename T>
+struct DevBuf {
+  T *p = nullptr;
+  size_t n = 0;
+  hipError_t upload(const std::vector<T> &v, hipStream_t s) {
+    if (v.size() > n) {
+      if (p) hipFree(p);
+      p = nullptr;
+      n = 0;
+      hipError_t e = hipMalloc((void **)&p, std::max<size_t>(v.size(), 1) * sizeof(T));
+      if (e != hipSuccess) return e;
+      n = v.size();
+    }
+    if (!p) {
+      hipError_t e = hipMalloc((void **)&p, sizeof(T));
+      if (e != hipSuccess) return e;
+      n = 1;
+    }
+    if (v.empty()) return hipSuccess;
+    hipError_t e = hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+  }
+  void release() {
+    if (p) hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+};
+
+}  // namespace
+
+struct lbm_ctx {
+  int dtype = LBM_F32;
+  int nbatch = 0;
+  double tau = 1.0;
+  hipStream_t stream = nullptr;
+  Layout L;
+  std::vector<lbm_grid> grids;
+  std::vector<lbm_bc> bc;
+  std::vector<std::vector<double>> sponge;       // per grid, 4 edges concatenated
+  std::vector<std::array<int32_t, 4>> sp_thick;
+  std::vector<std::vector<lbm_source>> sources;
+  std::vector<RecHost> recs;
+  std::vector<int> kmode;
+  std::vector<double> kscalar;
+  const void *rho = nullptr;                     // caller's density field (receiver scale)
+  std::vector<int64_t> cell_off;                 // per grid offset into the packed fields
+  char *ws = nullptr;
+  char *fbuf[2] = {nullptr, nullptr};
+  char *kcells = nullptr;
+  int cur = 0;                                   // buffer holding f*(t-1)
+  int64_t t = 0;
+  // library-owned device tables
+  DevBuf<GridDev> d_grids;
+  DevBuf<TileDev> d_tiles;
+  DevBuf<char> d_krows;                          // dtype elements
+  DevBuf<char> d_sponge;                         // dtype elements
+  DevBuf<SourceDev> d_src;
+  DevBuf<int32_t> d_itab;
+  DevBuf<char> d_rtab;                           // dtype elements
+  DevBuf<int64_t> d_time;
+  std::vector<int64_t> krow_off;                 // per grid offset into d_krows
+  std::vector<int64_t> rscale_off;               // per grid offset into d_rtab
+  std::vector<char> rtab_host;
+  bool tables_dirty = true;
+  lbm_launch launch{4, 64, 0, 0};
+  int ntiles = 0;
+  // graph of graph_chunk steps for each starting buffer parity
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  int gchunk = 0;
+};
+
+namespace {
+
+void drop_graphs(lbm_ctx *c) {
+  for (int i = 0; i < 2; ++i)
+    if (c->gexec[i]) {
+      hipGraphExecDestroy(c->gexec[i]);
+      c->gexec[i] = nullptr;
+    }
+  c->gchunk = 0;
+}
+
+int validate_grid(const lbm_grid &g, const lbm_bc &b, const lbm_sponge *sp, int idx) {
+  char buf[256];
+  if (g.nx < 3 || g.ny < 3) {
+    snprintf(buf, sizeof buf, "grid %d: nx and ny must be >= 3 (got %d x %d)", idx, g.nx, g.ny);
+    return fail(LBM_E_INVALID, buf);
+  }
+  if ((int64_t)g.nx * g.ny > (int64_t)1 << 31) {
+    snprintf(buf, sizeof buf, "grid %d: more than 2^31 cells", idx);
+    return fail(LBM_E_INVALID, buf);
+  }
+  for (int e = 0; e < 4; ++e)
+    if (b.edge[e] < LBM_PERIODIC || b.edge[e] > LBM_RIGID) {
+      snprintf(buf, sizeof buf, "grid %d: unknown boundary type on edge %d", idx, e);
+      return fail(LBM_E_INVALID, buf);
+    }
+  if ((b.edge[LBM_EDGE_TOP] == LBM_PERIODIC) != (b.edge[LBM_EDGE_BOTTOM] == LBM_PERIODIC) ||
+      (b.edge[LBM_EDGE_LEFT] == LBM_PERIODIC) != (b.edge[LBM_EDGE_RIGHT] == LBM_PERIODIC)) {
+    snprintf(buf, sizeof buf, "grid %d: periodic edges must be paired", idx);
+    return fail(LBM_E_INVALID, buf);
+  }
+  if (b.edge[LBM_EDGE_LEFT] == LBM_FREE || b.edge[LBM_EDGE_RIGHT] == LBM_FREE) {
+    snprintf(buf, sizeof buf, "grid %d: a free surface is supported on the top/bottom edges only", idx);
+    return fail(LBM_E_INVALID, buf);
+  }
+  if (b.rigid_row != -1 && (b.rigid_row < 2 || b.rigid_row > g.ny - 2)) {
+    snprintf(buf, sizeof buf, "grid %d: rigid_row must be -1 or in [2, ny-2]", idx);
+    return fail(LBM_E_INVALID, buf);
+  }
+  if (sp) {
+    for (int e = 0; e < 4; ++e) {
+      const int ext = (e < 2) ? g.ny : g.nx;
+      if (sp->thick[e] < 0 || sp->thick[e] > ext) {
+        snprintf(buf, sizeof buf, "grid %d: sponge thickness on edge %d must be in [0, extent]", idx, e);
+        return fail(LBM_E_INVALID, buf);
+      }
+      if (sp->thick[e] > 0 && !sp->profile[e]) {
+        snprintf(buf, sizeof buf, "grid %d: missing sponge profile on edge %d", idx, e);
+        return fail(LBM_E_INVALID, buf);
+      }
+      for (int k = 0; k < sp->thick[e]; ++k)
+        if (!(sp->profile[e][k] >= 0.0) || !std::isfinite(sp->profile[e][k])) {
+          snprintf(buf, sizeof buf, "grid %d: sponge profile values must be finite and >= 0", idx);
+          return fail(LBM_E_INVALID, buf);
+        }
+    }
+  }
+  return LBM_OK;
+}
+
+// Tiles: columns [x0, x0 + 64*waves), rows [y0, y1). Blocks are handed to the
+// 8 dies round-robin by block id, so block b takes the (b/8)-th tile of the
+// die-contiguous chunk (b%8): neighbouring tiles, which share halo lines, run
+// on the same die and hit the same L2.
+std::vector<TileDev> build_tiles(const lbm_ctx *c, int waves, int rows) {
+  std::vector<TileDev> logical;
+  const int W = 64 * waves;
+  for (int g = 0; g < c->nbatch; ++g) {
+    const int nx = c->grids[g].nx, ny = c->grids[g].ny;
+    for (int y0 = 0; y0 < ny; y0 += rows)
+      for (int x0 = 0; x0 < nx; x0 += W) logical.push_back({g, x0, y0, std::min(y0 + rows, ny)});
+  }
+  const int64_t T = (int64_t)logical.size();
+  const int64_t per = (T + kXcds - 1) / kXcds;
+  std::vector<TileDev> phys((size_t)(per * kXcds), TileDev{-1, 0, 0, 0});
+  for (int64_t b = 0; b < per * kXcds; ++b) {
+    const int64_t j = b % kXcds, i = b / kXcds;
+    const int64_t l = j * per + i;
+    if (i < per && l < T) phys[(size_t)b] = logical[(size_t)l];
+  }
+  return phys;
+}
+
+lbm_launch default_launch(const lbm_ctx *c) {
+  int64_t cells = 0;
+  for (const auto &g : c->grids) cells += (int64_t)g.nx * g.ny;
+  lbm_launch l{4, 64, 0, 0};
+  // aim for at least ~8 workgroups per compute unit (256 CUs)
+  const int64_t want = 2048;
+  int64_t rows = cells / (256 * want);
+  rows = std::max<int64_t>(8, std::min<int64_t>(128, rows));
+  l.rows = (int)rows;
+  if (cells < 256 * 2048) {
+    l.waves = 1;
+    l.rows = std::max<int64_t>(4, std::min<int64_t>(64, cells / (64 * 1024)));
+  }
+  return l;
+}
+
+template <typename real>
+int commit_tables(lbm_ctx *c) {
+  const hipStream_t s = c->stream;
+  // sponge table (dtype) and per-grid offsets
+  std::vector<real> sponge;
+  std::vector<std::array<int32_t, 4>> sp_off(c->nbatch);
+  for (int g = 0; g < c->nbatch; ++g) {
+    int64_t k = 0;
+    for (int e = 0; e < 4; ++e) {
+      sp_off[g][e] = (int32_t)sponge.size();
+      for (int i = 0; i < c->sp_thick[g][e]; ++i) sponge.push_back((real)c->sponge[g][k + i]);
+      k += c->sp_thick[g][e];
+    }
+  }
+  if (sponge.empty()) sponge.push_back(real(0));
+  std::vector<char> sbytes(sponge.size() * sizeof(real));
+  memcpy(sbytes.data(), sponge.data(), sbytes.size());
+  HIP_TRY(c->d_sponge.upload(sbytes, s));
+  // sources
+  std::vector<SourceDev> src;
+  std::vector<int32_t> src_off(c->nbatch);
+  for (int g = 0; g < c->nbatch; ++g) {
+    src_off[g] = (int32_t)src.size();
+    for (const auto &q : c->sources[g])
+      src.push_back({q.x, q.y, q.sigma, q.dir_x, q.dir_y, q.amp, q.period, q.t0});
+  }
+  HIP_TRY(c->d_src.upload(src, s));
+  // receivers: per grid a row table, a dense row map of receiver ids and a
+  // chain for several receivers in one cell
+  std::vector<int32_t> itab;
+  std::vector<int64_t> rowtab_off(c->nbatch), rmap_off(c->nbatch), rnext_off(c->nbatch);
+  for (int g = 0; g < c->nbatch; ++g) {
+    const int nx = c->grids[g].nx, ny = c->grids[g].ny;
+    const RecHost &R = c->recs[g];
+    const int nrec = (int)R.xy.size() / 2;
+    rowtab_off[g] = (int64_t)itab.size();
+    std::vector<int32_t> rowslot(ny, -1);
+    int nslots = 0;
+    for (int r = 0; r < nrec; ++r) {
+      const int y = R.xy[2 * r + 1];
+      if (rowslot[y] < 0) rowslot[y] = nslots++;
+    }
+    itab.insert(itab.end(), rowslot.begin(), rowslot.end());
+    rmap_off[g] = (int64_t)itab.size();
+    std::vector<int32_t> rmap((size_t)nslots * nx, -1), rnext(nrec, -1);
+    for (int r = nrec - 1; r >= 0; --r) {
+      const int x = R.xy[2 * r], y = R.xy[2 * r + 1];
+      int32_t &head = rmap[(size_t)rowslot[y] * nx + x];
+      rnext[r] = head;
+      head = r;
+    }
+    itab.insert(itab.end(), rmap.begin(), rmap.end());
+    rnext_off[g] = (int64_t)itab.size();
+    itab.insert(itab.end(), rnext.begin(), rnext.end());
+  }
+  HIP_TRY(c->d_itab.upload(itab, s));
+  // 1/rho0 per receiver (dtype)
+  std::vector<real> rtab;
+  for (int g = 0; g < c->nbatch; ++g) {
+    c->rscale_off[g] = (int64_t)rtab.size();
+    for (double v : c->recs[g].scale) rtab.push_back((real)v);
+  }
+  if (rtab.empty()) rtab.push_back(real(0));
+  std::vector<char> rbytes(rtab.size() * sizeof(real));
+  memcpy(rbytes.data(), rtab.data(), rbytes.size());
+  HIP_TRY(c->d_rtab.upload(rbytes, s));
+  // grid descriptors
+  std::vector<GridDev> gd(c->nbatch);
+  for (int g = 0; g < c->nbatch; ++g) {
+    GridDev &d = gd[g];
+    memset(&d, 0, sizeof d);
+    d.nx = c->grids[g].nx;
+    d.ny = c->grids[g].ny;
+    d.pitch = c->L.pitch[g];
+    d.kmode = c->kmode[g];
+    d.f_off = c->L.f_off[g];
+    d.plane = c->L.plane[g];
+    for (int e = 0; e < 4; ++e) d.bc[e] = c->bc[g].edge[e];
+    d.rigid_row = c->bc[g].rigid_row;
+    d.nsrc = (int32_t)c->sources[g].size();
+    d.src_off = src_off[g];
+    d.kscalar = c->kscalar[g];
+    d.k_off = d.kmode == kKappaRows ? c->krow_off[g] : c->L.k_off[g];
+    for (int e = 0; e < 4; ++e) {
+      d.sp_thick[e] = c->sp_thick[g][e];
+      d.sp_off[e] = sp_off[g][e];
+    }
+    const RecHost &R = c->recs[g];
+    d.nrec = (int32_t)R.xy.size() / 2;
+    d.rowtab_off = rowtab_off[g];
+    d.rmap_off = rmap_off[g];
+    d.rnext_off = rnext_off[g];
+    d.rscale_off = c->rscale_off[g];
+    d.trace = R.trace;
+    d.trace_t0 = R.t0;
+    d.trace_max = R.max_steps;
+    d.comp_mask = R.comp_mask;
+    d.ncomp = (R.comp_mask & 1) + ((R.comp_mask >> 1) & 1);
+  }
+  HIP_TRY(c->d_grids.upload(gd, s));
+  c->tables_dirty = false;
+  return LBM_OK;
+}
+
+int commit(lbm_ctx *c) {
+  if (!c->tables_dirty) return LBM_OK;
+  drop_graphs(c);
+  return c->dtype == LBM_F64 ? commit_tables<double>(c) : commit_tables<float>(c);
+}
+
+int rebuild_tiles(lbm_ctx *c) {
+  std::vector<TileDev> tiles = build_tiles(c, c->launch.waves, c->launch.rows);
+  c->ntiles = (int)tiles.size();
+  HIP_TRY(c->d_tiles.upload(tiles, c->stream));
+  drop_graphs(c);
+  return LBM_OK;
+}
+
+template <typename real>
+StepArgs<real> make_args(lbm_ctx *c, int src_buf) {
+  StepArgs<real> a;
+  memset(&a, 0, sizeof a);
+  a.fin = reinterpret_cast<const real *>(c->fbuf[src_buf]);
+  a.fout = reinterpret_cast<real *>(c->fbuf[src_buf ^ 1]);
+  a.grids = c->d_grids.p;
+  a.tiles = c->d_tiles.p;
+  a.kappa_rows = reinterpret_cast<const real *>(c->d_krows.p);
+  a.kappa_cells = reinterpret_cast<const real *>(c->kcells);
+  a.sponge = reinterpret_cast<const real *>(c->d_sponge.p);
+  a.sources = c->d_src.p;
+  a.itab = c->d_itab.p;
+  a.rtab = reinterpret_cast<const real *>(c->d_rtab.p);
+  a.t = c->t;
+  a.t_dev = nullptr;
+  a.omega = (real)(1.0 / c->tau);
+  a.cforce = (real)(1.0 - 0.5 / c->tau);
+  a.mom = nullptr;
+  a.mom_grid = -1;
+  return a;
+}
+
+template <typename real>
+int step_direct(lbm_ctx *c, int64_t n) {
+  for (int64_t k = 0; k < n; ++k) {
+    StepArgs<real> a = make_args<real>(c, c->cur);
+    HIP_TRY(launch_step<real>(a, c->launch.waves, c->ntiles, kModeStep, c->stream));
+    c->cur ^= 1;
+    c->t += 1;
+  }
+  return LBM_OK;
+}
+
+// Capture graph_chunk (even) steps reading the time from the device counter,
+// followed by a node that advances the counter.
+template <typename real>
+int build_graphs(lbm_ctx *c, int chunk) {
+  drop_graphs(c);
+  for (int parity = 0; parity < 2; ++parity) {
+    hipStream_t cs;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t graph;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      hipStreamDestroy(cs);
+      return fail(LBM_E_DEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+    }
+    int buf = parity;
+    for (int k = 0; k < chunk; ++k) {
+      StepArgs<real> a = make_args<real>(c, buf);
+      a.t = k;
+      a.t_dev = c->d_time.p;
+      launch_step<real>(a, c->launch.waves, c->ntiles, kModeStep, cs);
+      buf ^= 1;
+    }
+    launch_add_time(c->d_time.p, chunk, cs);
+    e = hipStreamEndCapture(cs, &graph);
+    if (e != hipSuccess) {
+      hipStreamDestroy(cs);
+      return fail(LBM_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(&c->gexec[parity], graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    hipStreamDestroy(cs);
+    if (e != hipSuccess) return fail(LBM_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  c->gchunk = chunk;
+  return LBM_OK;
+}
+
+template <typename real>
+int step_impl(lbm_ctx *c, int64_t n) {
+  int rc = commit(c);
+  if (rc) return rc;
+  const int chunk = c->launch.graph_chunk;
+  if (chunk > 0 && n >= chunk) {
+    if (c->gchunk != chunk) {
+      rc = build_graphs<real>(c, chunk);
+      if (rc) return rc;
+    }
+    HIP_TRY(launch_set_time(c->d_time.p, c->t, c->stream));
+    while (n >= chunk) {
+      HIP_TRY(hipGraphLaunch(c->gexec[c->cur], c->stream));
+      c->t += chunk;   // chunk is even: the state returns to the same buffer
+      n -= chunk;
+    }
+  }
+  return step_direct<real>(c, n);
+}
+
+template <typename real>
+int init_fields(lbm_ctx *c, const void *lam, const void *mu, const void *rho) {
+  const hipStream_t s = c->stream;
+  int *d_bad = nullptr, *d_rows = nullptr;
+  int64_t maxny = 0;
+  for (auto &g : c->grids) maxny = std::max<int64_t>(maxny, g.ny);
+  HIP_TRY(hipMalloc((void **)&d_bad, sizeof(int)));
+  HIP_TRY(hipMalloc((void **)&d_rows, maxny * sizeof(int)));
+  std::vector<real> krows_all;
+  int64_t cell_off = 0;
+  int rc = LBM_OK;
+  for (int g = 0; g < c->nbatch && rc == LBM_OK; ++g) {
+    const int nx = c->grids[g].nx, ny = c->grids[g].ny;
+    const real *l = reinterpret_cast<const real *>(lam) + cell_off;
+    const real *m = reinterpret_cast<const real *>(mu) + cell_off;
+    const real *r = reinterpret_cast<const real *>(rho) + cell_off;
+    real *kc = reinterpret_cast<real *>(c->kcells) + c->L.k_off[g];
+    hipMemsetAsync(d_bad, 0, sizeof(int), s);
+    hipMemsetAsync(d_rows, 0, ny * sizeof(int), s);
+    hipError_t e = launch_kappa<real>(l, m, r, nx, ny, c->L.pitch[g], kc, d_bad, d_rows, s);
+    if (e != hipSuccess) { rc = fail(LBM_E_DEVICE, hipGetErrorString(e)); break; }
+    int bad = 0;
+    std::vector<int> varies(ny);
+    hipMemcpyAsync(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost, s);
+    hipMemcpyAsync(varies.data(), d_rows, ny * sizeof(int), hipMemcpyDeviceToHost, s);
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { rc = fail(LBM_E_DEVICE, hipGetErrorString(e)); break; }
+    if (bad) {
+      char buf[200];
+      snprintf(buf, sizeof buf,
+               "grid %d: %d cells violate mu > 0, rho > 0, lambda >= 0, nu < 5/11", g, bad);
+      rc = fail(LBM_E_INVALID, buf);
+      break;
+    }
+    bool rows_const = std::none_of(varies.begin(), varies.end(), [](int v) { return v != 0; });
+    if (rows_const) {
+      std::vector<real> kr(ny);
+      real *d_tmp = nullptr;
+      HIP_TRY(hipMalloc((void **)&d_tmp, ny * sizeof(real)));
+      launch_kappa_rows<real>(kc, ny, c->L.pitch[g], d_tmp, s);
+      hipMemcpyAsync(kr.data(), d_tmp, ny * sizeof(real), hipMemcpyDeviceToHost, s);
+      hipStreamSynchronize(s);
+      hipFree(d_tmp);
+      const bool all_same = std::all_of(kr.begin(), kr.end(), [&](real v) { return v == kr[0]; });
+      if (all_same) {
+        c->kmode[g] = kKappaScalar;
+        c->kscalar[g] = (double)kr[0];
+      } else {
+        c->kmode[g] = kKappaRows;
+      }
+      c->krow_off[g] = (int64_t)krows_all.size();
+      krows_all.insert(krows_all.end(), kr.begin(), kr.end());
+    } else {
+      c->kmode[g] = kKappaCells;
+      c->krow_off[g] = 0;
+    }
+    cell_off += (int64_t)nx * ny;
+  }
+  hipFree(d_bad);
+  hipFree(d_rows);
+  if (rc) return rc;
+  if (krows_all.empty()) krows_all.push_back(real(0));
+  std::vector<char> kb(krows_all.size() * sizeof(real));
+  memcpy(kb.data(), krows_all.data(), kb.size());
+  HIP_TRY(c->d_krows.upload(kb, s));
+  return LBM_OK;
+}
+
+// 1/rho0 at the receiver cells, read from the caller's density field.
+template <typename real>
+int gather_scale(lbm_ctx *c, int g, RecHost &R) {
+  const int n = (int)R.xy.size() / 2;
+  const int nx = c->grids[g].nx;
+  std::vector<int64_t> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = c->cell_off[g] + (int64_t)R.xy[2 * i + 1] * nx + R.xy[2 * i];
+  int64_t *d_idx = nullptr;
+  real *d_val = nullptr;
+  HIP_TRY(hipMalloc((void **)&d_idx, n * sizeof(int64_t)));
+  hipError_t e = hipMalloc((void **)&d_val, n * sizeof(real));
+  std::vector<real> h(n);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_idx, idx.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = launch_gather<real>(reinterpret_cast<const real *>(c->rho), d_idx, n, d_val, c->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d_val, n * sizeof(real), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  hipFree(d_idx);
+  if (d_val) hipFree(d_val);
+  if (e != hipSuccess) return fail(LBM_E_DEVICE, hipGetErrorString(e));
+  R.scale.resize(n);
+  for (int i = 0; i < n; ++i) R.scale[i] = 1.0 / (double)h[i];
+  return LBM_OK;
+}
+
+int check_ctx(const lbm_ctx *c) {
+  if (!c) return fail(LBM_E_INVALID, "null context");
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_abi_version(void) { return LBM_ABI_VERSION; }
+
+const char *lbm_last_error(void) { return g_err.c_str(); }
+
+int lbm_workspace_bytes(const lbm_grid *grids, int32_t nbatch, int32_t dtype, size_t *bytes) {
+  if (!grids || nbatch <= 0 || !bytes) return fail(LBM_E_INVALID, "grids, nbatch > 0 and bytes required");
+  if (dtype != LBM_F32 && dtype != LBM_F64) return fail(LBM_E_INVALID, "dtype must be LBM_F32 or LBM_F64");
+  for (int g = 0; g < nbatch; ++g)
+    if (grids[g].nx < 3 || grids[g].ny < 3) return fail(LBM_E_INVALID, "nx and ny must be >= 3");
+  *bytes = make_layout(grids, nbatch, dtype).bytes();
+  return LBM_OK;
+}
+
+int lbm_init(lbm_ctx **out, const lbm_grid *grids, int32_t nbatch, int32_t dtype, const void *lam,
+             const void *mu, const void *rho, double tau, const lbm_bc *bc, const lbm_sponge *sponge,
+             void *workspace, size_t ws_bytes, void *hip_stream) {
+  g_err.clear();
+  if (!out) return fail(LBM_E_INVALID, "ctx pointer is null");
+  *out = nullptr;
+  if (!grids || nbatch <= 0) return fail(LBM_E_INVALID, "need nbatch >= 1 grids");
+  if (dtype != LBM_F32 && dtype != LBM_F64) return fail(LBM_E_INVALID, "dtype must be LBM_F32 or LBM_F64");
+  if (!lam || !mu || !rho) return fail(LBM_E_INVALID, "lam, mu and rho must be device arrays");
+  if (!(tau > 0.5) || !std::isfinite(tau)) return fail(LBM_E_INVALID, "tau must be > 1/2");
+  if (!bc) return fail(LBM_E_INVALID, "bc array is null");
+  for (int g = 0; g < nbatch; ++g) {
+    int rc = validate_grid(grids[g], bc[g], sponge ? &sponge[g] : nullptr, g);
+    if (rc) return rc;
+  }
+  Layout L = make_layout(grids, nbatch, dtype);
+  if (!workspace) return fail(LBM_E_INVALID, "workspace is null");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(LBM_E_INVALID, "workspace must be 256-byte aligned");
+  if (ws_bytes < L.bytes()) {
+    char buf[128];
+    snprintf(buf, sizeof buf, "workspace too small: %zu < %zu bytes", ws_bytes, L.bytes());
+    return fail(LBM_E_NOMEM, buf);
+  }
+  lbm_ctx *c = new (std::nothrow) lbm_ctx();
+  if (!c) return fail(LBM_E_NOMEM, "host allocation failed");
+  c->dtype = dtype;
+  c->nbatch = nbatch;
+  c->tau = tau;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  c->L = L;
+  c->grids.assign(grids, grids + nbatch);
+  c->bc.assign(bc, bc + nbatch);
+  c->sponge.resize(nbatch);
+  c->sp_thick.resize(nbatch);
+  for (int g = 0; g < nbatch; ++g) {
+    for (int e = 0; e < 4; ++e) {
+      const int th = sponge ? sponge[g].thick[e] : 0;
+      c->sp_thick[g][e] = th;
+      for (int k = 0; k < th; ++k) c->sponge[g].push_back(sponge[g].profile[e][k]);
+    }
+  }
+  c->sources.resize(nbatch);
+  c->recs.resize(nbatch);
+  c->kmode.assign(nbatch, kKappaScalar);
+  c->kscalar.assign(nbatch, 0.0);
+  c->krow_off.assign(nbatch, 0);
+  c->rscale_off.assign(nbatch, 0);
+  c->rho = rho;
+  {
+    int64_t off = 0;
+    for (int g = 0; g < nbatch; ++g) {
+      c->cell_off.push_back(off);
+      off += (int64_t)grids[g].nx * grids[g].ny;
+    }
+  }
+  c->ws = reinterpret_cast<char *>(workspace);
+  c->fbuf[0] = c->ws;
+  c->fbuf[1] = c->ws + round_up(L.f_elems * (int64_t)L.esize, 256);
+  c->kcells = c->fbuf[1] + round_up(L.f_elems * (int64_t)L.esize, 256);
+  auto bail = [&](int rc) {
+    lbm_destroy(c);
+    return rc;
+  };
+  hipError_t e = hipMemsetAsync(c->fbuf[0], 0, 2 * round_up(L.f_elems * (int64_t)L.esize, 256), c->stream);
+  if (e != hipSuccess) return bail(fail(LBM_E_DEVICE, hipGetErrorString(e)));
+  int rc = dtype == LBM_F64 ? init_fields<double>(c, lam, mu, rho) : init_fields<float>(c, lam, mu, rho);
+  if (rc) return bail(rc);
+  std::vector<int64_t> zero_time(1, 0);
+  e = c->d_time.upload(zero_time, c->stream);
+  if (e != hipSuccess) return bail(fail(LBM_E_DEVICE, hipGetErrorString(e)));
+  c->rtab_host.assign(L.esize, 0);
+  std::vector<char> r0(c->rtab_host);
+  e = c->d_rtab.upload(r0, c->stream);
+  if (e != hipSuccess) return bail(fail(LBM_E_DEVICE, hipGetErrorString(e)));
+  c->launch = default_launch(c);
+  rc = rebuild_tiles(c);
+  if (rc) return bail(rc);
+  rc = commit(c);
+  if (rc) return bail(rc);
+  *out = c;
+  return LBM_OK;
+}
+
+int lbm_set_sources(lbm_ctx *c, int32_t g, const lbm_source *src, int32_t n) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (g < 0 || g >= c->nbatch) return fail(LBM_E_INVALID, "grid index out of range");
+  if (n < 0 || (n > 0 && !src)) return fail(LBM_E_INVALID, "bad source array");
+  const lbm_grid &G = c->grids[g];
+  for (int i = 0; i < n; ++i) {
+    const lbm_source &q = src[i];
+    if (!(q.x >= 0 && q.x <= G.nx - 1 && q.y >= 0 && q.y <= G.ny - 1))
+      return fail(LBM_E_INVALID, "source outside the grid");
+    if (!(q.sigma > 0) || !(q.period > 0) || !std::isfinite(q.amp) || !std::isfinite(q.t0) ||
+        !std::isfinite(q.dir_x) || !std::isfinite(q.dir_y))
+      return fail(LBM_E_INVALID, "source needs sigma > 0, period > 0 and finite values");
+  }
+  c->sources[g].assign(src, src + n);
+  c->tables_dirty = true;
+  return commit(c);
+}
+
+int lbm_set_receivers(lbm_ctx *c, int32_t g, const int32_t *xy, int32_t n, int32_t comp_mask,
+                      void *traces, int64_t max_steps) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (g < 0 || g >= c->nbatch) return fail(LBM_E_INVALID, "grid index out of range");
+  if (n < 0 || (n > 0 && (!xy || !traces))) return fail(LBM_E_INVALID, "bad receiver arrays");
+  if (n > 0 && (comp_mask < 1 || comp_mask > 3)) return fail(LBM_E_INVALID, "comp_mask must be 1, 2 or 3");
+  if (max_steps < 0) return fail(LBM_E_INVALID, "max_steps must be >= 0");
+  const lbm_grid &G = c->grids[g];
+  for (int i = 0; i < n; ++i)
+    if (xy[2 * i] < 0 || xy[2 * i] >= G.nx || xy[2 * i + 1] < 0 || xy[2 * i + 1] >= G.ny)
+      return fail(LBM_E_INVALID, "receiver outside the grid");
+  RecHost R;
+  R.xy.assign(xy, xy + 2 * n);
+  R.comp_mask = n > 0 ? comp_mask : 0;
+  R.trace = n > 0 ? traces : nullptr;
+  R.max_steps = n > 0 ? max_steps : 0;
+  R.t0 = c->t;
+  if (n > 0) {
+    rc = c->dtype == LBM_F64 ? gather_scale<double>(c, g, R) : gather_scale<float>(c, g, R);
+    if (rc) return rc;
+  }
+  c->recs[g] = R;
+  c->tables_dirty = true;
+  return commit(c);
+}
+
+int lbm_step(lbm_ctx *c, int64_t n) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (n < 0) return fail(LBM_E_INVALID, "n must be >= 0");
+  if (n == 0) return LBM_OK;
+  return c->dtype == LBM_F64 ? step_impl<double>(c, n) : step_impl<float>(c, n);
+}
+
+int lbm_moments(lbm_ctx *c, int32_t g, void *out6) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (g < 0 || g >= c->nbatch) return fail(LBM_E_INVALID, "grid index out of range");
+  if (!out6) return fail(LBM_E_INVALID, "out6 is null");
+  rc = commit(c);
+  if (rc) return rc;
+  if (c->dtype == LBM_F64) {
+    StepArgs<double> a = make_args<double>(c, c->cur);
+    a.fout = nullptr;
+    a.mom = reinterpret_cast<double *>(out6);
+    a.mom_grid = g;
+    HIP_TRY(launch_step<double>(a, c->launch.waves, c->ntiles, kModeMoments, c->stream));
+  } else {
+    StepArgs<float> a = make_args<float>(c, c->cur);
+    a.fout = nullptr;
+    a.mom = reinterpret_cast<float *>(out6);
+    a.mom_grid = g;
+    HIP_TRY(launch_step<float>(a, c->launch.waves, c->ntiles, kModeMoments, c->stream));
+  }
+  return LBM_OK;
+}
+
+int lbm_get_time(const lbm_ctx *c, int64_t *t) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!t) return fail(LBM_E_INVALID, "t is null");
+  *t = c->t;
+  return LBM_OK;
+}
+
+int lbm_get_state(lbm_ctx *c, int32_t g, void *dst) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (g < 0 || g >= c->nbatch || !dst) return fail(LBM_E_INVALID, "bad grid index or dst");
+  const lbm_grid &G = c->grids[g];
+  const int64_t n = (int64_t)G.nx * G.ny;
+  if (c->dtype == LBM_F64) {
+    HIP_TRY(launch_copy_planes<double>(reinterpret_cast<const double *>(c->fbuf[c->cur]) + c->L.f_off[g],
+                                       c->L.plane[g], c->L.pitch[g], reinterpret_cast<double *>(dst), n,
+                                       G.nx, G.nx, G.ny, 9, c->stream));
+  } else {
+    HIP_TRY(launch_copy_planes<float>(reinterpret_cast<const float *>(c->fbuf[c->cur]) + c->L.f_off[g],
+                                      c->L.plane[g], c->L.pitch[g], reinterpret_cast<float *>(dst), n,
+                                      G.nx, G.nx, G.ny, 9, c->stream));
+  }
+  return LBM_OK;
+}
+
+int lbm_set_state(lbm_ctx *c, int32_t g, const void *src, int64_t t) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (g < 0 || g >= c->nbatch || !src) return fail(LBM_E_INVALID, "bad grid index or src");
+  if (t < 0) return fail(LBM_E_INVALID, "t must be >= 0");
+  const lbm_grid &G = c->grids[g];
+  const int64_t n = (int64_t)G.nx * G.ny;
+  if (c->dtype == LBM_F64) {
+    HIP_TRY(launch_copy_planes<double>(reinterpret_cast<const double *>(src), n, G.nx,
+                                       reinterpret_cast<double *>(c->fbuf[c->cur]) + c->L.f_off[g],
+                                       c->L.plane[g], c->L.pitch[g], G.nx, G.ny, 9, c->stream));
+  } else {
+    HIP_TRY(launch_copy_planes<float>(reinterpret_cast<const float *>(src), n, G.nx,
+                                      reinterpret_cast<float *>(c->fbuf[c->cur]) + c->L.f_off[g],
+                                      c->L.plane[g], c->L.pitch[g], G.nx, G.ny, 9, c->stream));
+  }
+  if (t != c->t) {
+    // The context moves to time t: every grid's trace restarts at row 0 = t.
+    c->t = t;
+    for (auto &R : c->recs) R.t0 = t;
+    c->tables_dirty = true;
+    return commit(c);
+  }
+  return LBM_OK;
+}
+
+int lbm_check_finite(lbm_ctx *c) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  int *d = nullptr;
+  HIP_TRY(hipMalloc((void **)&d, sizeof(int)));
+  hipMemsetAsync(d, 0, sizeof(int), c->stream);
+  hipError_t e;
+  if (c->dtype == LBM_F64)
+    e = launch_count_nonfinite<double>(reinterpret_cast<const double *>(c->fbuf[c->cur]), c->L.f_elems, d, c->stream);
+  else
+    e = launch_count_nonfinite<float>(reinterpret_cast<const float *>(c->fbuf[c->cur]), c->L.f_elems, d, c->stream);
+  int h = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof(int), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  hipFree(d);
+  if (e != hipSuccess) return fail(LBM_E_DEVICE, hipGetErrorString(e));
+  if (h) return fail(LBM_E_NONFINITE, "state holds NaN or Inf");
+  return LBM_OK;
+}
+
+int lbm_get_launch(const lbm_ctx *c, lbm_launch *out) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!out) return fail(LBM_E_INVALID, "out is null");
+  *out = c->launch;
+  return LBM_OK;
+}
+
+int lbm_set_launch(lbm_ctx *c, const lbm_launch *cfg) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!cfg) return fail(LBM_E_INVALID, "cfg is null");
+  if (cfg->waves != 1 && cfg->waves != 2 && cfg->waves != 4) return fail(LBM_E_INVALID, "waves must be 1, 2 or 4");
+  if (cfg->rows < 1) return fail(LBM_E_INVALID, "rows must be >= 1");
+  if (cfg->graph_chunk < 0) return fail(LBM_E_INVALID, "graph_chunk must be >= 0");
+  const bool retile = cfg->waves != c->launch.waves || cfg->rows != c->launch.rows;
+  c->launch = *cfg;
+  if (c->launch.graph_chunk % 2) c->launch.graph_chunk += 1;   // keep buffer parity
+  if (retile) return rebuild_tiles(c);
+  if (c->gchunk != c->launch.graph_chunk) drop_graphs(c);
+  return LBM_OK;
+}
+
+int lbm_autotune(lbm_ctx *c, int32_t steps, lbm_launch *chosen) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (steps < 1) return fail(LBM_E_INVALID, "steps must be >= 1");
+  rc = commit(c);
+  if (rc) return rc;
+  // Save the state; every candidate restarts from it.
+  const size_t bytes = (size_t)c->L.f_elems * c->L.esize;
+  void *save = nullptr;
+  HIP_TRY(hipMalloc(&save, bytes));
+  const int cur0 = c->cur;
+  const int64_t t0 = c->t;
+  const lbm_launch keep = c->launch;
+  hipError_t e = hipMemcpyAsync(save, c->fbuf[cur0], bytes, hipMemcpyDeviceToDevice, c->stream);
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&ev0);
+  if (e == hipSuccess) e = hipEventCreate(&ev1);
+  int64_t cells = 0;
+  for (auto &g : c->grids) cells += (int64_t)g.nx * g.ny;
+  lbm_launch best = keep;
+  float best_ms = 1e30f;
+  const int waves_c[3] = {1, 2, 4};
+  const int rows_c[6] = {8, 16, 32, 64, 128, 256};
+  for (int wi = 0; wi < 3 && e == hipSuccess && rc == LBM_OK; ++wi)
+    for (int ri = 0; ri < 6 && e == hipSuccess && rc == LBM_OK; ++ri) {
+      lbm_launch cand{waves_c[wi], rows_c[ri], 0, 0};
+      const int64_t tiles = cells / ((int64_t)64 * cand.waves * cand.rows);
+      if (tiles < 512 && !(cand.waves == 1 && cand.rows == 8)) continue;
+      c->launch = cand;
+      rc = rebuild_tiles(c);
+      if (rc) break;
+      c->cur = cur0;
+      c->t = t0;
+      e = hipMemcpyAsync(c->fbuf[cur0], save, bytes, hipMemcpyDeviceToDevice, c->stream);
+      if (e != hipSuccess) break;
+      rc = c->dtype == LBM_F64 ? step_direct<double>(c, 2) : step_direct<float>(c, 2);  // warm-up
+      if (rc) break;
+      e = hipEventRecord(ev0, c->stream);
+      if (e != hipSuccess) break;
+      rc = c->dtype == LBM_F64 ? step_direct<double>(c, steps) : step_direct<float>(c, steps);
+      if (rc) break;
+      e = hipEventRecord(ev1, c->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(ev1);
+      float ms = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+      if (e == hipSuccess && ms < best_ms) {
+        best_ms = ms;
+        best = cand;
+      }
+    }
+  // Restore the state and install the winner (keeping the graph chunk).
+  c->cur = cur0;
+  c->t = t0;
+  if (e == hipSuccess) e = hipMemcpyAsync(c->fbuf[cur0], save, bytes, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  hipFree(save);
+  if (ev0) hipEventDestroy(ev0);
+  if (ev1) hipEventDestroy(ev1);
+  if (rc) return rc;
+  if (e != hipSuccess) return fail(LBM_E_DEVICE, hipGetErrorString(e));
+  best.graph_chunk = keep.graph_chunk;
+  c->launch = best;
+  rc = rebuild_tiles(c);
+  if (rc) return rc;
+  if (chosen) *chosen = best;
+  return LBM_OK;
+}
+
+int lbm_destroy(lbm_ctx *c) {
+  if (!c) return LBM_OK;
+  drop_graphs(c);
+  c->d_grids.release();
+  c->d_tiles.release();
+  c->d_krows.release();
+  c->d_sponge.release();
+  c->d_src.release();
+  c->d_itab.release();
+  c->d_rtab.release();
+  c->d_time.release();
+  delete c;
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// Internal device-side descriptors shared by the kernels and the host API of
+// liblbm.so. Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// D2Q9, direction order (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1).
+constexpr int kQ = 9;
+constexpr int kEdgeTop = 0, kEdgeBottom = 1, kEdgeLeft = 2, kEdgeRight = 3;
+constexpr int kPeriodic = 0, kFree = 1, kRigid = 2;
+constexpr int kKappaScalar = 0, kKappaRows = 1, kKappaCells = 2;
+
+// One grid of a (possibly batched) context. Offsets are in elements of the
+// context's dtype unless stated otherwise.
+struct GridDev {
+  int32_t nx, ny, pitch, kmode;   // pitch: elements per stored row
+  int64_t f_off;                  // offset of plane 0 inside a population buffer
+  int64_t plane;                  // elements per plane (ny * pitch)
+  int32_t bc[4];
+  int32_t rigid_row;              // -1 none
+  int32_t nsrc, src_off;          // sources [src_off, src_off + nsrc)
+  int32_t nrec;                   // receivers of this grid
+  double kscalar;                 // kappa when kmode == scalar
+  int64_t k_off;                  // kappa rows: offset into the row table;
+                                  // kappa cells: offset into the cell plane
+  int32_t sp_thick[4];
+  int32_t sp_off[4];              // offsets into the sponge profile table
+  int64_t rowtab_off;             // int table: ny entries, receiver row slot or -1
+  int64_t rmap_off;               // int table: slots * nx entries, receiver id or -1
+  int64_t rnext_off;              // int table: nrec entries, next receiver in the same cell
+  int64_t rscale_off;             // real table: 1/rho0 per receiver
+  void *trace;                    // [max_steps][nrec][ncomp] of dtype
+  int64_t trace_t0, trace_max;
+  int32_t ncomp, comp_mask;
+};
+
+struct SourceDev {
+  double x, y, sigma, dir_x, dir_y, amp, period, t0;
+};
+
+// A tile is one workgroup's work: grid g, columns [x0, x0 + 64*waves),
+// rows [y0, y1).
+struct TileDev {
+  int32_t g, x0, y0, y1;
+};
+
+template <typename real>
+struct StepArgs {
+  const real *fin;       // state f*(t-1), all grids
+  real *fout;            // state f*(t)
+  const GridDev *grids;
+  const TileDev *tiles;
+  const real *kappa_rows;
+  const real *kappa_cells;
+  const real *sponge;
+  const SourceDev *sources;
+  const int32_t *itab;
+  const real *rtab;
+  int64_t t;             // step index (plus *t_dev when t_dev is set)
+  const int64_t *t_dev;  // device time base used by captured graphs, or null
+  real omega;            // 1 / tau
+  real cforce;           // 1 - 1/(2 tau)
+  real *mom;             // moments mode: [6][ny][nx] of grid mom_grid
+  int32_t mom_grid;
+};
+
+enum Mode { kModeStep = 0, kModeMoments = 1 };
+
+template <typename real>
+hipError_t launch_step(const StepArgs<real> &a, int waves, int ntiles, int mode,
+                       hipStream_t stream);
+
+// Initialisation and utility kernels (lbm_util.hip).
+template <typename real>
+hipError_t launch_kappa(const real *lam, const real *mu, const real *rho, int nx, int ny,
+                        int pitch, real *kappa, int *bad, int *row_varies,
+                        hipStream_t stream);
+template <typename real>
+hipError_t launch_kappa_rows(const real *kappa, int ny, int pitch, real *rows,
+                             hipStream_t stream);
+template <typename real>
+hipError_t launch_gather(const real *src, const int64_t *idx, int n, real *dst,
+                         hipStream_t stream);
+template <typename real>
+hipError_t launch_count_nonfinite(const real *f, int64_t n, int *count, hipStream_t stream);
+template <typename real>
+hipError_t launch_copy_planes(const real *src, int64_t src_plane, int src_pitch, real *dst,
+                              int64_t dst_plane, int dst_pitch, int nx, int ny, int nplanes,
+                              hipStream_t stream);
+hipError_t launch_set_time(int64_t *t_dev, int64_t value, hipStream_t stream);
+hipError_t launch_add_time(int64_t *t_dev, int64_t delta, hipStream_t stream);
+
+}  // namespace lbm

@@ -1,0 +1,144 @@
+// Initialisation and utility kernels of liblbm.so: the per-cell elastic
+// coefficient, field validation, receiver gathers, state copies, the finite
+// check and the device time base used by captured graphs.
+#include "lbm_internal.h"
+
+namespace lbm {
+namespace {
+
+// kappa = (mu - lambda)/rho0 with mu/rho0 = b^2, i.e. b^2 (mu - lambda)/mu
+// (Sec. 4). A cell is rejected unless mu > 0, rho > 0, lambda >= 0 and the
+// Poisson ratio lambda / (2 (lambda + mu)) < 5/11 (Sec. 4).
+template <typename real>
+__global__ void kappa_kernel(const real *__restrict__ lam, const real *__restrict__ mu,
+                             const real *__restrict__ rho, int nx, int ny, int pitch,
+                             real *__restrict__ kappa, int *bad, int *row_varies) {
+  const int64_t n = (int64_t)nx * ny;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int y = (int)(k / nx), x = (int)(k % nx);
+    const double l = (double)lam[k], m = (double)mu[k], r = (double)rho[k];
+    const bool ok = m > 0.0 && r > 0.0 && l >= 0.0 && (l / (2.0 * (l + m))) < 5.0 / 11.0;
+    if (!ok) atomicAdd(bad, 1);
+    const real kv = ok ? (real)((1.0 / 3.0) * (m - l) / m) : real(0);
+    kappa[(int64_t)y * pitch + x] = kv;
+    if (x > 0) {
+      const double l0 = (double)lam[(int64_t)y * nx], m0 = (double)mu[(int64_t)y * nx];
+      if (l0 != l || m0 != m) row_varies[y] = 1;
+    }
+  }
+}
+
+template <typename real>
+__global__ void kappa_rows_kernel(const real *__restrict__ kappa, int ny, int pitch,
+                                  real *__restrict__ rows) {
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  if (y < ny) rows[y] = kappa[(int64_t)y * pitch];
+}
+
+template <typename real>
+__global__ void gather_kernel(const real *__restrict__ src, const int64_t *__restrict__ idx,
+                              int n, real *__restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[idx[i]];
+}
+
+template <typename real>
+__global__ void nonfinite_kernel(const real *__restrict__ f, int64_t n, int *count) {
+  int local = 0;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const real v = f[k];
+    if (!(v - v == real(0))) local = 1;
+  }
+  if (local) atomicAdd(count, 1);
+}
+
+template <typename real>
+__global__ void copy_planes_kernel(const real *__restrict__ src, int64_t src_plane, int src_pitch,
+                                   real *__restrict__ dst, int64_t dst_plane, int dst_pitch,
+                                   int nx, int ny, int nplanes) {
+  const int64_t n = (int64_t)nx * ny * nplanes;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = k / ((int64_t)nx * ny);
+    const int64_t rem = k - p * (int64_t)nx * ny;
+    const int y = (int)(rem / nx), x = (int)(rem % nx);
+    dst[p * dst_plane + (int64_t)y * dst_pitch + x] = src[p * src_plane + (int64_t)y * src_pitch + x];
+  }
+}
+
+__global__ void set_time_kernel(int64_t *t_dev, int64_t value) { t_dev[0] = value; }
+__global__ void add_time_kernel(int64_t *t_dev, int64_t delta) { t_dev[0] += delta; }
+
+inline int blocks_for(int64_t n, int per_block = 256, int cap = 8192) {
+  int64_t b = (n + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  return (int)(b > cap ? cap : b);
+}
+
+}  // namespace
+
+template <typename real>
+hipError_t launch_kappa(const real *lam, const real *mu, const real *rho, int nx, int ny,
+                        int pitch, real *kappa, int *bad, int *row_varies, hipStream_t stream) {
+  hipLaunchKernelGGL(kappa_kernel<real>, dim3(blocks_for((int64_t)nx * ny)), dim3(256), 0, stream,
+                     lam, mu, rho, nx, ny, pitch, kappa, bad, row_varies);
+  return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_kappa_rows(const real *kappa, int ny, int pitch, real *rows, hipStream_t stream) {
+  hipLaunchKernelGGL(kappa_rows_kernel<real>, dim3((ny + 255) / 256), dim3(256), 0, stream, kappa,
+                     ny, pitch, rows);
+  return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_gather(const real *src, const int64_t *idx, int n, real *dst, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_kernel<real>, dim3((n + 255) / 256), dim3(256), 0, stream, src, idx, n,
+                     dst);
+  return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_count_nonfinite(const real *f, int64_t n, int *count, hipStream_t stream) {
+  hipLaunchKernelGGL(nonfinite_kernel<real>, dim3(blocks_for(n)), dim3(256), 0, stream, f, n, count);
+  return hipGetLastError();
+}
+
+template <typename real>
+hipError_t launch_copy_planes(const real *src, int64_t src_plane, int src_pitch, real *dst,
+                              int64_t dst_plane, int dst_pitch, int nx, int ny, int nplanes,
+                              hipStream_t stream) {
+  hipLaunchKernelGGL(copy_planes_kernel<real>, dim3(blocks_for((int64_t)nx * ny * nplanes)),
+                     dim3(256), 0, stream, src, src_plane, src_pitch, dst, dst_plane, dst_pitch,
+                     nx, ny, nplanes);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_time(int64_t *t_dev, int64_t value, hipStream_t stream) {
+  hipLaunchKernelGGL(set_time_kernel, dim3(1), dim3(1), 0, stream, t_dev, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_time(int64_t *t_dev, int64_t delta, hipStream_t stream) {
+  hipLaunchKernelGGL(add_time_kernel, dim3(1), dim3(1), 0, stream, t_dev, delta);
+  return hipGetLastError();
+}
+
+#define LBM_INST(real)                                                                          \
+  template hipError_t launch_kappa<real>(const real *, const real *, const real *, int, int, int, \
+                                         real *, int *, int *, hipStream_t);                      \
+  template hipError_t launch_kappa_rows<real>(const real *, int, int, real *, hipStream_t);      \
+  template hipError_t launch_gather<real>(const real *, const int64_t *, int, real *,            \
+                                          hipStream_t);                                          \
+  template hipError_t launch_count_nonfinite<real>(const real *, int64_t, int *, hipStream_t);   \
+  template hipError_t launch_copy_planes<real>(const real *, int64_t, int, real *, int64_t, int, \
+                                               int, int, int, hipStream_t);
+LBM_INST(float)
+LBM_INST(double)
+#undef LBM_INST
+
+}  // namespace lbm

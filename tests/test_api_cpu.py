@@ -1,0 +1,115 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point
+declared in include/lbm.h, and rejects invalid arguments before touching the
+device. No compute call is made (no GPU here)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "lbm.h")) as fh:
+        text = fh.read()
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("lbm_init", "lbm_step", "lbm_moments", "lbm_workspace_bytes",
+                 "lbm_set_sources", "lbm_set_receivers", "lbm_destroy", "lbm_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2009_06404_amd import _lib as L
+    lib = L.lib()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert set(L.ENTRY_POINTS) <= set(_declared())
+    assert L.lbm_abi_version() == 1
+
+
+def test_workspace_size_and_validation():
+    from paper_2009_06404_amd import _lib as L
+    b32 = L.lbm_workspace_bytes([(128, 128)], L.LBM_F32)
+    b64 = L.lbm_workspace_bytes([(128, 128)], L.LBM_F64)
+    assert b64 > b32 >= 2 * 9 * 128 * 128 * 4
+    # rows are padded to 64 elements
+    assert L.lbm_workspace_bytes([(65, 10)], L.LBM_F32) >= 19 * 128 * 10 * 4
+    with pytest.raises(L.LBMError):
+        L.lbm_workspace_bytes([(2, 10)], L.LBM_F32)
+    with pytest.raises(L.LBMError):
+        L.lbm_workspace_bytes([(10, 10)], 7)
+
+
+def _init(**kw):
+    from paper_2009_06404_amd import _lib as L
+    grids = kw.get("grids", [(16, 16)])
+    bcs = kw.get("bcs", [(L.LBM_FREE, L.LBM_RIGID, L.LBM_PERIODIC, L.LBM_PERIODIC, -1)])
+    sponges = kw.get("sponges", [((0, 0, 0, 0), (None,) * 4)])
+    tau = kw.get("tau", 1.0)
+    ws = kw.get("ws", 0x1000)
+    ws_bytes = kw.get("ws_bytes", 1 << 30)
+    fake = 0x2000
+    return L.lbm_init(grids, L.LBM_F32, fake, fake, fake, tau, bcs, sponges, ws, ws_bytes, None)
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(tau=0.5), "tau"),
+    (dict(tau=float("nan")), "tau"),
+    (dict(grids=[(2, 16)]), ">= 3"),
+    (dict(bcs=[(0, 1, 0, 0, -1)]), "paired"),
+    (dict(bcs=[(0, 0, 1, 1, -1)]), "free surface"),
+    (dict(bcs=[(1, 2, 0, 0, 1)]), "rigid_row"),
+    (dict(bcs=[(1, 2, 0, 0, 15)]), "rigid_row"),
+    (dict(bcs=[(1, 2, 0, 0, 3)], grids=[(16, 4)]), "rigid_row"),
+    (dict(sponges=[((0, 17, 0, 0), (None,) * 4)]), "sponge"),
+    (dict(ws=0), "workspace"),
+    (dict(ws=0x1004), "aligned"),
+    (dict(ws_bytes=100), "too small"),
+])
+def test_init_rejects_invalid_arguments(kw, msg):
+    from paper_2009_06404_amd import _lib as L
+    with pytest.raises(L.LBMError) as ei:
+        _init(**kw)
+    assert msg in str(ei.value)
+    assert ei.value.code in (L.LBM_E_INVALID, L.LBM_E_NOMEM)
+
+
+def test_negative_sponge_profile_rejected():
+    import numpy as np
+    from paper_2009_06404_amd import _lib as L
+    prof = np.array([0.1, -0.2, 0.0])
+    with pytest.raises(L.LBMError):
+        _init(sponges=[((0, 3, 0, 0), (None, prof, None, None))])
+
+
+def test_null_context_calls_fail_cleanly():
+    from paper_2009_06404_amd import _lib as L
+    lib = L.lib()
+    assert lib.lbm_step(None, 1) == L.LBM_E_INVALID
+    assert lib.lbm_moments(None, 0, None) == L.LBM_E_INVALID
+    assert lib.lbm_destroy(None) == L.LBM_OK
+    assert "null" in L.last_error() or L.last_error() == ""
+
+
+def test_binding_fails_loudly_without_library(monkeypatch):
+    from paper_2009_06404_amd import _lib as L
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", "/nonexistent/liblbm.so")
+    with pytest.raises(ImportError):
+        L.lib()
+
+
+def test_product_code_never_touches_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2009_06404_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                with open(os.path.join(dirpath, f)) as fh:
+                    text = fh.read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "lbm_oracle" not in text, f

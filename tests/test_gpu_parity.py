@@ -1,0 +1,199 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle, element
+by element on the same seeded inputs.
+
+Tolerances (relative L2 per field, per state and per trace set): FP64 1e-12,
+FP32 1e-5 against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+import workloads as w
+from workloads import BC_FREE, BC_PERIODIC, BC_RIGID, Medium, Problem, Source
+from oracle import stepper
+from gpu_helpers import compare, rel_l2, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+def _oracle(p, nsteps, fstar_init=None, t0=0):
+    return stepper.run(p, nsteps=nsteps, fstar_init=fstar_init, t0=t0)
+
+
+def _print(name, worst):
+    print(f"[parity] {name}: worst rel L2 {worst:.3e}", flush=True)
+
+
+def test_plain_small_full_config_f64():
+    """128x128 periodic box, nu = 0.25, x-force, 16-station ring, 600 steps:
+    the full small configuration, FP64."""
+    p = w.plain_small()
+    g = run_gpu(p, p.nsteps, "f64")
+    worst = compare(g, _oracle(p, p.nsteps), TOL["f64"], "plain_small f64")
+    _print("plain_small f64 600 steps", worst)
+
+
+def test_plain_small_f32():
+    p = w.plain_small()
+    g = run_gpu(p, p.nsteps, "f32")
+    worst = compare(g, _oracle(p, p.nsteps), TOL["f32"], "plain_small f32")
+    _print("plain_small f32 600 steps", worst)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_plain_large_reduced(dtype):
+    """Free surface, sponges, rigid bottom, nu = 0.33 (elastic force active),
+    surface receivers: the large configuration at 256x256."""
+    p = w.plain_large(n=256, nsteps=700, sponge=24, src_depth=20)
+    g = run_gpu(p, p.nsteps, dtype)
+    worst = compare(g, _oracle(p, p.nsteps), TOL[dtype], f"plain_large/256 {dtype}")
+    _print(f"plain_large 256 {dtype}", worst)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_hbm_scale_reduced(dtype):
+    """8 layers (per-row kappa), rigid internal interface, 3 sources."""
+    p = w.hbm_scale(n=256, nsteps=500, sponge=32)
+    assert p.rigid_row > 0
+    p = p.replace(receivers=np.array([[x, 0] for x in range(0, 256, 5)] +
+                                     [[x, p.rigid_row - 1] for x in range(3, 256, 7)] +
+                                     [[x, p.rigid_row] for x in range(1, 256, 9)], np.int32),
+                  comp_mask=3)
+    g = run_gpu(p, p.nsteps, dtype)
+    worst = compare(g, _oracle(p, p.nsteps), TOL[dtype], f"hbm_scale/256 {dtype}")
+    _print(f"hbm_scale 256 {dtype}", worst)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_field_medium_shots_batched(dtype):
+    """Per-cell kappa (random-field medium) with several shots in one batch."""
+    probs = w.adjoint_shots(n=128, shots=3, nsteps=300, sponge=16)
+    gs = run_gpu(probs, 300, dtype)
+    for s, (p, g) in enumerate(zip(probs, gs)):
+        worst = compare(g, _oracle(p, 300), TOL[dtype], f"shot {s} {dtype}")
+        _print(f"field medium shot {s} {dtype}", worst)
+
+
+def test_batched_uneven_grids_match_oracle_and_single_runs():
+    """Grids of uneven, ragged sizes in one launch: each matches the oracle and
+    is bitwise equal to the same grid run alone."""
+    probs = w.batched_shots(count=4, nsteps=250, sponge=16, sides=[70, 96, 131, 200])
+    probs = [p.replace(receivers=np.array([[x, 0] for x in range(0, p.nx, 3)], np.int32),
+                       comp_mask=2) for p in probs]
+    gb = run_gpu(probs, 250, "f32")
+    for p, g in zip(probs, gb):
+        compare(g, _oracle(p, 250), TOL["f32"], f"batched {p.nx}")
+        single = run_gpu(p, 250, "f32")
+        assert np.array_equal(single["fstar"], g["fstar"])
+        assert np.array_equal(single["mom"], g["mom"])
+        assert np.array_equal(single["trace"], g["trace"])
+
+
+def _feature_problem(nx=150, ny=77):
+    prof = w.default_sponge_profile(9)
+    lam = np.linspace(0.01, 0.05, ny)
+    mu = np.full(ny, 0.04)
+    return Problem(nx=nx, ny=ny, bc=(BC_FREE, BC_RIGID, BC_PERIODIC, BC_PERIODIC),
+                   medium=Medium("layered", lam, mu, np.ones(ny)), tau=0.9, rigid_row=40,
+                   sponge_thick=(0, 9, 7, 9), sponge_profiles=(None, prof, prof[:7] * 2, prof),
+                   sources=[Source(20.0, 5.0, 2.5, 0.3, 1.0, 1.0, 14.0, 10.0),
+                            Source(140.0, 60.0, 2.0, -1.0, 0.2, 0.5, 10.0, 12.0)],
+                   receivers=np.array([[0, 0], [149, 0], [75, 39], [75, 40], [3, 76], [3, 76]], np.int32),
+                   comp_mask=3, dtype="f64")
+
+
+def test_launch_configurations_agree_bitwise():
+    """Ragged grid (nx not a multiple of 64, odd ny), every wall type: all tile
+    shapes give bitwise the same state, and one of them matches the oracle."""
+    p = _feature_problem()
+    ref = None
+    for waves in (1, 2, 4):
+        for rows in (1, 5, 64):
+            g = run_gpu(p, 60, "f64", launch=dict(waves=waves, rows=rows))
+            if ref is None:
+                ref = g
+                compare(g, _oracle(p, 60), TOL["f64"], "feature problem")
+            else:
+                assert np.array_equal(ref["fstar"], g["fstar"]), (waves, rows)
+                assert np.array_equal(ref["trace"], g["trace"]), (waves, rows)
+
+
+BC_CASES = [
+    ("periodic", (BC_PERIODIC,) * 4, -1),
+    ("free_rigid", (BC_FREE, BC_RIGID, BC_PERIODIC, BC_PERIODIC), -1),
+    ("rigid_box", (BC_RIGID,) * 4, -1),
+    ("free_free_rigid_sides", (BC_FREE, BC_FREE, BC_RIGID, BC_RIGID), 6),
+    ("rigid_free", (BC_RIGID, BC_FREE, BC_PERIODIC, BC_PERIODIC), 5),
+    ("periodic_y_rigid_x", (BC_PERIODIC, BC_PERIODIC, BC_RIGID, BC_RIGID), -1),
+]
+
+
+@pytest.mark.parametrize("name,bc,rr", BC_CASES, ids=[c[0] for c in BC_CASES])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_random_state_every_link(name, bc, rr, dtype):
+    """From a random state every population and every wall link is active."""
+    rng = np.random.default_rng(7)
+    nx, ny = 67, 13
+    lam = rng.uniform(0.0, 0.06, size=(ny, nx))
+    mu = rng.uniform(0.035, 0.045, size=(ny, nx))
+    prof = w.default_sponge_profile(3, 0.3)
+    p = Problem(nx=nx, ny=ny, bc=bc, medium=Medium("field", lam, mu, rng.uniform(0.8, 1.2, (ny, nx))),
+                tau=0.8, rigid_row=rr, sponge_thick=(2, 3, 3, 2),
+                sponge_profiles=(prof, prof, prof, prof),
+                sources=[Source(33.0, 6.0, 2.0, 0.6, -0.8, 1.0, 6.0, 2.0)],
+                receivers=np.array([[x, y] for y in range(ny) for x in range(0, nx, 11)], np.int32),
+                comp_mask=3)
+    f0 = rng.normal(size=(9, ny, nx))
+    if dtype == "f32":
+        f0 = f0.astype(np.float32).astype(np.float64)
+    g = run_gpu(p, 6, dtype, state=f0, t0=3)
+    ref = _oracle(p, 6, fstar_init=f0, t0=3)
+    compare(g, ref, TOL[dtype], f"random state {name} {dtype}")
+
+
+def test_minimal_grid_and_zero_steps():
+    p = Problem(nx=3, ny=3, bc=(BC_PERIODIC,) * 4, medium=Medium("homogeneous", 0.02, 0.04, 1.0),
+                sources=[Source(1.0, 1.0, 1.0, 1.0, 0.0, 1.0, 4.0, 2.0)],
+                receivers=np.array([[1, 1]], np.int32), comp_mask=3, dtype="f64")
+    g = run_gpu(p, 9, "f64")
+    compare(g, _oracle(p, 9), TOL["f64"], "3x3")
+    g0 = run_gpu(p, 0, "f64")
+    assert np.all(g0["fstar"] == 0) and np.all(g0["mom"] == 0)
+
+
+def test_restart_and_graph_are_bitwise():
+    """n steps in one call == k steps, get/set state, n-k steps; and the
+    HIP-graph-captured loop == direct launches."""
+    import torch
+    from paper_2009_06404_amd import Solver
+    p = _feature_problem().replace(dtype="f32")
+    a = run_gpu(p, 40, "f32")
+    s = Solver(p, dtype="f32", trace_steps=40)
+    s.step(17)
+    st = s.state(0).clone()
+    s.close()
+    s2 = Solver(p, dtype="f32", trace_steps=40)
+    s2.set_state(0, st, 17)
+    s2.step(23)
+    fs = s2.state(0).double().cpu().numpy()
+    s2.close()
+    assert np.array_equal(fs, a["fstar"])
+    g = run_gpu(p, 40, "f32", launch=dict(waves=2, rows=16, graph_chunk=8))
+    d = run_gpu(p, 40, "f32", launch=dict(waves=2, rows=16, graph_chunk=0))
+    assert np.array_equal(g["fstar"], d["fstar"])
+    assert np.array_equal(g["trace"], d["trace"])
+    torch.cuda.synchronize()
+
+
+def test_plain_large_full_size_random_state_f32():
+    """The large configuration at its full 4096x4096 size, in the default
+    launch configuration, from a random state (all cells active): 12 steps
+    against the oracle, all fields, state and the 4096 surface traces."""
+    p = w.plain_large()
+    rng = np.random.default_rng(11)
+    f0 = rng.standard_normal(size=(9, p.ny, p.nx), dtype=np.float32).astype(np.float64) * 1e-3
+    g = run_gpu(p, 12, "f32", state=f0, t0=50)
+    ref = _oracle(p, 12, fstar_init=f0, t0=50)
+    worst = compare(g, ref, TOL["f32"], "plain_large 4096 random state")
+    _print("plain_large 4096 f32 random state 12 steps", worst)
