@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--rows", type=int, default=0)
     ap.add_argument("--graph-chunk", type=int, default=100)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of 9 x n^2 floats (counter calibration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -102,6 +104,15 @@ def main():
     from paper_2009_06404_amd import Solver
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(9 * args.n * args.n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
+                          "launches": 5}), flush=True)
+        return
     p = w.plain_large(n=args.n, dtype=args.dtype)
     total = args.warmup + args.steps
     s = Solver(p, dtype=args.dtype, trace_steps=total)

@@ -56,8 +56,18 @@ enum {
 enum { LBM_F32 = 0, LBM_F64 = 1 };
 
 /* Edge types (Sec. 6). PERIODIC must be paired (top with bottom, left with
- * right). FREE is accepted on the top and bottom edges only. */
-enum { LBM_PERIODIC = 0, LBM_FREE = 1, LBM_RIGID = 2 };
+ * right). FREE and FREE0 are accepted on the top and bottom edges only.
+ *  LBM_FREE   free surface (anti-bounce-back, Sec. 6.2) with rho_air and the
+ *             tangential stress P_xx,air linearly extrapolated half a cell out
+ *             (3/2 boundary cell - 1/2 the cell inside), as printed. This rule
+ *             lets short-wavelength surface modes grow for every tau (the step
+ *             has spectral radius > 1, e.g. 1.046 at nu = 0.25, tau = 1), so
+ *             long runs amplify rounding noise without bound.
+ *  LBM_FREE0  the same rule with the boundary cell's own rho and P_xx (zero-
+ *             order extrapolation): spectral radius <= 1 for 0.1 <= nu <= 0.33
+ *             at tau in [0.7, 2]; the stabilised variant for long runs.
+ *  LBM_RIGID  halfway bounce-back (eq. BB). */
+enum { LBM_PERIODIC = 0, LBM_FREE = 1, LBM_RIGID = 2, LBM_FREE0 = 3 };
 enum { LBM_EDGE_TOP = 0, LBM_EDGE_BOTTOM = 1, LBM_EDGE_LEFT = 2, LBM_EDGE_RIGHT = 3 };
 
 typedef struct {
@@ -71,7 +81,7 @@ typedef struct {
  * density is the linear extrapolation 2 rho_b - rho_in. A link that crosses a
  * rigid and a free edge at once bounces back as rigid. */
 typedef struct {
-  int32_t edge[4];   /* LBM_PERIODIC / LBM_FREE / LBM_RIGID per LBM_EDGE_* */
+  int32_t edge[4];   /* LBM_PERIODIC / LBM_FREE / LBM_FREE0 / LBM_RIGID per LBM_EDGE_* */
   int32_t rigid_row;
 } lbm_bc;
 
@@ -98,7 +108,9 @@ typedef struct {
   int32_t waves;      /* wavefronts per workgroup: 1, 2 or 4 (64 columns each) */
   int32_t rows;       /* rows marched per workgroup */
   int32_t graph_chunk;/* steps per captured HIP graph; 0 = direct launches */
-  int32_t reserved;
+  int32_t prefetch;   /* rows of populations in flight while marching: 1 or 2 */
+  int32_t split;      /* 1: tiles clear of walls, sources and receivers run in a
+                         lean interior kernel (default); 0: one kernel for all */
 } lbm_launch;
 
 /* Bytes of device workspace lbm_init needs for nbatch grids of the given
@@ -160,7 +172,8 @@ int lbm_set_state(lbm_ctx *ctx, int32_t g, const void *src, int64_t t);
 int lbm_check_finite(lbm_ctx *ctx);
 
 /* Launch configuration in use, and a way to set it (waves in {1,2,4},
- * rows >= 1, graph_chunk >= 0). */
+ * rows >= 1, graph_chunk >= 0, prefetch in {1,2}; 0 means 1). An odd
+ * graph_chunk is rounded up to keep the ping-pong parity. */
 int lbm_get_launch(const lbm_ctx *ctx, lbm_launch *out);
 int lbm_set_launch(lbm_ctx *ctx, const lbm_launch *cfg);
 

@@ -31,7 +31,9 @@
  *    linearly extrapolated ghost density 2 rho_b - rho_in in the centred
  *    difference of eq. FDrho;
  *  - free surface allowed on the top/bottom edges only; a link that crosses a
- *    rigid and a free edge at once (a corner) bounces back as rigid.
+ *    rigid and a free edge at once (a corner) bounces back as rigid;
+ *  - free-surface moments rho_b, rho_in, P_b, P_in are those of time t (the
+ *    post-collision populations f_i(x_b, t) are the ones reflected).
  */
 #include <math.h>
 #include <stdint.h>
@@ -41,7 +43,12 @@
 #include <omp.h>
 #endif
 
-enum { BC_PERIODIC = 0, BC_FREE = 1, BC_RIGID = 2 };
+/* BC_FREE: the free surface of Sec. 6.2 with rho_air and P_xx,air linearly
+ * extrapolated to the interface (as printed); BC_FREE0: the same rule with the
+ * boundary cell's own rho and P_xx (zero-order extrapolation), a stabilised
+ * variant -- the linear extrapolation makes short-wavelength surface modes
+ * grow for every tau (spectral radius of the step > 1). */
+enum { BC_PERIODIC = 0, BC_FREE = 1, BC_RIGID = 2, BC_FREE0 = 3 };
 enum { EDGE_TOP = 0, EDGE_BOTTOM = 1, EDGE_LEFT = 2, EDGE_RIGHT = 3 };
 
 /* D2Q9 lattice (Sec. 2): velocities, weights, opposite directions. */
@@ -312,12 +319,15 @@ static void phase_receivers(oracle_grid *g, double *row) {
  * linearly extrapolated from the boundary cell and the cell inside it, and the
  * normal rows of P_air zero (P_air n = 0). */
 static double free_surface_value(const oracle_grid *g, int x, int y, int i,
-                                 int normal_y, double fstar_i) {
+                                 int normal_y, int order, double fstar_i) {
   const int nx = g->nx;
   const size_t kb = (size_t)y * nx + x;
   const size_t kin = (size_t)(y - normal_y) * nx + x;
-  const double rho_air = 1.5 * g->rho[kb] - 0.5 * g->rho[kin];
-  const double pxx_air = 1.5 * g->pxx[kb] - 0.5 * g->pxx[kin];
+  /* interface half a cell outside x_b: linear extrapolation from x_b and x_in
+   * (order 1, as printed), or the boundary cell's value (order 0) */
+  const double cb = order ? 1.5 : 1.0, cin = order ? -0.5 : 0.0;
+  const double rho_air = cb * g->rho[kb] + cin * g->rho[kin];
+  const double pxx_air = cb * g->pxx[kb] + cin * g->pxx[kin];
   const double pn_xx = pxx_air - B2 * rho_air;
   const double pn_xy = 0.0;
   const double pn_yy = 0.0 - B2 * rho_air;
@@ -340,11 +350,15 @@ static void phase_stream(oracle_grid *g, const double *fstar, double *fnext) {
       for (int i = 0; i < 9; ++i) {
         int xd = x + CX[i], yd = y + CY[i];
         int rigid = 0, free_ny = 0; /* free_ny: outward normal y of a free edge */
+        int order = 1;
         if (yd < 0 || yd >= ny) {
           const int edge = (yd < 0) ? EDGE_TOP : EDGE_BOTTOM;
           if (c->bc[edge] == BC_PERIODIC) yd = (yd + ny) % ny;
           else if (c->bc[edge] == BC_RIGID) rigid = 1;
-          else free_ny = (yd < 0) ? -1 : +1;
+          else {
+            free_ny = (yd < 0) ? -1 : +1;
+            order = c->bc[edge] == BC_FREE ? 1 : 0;
+          }
         } else if (rr > 0 && ((CY[i] > 0 && y == rr - 1) || (CY[i] < 0 && y == rr))) {
           rigid = 1;
         }
@@ -357,7 +371,7 @@ static void phase_stream(oracle_grid *g, const double *fstar, double *fnext) {
         if (rigid) {
           fnext[OPP[i] * N + k] = fs;
         } else if (free_ny != 0) {
-          fnext[OPP[i] * N + k] = free_surface_value(g, x, y, i, free_ny, fs);
+          fnext[OPP[i] * N + k] = free_surface_value(g, x, y, i, free_ny, order, fs);
         } else {
           fnext[i * N + (size_t)yd * nx + xd] = fs;
         }

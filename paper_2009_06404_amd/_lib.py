@@ -26,6 +26,7 @@ LBM_F64 = 1
 LBM_PERIODIC = 0
 LBM_FREE = 1
 LBM_RIGID = 2
+LBM_FREE0 = 3
 
 ENTRY_POINTS = (
     "lbm_abi_version", "lbm_last_error", "lbm_workspace_bytes", "lbm_init",
@@ -53,7 +54,7 @@ class lbm_source(C.Structure):
 
 class lbm_launch(C.Structure):
     _fields_ = [("waves", C.c_int32), ("rows", C.c_int32), ("graph_chunk", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("prefetch", C.c_int32), ("split", C.c_int32)]
 
 
 class LBMError(RuntimeError):
@@ -203,18 +204,21 @@ def lbm_check_finite(ctx) -> bool:
 def lbm_get_launch(ctx):
     o = lbm_launch()
     check(lib().lbm_get_launch(ctx, C.byref(o)))
-    return dict(waves=o.waves, rows=o.rows, graph_chunk=o.graph_chunk)
+    return dict(waves=o.waves, rows=o.rows, graph_chunk=o.graph_chunk, prefetch=o.prefetch,
+                split=o.split)
 
 
-def lbm_set_launch(ctx, waves: int, rows: int, graph_chunk: int = 0) -> None:
-    o = lbm_launch(waves, rows, graph_chunk, 0)
+def lbm_set_launch(ctx, waves: int, rows: int, graph_chunk: int = 0, prefetch: int = 1,
+                   split: int = 1) -> None:
+    o = lbm_launch(waves, rows, graph_chunk, prefetch, split)
     check(lib().lbm_set_launch(ctx, C.byref(o)))
 
 
 def lbm_autotune(ctx, steps: int = 5):
     o = lbm_launch()
     check(lib().lbm_autotune(ctx, int(steps), C.byref(o)))
-    return dict(waves=o.waves, rows=o.rows, graph_chunk=o.graph_chunk)
+    return dict(waves=o.waves, rows=o.rows, graph_chunk=o.graph_chunk, prefetch=o.prefetch,
+                split=o.split)
 
 
 def lbm_destroy(ctx) -> None:

@@ -129,7 +129,8 @@ struct lbm_ctx {
   int64_t t = 0;
   // library-owned device tables
   DevBuf<GridDev> d_grids;
-  DevBuf<TileDev> d_tiles;
+  DevBuf<TileDev> d_tiles;                       // tiles for the general kernel
+  DevBuf<TileDev> d_tiles_int;                   // tiles for the interior kernel
   DevBuf<char> d_krows;                          // dtype elements
   DevBuf<char> d_sponge;                         // dtype elements
   DevBuf<SourceDev> d_src;
@@ -140,8 +141,8 @@ struct lbm_ctx {
   std::vector<int64_t> rscale_off;               // per grid offset into d_rtab
   std::vector<char> rtab_host;
   bool tables_dirty = true;
-  lbm_launch launch{4, 64, 0, 0};
-  int ntiles = 0;
+  lbm_launch launch{4, 64, 0, 1, 1};
+  int ntiles = 0, ntiles_int = 0;
   // graph of graph_chunk steps for each starting buffer parity
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   int gchunk = 0;
@@ -169,7 +170,7 @@ int validate_grid(const lbm_grid &g, const lbm_bc &b, const lbm_sponge *sp, int 
     return fail(LBM_E_INVALID, buf);
   }
   for (int e = 0; e < 4; ++e)
-    if (b.edge[e] < LBM_PERIODIC || b.edge[e] > LBM_RIGID) {
+    if (b.edge[e] < LBM_PERIODIC || b.edge[e] > LBM_FREE0) {
       snprintf(buf, sizeof buf, "grid %d: unknown boundary type on edge %d", idx, e);
       return fail(LBM_E_INVALID, buf);
     }
@@ -178,7 +179,8 @@ int validate_grid(const lbm_grid &g, const lbm_bc &b, const lbm_sponge *sp, int 
     snprintf(buf, sizeof buf, "grid %d: periodic edges must be paired", idx);
     return fail(LBM_E_INVALID, buf);
   }
-  if (b.edge[LBM_EDGE_LEFT] == LBM_FREE || b.edge[LBM_EDGE_RIGHT] == LBM_FREE) {
+  if (b.edge[LBM_EDGE_LEFT] == LBM_FREE || b.edge[LBM_EDGE_RIGHT] == LBM_FREE ||
+      b.edge[LBM_EDGE_LEFT] == LBM_FREE0 || b.edge[LBM_EDGE_RIGHT] == LBM_FREE0) {
     snprintf(buf, sizeof buf, "grid %d: a free surface is supported on the top/bottom edges only", idx);
     return fail(LBM_E_INVALID, buf);
   }
@@ -207,18 +209,11 @@ int validate_grid(const lbm_grid &g, const lbm_bc &b, const lbm_sponge *sp, int 
   return LBM_OK;
 }
 
-// Tiles: columns [x0, x0 + 64*waves), rows [y0, y1). Blocks are handed to the
-// 8 dies round-robin by block id, so block b takes the (b/8)-th tile of the
-// die-contiguous chunk (b%8): neighbouring tiles, which share halo lines, run
-// on the same die and hit the same L2.
-std::vector<TileDev> build_tiles(const lbm_ctx *c, int waves, int rows) {
-  std::vector<TileDev> logical;
-  const int W = 64 * waves;
-  for (int g = 0; g < c->nbatch; ++g) {
-    const int nx = c->grids[g].nx, ny = c->grids[g].ny;
-    for (int y0 = 0; y0 < ny; y0 += rows)
-      for (int x0 = 0; x0 < nx; x0 += W) logical.push_back({g, x0, y0, std::min(y0 + rows, ny)});
-  }
+// Blocks are handed to the 8 dies round-robin by block id, so block b takes
+// the (b/8)-th tile of the die-contiguous chunk (b%8) of the list:
+// neighbouring tiles, which share halo lines, run on the same die and hit the
+// same L2. Padding blocks carry g = -1.
+std::vector<TileDev> order_for_dies(const std::vector<TileDev> &logical) {
   const int64_t T = (int64_t)logical.size();
   const int64_t per = (T + kXcds - 1) / kXcds;
   std::vector<TileDev> phys((size_t)(per * kXcds), TileDev{-1, 0, 0, 0});
@@ -230,18 +225,70 @@ std::vector<TileDev> build_tiles(const lbm_ctx *c, int waves, int rows) {
   return phys;
 }
 
+double min_image_host(double d, int n, bool periodic) {
+  if (periodic) {
+    if (d > 0.5 * n) d -= n;
+    else if (d < -0.5 * n) d += n;
+  }
+  return d;
+}
+
+// Whether a tile can run in the interior kernel: every row it pulls (one
+// above, its own, one below) has no horizontal wall link and no wrap, every
+// column it touches (with the halo columns) has both x-neighbours inside the
+// grid or the x edges are periodic, no source reaches its rows and no receiver
+// sits in them.
+bool tile_is_interior(const lbm_ctx *c, int g, int x0, int y0, int y1, int W) {
+  const lbm_grid &G = c->grids[g];
+  const lbm_bc &b = c->bc[g];
+  const int nx = G.nx, ny = G.ny, rr = b.rigid_row;
+  if (y0 - 1 < 1 || y1 > ny - 2) return false;
+  if (rr > 0 && rr - 1 <= y1 && rr >= y0 - 1) return false;
+  const bool px = b.edge[LBM_EDGE_LEFT] == LBM_PERIODIC;
+  const bool py = b.edge[LBM_EDGE_TOP] == LBM_PERIODIC;
+  const int x_last = std::min(x0 + W, nx) - 1;
+  if (!px && (x0 - 2 < 0 || x_last + 2 > nx - 1)) return false;
+  for (const lbm_source &q : c->sources[g]) {
+    const double cut = 81.0 * q.sigma * q.sigma;
+    for (int y = y0; y < y1; ++y) {
+      const double dy = min_image_host((double)y - q.y, ny, py);
+      if (dy * dy <= cut) return false;
+    }
+  }
+  const std::vector<int32_t> &xy = c->recs[g].xy;
+  for (size_t r = 1; r < xy.size(); r += 2)
+    if (xy[r] >= y0 && xy[r] < y1) return false;
+  return true;
+}
+
+// Tiles: columns [x0, x0 + 64*waves), rows [y0, y1), sorted into the interior
+// list (when split) and the general list.
+void build_tiles(const lbm_ctx *c, int waves, int rows, bool split, std::vector<TileDev> &interior,
+                 std::vector<TileDev> &general) {
+  std::vector<TileDev> li, lg;
+  const int W = 64 * waves;
+  for (int g = 0; g < c->nbatch; ++g) {
+    const int nx = c->grids[g].nx, ny = c->grids[g].ny;
+    for (int y0 = 0; y0 < ny; y0 += rows)
+      for (int x0 = 0; x0 < nx; x0 += W) {
+        const TileDev t{g, x0, y0, std::min(y0 + rows, ny)};
+        if (split && tile_is_interior(c, g, x0, t.y0, t.y1, W)) li.push_back(t);
+        else lg.push_back(t);
+      }
+  }
+  interior = order_for_dies(li);
+  general = order_for_dies(lg);
+}
+
+// Default launch shape: 256-column tiles of 8 rows (many short tiles keep the
+// set of rows in flight compact); narrower tiles for small grids.
 lbm_launch default_launch(const lbm_ctx *c) {
   int64_t cells = 0;
   for (const auto &g : c->grids) cells += (int64_t)g.nx * g.ny;
-  lbm_launch l{4, 64, 0, 0};
-  // aim for at least ~8 workgroups per compute unit (256 CUs)
-  const int64_t want = 2048;
-  int64_t rows = cells / (256 * want);
-  rows = std::max<int64_t>(8, std::min<int64_t>(128, rows));
-  l.rows = (int)rows;
+  lbm_launch l{4, 8, 0, 1, 1};
   if (cells < 256 * 2048) {
     l.waves = 1;
-    l.rows = std::max<int64_t>(4, std::min<int64_t>(64, cells / (64 * 1024)));
+    l.rows = 4;
   }
   return l;
 }
@@ -249,14 +296,18 @@ lbm_launch default_launch(const lbm_ctx *c) {
 template <typename real>
 int commit_tables(lbm_ctx *c) {
   const hipStream_t s = c->stream;
-  // sponge table (dtype) and per-grid offsets
+  // sponge table (dtype): pairs (A, 1/(1 + A/2)) per profile entry
   std::vector<real> sponge;
   std::vector<std::array<int32_t, 4>> sp_off(c->nbatch);
   for (int g = 0; g < c->nbatch; ++g) {
     int64_t k = 0;
     for (int e = 0; e < 4; ++e) {
       sp_off[g][e] = (int32_t)sponge.size();
-      for (int i = 0; i < c->sp_thick[g][e]; ++i) sponge.push_back((real)c->sponge[g][k + i]);
+      for (int i = 0; i < c->sp_thick[g][e]; ++i) {
+        const double A = c->sponge[g][k + i];
+        sponge.push_back((real)A);
+        sponge.push_back((real)(1.0 / (1.0 + 0.5 * A)));
+      }
       k += c->sp_thick[g][e];
     }
   }
@@ -350,18 +401,40 @@ int commit_tables(lbm_ctx *c) {
   return LBM_OK;
 }
 
+int rebuild_tiles(lbm_ctx *c);
+
 int commit(lbm_ctx *c) {
   if (!c->tables_dirty) return LBM_OK;
   drop_graphs(c);
-  return c->dtype == LBM_F64 ? commit_tables<double>(c) : commit_tables<float>(c);
+  const int rc = c->dtype == LBM_F64 ? commit_tables<double>(c) : commit_tables<float>(c);
+  if (rc) return rc;
+  return rebuild_tiles(c);   // which tiles are interior depends on sources and receivers
 }
 
 int rebuild_tiles(lbm_ctx *c) {
-  std::vector<TileDev> tiles = build_tiles(c, c->launch.waves, c->launch.rows);
-  c->ntiles = (int)tiles.size();
-  HIP_TRY(c->d_tiles.upload(tiles, c->stream));
+  std::vector<TileDev> ti, tg;
+  build_tiles(c, c->launch.waves, c->launch.rows, c->launch.split != 0, ti, tg);
+  c->ntiles_int = (int)ti.size();
+  c->ntiles = (int)tg.size();
+  HIP_TRY(c->d_tiles_int.upload(ti, c->stream));
+  HIP_TRY(c->d_tiles.upload(tg, c->stream));
   drop_graphs(c);
   return LBM_OK;
+}
+
+// One step: the interior tiles and the general tiles (any order: both read
+// the state of step t-1 and write disjoint cells of step t).
+template <typename real>
+hipError_t launch_one_step(lbm_ctx *c, StepArgs<real> a, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  if (c->ntiles_int > 0) {
+    StepArgs<real> ai = a;
+    ai.tiles = c->d_tiles_int.p;
+    e = launch_interior<real>(ai, c->launch.waves, c->ntiles_int, s);
+    if (e != hipSuccess) return e;
+  }
+  a.tiles = c->d_tiles.p;
+  return launch_step<real>(a, c->launch.waves, c->launch.prefetch, c->ntiles, kModeStep, s);
 }
 
 template <typename real>
@@ -390,8 +463,7 @@ StepArgs<real> make_args(lbm_ctx *c, int src_buf) {
 template <typename real>
 int step_direct(lbm_ctx *c, int64_t n) {
   for (int64_t k = 0; k < n; ++k) {
-    StepArgs<real> a = make_args<real>(c, c->cur);
-    HIP_TRY(launch_step<real>(a, c->launch.waves, c->ntiles, kModeStep, c->stream));
+    HIP_TRY(launch_one_step<real>(c, make_args<real>(c, c->cur), c->stream));
     c->cur ^= 1;
     c->t += 1;
   }
@@ -417,7 +489,7 @@ int build_graphs(lbm_ctx *c, int chunk) {
       StepArgs<real> a = make_args<real>(c, buf);
       a.t = k;
       a.t_dev = c->d_time.p;
-      launch_step<real>(a, c->launch.waves, c->ntiles, kModeStep, cs);
+      launch_one_step<real>(c, a, cs);
       buf ^= 1;
     }
     launch_add_time(c->d_time.p, chunk, cs);
@@ -713,18 +785,23 @@ int lbm_moments(lbm_ctx *c, int32_t g, void *out6) {
   if (!out6) return fail(LBM_E_INVALID, "out6 is null");
   rc = commit(c);
   if (rc) return rc;
+  // The general kernel in moments mode over both tile lists.
   if (c->dtype == LBM_F64) {
     StepArgs<double> a = make_args<double>(c, c->cur);
     a.fout = nullptr;
     a.mom = reinterpret_cast<double *>(out6);
     a.mom_grid = g;
-    HIP_TRY(launch_step<double>(a, c->launch.waves, c->ntiles, kModeMoments, c->stream));
+    HIP_TRY(launch_step<double>(a, c->launch.waves, 1, c->ntiles, kModeMoments, c->stream));
+    a.tiles = c->d_tiles_int.p;
+    HIP_TRY(launch_step<double>(a, c->launch.waves, 1, c->ntiles_int, kModeMoments, c->stream));
   } else {
     StepArgs<float> a = make_args<float>(c, c->cur);
     a.fout = nullptr;
     a.mom = reinterpret_cast<float *>(out6);
     a.mom_grid = g;
-    HIP_TRY(launch_step<float>(a, c->launch.waves, c->ntiles, kModeMoments, c->stream));
+    HIP_TRY(launch_step<float>(a, c->launch.waves, 1, c->ntiles, kModeMoments, c->stream));
+    a.tiles = c->d_tiles_int.p;
+    HIP_TRY(launch_step<float>(a, c->launch.waves, 1, c->ntiles_int, kModeMoments, c->stream));
   }
   return LBM_OK;
 }
@@ -743,14 +820,15 @@ int lbm_get_state(lbm_ctx *c, int32_t g, void *dst) {
   if (g < 0 || g >= c->nbatch || !dst) return fail(LBM_E_INVALID, "bad grid index or dst");
   const lbm_grid &G = c->grids[g];
   const int64_t n = (int64_t)G.nx * G.ny;
+  const int64_t ps = c->L.pitch[g], ys = 9 * (int64_t)c->L.pitch[g];
   if (c->dtype == LBM_F64) {
     HIP_TRY(launch_copy_planes<double>(reinterpret_cast<const double *>(c->fbuf[c->cur]) + c->L.f_off[g],
-                                       c->L.plane[g], c->L.pitch[g], reinterpret_cast<double *>(dst), n,
-                                       G.nx, G.nx, G.ny, 9, c->stream));
+                                       ps, ys, reinterpret_cast<double *>(dst), n, G.nx, G.nx, G.ny,
+                                       9, c->stream));
   } else {
     HIP_TRY(launch_copy_planes<float>(reinterpret_cast<const float *>(c->fbuf[c->cur]) + c->L.f_off[g],
-                                      c->L.plane[g], c->L.pitch[g], reinterpret_cast<float *>(dst), n,
-                                      G.nx, G.nx, G.ny, 9, c->stream));
+                                      ps, ys, reinterpret_cast<float *>(dst), n, G.nx, G.nx, G.ny, 9,
+                                      c->stream));
   }
   return LBM_OK;
 }
@@ -762,14 +840,15 @@ int lbm_set_state(lbm_ctx *c, int32_t g, const void *src, int64_t t) {
   if (t < 0) return fail(LBM_E_INVALID, "t must be >= 0");
   const lbm_grid &G = c->grids[g];
   const int64_t n = (int64_t)G.nx * G.ny;
+  const int64_t ps = c->L.pitch[g], ys = 9 * (int64_t)c->L.pitch[g];
   if (c->dtype == LBM_F64) {
     HIP_TRY(launch_copy_planes<double>(reinterpret_cast<const double *>(src), n, G.nx,
                                        reinterpret_cast<double *>(c->fbuf[c->cur]) + c->L.f_off[g],
-                                       c->L.plane[g], c->L.pitch[g], G.nx, G.ny, 9, c->stream));
+                                       ps, ys, G.nx, G.ny, 9, c->stream));
   } else {
     HIP_TRY(launch_copy_planes<float>(reinterpret_cast<const float *>(src), n, G.nx,
                                       reinterpret_cast<float *>(c->fbuf[c->cur]) + c->L.f_off[g],
-                                      c->L.plane[g], c->L.pitch[g], G.nx, G.ny, 9, c->stream));
+                                      ps, ys, G.nx, G.ny, 9, c->stream));
   }
   if (t != c->t) {
     // The context moves to time t: every grid's trace restarts at row 0 = t.
@@ -816,8 +895,13 @@ int lbm_set_launch(lbm_ctx *c, const lbm_launch *cfg) {
   if (cfg->waves != 1 && cfg->waves != 2 && cfg->waves != 4) return fail(LBM_E_INVALID, "waves must be 1, 2 or 4");
   if (cfg->rows < 1) return fail(LBM_E_INVALID, "rows must be >= 1");
   if (cfg->graph_chunk < 0) return fail(LBM_E_INVALID, "graph_chunk must be >= 0");
-  const bool retile = cfg->waves != c->launch.waves || cfg->rows != c->launch.rows;
+  if (cfg->prefetch < 0 || cfg->prefetch > 2) return fail(LBM_E_INVALID, "prefetch must be 1 or 2");
+  const bool retile = cfg->waves != c->launch.waves || cfg->rows != c->launch.rows ||
+                      cfg->split != c->launch.split;
+  const bool regraph = retile || cfg->prefetch != c->launch.prefetch;
   c->launch = *cfg;
+  if (c->launch.prefetch == 0) c->launch.prefetch = 1;
+  if (regraph) drop_graphs(c);
   if (c->launch.graph_chunk % 2) c->launch.graph_chunk += 1;   // keep buffer parity
   if (retile) return rebuild_tiles(c);
   if (c->gchunk != c->launch.graph_chunk) drop_graphs(c);
@@ -846,10 +930,11 @@ int lbm_autotune(lbm_ctx *c, int32_t steps, lbm_launch *chosen) {
   lbm_launch best = keep;
   float best_ms = 1e30f;
   const int waves_c[3] = {1, 2, 4};
-  const int rows_c[6] = {8, 16, 32, 64, 128, 256};
+  const int rows_c[7] = {8, 16, 24, 32, 48, 64, 128};
+  for (int pf = 1; pf <= 2; ++pf)
   for (int wi = 0; wi < 3 && e == hipSuccess && rc == LBM_OK; ++wi)
-    for (int ri = 0; ri < 6 && e == hipSuccess && rc == LBM_OK; ++ri) {
-      lbm_launch cand{waves_c[wi], rows_c[ri], 0, 0};
+    for (int ri = 0; ri < 7 && e == hipSuccess && rc == LBM_OK; ++ri) {
+      lbm_launch cand{waves_c[wi], rows_c[ri], 0, pf, keep.split};
       const int64_t tiles = cells / ((int64_t)64 * cand.waves * cand.rows);
       if (tiles < 512 && !(cand.waves == 1 && cand.rows == 8)) continue;
       c->launch = cand;
@@ -897,6 +982,7 @@ int lbm_destroy(lbm_ctx *c) {
   drop_graphs(c);
   c->d_grids.release();
   c->d_tiles.release();
+  c->d_tiles_int.release();
   c->d_krows.release();
   c->d_sponge.release();
   c->d_src.release();

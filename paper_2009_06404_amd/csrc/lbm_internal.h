@@ -10,15 +10,17 @@ namespace lbm {
 // D2Q9, direction order (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1).
 constexpr int kQ = 9;
 constexpr int kEdgeTop = 0, kEdgeBottom = 1, kEdgeLeft = 2, kEdgeRight = 3;
-constexpr int kPeriodic = 0, kFree = 1, kRigid = 2;
+constexpr int kPeriodic = 0, kFree = 1, kRigid = 2, kFree0 = 3;
 constexpr int kKappaScalar = 0, kKappaRows = 1, kKappaCells = 2;
 
 // One grid of a (possibly batched) context. Offsets are in elements of the
 // context's dtype unless stated otherwise.
+// Populations of a grid: population i of cell (x, y) at
+// f_off + (y * 9 + i) * pitch + x of a population buffer.
 struct GridDev {
-  int32_t nx, ny, pitch, kmode;   // pitch: elements per stored row
-  int64_t f_off;                  // offset of plane 0 inside a population buffer
-  int64_t plane;                  // elements per plane (ny * pitch)
+  int32_t nx, ny, pitch, kmode;   // pitch: elements per stored population run
+  int64_t f_off;                  // offset of the grid inside a population buffer
+  int64_t plane;                  // ny * pitch (size of the kappa cell plane)
   int32_t bc[4];
   int32_t rigid_row;              // -1 none
   int32_t nsrc, src_off;          // sources [src_off, src_off + nsrc)
@@ -70,8 +72,11 @@ struct StepArgs {
 enum Mode { kModeStep = 0, kModeMoments = 1 };
 
 template <typename real>
-hipError_t launch_step(const StepArgs<real> &a, int waves, int ntiles, int mode,
+hipError_t launch_step(const StepArgs<real> &a, int waves, int prefetch, int ntiles, int mode,
                        hipStream_t stream);
+
+template <typename real>
+hipError_t launch_interior(const StepArgs<real> &a, int waves, int ntiles, hipStream_t stream);
 
 // Initialisation and utility kernels (lbm_util.hip).
 template <typename real>
@@ -87,8 +92,8 @@ hipError_t launch_gather(const real *src, const int64_t *idx, int n, real *dst,
 template <typename real>
 hipError_t launch_count_nonfinite(const real *f, int64_t n, int *count, hipStream_t stream);
 template <typename real>
-hipError_t launch_copy_planes(const real *src, int64_t src_plane, int src_pitch, real *dst,
-                              int64_t dst_plane, int dst_pitch, int nx, int ny, int nplanes,
+hipError_t launch_copy_planes(const real *src, int64_t src_ps, int64_t src_ys, real *dst,
+                              int64_t dst_ps, int64_t dst_ys, int nx, int ny, int nplanes,
                               hipStream_t stream);
 hipError_t launch_set_time(int64_t *t_dev, int64_t value, hipStream_t stream);
 hipError_t launch_add_time(int64_t *t_dev, int64_t delta, hipStream_t stream);

@@ -18,10 +18,24 @@
 //   5. relaxes toward the elastic equilibrium (eqs. equilibrium-solid, Pn) with
 //      the forcing populations of eq. Si and writes f*(t), one store per
 //      population, to the other buffer of the ping-pong pair.
-// Each population is read once and written once per step from HBM; the halo
-// reads for step 3 and the boundary-row moments for the free surface come from
-// L2. Populations are kept as structure-of-arrays planes with a pitch of a
-// multiple of 64 elements so every wavefront load and store is a full line.
+//
+// Memory: each population is read once and written once per step from HBM;
+// the rows above/below a tile and the halo columns are re-read from L2. The
+// pulled rows (and the halo columns) are prefetched two rows ahead so that a
+// wavefront keeps a full row of loads in flight while it computes; stores are
+// non-temporal so the write stream does not evict the lines neighbouring
+// tiles still have to read. Populations are stored row by row: population i
+// of row y is a contiguous run of `pitch` elements at ((y*9 + i) * pitch), the
+// pitch a multiple of 64 elements, so every wavefront access is one contiguous
+// 64-element span and a tile's rows are one contiguous region (a single
+// buffer descriptor covers all nine populations of a tile).
+//
+// Arithmetic: with b^2 = 1/3 the equilibrium and forcing populations times 36
+// have small integer coefficients in (rho, j, P, S); they are formed exactly
+// that way and divided by 36 once, with an FMA-corrected reciprocal. Writing
+// them with the rounded constants 1/3, 1/9, 1/36 instead biases every step in
+// the same direction (the collision invariants drift by ~1e-8 per step in
+// FP32), which grows linearly with the step count.
 #include "lbm_internal.h"
 
 namespace lbm {
@@ -31,16 +45,21 @@ constexpr int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 constexpr int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 
+// v / 36 for the integer-coefficient combinations: one multiply by the
+// rounded reciprocal and one Newton correction with the exact residual.
 template <typename real>
-__device__ __forceinline__ constexpr real weight(int i) {
-  return i == 0 ? real(4) / real(9) : (i < 5 ? real(1) / real(9) : real(1) / real(36));
+__device__ __forceinline__ real div36(real v) {
+  const real r = real(1) / real(36);
+  const real q = v * r;
+  const real e = fma(-q, real(36), v);
+  return fma(e, r, q);
 }
 
 // Row classification for the pull of row y (uniform across the workgroup).
 struct Row {
   int y;
-  int up, dn;          // source rows of links arriving with c_y = +1 / -1
-  int wall_up, wall_dn;// 0, kFree or kRigid: the wall those links cross
+  int up, dn;           // source rows of links arriving with c_y = +1 / -1
+  int wall_up, wall_dn; // 0, kFree, kFree0 or kRigid: the wall those links cross
 };
 
 __device__ __forceinline__ Row make_row(const GridDev &g, int y) {
@@ -67,10 +86,16 @@ __device__ __forceinline__ Row make_row(const GridDev &g, int y) {
   return r;
 }
 
+// The row after y in the marching order, or -1 past a non-periodic bottom.
+__device__ __forceinline__ int row_after(const GridDev &g, int y) {
+  if (y + 1 < g.ny) return y + 1;
+  return g.bc[kEdgeBottom] == kPeriodic ? 0 : -1;
+}
+
 // Column classification for one lane (left/right edges: periodic or rigid).
 struct Col {
-  int x, xl, xr;   // own column, source column for c_x = +1 and c_x = -1
-  bool wl, wr;     // links with c_x = +1 / -1 cross a rigid edge
+  int x, xl, xr;  // own column, source column for c_x = +1 and c_x = -1
+  bool wl, wr;    // links with c_x = +1 / -1 cross a rigid edge
 };
 
 __device__ __forceinline__ Col make_col(const GridDev &g, int x) {
@@ -91,69 +116,79 @@ __device__ __forceinline__ Col make_col(const GridDev &g, int x) {
   return c;
 }
 
-// Pulled populations f_i(x, t) of cell (c.x, r.y) from the state f*(t-1).
+// Offset of population i of cell (x, y): rows of nine population runs.
+__device__ __forceinline__ int64_t qidx(const GridDev &g, int i, int y, int x) {
+  return ((int64_t)y * 9 + i) * g.pitch + x;
+}
+
+// Pulled populations of a row without a horizontal wall (general addressing:
+// used for halo columns and for tiles that touch a rigid side edge).
 template <typename real>
-__device__ __forceinline__ void pull(const real *__restrict__ base, const GridDev &g,
-                                     const Row &r, const Col &c, real out[9]) {
-  const int64_t P = g.plane;
-  const int64_t ro = (int64_t)r.y * g.pitch;
-  const int64_t ru = (int64_t)r.up * g.pitch;
-  const int64_t rd = (int64_t)r.dn * g.pitch;
-  if ((r.wall_up | r.wall_dn) == 0) {
+__device__ __forceinline__ void pull_interior(const real *__restrict__ base, const GridDev &g,
+                                              const Row &r, const Col &c, real out[9]) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      const int64_t row = CY[i] == 0 ? ro : (CY[i] == 1 ? ru : rd);
-      const int col = CX[i] == 0 ? c.x : (CX[i] == 1 ? c.xl : c.xr);
-      const bool xw = CX[i] == 1 ? c.wl : (CX[i] == -1 ? c.wr : false);
-      const int64_t addr = xw ? (OPP[i] * P + ro + c.x) : (i * P + row + col);
-      out[i] = base[addr];
-    }
-    return;
+  for (int i = 0; i < 9; ++i) {
+    const int row = CY[i] == 0 ? r.y : (CY[i] == 1 ? r.up : r.dn);
+    const int col = CX[i] == 0 ? c.x : (CX[i] == 1 ? c.xl : c.xr);
+    const bool xw = CX[i] == 1 ? c.wl : (CX[i] == -1 ? c.wr : false);
+    const int64_t addr = xw ? qidx(g, OPP[i], r.y, c.x) : qidx(g, i, row, col);
+    out[i] = base[addr];
   }
-  // A row next to a horizontal wall. For a free surface, the anti-bounce-back
-  // needs rho and the tangential stress P_xx at the boundary cell and one cell
-  // inside, at time t-1: moments of the stored post-collision populations
-  // (rho and P are collision invariants).
+}
+
+// Pulled populations of a row next to a horizontal wall.
+template <typename real>
+__device__ __forceinline__ void pull_wall(const real *__restrict__ base, const GridDev &g,
+                                          const Row &r, const Col &c, real out[9]) {
+  // The free surface needs rho and the tangential stress P_xx of the boundary
+  // cell and of the cell inside it at time t-1: moments of the stored
+  // post-collision populations (rho and P are collision invariants),
+  // extrapolated half a cell out linearly (kFree, as printed) or taken from
+  // the boundary cell (kFree0).
   real rho_air = real(0), pxx_air = real(0);
-  const bool free_wall = (r.wall_up == kFree) || (r.wall_dn == kFree);
-  if (free_wall) {
-    const int yin = (r.wall_up == kFree) ? r.y + 1 : r.y - 1;
-    const int64_t rin = (int64_t)yin * g.pitch;
+  const bool free_up = r.wall_up == kFree || r.wall_up == kFree0;
+  const bool free_dn = r.wall_dn == kFree || r.wall_dn == kFree0;
+  if (free_up || free_dn) {
+    const int yin = free_up ? r.y + 1 : r.y - 1;
+    const bool linear = (free_up ? r.wall_up : r.wall_dn) == kFree;
     real rb = 0, xb = 0, ri = 0, xi = 0;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      const real vb = base[i * P + ro + c.x];
-      const real vi = base[i * P + rin + c.x];
+      const real vb = base[qidx(g, i, r.y, c.x)];
+      const real vi = base[qidx(g, i, yin, c.x)];
       rb += vb;
       ri += vi;
       if (CX[i] != 0) { xb += vb; xi += vi; }
     }
-    rho_air = real(1.5) * rb - real(0.5) * ri;
-    pxx_air = real(1.5) * xb - real(0.5) * xi;
+    rho_air = linear ? real(1.5) * rb - real(0.5) * ri : rb;
+    pxx_air = linear ? real(1.5) * xb - real(0.5) * xi : xb;
   }
-  const real b2 = real(1) / real(3);
-  const real pn_xx = pxx_air - b2 * rho_air;
-  const real pn_yy = -b2 * rho_air;
+  // 36 x 2 w_i (rho_air + P^n_air : (c c - b^2 I) / (2 b^4)) for a link with
+  // c_y^2 = 1, P^n_air = diag(P_xx,air - rho_air/3, -rho_air/3):
+  //   vertical link 4 rho_air - 12 P_xx,air, diagonal link 6 P_xx,air - 2 rho_air.
+  const real abb_axis = div36(real(4) * rho_air - real(12) * pxx_air);
+  const real abb_diag = div36(real(6) * pxx_air - real(2) * rho_air);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const int ywall = CY[i] == 1 ? r.wall_up : (CY[i] == -1 ? r.wall_dn : 0);
     const bool xw = CX[i] == 1 ? c.wl : (CX[i] == -1 ? c.wr : false);
     if (ywall == 0 && !xw) {
-      const int64_t row = CY[i] == 0 ? ro : (CY[i] == 1 ? ru : rd);
+      const int row = CY[i] == 0 ? r.y : (CY[i] == 1 ? r.up : r.dn);
       const int col = CX[i] == 0 ? c.x : (CX[i] == 1 ? c.xl : c.xr);
-      out[i] = base[i * P + row + col];
+      out[i] = base[qidx(g, i, row, col)];
     } else {
-      const real refl = base[OPP[i] * P + ro + c.x];
-      if (xw || ywall == kRigid) {
-        out[i] = refl;
-      } else {
-        // -f*_opp + 2 w (rho_air + P^n_air : (c c - b^2 I) / (2 b^4)), c_y^2 = 1
-        const real cxx = real(CX[i] * CX[i]) - b2;
-        const real q = pn_xx * cxx + pn_yy * (real(1) - b2);
-        out[i] = -refl + real(2) * weight<real>(i) * (rho_air + real(4.5) * q);
-      }
+      const real refl = base[qidx(g, OPP[i], r.y, c.x)];
+      if (xw || ywall == kRigid) out[i] = refl;
+      else out[i] = -refl + (CX[i] == 0 ? abb_axis : abb_diag);
     }
   }
+}
+
+template <typename real>
+__device__ __forceinline__ void pull(const real *__restrict__ base, const GridDev &g,
+                                     const Row &r, const Col &c, real out[9]) {
+  if ((r.wall_up | r.wall_dn) == 0) pull_interior(base, g, r, c, out);
+  else pull_wall(base, g, r, c, out);
 }
 
 template <typename real>
@@ -174,7 +209,154 @@ __device__ __forceinline__ double min_image(double d, int n, bool periodic) {
   return d;
 }
 
-template <typename real, int NW, int MODE>
+// Raw buffer access: the tile's rows live behind one buffer descriptor
+// (scalar registers), row and population select a scalar byte offset, and
+// the lane's column a 32-bit vector byte offset, so the interior loads and all
+// stores carry no per-row vector address arithmetic. 0x00020000 is the
+// descriptor's format word for raw accesses on gfx9-family targets.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const void *base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, 0x7fffffff, 0x00020000);
+}
+
+template <typename real>
+struct Buf;
+
+template <>
+struct Buf<float> {
+  static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  }
+  static __device__ __forceinline__ void store_nt(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                  uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 2);
+  }
+};
+
+template <>
+struct Buf<double> {
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ double load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  }
+  static __device__ __forceinline__ void store_nt(double v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                  uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 2);
+  }
+};
+
+// Pull of an interior row (no horizontal wall, no wrap in y, no rigid side
+// edge touched by the tile). rsrc is based at row ybase <= y - 1; rowb is the
+// byte size of one row of nine population runs, qb of one run.
+template <typename real>
+__device__ __forceinline__ void pull_fast(__amdgpu_buffer_rsrc_t rsrc, int ybase, int y,
+                                          uint32_t rowb, uint32_t qb, uint32_t o0, uint32_t ol,
+                                          uint32_t orr, real out[9]) {
+  const uint32_t rc = (uint32_t)(y - ybase) * rowb, ru = rc - rowb, rd = rc + rowb;
+  out[0] = Buf<real>::load(rsrc, o0, rc);            // ( 0, 0)
+  out[1] = Buf<real>::load(rsrc, ol, rc + qb);       // ( 1, 0) from (x-1, y)
+  out[2] = Buf<real>::load(rsrc, o0, ru + 2 * qb);   // ( 0, 1) from (x, y-1)
+  out[3] = Buf<real>::load(rsrc, orr, rc + 3 * qb);  // (-1, 0) from (x+1, y)
+  out[4] = Buf<real>::load(rsrc, o0, rd + 4 * qb);   // ( 0,-1) from (x, y+1)
+  out[5] = Buf<real>::load(rsrc, ol, ru + 5 * qb);   // ( 1, 1) from (x-1, y-1)
+  out[6] = Buf<real>::load(rsrc, orr, ru + 6 * qb);  // (-1, 1) from (x+1, y-1)
+  out[7] = Buf<real>::load(rsrc, orr, rd + 7 * qb);  // (-1,-1) from (x+1, y+1)
+  out[8] = Buf<real>::load(rsrc, ol, rd + 8 * qb);   // ( 1,-1) from (x-1, y+1)
+}
+
+// Moments of the pulled populations with the flux and the sponge-corrected
+// source: j = (m + G/2)/(1 + A/2), S = G - A j (eqs. MomentsFeq, S and
+// MomentChainAbsorbing, the sponge term solved implicitly).
+template <typename real>
+struct CellState {
+  real rho, jx, jy, pxx, pxy, pyy, Sx, Sy;
+};
+
+template <typename real>
+__device__ __forceinline__ CellState<real> cell_state(const real f[9], real rho, real Gx, real Gy,
+                                                      real A, real inv) {
+  CellState<real> c;
+  const real mx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+  const real my = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+  const real diag = (f[5] + f[6]) + (f[7] + f[8]);
+  c.rho = rho;
+  c.pxx = (f[1] + f[3]) + diag;
+  c.pyy = (f[2] + f[4]) + diag;
+  c.pxy = (f[5] + f[7]) - (f[6] + f[8]);
+  c.jx = (mx + real(0.5) * Gx) * inv;
+  c.jy = (my + real(0.5) * Gy) * inv;
+  c.Sx = Gx - A * c.jx;
+  c.Sy = Gy - A * c.jy;
+  return c;
+}
+
+// BGK collision with forcing, f*_i = (1 - w) f_i + w f^eq_i + c_f S_i
+// (w = 1/tau, c_f = 1 - 1/(2 tau); eqs. LBGK, equilibrium-solid, Pn, Si),
+// written as f_i - w f_i + E_i / 36 with E_i = 36 (w f^eq_i + c_f S_i):
+// 36 f^eq_i and 36 S_i have integer coefficients in rho, j, P, S (b^2 = 1/3;
+// weights 16, 4, 1 over 36), and the j- and S-terms share their coefficients,
+// so E_i is the equilibrium combination of (w rho, w j + c_f S, w P).
+template <typename real>
+__device__ __forceinline__ void collide(const real f[9], const CellState<real> &c, real omega,
+                                        real cforce, real out[9]) {
+  const real wr = omega * c.rho, wxx = omega * c.pxx, wyy = omega * c.pyy, wxy = omega * c.pxy;
+  const real ux = fma(omega, c.jx, cforce * c.Sx);
+  const real uy = fma(omega, c.jy, cforce * c.Sy);
+  const real spp = wxx + wyy;
+  const real e0 = real(32) * wr - real(24) * spp;
+  const real ax = real(2) * wr + real(12) * wxx - real(6) * wyy;
+  const real ay = real(2) * wr + real(12) * wyy - real(6) * wxx;
+  const real d = real(3) * spp - wr;
+  const real u12x = real(12) * ux, u12y = real(12) * uy;
+  const real tp = real(3) * (ux + uy), tm = real(3) * (uy - ux), q9 = real(9) * wxy;
+  const real E[9] = {e0, ax + u12x, ay + u12y, ax - u12x, ay - u12y,
+                     d + tp + q9, d + tm - q9, d - tp + q9, d - tm - q9};
+#pragma unroll
+  for (int i = 0; i < 9; ++i) out[i] = fma(-omega, f[i], f[i]) + div36(E[i]);
+}
+
+// Elastic coefficient of cell (x, y).
+template <typename real>
+__device__ __forceinline__ real cell_kappa(const StepArgs<real> &a, const GridDev &g, int y, int x) {
+  if (g.kmode == kKappaScalar) return (real)g.kscalar;
+  if (g.kmode == kKappaRows) return a.kappa_rows[g.k_off + y];
+  return a.kappa_cells[g.k_off + (int64_t)y * g.pitch + x];
+}
+
+// Sponge pair (A, 1/(1 + A/2)) along x for column x (left/right layers). The
+// table holds the pairs; the second decreases with the first, so the largest
+// A of overlapping layers pairs with the smallest reciprocal.
+template <typename real>
+__device__ __forceinline__ void sponge_x(const StepArgs<real> &a, const GridDev &g, int x, real &A,
+                                         real &inv) {
+  A = real(0);
+  inv = real(1);
+  const int dl = x, dr = g.nx - 1 - x;
+  if (dl < g.sp_thick[kEdgeLeft]) {
+    A = a.sponge[g.sp_off[kEdgeLeft] + 2 * dl];
+    inv = a.sponge[g.sp_off[kEdgeLeft] + 2 * dl + 1];
+  }
+  if (dr < g.sp_thick[kEdgeRight]) {
+    A = max(A, a.sponge[g.sp_off[kEdgeRight] + 2 * dr]);
+    inv = min(inv, a.sponge[g.sp_off[kEdgeRight] + 2 * dr + 1]);
+  }
+}
+
+// Add the top/bottom layers of row y to a column's sponge pair.
+template <typename real>
+__device__ __forceinline__ void sponge_y(const StepArgs<real> &a, const GridDev &g, int y, real &A,
+                                         real &inv) {
+  const int dt_ = y, db = g.ny - 1 - y;
+  if (dt_ < g.sp_thick[kEdgeTop]) {
+    A = max(A, a.sponge[g.sp_off[kEdgeTop] + 2 * dt_]);
+    inv = min(inv, a.sponge[g.sp_off[kEdgeTop] + 2 * dt_ + 1]);
+  }
+  if (db < g.sp_thick[kEdgeBottom]) {
+    A = max(A, a.sponge[g.sp_off[kEdgeBottom] + 2 * db]);
+    inv = min(inv, a.sponge[g.sp_off[kEdgeBottom] + 2 * db + 1]);
+  }
+}
+
+template <typename real, int NW, int MODE, int PF>
 __global__ __launch_bounds__(64 * NW) void step_kernel(StepArgs<real> a) {
   constexpr int W = 64 * NW;
   __shared__ real srho[2][W + 2];
@@ -184,27 +366,35 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepArgs<real> a) {
   if (MODE == kModeMoments && tile.g != a.mom_grid) return;
   const GridDev &g = a.grids[tile.g];
   const real *__restrict__ fin = a.fin + g.f_off;
+  const int pitch = g.pitch, nx = g.nx, ny = g.ny, rr = g.rigid_row;
 
   const int lane = threadIdx.x;
   const int x = tile.x0 + lane;
-  const bool active = x < g.nx;
-  const int xa = active ? x : g.nx - 1;
+  const bool active = x < nx;
+  const int xa = active ? x : nx - 1;
   const Col col = make_col(g, xa);
-  const int x_last = min(tile.x0 + W, g.nx) - 1;
+  const int x_last = min(tile.x0 + W, nx) - 1;
+  const uint32_t o0 = (uint32_t)xa * sizeof(real);
+  const uint32_t ol = (uint32_t)col.xl * sizeof(real);
+  const uint32_t orr = (uint32_t)col.xr * sizeof(real);
+  // Tiles that touch a rigid side edge take the general pull on every row.
+  const bool fast_x = !((g.bc[kEdgeLeft] == kRigid && tile.x0 == 0) ||
+                        (g.bc[kEdgeRight] == kRigid && x_last == nx - 1));
 
   // Lanes 0 and 1 also pull the tile's outer neighbour columns (for the
-  // density gradient of the first and last column).
+  // density gradient of the tile's first and last column).
   int hx = 0;
   bool hvalid = false;
   if (lane == 0) {
     hx = tile.x0 - 1;
     hvalid = true;
-    if (hx < 0) { hvalid = g.bc[kEdgeLeft] == kPeriodic; hx = g.nx - 1; }
+    if (hx < 0) { hvalid = g.bc[kEdgeLeft] == kPeriodic; hx = nx - 1; }
   } else if (lane == 1) {
     hx = x_last + 1;
     hvalid = true;
-    if (hx >= g.nx) { hvalid = g.bc[kEdgeRight] == kPeriodic; hx = 0; }
+    if (hx >= nx) { hvalid = g.bc[kEdgeRight] == kPeriodic; hx = 0; }
   }
+  const bool hlane = lane < 2 && hvalid;
   const Col hcol = make_col(g, hx);
   const int hslot = lane == 0 ? 0 : W + 1;
 
@@ -213,48 +403,99 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepArgs<real> a) {
   const real cforce = a.cforce;
   const bool px = g.bc[kEdgeLeft] == kPeriodic;
   const bool py = g.bc[kEdgeTop] == kPeriodic;
+  const int y0 = tile.y0, y1 = tile.y1;
+  // One descriptor per direction for all rows the tile touches (from two
+  // rows above its first row, the lowest row an interior pull reads).
+  const int ybase = max(y0 - 2, 0);
+  const uint32_t qb = (uint32_t)pitch * sizeof(real);
+  const uint32_t rowb = 9 * qb;
+  const __amdgpu_buffer_rsrc_t rin = tile_rsrc(fin + (int64_t)ybase * 9 * pitch);
+  const __amdgpu_buffer_rsrc_t rout = tile_rsrc(a.fout + g.f_off + (int64_t)ybase * 9 * pitch);
 
-  // Prologue: first row and the density of the row above it.
-  Row r = make_row(g, tile.y0);
-  real fc[9];
-  pull(fin, g, r, col, fc);
-  real rho_c = sum9(fc);
+  real A_x, inv_x;
+  sponge_x(a, g, xa, A_x, inv_x);
+
+  // Rows with a horizontal wall link or a wrap in y.
+  auto special = [&](int y) -> bool {
+    return y == 0 || y == ny - 1 || (rr > 0 && (y == rr - 1 || y == rr));
+  };
+  auto pull_row = [&](int y, real out[9]) {
+    if (fast_x && !special(y)) pull_fast(rin, ybase, y, rowb, qb, o0, ol, orr, out);
+    else pull(fin, g, make_row(g, y), col, out);
+  };
+  auto pull_halo = [&](int y) -> real {
+    real fh[9];
+    pull(fin, g, make_row(g, y), hcol, fh);
+    return sum9(fh);
+  };
+  // Whether the row after y is pulled while marching: as the next output row,
+  // or for the density gradient of row y.
+  auto need_after = [&](int y) -> bool {
+    if (row_after(g, y) < 0) return false;
+    if (y + 1 < y1) return true;
+    return !special(y) || make_row(g, y).wall_dn == 0;
+  };
+
+  // Prologue: density of the row above the tile and the first row.
+  int wall_up = special(y0) ? make_row(g, y0).wall_up : 0;
   real rho_m = real(0);
-  if (r.wall_up == 0) {
+  if (wall_up == 0) {
+    const int ya = y0 > 0 ? y0 - 1 : ny - 1;
     real fm[9];
-    pull(fin, g, make_row(g, r.up), col, fm);
+    pull_row(ya, fm);
     rho_m = sum9(fm);
   }
+  real fa[9], fb[9], hb[9];
+  pull_row(y0, fa);
+  real rho_c = sum9(fa);
   srho[0][lane + 1] = rho_c;
-  if (lane < 2) {
-    real hr = real(0);
-    if (hvalid) { real fh[9]; pull(fin, g, r, hcol, fh); hr = sum9(fh); }
-    srho[0][hslot] = hr;
+  if (lane < 2) srho[0][hslot] = hlane ? pull_halo(y0) : real(0);
+  bool nb = need_after(y0);
+  int yb = nb ? row_after(g, y0) : y0;
+  if (PF == 2) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) { fb[i] = real(0); hb[i] = real(0); }
+    if (nb) {
+      pull_row(yb, fb);
+      if (hlane) pull(fin, g, make_row(g, yb), hcol, hb);
+    }
   }
   __syncthreads();
 
-  for (int y = tile.y0, k = 0; y < tile.y1; ++y, ++k) {
-    // Next row: needed as the next output row and/or for d rho / dy.
-    int yn = y + 1;
-    if (yn >= g.ny) yn = (g.bc[kEdgeBottom] == kPeriodic) ? 0 : -1;
-    const bool need_next = yn >= 0 && ((y + 1 < tile.y1) || r.wall_dn == 0);
-    const Row rn = make_row(g, yn < 0 ? y : yn);
-    real fn[9];
-    real rho_n = real(0);
-    if (need_next) {
-      pull(fin, g, rn, col, fn);
-      rho_n = sum9(fn);
+  for (int y = y0, k = 0; y < y1; ++y, ++k) {
+    const int wall_dn = special(y) ? make_row(g, y).wall_dn : 0;
+    real rho_n = real(0), hr_n = real(0);
+    bool nc = false;
+    int yc = y;
+    real fc[9], hc[9];
+    if (PF == 2) {
+      // Row y+1 (fb) has been in flight since the previous iteration; issue
+      // row y+2 now so it is in flight while row y is computed.
+      if (nb) { rho_n = sum9(fb); hr_n = sum9(hb); }
+      nc = nb && (y + 1 < y1) && need_after(yb);
+      yc = nc ? row_after(g, yb) : y;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) { fc[i] = real(0); hc[i] = real(0); }
+      if (nc) {
+        pull_row(yc, fc);
+        if (hlane) pull(fin, g, make_row(g, yc), hcol, hc);
+      }
+    } else {
+      nb = need_after(y);
+      yb = nb ? row_after(g, y) : y;
+      if (nb) {
+        pull_row(yb, fb);
+        rho_n = sum9(fb);
+        if (hlane) hr_n = pull_halo(yb);
+      }
     }
+
     const int s = k & 1;
     const real rho_l = srho[s][lane];
     const real rho_r = (xa == x_last) ? srho[s][W + 1] : srho[s][lane + 2];
-    if (need_next) {
+    if (nb) {
       srho[s ^ 1][lane + 1] = rho_n;
-      if (lane < 2) {
-        real hr = real(0);
-        if (hvalid) { real fh[9]; pull(fin, g, rn, hcol, fh); hr = sum9(fh); }
-        srho[s ^ 1][hslot] = hr;
-      }
+      if (lane < 2) srho[s ^ 1][hslot] = hr_n;
     }
 
     // Centred density gradient (eq. FDrho); one-sided next to walls.
@@ -262,35 +503,23 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepArgs<real> a) {
     if (col.wl) dx = rho_r - rho_c;
     else if (col.wr) dx = rho_c - rho_l;
     else dx = real(0.5) * (rho_r - rho_l);
-    if (r.wall_up) dy = rho_n - rho_c;
-    else if (r.wall_dn) dy = rho_c - rho_m;
+    if (wall_up) dy = rho_n - rho_c;
+    else if (wall_dn) dy = rho_c - rho_m;
     else dy = real(0.5) * (rho_n - rho_m);
 
-    // Elastic coefficient.
-    real kap;
-    if (g.kmode == kKappaScalar) kap = (real)g.kscalar;
-    else if (g.kmode == kKappaRows) kap = a.kappa_rows[g.k_off + y];
-    else kap = a.kappa_cells[g.k_off + (int64_t)y * g.pitch + xa];
-
-    // Absorbing-layer damping.
-    real A = real(0);
-    {
-      const int dt_ = y, db = g.ny - 1 - y, dl = xa, dr = g.nx - 1 - xa;
-      if (dt_ < g.sp_thick[kEdgeTop]) A = max(A, a.sponge[g.sp_off[kEdgeTop] + dt_]);
-      if (db < g.sp_thick[kEdgeBottom]) A = max(A, a.sponge[g.sp_off[kEdgeBottom] + db]);
-      if (dl < g.sp_thick[kEdgeLeft]) A = max(A, a.sponge[g.sp_off[kEdgeLeft] + dl]);
-      if (dr < g.sp_thick[kEdgeRight]) A = max(A, a.sponge[g.sp_off[kEdgeRight] + dr]);
-    }
+    const real kap = cell_kappa(a, g, y, xa);
+    real A = A_x, inv = inv_x;
+    sponge_y(a, g, y, A, inv);
 
     // Body force (Gaussian x Ricker), only on rows within 9 sigma of a source.
     real Fx = real(0), Fy = real(0);
     for (int si = 0; si < g.nsrc; ++si) {
       const SourceDev sd = a.sources[g.src_off + si];
-      const double ddy = min_image((double)y - sd.y, g.ny, py);
+      const double ddy = min_image((double)y - sd.y, ny, py);
       const double cut = 81.0 * sd.sigma * sd.sigma;
       if (ddy * ddy > cut) continue;
       const double R = ricker((double)t, sd.period, sd.t0);
-      const double ddx = min_image((double)xa - sd.x, g.nx, px);
+      const double ddx = min_image((double)xa - sd.x, nx, px);
       const double r2 = ddx * ddx + ddy * ddy;
       if (r2 <= cut) {
         const double mag = sd.amp * exp(-r2 / (2.0 * sd.sigma * sd.sigma)) * R;
@@ -301,26 +530,13 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepArgs<real> a) {
 
     const real Gx = kap * dx + Fx;
     const real Gy = kap * dy + Fy;
-
-    // Moments of the pulled populations.
-    const real rho = rho_c;
-    const real mx = (fc[1] - fc[3]) + (fc[5] - fc[6]) + (fc[8] - fc[7]);
-    const real my = (fc[2] - fc[4]) + (fc[5] + fc[6]) - (fc[7] + fc[8]);
-    const real diag = (fc[5] + fc[6]) + (fc[7] + fc[8]);
-    const real pxx = (fc[1] + fc[3]) + diag;
-    const real pyy = (fc[2] + fc[4]) + diag;
-    const real pxy = (fc[5] + fc[7]) - (fc[6] + fc[8]);
-
-    const real inv = real(1) / (real(1) + real(0.5) * A);
-    const real jx = (mx + real(0.5) * Gx) * inv;
-    const real jy = (my + real(0.5) * Gy) * inv;
-    const real Sx = Gx - A * jx;
-    const real Sy = Gy - A * jy;
+    const CellState<real> cs = cell_state(fa, rho_c, Gx, Gy, A, inv);
+    const real rho = cs.rho, jx = cs.jx, jy = cs.jy, pxx = cs.pxx, pxy = cs.pxy, pyy = cs.pyy;
 
     if (MODE == kModeMoments) {
       if (active) {
-        const int64_t n = (int64_t)g.nx * g.ny;
-        const int64_t o = (int64_t)y * g.nx + x;
+        const int64_t n = (int64_t)nx * ny;
+        const int64_t o = (int64_t)y * nx + x;
         a.mom[o] = rho;
         a.mom[n + o] = jx;
         a.mom[2 * n + o] = jy;
@@ -333,7 +549,7 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepArgs<real> a) {
       if (g.nrec > 0) {
         const int slot = a.itab[g.rowtab_off + y];
         if (slot >= 0 && active) {
-          int rid = a.itab[g.rmap_off + (int64_t)slot * g.nx + x];
+          int rid = a.itab[g.rmap_off + (int64_t)slot * nx + x];
           const int64_t tk = t - g.trace_t0;
           while (rid >= 0) {
             if (tk >= 0 && tk < g.trace_max) {
@@ -347,29 +563,122 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepArgs<real> a) {
           }
         }
       }
-      // Equilibrium (b^2 = 1/3: 1/b^2 = 3, 1/(2 b^4) = 9/2) and BGK collision.
-      const real b2 = real(1) / real(3);
-      const real pnxx = pxx - b2 * rho;
-      const real pnyy = pyy - b2 * rho;
-      const real pnxy = pxy;
       if (active) {
-        real *__restrict__ out = a.fout + g.f_off + (int64_t)y * g.pitch + x;
+        real fs[9];
+        collide(fa, cs, omega, cforce, fs);
+        const uint32_t rs = (uint32_t)(y - ybase) * rowb;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-          const real cx = real(CX[i]), cy = real(CY[i]);
-          const real q = pnxx * (cx * cx - b2) + real(2) * pnxy * (cx * cy) + pnyy * (cy * cy - b2);
-          const real feq = weight<real>(i) * (rho + real(3) * (jx * cx + jy * cy) + real(4.5) * q);
-          const real si = weight<real>(i) * real(3) * (cx * Sx + cy * Sy);
-          out[i * g.plane] = fc[i] - omega * (fc[i] - feq) + cforce * si;
-        }
+        for (int i = 0; i < 9; ++i) Buf<real>::store_nt(fs[i], rout, o0, rs + i * qb);
       }
     }
 
-    // March.
+    // March: row y+1 becomes current (and row y+2 is in flight).
     __syncthreads();
-    r = rn;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) fc[i] = need_next ? fn[i] : fc[i];
+    for (int i = 0; i < 9; ++i) {
+      fa[i] = fb[i];
+      if (PF == 2) { fb[i] = fc[i]; hb[i] = hc[i]; }
+    }
+    if (PF == 2) { yb = yc; nb = nc; }
+    wall_up = (y + 1 < y1 && special(y + 1)) ? make_row(g, y + 1).wall_up : 0;
+    rho_m = rho_c;
+    rho_c = rho_n;
+  }
+}
+
+// The step for interior tiles: every row the tile pulls (one above, its own,
+// one below) is at least one row away from a horizontal wall or wrap, every
+// column it touches (with its halo) has both x-neighbours inside the grid or
+// wraps periodically, no source band reaches its rows and no receiver sits
+// in them. The host sorts tiles into this list; the arithmetic is the same
+// code as the general kernel's, so a cell's result does not depend on which
+// kernel updated it.
+template <typename real, int NW>
+__global__ __launch_bounds__(64 * NW) void interior_kernel(StepArgs<real> a) {
+  constexpr int W = 64 * NW;
+  __shared__ real srho[2][W + 2];
+
+  const TileDev tile = a.tiles[blockIdx.x];
+  if (tile.g < 0) return;                        // padding block (uniform)
+  const GridDev &g = a.grids[tile.g];
+  const real *__restrict__ fin = a.fin + g.f_off;
+  const int pitch = g.pitch, nx = g.nx;
+
+  const int lane = threadIdx.x;
+  const int x = tile.x0 + lane;
+  const bool active = x < nx;
+  const int xa = active ? x : nx - 1;
+  const int x_last = min(tile.x0 + W, nx) - 1;
+  const uint32_t esz = sizeof(real);
+  auto wrapx = [&](int c) { return c < 0 ? c + nx : (c >= nx ? c - nx : c); };
+  const uint32_t o0 = (uint32_t)xa * esz;
+  const uint32_t ol = (uint32_t)wrapx(xa - 1) * esz;
+  const uint32_t orr = (uint32_t)wrapx(xa + 1) * esz;
+  // Halo columns (lanes 0 and 1).
+  const int hx = lane == 0 ? wrapx(tile.x0 - 1) : wrapx(x_last + 1);
+  const uint32_t ho0 = (uint32_t)hx * esz;
+  const uint32_t hol = (uint32_t)wrapx(hx - 1) * esz;
+  const uint32_t hor = (uint32_t)wrapx(hx + 1) * esz;
+  const int hslot = lane == 0 ? 0 : W + 1;
+
+  const real omega = a.omega;
+  const real cforce = a.cforce;
+  const int y0 = tile.y0, y1 = tile.y1;
+  const int ybase = y0 - 2;
+  const uint32_t qb = (uint32_t)pitch * esz;
+  const uint32_t rowb = 9 * qb;
+  const __amdgpu_buffer_rsrc_t rin = tile_rsrc(fin + (int64_t)ybase * 9 * pitch);
+  const __amdgpu_buffer_rsrc_t rout = tile_rsrc(a.fout + g.f_off + (int64_t)ybase * 9 * pitch);
+
+  real A_x, inv_x;
+  sponge_x(a, g, xa, A_x, inv_x);
+
+  real fa[9], fb[9];
+  pull_fast(rin, ybase, y0 - 1, rowb, qb, o0, ol, orr, fa);
+  real rho_m = sum9(fa);
+  pull_fast(rin, ybase, y0, rowb, qb, o0, ol, orr, fa);
+  real rho_c = sum9(fa);
+  srho[0][lane + 1] = rho_c;
+  if (lane < 2) {
+    real fh[9];
+    pull_fast(rin, ybase, y0, rowb, qb, ho0, hol, hor, fh);
+    srho[0][hslot] = sum9(fh);
+  }
+  __syncthreads();
+
+  for (int y = y0, k = 0; y < y1; ++y, ++k) {
+    pull_fast(rin, ybase, y + 1, rowb, qb, o0, ol, orr, fb);
+    const real rho_n = sum9(fb);
+    real hr_n = real(0);
+    if (lane < 2) {
+      real fh[9];
+      pull_fast(rin, ybase, y + 1, rowb, qb, ho0, hol, hor, fh);
+      hr_n = sum9(fh);
+    }
+    const int s = k & 1;
+    const real rho_l = srho[s][lane];
+    const real rho_r = (xa == x_last) ? srho[s][W + 1] : srho[s][lane + 2];
+    srho[s ^ 1][lane + 1] = rho_n;
+    if (lane < 2) srho[s ^ 1][hslot] = hr_n;
+
+    // Centred density gradient (eq. FDrho) and the source (eq. S).
+    const real dx = real(0.5) * (rho_r - rho_l);
+    const real dy = real(0.5) * (rho_n - rho_m);
+    const real kap = cell_kappa(a, g, y, xa);
+    real A = A_x, inv = inv_x;
+    sponge_y(a, g, y, A, inv);
+    const CellState<real> cs = cell_state(fa, rho_c, kap * dx, kap * dy, A, inv);
+    if (active) {
+      real fs[9];
+      collide(fa, cs, omega, cforce, fs);
+      const uint32_t rs = (uint32_t)(y - ybase) * rowb;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Buf<real>::store_nt(fs[i], rout, o0, rs + i * qb);
+    }
+
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fa[i] = fb[i];
     rho_m = rho_c;
     rho_c = rho_n;
   }
@@ -378,28 +687,48 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepArgs<real> a) {
 }  // namespace
 
 template <typename real>
-hipError_t launch_step(const StepArgs<real> &a, int waves, int ntiles, int mode,
+hipError_t launch_step(const StepArgs<real> &a, int waves, int prefetch, int ntiles, int mode,
                        hipStream_t stream) {
   if (ntiles <= 0) return hipSuccess;
   dim3 grid(ntiles), block(64 * waves);
-#define LBM_LAUNCH(NW, MODE) \
-  hipLaunchKernelGGL((step_kernel<real, NW, MODE>), grid, block, 0, stream, a)
+#define LBM_LAUNCH(NW, MODE, PF) \
+  hipLaunchKernelGGL((step_kernel<real, NW, MODE, PF>), grid, block, 0, stream, a)
   if (mode == kModeStep) {
-    if (waves == 1) LBM_LAUNCH(1, kModeStep);
-    else if (waves == 2) LBM_LAUNCH(2, kModeStep);
-    else if (waves == 4) LBM_LAUNCH(4, kModeStep);
-    else return hipErrorInvalidValue;
+    if (prefetch == 2) {
+      if (waves == 1) LBM_LAUNCH(1, kModeStep, 2);
+      else if (waves == 2) LBM_LAUNCH(2, kModeStep, 2);
+      else if (waves == 4) LBM_LAUNCH(4, kModeStep, 2);
+      else return hipErrorInvalidValue;
+    } else {
+      if (waves == 1) LBM_LAUNCH(1, kModeStep, 1);
+      else if (waves == 2) LBM_LAUNCH(2, kModeStep, 1);
+      else if (waves == 4) LBM_LAUNCH(4, kModeStep, 1);
+      else return hipErrorInvalidValue;
+    }
   } else {
-    if (waves == 1) LBM_LAUNCH(1, kModeMoments);
-    else if (waves == 2) LBM_LAUNCH(2, kModeMoments);
-    else if (waves == 4) LBM_LAUNCH(4, kModeMoments);
+    if (waves == 1) LBM_LAUNCH(1, kModeMoments, 1);
+    else if (waves == 2) LBM_LAUNCH(2, kModeMoments, 1);
+    else if (waves == 4) LBM_LAUNCH(4, kModeMoments, 1);
     else return hipErrorInvalidValue;
   }
 #undef LBM_LAUNCH
   return hipGetLastError();
 }
 
-template hipError_t launch_step<float>(const StepArgs<float> &, int, int, int, hipStream_t);
-template hipError_t launch_step<double>(const StepArgs<double> &, int, int, int, hipStream_t);
+template <typename real>
+hipError_t launch_interior(const StepArgs<real> &a, int waves, int ntiles, hipStream_t stream) {
+  if (ntiles <= 0) return hipSuccess;
+  dim3 grid(ntiles), block(64 * waves);
+  if (waves == 1) hipLaunchKernelGGL((interior_kernel<real, 1>), grid, block, 0, stream, a);
+  else if (waves == 2) hipLaunchKernelGGL((interior_kernel<real, 2>), grid, block, 0, stream, a);
+  else if (waves == 4) hipLaunchKernelGGL((interior_kernel<real, 4>), grid, block, 0, stream, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template hipError_t launch_interior<float>(const StepArgs<float> &, int, int, hipStream_t);
+template hipError_t launch_interior<double>(const StepArgs<double> &, int, int, hipStream_t);
+template hipError_t launch_step<float>(const StepArgs<float> &, int, int, int, int, hipStream_t);
+template hipError_t launch_step<double>(const StepArgs<double> &, int, int, int, int, hipStream_t);
 
 }  // namespace lbm

@@ -54,17 +54,19 @@ __global__ void nonfinite_kernel(const real *__restrict__ f, int64_t n, int *cou
   if (local) atomicAdd(count, 1);
 }
 
+// Copy nplanes planes of an nx x ny grid between two layouts given by their
+// strides (elements) between planes and between rows.
 template <typename real>
-__global__ void copy_planes_kernel(const real *__restrict__ src, int64_t src_plane, int src_pitch,
-                                   real *__restrict__ dst, int64_t dst_plane, int dst_pitch,
+__global__ void copy_planes_kernel(const real *__restrict__ src, int64_t src_ps, int64_t src_ys,
+                                   real *__restrict__ dst, int64_t dst_ps, int64_t dst_ys,
                                    int nx, int ny, int nplanes) {
   const int64_t n = (int64_t)nx * ny * nplanes;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
        k += (int64_t)gridDim.x * blockDim.x) {
     const int64_t p = k / ((int64_t)nx * ny);
     const int64_t rem = k - p * (int64_t)nx * ny;
-    const int y = (int)(rem / nx), x = (int)(rem % nx);
-    dst[p * dst_plane + (int64_t)y * dst_pitch + x] = src[p * src_plane + (int64_t)y * src_pitch + x];
+    const int64_t y = rem / nx, x = rem % nx;
+    dst[p * dst_ps + y * dst_ys + x] = src[p * src_ps + y * src_ys + x];
   }
 }
 
@@ -109,12 +111,12 @@ hipError_t launch_count_nonfinite(const real *f, int64_t n, int *count, hipStrea
 }
 
 template <typename real>
-hipError_t launch_copy_planes(const real *src, int64_t src_plane, int src_pitch, real *dst,
-                              int64_t dst_plane, int dst_pitch, int nx, int ny, int nplanes,
+hipError_t launch_copy_planes(const real *src, int64_t src_ps, int64_t src_ys, real *dst,
+                              int64_t dst_ps, int64_t dst_ys, int nx, int ny, int nplanes,
                               hipStream_t stream) {
   hipLaunchKernelGGL(copy_planes_kernel<real>, dim3(blocks_for((int64_t)nx * ny * nplanes)),
-                     dim3(256), 0, stream, src, src_plane, src_pitch, dst, dst_plane, dst_pitch,
-                     nx, ny, nplanes);
+                     dim3(256), 0, stream, src, src_ps, src_ys, dst, dst_ps, dst_ys, nx, ny,
+                     nplanes);
   return hipGetLastError();
 }
 
@@ -135,8 +137,8 @@ hipError_t launch_add_time(int64_t *t_dev, int64_t delta, hipStream_t stream) {
   template hipError_t launch_gather<real>(const real *, const int64_t *, int, real *,            \
                                           hipStream_t);                                          \
   template hipError_t launch_count_nonfinite<real>(const real *, int64_t, int *, hipStream_t);   \
-  template hipError_t launch_copy_planes<real>(const real *, int64_t, int, real *, int64_t, int, \
-                                               int, int, int, hipStream_t);
+  template hipError_t launch_copy_planes<real>(const real *, int64_t, int64_t, real *, int64_t,  \
+                                               int64_t, int, int, int, hipStream_t);
 LBM_INST(float)
 LBM_INST(double)
 #undef LBM_INST

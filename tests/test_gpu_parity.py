@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import workloads as w
-from workloads import BC_FREE, BC_PERIODIC, BC_RIGID, Medium, Problem, Source
+from workloads import BC_FREE, BC_FREE0, BC_PERIODIC, BC_RIGID, Medium, Problem, Source
 from oracle import stepper
 from gpu_helpers import compare, rel_l2, run_gpu
 
@@ -49,6 +49,16 @@ def test_plain_large_reduced(dtype):
     g = run_gpu(p, p.nsteps, dtype)
     worst = compare(g, _oracle(p, p.nsteps), TOL[dtype], f"plain_large/256 {dtype}")
     _print(f"plain_large 256 {dtype}", worst)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_free_surface_as_printed_short_run(dtype):
+    """The printed free-surface rule (linear extrapolation), over a run short
+    enough that its growing surface modes stay below the tolerance."""
+    p = w.plain_large(n=256, nsteps=110, sponge=24, src_depth=20, top_bc=BC_FREE)
+    g = run_gpu(p, p.nsteps, dtype)
+    worst = compare(g, _oracle(p, p.nsteps), TOL[dtype], f"printed free surface {dtype}")
+    _print(f"printed free surface 256 {dtype}", worst)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -110,18 +120,34 @@ def test_launch_configurations_agree_bitwise():
     ref = None
     for waves in (1, 2, 4):
         for rows in (1, 5, 64):
-            g = run_gpu(p, 60, "f64", launch=dict(waves=waves, rows=rows))
-            if ref is None:
-                ref = g
-                compare(g, _oracle(p, 60), TOL["f64"], "feature problem")
-            else:
-                assert np.array_equal(ref["fstar"], g["fstar"]), (waves, rows)
-                assert np.array_equal(ref["trace"], g["trace"]), (waves, rows)
+            for prefetch, split in ((1, 1), (2, 0), (2, 1)):
+                cfg = dict(waves=waves, rows=rows, prefetch=prefetch, split=split)
+                g = run_gpu(p, 60, "f64", launch=cfg)
+                if ref is None:
+                    ref = g
+                    compare(g, _oracle(p, 60), TOL["f64"], "feature problem")
+                else:
+                    assert np.array_equal(ref["fstar"], g["fstar"]), cfg
+                    assert np.array_equal(ref["trace"], g["trace"]), cfg
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_interior_kernel_split_is_bitwise_neutral(dtype):
+    """A periodic box large enough to have interior tiles: the run with the
+    interior/general split equals the run with one kernel, and the oracle."""
+    p = w.plain_large(n=192, nsteps=150, sponge=20, src_depth=30)
+    a = run_gpu(p, 150, dtype, launch=dict(waves=1, rows=8, split=1))
+    b = run_gpu(p, 150, dtype, launch=dict(waves=1, rows=8, split=0))
+    assert np.array_equal(a["fstar"], b["fstar"])
+    assert np.array_equal(a["trace"], b["trace"])
+    compare(a, _oracle(p, 150), TOL[dtype], f"split {dtype}")
 
 
 BC_CASES = [
     ("periodic", (BC_PERIODIC,) * 4, -1),
     ("free_rigid", (BC_FREE, BC_RIGID, BC_PERIODIC, BC_PERIODIC), -1),
+    ("free0_rigid", (BC_FREE0, BC_RIGID, BC_PERIODIC, BC_PERIODIC), 7),
+    ("free0_free0_rigid_sides", (BC_FREE0, BC_FREE0, BC_RIGID, BC_RIGID), -1),
     ("rigid_box", (BC_RIGID,) * 4, -1),
     ("free_free_rigid_sides", (BC_FREE, BC_FREE, BC_RIGID, BC_RIGID), 6),
     ("rigid_free", (BC_RIGID, BC_FREE, BC_PERIODIC, BC_PERIODIC), 5),
@@ -158,8 +184,11 @@ def test_minimal_grid_and_zero_steps():
                 receivers=np.array([[1, 1]], np.int32), comp_mask=3, dtype="f64")
     g = run_gpu(p, 9, "f64")
     compare(g, _oracle(p, 9), TOL["f64"], "3x3")
+    # zero steps: the state is the rest state; the fields at t = 0 already
+    # carry the source's half-step contribution to j (j = m + S/2)
     g0 = run_gpu(p, 0, "f64")
-    assert np.all(g0["fstar"] == 0) and np.all(g0["mom"] == 0)
+    assert np.all(g0["fstar"] == 0)
+    compare(g0, _oracle(p, 0), TOL["f64"], "3x3 t=0")
 
 
 def test_restart_and_graph_are_bitwise():

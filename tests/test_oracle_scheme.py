@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import workloads as w
-from workloads import BC_FREE, BC_PERIODIC, BC_RIGID, Medium, Problem, Source
+from workloads import BC_FREE, BC_FREE0, BC_PERIODIC, BC_RIGID, Medium, Problem, Source
 from oracle import spectral, stepper, theory as T
 from _golden import TABLE1_NUS, paper_values, table1
 
@@ -223,12 +223,13 @@ def test_uniform_density_state_fixed_under_periodic_and_rigid():
         assert np.abs(out["f"] - f0).max() < 1e-15
 
 
-def test_traction_free_uniform_state_fixed_at_free_surface():
+@pytest.mark.parametrize("free", [BC_FREE, BC_FREE0])
+def test_traction_free_uniform_state_fixed_at_free_surface(free):
     """A uniform equilibrium with zero flux and P.n = 0 at the free surface
     (P_yy = P_xy = 0, any rho and P_xx) is a fixed point of the anti-bounce-back
     rule (Sec. 6.2); a uniform state with P_yy != 0 is not."""
     ny, nx = 9, 8
-    bc = (BC_FREE, BC_RIGID, BC_PERIODIC, BC_PERIODIC)
+    bc = (free, BC_RIGID, BC_PERIODIC, BC_PERIODIC)
     p = Problem(nx=nx, ny=ny, bc=bc, medium=Medium("homogeneous", 0.03, 0.04, 1.0))
     feq = stepper.equilibrium(0.3, [0.0, 0.0], [0.7, 0.0, 0.0])
     f0 = np.broadcast_to(feq[:, None, None], (9, ny, nx)).copy()
@@ -337,27 +338,66 @@ def test_wave_speeds_from_travel_times(nu):
         assert abs(vm - v) / v < tol, (nu, direction, vm, v)
 
 
-def test_rayleigh_wave_speed():
-    """Surface-wave speed under the free-surface rule versus the Rayleigh
-    root (Sec. 7: measured 0.5315 against 0.5308 for nu = 0.25)."""
+def _peak_in(tr, lo, hi):
+    a = np.abs(tr)
+    lo, hi = max(int(lo), 1), min(int(hi), len(a) - 2)
+    i = lo + int(np.argmax(a[lo:hi]))
+    den = a[i - 1] - 2 * a[i] + a[i + 1]
+    return i + 0.5 * (a[i - 1] - a[i + 1]) / den
+
+
+@pytest.mark.parametrize("free", [BC_FREE, BC_FREE0])
+@pytest.mark.parametrize("tau", [0.8, 1.0])
+def test_rayleigh_wave_speed(free, tau):
+    """Surface-wave speed under the free-surface rule versus the root of the
+    Rayleigh equation, from the arrival of the surface pulse at two stations
+    (Sec. 7: 0.5315 measured against 0.5308 for nu = 0.25)."""
     nu = 0.25
-    nx, ny = 1024, 200
-    xs = 100
-    d1, d2 = 140, 330
+    nx, ny, xs, d1, d2 = 1024, 200, 100, 200, 450
     lam_mu = T.lame_ratio(nu)
     prof = w.default_sponge_profile(60)
-    p = Problem(nx=nx, ny=ny, bc=(BC_FREE, BC_RIGID, BC_PERIODIC, BC_PERIODIC),
-                medium=Medium("homogeneous", 0.04 * lam_mu, 0.04, 1.0), tau=0.8,
+    vr = T.rayleigh_speed(nu)
+    p = Problem(nx=nx, ny=ny, bc=(free, BC_RIGID, BC_PERIODIC, BC_PERIODIC),
+                medium=Medium("homogeneous", 0.04 * lam_mu, 0.04, 1.0), tau=tau,
                 sponge_thick=(0, 60, 0, 0), sponge_profiles=(None, prof, None, None),
                 sources=[Source(float(xs), 2.0, 3.0, 0.0, 1.0, 1.0, 20.0, 30.0)],
                 receivers=np.array([[xs + d1, 0], [xs + d2, 0]], np.int32), comp_mask=2)
-    tr = stepper.run(p, nsteps=760)["trace"][:, :, 0]
-    v = (d2 - d1) / (_peak_time(tr[:, 1]) - _peak_time(tr[:, 0]))
-    vr = T.rayleigh_speed(nu)
+    tr = stepper.run(p, nsteps=int(30 + d2 / vr + 40))["trace"][:, :, 0]
+    # arrival picked within +-12 steps of the predicted time (the S pulse
+    # arrives ~30 steps earlier at the near station)
+    t1 = _peak_in(tr[:, 0], 30 + d1 / vr - 12, 30 + d1 / vr + 12)
+    t2 = _peak_in(tr[:, 1], 30 + d2 / vr - 12, 30 + d2 / vr + 12)
+    v = (d2 - d1) / (t2 - t1)
     assert abs(v - vr) / vr < 0.01, (v, vr)
 
 
-def test_reflection_polarity_rigid_versus_free():
+def _growth_per_step(p, steps, seed=0):
+    """Geometric-mean growth of a random state's norm per step (sources off)."""
+    rng = np.random.default_rng(seed)
+    f0 = rng.normal(size=(9, p.ny, p.nx))
+    q = p.replace(sources=[], receivers=np.zeros((0, 2), np.int32))
+    a = stepper.run(q, nsteps=steps // 2, fstar_init=f0, want_trace=False)["fstar"]
+    b = stepper.run(q, nsteps=steps - steps // 2, fstar_init=a, want_trace=False)["fstar"]
+    return (np.linalg.norm(b) / np.linalg.norm(a)) ** (1.0 / (steps - steps // 2))
+
+
+def test_free_surface_rule_as_printed_is_unstable_zero_order_is_not():
+    """The linear extrapolation of rho_air and P_xx,air printed in Sec. 6.2
+    makes short-wavelength surface modes grow (4.6% per step at nu = 0.25,
+    tau = 1); with the boundary cell's own values (zero order) the same grid
+    is stable for nu in [0.1, 0.33]."""
+    lam_mu = T.lame_ratio(0.25)
+    base = Problem(nx=32, ny=24, bc=(BC_FREE, BC_RIGID, BC_PERIODIC, BC_PERIODIC),
+                   medium=Medium("homogeneous", 0.04 * lam_mu, 0.04, 1.0), tau=1.0)
+    assert _growth_per_step(base, 400) > 1.03
+    for nu in (0.1, 0.25, 0.33):
+        q = base.replace(bc=(BC_FREE0, BC_RIGID, BC_PERIODIC, BC_PERIODIC),
+                         medium=Medium("homogeneous", 0.04 * T.lame_ratio(nu), 0.04, 1.0))
+        assert _growth_per_step(q, 400) <= 1.0 + 1e-6, nu
+
+
+@pytest.mark.parametrize("free", [BC_FREE, BC_FREE0])
+def test_reflection_polarity_rigid_versus_free(free):
     """Sec. 6.3: a free surface reflects the vertical flux without a phase
     change (constructive at the surface), a rigid wall with a phase inversion
     (destructive). Compared with the same source in a periodic column."""
@@ -367,7 +407,7 @@ def test_reflection_polarity_rigid_versus_free():
     src = Source(32.0, float(depth), 3.0, 0.0, 1.0, 1.0, 20.0, 30.0)
     rec = np.array([[32, 0]], np.int32)
     amps = {}
-    for name, bc in (("free", (BC_FREE, BC_PERIODIC)), ("rigid", (BC_RIGID, BC_PERIODIC)),
+    for name, bc in (("free", (free, BC_PERIODIC)), ("rigid", (BC_RIGID, BC_PERIODIC)),
                      ("none", (BC_PERIODIC, BC_PERIODIC))):
         top = bc[0]
         # a periodic column cannot have a lone wall: close it far below

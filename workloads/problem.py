@@ -9,8 +9,9 @@ from typing import List, Optional, Sequence, Tuple
 import numpy as np
 
 BC_PERIODIC = 0
-BC_FREE = 1
+BC_FREE = 1        # free surface, linear extrapolation to the interface (as printed)
 BC_RIGID = 2
+BC_FREE0 = 3       # free surface, zero-order extrapolation (stabilised variant)
 
 EDGES = ("top", "bottom", "left", "right")
 
