@@ -105,12 +105,14 @@ typedef struct {
 
 /* Launch configuration chosen by the autotuner or set by the caller. */
 typedef struct {
-  int32_t waves;      /* wavefronts per workgroup: 1, 2 or 4 (64 columns each) */
+  int32_t waves;      /* wavefronts per workgroup: 1, 2, 4 or 8 (64 columns each) */
   int32_t rows;       /* rows marched per workgroup */
   int32_t graph_chunk;/* steps per captured HIP graph; 0 = direct launches */
   int32_t prefetch;   /* rows of populations in flight while marching: 1 or 2 */
   int32_t split;      /* 1: tiles clear of walls, sources and receivers run in a
                          lean interior kernel (default); 0: one kernel for all */
+  int32_t pair;       /* 1: the interior kernel handles two columns per lane
+                         (used when every grid's nx is even and waves >= 2) */
 } lbm_launch;
 
 /* Bytes of device workspace lbm_init needs for nbatch grids of the given
@@ -150,6 +152,23 @@ int lbm_set_receivers(lbm_ctx *ctx, int32_t g, const int32_t *xy, int32_t n,
 /* Advance all grids n >= 0 steps. Asynchronous. */
 int lbm_step(lbm_ctx *ctx, int64_t n);
 
+/* Per-kernel timing of the step (diagnostics for roofline measurement). A
+ * step launches the interior kernel over the tiles clear of walls, sources and
+ * receivers (when split is on), then the general kernel over the rest. */
+typedef struct {
+  int64_t steps;          /* steps timed */
+  double interior_ms;     /* mean duration of one interior-kernel launch; 0 if none */
+  double general_ms;      /* mean duration of one general-kernel launch */
+  int64_t interior_cells; /* cells one interior-kernel launch updates */
+  int64_t general_cells;  /* cells one general-kernel launch updates */
+} lbm_kernel_times;
+
+/* Advance all grids n >= 0 steps like lbm_step, but with direct launches and
+ * a HIP event pair on the context's stream around every kernel launch; the
+ * mean launch durations and the cells each kernel covers go to *out (host).
+ * Synchronous (waits for every step). Results equal those of lbm_step. */
+int lbm_step_timed(lbm_ctx *ctx, int64_t n, lbm_kernel_times *out);
+
 /* Macroscopic fields of grid g at the current time t: DEVICE array of dtype,
  * layout [6][ny][nx] = rho, j_x, j_y, P_xx, P_xy, P_yy (Sec. 2: P is the
  * second moment, the stress with the opposite sign; j = sum f c + S/2 with
@@ -171,7 +190,7 @@ int lbm_set_state(lbm_ctx *ctx, int32_t g, const void *src, int64_t t);
  * LBM_E_NONFINITE. */
 int lbm_check_finite(lbm_ctx *ctx);
 
-/* Launch configuration in use, and a way to set it (waves in {1,2,4},
+/* Launch configuration in use, and a way to set it (waves in {1,2,4,8},
  * rows >= 1, graph_chunk >= 0, prefetch in {1,2}; 0 means 1). An odd
  * graph_chunk is rounded up to keep the ping-pong parity. */
 int lbm_get_launch(const lbm_ctx *ctx, lbm_launch *out);

@@ -30,7 +30,7 @@ LBM_FREE0 = 3
 
 ENTRY_POINTS = (
     "lbm_abi_version", "lbm_last_error", "lbm_workspace_bytes", "lbm_init",
-    "lbm_set_sources", "lbm_set_receivers", "lbm_step", "lbm_moments",
+    "lbm_set_sources", "lbm_set_receivers", "lbm_step", "lbm_step_timed", "lbm_moments",
     "lbm_get_time", "lbm_get_state", "lbm_set_state", "lbm_check_finite",
     "lbm_get_launch", "lbm_set_launch", "lbm_autotune", "lbm_destroy",
 )
@@ -54,7 +54,12 @@ class lbm_source(C.Structure):
 
 class lbm_launch(C.Structure):
     _fields_ = [("waves", C.c_int32), ("rows", C.c_int32), ("graph_chunk", C.c_int32),
-                ("prefetch", C.c_int32), ("split", C.c_int32)]
+                ("prefetch", C.c_int32), ("split", C.c_int32), ("pair", C.c_int32)]
+
+
+class lbm_kernel_times(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("interior_ms", C.c_double), ("general_ms", C.c_double),
+                ("interior_cells", C.c_int64), ("general_cells", C.c_int64)]
 
 
 class LBMError(RuntimeError):
@@ -86,6 +91,7 @@ def lib():
             "lbm_set_sources": ([vp, i32, C.POINTER(lbm_source), i32], C.c_int),
             "lbm_set_receivers": ([vp, i32, C.POINTER(C.c_int32), i32, i32, vp, i64], C.c_int),
             "lbm_step": ([vp, i64], C.c_int),
+            "lbm_step_timed": ([vp, i64, C.POINTER(lbm_kernel_times)], C.c_int),
             "lbm_moments": ([vp, i32, vp], C.c_int),
             "lbm_get_time": ([vp, C.POINTER(i64)], C.c_int),
             "lbm_get_state": ([vp, i32, vp], C.c_int),
@@ -175,6 +181,12 @@ def lbm_step(ctx, n: int) -> None:
     check(lib().lbm_step(ctx, int(n)))
 
 
+def lbm_step_timed(ctx, n: int) -> dict:
+    out = lbm_kernel_times()
+    check(lib().lbm_step_timed(ctx, int(n), C.byref(out)))
+    return {k: getattr(out, k) for k, _ in lbm_kernel_times._fields_}
+
+
 def lbm_moments(ctx, g: int, out_ptr) -> None:
     check(lib().lbm_moments(ctx, g, out_ptr))
 
@@ -205,12 +217,12 @@ def lbm_get_launch(ctx):
     o = lbm_launch()
     check(lib().lbm_get_launch(ctx, C.byref(o)))
     return dict(waves=o.waves, rows=o.rows, graph_chunk=o.graph_chunk, prefetch=o.prefetch,
-                split=o.split)
+                split=o.split, pair=o.pair)
 
 
 def lbm_set_launch(ctx, waves: int, rows: int, graph_chunk: int = 0, prefetch: int = 1,
-                   split: int = 1) -> None:
-    o = lbm_launch(waves, rows, graph_chunk, prefetch, split)
+                   split: int = 1, pair: int = 0) -> None:
+    o = lbm_launch(waves, rows, graph_chunk, prefetch, split, pair)
     check(lib().lbm_set_launch(ctx, C.byref(o)))
 
 
@@ -218,7 +230,7 @@ def lbm_autotune(ctx, steps: int = 5):
     o = lbm_launch()
     check(lib().lbm_autotune(ctx, int(steps), C.byref(o)))
     return dict(waves=o.waves, rows=o.rows, graph_chunk=o.graph_chunk, prefetch=o.prefetch,
-                split=o.split)
+                split=o.split, pair=o.pair)
 
 
 def lbm_destroy(ctx) -> None:

@@ -141,8 +141,9 @@ struct lbm_ctx {
   std::vector<int64_t> rscale_off;               // per grid offset into d_rtab
   std::vector<char> rtab_host;
   bool tables_dirty = true;
-  lbm_launch launch{4, 64, 0, 1, 1};
+  lbm_launch launch{4, 8, 0, 1, 1, 0};
   int ntiles = 0, ntiles_int = 0;
+  int64_t cells_int = 0, cells_gen = 0;          // cells each kernel's tile list covers
   // graph of graph_chunk steps for each starting buffer parity
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   int gchunk = 0;
@@ -280,12 +281,18 @@ void build_tiles(const lbm_ctx *c, int waves, int rows, bool split, std::vector<
   general = order_for_dies(lg);
 }
 
-// Default launch shape: 256-column tiles of 8 rows (many short tiles keep the
-// set of rows in flight compact); narrower tiles for small grids.
+// Default launch shape: 512-column tiles of 2 rows on large grids (many short
+// tiles keep the set of rows in flight compact, and wide tiles re-read fewer
+// halo columns); narrower tiles where the grid would otherwise give too few
+// workgroups to fill 256 compute units.
 lbm_launch default_launch(const lbm_ctx *c) {
   int64_t cells = 0;
   for (const auto &g : c->grids) cells += (int64_t)g.nx * g.ny;
-  lbm_launch l{4, 8, 0, 1, 1};
+  lbm_launch l{8, 2, 0, 1, 1, 0};
+  if (cells < 2048 * 2048) {
+    l.waves = 4;
+    l.rows = 4;
+  }
   if (cells < 256 * 2048) {
     l.waves = 1;
     l.rows = 4;
@@ -416,10 +423,28 @@ int rebuild_tiles(lbm_ctx *c) {
   build_tiles(c, c->launch.waves, c->launch.rows, c->launch.split != 0, ti, tg);
   c->ntiles_int = (int)ti.size();
   c->ntiles = (int)tg.size();
+  const int W = 64 * c->launch.waves;
+  auto cover = [&](const std::vector<TileDev> &v) {
+    int64_t n = 0;
+    for (const auto &t : v)
+      n += (int64_t)std::min(W, c->grids[t.g].nx - t.x0) * (t.y1 - t.y0);
+    return n;
+  };
+  c->cells_int = cover(ti);
+  c->cells_gen = cover(tg);
   HIP_TRY(c->d_tiles_int.upload(ti, c->stream));
   HIP_TRY(c->d_tiles.upload(tg, c->stream));
   drop_graphs(c);
   return LBM_OK;
+}
+
+// The two-column interior kernel needs an even nx in every grid and at least
+// two waves of tile width.
+int use_pair(const lbm_ctx *c) {
+  if (!c->launch.pair || c->launch.waves < 2) return 0;
+  for (const auto &g : c->grids)
+    if (g.nx % 2) return 0;
+  return 1;
 }
 
 // One step: the interior tiles and the general tiles (any order: both read
@@ -430,7 +455,7 @@ hipError_t launch_one_step(lbm_ctx *c, StepArgs<real> a, hipStream_t s) {
   if (c->ntiles_int > 0) {
     StepArgs<real> ai = a;
     ai.tiles = c->d_tiles_int.p;
-    e = launch_interior<real>(ai, c->launch.waves, c->ntiles_int, s);
+    e = launch_interior<real>(ai, c->launch.waves, use_pair(c), c->ntiles_int, s);
     if (e != hipSuccess) return e;
   }
   a.tiles = c->d_tiles.p;
@@ -467,6 +492,55 @@ int step_direct(lbm_ctx *c, int64_t n) {
     c->cur ^= 1;
     c->t += 1;
   }
+  return LBM_OK;
+}
+
+// Direct launches with an event pair around every kernel launch; the mean
+// duration of each kernel's launches goes to out.
+template <typename real>
+int step_timed(lbm_ctx *c, int64_t n, lbm_kernel_times *out) {
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+  double sum_int = 0.0, sum_gen = 0.0;
+  for (int64_t k = 0; k < n && e == hipSuccess; ++k) {
+    StepArgs<real> a = make_args<real>(c, c->cur);
+    if (c->ntiles_int > 0) {
+      StepArgs<real> ai = a;
+      ai.tiles = c->d_tiles_int.p;
+      e = hipEventRecord(ev[0], c->stream);
+      if (e == hipSuccess)
+        e = launch_interior<real>(ai, c->launch.waves, use_pair(c), c->ntiles_int, c->stream);
+      if (e == hipSuccess) e = hipEventRecord(ev[1], c->stream);
+    }
+    a.tiles = c->d_tiles.p;
+    if (e == hipSuccess) e = hipEventRecord(ev[2], c->stream);
+    if (e == hipSuccess)
+      e = launch_step<real>(a, c->launch.waves, c->launch.prefetch, c->ntiles, kModeStep, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[3], c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
+    float ms = 0.f;
+    if (e == hipSuccess && c->ntiles_int > 0) {
+      e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+      sum_int += ms;
+    }
+    if (e == hipSuccess) {
+      e = hipEventElapsedTime(&ms, ev[2], ev[3]);
+      sum_gen += ms;
+    }
+    if (e == hipSuccess) {
+      c->cur ^= 1;
+      c->t += 1;
+    }
+  }
+  for (int i = 0; i < 4; ++i)
+    if (ev[i]) hipEventDestroy(ev[i]);
+  if (e != hipSuccess) return fail(LBM_E_DEVICE, hipGetErrorString(e));
+  out->steps = n;
+  out->interior_ms = (n > 0 && c->ntiles_int > 0) ? sum_int / (double)n : 0.0;
+  out->general_ms = n > 0 ? sum_gen / (double)n : 0.0;
+  out->interior_cells = c->cells_int;
+  out->general_cells = c->cells_gen;
   return LBM_OK;
 }
 
@@ -778,6 +852,16 @@ int lbm_step(lbm_ctx *c, int64_t n) {
   return c->dtype == LBM_F64 ? step_impl<double>(c, n) : step_impl<float>(c, n);
 }
 
+int lbm_step_timed(lbm_ctx *c, int64_t n, lbm_kernel_times *out) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (n < 0) return fail(LBM_E_INVALID, "n must be >= 0");
+  if (!out) return fail(LBM_E_INVALID, "out is null");
+  rc = commit(c);
+  if (rc) return rc;
+  return c->dtype == LBM_F64 ? step_timed<double>(c, n, out) : step_timed<float>(c, n, out);
+}
+
 int lbm_moments(lbm_ctx *c, int32_t g, void *out6) {
   int rc = check_ctx(c);
   if (rc) return rc;
@@ -892,13 +976,14 @@ int lbm_set_launch(lbm_ctx *c, const lbm_launch *cfg) {
   int rc = check_ctx(c);
   if (rc) return rc;
   if (!cfg) return fail(LBM_E_INVALID, "cfg is null");
-  if (cfg->waves != 1 && cfg->waves != 2 && cfg->waves != 4) return fail(LBM_E_INVALID, "waves must be 1, 2 or 4");
+  if (cfg->waves != 1 && cfg->waves != 2 && cfg->waves != 4 && cfg->waves != 8)
+    return fail(LBM_E_INVALID, "waves must be 1, 2, 4 or 8");
   if (cfg->rows < 1) return fail(LBM_E_INVALID, "rows must be >= 1");
   if (cfg->graph_chunk < 0) return fail(LBM_E_INVALID, "graph_chunk must be >= 0");
   if (cfg->prefetch < 0 || cfg->prefetch > 2) return fail(LBM_E_INVALID, "prefetch must be 1 or 2");
   const bool retile = cfg->waves != c->launch.waves || cfg->rows != c->launch.rows ||
                       cfg->split != c->launch.split;
-  const bool regraph = retile || cfg->prefetch != c->launch.prefetch;
+  const bool regraph = retile || cfg->prefetch != c->launch.prefetch || cfg->pair != c->launch.pair;
   c->launch = *cfg;
   if (c->launch.prefetch == 0) c->launch.prefetch = 1;
   if (regraph) drop_graphs(c);
@@ -929,14 +1014,18 @@ int lbm_autotune(lbm_ctx *c, int32_t steps, lbm_launch *chosen) {
   for (auto &g : c->grids) cells += (int64_t)g.nx * g.ny;
   lbm_launch best = keep;
   float best_ms = 1e30f;
-  const int waves_c[3] = {1, 2, 4};
-  const int rows_c[7] = {8, 16, 24, 32, 48, 64, 128};
+  const int waves_c[4] = {1, 2, 4, 8};
+  const int rows_c[6] = {2, 4, 8, 16, 32, 64};
+  bool even = true;
+  for (auto &g : c->grids) even = even && (g.nx % 2 == 0);
+  for (int pair = 0; pair <= (even ? 1 : 0); ++pair)
   for (int pf = 1; pf <= 2; ++pf)
-  for (int wi = 0; wi < 3 && e == hipSuccess && rc == LBM_OK; ++wi)
-    for (int ri = 0; ri < 7 && e == hipSuccess && rc == LBM_OK; ++ri) {
-      lbm_launch cand{waves_c[wi], rows_c[ri], 0, pf, keep.split};
+  for (int wi = 0; wi < 4 && e == hipSuccess && rc == LBM_OK; ++wi)
+    for (int ri = 0; ri < 6 && e == hipSuccess && rc == LBM_OK; ++ri) {
+      lbm_launch cand{waves_c[wi], rows_c[ri], 0, pf, keep.split, pair};
+      if (pair && cand.waves == 1) continue;
       const int64_t tiles = cells / ((int64_t)64 * cand.waves * cand.rows);
-      if (tiles < 512 && !(cand.waves == 1 && cand.rows == 8)) continue;
+      if (tiles < 512 && !(cand.waves == 1 && cand.rows == 4)) continue;
       c->launch = cand;
       rc = rebuild_tiles(c);
       if (rc) break;

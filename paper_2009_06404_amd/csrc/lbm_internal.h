@@ -76,7 +76,8 @@ hipError_t launch_step(const StepArgs<real> &a, int waves, int prefetch, int nti
                        hipStream_t stream);
 
 template <typename real>
-hipError_t launch_interior(const StepArgs<real> &a, int waves, int ntiles, hipStream_t stream);
+hipError_t launch_interior(const StepArgs<real> &a, int waves, int pair, int ntiles,
+                           hipStream_t stream);
 
 // Initialisation and utility kernels (lbm_util.hip).
 template <typename real>

@@ -684,6 +684,183 @@ __global__ __launch_bounds__(64 * NW) void interior_kernel(StepArgs<real> a) {
   }
 }
 
+// Pair access for the two-column interior kernel: two consecutive elements
+// of one population run (dword-aligned multi-dword buffer accesses).
+template <typename real>
+struct Pair {
+  real a, b;
+};
+
+template <typename real>
+struct Buf2;
+
+template <>
+struct Buf2<float> {
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ Pair<float> load(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                     uint32_t soff) {
+    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    return {__uint_as_float(v.x), __uint_as_float(v.y)};
+  }
+  static __device__ __forceinline__ void store_nt(float a, float b, __amdgpu_buffer_rsrc_t r,
+                                                  uint32_t voff, uint32_t soff) {
+    u32x2 v;
+    v.x = __float_as_uint(a);
+    v.y = __float_as_uint(b);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 2);
+  }
+};
+
+template <>
+struct Buf2<double> {
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ Pair<double> load(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                      uint32_t soff) {
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    u32x2 lo, hi;
+    lo.x = v.x; lo.y = v.y;
+    hi.x = v.z; hi.y = v.w;
+    return {__builtin_bit_cast(double, lo), __builtin_bit_cast(double, hi)};
+  }
+  static __device__ __forceinline__ void store_nt(double a, double b, __amdgpu_buffer_rsrc_t r,
+                                                  uint32_t voff, uint32_t soff) {
+    const u32x2 lo = __builtin_bit_cast(u32x2, a), hi = __builtin_bit_cast(u32x2, b);
+    u32x4 v;
+    v.x = lo.x; v.y = lo.y; v.z = hi.x; v.w = hi.y;
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, voff, soff, 2);
+  }
+};
+
+// Pair of one population run shifted by one column: (x-1, x) for dir = -1,
+// (x+1, x+2) for dir = +1, with the periodic wrap for the pair that straddles
+// the x edge (two single loads there).
+template <typename real>
+__device__ __forceinline__ Pair<real> load_shift(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
+                                                 bool wrap, uint32_t last_off) {
+  if (wrap) return {Buf<real>::load(r, last_off, soff), Buf<real>::load(r, 0, soff)};
+  return Buf2<real>::load(r, voff, soff);
+}
+
+// Pulled populations of the column pair (x, x+1) of an interior row.
+template <typename real>
+__device__ __forceinline__ void pull_pair(__amdgpu_buffer_rsrc_t rsrc, int ybase, int y, uint32_t rowb,
+                                          uint32_t qb, uint32_t o0, uint32_t ol, uint32_t orr,
+                                          bool wl, bool wr, uint32_t last_off, real u[9], real v[9]) {
+  const uint32_t rc = (uint32_t)(y - ybase) * rowb, ru = rc - rowb, rd = rc + rowb;
+  Pair<real> p;
+  p = Buf2<real>::load(rsrc, o0, rc);                            u[0] = p.a; v[0] = p.b;
+  p = load_shift<real>(rsrc, ol, rc + qb, wl, last_off);         u[1] = p.a; v[1] = p.b;
+  p = Buf2<real>::load(rsrc, o0, ru + 2 * qb);                   u[2] = p.a; v[2] = p.b;
+  p = load_shift<real>(rsrc, orr, rc + 3 * qb, wr, last_off);    u[3] = p.a; v[3] = p.b;
+  p = Buf2<real>::load(rsrc, o0, rd + 4 * qb);                   u[4] = p.a; v[4] = p.b;
+  p = load_shift<real>(rsrc, ol, ru + 5 * qb, wl, last_off);     u[5] = p.a; v[5] = p.b;
+  p = load_shift<real>(rsrc, orr, ru + 6 * qb, wr, last_off);    u[6] = p.a; v[6] = p.b;
+  p = load_shift<real>(rsrc, orr, rd + 7 * qb, wr, last_off);    u[7] = p.a; v[7] = p.b;
+  p = load_shift<real>(rsrc, ol, rd + 8 * qb, wl, last_off);     u[8] = p.a; v[8] = p.b;
+}
+
+// Interior tiles with two columns per lane (grids with an even nx): the same
+// per-cell arithmetic as interior_kernel, half the memory instructions per
+// byte. A tile is 128*NW columns wide.
+template <typename real, int NW>
+__global__ __launch_bounds__(64 * NW) void interior2_kernel(StepArgs<real> a) {
+  constexpr int L = 64 * NW;     // lanes
+  constexpr int W = 2 * L;       // columns
+  __shared__ real srho[2][W + 2];
+
+  const TileDev tile = a.tiles[blockIdx.x];
+  if (tile.g < 0) return;
+  const GridDev &g = a.grids[tile.g];
+  const real *__restrict__ fin = a.fin + g.f_off;
+  const int pitch = g.pitch, nx = g.nx;
+
+  const int lane = threadIdx.x;
+  const int x = tile.x0 + 2 * lane;
+  const bool active = x < nx;
+  const int xa = active ? x : nx - 2;
+  const int x_last = min(tile.x0 + W, nx) - 1;
+  const uint32_t esz = sizeof(real);
+  auto wrapx = [&](int c) { return c < 0 ? c + nx : (c >= nx ? c - nx : c); };
+  const uint32_t o0 = (uint32_t)xa * esz;
+  const bool wl = xa == 0, wr = xa + 2 == nx;
+  const uint32_t ol = wl ? 0u : (uint32_t)(xa - 1) * esz;
+  const uint32_t orr = wr ? 0u : (uint32_t)(xa + 1) * esz;
+  const uint32_t last_off = (uint32_t)(nx - 1) * esz;
+  const int hx = lane == 0 ? wrapx(tile.x0 - 1) : wrapx(x_last + 1);
+  const uint32_t ho0 = (uint32_t)hx * esz;
+  const uint32_t hol = (uint32_t)wrapx(hx - 1) * esz;
+  const uint32_t hor = (uint32_t)wrapx(hx + 1) * esz;
+  const int hslot = lane == 0 ? 0 : W + 1;
+
+  const real omega = a.omega;
+  const real cforce = a.cforce;
+  const int y0 = tile.y0, y1 = tile.y1;
+  const int ybase = y0 - 2;
+  const uint32_t qb = (uint32_t)pitch * esz;
+  const uint32_t rowb = 9 * qb;
+  const __amdgpu_buffer_rsrc_t rin = tile_rsrc(fin + (int64_t)ybase * 9 * pitch);
+  const __amdgpu_buffer_rsrc_t rout = tile_rsrc(a.fout + g.f_off + (int64_t)ybase * 9 * pitch);
+
+  real A0, inv0, A1, inv1;
+  sponge_x(a, g, xa, A0, inv0);
+  sponge_x(a, g, xa + 1, A1, inv1);
+
+  real ua[9], va[9], ub[9], vb[9];
+  pull_pair(rin, ybase, y0 - 1, rowb, qb, o0, ol, orr, wl, wr, last_off, ua, va);
+  real rm0 = sum9(ua), rm1 = sum9(va);
+  pull_pair(rin, ybase, y0, rowb, qb, o0, ol, orr, wl, wr, last_off, ua, va);
+  real rc0 = sum9(ua), rc1 = sum9(va);
+  srho[0][2 * lane + 1] = rc0;
+  srho[0][2 * lane + 2] = rc1;
+  if (lane < 2) {
+    real fh[9];
+    pull_fast(rin, ybase, y0, rowb, qb, ho0, hol, hor, fh);
+    srho[0][hslot] = sum9(fh);
+  }
+  __syncthreads();
+
+  for (int y = y0, k = 0; y < y1; ++y, ++k) {
+    pull_pair(rin, ybase, y + 1, rowb, qb, o0, ol, orr, wl, wr, last_off, ub, vb);
+    const real rn0 = sum9(ub), rn1 = sum9(vb);
+    real hr_n = real(0);
+    if (lane < 2) {
+      real fh[9];
+      pull_fast(rin, ybase, y + 1, rowb, qb, ho0, hol, hor, fh);
+      hr_n = sum9(fh);
+    }
+    const int s = k & 1;
+    const real rl = srho[s][2 * lane];
+    const real rr = (xa + 1 == x_last) ? srho[s][W + 1] : srho[s][2 * lane + 3];
+    srho[s ^ 1][2 * lane + 1] = rn0;
+    srho[s ^ 1][2 * lane + 2] = rn1;
+    if (lane < 2) srho[s ^ 1][hslot] = hr_n;
+
+    const real kap0 = cell_kappa(a, g, y, xa), kap1 = cell_kappa(a, g, y, xa + 1);
+    real Ay0 = A0, iy0 = inv0, Ay1 = A1, iy1 = inv1;
+    sponge_y(a, g, y, Ay0, iy0);
+    sponge_y(a, g, y, Ay1, iy1);
+    const real dx0 = real(0.5) * (rc1 - rl), dy0 = real(0.5) * (rn0 - rm0);
+    const real dx1 = real(0.5) * (rr - rc0), dy1 = real(0.5) * (rn1 - rm1);
+    const CellState<real> c0 = cell_state(ua, rc0, kap0 * dx0, kap0 * dy0, Ay0, iy0);
+    const CellState<real> c1 = cell_state(va, rc1, kap1 * dx1, kap1 * dy1, Ay1, iy1);
+    if (active) {
+      real f0[9], f1[9];
+      collide(ua, c0, omega, cforce, f0);
+      collide(va, c1, omega, cforce, f1);
+      const uint32_t rs = (uint32_t)(y - ybase) * rowb;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Buf2<real>::store_nt(f0[i], f1[i], rout, o0, rs + i * qb);
+    }
+
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 9; ++i) { ua[i] = ub[i]; va[i] = vb[i]; }
+    rm0 = rc0; rm1 = rc1;
+    rc0 = rn0; rc1 = rn1;
+  }
+}
+
 }  // namespace
 
 template <typename real>
@@ -698,36 +875,52 @@ hipError_t launch_step(const StepArgs<real> &a, int waves, int prefetch, int nti
       if (waves == 1) LBM_LAUNCH(1, kModeStep, 2);
       else if (waves == 2) LBM_LAUNCH(2, kModeStep, 2);
       else if (waves == 4) LBM_LAUNCH(4, kModeStep, 2);
+      else if (waves == 8) LBM_LAUNCH(8, kModeStep, 2);
       else return hipErrorInvalidValue;
     } else {
       if (waves == 1) LBM_LAUNCH(1, kModeStep, 1);
       else if (waves == 2) LBM_LAUNCH(2, kModeStep, 1);
       else if (waves == 4) LBM_LAUNCH(4, kModeStep, 1);
+      else if (waves == 8) LBM_LAUNCH(8, kModeStep, 1);
       else return hipErrorInvalidValue;
     }
   } else {
     if (waves == 1) LBM_LAUNCH(1, kModeMoments, 1);
     else if (waves == 2) LBM_LAUNCH(2, kModeMoments, 1);
     else if (waves == 4) LBM_LAUNCH(4, kModeMoments, 1);
+    else if (waves == 8) LBM_LAUNCH(8, kModeMoments, 1);
     else return hipErrorInvalidValue;
   }
 #undef LBM_LAUNCH
   return hipGetLastError();
 }
 
+// waves: the tile width in units of 64 columns; pair = 1 selects the
+// two-column kernel (waves/2 wavefronts per workgroup).
 template <typename real>
-hipError_t launch_interior(const StepArgs<real> &a, int waves, int ntiles, hipStream_t stream) {
+hipError_t launch_interior(const StepArgs<real> &a, int waves, int pair, int ntiles,
+                           hipStream_t stream) {
   if (ntiles <= 0) return hipSuccess;
-  dim3 grid(ntiles), block(64 * waves);
-  if (waves == 1) hipLaunchKernelGGL((interior_kernel<real, 1>), grid, block, 0, stream, a);
-  else if (waves == 2) hipLaunchKernelGGL((interior_kernel<real, 2>), grid, block, 0, stream, a);
-  else if (waves == 4) hipLaunchKernelGGL((interior_kernel<real, 4>), grid, block, 0, stream, a);
-  else return hipErrorInvalidValue;
+  dim3 grid(ntiles);
+  if (pair) {
+    dim3 block(32 * waves);
+    if (waves == 2) hipLaunchKernelGGL((interior2_kernel<real, 1>), grid, block, 0, stream, a);
+    else if (waves == 4) hipLaunchKernelGGL((interior2_kernel<real, 2>), grid, block, 0, stream, a);
+    else if (waves == 8) hipLaunchKernelGGL((interior2_kernel<real, 4>), grid, block, 0, stream, a);
+    else return hipErrorInvalidValue;
+  } else {
+    dim3 block(64 * waves);
+    if (waves == 1) hipLaunchKernelGGL((interior_kernel<real, 1>), grid, block, 0, stream, a);
+    else if (waves == 2) hipLaunchKernelGGL((interior_kernel<real, 2>), grid, block, 0, stream, a);
+    else if (waves == 4) hipLaunchKernelGGL((interior_kernel<real, 4>), grid, block, 0, stream, a);
+    else if (waves == 8) hipLaunchKernelGGL((interior_kernel<real, 8>), grid, block, 0, stream, a);
+    else return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
-template hipError_t launch_interior<float>(const StepArgs<float> &, int, int, hipStream_t);
-template hipError_t launch_interior<double>(const StepArgs<double> &, int, int, hipStream_t);
+template hipError_t launch_interior<float>(const StepArgs<float> &, int, int, int, hipStream_t);
+template hipError_t launch_interior<double>(const StepArgs<double> &, int, int, int, hipStream_t);
 template hipError_t launch_step<float>(const StepArgs<float> &, int, int, int, int, hipStream_t);
 template hipError_t launch_step<double>(const StepArgs<double> &, int, int, int, int, hipStream_t);
 

@@ -91,6 +91,10 @@ class Solver:
     def step(self, n: int) -> None:
         L.lbm_step(self.ctx, n)
 
+    def step_timed(self, n: int) -> dict:
+        """Advance n steps with per-kernel event timing (synchronous)."""
+        return L.lbm_step_timed(self.ctx, n)
+
     def moments(self, g: int = 0) -> torch.Tensor:
         p = self.problems[g]
         out = torch.empty((6, p.ny, p.nx), dtype=self.tdtype, device=self.device)
@@ -122,8 +126,8 @@ class Solver:
         return L.lbm_get_launch(self.ctx)
 
     def set_launch(self, waves: int, rows: int, graph_chunk: int = 0, prefetch: int = 1,
-                   split: int = 1) -> None:
-        L.lbm_set_launch(self.ctx, waves, rows, graph_chunk, prefetch, split)
+                   split: int = 1, pair: int = 0) -> None:
+        L.lbm_set_launch(self.ctx, waves, rows, graph_chunk, prefetch, split, pair)
 
     def autotune(self, steps: int = 5) -> dict:
         return L.lbm_autotune(self.ctx, steps)

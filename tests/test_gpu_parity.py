@@ -138,9 +138,40 @@ def test_interior_kernel_split_is_bitwise_neutral(dtype):
     p = w.plain_large(n=192, nsteps=150, sponge=20, src_depth=30)
     a = run_gpu(p, 150, dtype, launch=dict(waves=1, rows=8, split=1))
     b = run_gpu(p, 150, dtype, launch=dict(waves=1, rows=8, split=0))
-    assert np.array_equal(a["fstar"], b["fstar"])
-    assert np.array_equal(a["trace"], b["trace"])
+    c = run_gpu(p, 150, dtype, launch=dict(waves=2, rows=4, split=1, pair=1))
+    for other in (b, c):
+        assert np.array_equal(a["fstar"], other["fstar"])
+        assert np.array_equal(a["trace"], other["trace"])
     compare(a, _oracle(p, 150), TOL[dtype], f"split {dtype}")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_timed_steps_equal_plain_steps(dtype):
+    """lbm_step_timed advances the state exactly like lbm_step, and its two
+    kernels' tile lists cover every cell once."""
+    import torch
+    from paper_2009_06404_amd import Solver
+    p = w.plain_large(n=320, nsteps=40, sponge=20, src_depth=30)
+    outs = []
+    for timed in (False, True):
+        s = Solver(p, dtype=dtype, trace_steps=40, launch=dict(waves=2, rows=4, split=1))
+        try:
+            s.step(10)
+            if timed:
+                kt = s.step_timed(30)
+            else:
+                s.step(30)
+            outs.append((s.state().double().cpu().numpy(), s.traces[0].double().cpu().numpy()))
+            assert s.time == 40
+            torch.cuda.synchronize()
+        finally:
+            s.close()
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert kt["steps"] == 30
+    assert kt["interior_cells"] > 0 and kt["general_cells"] > 0
+    assert kt["interior_cells"] + kt["general_cells"] == p.nx * p.ny
+    assert kt["interior_ms"] > 0 and kt["general_ms"] > 0
 
 
 BC_CASES = [
