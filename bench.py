@@ -113,13 +113,24 @@ def main():
 
     torch.cuda.set_device(0)
     if args.calibrate_copy:
+        # A plain device copy of one population buffer's size: the reference for
+        # the counter scale factors and the achievable read+write bandwidth.
         src = torch.ones(9 * args.n * args.n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(5):
             dst.copy_(src)
         torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 20
         print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
-                          "launches": 5}), flush=True)
+                          "launches": 25, "ms_per_copy": round(ms, 5),
+                          "copy_GBps": round(2 * src.numel() * 4 / (ms / 1e3) / 1e9, 1)}), flush=True)
         return
     p = w.plain_large(n=args.n, dtype=args.dtype)
     total = args.warmup + args.steps
