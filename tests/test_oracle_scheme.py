@@ -63,6 +63,44 @@ def test_lattice_isotropy():
         assert abs(lhs - b2 ** 3 * (d6 - 6 * allsame)) < 1e-15
 
 
+@pytest.mark.parametrize("A", ["0", "1/10"])
+@pytest.mark.parametrize("tau", ["1", "11/20"])
+def test_single_cell_collision_exact_rationals(A, tau):
+    """One cell's collision (Sec. 2 moments, the implicit sponge flux of
+    Sec. 6.3, the equilibrium with P^n = P - b^2 rho I and the forcing term)
+    evaluated in exact rational arithmetic for a hand-picked population
+    vector, gradient force G = kappa D rho + F with kappa = -1/5, D rho =
+    (1/2, -1/4) and F = (0, 0); the oracle must agree to rounding."""
+    from fractions import Fraction as Fr
+    cx = [0, 1, 0, -1, 0, 1, -1, -1, 1]
+    cy = [0, 0, 1, 0, -1, 1, 1, -1, -1]
+    wt = [Fr(4, 9)] + [Fr(1, 9)] * 4 + [Fr(1, 36)] * 4
+    b2 = Fr(1, 3)
+    A, tau = Fr(A), Fr(tau)
+    f = [Fr(i + 1, 100) for i in range(9)]
+    kappa = Fr(-1, 5)
+    G = (kappa * Fr(1, 2), kappa * Fr(-1, 4))
+    rho = sum(f)
+    m = (sum(fi * c for fi, c in zip(f, cx)), sum(fi * c for fi, c in zip(f, cy)))
+    P = [[sum(fi * a * b for fi, a, b in zip(f, ca, cb)) for cb in (cx, cy)] for ca in (cx, cy)]
+    j = tuple((m[a] + G[a] / 2) / (1 + A / 2) for a in range(2))
+    S = tuple(G[a] - A * j[a] for a in range(2))
+    Pn = [[P[a][b] - (b2 * rho if a == b else 0) for b in range(2)] for a in range(2)]
+    want = []
+    for i in range(9):
+        c = (cx[i], cy[i])
+        q = sum(Pn[a][b] * (c[a] * c[b] - (b2 if a == b else 0)) for a in range(2) for b in range(2))
+        feq = wt[i] * (rho + (j[0] * c[0] + j[1] * c[1]) / b2 + q / (2 * b2 * b2))
+        force = (1 - 1 / (2 * tau)) * wt[i] * (c[0] * S[0] + c[1] * S[1]) / b2
+        want.append(f[i] - (f[i] - feq) / tau + force)
+    fs, jo, So = stepper.collide_cell(np.array([float(x) for x in f]),
+                                      np.array([float(g) for g in G]), float(A), float(tau))
+    want = np.array([float(x) for x in want])
+    assert np.max(np.abs(fs - want)) <= 1e-15 * np.max(np.abs(want))
+    assert np.allclose(jo, [float(x) for x in j], rtol=1e-15, atol=0)
+    assert np.allclose(So, [float(x) for x in S], rtol=1e-15, atol=1e-18)
+
+
 def test_equilibrium_moments():
     """eq. MomentsFeq: moments 0-3 of f^eq are rho, j, P and
     Q^eq = b^2 (j d + j d + j d) (the paper's first moment read as j)."""
