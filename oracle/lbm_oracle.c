@@ -14,6 +14,8 @@
  * fusion or reordering: moments -> density gradient -> source -> flux and
  * sponge -> equilibrium and BGK collision -> receivers -> push streaming with
  * the wall rules of Sec. 6. OpenMP only splits each phase's loop over rows.
+ * The discrete adjoint (oracle_adjoint, at the end of the file) transposes
+ * each of these phases on its own and applies them in the reverse order.
  *
  * Conventions (readings of the paper, each listed in the design notes):
  *  - lattice: regular D2Q9, c = (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),
@@ -474,4 +476,317 @@ int oracle_run(const oracle_cfg *c, const double *lam, const double *mu,
   free(fs);
   grid_free(&g);
   return 0;
+}
+
+/* ------------------------------------------------------------------------ *
+ * Discrete adjoint of the step above.
+ *
+ * With kappa, the sponge and the sources fixed, one step maps the populations
+ * f(t) to f(t+1) linearly (plus the source term) and the receivers read a
+ * linear function of f(t). For the misfit L = 1/2 sum_t sum_r |v_r(t) -
+ * d_r(t)|^2 the adjoint populations fh(t) = dL/df(t) obey
+ *     fh(t) = (step)^T fh(t+1) + (receivers)^T e(t),   fh(T) = 0,
+ * with e = v - d the trace residual. Each phase of the forward step is
+ * transposed here on its own and applied in the reverse order:
+ *   push streaming^T  -> receivers^T -> collision, flux and sponge^T ->
+ *   source^T (gradients) -> density gradient^T -> moments^T.
+ * The gradients follow from the same sweep: G = kappa grad(rho) + F, so
+ *   dL/dkappa(x) = sum_t Gh(x, t) . grad(rho)(x, t),
+ *   dL/damp_s    = sum_t sum_x Gh(x, t) . d_s gauss_s(x) ricker_s(t).
+ * grad(rho)(t) comes from a forward run kept whole in memory (one rho plane
+ * per step), which suits the small grids this oracle is used on.
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+  double *rho, *mx, *my, *pxx, *pxy, *pyy; /* adjoints of the moments of f(t) */
+  double *Gx, *Gy, *jx, *jy;               /* adjoints of G and of j */
+  double *fstar;                           /* adjoint of f*(t), 9 planes */
+} oracle_adj;
+
+/* Transpose of phase_stream: fstar_h_i(x) gathers fh_i(x + c_i) through the
+ * same link classification; the free-surface values add their rho_air and
+ * P_xx,air sensitivities to the moment adjoints of rows b and in. */
+static void adj_stream(const oracle_grid *g, const double *fh_next, oracle_adj *a) {
+  const oracle_cfg *c = g->c;
+  const int nx = g->nx, ny = g->ny, rr = c->rigid_row;
+  const size_t N = g->N;
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) {
+      const size_t k = (size_t)y * nx + x;
+      for (int i = 0; i < 9; ++i) {
+        int xd = x + CX[i], yd = y + CY[i];
+        int rigid = 0, free_ny = 0, order = 1;
+        if (yd < 0 || yd >= ny) {
+          const int edge = (yd < 0) ? EDGE_TOP : EDGE_BOTTOM;
+          if (c->bc[edge] == BC_PERIODIC) yd = (yd + ny) % ny;
+          else if (c->bc[edge] == BC_RIGID) rigid = 1;
+          else {
+            free_ny = (yd < 0) ? -1 : +1;
+            order = c->bc[edge] == BC_FREE ? 1 : 0;
+          }
+        } else if (rr > 0 && ((CY[i] > 0 && y == rr - 1) || (CY[i] < 0 && y == rr))) {
+          rigid = 1;
+        }
+        if (xd < 0 || xd >= nx) {
+          const int edge = (xd < 0) ? EDGE_LEFT : EDGE_RIGHT;
+          if (c->bc[edge] == BC_PERIODIC) xd = (xd + nx) % nx;
+          else rigid = 1;
+        }
+        if (rigid) {
+          a->fstar[i * N + k] += fh_next[OPP[i] * N + k];
+        } else if (free_ny != 0) {
+          /* value = -f*_i + 2 w_i (rho_air + P^n_air : Q_i / (2 b^4)) */
+          const double gh = fh_next[OPP[i] * N + k];
+          const double cx = CX[i], cy = CY[i];
+          a->fstar[i * N + k] += -gh;
+          const double d_rho_air =
+              2.0 * WT[i] * (1.0 + (-B2 * (cx * cx - B2) - B2 * (cy * cy - B2)) / (2.0 * B2 * B2));
+          const double d_pxx_air = 2.0 * WT[i] * (cx * cx - B2) / (2.0 * B2 * B2);
+          const double cb = order ? 1.5 : 1.0, cin = order ? -0.5 : 0.0;
+          const size_t kb = k, kin = (size_t)(y - free_ny) * nx + x;
+          a->rho[kb] += cb * d_rho_air * gh;
+          a->rho[kin] += cin * d_rho_air * gh;
+          a->pxx[kb] += cb * d_pxx_air * gh;
+          a->pxx[kin] += cin * d_pxx_air * gh;
+        } else {
+          a->fstar[i * N + k] += fh_next[i * N + (size_t)yd * nx + xd];
+        }
+      }
+    }
+}
+
+/* Transpose of phase_receivers: v = j / rho0 at each receiver. */
+static void adj_receivers(const oracle_grid *g, const double *row, oracle_adj *a) {
+  const oracle_cfg *c = g->c;
+  const int ncomp = ((c->comp_mask & 1) ? 1 : 0) + ((c->comp_mask & 2) ? 1 : 0);
+  for (int r = 0; r < c->nrec; ++r) {
+    const size_t k = (size_t)c->rec_xy[2 * r + 1] * g->nx + c->rec_xy[2 * r];
+    int o = 0;
+    if (c->comp_mask & 1) a->jx[k] += row[r * ncomp + o++] * g->inv_rho0_rec[r];
+    if (c->comp_mask & 2) a->jy[k] += row[r * ncomp + o++] * g->inv_rho0_rec[r];
+  }
+}
+
+/* Transpose of oracle_collide_cell for one cell: from the adjoint of f* (and
+ * of j from the receivers) to the adjoints of f (direct part), rho, m, P, G. */
+static void adj_collide_cell(const double fsh[9], double A, double tau, double jh_rec[2],
+                             double fh[9], double *rh, double mh[2], double ph[3],
+                             double Gh[2]) {
+  const double cF = 1.0 - 1.0 / (2.0 * tau);
+  double jh[2] = {jh_rec[0], jh_rec[1]};
+  double Sh[2] = {0.0, 0.0};
+  double r = 0.0, pxx = 0.0, pxy = 0.0, pyy = 0.0;
+  for (int i = 0; i < 9; ++i) {
+    const double cx = CX[i], cy = CY[i];
+    /* f*_i = f_i - (f_i - feq_i)/tau + cF Si */
+    fh[i] = (1.0 - 1.0 / tau) * fsh[i];
+    const double eh = fsh[i] / tau;             /* adjoint of feq_i */
+    const double sih = cF * fsh[i];             /* adjoint of Si */
+    /* Si = w_i c_i . S / b^2 */
+    Sh[0] += sih * WT[i] * cx / B2;
+    Sh[1] += sih * WT[i] * cy / B2;
+    /* feq_i = w_i (rho + j.c/b^2 + P^n:Q_i/(2 b^4)), P^n = P - rho b^2 I */
+    const double qxx = (cx * cx - B2) / (2.0 * B2 * B2);
+    const double qxy = 2.0 * cx * cy / (2.0 * B2 * B2);
+    const double qyy = (cy * cy - B2) / (2.0 * B2 * B2);
+    r += eh * WT[i] * (1.0 - B2 * qxx - B2 * qyy);
+    jh[0] += eh * WT[i] * cx / B2;
+    jh[1] += eh * WT[i] * cy / B2;
+    pxx += eh * WT[i] * qxx;
+    pxy += eh * WT[i] * qxy;
+    pyy += eh * WT[i] * qyy;
+  }
+  const double inv = 1.0 / (1.0 + 0.5 * A);
+  for (int d = 0; d < 2; ++d) {
+    /* S = G - A j */
+    Gh[d] = Sh[d];
+    jh[d] -= A * Sh[d];
+    /* j = (m + G/2) / (1 + A/2) */
+    mh[d] = jh[d] * inv;
+    Gh[d] += 0.5 * jh[d] * inv;
+  }
+  *rh = r;
+  ph[0] = pxx;
+  ph[1] = pxy;
+  ph[2] = pyy;
+}
+
+/* Transpose of rho_x_neighbour / rho_y_neighbour: spread weight w of the
+ * neighbour density (or of its ghost 2 rho_b - rho_in) back onto rho. */
+static void adj_rho_x_neighbour(const oracle_grid *g, int x, int y, int dir, double w,
+                                double *rh) {
+  const int nx = g->nx;
+  int xn = x + dir;
+  double *r = rh + (size_t)y * nx;
+  if (xn < 0 || xn >= nx) {
+    const int edge = (xn < 0) ? EDGE_LEFT : EDGE_RIGHT;
+    if (g->c->bc[edge] == BC_PERIODIC) {
+      xn = (xn + nx) % nx;
+    } else {
+      r[x] += 2.0 * w;
+      r[x - dir] -= w;
+      return;
+    }
+  }
+  r[xn] += w;
+}
+
+static void adj_rho_y_neighbour(const oracle_grid *g, int x, int y, int dir, double w,
+                                double *rh) {
+  const int nx = g->nx, ny = g->ny;
+  const int rr = g->c->rigid_row;
+  int yn = y + dir;
+  int wall = 0;
+  if (yn < 0 || yn >= ny) {
+    const int edge = (yn < 0) ? EDGE_TOP : EDGE_BOTTOM;
+    if (g->c->bc[edge] == BC_PERIODIC)
+      yn = (yn + ny) % ny;
+    else
+      wall = 1;
+  } else if (rr > 0 && ((dir > 0 && y == rr - 1) || (dir < 0 && y == rr))) {
+    wall = 1;
+  }
+  if (wall) {
+    rh[(size_t)y * nx + x] += 2.0 * w;
+    rh[(size_t)(y - dir) * nx + x] -= w;
+    return;
+  }
+  rh[(size_t)yn * nx + x] += w;
+}
+
+static double *zalloc(size_t n) { return (double *)calloc(n ? n : 1, sizeof(double)); }
+
+/* Run the forward from t0 for nsteps steps (as oracle_run), then the adjoint
+ * back to t0.
+ *   residual:   e(t) for t = t0 .. t0+nsteps-1, layout of the traces
+ *               [nsteps][nrec][ncomp], or NULL (zero);
+ *   adj_init:   fh(t0+nsteps), 9 planes, or NULL (zero);
+ *   adj_out:    fh(t0), 9 planes (may be NULL);
+ *   grad_kappa: N values, dL/dkappa added in;
+ *   grad_amp:   nsrc values, dL/damp added in;
+ *   trace_out:  the forward traces (may be NULL).
+ * Returns 0, or -2 when memory runs out. */
+int oracle_adjoint(const oracle_cfg *c, const double *lam, const double *mu,
+                   const double *rho0, const double *init, int32_t init_kind, int64_t t0,
+                   int64_t nsteps, const double *residual, const double *adj_init,
+                   double *adj_out, double *grad_kappa, double *grad_amp,
+                   double *trace_out) {
+  oracle_grid g;
+  if (grid_alloc(&g, c, lam, mu, rho0) != 0) { grid_free(&g); return -2; }
+  const size_t N = g.N;
+  const int ncomp = ((c->comp_mask & 1) ? 1 : 0) + ((c->comp_mask & 2) ? 1 : 0);
+  double *f = zalloc(9 * N), *fs = zalloc(9 * N);
+  double *rho_hist = zalloc((size_t)(nsteps > 0 ? nsteps : 1) * N);
+  double *fh = zalloc(9 * N), *fh_next = zalloc(9 * N);
+  oracle_adj a;
+  a.rho = zalloc(N); a.mx = zalloc(N); a.my = zalloc(N);
+  a.pxx = zalloc(N); a.pxy = zalloc(N); a.pyy = zalloc(N);
+  a.Gx = zalloc(N); a.Gy = zalloc(N); a.jx = zalloc(N); a.jy = zalloc(N);
+  a.fstar = zalloc(9 * N);
+  double *dxh = zalloc(N), *dyh = zalloc(N);
+  int rc = 0;
+  if (!f || !fs || !rho_hist || !fh || !fh_next || !a.rho || !a.mx || !a.my || !a.pxx ||
+      !a.pxy || !a.pyy || !a.Gx || !a.Gy || !a.jx || !a.jy || !a.fstar || !dxh || !dyh) {
+    rc = -2;
+    goto done;
+  }
+
+  /* forward, keeping rho(t) of every step */
+  if (init && init_kind == 0) {
+    memcpy(fs, init, 9 * N * sizeof(double));
+    phase_moments(&g, fs);
+    phase_stream(&g, fs, f);
+  } else if (init) {
+    memcpy(f, init, 9 * N * sizeof(double));
+  }
+  for (int64_t n = 0; n < nsteps; ++n) {
+    const int64_t t = t0 + n;
+    phase_moments(&g, f);
+    memcpy(rho_hist + (size_t)n * N, g.rho, N * sizeof(double));
+    phase_density_gradient(&g);
+    phase_source(&g, t);
+    phase_collide(&g, f, fs);
+    if (trace_out && c->nrec > 0) phase_receivers(&g, trace_out + (size_t)n * c->nrec * ncomp);
+    phase_stream(&g, fs, f);
+  }
+
+  /* adjoint, t = t0+nsteps-1 down to t0 */
+  if (adj_init) memcpy(fh_next, adj_init, 9 * N * sizeof(double));
+  if (nsteps == 0) memcpy(fh, fh_next, 9 * N * sizeof(double));
+  for (int64_t n = nsteps - 1; n >= 0; --n) {
+    const int64_t t = t0 + n;
+    double *planes[] = {a.rho, a.mx, a.my, a.pxx, a.pxy, a.pyy, a.Gx, a.Gy, a.jx, a.jy};
+    for (size_t p = 0; p < sizeof(planes) / sizeof(planes[0]); ++p)
+      memset(planes[p], 0, N * sizeof(double));
+    memset(a.fstar, 0, 9 * N * sizeof(double));
+    /* the forward quantities of step t that the gradients need */
+    memcpy(g.rho, rho_hist + (size_t)n * N, N * sizeof(double));
+    phase_density_gradient(&g);
+
+    adj_stream(&g, fh_next, &a);
+    if (residual && c->nrec > 0) adj_receivers(&g, residual + (size_t)n * c->nrec * ncomp, &a);
+    for (size_t k = 0; k < N; ++k) {
+      double fsh[9], fhc[9], mh[2], ph[3], Gh[2], rh;
+      double jh[2] = {a.jx[k], a.jy[k]};
+      for (int i = 0; i < 9; ++i) fsh[i] = a.fstar[i * N + k];
+      adj_collide_cell(fsh, g.A[k], c->tau, jh, fhc, &rh, mh, ph, Gh);
+      for (int i = 0; i < 9; ++i) fh[i * N + k] = fhc[i];
+      a.rho[k] += rh;
+      a.mx[k] += mh[0];
+      a.my[k] += mh[1];
+      a.pxx[k] += ph[0];
+      a.pxy[k] += ph[1];
+      a.pyy[k] += ph[2];
+      a.Gx[k] = Gh[0];
+      a.Gy[k] = Gh[1];
+    }
+    /* source^T: G = kappa grad(rho) + F */
+    const int px = c->bc[EDGE_LEFT] == BC_PERIODIC;
+    const int py = c->bc[EDGE_TOP] == BC_PERIODIC;
+    for (int y = 0; y < g.ny; ++y)
+      for (int x = 0; x < g.nx; ++x) {
+        const size_t k = (size_t)y * g.nx + x;
+        if (grad_kappa) grad_kappa[k] += a.Gx[k] * g.dxr[k] + a.Gy[k] * g.dyr[k];
+        dxh[k] = g.kappa[k] * a.Gx[k];
+        dyh[k] = g.kappa[k] * a.Gy[k];
+        for (int s = 0; s < c->nsrc && grad_amp; ++s) {
+          const double *p = c->src + 8 * s;
+          const double dx = min_image(x - p[0], g.nx, px);
+          const double dy = min_image(y - p[1], g.ny, py);
+          const double r2 = dx * dx + dy * dy;
+          const double sig = p[2];
+          if (r2 > 81.0 * sig * sig) continue;
+          const double unit = exp(-r2 / (2.0 * sig * sig)) * ricker((double)t, p[6], p[7]);
+          grad_amp[s] += unit * (a.Gx[k] * p[3] + a.Gy[k] * p[4]);
+        }
+      }
+    /* density gradient^T: D_x rho = (N(+1) - N(-1)) / 2, the same for y */
+    for (int y = 0; y < g.ny; ++y)
+      for (int x = 0; x < g.nx; ++x) {
+        const size_t k = (size_t)y * g.nx + x;
+        adj_rho_x_neighbour(&g, x, y, +1, 0.5 * dxh[k], a.rho);
+        adj_rho_x_neighbour(&g, x, y, -1, -0.5 * dxh[k], a.rho);
+        adj_rho_y_neighbour(&g, x, y, +1, 0.5 * dyh[k], a.rho);
+        adj_rho_y_neighbour(&g, x, y, -1, -0.5 * dyh[k], a.rho);
+      }
+    /* moments^T */
+    for (size_t k = 0; k < N; ++k)
+      for (int i = 0; i < 9; ++i) {
+        const double cx = CX[i], cy = CY[i];
+        fh[i * N + k] += a.rho[k] + a.mx[k] * cx + a.my[k] * cy + a.pxx[k] * cx * cx +
+                         a.pxy[k] * cx * cy + a.pyy[k] * cy * cy;
+      }
+    double *tmp = fh_next;
+    fh_next = fh;
+    fh = tmp;
+  }
+  if (adj_out) memcpy(adj_out, nsteps > 0 ? fh_next : fh, 9 * N * sizeof(double));
+
+done:
+  free(f); free(fs); free(rho_hist); free(fh); free(fh_next);
+  free(a.rho); free(a.mx); free(a.my); free(a.pxx); free(a.pxy); free(a.pyy);
+  free(a.Gx); free(a.Gy); free(a.jx); free(a.jy); free(a.fstar);
+  free(dxh); free(dyh);
+  grid_free(&g);
+  return rc;
 }

@@ -46,6 +46,9 @@ def lib():
         L.oracle_run.restype = C.c_int
         L.oracle_run.argtypes = [C.POINTER(OracleCfg), _dp, _dp, _dp, _dp, C.c_int32,
                                  C.c_int64, C.c_int64, _dp, _dp, _dp, _dp]
+        L.oracle_adjoint.restype = C.c_int
+        L.oracle_adjoint.argtypes = [C.POINTER(OracleCfg), _dp, _dp, _dp, _dp, C.c_int32,
+                                     C.c_int64, C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp]
         L.oracle_collide_cell.restype = None
         L.oracle_collide_cell.argtypes = [_dp, _dp, C.c_double, C.c_double, _dp, _dp, _dp]
         L.oracle_equilibrium.restype = None
@@ -160,3 +163,60 @@ def run(p, nsteps: Optional[int] = None, t0: int = 0,
     del keep
     return {"fstar": fs_out, "f": f_out, "mom": mom,
             "trace": trace[:n, :p.nrec, :p.ncomp]}
+
+
+def adjoint(p, nsteps: Optional[int] = None, residual: Optional[np.ndarray] = None,
+            adj_init: Optional[np.ndarray] = None, t0: int = 0,
+            fstar_init: Optional[np.ndarray] = None, f_init: Optional[np.ndarray] = None,
+            medium=None):
+    """Forward run of ``p`` from t0 for nsteps steps, then the discrete adjoint
+    back to t0 (FP64, the transpose of every phase of the step).
+
+    residual: e(t) = v(t) - d(t), shape (nsteps, nrec, ncomp), or None (zero);
+    adj_init: fh(t0+nsteps) = dL/df(t0+nsteps), shape (9, ny, nx), or None.
+    Returns ``adj`` = dL/df(t0) (pre-collision populations at t0), ``grad_kappa``
+    (ny, nx), ``grad_amp`` (nsrc,) and the forward ``trace``.
+    """
+    n = p.nsteps if nsteps is None else int(nsteps)
+    lam, mu, rho0 = (medium if medium is not None else p.medium.full(p.ny, p.nx))
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    rho0 = np.ascontiguousarray(rho0, dtype=np.float64)
+    cfg, keep = _cfg(p)
+    shape = (9, p.ny, p.nx)
+    adj = np.zeros(shape)
+    gk = np.zeros((p.ny, p.nx))
+    ga = np.zeros(max(len(p.sources), 1))
+    trace = np.zeros((max(n, 1), max(p.nrec, 1), max(p.ncomp, 1)))
+    res = None
+    if residual is not None and p.nrec > 0:
+        res = np.ascontiguousarray(residual, dtype=np.float64).reshape(n, p.nrec, p.ncomp)
+    ai = None if adj_init is None else np.ascontiguousarray(adj_init, dtype=np.float64).reshape(shape)
+    init, kind = None, 0
+    if fstar_init is not None:
+        init = np.ascontiguousarray(fstar_init, dtype=np.float64).reshape(shape)
+    elif f_init is not None:
+        init, kind = np.ascontiguousarray(f_init, dtype=np.float64).reshape(shape), 1
+    rc = lib().oracle_adjoint(C.byref(cfg), _ptr(lam), _ptr(mu), _ptr(rho0), _ptr(init), kind,
+                              int(t0), n, _ptr(res), _ptr(ai), _ptr(adj), _ptr(gk), _ptr(ga),
+                              _ptr(trace) if p.nrec > 0 else _ptr(None))
+    if rc != 0:
+        raise MemoryError("oracle_adjoint failed with %d" % rc)
+    del keep
+    return {"adj": adj, "grad_kappa": gk, "grad_amp": ga[:len(p.sources)],
+            "trace": trace[:n, :p.nrec, :p.ncomp]}
+
+
+def misfit(trace: np.ndarray, d_obs: np.ndarray):
+    """L = 1/2 sum (v - d)^2 and the residual e = v - d."""
+    e = np.asarray(trace, dtype=np.float64) - np.asarray(d_obs, dtype=np.float64)
+    return 0.5 * float(np.sum(e * e)), e
+
+
+def lame_gradients(grad_kappa: np.ndarray, lam: np.ndarray, mu: np.ndarray):
+    """dL/dlambda and dL/dmu from dL/dkappa with kappa = b^2 (mu - lambda)/mu
+    (Sec. 4): dkappa/dlambda = -b^2/mu, dkappa/dmu = b^2 lambda/mu^2."""
+    b2 = 1.0 / 3.0
+    lam = np.asarray(lam, dtype=np.float64)
+    mu = np.asarray(mu, dtype=np.float64)
+    return -b2 * grad_kappa / mu, b2 * grad_kappa * lam / (mu * mu)
