@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 METRIC = "GLUPS (D2Q9 cell updates/s) and % HBM roofline; batched & adjoint vs plain"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2009_06404_amd/csrc/lbm_kernels.hip",
+                  "paper_2009_06404_amd/csrc/lbm_device.h",
                   "paper_2009_06404_amd/csrc/lbm_internal.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_interior_kernel_plain_large_4096_f32.txt")
 DOMINANT_KERNEL = "interior_kernel"

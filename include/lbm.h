@@ -201,6 +201,71 @@ int lbm_set_launch(lbm_ctx *ctx, const lbm_launch *cfg);
  * Synchronous. */
 int lbm_autotune(lbm_ctx *ctx, int32_t steps, lbm_launch *chosen);
 
+/* ---- Discrete adjoint: gradients of a receiver misfit ------------------
+ * With kappa, the sponge and the sources fixed, a step maps the pulled
+ * populations f(t) linearly to f(t+1) (plus the source term) and the
+ * receivers read v(t) = j(t)/rho0 linearly from f(t). For a misfit L of the
+ * traces, the adjoint state fh(t) = dL/df(t) obeys
+ *   fh(t) = step^T fh(t+1) + receivers^T e(t),  fh(T) = 0,  e(t) = dL/dv(t),
+ * and the gradients accumulate along the way:
+ *   dL/dkappa(x) = sum_t Gh(x,t) . grad(rho)(x,t),
+ *   dL/damp_s    = sum_t sum_x Gh(x,t) . d_s gauss_s(x) ricker_s(t),
+ * Gh = dL/dG being the adjoint of the source G = kappa grad(rho) + F (eq. S).
+ * grad(rho)(t) is recomputed per segment of seg_steps steps from checkpoints
+ * of the forward state taken while the forward run is recorded.
+ * Usage: lbm_adjoint_begin at the run's start time t0 (checkpoint 0 is the
+ * current state), lbm_step forward to t0 + nsteps (checkpoints are taken on
+ * the way), set the residual and gradient buffers per grid, then
+ * lbm_adjoint_step back towards t0. lbm_set_state ends the recording. */
+
+/* Device workspace an adjoint run of nsteps steps with checkpoints every
+ * seg_steps steps needs: ceil(nsteps/seg_steps) + 4 population buffers and
+ * seg_steps density planes. Host only. */
+int lbm_adjoint_workspace_bytes(const lbm_ctx *ctx, int32_t seg_steps, int64_t nsteps,
+                                size_t *bytes);
+
+/* Open a recording of the forward run from the current time t0 for nsteps
+ * steps. ws: caller-owned DEVICE memory, 256-B aligned, at least
+ * lbm_adjoint_workspace_bytes, used exclusively by this context until the
+ * next lbm_adjoint_begin or lbm_destroy. The adjoint state starts at
+ * t0 + nsteps with fh = 0. At most 16 sources per grid. Asynchronous. */
+int lbm_adjoint_begin(lbm_ctx *ctx, int32_t seg_steps, int64_t nsteps, void *ws, size_t ws_bytes);
+
+/* Per-grid adjoint inputs and outputs (DEVICE pointers, caller-owned, any may
+ * be NULL): residual e(t) in the layout of the grid's traces ([steps][n]
+ * [ncomp] of dtype, row k = step trace_t0 + k); grad_kappa [ny][nx] FP64 and
+ * grad_amp [nsrc] FP64, both accumulated into (the caller zeroes them). */
+int lbm_adjoint_set_io(lbm_ctx *ctx, int32_t g, const void *residual, double *grad_kappa,
+                       double *grad_amp);
+
+/* n adjoint steps from the adjoint time t_a down to t_a - n (>= t0), for all
+ * grids. The recorded forward run must have reached t0 + nsteps. Calls that
+ * overlap on one stream are ordered; the gradient buffers must stay valid
+ * until the work completes. Asynchronous. */
+int lbm_adjoint_step(lbm_ctx *ctx, int64_t n);
+
+int lbm_adjoint_time(const lbm_ctx *ctx, int64_t *t);
+
+/* The adjoint state fh(t_a) = dL/df(t_a) of grid g, DEVICE [9][ny][nx] of
+ * dtype in the direction order of lbm_get_state, out of / into the context.
+ * Asynchronous. */
+int lbm_adjoint_get_state(lbm_ctx *ctx, int32_t g, void *dst);
+int lbm_adjoint_set_state(lbm_ctx *ctx, int32_t g, const void *src);
+
+/* Residual and misfit of grid g's first nrows trace rows: residual = traces -
+ * d_obs (DEVICE, traces' layout, dtype; residual may be NULL), *misfit +=
+ * 1/2 sum residual^2 accumulated in FP64 (DEVICE double). Asynchronous. */
+int lbm_misfit(lbm_ctx *ctx, int32_t g, const void *d_obs, void *residual, int64_t nrows,
+               double *misfit);
+
+/* dL/dlambda = -b^2 dL/dkappa / mu and dL/dmu = b^2 lambda dL/dkappa / mu^2
+ * per cell (kappa = b^2 (mu - lambda)/mu, Sec. 4) for grid g, ADDED to
+ * grad_lam and grad_mu (so shots sharing a medium accumulate): lam, mu DEVICE
+ * [ny][nx] of dtype; grad_* DEVICE [ny][nx] FP64 (grad_lam or grad_mu may be
+ * NULL). Asynchronous. */
+int lbm_lame_gradient(lbm_ctx *ctx, int32_t g, const void *lam, const void *mu,
+                      const double *grad_kappa, double *grad_lam, double *grad_mu);
+
 /* Release the context's library-owned objects (device tables, graphs). Does
  * not touch caller-owned memory. Safe on NULL. */
 int lbm_destroy(lbm_ctx *ctx);

@@ -6,5 +6,6 @@ the torch tensors the library borrows."""
 from . import _lib
 from ._lib import LBMError
 from .solver import Solver
+from .autograd import ShotTraces, shot_traces
 
-__all__ = ["Solver", "LBMError", "_lib"]
+__all__ = ["Solver", "LBMError", "ShotTraces", "shot_traces", "_lib"]

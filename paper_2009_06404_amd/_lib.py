@@ -33,6 +33,9 @@ ENTRY_POINTS = (
     "lbm_set_sources", "lbm_set_receivers", "lbm_step", "lbm_step_timed", "lbm_moments",
     "lbm_get_time", "lbm_get_state", "lbm_set_state", "lbm_check_finite",
     "lbm_get_launch", "lbm_set_launch", "lbm_autotune", "lbm_destroy",
+    "lbm_adjoint_workspace_bytes", "lbm_adjoint_begin", "lbm_adjoint_set_io",
+    "lbm_adjoint_step", "lbm_adjoint_time", "lbm_adjoint_get_state", "lbm_adjoint_set_state",
+    "lbm_misfit", "lbm_lame_gradient",
 )
 
 
@@ -101,6 +104,15 @@ def lib():
             "lbm_set_launch": ([vp, C.POINTER(lbm_launch)], C.c_int),
             "lbm_autotune": ([vp, i32, C.POINTER(lbm_launch)], C.c_int),
             "lbm_destroy": ([vp], C.c_int),
+            "lbm_adjoint_workspace_bytes": ([vp, i32, i64, C.POINTER(C.c_size_t)], C.c_int),
+            "lbm_adjoint_begin": ([vp, i32, i64, vp, C.c_size_t], C.c_int),
+            "lbm_adjoint_set_io": ([vp, i32, vp, vp, vp], C.c_int),
+            "lbm_adjoint_step": ([vp, i64], C.c_int),
+            "lbm_adjoint_time": ([vp, C.POINTER(i64)], C.c_int),
+            "lbm_adjoint_get_state": ([vp, i32, vp], C.c_int),
+            "lbm_adjoint_set_state": ([vp, i32, vp], C.c_int),
+            "lbm_misfit": ([vp, i32, vp, vp, i64, vp], C.c_int),
+            "lbm_lame_gradient": ([vp, i32, vp, vp, vp, vp, vp], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -236,3 +248,44 @@ def lbm_autotune(ctx, steps: int = 5):
 def lbm_destroy(ctx) -> None:
     if ctx:
         check(lib().lbm_destroy(ctx))
+
+
+def lbm_adjoint_workspace_bytes(ctx, seg_steps: int, nsteps: int) -> int:
+    out = C.c_size_t(0)
+    check(lib().lbm_adjoint_workspace_bytes(ctx, int(seg_steps), int(nsteps), C.byref(out)))
+    return int(out.value)
+
+
+def lbm_adjoint_begin(ctx, seg_steps: int, nsteps: int, ws_ptr, ws_bytes: int) -> None:
+    check(lib().lbm_adjoint_begin(ctx, int(seg_steps), int(nsteps), ws_ptr, int(ws_bytes)))
+
+
+def lbm_adjoint_set_io(ctx, g: int, residual_ptr, grad_kappa_ptr, grad_amp_ptr) -> None:
+    check(lib().lbm_adjoint_set_io(ctx, int(g), residual_ptr, grad_kappa_ptr, grad_amp_ptr))
+
+
+def lbm_adjoint_step(ctx, n: int) -> None:
+    check(lib().lbm_adjoint_step(ctx, int(n)))
+
+
+def lbm_adjoint_time(ctx) -> int:
+    t = C.c_int64(0)
+    check(lib().lbm_adjoint_time(ctx, C.byref(t)))
+    return int(t.value)
+
+
+def lbm_adjoint_get_state(ctx, g: int, dst_ptr) -> None:
+    check(lib().lbm_adjoint_get_state(ctx, int(g), dst_ptr))
+
+
+def lbm_adjoint_set_state(ctx, g: int, src_ptr) -> None:
+    check(lib().lbm_adjoint_set_state(ctx, int(g), src_ptr))
+
+
+def lbm_misfit(ctx, g: int, d_obs_ptr, residual_ptr, nrows: int, misfit_ptr) -> None:
+    check(lib().lbm_misfit(ctx, int(g), d_obs_ptr, residual_ptr, int(nrows), misfit_ptr))
+
+
+def lbm_lame_gradient(ctx, g: int, lam_ptr, mu_ptr, grad_kappa_ptr, grad_lam_ptr, grad_mu_ptr) -> None:
+    check(lib().lbm_lame_gradient(ctx, int(g), lam_ptr, mu_ptr, grad_kappa_ptr, grad_lam_ptr,
+                                  grad_mu_ptr))

@@ -147,6 +147,20 @@ struct lbm_ctx {
   // graph of graph_chunk steps for each starting buffer parity
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   int gchunk = 0;
+  // adjoint: checkpoints of a recorded forward run and the adjoint state
+  struct Adj {
+    bool begun = false;
+    int32_t seg = 0;
+    int64_t t_begin = 0, nsteps = 0, nseg = 0, taken = 0;
+    size_t fbytes = 0, cbytes = 0;
+    char *ckpt = nullptr, *rbuf[2] = {nullptr, nullptr}, *abuf[2] = {nullptr, nullptr};
+    char *stash = nullptr;
+    int64_t t_adj = 0, stash_seg = -1;
+    int cur = 0;
+    std::vector<AdjGridDev> io;
+    bool io_dirty = true;
+  } adj;
+  DevBuf<AdjGridDev> d_adj_io;
 };
 
 namespace {
@@ -402,6 +416,7 @@ int commit_tables(lbm_ctx *c) {
     d.trace_max = R.max_steps;
     d.comp_mask = R.comp_mask;
     d.ncomp = (R.comp_mask & 1) + ((R.comp_mask >> 1) & 1);
+    d.c_off = c->L.k_off[g];
   }
   HIP_TRY(c->d_grids.upload(gd, s));
   c->tables_dirty = false;
@@ -693,6 +708,113 @@ int gather_scale(lbm_ctx *c, int g, RecHost &R) {
   return LBM_OK;
 }
 
+
+// ---- adjoint -------------------------------------------------------------
+
+size_t adj_fbytes(const lbm_ctx *c) { return (size_t)round_up(c->L.f_elems * (int64_t)c->L.esize, 256); }
+size_t adj_cbytes(const lbm_ctx *c) { return (size_t)round_up(c->L.k_elems * (int64_t)c->L.esize, 256); }
+
+size_t adj_ws_bytes(const lbm_ctx *c, int32_t seg, int64_t nsteps) {
+  const int64_t nseg = (nsteps + seg - 1) / seg;
+  return (size_t)nseg * adj_fbytes(c) + 4 * adj_fbytes(c) + (size_t)seg * adj_cbytes(c) + 256;
+}
+
+// Forward steps while an adjoint recording is open: the state at every
+// segment start t_begin + m * seg is copied to checkpoint m.
+int step_recording(lbm_ctx *c, int64_t n) {
+  auto &A = c->adj;
+  auto take = [&]() -> int {
+    HIP_TRY(hipMemcpyAsync(A.ckpt + (size_t)A.taken * A.fbytes, c->fbuf[c->cur], A.fbytes,
+                           hipMemcpyDeviceToDevice, c->stream));
+    A.taken += 1;
+    return LBM_OK;
+  };
+  while (n > 0) {
+    int64_t m = n;
+    if (A.taken < A.nseg) {
+      const int64_t next = A.t_begin + A.taken * A.seg;
+      if (c->t == next) {
+        int rc = take();
+        if (rc) return rc;
+        continue;
+      }
+      m = std::min(n, next - c->t);
+    }
+    int rc = c->dtype == LBM_F64 ? step_impl<double>(c, m) : step_impl<float>(c, m);
+    if (rc) return rc;
+    n -= m;
+  }
+  if (A.taken < A.nseg && c->t == A.t_begin + A.taken * A.seg) return take();
+  return LBM_OK;
+}
+
+// Recompute segment m from its checkpoint in the adjoint's own ping-pong
+// buffers, writing rho(t) of each step to the stash.
+template <typename real>
+int recompute_segment(lbm_ctx *c, int64_t m) {
+  auto &A = c->adj;
+  const int64_t tm = A.t_begin + m * A.seg;
+  const int64_t len = std::min<int64_t>(A.seg, A.t_begin + A.nsteps - tm);
+  HIP_TRY(hipMemcpyAsync(A.rbuf[0], A.ckpt + (size_t)m * A.fbytes, A.fbytes, hipMemcpyDeviceToDevice,
+                         c->stream));
+  for (int64_t s = 0; s < len; ++s) {
+    StepArgs<real> a = make_args<real>(c, 0);
+    a.fin = reinterpret_cast<const real *>(A.rbuf[s & 1]);
+    a.fout = reinterpret_cast<real *>(A.rbuf[(s & 1) ^ 1]);
+    a.t = tm + s;
+    a.rho_out = reinterpret_cast<real *>(A.stash + (size_t)s * A.cbytes);
+    if (c->ntiles_int > 0) {
+      StepArgs<real> ai = a;
+      ai.tiles = c->d_tiles_int.p;
+      HIP_TRY(launch_interior<real>(ai, c->launch.waves, 0, c->ntiles_int, c->stream));
+    }
+    HIP_TRY(launch_step<real>(a, c->launch.waves, 1, c->ntiles, kModeStash, c->stream));
+  }
+  A.stash_seg = m;
+  return LBM_OK;
+}
+
+template <typename real>
+int adjoint_impl(lbm_ctx *c, int64_t n) {
+  auto &A = c->adj;
+  if (A.io_dirty) {
+    HIP_TRY(c->d_adj_io.upload(A.io, c->stream));
+    A.io_dirty = false;
+  }
+  for (int64_t k = 0; k < n; ++k) {
+    const int64_t t = A.t_adj - 1;
+    const int64_t m = (t - A.t_begin) / A.seg;
+    if (A.stash_seg != m) {
+      int rc = recompute_segment<real>(c, m);
+      if (rc) return rc;
+    }
+    const int64_t tm = A.t_begin + m * A.seg;
+    AdjArgs<real> a;
+    memset(&a, 0, sizeof a);
+    a.fin = reinterpret_cast<const real *>(A.abuf[A.cur]);
+    a.fout = reinterpret_cast<real *>(A.abuf[A.cur ^ 1]);
+    a.grids = c->d_grids.p;
+    a.io = c->d_adj_io.p;
+    a.kappa_rows = reinterpret_cast<const real *>(c->d_krows.p);
+    a.kappa_cells = reinterpret_cast<const real *>(c->kcells);
+    a.sponge = reinterpret_cast<const real *>(c->d_sponge.p);
+    a.sources = c->d_src.p;
+    a.itab = c->d_itab.p;
+    a.rtab = reinterpret_cast<const real *>(c->d_rtab.p);
+    a.rho = reinterpret_cast<const real *>(A.stash + (size_t)(t - tm) * A.cbytes);
+    a.t = t;
+    a.omega = (real)(1.0 / c->tau);
+    a.cforce = (real)(1.0 - 0.5 / c->tau);
+    a.tiles = c->d_tiles.p;
+    HIP_TRY(launch_adjoint<real>(a, c->launch.waves, c->ntiles, c->stream));
+    a.tiles = c->d_tiles_int.p;
+    HIP_TRY(launch_adjoint<real>(a, c->launch.waves, c->ntiles_int, c->stream));
+    A.cur ^= 1;
+    A.t_adj = t;
+  }
+  return LBM_OK;
+}
+
 int check_ctx(const lbm_ctx *c) {
   if (!c) return fail(LBM_E_INVALID, "null context");
   return LBM_OK;
@@ -849,6 +971,11 @@ int lbm_step(lbm_ctx *c, int64_t n) {
   if (rc) return rc;
   if (n < 0) return fail(LBM_E_INVALID, "n must be >= 0");
   if (n == 0) return LBM_OK;
+  if (c->adj.begun && c->adj.taken < c->adj.nseg) {
+    rc = commit(c);
+    if (rc) return rc;
+    return step_recording(c, n);
+  }
   return c->dtype == LBM_F64 ? step_impl<double>(c, n) : step_impl<float>(c, n);
 }
 
@@ -857,6 +984,8 @@ int lbm_step_timed(lbm_ctx *c, int64_t n, lbm_kernel_times *out) {
   if (rc) return rc;
   if (n < 0) return fail(LBM_E_INVALID, "n must be >= 0");
   if (!out) return fail(LBM_E_INVALID, "out is null");
+  if (c->adj.begun && c->adj.taken < c->adj.nseg)
+    return fail(LBM_E_STATE, "an adjoint recording is open: advance it with lbm_step");
   rc = commit(c);
   if (rc) return rc;
   return c->dtype == LBM_F64 ? step_timed<double>(c, n, out) : step_timed<float>(c, n, out);
@@ -922,6 +1051,7 @@ int lbm_set_state(lbm_ctx *c, int32_t g, const void *src, int64_t t) {
   if (rc) return rc;
   if (g < 0 || g >= c->nbatch || !src) return fail(LBM_E_INVALID, "bad grid index or src");
   if (t < 0) return fail(LBM_E_INVALID, "t must be >= 0");
+  c->adj.begun = false;   // the recorded forward run no longer describes the state
   const lbm_grid &G = c->grids[g];
   const int64_t n = (int64_t)G.nx * G.ny;
   const int64_t ps = c->L.pitch[g], ys = 9 * (int64_t)c->L.pitch[g];
@@ -1066,9 +1196,149 @@ int lbm_autotune(lbm_ctx *c, int32_t steps, lbm_launch *chosen) {
   return LBM_OK;
 }
 
+
+int lbm_adjoint_workspace_bytes(const lbm_ctx *c, int32_t seg_steps, int64_t nsteps, size_t *bytes) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (seg_steps < 1 || nsteps < 1 || !bytes) return fail(LBM_E_INVALID, "need seg_steps >= 1, nsteps >= 1 and bytes");
+  *bytes = adj_ws_bytes(c, seg_steps, nsteps);
+  return LBM_OK;
+}
+
+int lbm_adjoint_begin(lbm_ctx *c, int32_t seg_steps, int64_t nsteps, void *ws, size_t ws_bytes) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (seg_steps < 1 || nsteps < 1) return fail(LBM_E_INVALID, "need seg_steps >= 1 and nsteps >= 1");
+  if (!ws || reinterpret_cast<uintptr_t>(ws) % 256) return fail(LBM_E_INVALID, "workspace must be 256-byte aligned device memory");
+  if (ws_bytes < adj_ws_bytes(c, seg_steps, nsteps)) return fail(LBM_E_NOMEM, "adjoint workspace too small");
+  for (int g = 0; g < c->nbatch; ++g)
+    if ((int)c->sources[g].size() > kMaxAdjSources)
+      return fail(LBM_E_INVALID, "at most 16 sources per grid in an adjoint run");
+  rc = commit(c);
+  if (rc) return rc;
+  auto &A = c->adj;
+  A.seg = seg_steps;
+  A.nsteps = nsteps;
+  A.nseg = (nsteps + seg_steps - 1) / seg_steps;
+  A.fbytes = adj_fbytes(c);
+  A.cbytes = adj_cbytes(c);
+  char *p = reinterpret_cast<char *>(ws);
+  A.ckpt = p;
+  p += (size_t)A.nseg * A.fbytes;
+  for (int i = 0; i < 2; ++i) { A.rbuf[i] = p; p += A.fbytes; }
+  for (int i = 0; i < 2; ++i) { A.abuf[i] = p; p += A.fbytes; }
+  A.stash = p;
+  A.t_begin = c->t;
+  A.t_adj = c->t + nsteps;
+  A.taken = 0;
+  A.cur = 0;
+  A.stash_seg = -1;
+  A.io.assign(c->nbatch, AdjGridDev{nullptr, nullptr, nullptr});
+  A.io_dirty = true;
+  HIP_TRY(hipMemsetAsync(A.abuf[0], 0, 2 * A.fbytes, c->stream));
+  HIP_TRY(hipMemcpyAsync(A.ckpt, c->fbuf[c->cur], A.fbytes, hipMemcpyDeviceToDevice, c->stream));
+  A.taken = 1;
+  A.begun = true;
+  return LBM_OK;
+}
+
+int lbm_adjoint_set_io(lbm_ctx *c, int32_t g, const void *residual, double *grad_kappa,
+                       double *grad_amp) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!c->adj.begun) return fail(LBM_E_STATE, "call lbm_adjoint_begin first");
+  if (g < 0 || g >= c->nbatch) return fail(LBM_E_INVALID, "grid index out of range");
+  c->adj.io[g] = AdjGridDev{residual, grad_kappa, grad_amp};
+  c->adj.io_dirty = true;
+  return LBM_OK;
+}
+
+int lbm_adjoint_step(lbm_ctx *c, int64_t n) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  auto &A = c->adj;
+  if (!A.begun) return fail(LBM_E_STATE, "call lbm_adjoint_begin first");
+  if (A.taken < A.nseg || c->t < A.t_begin + A.nsteps)
+    return fail(LBM_E_STATE, "the recorded forward run has not reached its last step yet");
+  if (n < 0 || n > A.t_adj - A.t_begin) return fail(LBM_E_INVALID, "n must be in [0, adjoint time - start time]");
+  if (n == 0) return LBM_OK;
+  rc = commit(c);
+  if (rc) return rc;
+  return c->dtype == LBM_F64 ? adjoint_impl<double>(c, n) : adjoint_impl<float>(c, n);
+}
+
+int lbm_adjoint_time(const lbm_ctx *c, int64_t *t) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!t) return fail(LBM_E_INVALID, "t is null");
+  if (!c->adj.begun) return fail(LBM_E_STATE, "call lbm_adjoint_begin first");
+  *t = c->adj.t_adj;
+  return LBM_OK;
+}
+
+static int adj_copy(lbm_ctx *c, int32_t g, void *dst, const void *src, bool out) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!c->adj.begun) return fail(LBM_E_STATE, "call lbm_adjoint_begin first");
+  if (g < 0 || g >= c->nbatch || !(out ? dst : src)) return fail(LBM_E_INVALID, "bad grid index or pointer");
+  const lbm_grid &G = c->grids[g];
+  const int64_t n = (int64_t)G.nx * G.ny;
+  const int64_t ps = c->L.pitch[g], ys = 9 * (int64_t)c->L.pitch[g];
+  char *buf = c->adj.abuf[c->adj.cur];
+  if (c->dtype == LBM_F64) {
+    double *b = reinterpret_cast<double *>(buf) + c->L.f_off[g];
+    if (out) HIP_TRY(launch_copy_planes<double>(b, ps, ys, reinterpret_cast<double *>(dst), n, G.nx, G.nx, G.ny, 9, c->stream));
+    else HIP_TRY(launch_copy_planes<double>(reinterpret_cast<const double *>(src), n, G.nx, b, ps, ys, G.nx, G.ny, 9, c->stream));
+  } else {
+    float *b = reinterpret_cast<float *>(buf) + c->L.f_off[g];
+    if (out) HIP_TRY(launch_copy_planes<float>(b, ps, ys, reinterpret_cast<float *>(dst), n, G.nx, G.nx, G.ny, 9, c->stream));
+    else HIP_TRY(launch_copy_planes<float>(reinterpret_cast<const float *>(src), n, G.nx, b, ps, ys, G.nx, G.ny, 9, c->stream));
+  }
+  return LBM_OK;
+}
+
+int lbm_adjoint_get_state(lbm_ctx *c, int32_t g, void *dst) { return adj_copy(c, g, dst, nullptr, true); }
+int lbm_adjoint_set_state(lbm_ctx *c, int32_t g, const void *src) { return adj_copy(c, g, nullptr, src, false); }
+
+int lbm_misfit(lbm_ctx *c, int32_t g, const void *d_obs, void *residual, int64_t nrows, double *misfit) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (g < 0 || g >= c->nbatch) return fail(LBM_E_INVALID, "grid index out of range");
+  const RecHost &R = c->recs[g];
+  if (!R.trace) return fail(LBM_E_STATE, "grid has no receivers");
+  if (!d_obs || !misfit) return fail(LBM_E_INVALID, "d_obs and misfit are required");
+  if (nrows < 0 || nrows > R.max_steps) return fail(LBM_E_INVALID, "nrows must be in [0, max_steps]");
+  const int ncomp = (R.comp_mask & 1) + ((R.comp_mask >> 1) & 1);
+  const int64_t n = nrows * (int64_t)(R.xy.size() / 2) * ncomp;
+  if (c->dtype == LBM_F64)
+    HIP_TRY(launch_misfit<double>(reinterpret_cast<const double *>(R.trace), reinterpret_cast<const double *>(d_obs),
+                                  reinterpret_cast<double *>(residual), n, misfit, c->stream));
+  else
+    HIP_TRY(launch_misfit<float>(reinterpret_cast<const float *>(R.trace), reinterpret_cast<const float *>(d_obs),
+                                 reinterpret_cast<float *>(residual), n, misfit, c->stream));
+  return LBM_OK;
+}
+
+int lbm_lame_gradient(lbm_ctx *c, int32_t g, const void *lam, const void *mu, const double *grad_kappa,
+                      double *grad_lam, double *grad_mu) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (g < 0 || g >= c->nbatch) return fail(LBM_E_INVALID, "grid index out of range");
+  if (!lam || !mu || !grad_kappa) return fail(LBM_E_INVALID, "lam, mu and grad_kappa are required");
+  const int64_t n = (int64_t)c->grids[g].nx * c->grids[g].ny;
+  if (c->dtype == LBM_F64)
+    HIP_TRY(launch_lame_gradient<double>(reinterpret_cast<const double *>(lam), reinterpret_cast<const double *>(mu),
+                                         grad_kappa, grad_lam, grad_mu, n, c->stream));
+  else
+    HIP_TRY(launch_lame_gradient<float>(reinterpret_cast<const float *>(lam), reinterpret_cast<const float *>(mu),
+                                        grad_kappa, grad_lam, grad_mu, n, c->stream));
+  return LBM_OK;
+}
+
 int lbm_destroy(lbm_ctx *c) {
   if (!c) return LBM_OK;
   drop_graphs(c);
+  c->d_adj_io.release();
   c->d_grids.release();
   c->d_tiles.release();
   c->d_tiles_int.release();

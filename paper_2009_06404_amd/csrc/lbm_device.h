@@ -1,0 +1,190 @@
+// Device helpers shared by the forward step kernels (lbm_kernels.hip) and the
+// adjoint kernels (lbm_adjoint.hip): the D2Q9 tables, the row and column
+// classification of the wall rules, population addressing, raw buffer
+// accesses, the source wavelet and the per-cell coefficient and sponge
+// look-ups. Not part of the public ABI.
+#pragma once
+
+#include "lbm_internal.h"
+
+namespace lbm {
+namespace dev {
+
+constexpr int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+// v / 36 for the integer-coefficient combinations: one multiply by the
+// rounded reciprocal and one Newton correction with the exact residual.
+template <typename real>
+__device__ __forceinline__ real div36(real v) {
+  const real r = real(1) / real(36);
+  const real q = v * r;
+  const real e = fma(-q, real(36), v);
+  return fma(e, r, q);
+}
+
+// Row classification for the pull of row y (uniform across the workgroup).
+struct Row {
+  int y;
+  int up, dn;           // source rows of links arriving with c_y = +1 / -1
+  int wall_up, wall_dn; // 0, kFree, kFree0 or kRigid: the wall those links cross
+};
+
+__device__ __forceinline__ Row make_row(const GridDev &g, int y) {
+  Row r;
+  r.y = y;
+  r.wall_up = 0;
+  r.wall_dn = 0;
+  r.up = y - 1;
+  r.dn = y + 1;
+  if (y == 0) {
+    if (g.bc[kEdgeTop] == kPeriodic) r.up = g.ny - 1;
+    else { r.wall_up = g.bc[kEdgeTop]; r.up = y; }
+  } else if (y == g.rigid_row) {
+    r.wall_up = kRigid;
+    r.up = y;
+  }
+  if (y == g.ny - 1) {
+    if (g.bc[kEdgeBottom] == kPeriodic) r.dn = 0;
+    else { r.wall_dn = g.bc[kEdgeBottom]; r.dn = y; }
+  } else if (g.rigid_row > 0 && y == g.rigid_row - 1) {
+    r.wall_dn = kRigid;
+    r.dn = y;
+  }
+  return r;
+}
+
+// The row after y in the marching order, or -1 past a non-periodic bottom.
+__device__ __forceinline__ int row_after(const GridDev &g, int y) {
+  if (y + 1 < g.ny) return y + 1;
+  return g.bc[kEdgeBottom] == kPeriodic ? 0 : -1;
+}
+
+// Column classification for one lane (left/right edges: periodic or rigid).
+struct Col {
+  int x, xl, xr;  // own column, source column for c_x = +1 and c_x = -1
+  bool wl, wr;    // links with c_x = +1 / -1 cross a rigid edge
+};
+
+__device__ __forceinline__ Col make_col(const GridDev &g, int x) {
+  Col c;
+  c.x = x;
+  c.wl = false;
+  c.wr = false;
+  c.xl = x - 1;
+  c.xr = x + 1;
+  if (x == 0) {
+    if (g.bc[kEdgeLeft] == kPeriodic) c.xl = g.nx - 1;
+    else { c.wl = true; c.xl = x; }
+  }
+  if (x == g.nx - 1) {
+    if (g.bc[kEdgeRight] == kPeriodic) c.xr = 0;
+    else { c.wr = true; c.xr = x; }
+  }
+  return c;
+}
+
+// Offset of population i of cell (x, y): rows of nine population runs.
+__device__ __forceinline__ int64_t qidx(const GridDev &g, int i, int y, int x) {
+  return ((int64_t)y * 9 + i) * g.pitch + x;
+}
+
+template <typename real>
+__device__ __forceinline__ real sum9(const real f[9]) {
+  return ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+}
+
+__device__ __forceinline__ double ricker(double t, double period, double t0) {
+  const double a = 3.14159265358979323846 * (t - t0) / period;
+  return (1.0 - 2.0 * a * a) * exp(-a * a);
+}
+
+__device__ __forceinline__ double min_image(double d, int n, bool periodic) {
+  if (periodic) {
+    if (d > 0.5 * n) d -= n;
+    else if (d < -0.5 * n) d += n;
+  }
+  return d;
+}
+
+// Raw buffer access: the tile's rows live behind one buffer descriptor
+// (scalar registers), row and population select a scalar byte offset, and
+// the lane's column a 32-bit vector byte offset, so the interior loads and all
+// stores carry no per-row vector address arithmetic. 0x00020000 is the
+// descriptor's format word for raw accesses on gfx9-family targets.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const void *base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, 0x7fffffff, 0x00020000);
+}
+
+template <typename real>
+struct Buf;
+
+template <>
+struct Buf<float> {
+  static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  }
+  static __device__ __forceinline__ void store_nt(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                  uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 2);
+  }
+};
+
+template <>
+struct Buf<double> {
+  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+  static __device__ __forceinline__ double load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  }
+  static __device__ __forceinline__ void store_nt(double v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                  uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 2);
+  }
+};
+
+// Elastic coefficient of cell (x, y).
+template <typename real>
+__device__ __forceinline__ real cell_kappa(const real *kappa_rows, const real *kappa_cells,
+                                           const GridDev &g, int y, int x) {
+  if (g.kmode == kKappaScalar) return (real)g.kscalar;
+  if (g.kmode == kKappaRows) return kappa_rows[g.k_off + y];
+  return kappa_cells[g.k_off + (int64_t)y * g.pitch + x];
+}
+
+// Sponge pair (A, 1/(1 + A/2)) along x for column x (left/right layers). The
+// table holds the pairs; the second decreases with the first, so the largest
+// A of overlapping layers pairs with the smallest reciprocal.
+template <typename real>
+__device__ __forceinline__ void sponge_x(const real *sponge, const GridDev &g, int x, real &A,
+                                         real &inv) {
+  A = real(0);
+  inv = real(1);
+  const int dl = x, dr = g.nx - 1 - x;
+  if (dl < g.sp_thick[kEdgeLeft]) {
+    A = sponge[g.sp_off[kEdgeLeft] + 2 * dl];
+    inv = sponge[g.sp_off[kEdgeLeft] + 2 * dl + 1];
+  }
+  if (dr < g.sp_thick[kEdgeRight]) {
+    A = max(A, sponge[g.sp_off[kEdgeRight] + 2 * dr]);
+    inv = min(inv, sponge[g.sp_off[kEdgeRight] + 2 * dr + 1]);
+  }
+}
+
+// Add the top/bottom layers of row y to a column's sponge pair.
+template <typename real>
+__device__ __forceinline__ void sponge_y(const real *sponge, const GridDev &g, int y, real &A,
+                                         real &inv) {
+  const int dt_ = y, db = g.ny - 1 - y;
+  if (dt_ < g.sp_thick[kEdgeTop]) {
+    A = max(A, sponge[g.sp_off[kEdgeTop] + 2 * dt_]);
+    inv = min(inv, sponge[g.sp_off[kEdgeTop] + 2 * dt_ + 1]);
+  }
+  if (db < g.sp_thick[kEdgeBottom]) {
+    A = max(A, sponge[g.sp_off[kEdgeBottom] + 2 * db]);
+    inv = min(inv, sponge[g.sp_off[kEdgeBottom] + 2 * db + 1]);
+  }
+}
+
+}  // namespace dev
+}  // namespace lbm

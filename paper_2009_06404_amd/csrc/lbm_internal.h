@@ -37,6 +37,8 @@ struct GridDev {
   void *trace;                    // [max_steps][nrec][ncomp] of dtype
   int64_t trace_t0, trace_max;
   int32_t ncomp, comp_mask;
+  int64_t c_off;                  // offset of the grid in a packed plane of one value
+                                  // per cell (same pitch), e.g. the density stash
 };
 
 struct SourceDev {
@@ -67,14 +69,54 @@ struct StepArgs {
   real cforce;           // 1 - 1/(2 tau)
   real *mom;             // moments mode: [6][ny][nx] of grid mom_grid
   int32_t mom_grid;
+  real *rho_out;         // stash mode: rho(t) of every cell at c_off + y * pitch + x
 };
 
-enum Mode { kModeStep = 0, kModeMoments = 1 };
+// kModeStash: the step plus the density of every cell written to rho_out,
+// without the receivers (the forward recompute of the adjoint).
+enum Mode { kModeStep = 0, kModeMoments = 1, kModeStash = 2 };
+
+// The adjoint's per-grid inputs and outputs (device pointers, caller-owned).
+struct AdjGridDev {
+  const void *residual;   // e(t) in the traces' layout [steps][nrec][ncomp], or null
+  double *grad_kappa;     // [ny][nx] dL/dkappa, accumulated, or null
+  double *grad_amp;       // [nsrc] dL/damp, accumulated, or null
+};
+
+constexpr int kMaxAdjSources = 16;   // sources per grid with an amplitude gradient
+
+template <typename real>
+struct AdjArgs {
+  const real *fin;        // fh(t+1), all grids (population-buffer layout)
+  real *fout;             // fh(t)
+  const GridDev *grids;
+  const AdjGridDev *io;
+  const TileDev *tiles;
+  const real *kappa_rows;
+  const real *kappa_cells;
+  const real *sponge;
+  const SourceDev *sources;
+  const int32_t *itab;
+  const real *rtab;
+  const real *rho;        // rho(t) of every cell (stash layout), for the gradient
+  int64_t t;
+  real omega, cforce;
+};
+
+template <typename real>
+hipError_t launch_adjoint(const AdjArgs<real> &a, int waves, int ntiles, hipStream_t stream);
+template <typename real>
+hipError_t launch_misfit(const real *trace, const real *d_obs, real *residual, int64_t n,
+                         double *misfit, hipStream_t stream);
+template <typename real>
+hipError_t launch_lame_gradient(const real *lam, const real *mu, const double *grad_kappa,
+                                double *grad_lam, double *grad_mu, int64_t n, hipStream_t stream);
 
 template <typename real>
 hipError_t launch_step(const StepArgs<real> &a, int waves, int prefetch, int ntiles, int mode,
                        hipStream_t stream);
 
+// Interior tiles; with a.rho_out set, the one-column kernel also writes rho(t).
 template <typename real>
 hipError_t launch_interior(const StepArgs<real> &a, int waves, int pair, int ntiles,
                            hipStream_t stream);

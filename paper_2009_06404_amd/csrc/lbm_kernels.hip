@@ -36,90 +36,14 @@
 // them with the rounded constants 1/3, 1/9, 1/36 instead biases every step in
 // the same direction (the collision invariants drift by ~1e-8 per step in
 // FP32), which grows linearly with the step count.
-#include "lbm_internal.h"
+#include "lbm_device.h"
 
 namespace lbm {
 namespace {
 
-constexpr int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-constexpr int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+using namespace dev;
 
-// v / 36 for the integer-coefficient combinations: one multiply by the
-// rounded reciprocal and one Newton correction with the exact residual.
-template <typename real>
-__device__ __forceinline__ real div36(real v) {
-  const real r = real(1) / real(36);
-  const real q = v * r;
-  const real e = fma(-q, real(36), v);
-  return fma(e, r, q);
-}
 
-// Row classification for the pull of row y (uniform across the workgroup).
-struct Row {
-  int y;
-  int up, dn;           // source rows of links arriving with c_y = +1 / -1
-  int wall_up, wall_dn; // 0, kFree, kFree0 or kRigid: the wall those links cross
-};
-
-__device__ __forceinline__ Row make_row(const GridDev &g, int y) {
-  Row r;
-  r.y = y;
-  r.wall_up = 0;
-  r.wall_dn = 0;
-  r.up = y - 1;
-  r.dn = y + 1;
-  if (y == 0) {
-    if (g.bc[kEdgeTop] == kPeriodic) r.up = g.ny - 1;
-    else { r.wall_up = g.bc[kEdgeTop]; r.up = y; }
-  } else if (y == g.rigid_row) {
-    r.wall_up = kRigid;
-    r.up = y;
-  }
-  if (y == g.ny - 1) {
-    if (g.bc[kEdgeBottom] == kPeriodic) r.dn = 0;
-    else { r.wall_dn = g.bc[kEdgeBottom]; r.dn = y; }
-  } else if (g.rigid_row > 0 && y == g.rigid_row - 1) {
-    r.wall_dn = kRigid;
-    r.dn = y;
-  }
-  return r;
-}
-
-// The row after y in the marching order, or -1 past a non-periodic bottom.
-__device__ __forceinline__ int row_after(const GridDev &g, int y) {
-  if (y + 1 < g.ny) return y + 1;
-  return g.bc[kEdgeBottom] == kPeriodic ? 0 : -1;
-}
-
-// Column classification for one lane (left/right edges: periodic or rigid).
-struct Col {
-  int x, xl, xr;  // own column, source column for c_x = +1 and c_x = -1
-  bool wl, wr;    // links with c_x = +1 / -1 cross a rigid edge
-};
-
-__device__ __forceinline__ Col make_col(const GridDev &g, int x) {
-  Col c;
-  c.x = x;
-  c.wl = false;
-  c.wr = false;
-  c.xl = x - 1;
-  c.xr = x + 1;
-  if (x == 0) {
-    if (g.bc[kEdgeLeft] == kPeriodic) c.xl = g.nx - 1;
-    else { c.wl = true; c.xl = x; }
-  }
-  if (x == g.nx - 1) {
-    if (g.bc[kEdgeRight] == kPeriodic) c.xr = 0;
-    else { c.wr = true; c.xr = x; }
-  }
-  return c;
-}
-
-// Offset of population i of cell (x, y): rows of nine population runs.
-__device__ __forceinline__ int64_t qidx(const GridDev &g, int i, int y, int x) {
-  return ((int64_t)y * 9 + i) * g.pitch + x;
-}
 
 // Pulled populations of a row without a horizontal wall (general addressing:
 // used for halo columns and for tiles that touch a rigid side edge).
@@ -191,58 +115,6 @@ __device__ __forceinline__ void pull(const real *__restrict__ base, const GridDe
   else pull_wall(base, g, r, c, out);
 }
 
-template <typename real>
-__device__ __forceinline__ real sum9(const real f[9]) {
-  return ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-}
-
-__device__ __forceinline__ double ricker(double t, double period, double t0) {
-  const double a = 3.14159265358979323846 * (t - t0) / period;
-  return (1.0 - 2.0 * a * a) * exp(-a * a);
-}
-
-__device__ __forceinline__ double min_image(double d, int n, bool periodic) {
-  if (periodic) {
-    if (d > 0.5 * n) d -= n;
-    else if (d < -0.5 * n) d += n;
-  }
-  return d;
-}
-
-// Raw buffer access: the tile's rows live behind one buffer descriptor
-// (scalar registers), row and population select a scalar byte offset, and
-// the lane's column a 32-bit vector byte offset, so the interior loads and all
-// stores carry no per-row vector address arithmetic. 0x00020000 is the
-// descriptor's format word for raw accesses on gfx9-family targets.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const void *base) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, 0x7fffffff, 0x00020000);
-}
-
-template <typename real>
-struct Buf;
-
-template <>
-struct Buf<float> {
-  static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
-  }
-  static __device__ __forceinline__ void store_nt(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
-                                                  uint32_t soff) {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, voff, soff, 2);
-  }
-};
-
-template <>
-struct Buf<double> {
-  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-  static __device__ __forceinline__ double load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
-  }
-  static __device__ __forceinline__ void store_nt(double v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
-                                                  uint32_t soff) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 2);
-  }
-};
 
 // Pull of an interior row (no horizontal wall, no wrap in y, no rigid side
 // edge touched by the tile). rsrc is based at row ybase <= y - 1; rowb is the
@@ -314,47 +186,6 @@ __device__ __forceinline__ void collide(const real f[9], const CellState<real> &
   for (int i = 0; i < 9; ++i) out[i] = fma(-omega, f[i], f[i]) + div36(E[i]);
 }
 
-// Elastic coefficient of cell (x, y).
-template <typename real>
-__device__ __forceinline__ real cell_kappa(const StepArgs<real> &a, const GridDev &g, int y, int x) {
-  if (g.kmode == kKappaScalar) return (real)g.kscalar;
-  if (g.kmode == kKappaRows) return a.kappa_rows[g.k_off + y];
-  return a.kappa_cells[g.k_off + (int64_t)y * g.pitch + x];
-}
-
-// Sponge pair (A, 1/(1 + A/2)) along x for column x (left/right layers). The
-// table holds the pairs; the second decreases with the first, so the largest
-// A of overlapping layers pairs with the smallest reciprocal.
-template <typename real>
-__device__ __forceinline__ void sponge_x(const StepArgs<real> &a, const GridDev &g, int x, real &A,
-                                         real &inv) {
-  A = real(0);
-  inv = real(1);
-  const int dl = x, dr = g.nx - 1 - x;
-  if (dl < g.sp_thick[kEdgeLeft]) {
-    A = a.sponge[g.sp_off[kEdgeLeft] + 2 * dl];
-    inv = a.sponge[g.sp_off[kEdgeLeft] + 2 * dl + 1];
-  }
-  if (dr < g.sp_thick[kEdgeRight]) {
-    A = max(A, a.sponge[g.sp_off[kEdgeRight] + 2 * dr]);
-    inv = min(inv, a.sponge[g.sp_off[kEdgeRight] + 2 * dr + 1]);
-  }
-}
-
-// Add the top/bottom layers of row y to a column's sponge pair.
-template <typename real>
-__device__ __forceinline__ void sponge_y(const StepArgs<real> &a, const GridDev &g, int y, real &A,
-                                         real &inv) {
-  const int dt_ = y, db = g.ny - 1 - y;
-  if (dt_ < g.sp_thick[kEdgeTop]) {
-    A = max(A, a.sponge[g.sp_off[kEdgeTop] + 2 * dt_]);
-    inv = min(inv, a.sponge[g.sp_off[kEdgeTop] + 2 * dt_ + 1]);
-  }
-  if (db < g.sp_thick[kEdgeBottom]) {
-    A = max(A, a.sponge[g.sp_off[kEdgeBottom] + 2 * db]);
-    inv = min(inv, a.sponge[g.sp_off[kEdgeBottom] + 2 * db + 1]);
-  }
-}
 
 template <typename real, int NW, int MODE, int PF>
 __global__ __launch_bounds__(64 * NW) void step_kernel(StepArgs<real> a) {
@@ -413,7 +244,7 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepArgs<real> a) {
   const __amdgpu_buffer_rsrc_t rout = tile_rsrc(a.fout + g.f_off + (int64_t)ybase * 9 * pitch);
 
   real A_x, inv_x;
-  sponge_x(a, g, xa, A_x, inv_x);
+  sponge_x(a.sponge, g, xa, A_x, inv_x);
 
   // Rows with a horizontal wall link or a wrap in y.
   auto special = [&](int y) -> bool {
@@ -507,9 +338,9 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepArgs<real> a) {
     else if (wall_dn) dy = rho_c - rho_m;
     else dy = real(0.5) * (rho_n - rho_m);
 
-    const real kap = cell_kappa(a, g, y, xa);
+    const real kap = cell_kappa(a.kappa_rows, a.kappa_cells, g, y, xa);
     real A = A_x, inv = inv_x;
-    sponge_y(a, g, y, A, inv);
+    sponge_y(a.sponge, g, y, A, inv);
 
     // Body force (Gaussian x Ricker), only on rows within 9 sigma of a source.
     real Fx = real(0), Fy = real(0);
@@ -545,8 +376,9 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepArgs<real> a) {
         a.mom[5 * n + o] = pyy;
       }
     } else {
+      if (MODE == kModeStash && active) a.rho_out[g.c_off + (int64_t)y * pitch + x] = rho;
       // Receivers on this row.
-      if (g.nrec > 0) {
+      if (MODE == kModeStep && g.nrec > 0) {
         const int slot = a.itab[g.rowtab_off + y];
         if (slot >= 0 && active) {
           int rid = a.itab[g.rmap_off + (int64_t)slot * nx + x];
@@ -593,7 +425,7 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepArgs<real> a) {
 // in them. The host sorts tiles into this list; the arithmetic is the same
 // code as the general kernel's, so a cell's result does not depend on which
 // kernel updated it.
-template <typename real, int NW>
+template <typename real, int NW, bool STASH>
 __global__ __launch_bounds__(64 * NW) void interior_kernel(StepArgs<real> a) {
   constexpr int W = 64 * NW;
   __shared__ real srho[2][W + 2];
@@ -631,7 +463,7 @@ __global__ __launch_bounds__(64 * NW) void interior_kernel(StepArgs<real> a) {
   const __amdgpu_buffer_rsrc_t rout = tile_rsrc(a.fout + g.f_off + (int64_t)ybase * 9 * pitch);
 
   real A_x, inv_x;
-  sponge_x(a, g, xa, A_x, inv_x);
+  sponge_x(a.sponge, g, xa, A_x, inv_x);
 
   real fa[9], fb[9];
   pull_fast(rin, ybase, y0 - 1, rowb, qb, o0, ol, orr, fa);
@@ -664,11 +496,12 @@ __global__ __launch_bounds__(64 * NW) void interior_kernel(StepArgs<real> a) {
     // Centred density gradient (eq. FDrho) and the source (eq. S).
     const real dx = real(0.5) * (rho_r - rho_l);
     const real dy = real(0.5) * (rho_n - rho_m);
-    const real kap = cell_kappa(a, g, y, xa);
+    const real kap = cell_kappa(a.kappa_rows, a.kappa_cells, g, y, xa);
     real A = A_x, inv = inv_x;
-    sponge_y(a, g, y, A, inv);
+    sponge_y(a.sponge, g, y, A, inv);
     const CellState<real> cs = cell_state(fa, rho_c, kap * dx, kap * dy, A, inv);
     if (active) {
+      if (STASH) a.rho_out[g.c_off + (int64_t)y * pitch + x] = rho_c;
       real fs[9];
       collide(fa, cs, omega, cforce, fs);
       const uint32_t rs = (uint32_t)(y - ybase) * rowb;
@@ -803,8 +636,8 @@ __global__ __launch_bounds__(64 * NW) void interior2_kernel(StepArgs<real> a) {
   const __amdgpu_buffer_rsrc_t rout = tile_rsrc(a.fout + g.f_off + (int64_t)ybase * 9 * pitch);
 
   real A0, inv0, A1, inv1;
-  sponge_x(a, g, xa, A0, inv0);
-  sponge_x(a, g, xa + 1, A1, inv1);
+  sponge_x(a.sponge, g, xa, A0, inv0);
+  sponge_x(a.sponge, g, xa + 1, A1, inv1);
 
   real ua[9], va[9], ub[9], vb[9];
   pull_pair(rin, ybase, y0 - 1, rowb, qb, o0, ol, orr, wl, wr, last_off, ua, va);
@@ -836,10 +669,10 @@ __global__ __launch_bounds__(64 * NW) void interior2_kernel(StepArgs<real> a) {
     srho[s ^ 1][2 * lane + 2] = rn1;
     if (lane < 2) srho[s ^ 1][hslot] = hr_n;
 
-    const real kap0 = cell_kappa(a, g, y, xa), kap1 = cell_kappa(a, g, y, xa + 1);
+    const real kap0 = cell_kappa(a.kappa_rows, a.kappa_cells, g, y, xa), kap1 = cell_kappa(a.kappa_rows, a.kappa_cells, g, y, xa + 1);
     real Ay0 = A0, iy0 = inv0, Ay1 = A1, iy1 = inv1;
-    sponge_y(a, g, y, Ay0, iy0);
-    sponge_y(a, g, y, Ay1, iy1);
+    sponge_y(a.sponge, g, y, Ay0, iy0);
+    sponge_y(a.sponge, g, y, Ay1, iy1);
     const real dx0 = real(0.5) * (rc1 - rl), dy0 = real(0.5) * (rn0 - rm0);
     const real dx1 = real(0.5) * (rr - rc0), dy1 = real(0.5) * (rn1 - rm1);
     const CellState<real> c0 = cell_state(ua, rc0, kap0 * dx0, kap0 * dy0, Ay0, iy0);
@@ -870,7 +703,13 @@ hipError_t launch_step(const StepArgs<real> &a, int waves, int prefetch, int nti
   dim3 grid(ntiles), block(64 * waves);
 #define LBM_LAUNCH(NW, MODE, PF) \
   hipLaunchKernelGGL((step_kernel<real, NW, MODE, PF>), grid, block, 0, stream, a)
-  if (mode == kModeStep) {
+  if (mode == kModeStash) {
+    if (waves == 1) LBM_LAUNCH(1, kModeStash, 1);
+    else if (waves == 2) LBM_LAUNCH(2, kModeStash, 1);
+    else if (waves == 4) LBM_LAUNCH(4, kModeStash, 1);
+    else if (waves == 8) LBM_LAUNCH(8, kModeStash, 1);
+    else return hipErrorInvalidValue;
+  } else if (mode == kModeStep) {
     if (prefetch == 2) {
       if (waves == 1) LBM_LAUNCH(1, kModeStep, 2);
       else if (waves == 2) LBM_LAUNCH(2, kModeStep, 2);
@@ -902,7 +741,14 @@ hipError_t launch_interior(const StepArgs<real> &a, int waves, int pair, int nti
                            hipStream_t stream) {
   if (ntiles <= 0) return hipSuccess;
   dim3 grid(ntiles);
-  if (pair) {
+  if (a.rho_out) {
+    dim3 block(64 * waves);
+    if (waves == 1) hipLaunchKernelGGL((interior_kernel<real, 1, true>), grid, block, 0, stream, a);
+    else if (waves == 2) hipLaunchKernelGGL((interior_kernel<real, 2, true>), grid, block, 0, stream, a);
+    else if (waves == 4) hipLaunchKernelGGL((interior_kernel<real, 4, true>), grid, block, 0, stream, a);
+    else if (waves == 8) hipLaunchKernelGGL((interior_kernel<real, 8, true>), grid, block, 0, stream, a);
+    else return hipErrorInvalidValue;
+  } else if (pair) {
     dim3 block(32 * waves);
     if (waves == 2) hipLaunchKernelGGL((interior2_kernel<real, 1>), grid, block, 0, stream, a);
     else if (waves == 4) hipLaunchKernelGGL((interior2_kernel<real, 2>), grid, block, 0, stream, a);
@@ -910,10 +756,10 @@ hipError_t launch_interior(const StepArgs<real> &a, int waves, int pair, int nti
     else return hipErrorInvalidValue;
   } else {
     dim3 block(64 * waves);
-    if (waves == 1) hipLaunchKernelGGL((interior_kernel<real, 1>), grid, block, 0, stream, a);
-    else if (waves == 2) hipLaunchKernelGGL((interior_kernel<real, 2>), grid, block, 0, stream, a);
-    else if (waves == 4) hipLaunchKernelGGL((interior_kernel<real, 4>), grid, block, 0, stream, a);
-    else if (waves == 8) hipLaunchKernelGGL((interior_kernel<real, 8>), grid, block, 0, stream, a);
+    if (waves == 1) hipLaunchKernelGGL((interior_kernel<real, 1, false>), grid, block, 0, stream, a);
+    else if (waves == 2) hipLaunchKernelGGL((interior_kernel<real, 2, false>), grid, block, 0, stream, a);
+    else if (waves == 4) hipLaunchKernelGGL((interior_kernel<real, 4, false>), grid, block, 0, stream, a);
+    else if (waves == 8) hipLaunchKernelGGL((interior_kernel<real, 8, false>), grid, block, 0, stream, a);
     else return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -36,7 +36,7 @@ class Solver:
 
     def __init__(self, problems, dtype: Optional[str] = None, device: str = "cuda",
                  trace_steps: Optional[int] = None, launch: Optional[dict] = None,
-                 autotune: bool = False):
+                 autotune: bool = False, fields=None):
         if not isinstance(problems, (list, tuple)):
             problems = [problems]
         self.problems = list(problems)
@@ -44,6 +44,8 @@ class Solver:
         self.dtype = dtype or p0.dtype
         self.code, self.tdtype = _DT[self.dtype]
         self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
         taus = {float(p.tau) for p in self.problems}
         if len(taus) != 1:
             raise ValueError("all problems of a batch must share tau")
@@ -51,13 +53,21 @@ class Solver:
         grids = [(p.nx, p.ny) for p in self.problems]
         lam, mu, rho = [], [], []
         for p in self.problems:
-            l, m, r = _field_tensor(p.medium, p.ny, p.nx, self.tdtype, self.device)
+            if fields is not None:
+                # (lam, mu, rho) tensors of shape (ny, nx), shared by every grid
+                l, m, r = (torch.as_tensor(f).to(device=self.device, dtype=self.tdtype)
+                           for f in fields)
+                if tuple(l.shape) != (p.ny, p.nx):
+                    raise ValueError("fields must have each grid's shape (ny, nx)")
+            else:
+                l, m, r = _field_tensor(p.medium, p.ny, p.nx, self.tdtype, self.device)
             lam.append(l.reshape(-1))
             mu.append(m.reshape(-1))
             rho.append(r.reshape(-1))
         self.lam = torch.cat(lam)
         self.mu = torch.cat(mu)
         self.rho = torch.cat(rho)
+        self.cell_off = np.cumsum([0] + [p.nx * p.ny for p in self.problems])
         self.ws_bytes = L.lbm_workspace_bytes(grids, self.code)
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.current_stream(self.device)
@@ -131,6 +141,76 @@ class Solver:
 
     def autotune(self, steps: int = 5) -> dict:
         return L.lbm_autotune(self.ctx, steps)
+
+    # -- adjoint ---------------------------------------------------------
+    def adjoint_begin(self, nsteps: int, seg_steps: int = 100) -> None:
+        """Record the next nsteps forward steps (checkpoints every seg_steps)."""
+        nbytes = L.lbm_adjoint_workspace_bytes(self.ctx, seg_steps, nsteps)
+        self.adj_ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        L.lbm_adjoint_begin(self.ctx, seg_steps, nsteps, self.adj_ws.data_ptr(), nbytes)
+        self._adj_keep = {}
+
+    def adjoint_set_io(self, g: int, residual: Optional[torch.Tensor] = None,
+                       grad_kappa: Optional[torch.Tensor] = None,
+                       grad_amp: Optional[torch.Tensor] = None) -> None:
+        """Residual dL/dv (traces' layout and dtype) and the FP64 gradient
+        buffers of grid g (accumulated into)."""
+        ptrs = []
+        for t, dt in ((residual, self.tdtype), (grad_kappa, torch.float64),
+                      (grad_amp, torch.float64)):
+            if t is None:
+                ptrs.append(None)
+                continue
+            if t.dtype != dt or not t.is_contiguous() or t.device != self.device:
+                raise ValueError("adjoint buffers must be contiguous device tensors of the "
+                                 "expected dtype")
+            ptrs.append(t.data_ptr())
+        self._adj_keep[g] = (residual, grad_kappa, grad_amp)
+        L.lbm_adjoint_set_io(self.ctx, g, *ptrs)
+
+    def adjoint_step(self, n: int) -> None:
+        L.lbm_adjoint_step(self.ctx, n)
+
+    @property
+    def adjoint_time(self) -> int:
+        return L.lbm_adjoint_time(self.ctx)
+
+    def adjoint_state(self, g: int = 0) -> torch.Tensor:
+        p = self.problems[g]
+        out = torch.empty((9, p.ny, p.nx), dtype=self.tdtype, device=self.device)
+        L.lbm_adjoint_get_state(self.ctx, g, out.data_ptr())
+        return out
+
+    def set_adjoint_state(self, g: int, src: torch.Tensor) -> None:
+        p = self.problems[g]
+        src = src.to(device=self.device, dtype=self.tdtype).contiguous()
+        if tuple(src.shape) != (9, p.ny, p.nx):
+            raise ValueError("adjoint state must have shape (9, ny, nx)")
+        self._keep = src
+        L.lbm_adjoint_set_state(self.ctx, g, src.data_ptr())
+
+    def misfit(self, g: int, d_obs: torch.Tensor, nrows: Optional[int] = None):
+        """(misfit, residual) of grid g's first nrows trace rows against d_obs:
+        residual = traces - d_obs, misfit = 1/2 sum residual^2 (FP64)."""
+        tr = self.traces[g]
+        n = tr.shape[0] if nrows is None else int(nrows)
+        d = d_obs.to(device=self.device, dtype=self.tdtype).contiguous()
+        if d.shape[1:] != tr.shape[1:] or d.shape[0] < n:
+            raise ValueError("d_obs must have the traces' layout")
+        res = torch.zeros_like(tr)
+        mis = torch.zeros(1, dtype=torch.float64, device=self.device)
+        L.lbm_misfit(self.ctx, g, d.data_ptr(), res.data_ptr(), n, mis.data_ptr())
+        return mis, res
+
+    def lame_gradient(self, g: int, grad_kappa: torch.Tensor, grad_lam: torch.Tensor,
+                      grad_mu: torch.Tensor) -> None:
+        """Add grid g's dL/dlambda, dL/dmu (from dL/dkappa) into the buffers."""
+        o0, o1 = int(self.cell_off[g]), int(self.cell_off[g + 1])
+        for t in (grad_kappa, grad_lam, grad_mu):
+            if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != o1 - o0:
+                raise ValueError("gradient buffers must be contiguous FP64 (ny, nx) tensors")
+        L.lbm_lame_gradient(self.ctx, g, self.lam[o0:o1].data_ptr(), self.mu[o0:o1].data_ptr(),
+                            grad_kappa.data_ptr(), grad_lam.data_ptr(), grad_mu.data_ptr())
 
     def close(self) -> None:
         if getattr(self, "ctx", None):

@@ -94,6 +94,18 @@ def test_null_context_calls_fail_cleanly():
     assert lib.lbm_moments(None, 0, None) == L.LBM_E_INVALID
     assert lib.lbm_destroy(None) == L.LBM_OK
     assert "null" in L.last_error() or L.last_error() == ""
+    sz = C.c_size_t(0)
+    t = C.c_int64(0)
+    assert lib.lbm_adjoint_workspace_bytes(None, 10, 100, C.byref(sz)) == L.LBM_E_INVALID
+    assert lib.lbm_adjoint_begin(None, 10, 100, None, 0) == L.LBM_E_INVALID
+    assert lib.lbm_adjoint_set_io(None, 0, None, None, None) == L.LBM_E_INVALID
+    assert lib.lbm_adjoint_step(None, 1) == L.LBM_E_INVALID
+    assert lib.lbm_adjoint_time(None, C.byref(t)) == L.LBM_E_INVALID
+    assert lib.lbm_adjoint_get_state(None, 0, None) == L.LBM_E_INVALID
+    assert lib.lbm_adjoint_set_state(None, 0, None) == L.LBM_E_INVALID
+    assert lib.lbm_misfit(None, 0, None, None, 0, None) == L.LBM_E_INVALID
+    assert lib.lbm_lame_gradient(None, 0, None, None, None, None, None) == L.LBM_E_INVALID
+    assert lib.lbm_step_timed(None, 1, None) == L.LBM_E_INVALID
 
 
 def test_binding_fails_loudly_without_library(monkeypatch):
