@@ -83,6 +83,114 @@ def cpu_baseline(problem, target_s: float = 15.0):
                       f"state, FP64, OpenMP over rows ({el:.1f} s incl. setup)"}
 
 
+def _timed_steps(s, steps: int, warmup: int, torch) -> float:
+    """ms per step over `steps` steps after `warmup`, HIP events on the stream."""
+    s.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    s.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def bench_hbm_scale(torch, w, Solver, steps: int = 200, warmup: int = 20) -> dict:
+    """16384^2 FP32, 8 layers, rigid interface, 3 sources (the HBM-scale
+    configuration), timed over a window of its 4000 steps."""
+    p = w.hbm_scale()
+    s = Solver(p, dtype="f32", trace_steps=1)
+    ms = _timed_steps(s, steps, warmup, torch)
+    kt = s.step_timed(20)
+    ok = s.check_finite()
+    launch = s.launch()
+    s.close()
+    cells = p.nx * p.ny
+    return {"workload": f"hbm_scale {p.nx}x{p.ny} FP32, 8 layers, rigid interface at row "
+                        f"{p.rigid_row}, 3 sources", "GLUPS": round(cells / ms / 1e6, 3),
+            "ms_per_step": round(ms, 4), "steps": steps, "warmup": warmup,
+            "interior_GBps": round(72 * kt["interior_cells"] / kt["interior_ms"] / 1e6, 1),
+            "launch": launch, "state_finite": bool(ok)}
+
+
+def bench_batched(torch, w, Solver, plain_glups: float, steps: int = 60,
+                  warmup: int = 10) -> dict:
+    """512 grids of uneven side (256..2048) in one context, one launch per
+    step over the flat tile list, HIP graphs of 10 steps."""
+    probs = w.batched_shots()
+    t0 = time.perf_counter()
+    s = Solver(probs, dtype="f32", trace_steps=1, launch={"waves": 4, "rows": 4,
+                                                          "graph_chunk": 10})
+    setup = time.perf_counter() - t0
+    ms = _timed_steps(s, steps, warmup, torch)
+    ok = s.check_finite()
+    launch = s.launch()
+    s.close()
+    cells = sum(p.nx * p.ny for p in probs)
+    g = cells / ms / 1e6
+    return {"workload": f"batched_shots: {len(probs)} grids, sides 256..2048, {cells} cells, FP32",
+            "GLUPS": round(g, 3), "ms_per_step": round(ms, 4), "steps": steps,
+            "warmup": warmup, "vs_plain": round(g / plain_glups, 4), "setup_s": round(setup, 1),
+            "launch": launch, "state_finite": bool(ok)}
+
+
+def bench_adjoint(torch, w, Solver, plain_glups: float, nsteps: int = 5000,
+                  seg: int = 100) -> dict:
+    """16 shots of 1024^2 FP32 through the perturbed medium, 5000 steps,
+    checkpoints every 100: the full gradient (recorded forward, misfit,
+    adjoint with recompute, Lame gradients) timed end to end, against the
+    observed data of the homogeneous background (computed beforehand)."""
+    shots = w.adjoint_shots(nsteps=nsteps)
+    bg = w.adjoint_shots(nsteps=nsteps, homogeneous=True)
+    sb = Solver(bg, dtype="f32", trace_steps=nsteps)
+    sb.step(nsteps)
+    d_obs = [t.clone() for t in sb.traces]
+    sb.close()
+    del sb
+    s = Solver(shots, dtype="f32", trace_steps=nsteps)
+    n = shots[0].nx
+    G = len(shots)
+    gk = torch.zeros((G, n, n), dtype=torch.float64, device="cuda")
+    ga = torch.zeros((G, 1), dtype=torch.float64, device="cuda")
+    gl = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    gm = torch.zeros_like(gl)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e2 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    s.adjoint_begin(nsteps, seg)
+    s.step(nsteps)
+    e1.record()
+    mis = []
+    res = []
+    for g in range(G):
+        m, r = s.misfit(g, d_obs[g])
+        mis.append(m)
+        res.append(r)
+        s.adjoint_set_io(g, r, gk[g], ga[g])
+    s.adjoint_step(nsteps)
+    for g in range(G):
+        s.lame_gradient(g, gk[g], gl, gm)
+    e2.record()
+    torch.cuda.synchronize()
+    t_fwd = e0.elapsed_time(e1)
+    t_all = e0.elapsed_time(e2)
+    ok = bool(torch.isfinite(gl).all().item() and torch.isfinite(gm).all().item())
+    misfit = float(sum(m.item() for m in mis))
+    s.close()
+    cells = G * n * n
+    g_rate = cells * nsteps / (t_all / 1e3) / 1e9
+    return {"workload": f"adjoint_shots: {G} shots of {n}x{n} FP32, {nsteps} steps, "
+                        f"checkpoints every {seg}", "gradient_GLUPS": round(g_rate, 3),
+            "ms_total": round(t_all, 1), "ms_forward_recorded": round(t_fwd, 1),
+            "vs_plain": round(g_rate / plain_glups, 4), "misfit": misfit,
+            "gradients_finite": ok,
+            "note": "gradient_GLUPS = cell-steps of the forward per second of forward + "
+                    "misfit + adjoint (with recompute) + Lame gradients"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,6 +205,8 @@ def main():
     ap.add_argument("--graph-chunk", type=int, default=100)
     ap.add_argument("--timed-launches", type=int, default=200,
                     help="steps of the per-kernel event-timing pass after the timed region")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the HBM-scale, batched and adjoint measurements")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 9 x n^2 floats (counter calibration)")
     args = ap.parse_args()
@@ -192,6 +302,15 @@ def main():
                                         "ms_per_launch": round(kt["general_ms"], 5)},
                      "whole_step_GBps": round(step_gbs, 1)},
     }
+    if not args.no_extras and args.n == 4096 and args.dtype == "f32":
+        extras = {}
+        for name, fn in (("hbm_scale", lambda: bench_hbm_scale(torch, w, Solver)),
+                         ("batched", lambda: bench_batched(torch, w, Solver, glups)),
+                         ("adjoint", lambda: bench_adjoint(torch, w, Solver, glups))):
+            print(f"[bench] {name} ...", file=sys.stderr, flush=True)
+            extras[name] = fn()
+            torch.cuda.empty_cache()
+        out["extras"] = extras
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)

@@ -935,8 +935,8 @@ int lbm_set_sources(lbm_ctx *c, int32_t g, const lbm_source *src, int32_t n) {
       return fail(LBM_E_INVALID, "source needs sigma > 0, period > 0 and finite values");
   }
   c->sources[g].assign(src, src + n);
-  c->tables_dirty = true;
-  return commit(c);
+  c->tables_dirty = true;   // committed by the next call that launches work
+  return LBM_OK;
 }
 
 int lbm_set_receivers(lbm_ctx *c, int32_t g, const int32_t *xy, int32_t n, int32_t comp_mask,
@@ -962,8 +962,8 @@ int lbm_set_receivers(lbm_ctx *c, int32_t g, const int32_t *xy, int32_t n, int32
     if (rc) return rc;
   }
   c->recs[g] = R;
-  c->tables_dirty = true;
-  return commit(c);
+  c->tables_dirty = true;   // committed by the next call that launches work
+  return LBM_OK;
 }
 
 int lbm_step(lbm_ctx *c, int64_t n) {
