@@ -356,6 +356,137 @@ __global__ __launch_bounds__(64 * NW) void adjoint_kernel(AdjArgs<real> a) {
   if (lane < nsrc && samp[lane] != 0.0) atomicAdd(io.grad_amp + lane, samp[lane]);
 }
 
+// Transposed pull of an interior row (no wall, no wrap in y): ah_k(x) =
+// fh_k(x + c_k) through the tile's buffer descriptor based at row ybase.
+template <typename real>
+__device__ __forceinline__ void adj_pull_fast(__amdgpu_buffer_rsrc_t rsrc, int ybase, int y,
+                                              uint32_t rowb, uint32_t qb, uint32_t o0, uint32_t ol,
+                                              uint32_t orr, real out[9]) {
+  const uint32_t rc = (uint32_t)(y - ybase) * rowb, ru = rc - rowb, rd = rc + rowb;
+  out[0] = Buf<real>::load(rsrc, o0, rc);            // ( 0, 0)
+  out[1] = Buf<real>::load(rsrc, orr, rc + qb);      // ( 1, 0) from (x+1, y)
+  out[2] = Buf<real>::load(rsrc, o0, rd + 2 * qb);   // ( 0, 1) from (x, y+1)
+  out[3] = Buf<real>::load(rsrc, ol, rc + 3 * qb);   // (-1, 0) from (x-1, y)
+  out[4] = Buf<real>::load(rsrc, o0, ru + 4 * qb);   // ( 0,-1) from (x, y-1)
+  out[5] = Buf<real>::load(rsrc, orr, rd + 5 * qb);  // ( 1, 1) from (x+1, y+1)
+  out[6] = Buf<real>::load(rsrc, ol, rd + 6 * qb);   // (-1, 1) from (x-1, y+1)
+  out[7] = Buf<real>::load(rsrc, ol, ru + 7 * qb);   // (-1,-1) from (x-1, y-1)
+  out[8] = Buf<real>::load(rsrc, orr, ru + 8 * qb);  // ( 1,-1) from (x+1, y-1)
+}
+
+// The adjoint step for interior tiles: every row the tile touches (one above
+// and one below its own) is clear of walls and of the y-wrap, its columns
+// (with the halo) have both x-neighbours inside the grid or wrap
+// periodically, and no source band and no receiver reaches those rows. The
+// per-cell arithmetic is the general kernel's.
+template <typename real, int NW>
+__global__ __launch_bounds__(64 * NW) void adjoint_interior_kernel(AdjArgs<real> a) {
+  constexpr int W = 64 * NW;
+  __shared__ real sq[2][W + 2];
+
+  const TileDev tile = a.tiles[blockIdx.x];
+  if (tile.g < 0) return;
+  const GridDev &g = a.grids[tile.g];
+  double *__restrict__ gk = a.io[tile.g].grad_kappa;
+  const int pitch = g.pitch, nx = g.nx;
+
+  const int lane = threadIdx.x;
+  const int x = tile.x0 + lane;
+  const bool active = x < nx;
+  const int xa = active ? x : nx - 1;
+  const int x_last = min(tile.x0 + W, nx) - 1;
+  const uint32_t esz = sizeof(real);
+  auto wrapx = [&](int c) { return c < 0 ? c + nx : (c >= nx ? c - nx : c); };
+  const int xl = wrapx(xa - 1), xr = wrapx(xa + 1);
+  const uint32_t o0 = (uint32_t)xa * esz, ol = (uint32_t)xl * esz, orr = (uint32_t)xr * esz;
+  const int hx = lane == 0 ? wrapx(tile.x0 - 1) : wrapx(x_last + 1);
+  const uint32_t ho0 = (uint32_t)hx * esz;
+  const uint32_t hol = (uint32_t)wrapx(hx - 1) * esz;
+  const uint32_t hor = (uint32_t)wrapx(hx + 1) * esz;
+  const int hslot = lane == 0 ? 0 : W + 1;
+
+  const real omega = a.omega, cforce = a.cforce;
+  const int y0 = tile.y0, y1 = tile.y1;
+  const int ybase = y0 - 2;
+  const uint32_t qb = (uint32_t)pitch * esz;
+  const uint32_t rowb = 9 * qb;
+  const __amdgpu_buffer_rsrc_t rin = tile_rsrc(a.fin + g.f_off + (int64_t)ybase * 9 * pitch);
+  const __amdgpu_buffer_rsrc_t rout = tile_rsrc(a.fout + g.f_off + (int64_t)ybase * 9 * pitch);
+  const __amdgpu_buffer_rsrc_t rrho = tile_rsrc(a.rho + g.c_off + (int64_t)ybase * pitch);
+
+  real A_x, inv_x, hA_x, hinv_x;
+  sponge_x(a.sponge, g, xa, A_x, inv_x);
+  sponge_x(a.sponge, g, hx, hA_x, hinv_x);
+
+  // Steps 1-2 for the lane's column (or the halo column) of row y.
+  auto cell = [&](int y, bool halo, real as[9], real &Gx, real &Gy, real &mx, real &my) {
+    if (halo) adj_pull_fast(rin, ybase, y, rowb, qb, ho0, hol, hor, as);
+    else adj_pull_fast(rin, ybase, y, rowb, qb, o0, ol, orr, as);
+    real A = halo ? hA_x : A_x, inv = halo ? hinv_x : inv_x;
+    sponge_y(a.sponge, g, y, A, inv);
+    adj_local(as, real(0), real(0), A, inv, omega, cforce, Gx, Gy, mx, my);
+  };
+
+  real as_c[9], gx_c, gy_c, mx_c, my_c;
+  real qy_m;
+  {
+    real t_[9], gx_, gy_, mx_, my_;
+    cell(y0 - 1, false, t_, gx_, gy_, mx_, my_);
+    qy_m = cell_kappa(a.kappa_rows, a.kappa_cells, g, y0 - 1, xa) * gy_;
+  }
+  cell(y0, false, as_c, gx_c, gy_c, mx_c, my_c);
+  real kap_c = cell_kappa(a.kappa_rows, a.kappa_cells, g, y0, xa);
+  sq[0][lane + 1] = kap_c * gx_c;
+  if (lane < 2) {
+    real t_[9], gx_, gy_, mx_, my_;
+    cell(y0, true, t_, gx_, gy_, mx_, my_);
+    sq[0][hslot] = cell_kappa(a.kappa_rows, a.kappa_cells, g, y0, hx) * gx_;
+  }
+  __syncthreads();
+
+  for (int y = y0, k = 0; y < y1; ++y, ++k) {
+    real as_n[9], gx_n, gy_n, mx_n, my_n;
+    cell(y + 1, false, as_n, gx_n, gy_n, mx_n, my_n);
+    const real kap_n = cell_kappa(a.kappa_rows, a.kappa_cells, g, y + 1, xa);
+    real hq_n = real(0);
+    if (lane < 2) {
+      real t_[9], gx_, gy_, mx_, my_;
+      cell(y + 1, true, t_, gx_, gy_, mx_, my_);
+      hq_n = cell_kappa(a.kappa_rows, a.kappa_cells, g, y + 1, hx) * gx_;
+    }
+    const int s = k & 1;
+    const real qx_l = sq[s][lane];
+    const real qx_r = (xa == x_last) ? sq[s][W + 1] : sq[s][lane + 2];
+    sq[s ^ 1][lane + 1] = kap_n * gx_n;
+    if (lane < 2) sq[s ^ 1][hslot] = hq_n;
+
+    // Step 3 (centred differences only) and step 4.
+    const real rD = real(0.5) * ((qx_l - qx_r) + (qy_m - kap_n * gy_n));
+    if (active) {
+      real fh[9];
+      adj_finish(as_c, omega, rD, mx_c, my_c, real(0), fh);
+      const uint32_t rs = (uint32_t)(y - ybase) * rowb;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Buf<real>::store_nt(fh[i], rout, o0, rs + i * qb);
+      // Step 5: dL/dkappa += Gh . grad(rho)(t).
+      const uint32_t pr = (uint32_t)(y - ybase) * qb;
+      const real dx = real(0.5) * (Buf<real>::load(rrho, orr, pr) - Buf<real>::load(rrho, ol, pr));
+      const real dy = real(0.5) * (Buf<real>::load(rrho, o0, pr + qb) - Buf<real>::load(rrho, o0, pr - qb));
+      if (gk) gk[(int64_t)y * nx + x] += (double)gx_c * (double)dx + (double)gy_c * (double)dy;
+    }
+
+    __syncthreads();
+    qy_m = kap_c * gy_c;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) as_c[i] = as_n[i];
+    gx_c = gx_n;
+    gy_c = gy_n;
+    mx_c = mx_n;
+    my_c = my_n;
+    kap_c = kap_n;
+  }
+}
+
 // Residual e = v - d of one grid's traces and the misfit L += 1/2 sum e^2,
 // accumulated in FP64: wavefront shuffles, then one atomic add per wavefront.
 template <typename real>
@@ -412,6 +543,18 @@ hipError_t launch_adjoint(const AdjArgs<real> &a, int waves, int ntiles, hipStre
 }
 
 template <typename real>
+hipError_t launch_adjoint_interior(const AdjArgs<real> &a, int waves, int ntiles, hipStream_t stream) {
+  if (ntiles <= 0) return hipSuccess;
+  dim3 grid(ntiles), block(64 * waves);
+  if (waves == 1) hipLaunchKernelGGL((adjoint_interior_kernel<real, 1>), grid, block, 0, stream, a);
+  else if (waves == 2) hipLaunchKernelGGL((adjoint_interior_kernel<real, 2>), grid, block, 0, stream, a);
+  else if (waves == 4) hipLaunchKernelGGL((adjoint_interior_kernel<real, 4>), grid, block, 0, stream, a);
+  else if (waves == 8) hipLaunchKernelGGL((adjoint_interior_kernel<real, 8>), grid, block, 0, stream, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <typename real>
 hipError_t launch_misfit(const real *trace, const real *d_obs, real *residual, int64_t n,
                          double *misfit, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
@@ -431,6 +574,8 @@ hipError_t launch_lame_gradient(const real *lam, const real *mu, const double *g
 
 #define LBM_INST(real)                                                                        \
   template hipError_t launch_adjoint<real>(const AdjArgs<real> &, int, int, hipStream_t);     \
+  template hipError_t launch_adjoint_interior<real>(const AdjArgs<real> &, int, int,          \
+                                                    hipStream_t);                             \
   template hipError_t launch_misfit<real>(const real *, const real *, real *, int64_t, double *, \
                                           hipStream_t);                                       \
   template hipError_t launch_lame_gradient<real>(const real *, const real *, const double *,  \

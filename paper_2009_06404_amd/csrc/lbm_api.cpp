@@ -144,6 +144,12 @@ struct lbm_ctx {
   lbm_launch launch{4, 8, 0, 1, 1, 0};
   int ntiles = 0, ntiles_int = 0;
   int64_t cells_int = 0, cells_gen = 0;          // cells each kernel's tile list covers
+  std::vector<TileDev> h_tiles_int, h_tiles_gen; // host copies of the two lists
+  // adjoint tile lists: interior tiles with no receiver in rows y0-1 .. y1,
+  // and the rest (rebuilt after every retiling)
+  DevBuf<TileDev> d_adj_int, d_adj_gen;
+  int n_adj_int = 0, n_adj_gen = 0;
+  bool adj_tiles_ok = false;
   // graph of graph_chunk steps for each starting buffer parity
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   int gchunk = 0;
@@ -442,11 +448,15 @@ int rebuild_tiles(lbm_ctx *c) {
   auto cover = [&](const std::vector<TileDev> &v) {
     int64_t n = 0;
     for (const auto &t : v)
-      n += (int64_t)std::min(W, c->grids[t.g].nx - t.x0) * (t.y1 - t.y0);
+      if (t.g >= 0)   // skip the padding entries of the die ordering
+        n += (int64_t)std::min(W, c->grids[t.g].nx - t.x0) * (t.y1 - t.y0);
     return n;
   };
   c->cells_int = cover(ti);
   c->cells_gen = cover(tg);
+  c->h_tiles_int = ti;
+  c->h_tiles_gen = tg;
+  c->adj_tiles_ok = false;
   HIP_TRY(c->d_tiles_int.upload(ti, c->stream));
   HIP_TRY(c->d_tiles.upload(tg, c->stream));
   drop_graphs(c);
@@ -774,9 +784,42 @@ int recompute_segment(lbm_ctx *c, int64_t m) {
   return LBM_OK;
 }
 
+// The adjoint's tile lists: the forward's interior tiles whose rows y0-1 and
+// y1 also hold no receiver, and every other tile. Built from the real tiles
+// of the two (die-ordered, padded) forward lists in their logical order
+// (grid, row, column) and die-ordered again.
+int build_adjoint_tiles(lbm_ctx *c) {
+  std::vector<TileDev> li, lg;
+  for (const TileDev &t : c->h_tiles_gen)
+    if (t.g >= 0) lg.push_back(t);
+  for (const TileDev &t : c->h_tiles_int) {
+    if (t.g < 0) continue;
+    bool rec = false;
+    const std::vector<int32_t> &xy = c->recs[t.g].xy;
+    for (size_t r = 1; r < xy.size() && !rec; r += 2) rec = xy[r] == t.y0 - 1 || xy[r] == t.y1;
+    (rec ? lg : li).push_back(t);
+  }
+  auto logical = [](const TileDev &a, const TileDev &b) {
+    return a.g != b.g ? a.g < b.g : (a.y0 != b.y0 ? a.y0 < b.y0 : a.x0 < b.x0);
+  };
+  std::sort(li.begin(), li.end(), logical);
+  std::sort(lg.begin(), lg.end(), logical);
+  const std::vector<TileDev> ai = order_for_dies(li), ag = order_for_dies(lg);
+  c->n_adj_int = (int)ai.size();
+  c->n_adj_gen = (int)ag.size();
+  HIP_TRY(c->d_adj_int.upload(ai, c->stream));
+  HIP_TRY(c->d_adj_gen.upload(ag, c->stream));
+  c->adj_tiles_ok = true;
+  return LBM_OK;
+}
+
 template <typename real>
 int adjoint_impl(lbm_ctx *c, int64_t n) {
   auto &A = c->adj;
+  if (!c->adj_tiles_ok) {
+    int rc = build_adjoint_tiles(c);
+    if (rc) return rc;
+  }
   if (A.io_dirty) {
     HIP_TRY(c->d_adj_io.upload(A.io, c->stream));
     A.io_dirty = false;
@@ -805,10 +848,10 @@ int adjoint_impl(lbm_ctx *c, int64_t n) {
     a.t = t;
     a.omega = (real)(1.0 / c->tau);
     a.cforce = (real)(1.0 - 0.5 / c->tau);
-    a.tiles = c->d_tiles.p;
-    HIP_TRY(launch_adjoint<real>(a, c->launch.waves, c->ntiles, c->stream));
-    a.tiles = c->d_tiles_int.p;
-    HIP_TRY(launch_adjoint<real>(a, c->launch.waves, c->ntiles_int, c->stream));
+    a.tiles = c->d_adj_int.p;
+    HIP_TRY(launch_adjoint_interior<real>(a, c->launch.waves, c->n_adj_int, c->stream));
+    a.tiles = c->d_adj_gen.p;
+    HIP_TRY(launch_adjoint<real>(a, c->launch.waves, c->n_adj_gen, c->stream));
     A.cur ^= 1;
     A.t_adj = t;
   }
@@ -1339,6 +1382,8 @@ int lbm_destroy(lbm_ctx *c) {
   if (!c) return LBM_OK;
   drop_graphs(c);
   c->d_adj_io.release();
+  c->d_adj_int.release();
+  c->d_adj_gen.release();
   c->d_grids.release();
   c->d_tiles.release();
   c->d_tiles_int.release();

@@ -105,6 +105,10 @@ struct AdjArgs {
 
 template <typename real>
 hipError_t launch_adjoint(const AdjArgs<real> &a, int waves, int ntiles, hipStream_t stream);
+// Interior tiles whose rows y0-1 .. y1 also hold no receiver.
+template <typename real>
+hipError_t launch_adjoint_interior(const AdjArgs<real> &a, int waves, int ntiles,
+                                   hipStream_t stream);
 template <typename real>
 hipError_t launch_misfit(const real *trace, const real *d_obs, real *residual, int64_t n,
                          double *misfit, hipStream_t stream);

@@ -1,0 +1,111 @@
+"""Drive the library's host code, built against the stub HIP runtime in this
+folder, through the same C-ABI call sequences as the GPU tests: forward
+stepping with launch changes, moments, state copies, and adjoint runs with
+checkpoints, uneven segments and batched grids. Run as a script by
+tests/test_host_code_cpu.py with the built library's path."""
+import ctypes as C
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+sys.path.insert(0, os.path.dirname(HERE))
+
+import paper_2009_06404_amd._lib as L  # noqa: E402
+
+L.LIB_PATH = sys.argv[1]
+L._lib = None
+lib = L.lib()
+sim = C.CDLL(sys.argv[1])
+sim.sim_register.argtypes = [C.c_void_p, C.c_size_t]
+
+from workloads import BC_FREE, BC_FREE0, BC_PERIODIC, BC_RIGID, Medium, Problem, Source  # noqa: E402
+from workloads.problem import default_sponge_profile  # noqa: E402
+
+keep = []
+
+
+def dev(a):
+    a = np.ascontiguousarray(a)
+    keep.append(a)
+    sim.sim_register(a.ctypes.data, a.nbytes)
+    return a
+
+
+def problem(bc, rr, nx, ny, seed, sources=None, receivers=None):
+    rng = np.random.default_rng(seed)
+    mu = rng.uniform(0.036, 0.044, (ny, nx))
+    nu = rng.uniform(0.15, 0.3, (ny, nx))
+    lam = 2 * nu * mu / (1 - 2 * nu)
+    prof = default_sponge_profile(6)
+    thick = (0, 6, 6, 0)
+    src = sources or [Source(nx * 0.3, ny * 0.4, 2.0, 0.0, 1.0, 1.0, 12.0, 16.0)]
+    rec = receivers or ([(x, 0) for x in range(0, nx, 3)] + [(x, ny // 2) for x in range(1, nx, 7)])
+    return Problem(nx=nx, ny=ny, bc=bc, medium=Medium("field", lam, mu, np.ones((ny, nx))),
+                   tau=0.9, rigid_row=rr, sponge_thick=thick,
+                   sponge_profiles=tuple(prof if t else None for t in thick), sources=src,
+                   receivers=np.asarray(rec, np.int32), comp_mask=3)
+
+
+def run(probs, T, seg, dtype, launch=None, chunks=None):
+    code, npdt = (L.LBM_F32, np.float32) if dtype == "f32" else (L.LBM_F64, np.float64)
+    grids = [(p.nx, p.ny) for p in probs]
+    fields = [np.concatenate([p.medium.full(p.ny, p.nx)[k].ravel() for p in probs]).astype(npdt)
+              for k in range(3)]
+    lam, mu, rho = (dev(f) for f in fields)
+    nb = L.lbm_workspace_bytes(grids, code)
+    ws = dev(np.zeros(nb + 512, np.uint8))
+    wp = (ws.ctypes.data + 255) // 256 * 256
+    bcs = [(p.bc[0], p.bc[1], p.bc[2], p.bc[3], p.rigid_row) for p in probs]
+    sps = [(tuple(p.sponge_thick), tuple(p.profile(e) for e in range(4))) for p in probs]
+    ctx = L.lbm_init(grids, code, lam.ctypes.data, mu.ctypes.data, rho.ctypes.data, probs[0].tau,
+                     bcs, sps, wp, nb, 0)
+    for g, p in enumerate(probs):
+        L.lbm_set_sources(ctx, g, [s.as_tuple() for s in p.sources])
+        tr = dev(np.zeros((T, p.nrec, p.ncomp), npdt))
+        L.lbm_set_receivers(ctx, g, np.asarray(p.receivers, np.int32), p.comp_mask, tr.ctypes.data, T)
+    if launch:
+        lc = L.lbm_get_launch(ctx)
+        lc.update(launch)
+        L.lbm_set_launch(ctx, lc["waves"], lc["rows"], lc["graph_chunk"], lc["prefetch"],
+                         lc["split"], lc["pair"])
+    ab = L.lbm_adjoint_workspace_bytes(ctx, seg, T)
+    aws = dev(np.zeros(ab + 512, np.uint8))
+    L.lbm_adjoint_begin(ctx, seg, T, (aws.ctypes.data + 255) // 256 * 256, ab)
+    L.lbm_step(ctx, T)
+    for g, p in enumerate(probs):
+        res = dev(np.ones((T, p.nrec, p.ncomp), npdt))
+        gk = dev(np.zeros((p.ny, p.nx)))
+        ga = dev(np.zeros(max(len(p.sources), 1)))
+        L.lbm_adjoint_set_io(ctx, g, res.ctypes.data, gk.ctypes.data, ga.ctypes.data)
+    for n in (chunks or [T]):
+        L.lbm_adjoint_step(ctx, n)
+    for g, p in enumerate(probs):
+        out = dev(np.zeros((9, p.ny, p.nx), npdt))
+        L.lbm_adjoint_get_state(ctx, g, out.ctypes.data)
+        mom = dev(np.zeros((6, p.ny, p.nx), npdt))
+        L.lbm_moments(ctx, g, mom.ctypes.data)
+        L.lbm_get_state(ctx, g, out.ctypes.data)
+    L.lbm_destroy(ctx)
+
+
+CASES = [
+    ("periodic", (BC_PERIODIC,) * 4, -1),
+    ("free_rigid_interface", (BC_FREE, BC_RIGID, BC_PERIODIC, BC_PERIODIC), 17),
+    ("free0_rigid_sides", (BC_FREE0, BC_FREE0, BC_RIGID, BC_RIGID), -1),
+    ("rigid_box_interface", (BC_RIGID,) * 4, 9),
+]
+for dtype in ("f64", "f32"):
+    for name, bc, rr in CASES:
+        run([problem(bc, rr, 70, 40, 1)], 24, 7, dtype)
+        big = problem(bc, -1 if rr < 0 else 90, 300, 200, 2,
+                      sources=[Source(40.0, 30.0, 2.0, 0.3, 0.9, 1.0, 12.0, 16.0)],
+                      receivers=[(x, 0) for x in range(0, 300, 5)] + [(x, 101) for x in range(3, 300, 11)])
+        for launch in (dict(waves=1, rows=4), dict(waves=2, rows=8), dict(waves=8, rows=2)):
+            run([big], 20, 8, dtype, launch=launch)
+        print("ok", name, dtype, flush=True)
+    run([problem(CASES[1][1], 20, 150, 37, 3), problem(CASES[3][1], -1, 64, 65, 4)], 18, 5, dtype,
+        launch=dict(waves=2, rows=4), chunks=[7, 11])
+print("ALL OK", flush=True)

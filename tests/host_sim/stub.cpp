@@ -1,0 +1,185 @@
+// CPU stand-in for the HIP runtime and the kernel launchers of liblbm.so, for
+// testing the library's host code without a GPU: "device" memory is host
+// memory (allocations are recorded), copies and fills are performed, graph and
+// event calls are inert, and every kernel launch checks that each tile and
+// each address range its kernel would touch lies inside a recorded
+// allocation (it aborts otherwise). The initialisation kernels are evaluated
+// on the host so the host code takes the same branches as on the device.
+#include <hip/hip_runtime.h>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <cmath>
+#include "lbm_internal.h"
+
+static std::map<uintptr_t, size_t> g_alloc;   // base -> bytes
+extern "C" void sim_register(void *p, size_t n) { g_alloc[(uintptr_t)p] = n; }
+extern "C" void sim_unregister(void *p) { g_alloc.erase((uintptr_t)p); }
+static void check_range(const void *p, size_t n, const char *what) {
+  uintptr_t a = (uintptr_t)p;
+  auto it = g_alloc.upper_bound(a);
+  if (it == g_alloc.begin()) { fprintf(stderr, "OOB %s: %p not in any allocation\n", what, p); abort(); }
+  --it;
+  if (a + n > it->first + it->second) {
+    fprintf(stderr, "OOB %s: [%p, +%zu) exceeds allocation [%p, +%zu)\n", what, p, n, (void *)it->first, it->second);
+    abort();
+  }
+}
+
+hipError_t hipMalloc(void **p, size_t n) { *p = malloc(n ? n : 1); g_alloc[(uintptr_t)*p] = n ? n : 1; return hipSuccess; }
+hipError_t hipFree(void *p) { if (p) { g_alloc.erase((uintptr_t)p); free(p); } return hipSuccess; }
+hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, hipMemcpyKind k, hipStream_t) {
+  if (k != hipMemcpyHostToDevice) check_range(s, n, "memcpy src");
+  if (k != hipMemcpyDeviceToHost) check_range(d, n, "memcpy dst");
+  memmove(d, s, n);
+  return hipSuccess;
+}
+hipError_t hipMemsetAsync(void *d, int v, size_t n, hipStream_t) { check_range(d, n, "memset"); memset(d, v, n); return hipSuccess; }
+hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+const char *hipGetErrorString(hipError_t) { return "sim error"; }
+hipError_t hipGetLastError() { return hipSuccess; }
+hipError_t hipEventCreate(hipEvent_t *e) { *e = (hipEvent_t)malloc(8); return hipSuccess; }
+hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
+hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
+hipError_t hipEventElapsedTime(float *ms, hipEvent_t, hipEvent_t) { *ms = 1.0f; return hipSuccess; }
+hipError_t hipEventDestroy(hipEvent_t e) { free(e); return hipSuccess; }
+hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned) { *s = (hipStream_t)malloc(8); return hipSuccess; }
+hipError_t hipStreamDestroy(hipStream_t s) { free(s); return hipSuccess; }
+hipError_t hipStreamBeginCapture(hipStream_t, hipStreamCaptureMode) { return hipSuccess; }
+hipError_t hipStreamEndCapture(hipStream_t, hipGraph_t *g) { *g = (hipGraph_t)malloc(8); return hipSuccess; }
+hipError_t hipGraphInstantiate(hipGraphExec_t *e, hipGraph_t, hipGraphNode_t *, char *, size_t) { *e = (hipGraphExec_t)malloc(8); return hipSuccess; }
+hipError_t hipGraphDestroy(hipGraph_t g) { free(g); return hipSuccess; }
+hipError_t hipGraphExecDestroy(hipGraphExec_t e) { free(e); return hipSuccess; }
+hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) { return hipSuccess; }
+
+namespace lbm {
+template <typename real>
+static void check_tiles(const TileDev *tiles, int ntiles, const GridDev *grids, int W, bool interior,
+                        const char *what) {
+  check_range(tiles, sizeof(TileDev) * ntiles, what);
+  for (int i = 0; i < ntiles; ++i) {
+    const TileDev t = tiles[i];
+    if (t.g < 0) continue;   // padding entries: the kernels return at once
+    check_range(&grids[t.g], sizeof(GridDev), "grid desc");
+    const GridDev &g = grids[t.g];
+    if (t.x0 < 0 || t.x0 >= g.nx || t.y0 < 0 || t.y1 > g.ny || t.y0 >= t.y1) { fprintf(stderr, "bad tile %s\n", what); abort(); }
+    if (interior && (t.y0 - 2 < 0 || t.y1 + 1 > g.ny - 1)) { fprintf(stderr, "interior tile rows out of range %s y0=%d y1=%d ny=%d\n", what, t.y0, t.y1, g.ny); abort(); }
+    (void)W;
+  }
+}
+template <typename real>
+static void check_pop(const real *base, const GridDev &g, const char *what) {
+  check_range(base + g.f_off, sizeof(real) * 9 * (size_t)g.pitch * g.ny, what);
+}
+template <typename real>
+hipError_t launch_step(const StepArgs<real> &a, int waves, int, int ntiles, int mode, hipStream_t) {
+  if (ntiles <= 0) return hipSuccess;
+  check_tiles<real>(a.tiles, ntiles, a.grids, 64 * waves, false, "step tiles");
+  for (int i = 0; i < ntiles; ++i) {
+    if (a.tiles[i].g < 0) continue;
+    const GridDev &g = a.grids[a.tiles[i].g];
+    check_pop(a.fin, g, "step fin");
+    if (mode != kModeMoments) check_pop(a.fout, g, "step fout");
+    if (mode == kModeStash) check_range(a.rho_out + g.c_off, sizeof(real) * (size_t)g.pitch * g.ny, "stash out");
+  }
+  return hipSuccess;
+}
+template <typename real>
+hipError_t launch_interior(const StepArgs<real> &a, int waves, int, int ntiles, hipStream_t) {
+  if (ntiles <= 0) return hipSuccess;
+  check_tiles<real>(a.tiles, ntiles, a.grids, 64 * waves, true, "interior tiles");
+  for (int i = 0; i < ntiles; ++i) {
+    if (a.tiles[i].g < 0) continue;
+    const GridDev &g = a.grids[a.tiles[i].g];
+    check_pop(a.fin, g, "int fin");
+    check_pop(a.fout, g, "int fout");
+    if (a.rho_out) check_range(a.rho_out + g.c_off, sizeof(real) * (size_t)g.pitch * g.ny, "int stash out");
+  }
+  return hipSuccess;
+}
+template <typename real>
+static hipError_t adj_common(const AdjArgs<real> &a, int waves, int ntiles, bool interior) {
+  if (ntiles <= 0) return hipSuccess;
+  check_tiles<real>(a.tiles, ntiles, a.grids, 64 * waves, interior, interior ? "adj int tiles" : "adj gen tiles");
+  for (int i = 0; i < ntiles; ++i) {
+    const TileDev t = a.tiles[i];
+    if (t.g < 0) continue;
+    const GridDev &g = a.grids[t.g];
+    check_range(&a.io[t.g], sizeof(AdjGridDev), "adj io");
+    const AdjGridDev io = a.io[t.g];
+    check_pop(a.fin, g, "adj fin");
+    check_pop(a.fout, g, "adj fout");
+    check_range(a.rho + g.c_off, sizeof(real) * (size_t)g.pitch * g.ny, "adj rho");
+    if (io.grad_kappa) check_range(io.grad_kappa, sizeof(double) * (size_t)g.nx * g.ny, "grad_kappa");
+    if (io.grad_amp && g.nsrc) check_range(io.grad_amp, sizeof(double) * (g.nsrc < kMaxAdjSources ? g.nsrc : kMaxAdjSources), "grad_amp");
+    if (io.residual && g.nrec) check_range(io.residual, sizeof(real) * (size_t)g.trace_max * g.nrec * g.ncomp, "residual");
+  }
+  return hipSuccess;
+}
+template <typename real>
+hipError_t launch_adjoint(const AdjArgs<real> &a, int waves, int ntiles, hipStream_t) { return adj_common(a, waves, ntiles, false); }
+template <typename real>
+hipError_t launch_adjoint_interior(const AdjArgs<real> &a, int waves, int ntiles, hipStream_t) { return adj_common(a, waves, ntiles, true); }
+template <typename real>
+hipError_t launch_misfit(const real *tr, const real *d, real *r, int64_t n, double *m, hipStream_t) {
+  check_range(tr, n * sizeof(real), "misfit tr"); check_range(d, n * sizeof(real), "misfit d");
+  if (r) check_range(r, n * sizeof(real), "misfit r");
+  check_range(m, 8, "misfit m"); return hipSuccess;
+}
+template <typename real>
+hipError_t launch_lame_gradient(const real *l, const real *m, const double *gk, double *gl, double *gm, int64_t n, hipStream_t) {
+  check_range(l, n * sizeof(real), "lame l"); check_range(m, n * sizeof(real), "lame m"); check_range(gk, n * 8, "lame gk");
+  if (gl) check_range(gl, n * 8, "lame gl"); if (gm) check_range(gm, n * 8, "lame gm"); return hipSuccess;
+}
+template <typename real>
+hipError_t launch_kappa(const real *lam, const real *mu, const real *rho, int nx, int ny, int pitch, real *kappa, int *bad, int *row_varies, hipStream_t) {
+  const int64_t n = (int64_t)nx * ny;
+  check_range(lam, n * sizeof(real), "kappa lam"); check_range(mu, n * sizeof(real), "kappa mu"); check_range(rho, n * sizeof(real), "kappa rho");
+  check_range(kappa, (size_t)pitch * ny * sizeof(real), "kappa out"); check_range(bad, 4, "bad"); check_range(row_varies, 4 * ny, "rows");
+  for (int64_t k = 0; k < n; ++k) {
+    const int y = k / nx, x = k % nx;
+    double l = lam[k], m = mu[k], r = rho[k];
+    bool ok = m > 0 && r > 0 && l >= 0 && l / (2 * (l + m)) < 5.0 / 11.0;
+    if (!ok) bad[0]++;
+    kappa[(int64_t)y * pitch + x] = ok ? (real)((1.0 / 3.0) * (m - l) / m) : real(0);
+    if (x > 0 && (lam[(int64_t)y * nx] != lam[k] || mu[(int64_t)y * nx] != mu[k])) row_varies[y] = 1;
+  }
+  return hipSuccess;
+}
+template <typename real>
+hipError_t launch_kappa_rows(const real *kappa, int ny, int pitch, real *rows, hipStream_t) {
+  check_range(rows, ny * sizeof(real), "krows"); for (int y = 0; y < ny; ++y) rows[y] = kappa[(int64_t)y * pitch]; return hipSuccess;
+}
+template <typename real>
+hipError_t launch_gather(const real *src, const int64_t *idx, int n, real *dst, hipStream_t) {
+  for (int i = 0; i < n; ++i) { check_range(src + idx[i], sizeof(real), "gather"); dst[i] = src[idx[i]]; } return hipSuccess;
+}
+template <typename real>
+hipError_t launch_count_nonfinite(const real *f, int64_t n, int *count, hipStream_t) { check_range(f, n * sizeof(real), "nonfinite"); return hipSuccess; }
+template <typename real>
+hipError_t launch_copy_planes(const real *src, int64_t sps, int64_t sys, real *dst, int64_t dps, int64_t dys, int nx, int ny, int np, hipStream_t) {
+  for (int p = 0; p < np; ++p) for (int y = 0; y < ny; ++y) {
+    check_range(src + p * sps + y * sys, nx * sizeof(real), "copy src"); check_range(dst + p * dps + y * dys, nx * sizeof(real), "copy dst");
+    memcpy(dst + p * dps + y * dys, src + p * sps + y * sys, nx * sizeof(real));
+  }
+  return hipSuccess;
+}
+hipError_t launch_set_time(int64_t *t, int64_t v, hipStream_t) { check_range(t, 8, "time"); *t = v; return hipSuccess; }
+hipError_t launch_add_time(int64_t *t, int64_t v, hipStream_t) { check_range(t, 8, "time"); *t += v; return hipSuccess; }
+
+#define INST(real) \
+  template hipError_t launch_step<real>(const StepArgs<real> &, int, int, int, int, hipStream_t); \
+  template hipError_t launch_interior<real>(const StepArgs<real> &, int, int, int, hipStream_t); \
+  template hipError_t launch_adjoint<real>(const AdjArgs<real> &, int, int, hipStream_t); \
+  template hipError_t launch_adjoint_interior<real>(const AdjArgs<real> &, int, int, hipStream_t); \
+  template hipError_t launch_misfit<real>(const real *, const real *, real *, int64_t, double *, hipStream_t); \
+  template hipError_t launch_lame_gradient<real>(const real *, const real *, const double *, double *, double *, int64_t, hipStream_t); \
+  template hipError_t launch_kappa<real>(const real *, const real *, const real *, int, int, int, real *, int *, int *, hipStream_t); \
+  template hipError_t launch_kappa_rows<real>(const real *, int, int, real *, hipStream_t); \
+  template hipError_t launch_gather<real>(const real *, const int64_t *, int, real *, hipStream_t); \
+  template hipError_t launch_count_nonfinite<real>(const real *, int64_t, int *, hipStream_t); \
+  template hipError_t launch_copy_planes<real>(const real *, int64_t, int64_t, real *, int64_t, int64_t, int, int, int, hipStream_t);
+INST(float)
+INST(double)
+}  // namespace lbm

@@ -99,6 +99,26 @@ def test_adjoint_matches_oracle(name, bc, rr, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("bc", [(BC_FREE0, BC_RIGID, BC_PERIODIC, BC_PERIODIC),
+                                (BC_PERIODIC,) * 4, (BC_FREE, BC_FREE, BC_RIGID, BC_RIGID)],
+                         ids=["free0_rigid_periodic_x", "periodic", "free_rigid_sides"])
+def test_adjoint_interior_tiles_match_oracle(bc, dtype):
+    """A grid large enough for interior tiles of the adjoint (source band in a
+    corner, a receiver row through the middle that sends the tiles beside it
+    to the general kernel)."""
+    p = _problem(bc, -1, nx=300, ny=200, seed=11)
+    p = p.replace(sources=[Source(40.0, 30.0, 2.0, 0.3, 0.9, 1.0, 12.0, 16.0)],
+                  receivers=np.asarray([(x, 0) for x in range(0, 300, 5)] +
+                                       [(x, 101) for x in range(3, 300, 11)], np.int32))
+    T, seg = 40, 16
+    res = np.random.default_rng(4).standard_normal((T, p.nrec, p.ncomp))
+    ref = stepper.adjoint(p, nsteps=T, residual=res)
+    for launch in (dict(waves=1, rows=4), dict(waves=2, rows=8)):
+        g = _gpu_adjoint([p], T, seg, dtype, [res], launch=launch)[0]
+        _compare(g, ref, TOL[dtype], f"interior tiles {bc} {launch} {dtype}")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_adjoint_chunks_and_segments_are_neutral(dtype):
     """Stepping the adjoint back in uneven pieces, and any checkpoint
     spacing, gives bitwise the same state and dL/dkappa; dL/damp is summed
