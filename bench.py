@@ -207,6 +207,9 @@ def main():
                     help="steps of the per-kernel event-timing pass after the timed region")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the HBM-scale, batched and adjoint measurements")
+    ap.add_argument("--only", choices=["hbm_scale", "batched", "adjoint"],
+                    help="run only this one of the extra measurements and print it")
+    ap.add_argument("--adjoint-steps", type=int, default=5000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 9 x n^2 floats (counter calibration)")
     args = ap.parse_args()
@@ -242,6 +245,13 @@ def main():
         print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4,
                           "launches": 25, "ms_per_copy": round(ms, 5),
                           "copy_GBps": round(2 * src.numel() * 4 / (ms / 1e3) / 1e9, 1)}), flush=True)
+        return
+    if args.only:
+        fn = {"hbm_scale": lambda: bench_hbm_scale(torch, w, Solver),
+              "batched": lambda: bench_batched(torch, w, Solver, float("nan")),
+              "adjoint": lambda: bench_adjoint(torch, w, Solver, float("nan"),
+                                               nsteps=args.adjoint_steps)}[args.only]
+        print(json.dumps({args.only: fn()}), flush=True)
         return
     p = w.plain_large(n=args.n, dtype=args.dtype)
     total = args.warmup + args.steps
