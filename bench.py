@@ -45,9 +45,10 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(cells=None):
     """Bytes per launch from the committed rocprofv3 counter summary, or None
-    when the kernel source has changed since the counters were taken."""
+    when the kernel source has changed since the counters were taken or the
+    launch covers another number of cells."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -59,6 +60,8 @@ def measured_traffic():
                 vals[k.strip()] = v.strip()
     if vals.get("kernel_hash") != kernel_hash():
         return None
+    if cells is not None and vals.get("cells_per_launch") != str(cells):
+        return None                      # counters taken for another launch shape
     try:
         return float(vals["bytes_per_launch"])
     except (KeyError, ValueError):
@@ -291,8 +294,8 @@ def main():
     alg_bytes = per_cell * kcells                  # per launch of the dominant kernel
     achieved = alg_bytes / (kms / 1e3) / 1e9       # GB/s
     step_gbs = per_cell * cells / (ms_step / 1e3) / 1e9
-    traffic = (measured_traffic() if (args.n == 4096 and args.dtype == "f32"
-                                      and kname == DOMINANT_KERNEL) else None)
+    traffic = (measured_traffic(kcells) if (args.n == 4096 and args.dtype == "f32"
+                                            and kname == DOMINANT_KERNEL) else None)
     out = {
         "metric": METRIC, "value": round(glups, 3), "unit": "GLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),

@@ -113,6 +113,10 @@ typedef struct {
                          lean interior kernel (default); 0: one kernel for all */
   int32_t pair;       /* 1: the interior kernel handles two columns per lane
                          (used when every grid's nx is even and waves >= 2) */
+  int32_t overlap;    /* 1: the general kernel runs on a second stream of the
+                         library, concurrently with the interior kernel, joined
+                         back to the context's stream at the end of the step
+                         (default); 0: one kernel after the other */
 } lbm_launch;
 
 /* Bytes of device workspace lbm_init needs for nbatch grids of the given
@@ -191,7 +195,8 @@ int lbm_set_state(lbm_ctx *ctx, int32_t g, const void *src, int64_t t);
 int lbm_check_finite(lbm_ctx *ctx);
 
 /* Launch configuration in use, and a way to set it (waves in {1,2,4,8},
- * rows >= 1, graph_chunk >= 0, prefetch in {1,2}; 0 means 1). An odd
+ * rows >= 1, graph_chunk >= 0, prefetch in {1,2} (0 means 1), split, pair and
+ * overlap in {0,1}). An odd
  * graph_chunk is rounded up to keep the ping-pong parity. */
 int lbm_get_launch(const lbm_ctx *ctx, lbm_launch *out);
 int lbm_set_launch(lbm_ctx *ctx, const lbm_launch *cfg);

@@ -57,7 +57,8 @@ class lbm_source(C.Structure):
 
 class lbm_launch(C.Structure):
     _fields_ = [("waves", C.c_int32), ("rows", C.c_int32), ("graph_chunk", C.c_int32),
-                ("prefetch", C.c_int32), ("split", C.c_int32), ("pair", C.c_int32)]
+                ("prefetch", C.c_int32), ("split", C.c_int32), ("pair", C.c_int32),
+                ("overlap", C.c_int32)]
 
 
 class lbm_kernel_times(C.Structure):
@@ -229,12 +230,12 @@ def lbm_get_launch(ctx):
     o = lbm_launch()
     check(lib().lbm_get_launch(ctx, C.byref(o)))
     return dict(waves=o.waves, rows=o.rows, graph_chunk=o.graph_chunk, prefetch=o.prefetch,
-                split=o.split, pair=o.pair)
+                split=o.split, pair=o.pair, overlap=o.overlap)
 
 
 def lbm_set_launch(ctx, waves: int, rows: int, graph_chunk: int = 0, prefetch: int = 1,
-                   split: int = 1, pair: int = 0) -> None:
-    o = lbm_launch(waves, rows, graph_chunk, prefetch, split, pair)
+                   split: int = 1, pair: int = 0, overlap: int = 1) -> None:
+    o = lbm_launch(waves, rows, graph_chunk, prefetch, split, pair, overlap)
     check(lib().lbm_set_launch(ctx, C.byref(o)))
 
 
@@ -242,7 +243,7 @@ def lbm_autotune(ctx, steps: int = 5):
     o = lbm_launch()
     check(lib().lbm_autotune(ctx, int(steps), C.byref(o)))
     return dict(waves=o.waves, rows=o.rows, graph_chunk=o.graph_chunk, prefetch=o.prefetch,
-                split=o.split, pair=o.pair)
+                split=o.split, pair=o.pair, overlap=o.overlap)
 
 
 def lbm_destroy(ctx) -> None:

@@ -141,8 +141,12 @@ struct lbm_ctx {
   std::vector<int64_t> rscale_off;               // per grid offset into d_rtab
   std::vector<char> rtab_host;
   bool tables_dirty = true;
-  lbm_launch launch{4, 8, 0, 1, 1, 0};
+  lbm_launch launch{4, 8, 0, 1, 1, 0, 1};
+  // second stream and fork/join events for the overlapped general kernel
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   int ntiles = 0, ntiles_int = 0;
+  int gen_waves = 1;                             // tile width (x64) of the general list
   int64_t cells_int = 0, cells_gen = 0;          // cells each kernel's tile list covers
   std::vector<TileDev> h_tiles_int, h_tiles_gen; // host copies of the two lists
   // adjoint tile lists: interior tiles with no receiver in rows y0-1 .. y1,
@@ -254,6 +258,18 @@ double min_image_host(double d, int n, bool periodic) {
   return d;
 }
 
+// Distance from p to the nearest of the integer points lo..hi of an axis of
+// n points, with the minimum image on a periodic axis.
+double dist_to_range(double p, int lo, int hi, int n, bool periodic) {
+  double best = 1e300;
+  for (int k = periodic ? -1 : 0; k <= (periodic ? 1 : 0); ++k) {
+    const double q = p + (double)k * n;
+    const double d = q < lo ? lo - q : (q > hi ? q - hi : 0.0);
+    best = std::min(best, d);
+  }
+  return best;
+}
+
 // Whether a tile can run in the interior kernel: every row it pulls (one
 // above, its own, one below) has no horizontal wall link and no wrap, every
 // column it touches (with the halo columns) has both x-neighbours inside the
@@ -269,12 +285,13 @@ bool tile_is_interior(const lbm_ctx *c, int g, int x0, int y0, int y1, int W) {
   const bool py = b.edge[LBM_EDGE_TOP] == LBM_PERIODIC;
   const int x_last = std::min(x0 + W, nx) - 1;
   if (!px && (x0 - 2 < 0 || x_last + 2 > nx - 1)) return false;
+  // the body force is zero on every cell of the tile: no cell within 9 sigma
+  // of a source (minimum image on periodic axes)
   for (const lbm_source &q : c->sources[g]) {
     const double cut = 81.0 * q.sigma * q.sigma;
-    for (int y = y0; y < y1; ++y) {
-      const double dy = min_image_host((double)y - q.y, ny, py);
-      if (dy * dy <= cut) return false;
-    }
+    const double dx = dist_to_range(q.x, x0, x_last, nx, px);
+    const double dy = dist_to_range(q.y, y0, y1 - 1, ny, py);
+    if (dx * dx + dy * dy <= cut) return false;
   }
   const std::vector<int32_t> &xy = c->recs[g].xy;
   for (size_t r = 1; r < xy.size(); r += 2)
@@ -284,6 +301,12 @@ bool tile_is_interior(const lbm_ctx *c, int g, int x0, int y0, int y1, int W) {
 
 // Tiles: columns [x0, x0 + 64*waves), rows [y0, y1), sorted into the interior
 // list (when split) and the general list.
+// A tile that is not interior as a whole is split into sub-tiles of at most
+// kSubRows rows, each classified again: tall tiles serve the open interior
+// (fewer halo rows per row) while the rows near walls, sources and receivers
+// go to the general kernel in thin tiles.
+constexpr int kSubRows = 2;
+
 void build_tiles(const lbm_ctx *c, int waves, int rows, bool split, std::vector<TileDev> &interior,
                  std::vector<TileDev> &general) {
   std::vector<TileDev> li, lg;
@@ -293,22 +316,37 @@ void build_tiles(const lbm_ctx *c, int waves, int rows, bool split, std::vector<
     for (int y0 = 0; y0 < ny; y0 += rows)
       for (int x0 = 0; x0 < nx; x0 += W) {
         const TileDev t{g, x0, y0, std::min(y0 + rows, ny)};
-        if (split && tile_is_interior(c, g, x0, t.y0, t.y1, W)) li.push_back(t);
-        else lg.push_back(t);
+        if (!split) {
+          lg.push_back(t);
+        } else if (tile_is_interior(c, g, x0, t.y0, t.y1, W)) {
+          li.push_back(t);
+        } else {
+          for (int ys = t.y0; ys < t.y1; ys += kSubRows) {
+            const TileDev u{g, x0, ys, std::min(ys + kSubRows, t.y1)};
+            if (tile_is_interior(c, g, x0, u.y0, u.y1, W)) {
+              li.push_back(u);
+            } else {
+              // general tiles are one wavefront wide: the few rows they cover
+              // then spread over many short workgroups
+              for (int xs = x0; xs < std::min(x0 + W, nx); xs += 64) lg.push_back(TileDev{g, xs, u.y0, u.y1});
+            }
+          }
+        }
       }
   }
   interior = order_for_dies(li);
   general = order_for_dies(lg);
 }
 
-// Default launch shape: 512-column tiles of 2 rows on large grids (many short
-// tiles keep the set of rows in flight compact, and wide tiles re-read fewer
-// halo columns); narrower tiles where the grid would otherwise give too few
-// workgroups to fill 256 compute units.
+// Default launch shape (measured on MI355X): on large grids 512-column
+// interior tiles of 8 rows in FP32 and 4 rows in FP64 (taller tiles re-read
+// fewer halo rows, shorter ones keep the rows in flight compact); narrower
+// tiles where the grid would otherwise give too few workgroups to fill 256
+// compute units.
 lbm_launch default_launch(const lbm_ctx *c) {
   int64_t cells = 0;
   for (const auto &g : c->grids) cells += (int64_t)g.nx * g.ny;
-  lbm_launch l{8, 2, 0, 1, 1, 0};
+  lbm_launch l{8, c->dtype == LBM_F64 ? 4 : 8, 0, 1, 1, 0, 1};
   if (cells < 2048 * 2048) {
     l.waves = 4;
     l.rows = 4;
@@ -444,16 +482,16 @@ int rebuild_tiles(lbm_ctx *c) {
   build_tiles(c, c->launch.waves, c->launch.rows, c->launch.split != 0, ti, tg);
   c->ntiles_int = (int)ti.size();
   c->ntiles = (int)tg.size();
-  const int W = 64 * c->launch.waves;
-  auto cover = [&](const std::vector<TileDev> &v) {
+  c->gen_waves = c->launch.split ? 1 : c->launch.waves;
+  auto cover = [&](const std::vector<TileDev> &v, int W) {
     int64_t n = 0;
     for (const auto &t : v)
       if (t.g >= 0)   // skip the padding entries of the die ordering
         n += (int64_t)std::min(W, c->grids[t.g].nx - t.x0) * (t.y1 - t.y0);
     return n;
   };
-  c->cells_int = cover(ti);
-  c->cells_gen = cover(tg);
+  c->cells_int = cover(ti, 64 * c->launch.waves);
+  c->cells_gen = cover(tg, 64 * c->gen_waves);
   c->h_tiles_int = ti;
   c->h_tiles_gen = tg;
   c->adj_tiles_ok = false;
@@ -474,17 +512,41 @@ int use_pair(const lbm_ctx *c) {
 
 // One step: the interior tiles and the general tiles (any order: both read
 // the state of step t-1 and write disjoint cells of step t).
+hipError_t ensure_side_stream(lbm_ctx *c) {
+  if (c->side) return hipSuccess;
+  hipError_t e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+  return e;
+}
+
+// One step: the interior kernel over its tiles and the general kernel over the
+// rest. The two write disjoint tiles of the output buffer and only read the
+// input buffer, so with overlap on the general kernel runs on the library's
+// second stream, forked from and joined back to s (under graph capture the
+// fork and join become graph edges).
 template <typename real>
 hipError_t launch_one_step(lbm_ctx *c, StepArgs<real> a, hipStream_t s) {
   hipError_t e = hipSuccess;
+  StepArgs<real> ai = a;
+  ai.tiles = c->d_tiles_int.p;
+  a.tiles = c->d_tiles.p;
+  if (c->launch.overlap && c->ntiles_int > 0 && c->ntiles > 0) {
+    e = ensure_side_stream(c);
+    if (e == hipSuccess) e = hipEventRecord(c->ev_fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->side, c->ev_fork, 0);
+    if (e == hipSuccess)
+      e = launch_step<real>(a, c->gen_waves, c->launch.prefetch, c->ntiles, kModeStep, c->side);
+    if (e == hipSuccess) e = hipEventRecord(c->ev_join, c->side);
+    if (e == hipSuccess) e = launch_interior<real>(ai, c->launch.waves, use_pair(c), c->ntiles_int, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, c->ev_join, 0);
+    return e;
+  }
   if (c->ntiles_int > 0) {
-    StepArgs<real> ai = a;
-    ai.tiles = c->d_tiles_int.p;
     e = launch_interior<real>(ai, c->launch.waves, use_pair(c), c->ntiles_int, s);
     if (e != hipSuccess) return e;
   }
-  a.tiles = c->d_tiles.p;
-  return launch_step<real>(a, c->launch.waves, c->launch.prefetch, c->ntiles, kModeStep, s);
+  return launch_step<real>(a, c->gen_waves, c->launch.prefetch, c->ntiles, kModeStep, s);
 }
 
 template <typename real>
@@ -541,7 +603,7 @@ int step_timed(lbm_ctx *c, int64_t n, lbm_kernel_times *out) {
     a.tiles = c->d_tiles.p;
     if (e == hipSuccess) e = hipEventRecord(ev[2], c->stream);
     if (e == hipSuccess)
-      e = launch_step<real>(a, c->launch.waves, c->launch.prefetch, c->ntiles, kModeStep, c->stream);
+      e = launch_step<real>(a, c->gen_waves, c->launch.prefetch, c->ntiles, kModeStep, c->stream);
     if (e == hipSuccess) e = hipEventRecord(ev[3], c->stream);
     if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
     float ms = 0.f;
@@ -778,7 +840,7 @@ int recompute_segment(lbm_ctx *c, int64_t m) {
       ai.tiles = c->d_tiles_int.p;
       HIP_TRY(launch_interior<real>(ai, c->launch.waves, 0, c->ntiles_int, c->stream));
     }
-    HIP_TRY(launch_step<real>(a, c->launch.waves, 1, c->ntiles, kModeStash, c->stream));
+    HIP_TRY(launch_step<real>(a, c->gen_waves, 1, c->ntiles, kModeStash, c->stream));
   }
   A.stash_seg = m;
   return LBM_OK;
@@ -797,7 +859,13 @@ int build_adjoint_tiles(lbm_ctx *c) {
     bool rec = false;
     const std::vector<int32_t> &xy = c->recs[t.g].xy;
     for (size_t r = 1; r < xy.size() && !rec; r += 2) rec = xy[r] == t.y0 - 1 || xy[r] == t.y1;
-    (rec ? lg : li).push_back(t);
+    if (!rec) {
+      li.push_back(t);
+    } else {
+      const int Wg = 64 * c->gen_waves, W = 64 * c->launch.waves;
+      for (int xs = t.x0; xs < std::min(t.x0 + W, c->grids[t.g].nx); xs += Wg)
+        lg.push_back(TileDev{t.g, xs, t.y0, t.y1});
+    }
   }
   auto logical = [](const TileDev &a, const TileDev &b) {
     return a.g != b.g ? a.g < b.g : (a.y0 != b.y0 ? a.y0 < b.y0 : a.x0 < b.x0);
@@ -851,7 +919,7 @@ int adjoint_impl(lbm_ctx *c, int64_t n) {
     a.tiles = c->d_adj_int.p;
     HIP_TRY(launch_adjoint_interior<real>(a, c->launch.waves, c->n_adj_int, c->stream));
     a.tiles = c->d_adj_gen.p;
-    HIP_TRY(launch_adjoint<real>(a, c->launch.waves, c->n_adj_gen, c->stream));
+    HIP_TRY(launch_adjoint<real>(a, c->gen_waves, c->n_adj_gen, c->stream));
     A.cur ^= 1;
     A.t_adj = t;
   }
@@ -1047,7 +1115,7 @@ int lbm_moments(lbm_ctx *c, int32_t g, void *out6) {
     a.fout = nullptr;
     a.mom = reinterpret_cast<double *>(out6);
     a.mom_grid = g;
-    HIP_TRY(launch_step<double>(a, c->launch.waves, 1, c->ntiles, kModeMoments, c->stream));
+    HIP_TRY(launch_step<double>(a, c->gen_waves, 1, c->ntiles, kModeMoments, c->stream));
     a.tiles = c->d_tiles_int.p;
     HIP_TRY(launch_step<double>(a, c->launch.waves, 1, c->ntiles_int, kModeMoments, c->stream));
   } else {
@@ -1055,7 +1123,7 @@ int lbm_moments(lbm_ctx *c, int32_t g, void *out6) {
     a.fout = nullptr;
     a.mom = reinterpret_cast<float *>(out6);
     a.mom_grid = g;
-    HIP_TRY(launch_step<float>(a, c->launch.waves, 1, c->ntiles, kModeMoments, c->stream));
+    HIP_TRY(launch_step<float>(a, c->gen_waves, 1, c->ntiles, kModeMoments, c->stream));
     a.tiles = c->d_tiles_int.p;
     HIP_TRY(launch_step<float>(a, c->launch.waves, 1, c->ntiles_int, kModeMoments, c->stream));
   }
@@ -1156,7 +1224,11 @@ int lbm_set_launch(lbm_ctx *c, const lbm_launch *cfg) {
   if (cfg->prefetch < 0 || cfg->prefetch > 2) return fail(LBM_E_INVALID, "prefetch must be 1 or 2");
   const bool retile = cfg->waves != c->launch.waves || cfg->rows != c->launch.rows ||
                       cfg->split != c->launch.split;
-  const bool regraph = retile || cfg->prefetch != c->launch.prefetch || cfg->pair != c->launch.pair;
+  if (cfg->split < 0 || cfg->split > 1 || cfg->pair < 0 || cfg->pair > 1 || cfg->overlap < 0 ||
+      cfg->overlap > 1)
+    return fail(LBM_E_INVALID, "split, pair and overlap must be 0 or 1");
+  const bool regraph = retile || cfg->prefetch != c->launch.prefetch || cfg->pair != c->launch.pair ||
+                       cfg->overlap != c->launch.overlap;
   c->launch = *cfg;
   if (c->launch.prefetch == 0) c->launch.prefetch = 1;
   if (regraph) drop_graphs(c);
@@ -1195,7 +1267,7 @@ int lbm_autotune(lbm_ctx *c, int32_t steps, lbm_launch *chosen) {
   for (int pf = 1; pf <= 2; ++pf)
   for (int wi = 0; wi < 4 && e == hipSuccess && rc == LBM_OK; ++wi)
     for (int ri = 0; ri < 6 && e == hipSuccess && rc == LBM_OK; ++ri) {
-      lbm_launch cand{waves_c[wi], rows_c[ri], 0, pf, keep.split, pair};
+      lbm_launch cand{waves_c[wi], rows_c[ri], 0, pf, keep.split, pair, keep.overlap};
       if (pair && cand.waves == 1) continue;
       const int64_t tiles = cells / ((int64_t)64 * cand.waves * cand.rows);
       if (tiles < 512 && !(cand.waves == 1 && cand.rows == 4)) continue;
@@ -1381,6 +1453,12 @@ int lbm_lame_gradient(lbm_ctx *c, int32_t g, const void *lam, const void *mu, co
 int lbm_destroy(lbm_ctx *c) {
   if (!c) return LBM_OK;
   drop_graphs(c);
+  if (c->side) {
+    hipStreamSynchronize(c->side);
+    hipStreamDestroy(c->side);
+  }
+  if (c->ev_fork) hipEventDestroy(c->ev_fork);
+  if (c->ev_join) hipEventDestroy(c->ev_join);
   c->d_adj_io.release();
   c->d_adj_int.release();
   c->d_adj_gen.release();

@@ -139,7 +139,11 @@ def test_interior_kernel_split_is_bitwise_neutral(dtype):
     a = run_gpu(p, 150, dtype, launch=dict(waves=1, rows=8, split=1))
     b = run_gpu(p, 150, dtype, launch=dict(waves=1, rows=8, split=0))
     c = run_gpu(p, 150, dtype, launch=dict(waves=2, rows=4, split=1, pair=1))
-    for other in (b, c):
+    # the general kernel on the second stream, with direct launches and inside
+    # captured graphs (fork and join as graph edges), and without the overlap
+    d = run_gpu(p, 150, dtype, launch=dict(waves=1, rows=8, split=1, overlap=0))
+    e = run_gpu(p, 150, dtype, launch=dict(waves=1, rows=8, split=1, overlap=1, graph_chunk=10))
+    for other in (b, c, d, e):
         assert np.array_equal(a["fstar"], other["fstar"])
         assert np.array_equal(a["trace"], other["trace"])
     compare(a, _oracle(p, 150), TOL[dtype], f"split {dtype}")
