@@ -117,14 +117,17 @@ def bench_hbm_scale(torch, w, Solver, steps: int = 200, warmup: int = 20) -> dic
             "launch": launch, "state_finite": bool(ok)}
 
 
+BATCHED_LAUNCH = {"waves": 8, "rows": 8, "graph_chunk": 10}
+ADJOINT_LAUNCH = {"waves": 4, "rows": 4}      # 1024-column grids: narrower, shorter tiles
+
+
 def bench_batched(torch, w, Solver, plain_glups: float, steps: int = 60,
-                  warmup: int = 10) -> dict:
+                  warmup: int = 10, launch=None) -> dict:
     """512 grids of uneven side (256..2048) in one context, one launch per
     step over the flat tile list, HIP graphs of 10 steps."""
     probs = w.batched_shots()
     t0 = time.perf_counter()
-    s = Solver(probs, dtype="f32", trace_steps=1, launch={"waves": 4, "rows": 4,
-                                                          "graph_chunk": 10})
+    s = Solver(probs, dtype="f32", trace_steps=1, launch=dict(launch or BATCHED_LAUNCH))
     setup = time.perf_counter() - t0
     ms = _timed_steps(s, steps, warmup, torch)
     ok = s.check_finite()
@@ -139,7 +142,7 @@ def bench_batched(torch, w, Solver, plain_glups: float, steps: int = 60,
 
 
 def bench_adjoint(torch, w, Solver, plain_glups: float, nsteps: int = 5000,
-                  seg: int = 100) -> dict:
+                  seg: int = 100, launch=None) -> dict:
     """16 shots of 1024^2 FP32 through the perturbed medium, 5000 steps,
     checkpoints every 100: the full gradient (recorded forward, misfit,
     adjoint with recompute, Lame gradients) timed end to end, against the
@@ -151,7 +154,7 @@ def bench_adjoint(torch, w, Solver, plain_glups: float, nsteps: int = 5000,
     d_obs = [t.clone() for t in sb.traces]
     sb.close()
     del sb
-    s = Solver(shots, dtype="f32", trace_steps=nsteps)
+    s = Solver(shots, dtype="f32", trace_steps=nsteps, launch=dict(launch or ADJOINT_LAUNCH))
     n = shots[0].nx
     G = len(shots)
     gk = torch.zeros((G, n, n), dtype=torch.float64, device="cuda")

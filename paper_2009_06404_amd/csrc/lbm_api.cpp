@@ -520,33 +520,43 @@ hipError_t ensure_side_stream(lbm_ctx *c) {
   return e;
 }
 
-// One step: the interior kernel over its tiles and the general kernel over the
-// rest. The two write disjoint tiles of the output buffer and only read the
-// input buffer, so with overlap on the general kernel runs on the library's
-// second stream, forked from and joined back to s (under graph capture the
-// fork and join become graph edges).
-template <typename real>
-hipError_t launch_one_step(lbm_ctx *c, StepArgs<real> a, hipStream_t s) {
+// The interior kernel and the general kernel of one step (forward, recompute
+// or adjoint) write disjoint tiles of their output and only read their input,
+// so with overlap on the general one runs on the library's second stream,
+// forked from and joined back to s (under graph capture the fork and join
+// become graph edges); otherwise the interior kernel runs first.
+template <typename Gen, typename Int>
+hipError_t launch_pair(lbm_ctx *c, hipStream_t s, bool has_int, bool has_gen, Gen general,
+                       Int interior) {
   hipError_t e = hipSuccess;
-  StepArgs<real> ai = a;
-  ai.tiles = c->d_tiles_int.p;
-  a.tiles = c->d_tiles.p;
-  if (c->launch.overlap && c->ntiles_int > 0 && c->ntiles > 0) {
+  if (c->launch.overlap && has_int && has_gen) {
     e = ensure_side_stream(c);
     if (e == hipSuccess) e = hipEventRecord(c->ev_fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(c->side, c->ev_fork, 0);
-    if (e == hipSuccess)
-      e = launch_step<real>(a, c->gen_waves, c->launch.prefetch, c->ntiles, kModeStep, c->side);
+    if (e == hipSuccess) e = general(c->side);
     if (e == hipSuccess) e = hipEventRecord(c->ev_join, c->side);
-    if (e == hipSuccess) e = launch_interior<real>(ai, c->launch.waves, use_pair(c), c->ntiles_int, s);
+    if (e == hipSuccess) e = interior(s);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, c->ev_join, 0);
     return e;
   }
-  if (c->ntiles_int > 0) {
-    e = launch_interior<real>(ai, c->launch.waves, use_pair(c), c->ntiles_int, s);
-    if (e != hipSuccess) return e;
-  }
-  return launch_step<real>(a, c->gen_waves, c->launch.prefetch, c->ntiles, kModeStep, s);
+  if (has_int) e = interior(s);
+  if (e == hipSuccess && has_gen) e = general(s);
+  return e;
+}
+
+template <typename real>
+hipError_t launch_one_step(lbm_ctx *c, StepArgs<real> a, hipStream_t s) {
+  StepArgs<real> ai = a;
+  ai.tiles = c->d_tiles_int.p;
+  a.tiles = c->d_tiles.p;
+  return launch_pair(
+      c, s, c->ntiles_int > 0, c->ntiles > 0,
+      [&](hipStream_t q) {
+        return launch_step<real>(a, c->gen_waves, c->launch.prefetch, c->ntiles, kModeStep, q);
+      },
+      [&](hipStream_t q) {
+        return launch_interior<real>(ai, c->launch.waves, use_pair(c), c->ntiles_int, q);
+      });
 }
 
 template <typename real>
@@ -835,12 +845,12 @@ int recompute_segment(lbm_ctx *c, int64_t m) {
     a.fout = reinterpret_cast<real *>(A.rbuf[(s & 1) ^ 1]);
     a.t = tm + s;
     a.rho_out = reinterpret_cast<real *>(A.stash + (size_t)s * A.cbytes);
-    if (c->ntiles_int > 0) {
-      StepArgs<real> ai = a;
-      ai.tiles = c->d_tiles_int.p;
-      HIP_TRY(launch_interior<real>(ai, c->launch.waves, 0, c->ntiles_int, c->stream));
-    }
-    HIP_TRY(launch_step<real>(a, c->gen_waves, 1, c->ntiles, kModeStash, c->stream));
+    StepArgs<real> ai = a;
+    ai.tiles = c->d_tiles_int.p;
+    HIP_TRY(launch_pair(
+        c, c->stream, c->ntiles_int > 0, c->ntiles > 0,
+        [&](hipStream_t q) { return launch_step<real>(a, c->gen_waves, 1, c->ntiles, kModeStash, q); },
+        [&](hipStream_t q) { return launch_interior<real>(ai, c->launch.waves, 0, c->ntiles_int, q); }));
   }
   A.stash_seg = m;
   return LBM_OK;
@@ -916,10 +926,13 @@ int adjoint_impl(lbm_ctx *c, int64_t n) {
     a.t = t;
     a.omega = (real)(1.0 / c->tau);
     a.cforce = (real)(1.0 - 0.5 / c->tau);
+    AdjArgs<real> ag = a;
     a.tiles = c->d_adj_int.p;
-    HIP_TRY(launch_adjoint_interior<real>(a, c->launch.waves, c->n_adj_int, c->stream));
-    a.tiles = c->d_adj_gen.p;
-    HIP_TRY(launch_adjoint<real>(a, c->gen_waves, c->n_adj_gen, c->stream));
+    ag.tiles = c->d_adj_gen.p;
+    HIP_TRY(launch_pair(
+        c, c->stream, c->n_adj_int > 0, c->n_adj_gen > 0,
+        [&](hipStream_t q) { return launch_adjoint<real>(ag, c->gen_waves, c->n_adj_gen, q); },
+        [&](hipStream_t q) { return launch_adjoint_interior<real>(a, c->launch.waves, c->n_adj_int, q); }));
     A.cur ^= 1;
     A.t_adj = t;
   }
