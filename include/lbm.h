@@ -117,10 +117,21 @@ typedef struct {
                          library, concurrently with the interior kernel, joined
                          back to the context's stream at the end of the step
                          (default); 0: one kernel after the other */
+  int32_t fuse_rows;  /* 0: one kernel pass per step (default). 4..248: steps run
+                         in pairs; blocks of 256 columns by fuse_rows rows that
+                         hold no boundary, receiver or source take two steps in
+                         one pass (the intermediate state stays on chip, apart
+                         from the block's border, kept in a third buffer for the
+                         neighbouring blocks); the other cells take the two steps
+                         one at a time. Results are bitwise those of single
+                         steps. graph_chunk is rounded up to a multiple of 4. */
 } lbm_launch;
 
 /* Bytes of device workspace lbm_init needs for nbatch grids of the given
- * sizes and dtype. Synchronous, host only. Returns LBM_OK or LBM_E_INVALID. */
+ * sizes and dtype: three population buffers of 9 x pitch x ny elements per
+ * grid (the state, the next state and the intermediate state of the two-step
+ * path; pitch = nx rounded up to 64) and one x pitch x ny plane of cell
+ * moduli. Synchronous, host only. Returns LBM_OK or LBM_E_INVALID. */
 int lbm_workspace_bytes(const lbm_grid *grids, int32_t nbatch, int32_t dtype,
                         size_t *bytes);
 
@@ -158,13 +169,19 @@ int lbm_step(lbm_ctx *ctx, int64_t n);
 
 /* Per-kernel timing of the step (diagnostics for roofline measurement). A
  * step launches the interior kernel over the tiles clear of walls, sources and
- * receivers (when split is on), then the general kernel over the rest. */
+ * receivers (when split is on), then the general kernel over the rest. With
+ * fuse_rows > 0 the steps go in pairs: the general kernel (step t), the
+ * two-step kernel (steps t and t+1 of its blocks), the general kernel (step
+ * t+1); an odd last step runs alone as above. */
 typedef struct {
   int64_t steps;          /* steps timed */
   double interior_ms;     /* mean duration of one interior-kernel launch; 0 if none */
-  double general_ms;      /* mean duration of one general-kernel launch */
+  double general_ms;      /* mean duration of one general-kernel launch; 0 if none */
   int64_t interior_cells; /* cells one interior-kernel launch updates */
-  int64_t general_cells;  /* cells one general-kernel launch updates */
+  int64_t general_cells;  /* cells one general-kernel launch updates (of the
+                             two-step path's general tiles when fuse_rows > 0) */
+  double fused_ms;        /* mean duration of one two-step-kernel launch; 0 if none */
+  int64_t fused_cells;    /* cells one two-step-kernel launch advances by two steps */
 } lbm_kernel_times;
 
 /* Advance all grids n >= 0 steps like lbm_step, but with direct launches and
@@ -196,8 +213,9 @@ int lbm_check_finite(lbm_ctx *ctx);
 
 /* Launch configuration in use, and a way to set it (waves in {1,2,4,8},
  * rows >= 1, graph_chunk >= 0, prefetch in {1,2} (0 means 1), split, pair and
- * overlap in {0,1}). An odd
- * graph_chunk is rounded up to keep the ping-pong parity. */
+ * overlap in {0,1}, fuse_rows 0 or in [4, 248]). graph_chunk is rounded up to keep
+ * the ping-pong parity (to even, or to a multiple of 4 with fuse_rows > 0).
+ * Returns LBM_OK or LBM_E_INVALID (the configuration in use is kept). */
 int lbm_get_launch(const lbm_ctx *ctx, lbm_launch *out);
 int lbm_set_launch(lbm_ctx *ctx, const lbm_launch *cfg);
 

@@ -44,8 +44,11 @@ struct Layout {
   int64_t f_elems = 0;   // one population buffer
   int64_t k_elems = 0;   // kappa cell planes
   size_t esize = 4;
+  // three population buffers (the ping-pong pair and the two-step kernel's
+  // intermediate buffer) and the kappa cell planes, each 256-B aligned
   size_t bytes() const {
-    return (size_t)round_up((2 * f_elems + k_elems) * (int64_t)esize, 256) + 256;
+    return 3 * (size_t)round_up(f_elems * (int64_t)esize, 256) +
+           (size_t)round_up(k_elems * (int64_t)esize, 256) + 256;
   }
 };
 
@@ -125,6 +128,7 @@ struct lbm_ctx {
   char *ws = nullptr;
   char *fbuf[2] = {nullptr, nullptr};
   char *kcells = nullptr;
+  char *fmid = nullptr;                          // intermediate state of the two-step path
   int cur = 0;                                   // buffer holding f*(t-1)
   int64_t t = 0;
   // library-owned device tables
@@ -141,7 +145,12 @@ struct lbm_ctx {
   std::vector<int64_t> rscale_off;               // per grid offset into d_rtab
   std::vector<char> rtab_host;
   bool tables_dirty = true;
-  lbm_launch launch{4, 8, 0, 1, 1, 0, 1};
+  lbm_launch launch{4, 8, 0, 1, 1, 0, 1, 0};
+  // two-step path: fused tiles and the general tiles advanced step by step
+  DevBuf<FusedTileDev> d_ftiles;
+  DevBuf<TileDev> d_gtiles2;
+  int nftiles = 0, ngtiles2 = 0;
+  int64_t cells_fused = 0, cells_gen2 = 0;
   // second stream and fork/join events for the overlapped general kernel
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -346,7 +355,7 @@ void build_tiles(const lbm_ctx *c, int waves, int rows, bool split, std::vector<
 lbm_launch default_launch(const lbm_ctx *c) {
   int64_t cells = 0;
   for (const auto &g : c->grids) cells += (int64_t)g.nx * g.ny;
-  lbm_launch l{8, c->dtype == LBM_F64 ? 4 : 8, 0, 1, 1, 0, 1};
+  lbm_launch l{8, c->dtype == LBM_F64 ? 4 : 8, 0, 1, 1, 0, 1, 0};
   if (cells < 2048 * 2048) {
     l.waves = 4;
     l.rows = 4;
@@ -477,6 +486,93 @@ int commit(lbm_ctx *c) {
   return rebuild_tiles(c);   // which tiles are interior depends on sources and receivers
 }
 
+// Two-step path (launch.fuse_rows > 0): the grid is cut into blocks of
+// kFusedW columns x fuse_rows rows. A block runs in the two-step kernel when
+// it is a full block and, over the reach of two steps (4 columns and 3 rows
+// around it for the step-t collisions, one more for their pulls), it meets no
+// wall, no y-wrap, no source disk, and no receiver lies in its own rows.
+// Every other block is advanced step by step by the general kernel in
+// one-wavefront tiles of two rows. A fused block flags the sides next to
+// non-fused blocks: the general kernel's second step reads the intermediate
+// state of the two rows or columns there.
+constexpr int kFusedWaves = 4, kFusedW = 64 * kFusedWaves;
+
+bool block_is_fused(const lbm_ctx *c, int g, int x0, int y0, int y1) {
+  const lbm_grid &G = c->grids[g];
+  const lbm_bc &b = c->bc[g];
+  const int nx = G.nx, ny = G.ny, rr = b.rigid_row;
+  if (x0 + kFusedW > nx) return false;
+  if (y0 - 4 < 0 || y1 + 3 > ny - 1) return false;
+  const bool pbt = b.edge[LBM_EDGE_TOP] == LBM_PERIODIC;
+  const bool px = b.edge[LBM_EDGE_LEFT] == LBM_PERIODIC;
+  // rows whose pulls cross a wall: y0 - 3 .. y1 + 2 must hold none
+  if (!pbt && (y0 - 3 <= 0 || y1 + 2 >= ny - 1)) return false;
+  if (rr > 0 && rr - 1 <= y1 + 2 && rr >= y0 - 3) return false;
+  if (!px && (x0 - 5 < 0 || x0 + kFusedW + 4 > nx - 1)) return false;
+  for (const lbm_source &q : c->sources[g]) {
+    const double cut = 81.0 * q.sigma * q.sigma;
+    const double dx = dist_to_range(q.x, x0 - 4, x0 + kFusedW + 3, nx, px);
+    const double dy = dist_to_range(q.y, y0 - 3, y1 + 2, ny, pbt);
+    if (dx * dx + dy * dy <= cut) return false;
+  }
+  const std::vector<int32_t> &xy = c->recs[g].xy;
+  for (size_t r = 1; r < xy.size(); r += 2)
+    if (xy[r] >= y0 && xy[r] < y1) return false;
+  return true;
+}
+
+void build_fused_tiles(const lbm_ctx *c, int rows, std::vector<FusedTileDev> &fused,
+                       std::vector<TileDev> &general, int64_t &fused_cells) {
+  std::vector<FusedTileDev> lf;
+  std::vector<TileDev> lg;
+  fused_cells = 0;
+  for (int g = 0; g < c->nbatch; ++g) {
+    const int nx = c->grids[g].nx, ny = c->grids[g].ny;
+    const int bx = (nx + kFusedW - 1) / kFusedW, by = (ny + rows - 1) / rows;
+    const bool px = c->bc[g].edge[LBM_EDGE_LEFT] == LBM_PERIODIC;
+    const bool py = c->bc[g].edge[LBM_EDGE_TOP] == LBM_PERIODIC;
+    std::vector<char> isf((size_t)bx * by, 0);
+    for (int j = 0; j < by; ++j)
+      for (int i = 0; i < bx; ++i)
+        isf[(size_t)j * bx + i] =
+            block_is_fused(c, g, i * kFusedW, j * rows, std::min(j * rows + rows, ny));
+    auto fused_at = [&](int i, int j) -> int {   // 1 fused, 0 not, -1 outside the grid
+      if (i < 0 || i >= bx) { if (!px) return -1; i = (i + bx) % bx; }
+      if (j < 0 || j >= by) { if (!py) return -1; j = (j + by) % by; }
+      return isf[(size_t)j * bx + i];
+    };
+    for (int j = 0; j < by; ++j)
+      for (int i = 0; i < bx; ++i) {
+        const int x0 = i * kFusedW, y0 = j * rows, y1 = std::min(y0 + rows, ny);
+        if (isf[(size_t)j * bx + i]) {
+          int flags = 0;
+          for (int dj = -1; dj <= 1; ++dj)
+            for (int di = -1; di <= 1; ++di) {
+              if ((di | dj) == 0 || fused_at(i + di, j + dj) != 0) continue;
+              if (dj < 0) flags |= 1;
+              if (dj > 0) flags |= 2;
+              if (di < 0) flags |= 4;
+              if (di > 0) flags |= 8;
+            }
+          lf.push_back(FusedTileDev{g, x0, y0, y1, flags});
+          fused_cells += (int64_t)kFusedW * (y1 - y0);
+        } else {
+          for (int ys = y0; ys < y1; ys += kSubRows)
+            for (int xs = x0; xs < std::min(x0 + kFusedW, nx); xs += 64)
+              lg.push_back(TileDev{g, xs, ys, std::min(ys + kSubRows, y1)});
+        }
+      }
+  }
+  // die ordering as for the single-step lists
+  const int64_t T = (int64_t)lf.size(), per = (T + kXcds - 1) / kXcds;
+  fused.assign((size_t)(per * kXcds), FusedTileDev{-1, 0, 0, 0, 0});
+  for (int64_t b = 0; b < per * kXcds; ++b) {
+    const int64_t jx = b % kXcds, ix = b / kXcds, l = jx * per + ix;
+    if (ix < per && l < T) fused[(size_t)b] = lf[(size_t)l];
+  }
+  general = order_for_dies(lg);
+}
+
 int rebuild_tiles(lbm_ctx *c) {
   std::vector<TileDev> ti, tg;
   build_tiles(c, c->launch.waves, c->launch.rows, c->launch.split != 0, ti, tg);
@@ -495,6 +591,18 @@ int rebuild_tiles(lbm_ctx *c) {
   c->h_tiles_int = ti;
   c->h_tiles_gen = tg;
   c->adj_tiles_ok = false;
+  c->nftiles = c->ngtiles2 = 0;
+  c->cells_fused = c->cells_gen2 = 0;
+  if (c->launch.fuse_rows > 0) {
+    std::vector<FusedTileDev> tf;
+    std::vector<TileDev> tg2;
+    build_fused_tiles(c, c->launch.fuse_rows, tf, tg2, c->cells_fused);
+    c->nftiles = (int)tf.size();
+    c->ngtiles2 = (int)tg2.size();
+    c->cells_gen2 = cover(tg2, 64);
+    HIP_TRY(c->d_ftiles.upload(tf, c->stream));
+    HIP_TRY(c->d_gtiles2.upload(tg2, c->stream));
+  }
   HIP_TRY(c->d_tiles_int.upload(ti, c->stream));
   HIP_TRY(c->d_tiles.upload(tg, c->stream));
   drop_graphs(c);
@@ -544,6 +652,33 @@ hipError_t launch_pair(lbm_ctx *c, hipStream_t s, bool has_int, bool has_gen, Ge
   return e;
 }
 
+int use_fused(const lbm_ctx *c) { return c->launch.fuse_rows > 0 && c->nftiles > 0; }
+
+// Two steps (t and t+1) on the two-step path: the general kernel advances its
+// tiles to f*(t) in the intermediate buffer while the fused kernel takes its
+// tiles straight to f*(t+1) (and leaves f*(t) of its flagged border cells in
+// the intermediate buffer); then the general kernel takes its tiles from the
+// intermediate buffer to f*(t+1).
+template <typename real>
+hipError_t launch_two_steps(lbm_ctx *c, StepArgs<real> a, hipStream_t s) {
+  StepArgs<real> g1 = a, f2 = a, g2 = a;
+  g1.fout = reinterpret_cast<real *>(c->fmid);
+  g1.tiles = c->d_gtiles2.p;
+  f2.ftiles = c->d_ftiles.p;
+  f2.fmid = reinterpret_cast<real *>(c->fmid);
+  f2.f_elems = c->L.f_elems;
+  g2.fin = reinterpret_cast<const real *>(c->fmid);
+  g2.tiles = c->d_gtiles2.p;
+  g2.t = a.t + 1;
+  const int pf = c->launch.prefetch;
+  hipError_t e = launch_pair(
+      c, s, c->nftiles > 0, c->ngtiles2 > 0,
+      [&](hipStream_t q) { return launch_step<real>(g1, 1, pf, c->ngtiles2, kModeStep, q); },
+      [&](hipStream_t q) { return launch_fused2<real>(f2, kFusedWaves, c->nftiles, q); });
+  if (e == hipSuccess) e = launch_step<real>(g2, 1, pf, c->ngtiles2, kModeStep, s);
+  return e;
+}
+
 template <typename real>
 hipError_t launch_one_step(lbm_ctx *c, StepArgs<real> a, hipStream_t s) {
   StepArgs<real> ai = a;
@@ -584,6 +719,13 @@ StepArgs<real> make_args(lbm_ctx *c, int src_buf) {
 
 template <typename real>
 int step_direct(lbm_ctx *c, int64_t n) {
+  if (use_fused(c)) {
+    for (; n >= 2; n -= 2) {
+      HIP_TRY(launch_two_steps<real>(c, make_args<real>(c, c->cur), c->stream));
+      c->cur ^= 1;
+      c->t += 2;
+    }
+  }
   for (int64_t k = 0; k < n; ++k) {
     HIP_TRY(launch_one_step<real>(c, make_args<real>(c, c->cur), c->stream));
     c->cur ^= 1;
@@ -596,48 +738,75 @@ int step_direct(lbm_ctx *c, int64_t n) {
 // duration of each kernel's launches goes to out.
 template <typename real>
 int step_timed(lbm_ctx *c, int64_t n, lbm_kernel_times *out) {
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
   hipError_t e = hipSuccess;
-  for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
-  double sum_int = 0.0, sum_gen = 0.0;
-  for (int64_t k = 0; k < n && e == hipSuccess; ++k) {
+  for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+  double sum[3] = {0.0, 0.0, 0.0};   // interior, general, two-step
+  int64_t cnt[3] = {0, 0, 0};
+  // One launch between an event pair on the context's stream.
+  auto timed = [&](int kind, auto &&launch) {
+    if (e == hipSuccess) e = hipEventRecord(ev[0], c->stream);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(ev[1], c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+    if (e == hipSuccess) { sum[kind] += ms; cnt[kind] += 1; }
+  };
+  int64_t k = 0;
+  const int pf = c->launch.prefetch;
+  if (use_fused(c)) {
+    for (; k + 2 <= n && e == hipSuccess; k += 2) {
+      const StepArgs<real> a = make_args<real>(c, c->cur);
+      StepArgs<real> g1 = a, f2 = a, g2 = a;
+      g1.fout = reinterpret_cast<real *>(c->fmid);
+      g1.tiles = c->d_gtiles2.p;
+      f2.ftiles = c->d_ftiles.p;
+      f2.fmid = reinterpret_cast<real *>(c->fmid);
+      f2.f_elems = c->L.f_elems;
+      g2.fin = reinterpret_cast<const real *>(c->fmid);
+      g2.tiles = c->d_gtiles2.p;
+      g2.t = a.t + 1;
+      if (c->ngtiles2 > 0)
+        timed(1, [&] { return launch_step<real>(g1, 1, pf, c->ngtiles2, kModeStep, c->stream); });
+      timed(2, [&] { return launch_fused2<real>(f2, kFusedWaves, c->nftiles, c->stream); });
+      if (c->ngtiles2 > 0)
+        timed(1, [&] { return launch_step<real>(g2, 1, pf, c->ngtiles2, kModeStep, c->stream); });
+      if (e == hipSuccess) {
+        c->cur ^= 1;
+        c->t += 2;
+      }
+    }
+  }
+  for (; k < n && e == hipSuccess; ++k) {
     StepArgs<real> a = make_args<real>(c, c->cur);
     if (c->ntiles_int > 0) {
       StepArgs<real> ai = a;
       ai.tiles = c->d_tiles_int.p;
-      e = hipEventRecord(ev[0], c->stream);
-      if (e == hipSuccess)
-        e = launch_interior<real>(ai, c->launch.waves, use_pair(c), c->ntiles_int, c->stream);
-      if (e == hipSuccess) e = hipEventRecord(ev[1], c->stream);
+      timed(0, [&] {
+        return launch_interior<real>(ai, c->launch.waves, use_pair(c), c->ntiles_int, c->stream);
+      });
     }
     a.tiles = c->d_tiles.p;
-    if (e == hipSuccess) e = hipEventRecord(ev[2], c->stream);
-    if (e == hipSuccess)
-      e = launch_step<real>(a, c->gen_waves, c->launch.prefetch, c->ntiles, kModeStep, c->stream);
-    if (e == hipSuccess) e = hipEventRecord(ev[3], c->stream);
-    if (e == hipSuccess) e = hipEventSynchronize(ev[3]);
-    float ms = 0.f;
-    if (e == hipSuccess && c->ntiles_int > 0) {
-      e = hipEventElapsedTime(&ms, ev[0], ev[1]);
-      sum_int += ms;
-    }
-    if (e == hipSuccess) {
-      e = hipEventElapsedTime(&ms, ev[2], ev[3]);
-      sum_gen += ms;
-    }
+    if (c->ntiles > 0)
+      timed(1, [&] {
+        return launch_step<real>(a, c->gen_waves, pf, c->ntiles, kModeStep, c->stream);
+      });
     if (e == hipSuccess) {
       c->cur ^= 1;
       c->t += 1;
     }
   }
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
     if (ev[i]) hipEventDestroy(ev[i]);
   if (e != hipSuccess) return fail(LBM_E_DEVICE, hipGetErrorString(e));
   out->steps = n;
-  out->interior_ms = (n > 0 && c->ntiles_int > 0) ? sum_int / (double)n : 0.0;
-  out->general_ms = n > 0 ? sum_gen / (double)n : 0.0;
+  out->interior_ms = cnt[0] ? sum[0] / (double)cnt[0] : 0.0;
+  out->general_ms = cnt[1] ? sum[1] / (double)cnt[1] : 0.0;
+  out->fused_ms = cnt[2] ? sum[2] / (double)cnt[2] : 0.0;
   out->interior_cells = c->cells_int;
-  out->general_cells = c->cells_gen;
+  out->general_cells = use_fused(c) ? c->cells_gen2 : c->cells_gen;
+  out->fused_cells = use_fused(c) ? c->cells_fused : 0;
   return LBM_OK;
 }
 
@@ -656,11 +825,13 @@ int build_graphs(lbm_ctx *c, int chunk) {
       return fail(LBM_E_DEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
     }
     int buf = parity;
-    for (int k = 0; k < chunk; ++k) {
+    const bool fused = use_fused(c);
+    for (int k = 0; k < chunk; k += fused ? 2 : 1) {
       StepArgs<real> a = make_args<real>(c, buf);
       a.t = k;
       a.t_dev = c->d_time.p;
-      launch_one_step<real>(c, a, cs);
+      if (fused) launch_two_steps<real>(c, a, cs);
+      else launch_one_step<real>(c, a, cs);
       buf ^= 1;
     }
     launch_add_time(c->d_time.p, chunk, cs);
@@ -691,7 +862,9 @@ int step_impl(lbm_ctx *c, int64_t n) {
     HIP_TRY(launch_set_time(c->d_time.p, c->t, c->stream));
     while (n >= chunk) {
       HIP_TRY(hipGraphLaunch(c->gexec[c->cur], c->stream));
-      c->t += chunk;   // chunk is even: the state returns to the same buffer
+      // the chunk flips the buffers an even number of times (an even number
+      // of single steps, or a multiple of four steps in pairs)
+      c->t += chunk;
       n -= chunk;
     }
   }
@@ -1020,6 +1193,7 @@ int lbm_init(lbm_ctx **out, const lbm_grid *grids, int32_t nbatch, int32_t dtype
   c->fbuf[0] = c->ws;
   c->fbuf[1] = c->ws + round_up(L.f_elems * (int64_t)L.esize, 256);
   c->kcells = c->fbuf[1] + round_up(L.f_elems * (int64_t)L.esize, 256);
+  c->fmid = c->kcells + round_up(L.k_elems * (int64_t)L.esize, 256);
   auto bail = [&](int rc) {
     lbm_destroy(c);
     return rc;
@@ -1235,8 +1409,10 @@ int lbm_set_launch(lbm_ctx *c, const lbm_launch *cfg) {
   if (cfg->rows < 1) return fail(LBM_E_INVALID, "rows must be >= 1");
   if (cfg->graph_chunk < 0) return fail(LBM_E_INVALID, "graph_chunk must be >= 0");
   if (cfg->prefetch < 0 || cfg->prefetch > 2) return fail(LBM_E_INVALID, "prefetch must be 1 or 2");
+  if (cfg->fuse_rows != 0 && (cfg->fuse_rows < 4 || cfg->fuse_rows > kFusedMaxRows))
+    return fail(LBM_E_INVALID, "fuse_rows must be 0 or in [4, 248]");
   const bool retile = cfg->waves != c->launch.waves || cfg->rows != c->launch.rows ||
-                      cfg->split != c->launch.split;
+                      cfg->split != c->launch.split || cfg->fuse_rows != c->launch.fuse_rows;
   if (cfg->split < 0 || cfg->split > 1 || cfg->pair < 0 || cfg->pair > 1 || cfg->overlap < 0 ||
       cfg->overlap > 1)
     return fail(LBM_E_INVALID, "split, pair and overlap must be 0 or 1");
@@ -1245,7 +1421,10 @@ int lbm_set_launch(lbm_ctx *c, const lbm_launch *cfg) {
   c->launch = *cfg;
   if (c->launch.prefetch == 0) c->launch.prefetch = 1;
   if (regraph) drop_graphs(c);
-  if (c->launch.graph_chunk % 2) c->launch.graph_chunk += 1;   // keep buffer parity
+  // keep the buffer parity across a captured chunk: an even number of single
+  // steps, or a multiple of four steps on the two-step path
+  const int q = c->launch.fuse_rows > 0 ? 4 : 2;
+  if (c->launch.graph_chunk % q) c->launch.graph_chunk += q - c->launch.graph_chunk % q;
   if (retile) return rebuild_tiles(c);
   if (c->gchunk != c->launch.graph_chunk) drop_graphs(c);
   return LBM_OK;
@@ -1280,7 +1459,7 @@ int lbm_autotune(lbm_ctx *c, int32_t steps, lbm_launch *chosen) {
   for (int pf = 1; pf <= 2; ++pf)
   for (int wi = 0; wi < 4 && e == hipSuccess && rc == LBM_OK; ++wi)
     for (int ri = 0; ri < 6 && e == hipSuccess && rc == LBM_OK; ++ri) {
-      lbm_launch cand{waves_c[wi], rows_c[ri], 0, pf, keep.split, pair, keep.overlap};
+      lbm_launch cand{waves_c[wi], rows_c[ri], 0, pf, keep.split, pair, keep.overlap, 0};
       if (pair && cand.waves == 1) continue;
       const int64_t tiles = cells / ((int64_t)64 * cand.waves * cand.rows);
       if (tiles < 512 && !(cand.waves == 1 && cand.rows == 4)) continue;
@@ -1317,6 +1496,7 @@ int lbm_autotune(lbm_ctx *c, int32_t steps, lbm_launch *chosen) {
   if (rc) return rc;
   if (e != hipSuccess) return fail(LBM_E_DEVICE, hipGetErrorString(e));
   best.graph_chunk = keep.graph_chunk;
+  best.fuse_rows = keep.fuse_rows;
   c->launch = best;
   rc = rebuild_tiles(c);
   if (rc) return rc;
@@ -1477,6 +1657,8 @@ int lbm_destroy(lbm_ctx *c) {
   c->d_adj_gen.release();
   c->d_grids.release();
   c->d_tiles.release();
+  c->d_ftiles.release();
+  c->d_gtiles2.release();
   c->d_tiles_int.release();
   c->d_krows.release();
   c->d_sponge.release();

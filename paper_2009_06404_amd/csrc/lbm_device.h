@@ -152,6 +152,39 @@ __device__ __forceinline__ real cell_kappa(const real *kappa_rows, const real *k
   return kappa_cells[g.k_off + (int64_t)y * g.pitch + x];
 }
 
+// The fields of a grid descriptor that the per-cell look-ups read, moved to
+// scalar registers (the descriptor is uniform across the workgroup). A loop
+// that stores to memory otherwise keeps re-reading them, or keeps them in
+// vector registers whose loads the compiler cannot prove complete inside the
+// loop, and waits for all outstanding loads at every use.
+__device__ __forceinline__ int32_t sreg(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t sreg(int64_t v) {
+  const uint64_t u = (uint64_t)v;
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)u);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)(u >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double sreg(double v) {
+  return __builtin_bit_cast(double, sreg(__builtin_bit_cast(int64_t, v)));
+}
+__device__ __forceinline__ GridDev uniform_lookup_fields(const GridDev &src) {
+  GridDev g;
+  g.nx = sreg(src.nx);
+  g.ny = sreg(src.ny);
+  g.pitch = sreg(src.pitch);
+  g.kmode = sreg(src.kmode);
+  g.f_off = sreg(src.f_off);
+  g.kscalar = sreg(src.kscalar);
+  g.k_off = sreg(src.k_off);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    g.bc[e] = sreg(src.bc[e]);
+    g.sp_thick[e] = sreg(src.sp_thick[e]);
+    g.sp_off[e] = sreg(src.sp_off[e]);
+  }
+  return g;
+}
+
 // Sponge pair (A, 1/(1 + A/2)) along x for column x (left/right layers). The
 // table holds the pairs; the second decreases with the first, so the largest
 // A of overlapping layers pairs with the smallest reciprocal.

@@ -51,6 +51,18 @@ struct TileDev {
   int32_t g, x0, y0, y1;
 };
 
+// Largest block height of the two-step kernel (its per-row table in LDS).
+constexpr int kFusedMaxRows = 248;
+
+// A tile of the two-step kernel: grid g, columns [x0, x0 + 64*NW), rows
+// [y0, y1) with y1 - y0 <= kFusedMaxRows; flags: bit 0/1/2/3 = also write
+// the intermediate state of the tile's two top rows / bottom rows / left
+// columns / right columns (next to cells the general kernel advances step by
+// step).
+struct FusedTileDev {
+  int32_t g, x0, y0, y1, flags;
+};
+
 template <typename real>
 struct StepArgs {
   const real *fin;       // state f*(t-1), all grids
@@ -70,6 +82,9 @@ struct StepArgs {
   real *mom;             // moments mode: [6][ny][nx] of grid mom_grid
   int32_t mom_grid;
   real *rho_out;         // stash mode: rho(t) of every cell at c_off + y * pitch + x
+  const FusedTileDev *ftiles;  // two-step kernel: its tiles
+  real *fmid;            // two-step kernel: intermediate state f*(t) of the border cells
+  int64_t f_elems;       // elements of one population buffer (bounds of fin/fout/fmid)
 };
 
 // kModeStash: the step plus the density of every cell written to rho_out,
@@ -119,6 +134,11 @@ hipError_t launch_lame_gradient(const real *lam, const real *mu, const double *g
 template <typename real>
 hipError_t launch_step(const StepArgs<real> &a, int waves, int prefetch, int ntiles, int mode,
                        hipStream_t stream);
+
+// Two steps (t and t+1) of the interior tiles in a.ftiles: reads a.fin =
+// f*(t-1), writes a.fout = f*(t+1) and, for flagged border cells, a.fmid = f*(t).
+template <typename real>
+hipError_t launch_fused2(const StepArgs<real> &a, int waves, int ntiles, hipStream_t stream);
 
 // Interior tiles; with a.rho_out set, the one-column kernel also writes rho(t).
 template <typename real>

@@ -694,6 +694,179 @@ __global__ __launch_bounds__(64 * NW) void interior2_kernel(StepArgs<real> a) {
   }
 }
 
+
+// Buffer descriptor covering [base, base + bytes) (capped at 4 GiB - 1):
+// accesses past the end read zero and drop their stores instead of faulting.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t range_rsrc(const void *base, uint64_t bytes) {
+  const uint32_t n = bytes > 0xffffffffull ? 0xffffffffu : (uint32_t)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)n, 0x00020000);
+}
+
+// Two time steps of an interior tile in one pass (temporal blocking). The
+// workgroup marches down the tile's rows with a four-stage pipeline:
+//   A (row r):   pull f(t) from f*(t-1) in HBM, rho(t) into an LDS ring;
+//   B (row r-1): density gradient and collision of step t -> f*(t) into an
+//                LDS ring of three rows (and to HBM for flagged border cells);
+//   C (row r-2): pull f(t+1) from the f*(t) ring, rho(t+1) into an LDS ring;
+//   D (row r-3): density gradient and collision of step t+1 -> f*(t+1) to HBM.
+// Stage B runs on the tile's columns plus three halo columns on each side
+// and stage C on two, so stage D has every neighbour it needs; the four halo
+// columns per side are handled by an extra wavefront (the output wavefronts
+// keep aligned accesses). Rows: output rows [y0, y1) need f*(t) on rows
+// y0-2 .. y1+1 and f*(t-1) on rows y0-4 .. y1+3. The per-cell arithmetic is
+// the single-step kernels' (same operations in the same order), so two
+// steps here equal two single steps bit for bit. Tiles are clear of walls,
+// the y-wrap, source disks and receivers over that whole reach.
+template <typename real, int NW>
+__global__ __launch_bounds__(64 * NW + 64) void fused2_kernel(StepArgs<real> a) {
+  constexpr int W = 64 * NW;
+  constexpr int LW = W + 8;                 // LDS columns: tile plus 4 each side
+  constexpr int RT = kFusedMaxRows + 8;     // per-row table: rows y0-4 .. y1+3
+  __shared__ real sA[2][LW];
+  __shared__ real sS1[3][9][LW];
+  __shared__ real sC[2][LW];
+  __shared__ real sRowA[RT], sRowI[RT], sRowK[RT];
+
+  const FusedTileDev tile = a.ftiles[blockIdx.x];
+  if (tile.g < 0) return;
+  const GridDev g = uniform_lookup_fields(a.grids[tile.g]);
+  const int pitch = g.pitch, nx = g.nx;
+  const int tid = threadIdx.x;
+  const bool outlane = tid < W;
+  const int hl = tid - W;
+  // LDS column lc in [0, LW): 0..3 left halo, 4..W+3 the tile, W+4..W+7 right halo
+  int lc = -1;
+  if (outlane) lc = tid + 4;
+  else if (hl < 4) lc = hl;
+  else if (hl < 8) lc = W + hl;
+  const bool live = lc >= 0;
+  auto wrapx = [&](int c) { return c < 0 ? c + nx : (c >= nx ? c - nx : c); };
+  const int col = live ? wrapx(tile.x0 - 4 + lc) : 0;
+  const uint32_t esz = sizeof(real);
+  const uint32_t o0 = (uint32_t)col * esz;
+  const uint32_t ol = (uint32_t)wrapx(col - 1) * esz;
+  const uint32_t orr = (uint32_t)wrapx(col + 1) * esz;
+
+  const real omega = a.omega, cforce = a.cforce;
+  const int y0 = tile.y0, y1 = tile.y1;
+  const int ybase = y0 - 4;
+  const uint32_t qb = (uint32_t)pitch * esz;
+  const uint32_t rowb = 9 * qb;
+  const int64_t base = g.f_off + (int64_t)ybase * 9 * pitch;
+  const uint64_t rest = (uint64_t)(a.f_elems - base) * esz;
+  const __amdgpu_buffer_rsrc_t rin = range_rsrc(a.fin + base, rest);
+  const __amdgpu_buffer_rsrc_t rout = range_rsrc(a.fout + base, rest);
+  const __amdgpu_buffer_rsrc_t rmid = range_rsrc(a.fmid + base, rest);
+
+  // Per-row look-ups of the tile's rows, read once: the top/bottom sponge
+  // pair of the row (combined with the column's pair by the same max/min as
+  // the single-step kernels, exact operations, so the order does not matter)
+  // and the row's modulus for layered media. The row loop then issues no
+  // global loads besides the populations (and the modulus of cell-wise media).
+  const int nrows = y1 - y0 + 8;
+  for (int k = tid; k < nrows; k += W + 64) {
+    real Ay = real(0), Iy = real(1);
+    sponge_y(a.sponge, g, ybase + k, Ay, Iy);
+    sRowA[k] = Ay;
+    sRowI[k] = Iy;
+    sRowK[k] = g.kmode == kKappaRows ? a.kappa_rows[g.k_off + ybase + k] : real(0);
+  }
+  real A_x, inv_x;
+  sponge_x(a.sponge, g, col, A_x, inv_x);
+  const bool kcells = g.kmode == kKappaCells;
+  const real kscalar = (real)g.kscalar;
+  const real *kcol = a.kappa_cells + g.k_off + col;
+  const bool inB = lc >= 1 && lc <= W + 6, inC = lc >= 2 && lc <= W + 5;
+  const int dump = tile.flags;
+  const bool dump_col = (outlane && (((dump & 4) && lc < 6) || ((dump & 8) && lc >= W + 2)));
+  __syncthreads();
+
+  // Registers carried down the rows: fa/fb the pulled f(t) of rows r-1 and r,
+  // fc row r+1 (in flight while row r is worked on), gc/gn the pulled
+  // f(t+1) of rows r-3 and r-2; for cell-wise moduli, the cell's modulus of
+  // rows r+1 (in flight), r and r-1 .. r-3 (stage B takes row r-1's, stage D
+  // two rows later the same).
+  real fa[9], fb[9], fc[9], gc[9], gn[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) { fa[i] = fb[i] = fc[i] = gc[i] = gn[i] = real(0); }
+  real rA_m = real(0), rA_c = real(0), rC_m = real(0), rC_c = real(0);
+  real kq = real(0), k1 = real(0), k2 = real(0), k3 = real(0);
+  if (live) pull_fast(rin, ybase, y0 - 3, rowb, qb, o0, ol, orr, fb);
+  if (live && kcells) kq = kcol[(int64_t)(y0 - 3) * pitch];
+
+  for (int r = y0 - 3; r <= y1 + 2; ++r) {
+    real kn = real(0);
+    if (live && r < y1 + 2) {
+      pull_fast(rin, ybase, r + 1, rowb, qb, o0, ol, orr, fc);
+      if (kcells) kn = kcol[(int64_t)(r + 1) * pitch];
+    }
+    // Stage A: row r of step t.
+    real rA_n = real(0);
+    if (live) {
+      rA_n = sum9(fb);
+      sA[r & 1][lc] = rA_n;
+    }
+    // Stage B: row r-1 of step t (needs rho(t) of rows r-2 .. r).
+    const int rb = r - 1;
+    if (rb >= y0 - 2 && inB) {
+      const real dx = real(0.5) * (sA[rb & 1][lc + 1] - sA[rb & 1][lc - 1]);
+      const real dy = real(0.5) * (rA_n - rA_m);
+      const real kap = kcells ? k1 : (g.kmode == kKappaRows ? sRowK[rb - ybase] : kscalar);
+      const real A = max(A_x, sRowA[rb - ybase]), inv = min(inv_x, sRowI[rb - ybase]);
+      const CellState<real> cs = cell_state(fa, rA_c, kap * dx, kap * dy, A, inv);
+      real s1[9];
+      collide(fa, cs, omega, cforce, s1);
+      const int slot = (rb + 3) % 3;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) sS1[slot][i][lc] = s1[i];
+      if (dump && outlane && rb >= y0 && rb < y1 &&
+          (dump_col || ((dump & 1) && rb < y0 + 2) || ((dump & 2) && rb >= y1 - 2))) {
+        const uint32_t rs = (uint32_t)(rb - ybase) * rowb;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Buf<real>::store_nt(s1[i], rmid, o0, rs + i * qb);
+      }
+    }
+    __syncthreads();
+    // Stage C: row r-2 of step t+1 (pull from the f*(t) ring).
+    const int rc = r - 2;
+    real rC_n = real(0);
+    if (rc >= y0 - 1 && inC) {
+      const int sm = (rc + 2) % 3, s0 = (rc + 3) % 3, sp = (rc + 4) % 3;   // rows rc-1, rc, rc+1
+      gn[0] = sS1[s0][0][lc];
+      gn[1] = sS1[s0][1][lc - 1];
+      gn[2] = sS1[sm][2][lc];
+      gn[3] = sS1[s0][3][lc + 1];
+      gn[4] = sS1[sp][4][lc];
+      gn[5] = sS1[sm][5][lc - 1];
+      gn[6] = sS1[sm][6][lc + 1];
+      gn[7] = sS1[sp][7][lc + 1];
+      gn[8] = sS1[sp][8][lc - 1];
+      rC_n = sum9(gn);
+      sC[rc & 1][lc] = rC_n;
+    }
+    // Stage D: row r-3 of step t+1 (needs rho(t+1) of rows r-4 .. r-2).
+    const int rd = r - 3;
+    if (rd >= y0 && outlane) {
+      const real dx = real(0.5) * (sC[rd & 1][lc + 1] - sC[rd & 1][lc - 1]);
+      const real dy = real(0.5) * (rC_n - rC_m);
+      const real kap = kcells ? k3 : (g.kmode == kKappaRows ? sRowK[rd - ybase] : kscalar);
+      const real A = max(A_x, sRowA[rd - ybase]), inv = min(inv_x, sRowI[rd - ybase]);
+      const CellState<real> cs = cell_state(gc, rC_c, kap * dx, kap * dy, A, inv);
+      real s2[9];
+      collide(gc, cs, omega, cforce, s2);
+      const uint32_t rs = (uint32_t)(rd - ybase) * rowb;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Buf<real>::store_nt(s2[i], rout, o0, rs + i * qb);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 9; ++i) { fa[i] = fb[i]; fb[i] = fc[i]; gc[i] = gn[i]; }
+    rA_m = rA_c; rA_c = rA_n;
+    rC_m = rC_c; rC_c = rC_n;
+    k3 = k2; k2 = k1; k1 = kq; kq = kn;
+  }
+}
+
 }  // namespace
 
 template <typename real>
@@ -764,6 +937,20 @@ hipError_t launch_interior(const StepArgs<real> &a, int waves, int pair, int nti
   }
   return hipGetLastError();
 }
+
+
+template <typename real>
+hipError_t launch_fused2(const StepArgs<real> &a, int waves, int ntiles, hipStream_t stream) {
+  if (ntiles <= 0) return hipSuccess;
+  dim3 grid(ntiles), block(64 * waves + 64);
+  if (waves == 2) hipLaunchKernelGGL((fused2_kernel<real, 2>), grid, block, 0, stream, a);
+  else if (waves == 4) hipLaunchKernelGGL((fused2_kernel<real, 4>), grid, block, 0, stream, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template hipError_t launch_fused2<float>(const StepArgs<float> &, int, int, hipStream_t);
+template hipError_t launch_fused2<double>(const StepArgs<double> &, int, int, hipStream_t);
 
 template hipError_t launch_interior<float>(const StepArgs<float> &, int, int, int, hipStream_t);
 template hipError_t launch_interior<double>(const StepArgs<double> &, int, int, int, hipStream_t);

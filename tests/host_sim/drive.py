@@ -69,8 +69,7 @@ def run(probs, T, seg, dtype, launch=None, chunks=None):
     if launch:
         lc = L.lbm_get_launch(ctx)
         lc.update(launch)
-        L.lbm_set_launch(ctx, lc["waves"], lc["rows"], lc["graph_chunk"], lc["prefetch"],
-                         lc["split"], lc["pair"])
+        L.lbm_set_launch(ctx, **lc)
     ab = L.lbm_adjoint_workspace_bytes(ctx, seg, T)
     aws = dev(np.zeros(ab + 512, np.uint8))
     L.lbm_adjoint_begin(ctx, seg, T, (aws.ctypes.data + 255) // 256 * 256, ab)
@@ -91,6 +90,41 @@ def run(probs, T, seg, dtype, launch=None, chunks=None):
     L.lbm_destroy(ctx)
 
 
+sim.sim_pairs_checked.restype = C.c_int64
+
+
+def run_forward(probs, T, launch, steps=(5, 1, 8)):
+    """Forward steps only, with the given launch (two-step path when
+    fuse_rows > 0): odd and even step counts, graphs, timed steps."""
+    code, npdt = (L.LBM_F32, np.float32)
+    grids = [(p.nx, p.ny) for p in probs]
+    fields = [np.concatenate([p.medium.full(p.ny, p.nx)[k].ravel() for p in probs]).astype(npdt)
+              for k in range(3)]
+    lam, mu, rho = (dev(f) for f in fields)
+    nb = L.lbm_workspace_bytes(grids, code)
+    ws = dev(np.zeros(nb + 512, np.uint8))
+    wp = (ws.ctypes.data + 255) // 256 * 256
+    bcs = [(p.bc[0], p.bc[1], p.bc[2], p.bc[3], p.rigid_row) for p in probs]
+    sps = [(tuple(p.sponge_thick), tuple(p.profile(e) for e in range(4))) for p in probs]
+    ctx = L.lbm_init(grids, code, lam.ctypes.data, mu.ctypes.data, rho.ctypes.data, probs[0].tau,
+                     bcs, sps, wp, nb, 0)
+    T = sum(steps) + 8
+    for g, p in enumerate(probs):
+        L.lbm_set_sources(ctx, g, [s.as_tuple() for s in p.sources])
+        tr = dev(np.zeros((T, p.nrec, p.ncomp), npdt))
+        L.lbm_set_receivers(ctx, g, np.asarray(p.receivers, np.int32), p.comp_mask, tr.ctypes.data, T)
+    lc = L.lbm_get_launch(ctx)
+    lc.update(launch)
+    L.lbm_set_launch(ctx, **lc)
+    before = sim.sim_pairs_checked()
+    for n in steps:
+        L.lbm_step(ctx, n)
+    kt = L.lbm_step_timed(ctx, 4)
+    after = sim.sim_pairs_checked()
+    L.lbm_destroy(ctx)
+    return after - before, kt
+
+
 CASES = [
     ("periodic", (BC_PERIODIC,) * 4, -1),
     ("free_rigid_interface", (BC_FREE, BC_RIGID, BC_PERIODIC, BC_PERIODIC), 17),
@@ -108,4 +142,22 @@ for dtype in ("f64", "f32"):
         print("ok", name, dtype, flush=True)
     run([problem(CASES[1][1], 20, 150, 37, 3), problem(CASES[3][1], -1, 64, 65, 4)], 18, 5, dtype,
         launch=dict(waves=2, rows=4), chunks=[7, 11])
+# two-step path: blocks of 256 columns; every pair must write each cell once
+# and the second general step may read only intermediate cells of its pair
+FUSED = [
+    ("periodic", (BC_PERIODIC,) * 4, -1, 600, 120),
+    ("free_rigid_interface", (BC_FREE, BC_RIGID, BC_PERIODIC, BC_PERIODIC), 61, 530, 150),
+    ("free0_rigid_sides", (BC_FREE0, BC_FREE0, BC_RIGID, BC_RIGID), -1, 780, 97),
+]
+for name, bc, rr, nx, ny in FUSED:
+    p = problem(bc, rr, nx, ny, 5, sources=[Source(nx * 0.7, ny * 0.5, 2.0, 0.3, 0.9, 1.0, 12.0, 16.0)],
+                receivers=[(x, 0) for x in range(0, nx, 5)] + [(x, 77) for x in range(3, nx, 11)])
+    for fr in (4, 8, 13):
+        for extra in (dict(), dict(overlap=0), dict(graph_chunk=6)):
+            pairs, kt = run_forward([p], 0, dict(waves=4, rows=8, fuse_rows=fr, **extra))
+            assert pairs > 0 and kt["fused_cells"] > 0, (name, fr, extra, pairs, kt)
+    print("ok fused", name, flush=True)
+pairs, kt = run_forward([problem(FUSED[1][1], 40, 530, 90, 6), problem(FUSED[0][1], -1, 300, 64, 7),
+                         problem(FUSED[2][1], -1, 1100, 50, 8)], 0, dict(waves=2, rows=4, fuse_rows=6))
+assert pairs > 0, pairs
 print("ALL OK", flush=True)

@@ -9,8 +9,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <cmath>
+#include <vector>
 #include "lbm_internal.h"
 
 static std::map<uintptr_t, size_t> g_alloc;   // base -> bytes
@@ -74,10 +76,78 @@ template <typename real>
 static void check_pop(const real *base, const GridDev &g, const char *what) {
   check_range(base + g.f_off, sizeof(real) * 9 * (size_t)g.pitch * g.ny, what);
 }
+// Two-step path bookkeeping. Each launch gets a sequence number and stamps
+// the cells it writes in its output buffer. A pair is general step t into the
+// intermediate buffer, the two-step kernel (seq s) and general step t+1 out of
+// the intermediate buffer: the first general launch runs just before or just
+// after the two-step kernel (seq s-1 or s+1), so the last must find every
+// cell it may read (within two cells of its tiles) stamped s-1 or later, and
+// the two-step kernel plus the second general launch must write every cell of
+// every grid exactly once.
+static int64_t g_seq = 0, g_fused_seq = -10;
+static const void *g_fmid = nullptr, *g_pair_out = nullptr;
+static std::map<const void *, std::map<int, std::vector<int64_t>>> g_stamps;
+static std::map<int, std::vector<int>> g_cov;   // per grid and cell: writes of the pending pair
+static int g_ngrids = 0;
+static bool g_pending = false;
+static int64_t g_pairs_checked = 0;
+
+static std::vector<int64_t> &stamps(const void *buf, int g, const GridDev &G) {
+  std::vector<int64_t> &v = g_stamps[buf][g];
+  if (v.empty()) v.assign((size_t)G.nx * G.ny, -100);
+  return v;
+}
+static void pair_check_done() {
+  if (!g_pending) return;
+  for (int g = 0; g < g_ngrids; ++g) {
+    const std::vector<int> &v = g_cov[g];
+    for (size_t i = 0; i < v.size(); ++i)
+      if (v[i] != 1) {
+        fprintf(stderr, "two-step pair wrote cell %zu of grid %d %d times\n", i, g, v[i]);
+        abort();
+      }
+  }
+  g_pending = false;
+  ++g_pairs_checked;
+}
+extern "C" int64_t sim_pairs_checked() { pair_check_done(); return g_pairs_checked; }
+
 template <typename real>
 hipError_t launch_step(const StepArgs<real> &a, int waves, int, int ntiles, int mode, hipStream_t) {
   if (ntiles <= 0) return hipSuccess;
   check_tiles<real>(a.tiles, ntiles, a.grids, 64 * waves, false, "step tiles");
+  const int64_t seq = g_seq++;
+  const int W = 64 * waves;
+  const bool second = g_fmid && (const void *)a.fin == g_fmid;
+  for (int i = 0; i < ntiles && mode != kModeMoments; ++i) {
+    const TileDev t = a.tiles[i];
+    if (t.g < 0) continue;
+    const GridDev &g = a.grids[t.g];
+    const bool px = g.bc[kEdgeLeft] == kPeriodic, py = g.bc[kEdgeTop] == kPeriodic;
+    std::vector<int64_t> &out = stamps(a.fout, t.g, g);
+    std::vector<int64_t> *mid = second ? &stamps(g_fmid, t.g, g) : nullptr;
+    if (second && (!g_pending || (const void *)a.fout != g_pair_out)) {
+      fprintf(stderr, "second general step without its two-step launch\n");
+      abort();
+    }
+    for (int y = t.y0; y < t.y1; ++y)
+      for (int x = t.x0; x < t.x0 + W && x < g.nx; ++x) {
+        out[(size_t)y * g.nx + x] = seq;
+        if (!second) continue;
+        g_cov[t.g][(size_t)y * g.nx + x] += 1;
+        for (int dy = -2; dy <= 2; ++dy)
+          for (int dx = -2; dx <= 2; ++dx) {
+            int xx = x + dx, yy = y + dy;
+            if (xx < 0 || xx >= g.nx) { if (!px) continue; xx = (xx + g.nx) % g.nx; }
+            if (yy < 0 || yy >= g.ny) { if (!py) continue; yy = (yy + g.ny) % g.ny; }
+            if ((*mid)[(size_t)yy * g.nx + xx] < g_fused_seq - 1) {
+              fprintf(stderr, "second general step reads stale intermediate cell g=%d (%d,%d) from (%d,%d)\n",
+                      t.g, xx, yy, x, y);
+              abort();
+            }
+          }
+      }
+  }
   for (int i = 0; i < ntiles; ++i) {
     if (a.tiles[i].g < 0) continue;
     const GridDev &g = a.grids[a.tiles[i].g];
@@ -97,6 +167,51 @@ hipError_t launch_interior(const StepArgs<real> &a, int waves, int, int ntiles, 
     check_pop(a.fin, g, "int fin");
     check_pop(a.fout, g, "int fout");
     if (a.rho_out) check_range(a.rho_out + g.c_off, sizeof(real) * (size_t)g.pitch * g.ny, "int stash out");
+  }
+  return hipSuccess;
+}
+template <typename real>
+hipError_t launch_fused2(const StepArgs<real> &a, int waves, int ntiles, hipStream_t) {
+  if (ntiles <= 0) return hipSuccess;
+  const int W = 64 * waves;
+  check_range(a.ftiles, sizeof(FusedTileDev) * ntiles, "fused tiles");
+  pair_check_done();
+  // every grid's population block lies inside f_elems: count the grids
+  g_ngrids = 0;
+  for (int64_t fe = 0; fe < a.f_elems; ++g_ngrids)
+    fe = a.grids[g_ngrids].f_off + 9 * (int64_t)a.grids[g_ngrids].pitch * a.grids[g_ngrids].ny;
+  const int64_t seq = g_seq++;
+  g_fused_seq = seq;
+  g_fmid = a.fmid;
+  g_pair_out = a.fout;
+  g_pending = true;
+  g_cov.clear();
+  for (int g = 0; g < g_ngrids; ++g) g_cov[g].assign((size_t)a.grids[g].nx * a.grids[g].ny, 0);
+  for (int i = 0; i < ntiles; ++i) {
+    const FusedTileDev t = a.ftiles[i];
+    if (t.g < 0) continue;
+    if (t.g >= g_ngrids) { fprintf(stderr, "fused tile grid %d out of range\n", t.g); abort(); }
+    const GridDev &g = a.grids[t.g];
+    if (t.x0 < 0 || t.x0 + W > g.nx || t.y0 - 4 < 0 || t.y1 + 3 > g.ny - 1 || t.y0 >= t.y1 ||
+        t.y1 - t.y0 > kFusedMaxRows) {
+      fprintf(stderr, "bad fused tile g=%d x0=%d y0=%d y1=%d (nx=%d ny=%d)\n", t.g, t.x0, t.y0, t.y1, g.nx, g.ny);
+      abort();
+    }
+    check_pop(a.fin, g, "fused fin");
+    check_pop(a.fout, g, "fused fout");
+    check_pop(a.fmid, g, "fused fmid");
+    std::vector<int64_t> &mid = stamps(a.fmid, t.g, g);
+    std::vector<int64_t> &out = stamps(a.fout, t.g, g);
+    for (int y = t.y0; y < t.y1; ++y)
+      for (int x = t.x0; x < t.x0 + W; ++x) {
+        const size_t c = (size_t)y * g.nx + x;
+        g_cov[t.g][c] += 1;
+        out[c] = seq;
+        const int lx = x - t.x0;
+        const bool dump = ((t.flags & 4) && lx < 2) || ((t.flags & 8) && lx >= W - 2) ||
+                          ((t.flags & 1) && y < t.y0 + 2) || ((t.flags & 2) && y >= t.y1 - 2);
+        if (dump) mid[c] = seq;
+      }
   }
   return hipSuccess;
 }
@@ -173,6 +288,7 @@ hipError_t launch_add_time(int64_t *t, int64_t v, hipStream_t) { check_range(t, 
 #define INST(real) \
   template hipError_t launch_step<real>(const StepArgs<real> &, int, int, int, int, hipStream_t); \
   template hipError_t launch_interior<real>(const StepArgs<real> &, int, int, int, hipStream_t); \
+  template hipError_t launch_fused2<real>(const StepArgs<real> &, int, int, hipStream_t); \
   template hipError_t launch_adjoint<real>(const AdjArgs<real> &, int, int, hipStream_t); \
   template hipError_t launch_adjoint_interior<real>(const AdjArgs<real> &, int, int, hipStream_t); \
   template hipError_t launch_misfit<real>(const real *, const real *, real *, int64_t, double *, hipStream_t); \
