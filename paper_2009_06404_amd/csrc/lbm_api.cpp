@@ -352,13 +352,22 @@ void build_tiles(const lbm_ctx *c, int waves, int rows, bool split, std::vector<
 // fewer halo rows, shorter ones keep the rows in flight compact); narrower
 // tiles where the grid would otherwise give too few workgroups to fill 256
 // compute units.
+// Launch shape by size (measured on MI355X): large contexts take the two-step
+// path, with taller blocks on very tall grids and in FP64 (where the halo
+// rows cost twice the bytes); small ones single steps in smaller tiles.
 lbm_launch default_launch(const lbm_ctx *c) {
   int64_t cells = 0;
-  for (const auto &g : c->grids) cells += (int64_t)g.nx * g.ny;
+  int max_ny = 0;
+  for (const auto &g : c->grids) {
+    cells += (int64_t)g.nx * g.ny;
+    max_ny = std::max(max_ny, g.ny);
+  }
   lbm_launch l{8, c->dtype == LBM_F64 ? 4 : 8, 0, 1, 1, 0, 1, 0};
+  l.fuse_rows = (c->dtype == LBM_F64 || max_ny >= 8192) ? 64 : 20;
   if (cells < 2048 * 2048) {
     l.waves = 4;
     l.rows = 4;
+    l.fuse_rows = 0;
   }
   if (cells < 256 * 2048) {
     l.waves = 1;
