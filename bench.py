@@ -135,14 +135,16 @@ def bench_hbm_scale(torch, w, Solver, steps: int = 200, warmup: int = 20) -> dic
             "launch": launch, "state_finite": bool(ok)}
 
 
-BATCHED_LAUNCH = {"waves": 8, "rows": 8, "graph_chunk": 12, "fuse_rows": 16}
-ADJOINT_LAUNCH = {"waves": 4, "rows": 4}      # 1024-column grids: narrower, shorter tiles
+BATCHED_LAUNCH = {"waves": 2, "rows": 8, "fuse_rows": 64}
+# 1024-column grids: narrower, shorter tiles for the adjoint and the recompute;
+# the recorded forward runs on the two-step path
+ADJOINT_LAUNCH = {"waves": 4, "rows": 4, "fuse_rows": 32}
 
 
 def bench_batched(torch, w, Solver, plain_glups: float, steps: int = 60,
                   warmup: int = 10, launch=None) -> dict:
-    """512 grids of uneven side (256..2048) in one context, one launch per
-    step over the flat tile list, HIP graphs of 10 steps."""
+    """512 grids of uneven side (256..2048) in one context, one launch of each
+    kernel per step (or pair of steps) over the flat tile lists."""
     probs = w.batched_shots()
     t0 = time.perf_counter()
     s = Solver(probs, dtype="f32", trace_steps=1, launch=dict(launch or BATCHED_LAUNCH))

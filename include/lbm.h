@@ -117,14 +117,17 @@ typedef struct {
                          library, concurrently with the interior kernel, joined
                          back to the context's stream at the end of the step
                          (default); 0: one kernel after the other */
-  int32_t fuse_rows;  /* 0: one kernel pass per step (default). 4..248: steps run
-                         in pairs; blocks of 256 columns by fuse_rows rows that
-                         hold no boundary, receiver or source take two steps in
-                         one pass (the intermediate state stays on chip, apart
-                         from the block's border, kept in a third buffer for the
-                         neighbouring blocks); the other cells take the two steps
-                         one at a time. Results are bitwise those of single
-                         steps. graph_chunk is rounded up to a multiple of 4. */
+  int32_t fuse_rows;  /* 0: one kernel pass per step. 4..248: steps run in
+                         pairs; blocks of 64 x max(waves, 2) columns by up to
+                         fuse_rows rows that hold no boundary, receiver or
+                         source take two steps in one pass (the intermediate
+                         state stays on chip, apart from the block's border,
+                         kept in a third buffer for the neighbouring blocks);
+                         the other cells take the two steps one at a time.
+                         Results are bitwise those of single steps. The
+                         two-step path launches directly (graph_chunk is not
+                         used). The default is set by size: the two-step path
+                         on contexts of 2048^2 cells and more. */
 } lbm_launch;
 
 /* Bytes of device workspace lbm_init needs for nbatch grids of the given
@@ -213,8 +216,8 @@ int lbm_check_finite(lbm_ctx *ctx);
 
 /* Launch configuration in use, and a way to set it (waves in {1,2,4,8},
  * rows >= 1, graph_chunk >= 0, prefetch in {1,2} (0 means 1), split, pair and
- * overlap in {0,1}, fuse_rows 0 or in [4, 248]). graph_chunk is rounded up to keep
- * the ping-pong parity (to even, or to a multiple of 4 with fuse_rows > 0).
+ * overlap in {0,1}, fuse_rows 0 or in [4, 248]). An odd graph_chunk is
+ * rounded up to keep the ping-pong parity.
  * Returns LBM_OK or LBM_E_INVALID (the configuration in use is kept). */
 int lbm_get_launch(const lbm_ctx *ctx, lbm_launch *out);
 int lbm_set_launch(lbm_ctx *ctx, const lbm_launch *cfg);

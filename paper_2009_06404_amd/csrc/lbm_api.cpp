@@ -259,14 +259,6 @@ std::vector<TileDev> order_for_dies(const std::vector<TileDev> &logical) {
   return phys;
 }
 
-double min_image_host(double d, int n, bool periodic) {
-  if (periodic) {
-    if (d > 0.5 * n) d -= n;
-    else if (d < -0.5 * n) d += n;
-  }
-  return d;
-}
-
 // Distance from p to the nearest of the integer points lo..hi of an axis of
 // n points, with the minimum image on a periodic axis.
 double dist_to_range(double p, int lo, int hi, int n, bool periodic) {
@@ -363,7 +355,11 @@ lbm_launch default_launch(const lbm_ctx *c) {
     max_ny = std::max(max_ny, g.ny);
   }
   lbm_launch l{8, c->dtype == LBM_F64 ? 4 : 8, 0, 1, 1, 0, 1, 0};
-  l.fuse_rows = (c->dtype == LBM_F64 || max_ny >= 8192) ? 64 : 20;
+  // two-step blocks: 128 columns (more workgroups per CU hide the row loop's
+  // barriers), 256 on very tall grids; taller blocks where there are enough
+  // of them to fill the chip, and in FP64
+  l.waves = max_ny >= 8192 ? 4 : 2;
+  l.fuse_rows = (c->dtype == LBM_F32 && cells >= (int64_t)8192 * 8192) ? 64 : 32;
   if (cells < 2048 * 2048) {
     l.waves = 4;
     l.rows = 4;
@@ -495,39 +491,102 @@ int commit(lbm_ctx *c) {
   return rebuild_tiles(c);   // which tiles are interior depends on sources and receivers
 }
 
-// Two-step path (launch.fuse_rows > 0): the grid is cut into blocks of
-// kFusedW columns x fuse_rows rows. A block runs in the two-step kernel when
-// it is a full block and, over the reach of two steps (4 columns and 3 rows
-// around it for the step-t collisions, one more for their pulls), it meets no
-// wall, no y-wrap, no source disk, and no receiver lies in its own rows.
-// Every other block is advanced step by step by the general kernel in
-// one-wavefront tiles of two rows. A fused block flags the sides next to
-// non-fused blocks: the general kernel's second step reads the intermediate
+// Two-step path (launch.fuse_rows > 0). Each grid is cut into row segments
+// and column segments:
+//  * rows: a row may be an own row of a two-step block when the block's reach
+//    over two steps (step t+1 needs f*(t) 2 rows out, that needs rho(t) 3
+//    rows out, pulled from 4 rows out) stays inside the grid without the
+//    y-wrap and pulls across no wall link or rigid-row link, and no receiver
+//    lies in it. Runs of such
+//    rows are split into blocks of near-equal height <= fuse_rows (at least
+//    2, the depth of the border the general kernel reads back); the other
+//    rows form general segments;
+//  * columns: blocks of 64 * fused_waves columns starting at a multiple of 64 (the
+//    general kernel's tile width), the last one narrower (a multiple of 64,
+//    or reaching nx on a periodic axis); without x-wrap the block's reach
+//    (4 columns and one more for the pulls) must stay off the side walls.
+// A block of an allowed row segment and an allowed column segment runs in
+// the two-step kernel unless a source disk reaches into its reach; every
+// other cell is advanced step by step by the general kernel in
+// one-wavefront tiles of two rows. A two-step block flags the sides next to
+// general cells: the general kernel's second step reads the intermediate
 // state of the two rows or columns there.
-constexpr int kFusedWaves = 4, kFusedW = 64 * kFusedWaves;
+// Two-step blocks are 64 * fused_waves columns wide: the launch's waves
+// (2, 4 or 8; 1 counts as 2).
+int fused_waves(const lbm_ctx *c) { return std::max(2, (int)c->launch.waves); }
 
-bool block_is_fused(const lbm_ctx *c, int g, int x0, int y0, int y1) {
-  const lbm_grid &G = c->grids[g];
-  const lbm_bc &b = c->bc[g];
-  const int nx = G.nx, ny = G.ny, rr = b.rigid_row;
-  if (x0 + kFusedW > nx) return false;
-  if (y0 - 4 < 0 || y1 + 3 > ny - 1) return false;
-  const bool pbt = b.edge[LBM_EDGE_TOP] == LBM_PERIODIC;
-  const bool px = b.edge[LBM_EDGE_LEFT] == LBM_PERIODIC;
-  // rows whose pulls cross a wall: y0 - 3 .. y1 + 2 must hold none
-  if (!pbt && (y0 - 3 <= 0 || y1 + 2 >= ny - 1)) return false;
-  if (rr > 0 && rr - 1 <= y1 + 2 && rr >= y0 - 3) return false;
-  if (!px && (x0 - 5 < 0 || x0 + kFusedW + 4 > nx - 1)) return false;
+struct Seg {
+  int lo, hi;    // [lo, hi)
+  bool ok;       // may hold two-step blocks
+};
+
+std::vector<Seg> fused_row_segments(const lbm_ctx *c, int g, int rows) {
+  const int ny = c->grids[g].ny, rr = c->bc[g].rigid_row;
+  std::vector<char> allowed((size_t)ny, 0);
+  std::vector<char> has_rec((size_t)ny, 0);
+  const std::vector<int32_t> &xy = c->recs[g].xy;
+  for (size_t r = 1; r < xy.size(); r += 2) has_rec[(size_t)xy[r]] = 1;
+  for (int y = 0; y < ny; ++y) {
+    // the first step pulls rows y-3 .. y+3 (reading y-4 .. y+4): inside the
+    // grid without the wrap, and off rows 0 and ny-1 where walls cut links
+    bool ok = y - 4 >= 0 && y + 4 <= ny - 1;
+    // rigid-row links cross between rows rr-1 and rr: no pulled row may be
+    // either of them
+    if (rr > 0 && y - 3 <= rr && y + 3 >= rr - 1) ok = false;
+    if (has_rec[(size_t)y]) ok = false;
+    allowed[(size_t)y] = ok;
+  }
+  std::vector<Seg> segs;
+  for (int y = 0; y < ny;) {
+    int e = y;
+    while (e < ny && allowed[(size_t)e] == allowed[(size_t)y]) ++e;
+    const int len = e - y;
+    if (!allowed[(size_t)y] || len < 2) {
+      if (!segs.empty() && !segs.back().ok) segs.back().hi = e;
+      else segs.push_back(Seg{y, e, false});
+    } else {
+      const int nb = (len + rows - 1) / rows;
+      for (int k = 0; k < nb; ++k)
+        segs.push_back(Seg{y + (int)((int64_t)len * k / nb), y + (int)((int64_t)len * (k + 1) / nb), true});
+    }
+    y = e;
+  }
+  return segs;
+}
+
+std::vector<Seg> fused_col_segments(const lbm_ctx *c, int g) {
+  const int nx = c->grids[g].nx, bw = 64 * fused_waves(c);
+  const bool px = c->bc[g].edge[LBM_EDGE_LEFT] == LBM_PERIODIC;
+  // allowed columns [a, b): with x-wrap all; without, x-5 >= 0 and x+4 <= nx-1
+  // for every own column x
+  int a = px ? 0 : 64;                  // first multiple of 64 >= 5
+  const int b = px ? nx : nx - 5;
+  std::vector<Seg> segs;
+  if (a > 0) segs.push_back(Seg{0, std::min(a, nx), false});
+  for (int x = a; x < nx;) {
+    int w = std::min(bw, b - x);
+    if (!(px && x + w == nx)) w = w / 64 * 64;   // keep general tiles 64-aligned
+    if (w < 64) {
+      segs.push_back(Seg{x, nx, false});
+      break;
+    }
+    segs.push_back(Seg{x, x + w, true});
+    x += w;
+  }
+  return segs;
+}
+
+bool source_reaches(const lbm_ctx *c, int g, const Seg &cs, const Seg &rs) {
+  const int nx = c->grids[g].nx, ny = c->grids[g].ny;
+  const bool px = c->bc[g].edge[LBM_EDGE_LEFT] == LBM_PERIODIC;
+  const bool py = c->bc[g].edge[LBM_EDGE_TOP] == LBM_PERIODIC;
   for (const lbm_source &q : c->sources[g]) {
     const double cut = 81.0 * q.sigma * q.sigma;
-    const double dx = dist_to_range(q.x, x0 - 4, x0 + kFusedW + 3, nx, px);
-    const double dy = dist_to_range(q.y, y0 - 3, y1 + 2, ny, pbt);
-    if (dx * dx + dy * dy <= cut) return false;
+    const double dx = dist_to_range(q.x, cs.lo - 4, cs.hi + 3, nx, px);
+    const double dy = dist_to_range(q.y, rs.lo - 3, rs.hi + 2, ny, py);
+    if (dx * dx + dy * dy <= cut) return true;
   }
-  const std::vector<int32_t> &xy = c->recs[g].xy;
-  for (size_t r = 1; r < xy.size(); r += 2)
-    if (xy[r] >= y0 && xy[r] < y1) return false;
-  return true;
+  return false;
 }
 
 void build_fused_tiles(const lbm_ctx *c, int rows, std::vector<FusedTileDev> &fused,
@@ -536,24 +595,23 @@ void build_fused_tiles(const lbm_ctx *c, int rows, std::vector<FusedTileDev> &fu
   std::vector<TileDev> lg;
   fused_cells = 0;
   for (int g = 0; g < c->nbatch; ++g) {
-    const int nx = c->grids[g].nx, ny = c->grids[g].ny;
-    const int bx = (nx + kFusedW - 1) / kFusedW, by = (ny + rows - 1) / rows;
+    const std::vector<Seg> R = fused_row_segments(c, g, rows), C = fused_col_segments(c, g);
+    const int nr = (int)R.size(), nc = (int)C.size();
     const bool px = c->bc[g].edge[LBM_EDGE_LEFT] == LBM_PERIODIC;
     const bool py = c->bc[g].edge[LBM_EDGE_TOP] == LBM_PERIODIC;
-    std::vector<char> isf((size_t)bx * by, 0);
-    for (int j = 0; j < by; ++j)
-      for (int i = 0; i < bx; ++i)
-        isf[(size_t)j * bx + i] =
-            block_is_fused(c, g, i * kFusedW, j * rows, std::min(j * rows + rows, ny));
-    auto fused_at = [&](int i, int j) -> int {   // 1 fused, 0 not, -1 outside the grid
-      if (i < 0 || i >= bx) { if (!px) return -1; i = (i + bx) % bx; }
-      if (j < 0 || j >= by) { if (!py) return -1; j = (j + by) % by; }
-      return isf[(size_t)j * bx + i];
+    std::vector<char> isf((size_t)nr * nc, 0);
+    for (int j = 0; j < nr; ++j)
+      for (int i = 0; i < nc; ++i)
+        isf[(size_t)j * nc + i] = R[j].ok && C[i].ok && !source_reaches(c, g, C[i], R[j]);
+    auto fused_at = [&](int i, int j) -> int {   // 1 two-step, 0 general, -1 outside the grid
+      if (i < 0 || i >= nc) { if (!px) return -1; i = (i + nc) % nc; }
+      if (j < 0 || j >= nr) { if (!py) return -1; j = (j + nr) % nr; }
+      return isf[(size_t)j * nc + i];
     };
-    for (int j = 0; j < by; ++j)
-      for (int i = 0; i < bx; ++i) {
-        const int x0 = i * kFusedW, y0 = j * rows, y1 = std::min(y0 + rows, ny);
-        if (isf[(size_t)j * bx + i]) {
+    for (int j = 0; j < nr; ++j)
+      for (int i = 0; i < nc; ++i) {
+        const Seg &rs = R[j], &cs = C[i];
+        if (isf[(size_t)j * nc + i]) {
           int flags = 0;
           for (int dj = -1; dj <= 1; ++dj)
             for (int di = -1; di <= 1; ++di) {
@@ -563,18 +621,18 @@ void build_fused_tiles(const lbm_ctx *c, int rows, std::vector<FusedTileDev> &fu
               if (di < 0) flags |= 4;
               if (di > 0) flags |= 8;
             }
-          lf.push_back(FusedTileDev{g, x0, y0, y1, flags});
-          fused_cells += (int64_t)kFusedW * (y1 - y0);
+          lf.push_back(FusedTileDev{g, cs.lo, cs.hi, rs.lo, rs.hi, flags});
+          fused_cells += (int64_t)(cs.hi - cs.lo) * (rs.hi - rs.lo);
         } else {
-          for (int ys = y0; ys < y1; ys += kSubRows)
-            for (int xs = x0; xs < std::min(x0 + kFusedW, nx); xs += 64)
-              lg.push_back(TileDev{g, xs, ys, std::min(ys + kSubRows, y1)});
+          for (int ys = rs.lo; ys < rs.hi; ys += kSubRows)
+            for (int xs = cs.lo; xs < cs.hi; xs += 64)
+              lg.push_back(TileDev{g, xs, ys, std::min(ys + kSubRows, rs.hi)});
         }
       }
   }
   // die ordering as for the single-step lists
   const int64_t T = (int64_t)lf.size(), per = (T + kXcds - 1) / kXcds;
-  fused.assign((size_t)(per * kXcds), FusedTileDev{-1, 0, 0, 0, 0});
+  fused.assign((size_t)(per * kXcds), FusedTileDev{-1, 0, 0, 0, 0, 0});
   for (int64_t b = 0; b < per * kXcds; ++b) {
     const int64_t jx = b % kXcds, ix = b / kXcds, l = jx * per + ix;
     if (ix < per && l < T) fused[(size_t)b] = lf[(size_t)l];
@@ -683,7 +741,7 @@ hipError_t launch_two_steps(lbm_ctx *c, StepArgs<real> a, hipStream_t s) {
   hipError_t e = launch_pair(
       c, s, c->nftiles > 0, c->ngtiles2 > 0,
       [&](hipStream_t q) { return launch_step<real>(g1, 1, pf, c->ngtiles2, kModeStep, q); },
-      [&](hipStream_t q) { return launch_fused2<real>(f2, kFusedWaves, c->nftiles, q); });
+      [&](hipStream_t q) { return launch_fused2<real>(f2, fused_waves(c), c->nftiles, q); });
   if (e == hipSuccess) e = launch_step<real>(g2, 1, pf, c->ngtiles2, kModeStep, s);
   return e;
 }
@@ -778,7 +836,7 @@ int step_timed(lbm_ctx *c, int64_t n, lbm_kernel_times *out) {
       g2.t = a.t + 1;
       if (c->ngtiles2 > 0)
         timed(1, [&] { return launch_step<real>(g1, 1, pf, c->ngtiles2, kModeStep, c->stream); });
-      timed(2, [&] { return launch_fused2<real>(f2, kFusedWaves, c->nftiles, c->stream); });
+      timed(2, [&] { return launch_fused2<real>(f2, fused_waves(c), c->nftiles, c->stream); });
       if (c->ngtiles2 > 0)
         timed(1, [&] { return launch_step<real>(g2, 1, pf, c->ngtiles2, kModeStep, c->stream); });
       if (e == hipSuccess) {
@@ -834,13 +892,11 @@ int build_graphs(lbm_ctx *c, int chunk) {
       return fail(LBM_E_DEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
     }
     int buf = parity;
-    const bool fused = use_fused(c);
-    for (int k = 0; k < chunk; k += fused ? 2 : 1) {
+    for (int k = 0; k < chunk; ++k) {
       StepArgs<real> a = make_args<real>(c, buf);
       a.t = k;
       a.t_dev = c->d_time.p;
-      if (fused) launch_two_steps<real>(c, a, cs);
-      else launch_one_step<real>(c, a, cs);
+      launch_one_step<real>(c, a, cs);
       buf ^= 1;
     }
     launch_add_time(c->d_time.p, chunk, cs);
@@ -862,8 +918,11 @@ template <typename real>
 int step_impl(lbm_ctx *c, int64_t n) {
   int rc = commit(c);
   if (rc) return rc;
+  // Graphs serve the single-step path. The two-step path launches directly:
+  // on MI355X the gaps between its graph nodes (three kernels and a fork and
+  // join per pair) measured longer than direct dispatch.
   const int chunk = c->launch.graph_chunk;
-  if (chunk > 0 && n >= chunk) {
+  if (chunk > 0 && n >= chunk && !use_fused(c)) {
     if (c->gchunk != chunk) {
       rc = build_graphs<real>(c, chunk);
       if (rc) return rc;
@@ -871,9 +930,7 @@ int step_impl(lbm_ctx *c, int64_t n) {
     HIP_TRY(launch_set_time(c->d_time.p, c->t, c->stream));
     while (n >= chunk) {
       HIP_TRY(hipGraphLaunch(c->gexec[c->cur], c->stream));
-      // the chunk flips the buffers an even number of times (an even number
-      // of single steps, or a multiple of four steps in pairs)
-      c->t += chunk;
+      c->t += chunk;   // chunk is even: the state returns to the same buffer
       n -= chunk;
     }
   }
@@ -1430,10 +1487,7 @@ int lbm_set_launch(lbm_ctx *c, const lbm_launch *cfg) {
   c->launch = *cfg;
   if (c->launch.prefetch == 0) c->launch.prefetch = 1;
   if (regraph) drop_graphs(c);
-  // keep the buffer parity across a captured chunk: an even number of single
-  // steps, or a multiple of four steps on the two-step path
-  const int q = c->launch.fuse_rows > 0 ? 4 : 2;
-  if (c->launch.graph_chunk % q) c->launch.graph_chunk += q - c->launch.graph_chunk % q;
+  if (c->launch.graph_chunk % 2) c->launch.graph_chunk += 1;   // keep buffer parity
   if (retile) return rebuild_tiles(c);
   if (c->gchunk != c->launch.graph_chunk) drop_graphs(c);
   return LBM_OK;

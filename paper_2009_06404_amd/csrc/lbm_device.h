@@ -14,14 +14,26 @@ constexpr int CX[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 constexpr int CY[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 
-// v / 36 for the integer-coefficient combinations: one multiply by the
-// rounded reciprocal and one Newton correction with the exact residual.
+// v / 36 for the integer-coefficient combinations: 1/36 split into a
+// rounded head and the rounded remainder, hi + lo = 1/36 to about twice the
+// working precision, and v*hi + v*lo formed with a single rounding (the
+// small v*lo is added inside the FMA). The quotient is the correctly
+// rounded one except in rare near-ties, so it carries no systematic bias
+// (a bare multiply by the rounded 1/36 would scale every equilibrium term
+// by the same 1 + delta).
+template <typename real>
+struct Inv36;
+template <>
+struct Inv36<float> {
+  static constexpr float hi = 0x1.c71c72p-6f, lo = -0x1.c71c72p-33f;
+};
+template <>
+struct Inv36<double> {
+  static constexpr double hi = 0x1.c71c71c71c71cp-6, lo = 0x1.c71c71c71c71cp-60;
+};
 template <typename real>
 __device__ __forceinline__ real div36(real v) {
-  const real r = real(1) / real(36);
-  const real q = v * r;
-  const real e = fma(-q, real(36), v);
-  return fma(e, r, q);
+  return fma(v, Inv36<real>::hi, v * Inv36<real>::lo);
 }
 
 // Row classification for the pull of row y (uniform across the workgroup).

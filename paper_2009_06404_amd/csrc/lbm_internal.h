@@ -54,13 +54,13 @@ struct TileDev {
 // Largest block height of the two-step kernel (its per-row table in LDS).
 constexpr int kFusedMaxRows = 248;
 
-// A tile of the two-step kernel: grid g, columns [x0, x0 + 64*NW), rows
-// [y0, y1) with y1 - y0 <= kFusedMaxRows; flags: bit 0/1/2/3 = also write
-// the intermediate state of the tile's two top rows / bottom rows / left
-// columns / right columns (next to cells the general kernel advances step by
-// step).
+// A tile of the two-step kernel: grid g, columns [x0, x1) with
+// 0 < x1 - x0 <= 64*NW, rows [y0, y1) with y1 - y0 <= kFusedMaxRows; flags:
+// bit 0/1/2/3 = also write the intermediate state of the tile's two top rows
+// / bottom rows / left columns / right columns (next to cells the general
+// kernel advances step by step).
 struct FusedTileDev {
-  int32_t g, x0, y0, y1, flags;
+  int32_t g, x0, x1, y0, y1, flags;
 };
 
 template <typename real>

@@ -32,7 +32,7 @@
 //
 // Arithmetic: with b^2 = 1/3 the equilibrium and forcing populations times 36
 // have small integer coefficients in (rho, j, P, S); they are formed exactly
-// that way and divided by 36 once, with an FMA-corrected reciprocal. Writing
+// that way and divided by 36 once, with a two-term reciprocal (div36). Writing
 // them with the rounded constants 1/3, 1/9, 1/36 instead biases every step in
 // the same direction (the collision invariants drift by ~1e-8 per step in
 // FP32), which grows linearly with the step count.
@@ -704,42 +704,61 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t range_rsrc(const void *base, u
 
 // Two time steps of an interior tile in one pass (temporal blocking). The
 // workgroup marches down the tile's rows with a four-stage pipeline:
-//   A (row r):   pull f(t) from f*(t-1) in HBM, rho(t) into an LDS ring;
-//   B (row r-1): density gradient and collision of step t -> f*(t) into an
-//                LDS ring of three rows (and to HBM for flagged border cells);
-//   C (row r-2): pull f(t+1) from the f*(t) ring, rho(t+1) into an LDS ring;
+//   A (row r):   pull f(t) from f*(t-1) in HBM (row r+1 already in flight),
+//                rho(t) into an LDS ring;
+//   B (row r-1): density gradient and collision of step t -> f*(t) (and to
+//                HBM for flagged border cells);
+//   C (row r-2): pull f(t+1) from f*(t) of rows r-3 .. r-1, rho(t+1) into an
+//                LDS ring;
 //   D (row r-3): density gradient and collision of step t+1 -> f*(t+1) to HBM.
-// Stage B runs on the tile's columns plus three halo columns on each side
-// and stage C on two, so stage D has every neighbour it needs; the four halo
-// columns per side are handled by an extra wavefront (the output wavefronts
-// keep aligned accesses). Rows: output rows [y0, y1) need f*(t) on rows
-// y0-2 .. y1+1 and f*(t-1) on rows y0-4 .. y1+3. The per-cell arithmetic is
-// the single-step kernels' (same operations in the same order), so two
-// steps here equal two single steps bit for bit. Tiles are clear of walls,
-// the y-wrap, source disks and receivers over that whole reach.
+// Of f*(t), only the six populations that stage C takes from a neighbouring
+// column go through LDS, each in a ring as deep as the rows it must wait
+// (c_y = -1: this row, c_y = 0: one more, c_y = +1: two more); the three
+// with c_x = 0 stay in the lane's registers. Stage B runs on the tile's
+// columns plus three halo columns on each side and stage C on two, so stage
+// D has every neighbour it needs; the four left halo columns (and the right
+// ones of a full-width tile) are handled by an extra wavefront, so the
+// output wavefronts keep aligned accesses. Rows: output rows [y0, y1) need
+// f*(t) on rows y0-2 .. y1+1 and f*(t-1) on rows y0-4 .. y1+3. The row loop
+// is unrolled six times, the period of its register rotations, so that
+// rotating the carried rows costs no moves; the first iterations before
+// row y0-3 only start the loads. The per-cell arithmetic is the single-step
+// kernels' (same operations in the same order), so two steps here equal two
+// single steps bit for bit. Tiles are clear of walls, the y-wrap, source
+// disks and receivers over that whole reach.
+template <int N>
+struct Phase {
+  static constexpr int value = N;
+};
+
 template <typename real, int NW>
 __global__ __launch_bounds__(64 * NW + 64) void fused2_kernel(StepArgs<real> a) {
   constexpr int W = 64 * NW;
   constexpr int LW = W + 8;                 // LDS columns: tile plus 4 each side
   constexpr int RT = kFusedMaxRows + 8;     // per-row table: rows y0-4 .. y1+3
-  __shared__ real sA[2][LW];
-  __shared__ real sS1[3][9][LW];
-  __shared__ real sC[2][LW];
+  __shared__ real sA[2][LW];                // rho(t) of rows r-1, r
+  __shared__ real sC[2][LW];                // rho(t+1) of rows r-3, r-2
+  __shared__ real s78[2][LW];               // f*(t) populations 7, 8 of row r-1
+  __shared__ real s13[2][2][LW];            // populations 1, 3 of rows r-2, r-1
+  __shared__ real s56[3][2][LW];            // populations 5, 6 of rows r-3 .. r-1
   __shared__ real sRowA[RT], sRowI[RT], sRowK[RT];
 
   const FusedTileDev tile = a.ftiles[blockIdx.x];
   if (tile.g < 0) return;
   const GridDev g = uniform_lookup_fields(a.grids[tile.g]);
   const int pitch = g.pitch, nx = g.nx;
+  const int w = tile.x1 - tile.x0;          // 0 < w <= W
   const int tid = threadIdx.x;
-  const bool outlane = tid < W;
   const int hl = tid - W;
-  // LDS column lc in [0, LW): 0..3 left halo, 4..W+3 the tile, W+4..W+7 right halo
+  // LDS column lc of column x0 - 4 + lc: 0..3 the left halo (lanes of the
+  // extra wavefront), 4..w+3 the tile, w+4..w+7 the right halo (the next
+  // output lanes, or the extra wavefront's lanes 4..7 for a full tile)
   int lc = -1;
-  if (outlane) lc = tid + 4;
+  if (tid < W) lc = tid + 4;
   else if (hl < 4) lc = hl;
   else if (hl < 8) lc = W + hl;
-  const bool live = lc >= 0;
+  const bool live = lc >= 0 && lc < w + 8;
+  const bool outlane = tid < w;
   auto wrapx = [&](int c) { return c < 0 ? c + nx : (c >= nx ? c - nx : c); };
   const int col = live ? wrapx(tile.x0 - 4 + lc) : 0;
   const uint32_t esz = sizeof(real);
@@ -776,38 +795,51 @@ __global__ __launch_bounds__(64 * NW + 64) void fused2_kernel(StepArgs<real> a) 
   const bool kcells = g.kmode == kKappaCells;
   const real kscalar = (real)g.kscalar;
   const real *kcol = a.kappa_cells + g.k_off + col;
-  const bool inB = lc >= 1 && lc <= W + 6, inC = lc >= 2 && lc <= W + 5;
+  const bool inB = lc >= 1 && lc <= w + 6, inC = lc >= 2 && lc <= w + 5;
   const int dump = tile.flags;
-  const bool dump_col = (outlane && (((dump & 4) && lc < 6) || ((dump & 8) && lc >= W + 2)));
+  const bool dump_col = (outlane && (((dump & 4) && lc < 6) || ((dump & 8) && lc >= w + 2)));
   __syncthreads();
 
-  // Registers carried down the rows: fa/fb the pulled f(t) of rows r-1 and r,
-  // fc row r+1 (in flight while row r is worked on), gc/gn the pulled
-  // f(t+1) of rows r-3 and r-2; for cell-wise moduli, the cell's modulus of
-  // rows r+1 (in flight), r and r-1 .. r-3 (stage B takes row r-1's, stage D
-  // two rows later the same).
-  real fa[9], fb[9], fc[9], gc[9], gn[9];
+  // Registers carried down the rows, each set rotated with its period:
+  // F the pulled f(t) of rows r-1, r and r+1 (in flight), G the pulled
+  // f(t+1) of rows r-3 and r-2, RA / RC rho(t) / rho(t+1) of three rows,
+  // D0 / E2 populations 0 and 2 of f*(t) waiting one and two rows for stage
+  // C; for cell-wise moduli, the modulus of rows r+1 (in flight) .. r-3.
+  real F[3][9], G[2][9], D0[2], E2[3], RA[3], RC[3];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) { fa[i] = fb[i] = fc[i] = gc[i] = gn[i] = real(0); }
-  real rA_m = real(0), rA_c = real(0), rC_m = real(0), rC_c = real(0);
+  for (int i = 0; i < 9; ++i) { F[0][i] = F[1][i] = F[2][i] = G[0][i] = G[1][i] = real(0); }
+  D0[0] = D0[1] = E2[0] = E2[1] = E2[2] = real(0);
+  RA[0] = RA[1] = RA[2] = RC[0] = RC[1] = RC[2] = real(0);
   real kq = real(0), k1 = real(0), k2 = real(0), k3 = real(0);
-  if (live) pull_fast(rin, ybase, y0 - 3, rowb, qb, o0, ol, orr, fb);
-  if (live && kcells) kq = kcol[(int64_t)(y0 - 3) * pitch];
 
-  for (int r = y0 - 3; r <= y1 + 2; ++r) {
+  const int rlast = y1 + 2;
+  // iterations from y0-4 (which only starts the loads of row y0-3) to rlast,
+  // rounded up to whole unrolled rounds by starting earlier
+  const int r0 = rlast + 1 - (rlast - (y0 - 4) + 1 + 5) / 6 * 6;
+
+  auto iter = [&](const int r, auto ph) {
+    constexpr int P = decltype(ph)::value;
+    real(&fa)[9] = F[P % 3];
+    real(&fb)[9] = F[(P + 1) % 3];
+    real(&fc)[9] = F[(P + 2) % 3];
+    real(&gc)[9] = G[P % 2];
+    real(&gn)[9] = G[(P + 1) % 2];
+    real &rA_n = RA[P % 3], &rA_c = RA[(P + 2) % 3], &rA_m = RA[(P + 1) % 3];
+    real &rC_n = RC[P % 3], &rC_c = RC[(P + 2) % 3], &rC_m = RC[(P + 1) % 3];
     real kn = real(0);
-    if (live && r < y1 + 2) {
+    if (live && r + 1 >= y0 - 3 && r + 1 <= rlast) {
       pull_fast(rin, ybase, r + 1, rowb, qb, o0, ol, orr, fc);
       if (kcells) kn = kcol[(int64_t)(r + 1) * pitch];
     }
     // Stage A: row r of step t.
-    real rA_n = real(0);
-    if (live) {
+    rA_n = real(0);
+    if (live && r >= y0 - 3) {
       rA_n = sum9(fb);
       sA[r & 1][lc] = rA_n;
     }
     // Stage B: row r-1 of step t (needs rho(t) of rows r-2 .. r).
     const int rb = r - 1;
+    real p0 = real(0), p2 = real(0), p4 = real(0);
     if (rb >= y0 - 2 && inB) {
       const real dx = real(0.5) * (sA[rb & 1][lc + 1] - sA[rb & 1][lc - 1]);
       const real dy = real(0.5) * (rA_n - rA_m);
@@ -816,9 +848,15 @@ __global__ __launch_bounds__(64 * NW + 64) void fused2_kernel(StepArgs<real> a) 
       const CellState<real> cs = cell_state(fa, rA_c, kap * dx, kap * dy, A, inv);
       real s1[9];
       collide(fa, cs, omega, cforce, s1);
-      const int slot = (rb + 3) % 3;
-#pragma unroll
-      for (int i = 0; i < 9; ++i) sS1[slot][i][lc] = s1[i];
+      s78[0][lc] = s1[7];
+      s78[1][lc] = s1[8];
+      s13[rb & 1][0][lc] = s1[1];
+      s13[rb & 1][1][lc] = s1[3];
+      s56[rb % 3][0][lc] = s1[5];
+      s56[rb % 3][1][lc] = s1[6];
+      p0 = s1[0];
+      p2 = s1[2];
+      p4 = s1[4];
       if (dump && outlane && rb >= y0 && rb < y1 &&
           (dump_col || ((dump & 1) && rb < y0 + 2) || ((dump & 2) && rb >= y1 - 2))) {
         const uint32_t rs = (uint32_t)(rb - ybase) * rowb;
@@ -827,20 +865,20 @@ __global__ __launch_bounds__(64 * NW + 64) void fused2_kernel(StepArgs<real> a) 
       }
     }
     __syncthreads();
-    // Stage C: row r-2 of step t+1 (pull from the f*(t) ring).
+    // Stage C: row r-2 of step t+1, pulled from f*(t) of rows r-3 .. r-1.
     const int rc = r - 2;
-    real rC_n = real(0);
+    rC_n = real(0);
     if (rc >= y0 - 1 && inC) {
-      const int sm = (rc + 2) % 3, s0 = (rc + 3) % 3, sp = (rc + 4) % 3;   // rows rc-1, rc, rc+1
-      gn[0] = sS1[s0][0][lc];
-      gn[1] = sS1[s0][1][lc - 1];
-      gn[2] = sS1[sm][2][lc];
-      gn[3] = sS1[s0][3][lc + 1];
-      gn[4] = sS1[sp][4][lc];
-      gn[5] = sS1[sm][5][lc - 1];
-      gn[6] = sS1[sm][6][lc + 1];
-      gn[7] = sS1[sp][7][lc + 1];
-      gn[8] = sS1[sp][8][lc - 1];
+      const int s13i = rc & 1, s56i = (rc + 2) % 3;   // rows rc and rc-1
+      gn[0] = D0[P % 2];                            // row rc, this column
+      gn[1] = s13[s13i][0][lc - 1];
+      gn[2] = E2[P % 3];                            // row rc-1, this column
+      gn[3] = s13[s13i][1][lc + 1];
+      gn[4] = p4;                                   // row rc+1, this column
+      gn[5] = s56[s56i][0][lc - 1];
+      gn[6] = s56[s56i][1][lc + 1];
+      gn[7] = s78[0][lc + 1];
+      gn[8] = s78[1][lc - 1];
       rC_n = sum9(gn);
       sC[rc & 1][lc] = rC_n;
     }
@@ -859,11 +897,18 @@ __global__ __launch_bounds__(64 * NW + 64) void fused2_kernel(StepArgs<real> a) 
       for (int i = 0; i < 9; ++i) Buf<real>::store_nt(s2[i], rout, o0, rs + i * qb);
     }
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 9; ++i) { fa[i] = fb[i]; fb[i] = fc[i]; gc[i] = gn[i]; }
-    rA_m = rA_c; rA_c = rA_n;
-    rC_m = rC_c; rC_c = rC_n;
+    D0[(P + 1) % 2] = p0;
+    E2[(P + 2) % 3] = p2;
     k3 = k2; k2 = k1; k1 = kq; kq = kn;
+  };
+
+  for (int r = r0; r <= rlast; r += 6) {
+    iter(r, Phase<0>{});
+    iter(r + 1, Phase<1>{});
+    iter(r + 2, Phase<2>{});
+    iter(r + 3, Phase<3>{});
+    iter(r + 4, Phase<4>{});
+    iter(r + 5, Phase<5>{});
   }
 }
 
@@ -945,6 +990,7 @@ hipError_t launch_fused2(const StepArgs<real> &a, int waves, int ntiles, hipStre
   dim3 grid(ntiles), block(64 * waves + 64);
   if (waves == 2) hipLaunchKernelGGL((fused2_kernel<real, 2>), grid, block, 0, stream, a);
   else if (waves == 4) hipLaunchKernelGGL((fused2_kernel<real, 4>), grid, block, 0, stream, a);
+  else if (waves == 8) hipLaunchKernelGGL((fused2_kernel<real, 8>), grid, block, 0, stream, a);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

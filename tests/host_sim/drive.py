@@ -153,8 +153,8 @@ for name, bc, rr, nx, ny in FUSED:
     p = problem(bc, rr, nx, ny, 5, sources=[Source(nx * 0.7, ny * 0.5, 2.0, 0.3, 0.9, 1.0, 12.0, 16.0)],
                 receivers=[(x, 0) for x in range(0, nx, 5)] + [(x, 77) for x in range(3, nx, 11)])
     for fr in (4, 8, 13):
-        for extra in (dict(), dict(overlap=0), dict(graph_chunk=6)):
-            pairs, kt = run_forward([p], 0, dict(waves=4, rows=8, fuse_rows=fr, **extra))
+        for extra in (dict(), dict(overlap=0), dict(graph_chunk=6), dict(waves=8), dict(waves=1)):
+            pairs, kt = run_forward([p], 0, dict(dict(waves=4, rows=8, fuse_rows=fr), **extra))
             assert pairs > 0 and kt["fused_cells"] > 0, (name, fr, extra, pairs, kt)
     print("ok fused", name, flush=True)
 pairs, kt = run_forward([problem(FUSED[1][1], 40, 530, 90, 6), problem(FUSED[0][1], -1, 300, 64, 7),

@@ -192,23 +192,44 @@ hipError_t launch_fused2(const StepArgs<real> &a, int waves, int ntiles, hipStre
     if (t.g < 0) continue;
     if (t.g >= g_ngrids) { fprintf(stderr, "fused tile grid %d out of range\n", t.g); abort(); }
     const GridDev &g = a.grids[t.g];
-    if (t.x0 < 0 || t.x0 + W > g.nx || t.y0 - 4 < 0 || t.y1 + 3 > g.ny - 1 || t.y0 >= t.y1 ||
-        t.y1 - t.y0 > kFusedMaxRows) {
-      fprintf(stderr, "bad fused tile g=%d x0=%d y0=%d y1=%d (nx=%d ny=%d)\n", t.g, t.x0, t.y0, t.y1, g.nx, g.ny);
+    if (t.x0 < 0 || t.x1 > g.nx || t.x1 <= t.x0 || t.x1 - t.x0 > W || t.y0 - 4 < 0 ||
+        t.y1 + 3 > g.ny - 1 || t.y0 >= t.y1 || t.y1 - t.y0 > kFusedMaxRows) {
+      fprintf(stderr, "bad fused tile g=%d x0=%d x1=%d y0=%d y1=%d (nx=%d ny=%d)\n", t.g, t.x0, t.x1, t.y0, t.y1, g.nx, g.ny);
       abort();
     }
     check_pop(a.fin, g, "fused fin");
     check_pop(a.fout, g, "fused fout");
     check_pop(a.fmid, g, "fused fmid");
+    // what the two-step kernel does not handle must lie outside its reach:
+    // rigid-row links and side walls among the pulled cells, source disks
+    // within four cells, receivers in its own rows
+    const int rr = g.rigid_row;
+    if (rr > 0 && t.y0 - 3 <= rr && t.y1 + 2 >= rr - 1) { fprintf(stderr, "fused tile pulls across the rigid row\n"); abort(); }
+    const bool px = g.bc[kEdgeLeft] == kPeriodic, py = g.bc[kEdgeTop] == kPeriodic;
+    if (!px && (t.x0 - 5 < 0 || t.x1 + 4 > g.nx - 1)) { fprintf(stderr, "fused tile pulls across a side wall\n"); abort(); }
+    for (int si = 0; si < g.nsrc; ++si) {
+      const SourceDev q = a.sources[g.src_off + si];
+      for (int y = t.y0 - 3; y <= t.y1 + 2; ++y)
+        for (int x = t.x0 - 4; x <= t.x1 + 3; ++x) {
+          double dx = x - q.x, dy = y - q.y;
+          if (px) { if (dx > 0.5 * g.nx) dx -= g.nx; else if (dx < -0.5 * g.nx) dx += g.nx; }
+          if (py) { if (dy > 0.5 * g.ny) dy -= g.ny; else if (dy < -0.5 * g.ny) dy += g.ny; }
+          if (dx * dx + dy * dy <= 81.0 * q.sigma * q.sigma) { fprintf(stderr, "source reaches a fused tile\n"); abort(); }
+        }
+    }
+    if (g.nrec > 0)
+      for (int y = t.y0; y < t.y1; ++y)
+        if (a.itab[g.rowtab_off + y] >= 0) { fprintf(stderr, "receiver row %d in a fused tile\n", y); abort(); }
     std::vector<int64_t> &mid = stamps(a.fmid, t.g, g);
     std::vector<int64_t> &out = stamps(a.fout, t.g, g);
+    const int w = t.x1 - t.x0;
     for (int y = t.y0; y < t.y1; ++y)
-      for (int x = t.x0; x < t.x0 + W; ++x) {
+      for (int x = t.x0; x < t.x1; ++x) {
         const size_t c = (size_t)y * g.nx + x;
         g_cov[t.g][c] += 1;
         out[c] = seq;
         const int lx = x - t.x0;
-        const bool dump = ((t.flags & 4) && lx < 2) || ((t.flags & 8) && lx >= W - 2) ||
+        const bool dump = ((t.flags & 4) && lx < 2) || ((t.flags & 8) && lx >= w - 2) ||
                           ((t.flags & 1) && y < t.y0 + 2) || ((t.flags & 2) && y >= t.y1 - 2);
         if (dump) mid[c] = seq;
       }

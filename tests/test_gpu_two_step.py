@@ -24,7 +24,7 @@ TOL = {"f64": 1e-12, "f32": 1e-5}
 NSTEPS = 61
 
 
-def _field_periodic(nx=800, ny=200, seed=11, tau=0.8):
+def _field_periodic(nx=700, ny=200, seed=11, tau=0.8):
     rng = np.random.default_rng(seed)
     mu = rng.uniform(0.036, 0.044, (ny, nx))
     nu = rng.uniform(0.1, 0.3, (ny, nx))
@@ -127,3 +127,20 @@ def test_two_step_timed_steps_equal_plain_steps(dtype):
     assert np.array_equal(outs[0][1], outs[1][1])
     assert kt["steps"] == 31 and kt["fused_ms"] > 0 and kt["fused_cells"] > 0
     assert kt["general_ms"] > 0
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_adjoint_with_two_step_forward(dtype):
+    """The adjoint's recorded forward may run on the two-step path (pairs, and
+    single steps up to each checkpoint): the checkpoints, traces, adjoint
+    state and dL/dkappa equal those of a single-step forward bit for bit."""
+    from test_gpu_adjoint import _gpu_adjoint, _problem
+    p = _problem((BC_FREE0, BC_RIGID, BC_PERIODIC, BC_PERIODIC), -1, nx=600, ny=90, seed=5)
+    T = 31
+    res = np.random.default_rng(6).standard_normal((T, p.nrec, p.ncomp))
+    assert _fused_cells(p, dtype, dict(waves=4, rows=8, fuse_rows=16)) > 0
+    a = _gpu_adjoint([p], T, 7, dtype, [res], launch=dict(waves=4, rows=8))[0]
+    b = _gpu_adjoint([p], T, 7, dtype, [res], launch=dict(waves=4, rows=8, fuse_rows=16))[0]
+    for k in ("trace", "adj", "grad_kappa"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.allclose(a["grad_amp"], b["grad_amp"], rtol=1e-13, atol=0)
