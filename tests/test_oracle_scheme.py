@@ -461,3 +461,23 @@ def test_reflection_polarity_rigid_versus_free(free):
     ref = np.abs(amps["none"]).max()
     assert np.abs(amps["free"]).max() > 1.6 * ref
     assert np.abs(amps["rigid"]).max() < 0.6 * ref
+
+
+def test_rayleigh_protocol_two_turns_and_depth_profile():
+    """Sec. 7's surface-wave experiment on the oracle: the speed from two
+    complete turns around the periodic surface lies within 0.5% of the root
+    of the Rayleigh equation (the paper: 0.14%), and the depth profile of j_y
+    at step 1800 follows the half-space Rayleigh profile far better than a
+    plain exponential or the printed form with a_P and a_S exchanged."""
+    import _rayleigh as RY
+    p1, p2 = RY.problems()
+    a = stepper.run(p1, nsteps=RY.SWITCH)
+    b = stepper.run(p2, nsteps=RY.PROFILE_STEP - RY.SWITCH, t0=RY.SWITCH, fstar_init=a["fstar"])
+    c = stepper.run(p2, nsteps=RY.END - RY.PROFILE_STEP, t0=RY.PROFILE_STEP, fstar_init=b["fstar"])
+    trace = np.concatenate([a["trace"][:, :, 0], b["trace"][:, :, 0], c["trace"][:, :, 0]])
+    vr, _, _ = RY.speeds()
+    v, spread, n = RY.two_turn_speed(trace)
+    assert n >= 20 and abs(v - vr) / vr < 0.005, (v, vr, spread)
+    fits = RY.depth_fits(b["mom"][2])
+    assert fits["rayleigh"][1] < 0.5 * fits["exp"][1], fits
+    assert fits["rayleigh"][1] < 0.1 * fits["printed"][1], fits
