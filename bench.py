@@ -136,9 +136,9 @@ def bench_hbm_scale(torch, w, Solver, steps: int = 200, warmup: int = 20) -> dic
 
 
 BATCHED_LAUNCH = {"waves": 2, "rows": 8, "fuse_rows": 64}
-# 1024-column grids: narrower, shorter tiles for the adjoint and the recompute;
-# the recorded forward runs on the two-step path
-ADJOINT_LAUNCH = {"waves": 4, "rows": 4, "fuse_rows": 32}
+# 1024-column grids: narrow, short tiles for the adjoint kernels; the recorded
+# forward and the recompute run on the two-step path (128-column blocks)
+ADJOINT_LAUNCH = {"waves": 2, "rows": 4, "fuse_rows": 32}
 
 
 def bench_batched(torch, w, Solver, plain_glups: float, steps: int = 60,

@@ -726,9 +726,17 @@ int use_fused(const lbm_ctx *c) { return c->launch.fuse_rows > 0 && c->nftiles >
 // tiles straight to f*(t+1) (and leaves f*(t) of its flagged border cells in
 // the intermediate buffer); then the general kernel takes its tiles from the
 // intermediate buffer to f*(t+1).
+// With stash planes (the adjoint's recompute), the three launches also write
+// rho(t) and rho(t+1) of every cell to rho_t and rho_t1 and skip the receivers.
 template <typename real>
-hipError_t launch_two_steps(lbm_ctx *c, StepArgs<real> a, hipStream_t s) {
+hipError_t launch_two_steps(lbm_ctx *c, StepArgs<real> a, hipStream_t s, real *rho_t = nullptr,
+                            real *rho_t1 = nullptr) {
   StepArgs<real> g1 = a, f2 = a, g2 = a;
+  const int mode = rho_t ? kModeStash : kModeStep;
+  g1.rho_out = rho_t;
+  f2.rho_out = rho_t;
+  f2.rho_out2 = rho_t1;
+  g2.rho_out = rho_t1;
   g1.fout = reinterpret_cast<real *>(c->fmid);
   g1.tiles = c->d_gtiles2.p;
   f2.ftiles = c->d_ftiles.p;
@@ -740,9 +748,9 @@ hipError_t launch_two_steps(lbm_ctx *c, StepArgs<real> a, hipStream_t s) {
   const int pf = c->launch.prefetch;
   hipError_t e = launch_pair(
       c, s, c->nftiles > 0, c->ngtiles2 > 0,
-      [&](hipStream_t q) { return launch_step<real>(g1, 1, pf, c->ngtiles2, kModeStep, q); },
+      [&](hipStream_t q) { return launch_step<real>(g1, 1, pf, c->ngtiles2, mode, q); },
       [&](hipStream_t q) { return launch_fused2<real>(f2, fused_waves(c), c->nftiles, q); });
-  if (e == hipSuccess) e = launch_step<real>(g2, 1, pf, c->ngtiles2, kModeStep, s);
+  if (e == hipSuccess) e = launch_step<real>(g2, 1, pf, c->ngtiles2, mode, s);
   return e;
 }
 
@@ -1078,12 +1086,25 @@ int recompute_segment(lbm_ctx *c, int64_t m) {
   const int64_t len = std::min<int64_t>(A.seg, A.t_begin + A.nsteps - tm);
   HIP_TRY(hipMemcpyAsync(A.rbuf[0], A.ckpt + (size_t)m * A.fbytes, A.fbytes, hipMemcpyDeviceToDevice,
                          c->stream));
-  for (int64_t s = 0; s < len; ++s) {
+  auto stash = [&](int64_t s) { return reinterpret_cast<real *>(A.stash + (size_t)s * A.cbytes); };
+  int cur = 0;
+  int64_t s = 0;
+  if (use_fused(c)) {
+    for (; s + 2 <= len; s += 2) {
+      StepArgs<real> a = make_args<real>(c, 0);
+      a.fin = reinterpret_cast<const real *>(A.rbuf[cur]);
+      a.fout = reinterpret_cast<real *>(A.rbuf[cur ^ 1]);
+      a.t = tm + s;
+      HIP_TRY(launch_two_steps<real>(c, a, c->stream, stash(s), stash(s + 1)));
+      cur ^= 1;
+    }
+  }
+  for (; s < len; ++s, cur ^= 1) {
     StepArgs<real> a = make_args<real>(c, 0);
-    a.fin = reinterpret_cast<const real *>(A.rbuf[s & 1]);
-    a.fout = reinterpret_cast<real *>(A.rbuf[(s & 1) ^ 1]);
+    a.fin = reinterpret_cast<const real *>(A.rbuf[cur]);
+    a.fout = reinterpret_cast<real *>(A.rbuf[cur ^ 1]);
     a.t = tm + s;
-    a.rho_out = reinterpret_cast<real *>(A.stash + (size_t)s * A.cbytes);
+    a.rho_out = stash(s);
     StepArgs<real> ai = a;
     ai.tiles = c->d_tiles_int.p;
     HIP_TRY(launch_pair(

@@ -188,6 +188,7 @@ __device__ __forceinline__ GridDev uniform_lookup_fields(const GridDev &src) {
   g.f_off = sreg(src.f_off);
   g.kscalar = sreg(src.kscalar);
   g.k_off = sreg(src.k_off);
+  g.c_off = sreg(src.c_off);
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     g.bc[e] = sreg(src.bc[e]);

@@ -82,6 +82,7 @@ struct StepArgs {
   real *mom;             // moments mode: [6][ny][nx] of grid mom_grid
   int32_t mom_grid;
   real *rho_out;         // stash mode: rho(t) of every cell at c_off + y * pitch + x
+  real *rho_out2;        // two-step kernel in stash mode: rho(t+1), same layout
   const FusedTileDev *ftiles;  // two-step kernel: its tiles
   real *fmid;            // two-step kernel: intermediate state f*(t) of the border cells
   int64_t f_elems;       // elements of one population buffer (bounds of fin/fout/fmid)
@@ -136,7 +137,9 @@ hipError_t launch_step(const StepArgs<real> &a, int waves, int prefetch, int nti
                        hipStream_t stream);
 
 // Two steps (t and t+1) of the interior tiles in a.ftiles: reads a.fin =
-// f*(t-1), writes a.fout = f*(t+1) and, for flagged border cells, a.fmid = f*(t).
+// f*(t-1), writes a.fout = f*(t+1) and, for flagged border cells, a.fmid = f*(t);
+// with a.rho_out set also rho(t) and rho(t+1) of its cells to a.rho_out and
+// a.rho_out2.
 template <typename real>
 hipError_t launch_fused2(const StepArgs<real> &a, int waves, int ntiles, hipStream_t stream);
 

@@ -731,7 +731,7 @@ struct Phase {
   static constexpr int value = N;
 };
 
-template <typename real, int NW>
+template <typename real, int NW, bool STASH>
 __global__ __launch_bounds__(64 * NW + 64) void fused2_kernel(StepArgs<real> a) {
   constexpr int W = 64 * NW;
   constexpr int LW = W + 8;                 // LDS columns: tile plus 4 each side
@@ -836,6 +836,7 @@ __global__ __launch_bounds__(64 * NW + 64) void fused2_kernel(StepArgs<real> a) 
     if (live && r >= y0 - 3) {
       rA_n = sum9(fb);
       sA[r & 1][lc] = rA_n;
+      if (STASH && outlane && r >= y0 && r < y1) a.rho_out[g.c_off + (int64_t)r * pitch + col] = rA_n;
     }
     // Stage B: row r-1 of step t (needs rho(t) of rows r-2 .. r).
     const int rb = r - 1;
@@ -881,6 +882,7 @@ __global__ __launch_bounds__(64 * NW + 64) void fused2_kernel(StepArgs<real> a) 
       gn[8] = s78[1][lc - 1];
       rC_n = sum9(gn);
       sC[rc & 1][lc] = rC_n;
+      if (STASH && outlane && rc >= y0 && rc < y1) a.rho_out2[g.c_off + (int64_t)rc * pitch + col] = rC_n;
     }
     // Stage D: row r-3 of step t+1 (needs rho(t+1) of rows r-4 .. r-2).
     const int rd = r - 3;
@@ -988,9 +990,14 @@ template <typename real>
 hipError_t launch_fused2(const StepArgs<real> &a, int waves, int ntiles, hipStream_t stream) {
   if (ntiles <= 0) return hipSuccess;
   dim3 grid(ntiles), block(64 * waves + 64);
-  if (waves == 2) hipLaunchKernelGGL((fused2_kernel<real, 2>), grid, block, 0, stream, a);
-  else if (waves == 4) hipLaunchKernelGGL((fused2_kernel<real, 4>), grid, block, 0, stream, a);
-  else if (waves == 8) hipLaunchKernelGGL((fused2_kernel<real, 8>), grid, block, 0, stream, a);
+  if (a.rho_out) {
+    if (waves == 2) hipLaunchKernelGGL((fused2_kernel<real, 2, true>), grid, block, 0, stream, a);
+    else if (waves == 4) hipLaunchKernelGGL((fused2_kernel<real, 4, true>), grid, block, 0, stream, a);
+    else if (waves == 8) hipLaunchKernelGGL((fused2_kernel<real, 8, true>), grid, block, 0, stream, a);
+    else return hipErrorInvalidValue;
+  } else if (waves == 2) hipLaunchKernelGGL((fused2_kernel<real, 2, false>), grid, block, 0, stream, a);
+  else if (waves == 4) hipLaunchKernelGGL((fused2_kernel<real, 4, false>), grid, block, 0, stream, a);
+  else if (waves == 8) hipLaunchKernelGGL((fused2_kernel<real, 8, false>), grid, block, 0, stream, a);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

@@ -137,7 +137,8 @@ for dtype in ("f64", "f32"):
         big = problem(bc, -1 if rr < 0 else 90, 300, 200, 2,
                       sources=[Source(40.0, 30.0, 2.0, 0.3, 0.9, 1.0, 12.0, 16.0)],
                       receivers=[(x, 0) for x in range(0, 300, 5)] + [(x, 101) for x in range(3, 300, 11)])
-        for launch in (dict(waves=1, rows=4), dict(waves=2, rows=8), dict(waves=8, rows=2)):
+        for launch in (dict(waves=1, rows=4), dict(waves=2, rows=8), dict(waves=8, rows=2),
+                       dict(waves=2, rows=8, fuse_rows=6)):
             run([big], 20, 8, dtype, launch=launch)
         print("ok", name, dtype, flush=True)
     run([problem(CASES[1][1], 20, 150, 37, 3), problem(CASES[3][1], -1, 64, 65, 4)], 18, 5, dtype,

@@ -200,6 +200,10 @@ hipError_t launch_fused2(const StepArgs<real> &a, int waves, int ntiles, hipStre
     check_pop(a.fin, g, "fused fin");
     check_pop(a.fout, g, "fused fout");
     check_pop(a.fmid, g, "fused fmid");
+    if (a.rho_out) {
+      check_range(a.rho_out + g.c_off, sizeof(real) * (size_t)g.pitch * g.ny, "fused stash t");
+      check_range(a.rho_out2 + g.c_off, sizeof(real) * (size_t)g.pitch * g.ny, "fused stash t+1");
+    }
     // what the two-step kernel does not handle must lie outside its reach:
     // rigid-row links and side walls among the pulled cells, source disks
     // within four cells, receivers in its own rows

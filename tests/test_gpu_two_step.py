@@ -4,9 +4,10 @@ steps and the FP64 oracle.
 The two-step kernel performs the single-step kernels' per-cell operations in
 the same order, so a run on the two-step path must equal the single-step run
 bit for bit: state and traces, for odd and even step counts, with and without
-the general kernel on the second stream, with direct launches and inside
-captured graphs, for several block heights, boundary mixes, media and a
-batch of uneven grids. One run per case is also compared with the oracle.
+the general kernel on the second stream, for several block widths and
+heights, boundary mixes, media and a batch of uneven grids (a graph_chunk in
+the launch is ignored on this path, which launches directly). One run per
+case is also compared with the oracle.
 """
 import numpy as np
 import pytest
@@ -131,9 +132,11 @@ def test_two_step_timed_steps_equal_plain_steps(dtype):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_adjoint_with_two_step_forward(dtype):
-    """The adjoint's recorded forward may run on the two-step path (pairs, and
-    single steps up to each checkpoint): the checkpoints, traces, adjoint
-    state and dL/dkappa equal those of a single-step forward bit for bit."""
+    """The adjoint's recorded forward and its recompute may run on the
+    two-step path (pairs, and single steps up to each checkpoint; the
+    recompute also stashes rho of both steps of a pair): the checkpoints,
+    traces, adjoint state and dL/dkappa equal those of single steps bit for
+    bit."""
     from test_gpu_adjoint import _gpu_adjoint, _problem
     p = _problem((BC_FREE0, BC_RIGID, BC_PERIODIC, BC_PERIODIC), -1, nx=600, ny=90, seed=5)
     T = 31
