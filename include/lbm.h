@@ -45,6 +45,8 @@ extern "C" {
 typedef struct lbm_ctx lbm_ctx; /* opaque, owned by the library */
 
 enum {
+  LBM_WARN_UNSTABLE = 1, /* accepted, but outside the scheme's stable window
+                            (lbm_init, lbm_stability); the run proceeds */
   LBM_OK = 0,
   LBM_E_INVALID = -1,   /* argument out of range or inconsistent */
   LBM_E_NOMEM = -2,     /* workspace too small or host allocation failed */
@@ -148,7 +150,10 @@ int lbm_workspace_bytes(const lbm_grid *grids, int32_t nbatch, int32_t dtype,
  *    owned by the caller and used exclusively by this context.
  *  hip_stream: the hipStream_t all work is enqueued on (NULL = default).
  * Synchronous (validates the fields on the device and waits for it). On
- * success *ctx holds a context at time t = 0 with the rest state. */
+ * success *ctx holds a context at time t = 0 with the rest state; the return
+ * is LBM_OK, or LBM_WARN_UNSTABLE (the context is created and usable) when a
+ * bulk mode grows for the media's Poisson ratios at tau (see lbm_stability)
+ * or an edge uses LBM_FREE, with the reason in lbm_last_error. */
 int lbm_init(lbm_ctx **ctx, const lbm_grid *grids, int32_t nbatch,
              int32_t dtype, const void *lam, const void *mu, const void *rho,
              double tau, const lbm_bc *bc, const lbm_sponge *sponge,
@@ -209,6 +214,21 @@ int lbm_get_time(const lbm_ctx *ctx, int64_t *t);
  * 0 records step t). Asynchronous. */
 int lbm_get_state(lbm_ctx *ctx, int32_t g, void *dst);
 int lbm_set_state(lbm_ctx *ctx, int32_t g, const void *src, int64_t t);
+
+/* Von Neumann stability of the step (Sec. 4): the largest amplification
+ * factor per step of a plane wave exp(i k.x) under the bulk scheme (periodic,
+ * no sponge, no source) over an nk x nk grid of wavenumbers in [0, pi]^2, for
+ * Poisson ratio nu in [0, 1/2) and tau > 1/2, into *growth (host). A factor
+ * above 1 means some mode grows without bound (the paper's instability of
+ * nu != 1/4 at high wavenumbers). Synchronous, host only. Returns LBM_OK or
+ * LBM_E_INVALID. */
+int lbm_vn_growth(double nu, double tau, int32_t nk, double *growth);
+
+/* The factor lbm_init computed for this context: the largest of
+ * lbm_vn_growth(nu, tau, 33) over the media's Poisson ratios (all of them
+ * for homogeneous and layered media, up to 16 evenly spaced over the range
+ * otherwise). Returns LBM_OK or LBM_WARN_UNSTABLE as lbm_init did. Host only. */
+int lbm_stability(const lbm_ctx *ctx, double *growth);
 
 /* Check every grid's state for NaN/Inf. Synchronous. Returns LBM_OK or
  * LBM_E_NONFINITE. */

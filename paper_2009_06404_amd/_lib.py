@@ -9,12 +9,14 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import warnings
 
 import torch  # noqa: F401  (loads the HIP runtime before liblbm.so)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm.so")
 
+LBM_WARN_UNSTABLE = 1
 LBM_OK = 0
 LBM_E_INVALID = -1
 LBM_E_NOMEM = -2
@@ -35,7 +37,7 @@ ENTRY_POINTS = (
     "lbm_get_launch", "lbm_set_launch", "lbm_autotune", "lbm_destroy",
     "lbm_adjoint_workspace_bytes", "lbm_adjoint_begin", "lbm_adjoint_set_io",
     "lbm_adjoint_step", "lbm_adjoint_time", "lbm_adjoint_get_state", "lbm_adjoint_set_state",
-    "lbm_misfit", "lbm_lame_gradient",
+    "lbm_misfit", "lbm_lame_gradient", "lbm_vn_growth", "lbm_stability",
 )
 
 
@@ -115,6 +117,8 @@ def lib():
             "lbm_adjoint_set_state": ([vp, i32, vp], C.c_int),
             "lbm_misfit": ([vp, i32, vp, vp, i64, vp], C.c_int),
             "lbm_lame_gradient": ([vp, i32, vp, vp, vp, vp, vp], C.c_int),
+            "lbm_vn_growth": ([C.c_double, C.c_double, i32, C.POINTER(C.c_double)], C.c_int),
+            "lbm_stability": ([vp, C.POINTER(C.c_double)], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -169,10 +173,25 @@ def lbm_init(grids, dtype, lam_ptr, mu_ptr, rho_ptr, tau, bcs, sponges, ws_ptr, 
                 keep.append(arr)
                 s[i].profile[e] = arr.ctypes.data_as(C.POINTER(C.c_double))
     ctx = C.c_void_p()
-    check(lib().lbm_init(C.byref(ctx), g, n, dtype, lam_ptr, mu_ptr, rho_ptr, float(tau), b, s,
-                         ws_ptr, ws_bytes, stream_ptr))
+    rc = check(lib().lbm_init(C.byref(ctx), g, n, dtype, lam_ptr, mu_ptr, rho_ptr, float(tau), b, s,
+                              ws_ptr, ws_bytes, stream_ptr))
     del keep
+    if rc == LBM_WARN_UNSTABLE:
+        warnings.warn("liblbm: " + last_error(), RuntimeWarning, stacklevel=3)
     return ctx
+
+
+def lbm_vn_growth(nu: float, tau: float, nk: int = 17) -> float:
+    out = C.c_double()
+    check(lib().lbm_vn_growth(float(nu), float(tau), int(nk), C.byref(out)))
+    return out.value
+
+
+def lbm_stability(ctx):
+    """(largest von Neumann factor, stable?) of the context."""
+    out = C.c_double()
+    rc = check(lib().lbm_stability(ctx, C.byref(out)))
+    return out.value, rc == LBM_OK
 
 
 def lbm_set_sources(ctx, g: int, sources) -> None:

@@ -123,6 +123,8 @@ struct lbm_ctx {
   std::vector<RecHost> recs;
   std::vector<int> kmode;
   std::vector<double> kscalar;
+  std::vector<double> nu_seen;   // Poisson ratios of the media (samples of their range)
+  double vn_growth = 0.0;        // largest von Neumann factor over nu_seen at tau
   const void *rho = nullptr;                     // caller's density field (receiver scale)
   std::vector<int64_t> cell_off;                 // per grid offset into the packed fields
   char *ws = nullptr;
@@ -945,6 +947,30 @@ int step_impl(lbm_ctx *c, int64_t n) {
   return step_direct<real>(c, n);
 }
 
+// Poisson ratio from kappa = b^2 (mu - lambda)/mu: lambda/mu = 1 - 3 kappa.
+double nu_of_kappa(double kappa) {
+  const double r = 1.0 - 3.0 * kappa;
+  return r / (2.0 * (1.0 + r));
+}
+
+// Largest von Neumann amplification factor over the media's Poisson ratios
+// (at most 16 of them: the extremes and evenly spaced ones between) at the
+// context's tau, on a 33 x 33 grid of wavenumbers in [0, pi]^2.
+double context_vn_growth(const lbm_ctx *c) {
+  std::vector<double> v = c->nu_seen;
+  std::sort(v.begin(), v.end());
+  v.erase(std::unique(v.begin(), v.end(), [](double a, double b) { return std::fabs(a - b) < 1e-9; }),
+          v.end());
+  if (v.size() > 16) {
+    std::vector<double> w;
+    for (int q = 0; q < 16; ++q) w.push_back(v[(size_t)((v.size() - 1) * q / 15)]);
+    v = w;
+  }
+  double g = 0.0;
+  for (double nu : v) g = std::max(g, vn_growth(nu, c->tau, 33));
+  return g;
+}
+
 template <typename real>
 int init_fields(lbm_ctx *c, const void *lam, const void *mu, const void *rho) {
   const hipStream_t s = c->stream;
@@ -997,9 +1023,26 @@ int init_fields(lbm_ctx *c, const void *lam, const void *mu, const void *rho) {
       }
       c->krow_off[g] = (int64_t)krows_all.size();
       krows_all.insert(krows_all.end(), kr.begin(), kr.end());
+      for (real k : kr) c->nu_seen.push_back(nu_of_kappa((double)k));
     } else {
       c->kmode[g] = kKappaCells;
       c->krow_off[g] = 0;
+      // the range of the cell-wise moduli, sampled evenly
+      const int nb = (int)std::min<int64_t>(1024, ((int64_t)nx * ny + 255) / 256);
+      real *d_mm = nullptr;
+      HIP_TRY(hipMalloc((void **)&d_mm, 2 * nb * sizeof(real)));
+      std::vector<real> mm(2 * nb);
+      e = launch_kappa_range<real>(kc, nx, ny, c->L.pitch[g], d_mm, nb, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(mm.data(), d_mm, 2 * nb * sizeof(real), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      hipFree(d_mm);
+      if (e != hipSuccess) { rc = fail(LBM_E_DEVICE, hipGetErrorString(e)); break; }
+      double klo = 1e300, khi = -1e300;
+      for (int b = 0; b < nb; ++b) {
+        klo = std::min(klo, (double)mm[2 * b]);
+        khi = std::max(khi, (double)mm[2 * b + 1]);
+      }
+      for (int q = 0; q <= 8; ++q) c->nu_seen.push_back(nu_of_kappa(klo + (khi - klo) * q / 8.0));
     }
     cell_off += (int64_t)nx * ny;
   }
@@ -1204,11 +1247,33 @@ int check_ctx(const lbm_ctx *c) {
   return LBM_OK;
 }
 
+// LBM_OK, or LBM_WARN_UNSTABLE with the reason in the error text: a bulk mode
+// grows (the media's Poisson ratios at tau, Sec. 4), or an edge uses the
+// printed free-surface rule, whose surface modes grow for every tau.
+int stability_verdict(const lbm_ctx *c) {
+  if (c->vn_growth > 1.0 + 1e-6) {
+    char buf[200];
+    snprintf(buf, sizeof buf,
+             "unstable: a bulk mode grows by %.6f per step for Poisson ratios %.4f..%.4f at tau %.4f",
+             c->vn_growth, *std::min_element(c->nu_seen.begin(), c->nu_seen.end()),
+             *std::max_element(c->nu_seen.begin(), c->nu_seen.end()), c->tau);
+    return fail(LBM_WARN_UNSTABLE, buf);
+  }
+  for (const lbm_bc &b : c->bc)
+    for (int e = 0; e < 4; ++e)
+      if (b.edge[e] == LBM_FREE)
+        return fail(LBM_WARN_UNSTABLE, "unstable: the printed free-surface rule (LBM_FREE) lets "
+                                       "surface modes grow; LBM_FREE0 does not");
+  return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
 int lbm_abi_version(void) { return LBM_ABI_VERSION; }
+
+
 
 const char *lbm_last_error(void) { return g_err.c_str(); }
 
@@ -1299,10 +1364,28 @@ int lbm_init(lbm_ctx **out, const lbm_grid *grids, int32_t nbatch, int32_t dtype
   c->launch = default_launch(c);
   rc = rebuild_tiles(c);
   if (rc) return bail(rc);
+  c->vn_growth = context_vn_growth(c);
   rc = commit(c);
   if (rc) return bail(rc);
   *out = c;
+  return stability_verdict(c);
+}
+
+int lbm_vn_growth(double nu, double tau, int32_t nk, double *growth) {
+  if (!growth) return fail(LBM_E_INVALID, "growth is null");
+  if (!(nu >= 0.0 && nu < 0.5) || !(tau > 0.5) || !std::isfinite(tau))
+    return fail(LBM_E_INVALID, "need 0 <= nu < 1/2 and tau > 1/2");
+  if (nk < 2 || nk > 1025) return fail(LBM_E_INVALID, "nk must be in [2, 1025]");
+  *growth = vn_growth(nu, tau, nk);
   return LBM_OK;
+}
+
+int lbm_stability(const lbm_ctx *c, double *growth) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!growth) return fail(LBM_E_INVALID, "growth is null");
+  *growth = c->vn_growth;
+  return stability_verdict(c);
 }
 
 int lbm_set_sources(lbm_ctx *c, int32_t g, const lbm_source *src, int32_t n) {

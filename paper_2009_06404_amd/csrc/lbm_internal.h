@@ -165,7 +165,16 @@ template <typename real>
 hipError_t launch_copy_planes(const real *src, int64_t src_ps, int64_t src_ys, real *dst,
                               int64_t dst_ps, int64_t dst_ys, int nx, int ny, int nplanes,
                               hipStream_t stream);
+// Per-block minimum and maximum of the kappa cells of one grid:
+// minmax[2*b], minmax[2*b+1] for b < nblocks (nblocks <= 1024).
+template <typename real>
+hipError_t launch_kappa_range(const real *kappa, int nx, int ny, int pitch, real *minmax,
+                              int nblocks, hipStream_t stream);
 hipError_t launch_set_time(int64_t *t_dev, int64_t value, hipStream_t stream);
+
+// Largest von Neumann amplification factor of one step of the bulk scheme
+// over an nk x nk grid of wavenumbers in [0, pi]^2 (lbm_stability.cpp).
+double vn_growth(double nu, double tau, int nk);
 hipError_t launch_add_time(int64_t *t_dev, int64_t delta, hipStream_t stream);
 
 }  // namespace lbm

@@ -30,6 +30,34 @@ __global__ void kappa_kernel(const real *__restrict__ lam, const real *__restric
 }
 
 template <typename real>
+__global__ void kappa_range_kernel(const real *__restrict__ kappa, int nx, int ny, int pitch,
+                                   real *__restrict__ minmax) {
+  __shared__ real lo[256], hi[256];
+  const int64_t n = (int64_t)nx * ny;
+  real a = real(1e30), b = real(-1e30);
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const real v = kappa[(k / nx) * pitch + k % nx];
+    a = min(a, v);
+    b = max(b, v);
+  }
+  lo[threadIdx.x] = a;
+  hi[threadIdx.x] = b;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      lo[threadIdx.x] = min(lo[threadIdx.x], lo[threadIdx.x + s]);
+      hi[threadIdx.x] = max(hi[threadIdx.x], hi[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    minmax[2 * blockIdx.x] = lo[0];
+    minmax[2 * blockIdx.x + 1] = hi[0];
+  }
+}
+
+template <typename real>
 __global__ void kappa_rows_kernel(const real *__restrict__ kappa, int ny, int pitch,
                                   real *__restrict__ rows) {
   const int y = blockIdx.x * blockDim.x + threadIdx.x;
@@ -90,6 +118,15 @@ hipError_t launch_kappa(const real *lam, const real *mu, const real *rho, int nx
 }
 
 template <typename real>
+hipError_t launch_kappa_range(const real *kappa, int nx, int ny, int pitch, real *minmax,
+                              int nblocks, hipStream_t stream) {
+  if (nblocks < 1 || nblocks > 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(kappa_range_kernel<real>, dim3(nblocks), dim3(256), 0, stream, kappa, nx, ny,
+                     pitch, minmax);
+  return hipGetLastError();
+}
+
+template <typename real>
 hipError_t launch_kappa_rows(const real *kappa, int ny, int pitch, real *rows, hipStream_t stream) {
   hipLaunchKernelGGL(kappa_rows_kernel<real>, dim3((ny + 255) / 256), dim3(256), 0, stream, kappa,
                      ny, pitch, rows);
@@ -134,6 +171,8 @@ hipError_t launch_add_time(int64_t *t_dev, int64_t delta, hipStream_t stream) {
   template hipError_t launch_kappa<real>(const real *, const real *, const real *, int, int, int, \
                                          real *, int *, int *, hipStream_t);                      \
   template hipError_t launch_kappa_rows<real>(const real *, int, int, real *, hipStream_t);      \
+  template hipError_t launch_kappa_range<real>(const real *, int, int, int, real *, int,         \
+                                               hipStream_t);                                     \
   template hipError_t launch_gather<real>(const real *, const int64_t *, int, real *,            \
                                           hipStream_t);                                          \
   template hipError_t launch_count_nonfinite<real>(const real *, int64_t, int *, hipStream_t);   \

@@ -290,6 +290,17 @@ hipError_t launch_kappa(const real *lam, const real *mu, const real *rho, int nx
   return hipSuccess;
 }
 template <typename real>
+hipError_t launch_kappa_range(const real *kappa, int nx, int ny, int pitch, real *minmax, int nblocks, hipStream_t) {
+  if (nblocks < 1 || nblocks > 1024) { fprintf(stderr, "kappa range blocks %d\n", nblocks); abort(); }
+  check_range(kappa, sizeof(real) * (size_t)pitch * ny, "kappa range in");
+  check_range(minmax, sizeof(real) * 2 * nblocks, "kappa range out");
+  real lo = kappa[0], hi = kappa[0];
+  for (int y = 0; y < ny; ++y)
+    for (int x = 0; x < nx; ++x) { lo = std::min(lo, kappa[(int64_t)y * pitch + x]); hi = std::max(hi, kappa[(int64_t)y * pitch + x]); }
+  for (int b = 0; b < nblocks; ++b) { minmax[2 * b] = lo; minmax[2 * b + 1] = hi; }
+  return hipSuccess;
+}
+template <typename real>
 hipError_t launch_kappa_rows(const real *kappa, int ny, int pitch, real *rows, hipStream_t) {
   check_range(rows, ny * sizeof(real), "krows"); for (int y = 0; y < ny; ++y) rows[y] = kappa[(int64_t)y * pitch]; return hipSuccess;
 }
@@ -320,6 +331,7 @@ hipError_t launch_add_time(int64_t *t, int64_t v, hipStream_t) { check_range(t, 
   template hipError_t launch_lame_gradient<real>(const real *, const real *, const double *, double *, double *, int64_t, hipStream_t); \
   template hipError_t launch_kappa<real>(const real *, const real *, const real *, int, int, int, real *, int *, int *, hipStream_t); \
   template hipError_t launch_kappa_rows<real>(const real *, int, int, real *, hipStream_t); \
+  template hipError_t launch_kappa_range<real>(const real *, int, int, int, real *, int, hipStream_t); \
   template hipError_t launch_gather<real>(const real *, const int64_t *, int, real *, hipStream_t); \
   template hipError_t launch_count_nonfinite<real>(const real *, int64_t, int *, hipStream_t); \
   template hipError_t launch_copy_planes<real>(const real *, int64_t, int64_t, real *, int64_t, int64_t, int, int, int, hipStream_t);

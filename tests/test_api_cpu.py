@@ -106,6 +106,37 @@ def test_null_context_calls_fail_cleanly():
     assert lib.lbm_misfit(None, 0, None, None, 0, None) == L.LBM_E_INVALID
     assert lib.lbm_lame_gradient(None, 0, None, None, None, None, None) == L.LBM_E_INVALID
     assert lib.lbm_step_timed(None, 1, None) == L.LBM_E_INVALID
+    g = C.c_double(0)
+    assert lib.lbm_stability(None, C.byref(g)) == L.LBM_E_INVALID
+
+
+@pytest.mark.parametrize("nu,tau", [(0.25, 1.0), (0.0, 1.0), (0.33, 1.0), (0.36, 1.0), (0.37, 1.0),
+                                    (0.0, 0.55), (0.1, 0.55), (0.3, 0.55), (0.33, 0.6), (0.4, 2.0)])
+def test_library_stability_factor_matches_oracle_theory(nu, tau):
+    """lbm_vn_growth (the library's own plane-wave step, host code) against
+    the largest eigenvalue modulus of the oracle's independently built von
+    Neumann matrix on the same wavenumber grid; the oracle's matrix is pinned
+    by plane-wave stepping and the Sec. 4 stability claims."""
+    from paper_2009_06404_amd import _lib as L
+    from oracle import theory as T
+    for nk in (17, 33):
+        g = L.lbm_vn_growth(nu, tau, nk)
+        ref = T.max_growth(nu, tau, n=nk)
+        assert abs(g - ref) < 1e-7, (nk, g, ref)
+    # the window the library reports against (Sec. 4: nu = 1/4 unconditionally
+    # stable; nu = 0.37 unstable at tau = 1; nu = 0.4 unstable for every tau)
+    stable = L.lbm_vn_growth(nu, tau, 33) <= 1.0 + 1e-6
+    if nu == 0.25:
+        assert stable
+    if (nu, tau) in ((0.37, 1.0), (0.4, 2.0), (0.0, 0.55)):
+        assert not stable
+
+
+def test_stability_factor_rejects_bad_arguments():
+    from paper_2009_06404_amd import _lib as L
+    for nu, tau, nk in ((0.5, 1.0, 17), (-0.1, 1.0, 17), (0.25, 0.5, 17), (0.25, 1.0, 1)):
+        with pytest.raises(L.LBMError):
+            L.lbm_vn_growth(nu, tau, nk)
 
 
 def test_binding_fails_loudly_without_library(monkeypatch):

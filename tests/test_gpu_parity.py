@@ -306,3 +306,46 @@ def test_hbm_scale_full_size_light_cone_windows():
         assert float(outside.max().item()) == 0.0
     finally:
         s.close()
+
+
+def test_init_reports_the_stability_window():
+    """lbm_init returns LBM_WARN_UNSTABLE (the context is still made) when a
+    bulk mode grows for the media's Poisson ratios at tau, or when an edge
+    uses the printed free-surface rule; lbm_stability reports the factor."""
+    import warnings
+    from paper_2009_06404_amd import Solver, _lib as L
+    from oracle import theory as T
+    base = w.plain_small(n=64, nsteps=1)
+    cases = []
+    for nu, tau, bc in ((0.25, 1.0, base.bc), (0.33, 1.0, base.bc), (0.37, 1.0, base.bc),
+                        (0.0, 0.55, base.bc), (0.25, 1.0, (BC_FREE, BC_RIGID, BC_PERIODIC, BC_PERIODIC))):
+        lam = 0.04 * T.lame_ratio(nu)
+        cases.append((base.replace(medium=Medium("homogeneous", lam, 0.04, 1.0), tau=tau, bc=bc), nu, tau,
+                      bc == base.bc))
+    for p, nu, tau, bulk_only in cases:
+        with warnings.catch_warnings(record=True) as rec:
+            warnings.simplefilter("always")
+            s = Solver(p, dtype="f32", trace_steps=1)
+        try:
+            g, stable = L.lbm_stability(s.ctx)
+        finally:
+            s.close()
+        expect = T.max_growth(nu, tau, n=33) <= 1.0 + 1e-6 and bulk_only
+        assert stable == expect, (nu, tau, g)
+        assert abs(g - T.max_growth(nu, tau, n=33)) < 1e-7
+        assert (len([r for r in rec if "liblbm" in str(r.message)]) > 0) == (not expect)
+    # a cell-wise medium: its sampled range decides
+    rng = np.random.default_rng(3)
+    mu = np.full((48, 64), 0.04)
+    nu_f = rng.uniform(0.3, 0.39, (48, 64))
+    lam = 2 * nu_f * mu / (1 - 2 * nu_f)
+    p = base.replace(nx=64, ny=48, medium=Medium("field", lam, mu, np.ones((48, 64))), tau=1.0,
+                     sources=[], receivers=np.zeros((0, 2), np.int32))
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        s = Solver(p, dtype="f32", trace_steps=1)
+    try:
+        g, stable = L.lbm_stability(s.ctx)
+    finally:
+        s.close()
+    assert not stable and g >= T.max_growth(float(nu_f.max()), 1.0, n=33) - 1e-3

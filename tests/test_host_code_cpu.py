@@ -22,6 +22,7 @@ def test_host_code_paths_stay_in_bounds(tmp_path):
            "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include"),
            "-I" + os.path.join(ROOT, "paper_2009_06404_amd", "csrc"), "-Wno-unused-result",
            os.path.join(ROOT, "paper_2009_06404_amd", "csrc", "lbm_api.cpp"),
+           os.path.join(ROOT, "paper_2009_06404_amd", "csrc", "lbm_stability.cpp"),
            os.path.join(HERE, "stub.cpp"), "-o", lib]
     subprocess.run(cmd, check=True)
     r = subprocess.run([sys.executable, os.path.join(HERE, "drive.py"), lib],
