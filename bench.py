@@ -117,6 +117,31 @@ def _dominant_gbps(kt: dict, esize: int) -> dict:
     return {"kernel": name, "GBps": round(18 * esize * cells / ms / 1e6, 1) if ms > 0 else None}
 
 
+def bench_filter(torch, w, Solver, steps_ms: float, passes: int = 20) -> dict:
+    """The high-wavenumber filter (lbm_filter) on the 4096^2 FP32 state: one
+    pass reads and writes every population word (72 B per cell)."""
+    import warnings
+    p = w.plain_large(nsteps=2)
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        s = Solver(p, dtype="f32", trace_steps=4)
+    s.step(2)
+    for _ in range(3):
+        s.filter(0.01)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(passes):
+        s.filter(0.01)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / passes
+    s.close()
+    return {"workload": "lbm_filter on the plain_large 4096x4096 FP32 state", "ms_per_pass": round(ms, 4),
+            "GBps": round(72 * p.nx * p.ny / (ms / 1e3) / 1e9, 1), "passes": passes,
+            "vs_one_step": round(ms / steps_ms, 3)}
+
+
 def bench_hbm_scale(torch, w, Solver, steps: int = 200, warmup: int = 20) -> dict:
     """16384^2 FP32, 8 layers, rigid interface, 3 sources (the HBM-scale
     configuration), timed over a window of its 4000 steps."""
@@ -233,7 +258,7 @@ def main():
                     help="steps of the per-kernel event-timing pass after the timed region")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the HBM-scale, batched and adjoint measurements")
-    ap.add_argument("--only", choices=["hbm_scale", "batched", "adjoint"],
+    ap.add_argument("--only", choices=["hbm_scale", "batched", "adjoint", "filter"],
                     help="run only this one of the extra measurements and print it")
     ap.add_argument("--adjoint-steps", type=int, default=5000)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -276,7 +301,8 @@ def main():
         fn = {"hbm_scale": lambda: bench_hbm_scale(torch, w, Solver),
               "batched": lambda: bench_batched(torch, w, Solver, float("nan")),
               "adjoint": lambda: bench_adjoint(torch, w, Solver, float("nan"),
-                                               nsteps=args.adjoint_steps)}[args.only]
+                                               nsteps=args.adjoint_steps),
+              "filter": lambda: bench_filter(torch, w, Solver, float("nan"))}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
     p = w.plain_large(n=args.n, dtype=args.dtype)
@@ -349,7 +375,8 @@ def main():
         extras = {}
         for name, fn in (("hbm_scale", lambda: bench_hbm_scale(torch, w, Solver)),
                          ("batched", lambda: bench_batched(torch, w, Solver, glups)),
-                         ("adjoint", lambda: bench_adjoint(torch, w, Solver, glups))):
+                         ("adjoint", lambda: bench_adjoint(torch, w, Solver, glups)),
+                         ("filter", lambda: bench_filter(torch, w, Solver, ms_step))):
             print(f"[bench] {name} ...", file=sys.stderr, flush=True)
             extras[name] = fn()
             torch.cuda.empty_cache()

@@ -224,6 +224,25 @@ int lbm_set_state(lbm_ctx *ctx, int32_t g, const void *src, int64_t t);
  * LBM_E_INVALID. */
 int lbm_vn_growth(double nu, double tau, int32_t nk, double *growth);
 
+/* The same factor per step for `every` (1..1000) steps followed by one
+ * lbm_filter of strength sigma in [0, 1/16]: the spectral radius of
+ * F(k) M(k)^every to the power 1/every, F the filter's factor below. Host
+ * only. Returns LBM_OK or LBM_E_INVALID. */
+int lbm_vn_growth_filtered(double nu, double tau, double sigma, int32_t every, int32_t nk,
+                           double *growth);
+
+/* High-wavenumber filter of the state (Sec. 4: instability of nu != 1/4
+ * sits at high wavenumbers, and filtering high frequencies at the end of a
+ * step restores stability; the paper leaves the filter open). Every
+ * population of every grid becomes f - sigma (d4x f + d4y f), d4 the fourth
+ * difference g(-2) - 4 g(-1) + 6 g(0) - 4 g(1) + g(2) along x or y; its factor
+ * on a plane wave is 1 - 16 sigma (sin^4(kx/2) + sin^4(ky/2)). An axis term
+ * is left out where its five-point stencil would leave the grid through a
+ * non-periodic edge or cross the internal rigid wall. The time is unchanged.
+ * 0 < sigma <= 1/16. Asynchronous. Returns LBM_OK, LBM_E_INVALID, or
+ * LBM_E_STATE while an adjoint recording is open. */
+int lbm_filter(lbm_ctx *ctx, double sigma);
+
 /* The factor lbm_init computed for this context: the largest of
  * lbm_vn_growth(nu, tau, 33) over the media's Poisson ratios (all of them
  * for homogeneous and layered media, up to 16 evenly spaced over the range

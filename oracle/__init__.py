@@ -10,4 +10,6 @@ no code with ``paper_2009_06404_amd`` and imports nothing from it.
 * :mod:`oracle.theory` -- von Neumann matrix (Sec. 4), wave speeds (Sec. 2),
   Rayleigh-wave root (Sec. 7).
 * :mod:`oracle.spectral` -- the Fourier / Crank-Nicolson reference of App. B.
+* :mod:`oracle.filter` -- the high-wavenumber filter of a state (Sec. 4's
+  remedy for the instability of nu != 1/4; the form is the library's own).
 """

@@ -38,6 +38,7 @@ ENTRY_POINTS = (
     "lbm_adjoint_workspace_bytes", "lbm_adjoint_begin", "lbm_adjoint_set_io",
     "lbm_adjoint_step", "lbm_adjoint_time", "lbm_adjoint_get_state", "lbm_adjoint_set_state",
     "lbm_misfit", "lbm_lame_gradient", "lbm_vn_growth", "lbm_stability",
+    "lbm_vn_growth_filtered", "lbm_filter",
 )
 
 
@@ -119,6 +120,9 @@ def lib():
             "lbm_lame_gradient": ([vp, i32, vp, vp, vp, vp, vp], C.c_int),
             "lbm_vn_growth": ([C.c_double, C.c_double, i32, C.POINTER(C.c_double)], C.c_int),
             "lbm_stability": ([vp, C.POINTER(C.c_double)], C.c_int),
+            "lbm_vn_growth_filtered": ([C.c_double, C.c_double, C.c_double, i32, i32,
+                                        C.POINTER(C.c_double)], C.c_int),
+            "lbm_filter": ([vp, C.c_double], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -185,6 +189,17 @@ def lbm_vn_growth(nu: float, tau: float, nk: int = 17) -> float:
     out = C.c_double()
     check(lib().lbm_vn_growth(float(nu), float(tau), int(nk), C.byref(out)))
     return out.value
+
+
+def lbm_vn_growth_filtered(nu: float, tau: float, sigma: float, every: int = 1, nk: int = 17) -> float:
+    out = C.c_double()
+    check(lib().lbm_vn_growth_filtered(float(nu), float(tau), float(sigma), int(every), int(nk),
+                                       C.byref(out)))
+    return out.value
+
+
+def lbm_filter(ctx, sigma: float) -> None:
+    check(lib().lbm_filter(ctx, float(sigma)))
 
 
 def lbm_stability(ctx):

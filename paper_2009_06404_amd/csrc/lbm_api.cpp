@@ -151,6 +151,9 @@ struct lbm_ctx {
   // two-step path: fused tiles and the general tiles advanced step by step
   DevBuf<FusedTileDev> d_ftiles;
   DevBuf<TileDev> d_gtiles2;
+  // the filter's tiles: 256 columns x kFilterRows rows of every grid
+  DevBuf<TileDev> d_filt_tiles;
+  int nfilt_tiles = 0;
   int nftiles = 0, ngtiles2 = 0;
   int64_t cells_fused = 0, cells_gen2 = 0;
   // second stream and fork/join events for the overlapped general kernel
@@ -642,6 +645,8 @@ void build_fused_tiles(const lbm_ctx *c, int rows, std::vector<FusedTileDev> &fu
   general = order_for_dies(lg);
 }
 
+constexpr int kFilterRows = 32;
+
 int rebuild_tiles(lbm_ctx *c) {
   std::vector<TileDev> ti, tg;
   build_tiles(c, c->launch.waves, c->launch.rows, c->launch.split != 0, ti, tg);
@@ -674,6 +679,16 @@ int rebuild_tiles(lbm_ctx *c) {
   }
   HIP_TRY(c->d_tiles_int.upload(ti, c->stream));
   HIP_TRY(c->d_tiles.upload(tg, c->stream));
+  if (c->nfilt_tiles == 0) {   // independent of the launch shape: built once
+    std::vector<TileDev> tf;
+    for (int g = 0; g < c->nbatch; ++g)
+      for (int y0 = 0; y0 < c->grids[g].ny; y0 += kFilterRows)
+        for (int x0 = 0; x0 < c->grids[g].nx; x0 += 256)
+          tf.push_back(TileDev{g, x0, y0, std::min(y0 + kFilterRows, c->grids[g].ny)});
+    tf = order_for_dies(tf);
+    c->nfilt_tiles = (int)tf.size();
+    HIP_TRY(c->d_filt_tiles.upload(tf, c->stream));
+  }
   drop_graphs(c);
   return LBM_OK;
 }
@@ -1542,6 +1557,39 @@ int lbm_set_state(lbm_ctx *c, int32_t g, const void *src, int64_t t) {
   return LBM_OK;
 }
 
+int lbm_filter(lbm_ctx *c, double sigma) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!(sigma > 0.0 && sigma <= 1.0 / 16.0)) return fail(LBM_E_INVALID, "sigma must be in (0, 1/16]");
+  if (c->adj.begun && c->adj.taken < c->adj.nseg)
+    return fail(LBM_E_STATE, "an adjoint recording is open: it assumes unfiltered steps");
+  rc = commit(c);
+  if (rc) return rc;
+  const void *fin = c->fbuf[c->cur];
+  void *fout = c->fbuf[c->cur ^ 1];
+  hipError_t e = c->dtype == LBM_F64
+                     ? launch_filter<double>(reinterpret_cast<const double *>(fin), reinterpret_cast<double *>(fout),
+                                             c->d_grids.p, c->d_filt_tiles.p, c->nfilt_tiles, sigma, c->stream)
+                     : launch_filter<float>(reinterpret_cast<const float *>(fin), reinterpret_cast<float *>(fout),
+                                            c->d_grids.p, c->d_filt_tiles.p, c->nfilt_tiles, (float)sigma,
+                                            c->stream);
+  if (e != hipSuccess) return fail(LBM_E_DEVICE, hipGetErrorString(e));
+  c->cur ^= 1;
+  return LBM_OK;
+}
+
+int lbm_vn_growth_filtered(double nu, double tau, double sigma, int32_t every, int32_t nk,
+                           double *growth) {
+  if (!growth) return fail(LBM_E_INVALID, "growth is null");
+  if (!(nu >= 0.0 && nu < 0.5) || !(tau > 0.5) || !std::isfinite(tau))
+    return fail(LBM_E_INVALID, "need 0 <= nu < 1/2 and tau > 1/2");
+  if (!(sigma >= 0.0 && sigma <= 1.0 / 16.0)) return fail(LBM_E_INVALID, "sigma must be in [0, 1/16]");
+  if (every < 1 || every > 1000) return fail(LBM_E_INVALID, "every must be in [1, 1000]");
+  if (nk < 2 || nk > 1025) return fail(LBM_E_INVALID, "nk must be in [2, 1025]");
+  *growth = vn_growth_filtered(nu, tau, sigma, every, nk);
+  return LBM_OK;
+}
+
 int lbm_check_finite(lbm_ctx *c) {
   int rc = check_ctx(c);
   if (rc) return rc;
@@ -1825,6 +1873,7 @@ int lbm_destroy(lbm_ctx *c) {
   c->d_grids.release();
   c->d_tiles.release();
   c->d_ftiles.release();
+  c->d_filt_tiles.release();
   c->d_gtiles2.release();
   c->d_tiles_int.release();
   c->d_krows.release();

@@ -143,6 +143,12 @@ hipError_t launch_step(const StepArgs<real> &a, int waves, int prefetch, int nti
 template <typename real>
 hipError_t launch_fused2(const StepArgs<real> &a, int waves, int ntiles, hipStream_t stream);
 
+// The high-wavenumber filter (lbm_filter.hip): fout = fin - sigma (d4x + d4y)
+// fin for the cells of the 256-column tiles in tiles.
+template <typename real>
+hipError_t launch_filter(const real *fin, real *fout, const GridDev *grids, const TileDev *tiles,
+                         int ntiles, real sigma, hipStream_t stream);
+
 // Interior tiles; with a.rho_out set, the one-column kernel also writes rho(t).
 template <typename real>
 hipError_t launch_interior(const StepArgs<real> &a, int waves, int pair, int ntiles,
@@ -175,6 +181,8 @@ hipError_t launch_set_time(int64_t *t_dev, int64_t value, hipStream_t stream);
 // Largest von Neumann amplification factor of one step of the bulk scheme
 // over an nk x nk grid of wavenumbers in [0, pi]^2 (lbm_stability.cpp).
 double vn_growth(double nu, double tau, int nk);
+// The same for `every` steps followed by the filter of strength sigma, per step.
+double vn_growth_filtered(double nu, double tau, double sigma, int every, int nk);
 hipError_t launch_add_time(int64_t *t_dev, int64_t delta, hipStream_t stream);
 
 }  // namespace lbm

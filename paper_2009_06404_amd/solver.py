@@ -101,6 +101,10 @@ class Solver:
     def step(self, n: int) -> None:
         L.lbm_step(self.ctx, n)
 
+    def filter(self, sigma: float) -> None:
+        """High-wavenumber filter of the current state (lbm_filter)."""
+        L.lbm_filter(self.ctx, sigma)
+
     def step_timed(self, n: int) -> dict:
         """Advance n steps with per-kernel event timing (synchronous)."""
         return L.lbm_step_timed(self.ctx, n)

@@ -119,6 +119,7 @@ def run_forward(probs, T, launch, steps=(5, 1, 8)):
     before = sim.sim_pairs_checked()
     for n in steps:
         L.lbm_step(ctx, n)
+        L.lbm_filter(ctx, 0.01)
     kt = L.lbm_step_timed(ctx, 4)
     after = sim.sim_pairs_checked()
     L.lbm_destroy(ctx)

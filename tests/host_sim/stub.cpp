@@ -241,6 +241,18 @@ hipError_t launch_fused2(const StepArgs<real> &a, int waves, int ntiles, hipStre
   return hipSuccess;
 }
 template <typename real>
+hipError_t launch_filter(const real *fin, real *fout, const GridDev *grids, const TileDev *tiles, int ntiles,
+                         real, hipStream_t) {
+  if (ntiles <= 0) return hipSuccess;
+  check_tiles<real>(tiles, ntiles, grids, 256, false, "filter tiles");
+  for (int i = 0; i < ntiles; ++i) {
+    if (tiles[i].g < 0) continue;
+    check_pop(fin, grids[tiles[i].g], "filter in");
+    check_pop(fout, grids[tiles[i].g], "filter out");
+  }
+  return hipSuccess;
+}
+template <typename real>
 static hipError_t adj_common(const AdjArgs<real> &a, int waves, int ntiles, bool interior) {
   if (ntiles <= 0) return hipSuccess;
   check_tiles<real>(a.tiles, ntiles, a.grids, 64 * waves, interior, interior ? "adj int tiles" : "adj gen tiles");
@@ -325,6 +337,7 @@ hipError_t launch_add_time(int64_t *t, int64_t v, hipStream_t) { check_range(t, 
   template hipError_t launch_step<real>(const StepArgs<real> &, int, int, int, int, hipStream_t); \
   template hipError_t launch_interior<real>(const StepArgs<real> &, int, int, int, hipStream_t); \
   template hipError_t launch_fused2<real>(const StepArgs<real> &, int, int, hipStream_t); \
+  template hipError_t launch_filter<real>(const real *, real *, const GridDev *, const TileDev *, int, real, hipStream_t); \
   template hipError_t launch_adjoint<real>(const AdjArgs<real> &, int, int, hipStream_t); \
   template hipError_t launch_adjoint_interior<real>(const AdjArgs<real> &, int, int, hipStream_t); \
   template hipError_t launch_misfit<real>(const real *, const real *, real *, int64_t, double *, hipStream_t); \
