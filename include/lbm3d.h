@@ -1,0 +1,137 @@
+/*
+ * lbm3d.h -- C ABI of the three-dimensional (D3Q19) elastic-wave lattice
+ * Boltzmann step of liblbm.so on MI355X (gfx950).
+ *
+ * The step is the one of lbm.h carried to the regular D3Q19 lattice, which the
+ * paper's Chapman-Enskog analysis covers (Escande, Kolluru, Cleon & Sagaut,
+ * arXiv 2009.06404, Sec. 3: the isotropy conditions of D2Q9, D3Q15, D3Q19 and
+ * D3Q27): BGK collision toward the elastic equilibrium (eqs. equilibrium-solid
+ * and Pn with the full 3 x 3 second moment), the source of eq. S (elastic force
+ * from the centred density gradient of eq. FDrho along x, y and z, plus a
+ * Gaussian x Ricker body force, Sec. 5) added through eq. Si, the absorbing
+ * layers of eq. MomentChainAbsorbing (Sec. 6.4), fused with pull streaming
+ * (eq. LBGK) and the periodic, rigid (eq. BB) and free-surface (Sec. 6.2) face
+ * rules.
+ *
+ * Conventions (in addition to those of lbm.h, whose error codes, dtypes and
+ * face kinds LBM_PERIODIC / LBM_FREE / LBM_FREE0 / LBM_RIGID this header uses).
+ *  - Cell (x, y, z): x fastest, then y, then z; z = 0 is the TOP face and z
+ *    grows with depth.
+ *  - Directions: the rest vector, then (+x,-x), (+y,-y), (+z,-z), (x+y),
+ *    (-x-y), (x-y), (-x+y), (x+z), (-x-z), (x-z), (-x+z), (y+z), (-y-z),
+ *    (y-z), (-y+z); weights 1/3, 1/18 (axes), 1/36 (edges); b^2 = 1/3.
+ *  - One volume per context; kappa = b^2 (mu - lambda) / mu per cell.
+ *  - Free surfaces (top and bottom faces only): anti-bounce-back toward the
+ *    air state whose density and tangential stress (P_xx, P_xy, P_yy) are the
+ *    boundary cell's (LBM_FREE0) or extrapolated half a cell out (LBM_FREE),
+ *    with the stress rows along the normal zero (P_air n = 0, Sec. 6.2). A link
+ *    that leaves through several faces bounces back as rigid if any of them is
+ *    rigid, else follows the free rule if any is free, else wraps.
+ *  - Beyond a non-periodic face the centred density gradient uses the ghost
+ *    2 rho_b - rho_in.
+ *  - Caller-owned arrays, asynchronous calls on the context's stream and
+ *    negative error returns with lbm_last_error() as in lbm.h.
+ */
+#ifndef LBM3D_H_
+#define LBM3D_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "lbm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm3_ctx lbm3_ctx; /* opaque, owned by the library */
+
+enum { LBM3_FACE_TOP = 0, LBM3_FACE_BOTTOM = 1, LBM3_FACE_LEFT = 2, LBM3_FACE_RIGHT = 3,
+       LBM3_FACE_FRONT = 4, LBM3_FACE_BACK = 5 };
+
+/* Face rules and absorbing layers of a volume. face[LBM3_FACE_*]: PERIODIC in
+ * opposite pairs; FREE and FREE0 on the top and bottom faces only. Absorbing
+ * layers (Sec. 6.4): damping A(x, y, z) = max over faces f with d_f < thick[f]
+ * of profile[f][d_f], d_f = cells from face f; host arrays of length thick[f]
+ * (0 <= thick[f] <= the extent normal to f, values >= 0), copied by lbm3_init. */
+typedef struct {
+  int32_t face[6];
+  int32_t thick[6];
+  const double *profile[6];
+} lbm3_bc;
+
+/* Gaussian-in-space, Ricker-in-time body force (Sec. 5) in three dimensions:
+ * F(x, t) = amp exp(-r^2 / (2 sigma^2)) R(t) dir, r with the minimum image
+ * along periodic axes, F = 0 for r > 9 sigma; R as in lbm.h. */
+typedef struct {
+  double x, y, z, sigma, dir_x, dir_y, dir_z, amp, period, t0;
+} lbm3_source;
+
+/* Bytes of device workspace lbm3_init needs: two population buffers of
+ * 19 x pitch x ny x nz elements (pitch = nx rounded up to 64) and one
+ * pitch x ny x nz plane of kappa. Synchronous, host only. Returns LBM_OK or
+ * LBM_E_INVALID (a side < 3, a bad dtype, more than 2^31 cells, or one z
+ * plane of populations, 19 x pitch x ny elements, of 2 GiB or more). */
+int lbm3_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t dtype, size_t *bytes);
+
+/* Create a context for one nx x ny x nz volume at time t = 0, rest state.
+ *  lam, mu, rho: DEVICE arrays of dtype, [nz][ny][nx]; 0 <= nu < 1/2 and
+ *    mu, rho > 0 per cell (checked on the device).
+ *  tau > 1/2. bc: host struct as above.
+ *  workspace: DEVICE memory of at least lbm3_workspace_bytes, 256-B aligned,
+ *    owned by the caller and used only by this context.
+ *  hip_stream: the hipStream_t all work goes to (NULL = default stream).
+ * Synchronous. Returns LBM_OK, LBM_E_INVALID, LBM_E_NOMEM or LBM_E_DEVICE. */
+int lbm3_init(lbm3_ctx **ctx, int32_t nx, int32_t ny, int32_t nz, int32_t dtype,
+              const void *lam, const void *mu, const void *rho, double tau,
+              const lbm3_bc *bc, void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Replace the sources (host array, copied; at most 256). Sources lie inside
+ * the volume; sigma > 0, period > 0. Synchronous on the stream. */
+int lbm3_set_sources(lbm3_ctx *ctx, const lbm3_source *src, int32_t n);
+
+/* Record v = j / rho0 at n receiver cells at every step.
+ *  xyz: host int32 triples (x, y, z), copied; cells inside the volume.
+ *  comp_mask: bit 0 v_x, bit 1 v_y, bit 2 v_z (ncomp = popcount).
+ *  traces: DEVICE array of dtype [max_steps][n][ncomp]; row k holds step
+ *    t_now + k. n = 0 removes the receivers. Synchronous on the stream. */
+int lbm3_set_receivers(lbm3_ctx *ctx, const int32_t *xyz, int32_t n, int32_t comp_mask,
+                       void *traces, int64_t max_steps);
+
+/* Advance n >= 0 steps. Asynchronous. */
+int lbm3_step(lbm3_ctx *ctx, int64_t n);
+
+/* Advance n >= 1 steps like lbm3_step with a HIP event pair on the context's
+ * stream around every launch; *ms gets the mean launch duration (one launch
+ * per step) and *cells the cells a launch updates. Synchronous. */
+int lbm3_step_timed(lbm3_ctx *ctx, int64_t n, double *ms, int64_t *cells);
+
+/* Macroscopic fields at the current time: DEVICE array of dtype [10][nz][ny][nx]
+ * = rho, j_x, j_y, j_z, P_xx, P_xy, P_xz, P_yy, P_yz, P_zz (j with the source
+ * and the implicit sponge, as in lbm.h). Asynchronous. */
+int lbm3_moments(lbm3_ctx *ctx, void *out10);
+
+int lbm3_get_time(const lbm3_ctx *ctx, int64_t *t);
+
+/* Copy the state (post-collision populations of step t-1, DEVICE
+ * [19][nz][ny][nx] of dtype, direction order above) out of / into the
+ * context; set_state makes t the context time and restarts the receiver
+ * trace at row 0 when t differs from it. Asynchronous. */
+int lbm3_get_state(lbm3_ctx *ctx, void *dst);
+int lbm3_set_state(lbm3_ctx *ctx, const void *src, int64_t t);
+
+/* Workgroup tile: 64 columns by rows_y (2, 6 or 14) rows, marching planes_z
+ * planes (>= 1) in z. Defaults: rows_y 6, planes_z chosen so a launch has at
+ * least 2048 workgroups. Returns LBM_OK or LBM_E_INVALID. Host only. */
+int lbm3_set_tile(lbm3_ctx *ctx, int32_t rows_y, int32_t planes_z);
+int lbm3_get_tile(const lbm3_ctx *ctx, int32_t *rows_y, int32_t *planes_z);
+
+/* Free the context's own device tables; the workspace stays the caller's.
+ * Synchronous. NULL is accepted. */
+int lbm3_destroy(lbm3_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM3D_H_ */

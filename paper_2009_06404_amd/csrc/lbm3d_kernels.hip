@@ -1,0 +1,540 @@
+// D3Q19 elastic-wave step on gfx950: one kernel per step (or per evaluation
+// of the macroscopic fields), HBM-bound at 2 x 19 population words per cell.
+//
+// Work decomposition. A workgroup owns a tile of 64 columns by TY rows and a
+// segment of planes in z, and marches the segment plane by plane. It runs
+// 64 x (TY + 2) lanes: lane (lx, ly) with 1 <= ly <= TY owns cell
+// (x0 + lx, y0 + ly - 1); the rows ly = 0 and TY + 1 are halo lanes that
+// compute the density of the rows just outside the tile (and, in their first
+// TY lanes, of the columns just left and right of it). The density of each
+// plane is gathered in a (TY + 2) x 66 LDS tile, double-buffered by plane
+// parity, for the x and y differences of eq. FDrho; the z difference uses the
+// density of the planes before and after, kept in registers. Each lane pulls
+// the populations of plane z + 1 (streaming of eq. LBGK, with the face rules)
+// while the tile's LDS holds plane z, so one barrier per plane suffices.
+//
+// Addressing: the three planes a pull reads are uniform base pointers; within
+// a plane, 32-bit element offsets (y * 19 + i) * pitch + x.
+#include <hip/hip_runtime.h>
+
+#include "lbm3d_internal.h"
+#include "lbm_device.h"
+
+namespace lbm3 {
+namespace {
+
+// D3Q19 velocities in the order of the public header; weights by speed class.
+__host__ __device__ constexpr int cxv(int i) {
+  constexpr int t[kQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+  return t[i];
+}
+__host__ __device__ constexpr int cyv(int i) {
+  constexpr int t[kQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+  return t[i];
+}
+__host__ __device__ constexpr int czv(int i) {
+  constexpr int t[kQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+  return t[i];
+}
+__host__ __device__ constexpr int oppv(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+__host__ __device__ constexpr int speed2(int i) {
+  return cxv(i) * cxv(i) + cyv(i) * cyv(i) + czv(i) * czv(i);
+}
+
+template <typename real>
+__device__ __forceinline__ real wgt(int i) {
+  return speed2(i) == 0 ? real(1) / real(3) : (speed2(i) == 1 ? real(1) / real(18) : real(1) / real(36));
+}
+
+// Link kinds, ordered by precedence: a link that leaves through a rigid face
+// bounces back even if it also crosses a free one.
+constexpr int kIn = 0, kLinkFree = 1, kLinkRigid = 2;
+
+__device__ __forceinline__ int face_link_kind(int face_kind) {
+  return face_kind == kRigid ? kLinkRigid : (face_kind == kPeriodic ? kIn : kLinkFree);
+}
+
+__device__ __forceinline__ double ricker3(double t, double period, double t0) {
+  const double a = 3.14159265358979323846 * (t - t0) / period;
+  return (1.0 - 2.0 * a * a) * exp(-a * a);
+}
+
+__device__ __forceinline__ double min_image(double d, int n, bool periodic) {
+  if (!periodic) return d;
+  const double h = 0.5 * n;
+  while (d > h) d -= n;
+  while (d < -h) d += n;
+  return d;
+}
+
+// Pull of a cell none of whose links leaves through a non-periodic face:
+// every population arrives from a neighbour (periodic axes already wrapped).
+// The three planes sit behind buffer descriptors (scalar registers); a load's
+// vector offset is the byte offset of its source row and column inside the
+// plane, its scalar offset the population's run (i * pitch elements).
+using lbm::dev::Buf;
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+
+template <typename real>
+__device__ __forceinline__ real pull_inner(rsrc_t R0, rsrc_t R1, rsrc_t R2, const uint32_t (&xb)[3],
+                                           const uint32_t (&rb)[3], uint32_t run, real (&f)[kQ]) {
+  real rho = real(0);
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    const int dx = 1 - cxv(i), dy = 1 - cyv(i), dz = 1 - czv(i);
+    const rsrc_t R = dz == 0 ? R0 : (dz == 1 ? R1 : R2);
+    f[i] = Buf<real>::load(R, rb[dy] + xb[dx], (uint32_t)i * run);
+    rho += f[i];
+  }
+  return rho;
+}
+
+// A cell a task of a lane pulls every plane: the byte offsets of its wrapped
+// neighbours' columns (x-1, x, x+1) and rows (y-1, y, y+1) inside a plane,
+// and the link kind of a source beyond each of its x and y faces (kIn where
+// the cell is not on that face or the face is periodic).
+struct Task {
+  uint32_t xb[3];
+  uint32_t rb[3];
+  int kx0, kx2, ky0, ky2;
+};
+
+template <typename real>
+__device__ __forceinline__ Task make_task(const Vol3Dev &v, int x, int y) {
+  Task k;
+  const int nx = v.nx, ny = v.ny;
+  const uint32_t es = sizeof(real), rp = (uint32_t)(kQ * v.pitch) * es;
+  k.xb[0] = (uint32_t)(x > 0 ? x - 1 : nx - 1) * es;
+  k.xb[1] = (uint32_t)x * es;
+  k.xb[2] = (uint32_t)(x < nx - 1 ? x + 1 : 0) * es;
+  k.rb[0] = (uint32_t)(y > 0 ? y - 1 : ny - 1) * rp;
+  k.rb[1] = (uint32_t)y * rp;
+  k.rb[2] = (uint32_t)(y < ny - 1 ? y + 1 : 0) * rp;
+  k.kx0 = x == 0 ? face_link_kind(v.face[kFaceLeft]) : kIn;
+  k.kx2 = x == nx - 1 ? face_link_kind(v.face[kFaceRight]) : kIn;
+  k.ky0 = y == 0 ? face_link_kind(v.face[kFaceFront]) : kIn;
+  k.ky2 = y == ny - 1 ? face_link_kind(v.face[kFaceBack]) : kIn;
+  return k;
+}
+
+// Face rules for a cell some of whose links leave through a non-periodic
+// face: f holds what the wrapped pull loaded; the links whose source lies
+// beyond a rigid face take the bounce-back f*_opp(i) of the cell itself (eq.
+// BB), those beyond a free face (and no rigid one) the anti-bounce-back
+// toward the air state (Sec. 6.2): -f*_opp(i) + 2 w_i (rho_air + P^n_air :
+// (c_i c_i - b^2 I) / (2 b^4)) with P_air n = 0. The air state's density and
+// tangential stress (P_xx, P_xy, P_yy) are the cell's (FREE0) or 3/2 the
+// cell's - 1/2 the inner neighbour's (FREE): moments of the post-collision
+// populations, which the collision leaves unchanged. Returns the new rho.
+template <typename real>
+__device__ __forceinline__ real apply_faces(const Vol3Dev &v, rsrc_t R0, rsrc_t R1, rsrc_t R2,
+                                            const Task &T, int kz0, int kz2, uint32_t run,
+                                            real (&f)[kQ]) {
+  const uint32_t own = T.rb[1] + T.xb[1];
+  real rho_air = real(0), pxx = real(0), pxy = real(0), pyy = real(0);
+  if (kz0 == kLinkFree || kz2 == kLinkFree) {
+    const int kind = v.face[kz0 == kLinkFree ? kFaceTop : kFaceBottom];
+    const real wb = kind == kFree ? real(1.5) : real(1), wi = kind == kFree ? real(-0.5) : real(0);
+    const rsrc_t Rin = kz0 == kLinkFree ? R2 : R0;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+      real g = wb * Buf<real>::load(R1, own, (uint32_t)i * run);
+      if (kind == kFree) g += wi * Buf<real>::load(Rin, own, (uint32_t)i * run);
+      rho_air += g;
+      if (cxv(i) != 0) pxx += g;
+      if (cyv(i) != 0) pyy += g;
+      if (cxv(i) * cyv(i) != 0) pxy += real(cxv(i) * cyv(i)) * g;
+    }
+  }
+  const real b2 = real(1) / real(3);
+  const real pn_xx = pxx - b2 * rho_air, pn_yy = pyy - b2 * rho_air, pn_zz = -b2 * rho_air;
+  real rho = real(0);
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) {
+    // the population arrives from x - c_i
+    const int kxi = cxv(i) > 0 ? T.kx0 : (cxv(i) < 0 ? T.kx2 : kIn);
+    const int kyi = cyv(i) > 0 ? T.ky0 : (cyv(i) < 0 ? T.ky2 : kIn);
+    const int kzi = czv(i) > 0 ? kz0 : (czv(i) < 0 ? kz2 : kIn);
+    int kind = kxi > kyi ? kxi : kyi;
+    kind = kind > kzi ? kind : kzi;
+    if (kind != kIn) {
+      const real back = Buf<real>::load(R1, own, (uint32_t)oppv(i) * run);
+      if (kind == kLinkRigid) {
+        f[i] = back;
+      } else {
+        const real cx = real(cxv(i)), cy = real(cyv(i)), cz = real(czv(i));
+        const real q = pn_xx * (cx * cx - b2) + pn_yy * (cy * cy - b2) + pn_zz * (cz * cz - b2) +
+                       real(2) * pxy * cx * cy;
+        f[i] = -back + real(2) * wgt<real>(i) * (rho_air + real(4.5) * q);
+      }
+    }
+    rho += f[i];
+  }
+  return rho;
+}
+
+template <typename real, int TY, int MODE>
+__global__ void __launch_bounds__(64 * (TY + 2))
+step3_kernel(const real *__restrict__ fin, real *__restrict__ fout, real *__restrict__ out10,
+             const Vol3Dev v, int64_t t, int ntx, int nty, int nseg, int planes_z, int nblocks) {
+  __shared__ real srho[2][TY + 2][66];
+
+  // die-aware order: workgroup b runs on die b % 8; give each die a
+  // contiguous run of tiles so the tiles sharing halo rows share an L2
+  const int per_die = (nblocks + 7) / 8;
+  const int lin = (int)(blockIdx.x % 8) * per_die + (int)(blockIdx.x / 8);
+  if (lin >= nblocks) return;
+  const int tx = lin % ntx;
+  const int ty = (lin / ntx) % nty;
+  const int seg = lin / (ntx * nty);
+
+  const int nx = v.nx, ny = v.ny, nz = v.nz, pitch = v.pitch;
+  const int x0 = tx * 64, y0 = ty * TY;
+  const int w = min(64, nx - x0), h = min(TY, ny - y0);
+  const int zb = seg * planes_z, ze = min(zb + planes_z, nz);
+  const bool zper = v.face[kFaceTop] == kPeriodic;
+  const bool xper = v.face[kFaceLeft] == kPeriodic, yper = v.face[kFaceFront] == kPeriodic;
+
+  const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+  const bool interior = ly >= 1 && ly <= TY;
+  const bool active = interior && lx < w && ly <= h;
+  const int x = x0 + lx;
+  const int y = y0 + ly - 1;
+
+  // Task A: interior lanes their own cell; the halo rows (ly = 0, TY + 1) the
+  // cell just above / below the tile in their column. Task B: in the halo
+  // rows' first h lanes, the cell just left / right of the tile in row lx.
+  bool hasA = active, hasB = false;
+  int ax = x, ay = y, arow = ly, acol = lx + 1;
+  int bx = 0, by = 0, brow = 0, bcol = 0;
+  if (ly == 0 || ly == TY + 1) {
+    const bool top = ly == 0;
+    int yy = top ? y0 - 1 : y0 + h;
+    if (yy < 0 || yy >= ny) yy = yper ? (yy + ny) % ny : -1;
+    hasA = lx < w && yy >= 0;
+    ay = yy;
+    arow = top ? 0 : h + 1;
+    if (lx < h) {
+      int xx = top ? x0 - 1 : x0 + w;
+      if (xx < 0 || xx >= nx) xx = xper ? (xx + nx) % nx : -1;
+      hasB = xx >= 0;
+      bx = xx;
+      by = y0 + lx;
+      brow = lx + 1;
+      bcol = top ? 0 : w + 1;
+    }
+  }
+  const Task TA = make_task<real>(v, hasA ? ax : 0, hasA ? ay : 0);
+  const Task TB = make_task<real>(v, hasB ? bx : 0, hasB ? by : 0);
+
+  const real *__restrict__ kap = reinterpret_cast<const real *>(v.kappa);
+  const real *__restrict__ damp = reinterpret_cast<const real *>(v.damp);
+  real Axy = real(0);
+  if (active) {
+    const real a = damp[x], b = damp[nx + y];
+    Axy = a > b ? a : b;
+  }
+
+  const uint32_t run = (uint32_t)pitch * (uint32_t)sizeof(real);   // bytes of one population run
+  // pull of task T at plane p (0 <= p < nz)
+  auto pull_task = [&](const Task &T, int p, real(&f)[kQ]) -> real {
+    const int zm = p > 0 ? p - 1 : nz - 1;
+    const int zp = p < nz - 1 ? p + 1 : 0;
+    const rsrc_t R0 = lbm::dev::tile_rsrc(fin + (int64_t)zm * v.zplane);
+    const rsrc_t R1 = lbm::dev::tile_rsrc(fin + (int64_t)p * v.zplane);
+    const rsrc_t R2 = lbm::dev::tile_rsrc(fin + (int64_t)zp * v.zplane);
+    real rho = pull_inner<real>(R0, R1, R2, T.xb, T.rb, run, f);
+    const int kz0 = p == 0 ? face_link_kind(v.face[kFaceTop]) : kIn;
+    const int kz2 = p == nz - 1 ? face_link_kind(v.face[kFaceBottom]) : kIn;
+    if ((T.kx0 | T.kx2 | T.ky0 | T.ky2 | kz0 | kz2) != kIn)
+      rho = apply_faces<real>(v, R0, R1, R2, T, kz0, kz2, run, f);
+    return rho;
+  };
+
+  const real om = real(v.omega), src_w = real(1) - real(0.5) * om;
+  real cur[kQ], nxt[kQ];
+#pragma unroll
+  for (int i = 0; i < kQ; ++i) cur[i] = real(0);
+  real rp = real(0), rc = real(0), rn = real(0);
+
+  // Plane zl + 1 is pulled while plane zl is updated: task A from plane
+  // zb - 1 (its density only) to ze (its density only, for the z difference),
+  // task B from zb to ze - 1. Planes beyond a non-periodic face are skipped.
+  for (int zl = zb - 2; zl < ze; ++zl) {
+    const int p = zl + 1;
+    const bool inside = (p >= 0 && p < nz) || zper;
+    const int pw = p < 0 ? p + nz : (p >= nz ? p - nz : p);
+    const int nslot = p & 1, slot = zl & 1;
+    rn = real(0);
+    if (hasA && inside && p <= ze) rn = pull_task(TA, pw, nxt);
+    if (!active && hasA && p >= zb && p < ze) srho[nslot][arow][acol] = rn;
+    if (hasB && p >= zb && p < ze) srho[nslot][brow][bcol] = pull_task(TB, pw, nxt);
+
+    if (active && zl >= zb) {
+      const int z = zl;
+      // centred density differences (eq. FDrho), ghosts beyond non-periodic faces
+      real rl = srho[slot][ly][lx], rr = srho[slot][ly][lx + 2];
+      real ru = srho[slot][ly - 1][lx + 1], rd = srho[slot][ly + 1][lx + 1];
+      if (!xper && x == 0) rl = real(2) * rc - rr;
+      if (!xper && x == nx - 1) rr = real(2) * rc - rl;
+      if (!yper && y == 0) ru = real(2) * rc - rd;
+      if (!yper && y == ny - 1) rd = real(2) * rc - ru;
+      real rzm = rp, rzp = rn;
+      if (!zper && z == 0) rzm = real(2) * rc - rzp;
+      if (!zper && z == nz - 1) rzp = real(2) * rc - rzm;
+      const real gx = real(0.5) * (rr - rl), gy = real(0.5) * (rd - ru), gz = real(0.5) * (rzp - rzm);
+
+      // moments of the pulled populations
+      real mx = 0, my = 0, mz = 0, pxx = 0, pxy = 0, pxz = 0, pyy = 0, pyz = 0, pzz = 0;
+#pragma unroll
+      for (int i = 0; i < kQ; ++i) {
+        const real f = cur[i];
+        if (cxv(i) != 0) { mx += real(cxv(i)) * f; pxx += f; }
+        if (cyv(i) != 0) { my += real(cyv(i)) * f; pyy += f; }
+        if (czv(i) != 0) { mz += real(czv(i)) * f; pzz += f; }
+        if (cxv(i) * cyv(i) != 0) pxy += real(cxv(i) * cyv(i)) * f;
+        if (cxv(i) * czv(i) != 0) pxz += real(cxv(i) * czv(i)) * f;
+        if (cyv(i) * czv(i) != 0) pyz += real(cyv(i) * czv(i)) * f;
+      }
+      // source G = kappa grad(rho) + F (eq. S, Sec. 5)
+      const real kap_c = v.kcells ? kap[((int64_t)z * ny + y) * pitch + x] : real(v.kscalar);
+      real Gx = kap_c * gx, Gy = kap_c * gy, Gz = kap_c * gz;
+      for (int s = 0; s < v.nsrc; ++s) {
+        const Src3Dev sd = v.src[s];
+        const double dz = min_image((double)z - sd.z, nz, zper);
+        const double cut = 81.0 * sd.sigma * sd.sigma;
+        if (dz * dz > cut) continue;
+        const double dx = min_image((double)x - sd.x, nx, xper);
+        const double dy = min_image((double)y - sd.y, ny, yper);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 > cut) continue;
+        const double mag = sd.amp * exp(-r2 / (2.0 * sd.sigma * sd.sigma)) *
+                           ricker3((double)t, sd.period, sd.t0);
+        Gx += real(mag * sd.dir_x);
+        Gy += real(mag * sd.dir_y);
+        Gz += real(mag * sd.dir_z);
+      }
+      // flux with the implicit sponge (eq. MomentChainAbsorbing)
+      const real az = damp[nx + ny + z];
+      const real A = Axy > az ? Axy : az;
+      const real inv = real(1) / (real(1) + real(0.5) * A);
+      const real jx = (mx + real(0.5) * Gx) * inv, jy = (my + real(0.5) * Gy) * inv,
+                 jz = (mz + real(0.5) * Gz) * inv;
+
+      if (MODE == 0 && v.rec_row && v.rec_plane[z]) {
+        const int64_t row = t - v.trace_t0;
+        if (row >= 0 && row < v.trace_max) {
+          const int rb = v.rec_row[z * ny + y], re = v.rec_row[z * ny + y + 1];
+          const real *sc = reinterpret_cast<const real *>(v.rec_scale);
+          real *tr = reinterpret_cast<real *>(v.trace);
+          const int nc = __builtin_popcount(v.comp_mask);
+          for (int r = rb; r < re; ++r) {
+            if (v.rec_x[r] != x) continue;
+            real *o = tr + (row * v.nrec + v.rec_id[r]) * nc;
+            int k = 0;
+            if (v.comp_mask & 1) o[k++] = jx * sc[r];
+            if (v.comp_mask & 2) o[k++] = jy * sc[r];
+            if (v.comp_mask & 4) o[k++] = jz * sc[r];
+          }
+        }
+      }
+
+      if (MODE == 1) {
+        const int64_t N = (int64_t)nx * ny * nz;
+        real *o = out10 + ((int64_t)z * ny + y) * nx + x;
+        o[0] = rc;
+        o[N] = jx;
+        o[2 * N] = jy;
+        o[3 * N] = jz;
+        o[4 * N] = pxx;
+        o[5 * N] = pxy;
+        o[6 * N] = pxz;
+        o[7 * N] = pyy;
+        o[8 * N] = pyz;
+        o[9 * N] = pzz;
+      } else {
+        const real Sx = Gx - A * jx, Sy = Gy - A * jy, Sz = Gz - A * jz;
+        const real b2 = real(1) / real(3);
+        // P^n = P - rho b^2 I (eq. Pn); its trace part of P^n : (c c - b^2 I)
+        const real nxx = pxx - b2 * rc, nyy = pyy - b2 * rc, nzz = pzz - b2 * rc;
+        const real btr = b2 * (nxx + nyy + nzz);
+        const rsrc_t O = lbm::dev::tile_rsrc(fout + (int64_t)z * v.zplane);
+        const uint32_t own = (uint32_t)(y * kQ * pitch + x) * (uint32_t)sizeof(real);
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+          const real cx = real(cxv(i)), cy = real(cyv(i)), cz = real(czv(i));
+          const real q = nxx * cx * cx + nyy * cy * cy + nzz * cz * cz +
+                         real(2) * (pxy * cx * cy + pxz * cx * cz + pyz * cy * cz) - btr;
+          const real jc = jx * cx + jy * cy + jz * cz;
+          const real sc = Sx * cx + Sy * cy + Sz * cz;
+          const real wi = wgt<real>(i);
+          // equilibrium (eq. equilibrium-solid): w (rho + j.c / b^2 + P^n:Q / (2 b^4))
+          const real feq = wi * (rc + real(3) * jc + real(4.5) * q);
+          // BGK (eq. LBGK) with the source of eq. Si
+          Buf<real>::store_nt(cur[i] - om * (cur[i] - feq) + src_w * wi * real(3) * sc, O, own,
+                              (uint32_t)i * run);
+        }
+      }
+    }
+    if (active && p >= zb && p < ze) srho[nslot][ly][lx + 1] = rn;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) cur[i] = nxt[i];
+    rp = rc;
+    rc = rn;
+    __syncthreads();
+  }
+}
+
+template <typename real>
+__global__ void kappa3_kernel(const real *__restrict__ lam, const real *__restrict__ mu,
+                              const real *__restrict__ rho, real *__restrict__ kappa, int nx,
+                              int ny, int nz, int pitch, unsigned int *bad, double *minmax) {
+  __shared__ double smin[256], smax[256];
+  const int64_t N = (int64_t)nx * ny * nz;
+  double lo = 1e300, hi = -1e300;
+  unsigned int nbad = 0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < N;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const double l = (double)lam[k], m = (double)mu[k], r = (double)rho[k];
+    const double nu = l / (2.0 * (l + m));
+    if (!(m > 0.0) || !(r > 0.0) || !(nu >= 0.0) || !(nu < 0.5)) ++nbad;
+    const real kv = real(1) / real(3) * (mu[k] - lam[k]) / mu[k];
+    const int64_t x = k % nx, yz = k / nx;
+    kappa[yz * pitch + x] = kv;
+    lo = fmin(lo, (double)kv);
+    hi = fmax(hi, (double)kv);
+  }
+  if (nbad) atomicAdd(bad, nbad);
+  smin[threadIdx.x] = lo;
+  smax[threadIdx.x] = hi;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    minmax[2 * blockIdx.x] = smin[0];
+    minmax[2 * blockIdx.x + 1] = smax[0];
+  }
+}
+
+template <typename real>
+__global__ void gather_inv3_kernel(const real *__restrict__ rho, const int32_t *__restrict__ xyz,
+                                   int n, int nx, int ny, real *__restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int64_t c = ((int64_t)xyz[3 * k + 2] * ny + xyz[3 * k + 1]) * nx + xyz[3 * k];
+  out[k] = real(1) / rho[c];
+}
+
+template <typename real>
+__global__ void pack3_kernel(const real *__restrict__ src, real *__restrict__ dst, int nx, int ny,
+                             int nz, int pitch, int to_pitched) {
+  // one row (i, z, y) per block.y index, columns over threads
+  const int64_t rowid = blockIdx.y + (int64_t)blockIdx.z * 65535;
+  const int64_t nrows = (int64_t)kQ * nz * ny;
+  if (rowid >= nrows) return;
+  const int i = (int)(rowid / ((int64_t)nz * ny));
+  const int64_t zy = rowid % ((int64_t)nz * ny);
+  const int z = (int)(zy / ny), y = (int)(zy % ny);
+  const int64_t d = (int64_t)i * nz * ny * nx + zy * nx;
+  const int64_t p = (int64_t)z * ny * kQ * pitch + ((int64_t)y * kQ + i) * pitch;
+  for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < nx; x += gridDim.x * blockDim.x) {
+    if (to_pitched)
+      dst[p + x] = src[d + x];
+    else
+      dst[d + x] = src[p + x];
+  }
+}
+
+template <typename real, int TY>
+void launch_tile(int planes_z, const void *fin, void *fout, void *out10, const Vol3Dev &v,
+                 int64_t t, int mode, hipStream_t s) {
+  const int ntx = (v.nx + 63) / 64, nty = (v.ny + TY - 1) / TY;
+  const int nseg = (v.nz + planes_z - 1) / planes_z;
+  const int nblocks = ntx * nty * nseg;
+  const int grid = (nblocks + 7) / 8 * 8;
+  const dim3 block(64 * (TY + 2));
+  if (mode == 0)
+    hipLaunchKernelGGL((step3_kernel<real, TY, 0>), dim3(grid), block, 0, s,
+                       reinterpret_cast<const real *>(fin), reinterpret_cast<real *>(fout),
+                       static_cast<real *>(nullptr), v, t, ntx, nty, nseg, planes_z, nblocks);
+  else
+    hipLaunchKernelGGL((step3_kernel<real, TY, 1>), dim3(grid), block, 0, s,
+                       reinterpret_cast<const real *>(fin), static_cast<real *>(nullptr),
+                       reinterpret_cast<real *>(out10), v, t, ntx, nty, nseg, planes_z, nblocks);
+}
+
+template <typename real>
+void launch_rows(int rows_y, int planes_z, const void *fin, void *fout, void *out10,
+                 const Vol3Dev &v, int64_t t, int mode, hipStream_t s) {
+  if (rows_y == 2)
+    launch_tile<real, 2>(planes_z, fin, fout, out10, v, t, mode, s);
+  else if (rows_y == 14)
+    launch_tile<real, 14>(planes_z, fin, fout, out10, v, t, mode, s);
+  else
+    launch_tile<real, 6>(planes_z, fin, fout, out10, v, t, mode, s);
+}
+
+}  // namespace
+
+int launch_step3(bool f64, int rows_y, int planes_z, const void *fin, void *fout, void *out10,
+                 const Vol3Dev &v, int64_t t, int mode, hipStream_t s) {
+  if (f64)
+    launch_rows<double>(rows_y, planes_z, fin, fout, out10, v, t, mode, s);
+  else
+    launch_rows<float>(rows_y, planes_z, fin, fout, out10, v, t, mode, s);
+  return (int)hipGetLastError();
+}
+
+int launch_kappa3(bool f64, const void *lam, const void *mu, const void *rho, void *kappa,
+                  int nx, int ny, int nz, int pitch, unsigned int *bad, double *minmax,
+                  int *nblocks, hipStream_t s) {
+  const int64_t N = (int64_t)nx * ny * nz;
+  const int nb = (int)std::min<int64_t>(kKappaBlocks, (N + 255) / 256);
+  *nblocks = nb;
+  if (f64)
+    hipLaunchKernelGGL(kappa3_kernel<double>, dim3(nb), dim3(256), 0, s,
+                       static_cast<const double *>(lam), static_cast<const double *>(mu),
+                       static_cast<const double *>(rho), static_cast<double *>(kappa), nx, ny, nz,
+                       pitch, bad, minmax);
+  else
+    hipLaunchKernelGGL(kappa3_kernel<float>, dim3(nb), dim3(256), 0, s,
+                       static_cast<const float *>(lam), static_cast<const float *>(mu),
+                       static_cast<const float *>(rho), static_cast<float *>(kappa), nx, ny, nz,
+                       pitch, bad, minmax);
+  return (int)hipGetLastError();
+}
+
+int launch_gather_inv3(bool f64, const void *rho, const int32_t *xyz, int n, int nx, int ny,
+                       void *out, hipStream_t s) {
+  if (n <= 0) return 0;
+  const int nb = (n + 255) / 256;
+  if (f64)
+    hipLaunchKernelGGL(gather_inv3_kernel<double>, dim3(nb), dim3(256), 0, s,
+                       static_cast<const double *>(rho), xyz, n, nx, ny, static_cast<double *>(out));
+  else
+    hipLaunchKernelGGL(gather_inv3_kernel<float>, dim3(nb), dim3(256), 0, s,
+                       static_cast<const float *>(rho), xyz, n, nx, ny, static_cast<float *>(out));
+  return (int)hipGetLastError();
+}
+
+int launch_pack3(bool f64, const void *src, void *dst, int nx, int ny, int nz, int pitch,
+                 bool to_pitched, hipStream_t s) {
+  const int64_t nrows = (int64_t)kQ * nz * ny;
+  const dim3 grid((nx + 255) / 256 < 4 ? (nx + 255) / 256 : 4, 65535,
+                  (unsigned)((nrows + 65534) / 65535));
+  const dim3 g2(grid.x, nrows < 65535 ? (unsigned)nrows : 65535u, grid.z);
+  if (f64)
+    hipLaunchKernelGGL(pack3_kernel<double>, g2, dim3(256), 0, s, static_cast<const double *>(src),
+                       static_cast<double *>(dst), nx, ny, nz, pitch, to_pitched ? 1 : 0);
+  else
+    hipLaunchKernelGGL(pack3_kernel<float>, g2, dim3(256), 0, s, static_cast<const float *>(src),
+                       static_cast<float *>(dst), nx, ny, nz, pitch, to_pitched ? 1 : 0);
+  return (int)hipGetLastError();
+}
+
+}  // namespace lbm3

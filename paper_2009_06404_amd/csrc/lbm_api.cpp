@@ -109,6 +109,12 @@ struct DevBuf {
 
 }  // namespace
 
+namespace lbm {
+// The error text lbm_last_error returns, for the other entry points of the
+// library (the three-dimensional step).
+int report_error(int code, const char *msg) { return fail(code, msg); }
+}  // namespace lbm
+
 struct lbm_ctx {
   int dtype = LBM_F32;
   int nbatch = 0;

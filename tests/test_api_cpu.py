@@ -16,6 +16,76 @@ def _declared():
     return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", text)))
 
 
+def _declared3():
+    with open(os.path.join(ROOT, "include", "lbm3d.h")) as fh:
+        text = fh.read()
+    return sorted(set(re.findall(r"\b(lbm3_[a-z_]+)\s*\(", text)))
+
+
+def test_three_dimensional_header_exported():
+    from paper_2009_06404_amd import _lib3d as L3
+    lib = L3.lib()
+    names = _declared3()
+    assert len(names) == len(L3.ENTRY_POINTS) == 13
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(L3.ENTRY_POINTS) == set(names)
+
+
+def _init3(**kw):
+    from paper_2009_06404_amd import _lib as L
+    from paper_2009_06404_amd import _lib3d as L3
+    faces = kw.get("faces", (L.LBM_FREE0, L.LBM_RIGID) + (L.LBM_PERIODIC,) * 4)
+    thick = kw.get("thick", (0,) * 6)
+    prof = kw.get("prof", (None,) * 6)
+    bc, keep = L3.make_bc(faces, thick, prof)
+    shape = kw.get("shape", (16, 16, 16))
+    fake = 0x2000
+    return L3.lbm3_init(*shape, L.LBM_F32, fake, fake, fake, kw.get("tau", 1.0), bc,
+                        kw.get("ws", 0x1000), kw.get("ws_bytes", 1 << 34), None)
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(tau=0.5), "tau"),
+    (dict(shape=(2, 16, 16)), ">= 3"),
+    (dict(faces=(0, 2, 0, 0, 0, 0)), "paired"),
+    (dict(faces=(1, 2, 1, 2, 0, 0)), "top and bottom"),
+    (dict(faces=(1, 2, 0, 0, 0, 0), thick=(0, 17, 0, 0, 0, 0), prof=(None, [0.1] * 17) + (None,) * 4),
+     "sponge"),
+    (dict(faces=(1, 2, 0, 0, 0, 0), thick=(0, 2, 0, 0, 0, 0), prof=(None, [0.1, -1.0]) + (None,) * 4),
+     "sponge"),
+    (dict(ws=0), "workspace"),
+    (dict(ws=0x1004), "aligned"),
+    (dict(ws_bytes=100), "too small"),
+])
+def test_init3_rejects_invalid_arguments(kw, msg):
+    from paper_2009_06404_amd import _lib as L
+    with pytest.raises(L.LBMError) as ei:
+        _init3(**kw)
+    assert msg in str(ei.value)
+
+
+def test_workspace3_size_and_null_context():
+    import ctypes as C
+    from paper_2009_06404_amd import _lib as L
+    from paper_2009_06404_amd import _lib3d as L3
+    b32 = L3.lbm3_workspace_bytes(100, 20, 10, L.LBM_F32)
+    assert b32 >= 2 * 19 * 128 * 20 * 10 * 4 + 128 * 20 * 10 * 4
+    assert L3.lbm3_workspace_bytes(100, 20, 10, L.LBM_F64) > b32
+    for bad in ((2, 5, 5), (5, 5, 2)):
+        with pytest.raises(L.LBMError):
+            L3.lbm3_workspace_bytes(*bad, L.LBM_F32)
+    with pytest.raises(L.LBMError):
+        L3.lbm3_workspace_bytes(2048, 2048, 1024, L.LBM_F32)   # > 2^31 cells
+    lib = L3.lib()
+    assert lib.lbm3_step(None, 1) == L.LBM_E_INVALID
+    assert lib.lbm3_moments(None, None) == L.LBM_E_INVALID
+    assert lib.lbm3_set_tile(None, 6, 0) == L.LBM_E_INVALID
+    assert lib.lbm3_destroy(None) == L.LBM_OK
+    t = C.c_int64(0)
+    assert lib.lbm3_get_time(None, C.byref(t)) == L.LBM_E_INVALID
+
+
 def test_header_declares_the_boundary():
     names = _declared()
     for must in ("lbm_init", "lbm_step", "lbm_moments", "lbm_workspace_bytes",
