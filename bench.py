@@ -142,6 +142,42 @@ def bench_filter(torch, w, Solver, steps_ms: float, passes: int = 20) -> dict:
             "vs_one_step": round(ms / steps_ms, 3)}
 
 
+def bench_volume(torch, dtype: str = "f32", n: int = 256, steps: int = 400, warmup: int = 20) -> dict:
+    """The three-dimensional (D3Q19) step on the 256^3 half-space (free
+    surface, sponges, source, 4096 surface receivers): one kernel launch per
+    step, 2 x 19 population words per cell (152 B in FP32)."""
+    from workloads.problem3 import volume_half_space
+    from paper_2009_06404_amd.solver3d import Solver3
+    p = volume_half_space(n=n, nsteps=warmup + steps)
+    s = Solver3(p, dtype=dtype, trace_steps=warmup + steps + 50)
+    s.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    s.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    kt = s.step_timed(50)
+    ok = bool(torch.isfinite(s.state()).all().item())
+    tile = s.tile()
+    s.close()
+    esize = 4 if dtype == "f32" else 8
+    per_cell = 38 * esize
+    kms, kcells = kt["lean_ms"], kt["lean_cells"]
+    gbps = per_cell * kcells / (kms / 1e3) / 1e9
+    return {"workload": f"volume_half_space {n}^3 {dtype.upper()} (D3Q19): free surface top, "
+                        f"24-cell sponges (rigid bottom, periodic sides), nu=0.25, vertical Ricker "
+                        f"source at depth 12, {p.nrec} surface receivers",
+            "GLUPS": round(p.cells / ms / 1e6, 3), "ms_per_step": round(ms, 4), "steps": steps,
+            "warmup": warmup, "kernel": "step3_kernel (lean)", "kernel_ms": round(kms, 5),
+            "cells_per_launch": kcells, "bytes_per_launch": per_cell * kcells,
+            "kernel_GBps": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBS, 4),
+            "general_kernel": {"cells_per_launch": kt["general_cells"],
+                               "ms_per_launch": round(kt["general_ms"], 5)},
+            "tile": list(tile), "state_finite": ok}
+
+
 def bench_hbm_scale(torch, w, Solver, steps: int = 200, warmup: int = 20) -> dict:
     """16384^2 FP32, 8 layers, rigid interface, 3 sources (the HBM-scale
     configuration), timed over a window of its 4000 steps."""
@@ -258,7 +294,7 @@ def main():
                     help="steps of the per-kernel event-timing pass after the timed region")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the HBM-scale, batched and adjoint measurements")
-    ap.add_argument("--only", choices=["hbm_scale", "batched", "adjoint", "filter"],
+    ap.add_argument("--only", choices=["hbm_scale", "batched", "adjoint", "filter", "volume"],
                     help="run only this one of the extra measurements and print it")
     ap.add_argument("--adjoint-steps", type=int, default=5000)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -302,7 +338,8 @@ def main():
               "batched": lambda: bench_batched(torch, w, Solver, float("nan")),
               "adjoint": lambda: bench_adjoint(torch, w, Solver, float("nan"),
                                                nsteps=args.adjoint_steps),
-              "filter": lambda: bench_filter(torch, w, Solver, float("nan"))}[args.only]
+              "filter": lambda: bench_filter(torch, w, Solver, float("nan")),
+              "volume": lambda: bench_volume(torch, args.dtype)}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
     p = w.plain_large(n=args.n, dtype=args.dtype)
@@ -376,7 +413,8 @@ def main():
         for name, fn in (("hbm_scale", lambda: bench_hbm_scale(torch, w, Solver)),
                          ("batched", lambda: bench_batched(torch, w, Solver, glups)),
                          ("adjoint", lambda: bench_adjoint(torch, w, Solver, glups)),
-                         ("filter", lambda: bench_filter(torch, w, Solver, ms_step))):
+                         ("filter", lambda: bench_filter(torch, w, Solver, ms_step)),
+                         ("volume_d3q19", lambda: bench_volume(torch))):
             print(f"[bench] {name} ...", file=sys.stderr, flush=True)
             extras[name] = fn()
             torch.cuda.empty_cache()

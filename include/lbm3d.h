@@ -98,13 +98,28 @@ int lbm3_set_sources(lbm3_ctx *ctx, const lbm3_source *src, int32_t n);
 int lbm3_set_receivers(lbm3_ctx *ctx, const int32_t *xyz, int32_t n, int32_t comp_mask,
                        void *traces, int64_t max_steps);
 
-/* Advance n >= 0 steps. Asynchronous. */
+/* Advance n >= 0 steps. Asynchronous. A step runs the lean kernel on the
+ * context's stream and the general kernel (see lbm3_kernel_times) on a second
+ * stream of the library, forked from and joined back to the context's stream
+ * by events, so work queued after the call sees the whole step. */
 int lbm3_step(lbm3_ctx *ctx, int64_t n);
 
-/* Advance n >= 1 steps like lbm3_step with a HIP event pair on the context's
- * stream around every launch; *ms gets the mean launch duration (one launch
- * per step) and *cells the cells a launch updates. Synchronous. */
-int lbm3_step_timed(lbm3_ctx *ctx, int64_t n, double *ms, int64_t *cells);
+/* Per-kernel timing of the step. A step launches the lean kernel over the
+ * tiles none of whose pulled cells lies on a non-periodic face and which hold
+ * no source or receiver cell, then the general kernel over the others. */
+typedef struct {
+  int64_t steps;         /* steps timed */
+  double lean_ms;        /* mean duration of one lean-kernel launch; 0 if none */
+  double general_ms;     /* mean duration of one general-kernel launch; 0 if none */
+  int64_t lean_cells;    /* cells one lean-kernel launch updates */
+  int64_t general_cells; /* cells one general-kernel launch updates */
+  double step_ms;        /* mean duration of a step (both launches) */
+} lbm3_kernel_times;
+
+/* Advance n >= 1 steps like lbm3_step, but with both kernels on the context's
+ * stream one after the other and HIP events around every launch; the means go
+ * to *out (host). Synchronous. Results equal those of lbm3_step. */
+int lbm3_step_timed(lbm3_ctx *ctx, int64_t n, lbm3_kernel_times *out);
 
 /* Macroscopic fields at the current time: DEVICE array of dtype [10][nz][ny][nx]
  * = rho, j_x, j_y, j_z, P_xx, P_xy, P_xz, P_yy, P_yz, P_zz (j with the source
@@ -121,8 +136,9 @@ int lbm3_get_state(lbm3_ctx *ctx, void *dst);
 int lbm3_set_state(lbm3_ctx *ctx, const void *src, int64_t t);
 
 /* Workgroup tile: 64 columns by rows_y (2, 6 or 14) rows, marching planes_z
- * planes (>= 1) in z. Defaults: rows_y 6, planes_z chosen so a launch has at
- * least 2048 workgroups. Returns LBM_OK or LBM_E_INVALID. Host only. */
+ * planes (>= 1) in z. Defaults: rows_y 6 and planes_z 16 (fewer when a plane
+ * has too few tiles for 2048 workgroups); planes_z = 0 selects the default.
+ * Returns LBM_OK or LBM_E_INVALID. Host only. */
 int lbm3_set_tile(lbm3_ctx *ctx, int32_t rows_y, int32_t planes_z);
 int lbm3_get_tile(const lbm3_ctx *ctx, int32_t *rows_y, int32_t *planes_z);
 

@@ -22,6 +22,11 @@ class lbm3_bc(C.Structure):
     _fields_ = [("face", C.c_int32 * 6), ("thick", C.c_int32 * 6), ("profile", _dp * 6)]
 
 
+class lbm3_kernel_times(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("lean_ms", C.c_double), ("general_ms", C.c_double),
+                ("lean_cells", C.c_int64), ("general_cells", C.c_int64), ("step_ms", C.c_double)]
+
+
 class lbm3_source(C.Structure):
     _fields_ = [(n, C.c_double) for n in
                 ("x", "y", "z", "sigma", "dir_x", "dir_y", "dir_z", "amp", "period", "t0")]
@@ -43,7 +48,7 @@ def lib():
             "lbm3_set_sources": ([vp, C.POINTER(lbm3_source), i32], C.c_int),
             "lbm3_set_receivers": ([vp, C.POINTER(C.c_int32), i32, i32, vp, i64], C.c_int),
             "lbm3_step": ([vp, i64], C.c_int),
-            "lbm3_step_timed": ([vp, i64, C.POINTER(C.c_double), C.POINTER(i64)], C.c_int),
+            "lbm3_step_timed": ([vp, i64, C.POINTER(lbm3_kernel_times)], C.c_int),
             "lbm3_moments": ([vp, vp], C.c_int),
             "lbm3_get_time": ([vp, C.POINTER(i64)], C.c_int),
             "lbm3_get_state": ([vp, vp], C.c_int),
@@ -105,11 +110,10 @@ def lbm3_step(ctx, n: int) -> None:
     check(lib().lbm3_step(ctx, n))
 
 
-def lbm3_step_timed(ctx, n: int):
-    ms = C.c_double(0)
-    cells = C.c_int64(0)
-    check(lib().lbm3_step_timed(ctx, n, C.byref(ms), C.byref(cells)))
-    return ms.value, cells.value
+def lbm3_step_timed(ctx, n: int) -> dict:
+    kt = lbm3_kernel_times()
+    check(lib().lbm3_step_timed(ctx, n, C.byref(kt)))
+    return {name: getattr(kt, name) for name, _ in lbm3_kernel_times._fields_}
 
 
 def lbm3_moments(ctx, out_ptr) -> None:

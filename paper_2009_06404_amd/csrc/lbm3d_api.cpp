@@ -104,7 +104,15 @@ struct lbm3_ctx {
   DBuf<Src3Dev> d_src;
   DBuf<int32_t> d_rec_row, d_rec_plane, d_rec_x, d_rec_id, d_xyz;
   std::vector<Src3Dev> sources;
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  std::vector<int32_t> rec_xyz;     // receivers (x, y, z), for the tile classification
+  // tile lists: lean, general, and every tile (for the macroscopic fields)
+  DBuf<Tile3Dev> d_lean, d_general, d_all;
+  int n_lean = 0, n_general = 0, n_all = 0;
+  int64_t lean_cells = 0, general_cells = 0;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // the general kernel runs on a second stream, beside the lean one
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 
 namespace {
@@ -112,20 +120,135 @@ namespace {
 bool f64(const lbm3_ctx *c) { return c->dtype == LBM_F64; }
 
 int default_planes(const lbm3_ctx *c, int rows_y) {
+  // segments of 16 planes (each re-pulls one plane before and after it: 1/8
+  // more reads, from L2), shorter when the volume has too few tiles per plane
+  // for 2048 workgroups (8 per CU)
   const int64_t tiles = (int64_t)((c->nx + 63) / 64) * ((c->ny + rows_y - 1) / rows_y);
-  // at least 2048 workgroups (8 per CU), segments of at least 16 planes
   const int64_t nseg = std::max<int64_t>(1, (2048 + tiles - 1) / tiles);
-  int64_t pz = (c->nz + nseg - 1) / nseg;
-  pz = std::max<int64_t>(pz, std::min<int64_t>(16, c->nz));
-  return (int)pz;
+  const int64_t pz = std::max<int64_t>(4, std::min<int64_t>(16, (c->nz + nseg - 1) / nseg));
+  return (int)std::min<int64_t>(pz, c->nz);
 }
 
-int launch(lbm3_ctx *c, const void *fin, void *fout, void *out10, int mode) {
+// Plane segments of the z march. With non-periodic top and bottom faces the
+// two planes next to each face form segments of their own (their tiles pull
+// face cells), the planes between them segments of planes_z.
+std::vector<std::pair<int, int>> z_segments(const lbm3_ctx *c) {
+  std::vector<std::pair<int, int>> segs;
+  const int nz = c->nz, pz = std::max(1, c->planes_z);
+  const bool zper = c->bc.face[LBM3_FACE_TOP] == LBM_PERIODIC;
+  int lo = 0, hi = nz;
+  if (!zper && nz > 4) {
+    segs.push_back({0, 2});
+    lo = 2;
+    hi = nz - 2;
+  }
+  for (int z = lo; z < hi; z += pz) segs.push_back({z, std::min(z + pz, hi)});
+  if (!zper && nz > 4) segs.push_back({nz - 2, nz});
+  return segs;
+}
+
+// Smallest distance from coordinate s to the cells [a, b) along an axis of n
+// cells (the minimum image where the axis is periodic).
+double axis_gap(double s, int a, int b, int n, bool periodic) {
+  auto gap = [&](double q) { return q < a ? a - q : (q > b - 1 ? q - (b - 1) : 0.0); };
+  double g = gap(s);
+  if (periodic) g = std::min(g, std::min(gap(s - n), gap(s + n)));
+  return g;
+}
+
+// Split the tiles into the lean list (no pulled cell on a non-periodic face,
+// no source within 9 sigma of a cell, no receiver) and the general list.
+int build_tiles(lbm3_ctx *c) {
+  const int nx = c->nx, ny = c->ny, nz = c->nz, ty = c->rows_y;
+  const bool xper = c->bc.face[LBM3_FACE_LEFT] == LBM_PERIODIC;
+  const bool yper = c->bc.face[LBM3_FACE_FRONT] == LBM_PERIODIC;
+  const bool zper = c->bc.face[LBM3_FACE_TOP] == LBM_PERIODIC;
+  const auto segs = z_segments(c);
+  const int ntx = (nx + 63) / 64, nty = (ny + ty - 1) / ty, ns = (int)segs.size();
+  std::vector<char> rec(static_cast<size_t>(ntx) * nty * ns, 0);
+  std::vector<int> seg_of(nz);
+  for (int k = 0; k < ns; ++k)
+    for (int z = segs[k].first; z < segs[k].second; ++z) seg_of[z] = k;
+  for (size_t r = 0; r + 2 < c->rec_xyz.size(); r += 3) {
+    const int x = c->rec_xyz[r], y = c->rec_xyz[r + 1], z = c->rec_xyz[r + 2];
+    rec[((size_t)seg_of[z] * nty + y / ty) * ntx + x / 64] = 1;
+  }
+  std::vector<Tile3Dev> lean, gen, all;
+  int64_t lean_cells = 0, gen_cells = 0;
+  for (int k = 0; k < ns; ++k) {
+    const int z0 = segs[k].first, z1 = segs[k].second;
+    for (int j = 0; j < nty; ++j) {
+      const int y0 = j * ty, h = std::min(ty, ny - y0);
+      for (int i = 0; i < ntx; ++i) {
+        const int x0 = i * 64, w = std::min(64, nx - x0);
+        bool general = rec[((size_t)k * nty + j) * ntx + i] != 0;
+        // pulled cells: [x0-1, x0+w] x [y0-1, y0+h] x [z0-1, z1]
+        if (!xper && (x0 - 1 <= 0 || x0 + w >= nx - 1)) general = true;
+        if (!yper && (y0 - 1 <= 0 || y0 + h >= ny - 1)) general = true;
+        if (!zper && (z0 - 1 <= 0 || z1 >= nz - 1)) general = true;
+        for (const Src3Dev &q : c->sources) {
+          const double cut = 9.0 * q.sigma;
+          if (axis_gap(q.x, x0, x0 + w, nx, xper) <= cut && axis_gap(q.y, y0, y0 + h, ny, yper) <= cut &&
+              axis_gap(q.z, z0, z1, nz, zper) <= cut)
+            general = true;
+        }
+        const Tile3Dev t{x0, y0, z0, z1};
+        const int64_t cells = (int64_t)w * h * (z1 - z0);
+        all.push_back(t);
+        if (general) {
+          gen.push_back(t);
+          gen_cells += cells;
+        } else {
+          lean.push_back(t);
+          lean_cells += cells;
+        }
+      }
+    }
+  }
+  HIP3_TRY(c->d_lean.put(lean, c->stream));
+  HIP3_TRY(c->d_general.put(gen, c->stream));
+  HIP3_TRY(c->d_all.put(all, c->stream));
+  c->n_lean = (int)lean.size();
+  c->n_general = (int)gen.size();
+  c->n_all = (int)all.size();
+  c->lean_cells = lean_cells;
+  c->general_cells = gen_cells;
+  return LBM_OK;
+}
+
+int launch_list(lbm3_ctx *c, bool general, const Tile3Dev *tiles, int n, const void *fin,
+                void *fout, void *out10, int mode) {
+  if (n <= 0) return LBM_OK;
   c->v.omega = 1.0 / c->tau;
-  const int rc = launch_step3(f64(c), c->rows_y, c->planes_z, fin, fout, out10, c->v, c->t, mode,
-                              c->stream);
+  const int rc = launch_step3(f64(c), general, c->rows_y, tiles, n, fin, fout, out10, c->v, c->t,
+                              mode, c->stream);
   if (rc != 0) return fail3(LBM_E_DEVICE, std::string("step launch: ") + hipGetErrorString((hipError_t)rc));
   return LBM_OK;
+}
+
+// One step: the general tiles on the library's second stream, forked from and
+// joined back to the context's stream, beside the lean tiles on the context's
+// stream. The two read the same state and write disjoint cells.
+int launch_step(lbm3_ctx *c) {
+  const void *fin = c->fbuf[c->cur];
+  void *fout = c->fbuf[c->cur ^ 1];
+  if (c->n_general > 0 && c->n_lean > 0) {
+    HIP3_TRY(hipEventRecord(c->fork, c->stream));
+    HIP3_TRY(hipStreamWaitEvent(c->side, c->fork, 0));
+    hipStream_t main = c->stream;
+    c->stream = c->side;
+    int rc = launch_list(c, true, c->d_general.p, c->n_general, fin, fout, nullptr, 0);
+    c->stream = main;
+    if (rc) return rc;
+    HIP3_TRY(hipEventRecord(c->join, c->side));
+    rc = launch_list(c, false, c->d_lean.p, c->n_lean, fin, fout, nullptr, 0);
+    if (rc) return rc;
+    HIP3_TRY(hipStreamWaitEvent(c->stream, c->join, 0));
+    return LBM_OK;
+  }
+  int rc = launch_list(c, false, c->d_lean.p, c->n_lean, fin, fout, nullptr, 0);
+  if (!rc) rc = launch_list(c, true, c->d_general.p, c->n_general, fin, fout, nullptr, 0);
+  return rc;
 }
 
 int validate_bc(const lbm3_bc *bc, int32_t nx, int32_t ny, int32_t nz) {
@@ -257,8 +380,10 @@ int lbm3_init(lbm3_ctx **ctx, int32_t nx, int32_t ny, int32_t nz, int32_t dtype,
   std::vector<char> damp = dtype == LBM_F64 ? damp_table<double>(c) : damp_table<float>(c);
   e = c->d_damp.put(damp, c->stream);
   if (e == hipSuccess) e = c->d_src.put(std::vector<Src3Dev>(), c->stream);
-  if (e == hipSuccess) e = hipEventCreate(&c->ev[0]);
-  if (e == hipSuccess) e = hipEventCreate(&c->ev[1]);
+  for (int k = 0; k < 4 && e == hipSuccess; ++k) e = hipEventCreate(&c->ev[k]);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->join, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
   if (e != hipSuccess) return bail(fail3(LBM_E_DEVICE, hipGetErrorString(e)));
 
   Vol3Dev &v = c->v;
@@ -276,6 +401,7 @@ int lbm3_init(lbm3_ctx **ctx, int32_t nx, int32_t ny, int32_t nz, int32_t dtype,
   c->planes_z = default_planes(c, c->rows_y);
   // the profiles were only needed for the damping table
   for (int f = 0; f < 6; ++f) c->bc.profile[f] = nullptr;
+  if ((rc = build_tiles(c))) return bail(rc);
   *ctx = c;
   return LBM_OK;
 }
@@ -296,7 +422,8 @@ int lbm3_set_sources(lbm3_ctx *c, const lbm3_source *src, int32_t n) {
   HIP3_TRY(c->d_src.put(s, c->stream));
   c->v.src = c->d_src.p;
   c->v.nsrc = n;
-  return LBM_OK;
+  c->sources = s;
+  return build_tiles(c);
 }
 
 int lbm3_set_receivers(lbm3_ctx *c, const int32_t *xyz, int32_t n, int32_t comp_mask, void *traces,
@@ -309,7 +436,8 @@ int lbm3_set_receivers(lbm3_ctx *c, const int32_t *xyz, int32_t n, int32_t comp_
     c->v.rec_row = nullptr;
     c->v.nrec = 0;
     c->v.trace = nullptr;
-    return LBM_OK;
+    c->rec_xyz.clear();
+    return build_tiles(c);
   }
   std::vector<int32_t> q(xyz, xyz + 3 * (size_t)n);
   for (int k = 0; k < n; ++k)
@@ -353,14 +481,15 @@ int lbm3_set_receivers(lbm3_ctx *c, const int32_t *xyz, int32_t n, int32_t comp_
   v.trace_max = max_steps;
   v.nrec = n;
   v.comp_mask = comp_mask;
-  return LBM_OK;
+  c->rec_xyz = q;
+  return build_tiles(c);
 }
 
 int lbm3_step(lbm3_ctx *c, int64_t n) {
   if (!c) return fail3(LBM_E_INVALID, "null context");
   if (n < 0) return fail3(LBM_E_INVALID, "n must be >= 0");
   for (int64_t k = 0; k < n; ++k) {
-    const int rc = launch(c, c->fbuf[c->cur], c->fbuf[c->cur ^ 1], nullptr, 0);
+    const int rc = launch_step(c);
     if (rc) return rc;
     c->cur ^= 1;
     c->t += 1;
@@ -368,30 +497,42 @@ int lbm3_step(lbm3_ctx *c, int64_t n) {
   return LBM_OK;
 }
 
-int lbm3_step_timed(lbm3_ctx *c, int64_t n, double *ms, int64_t *cells) {
+int lbm3_step_timed(lbm3_ctx *c, int64_t n, lbm3_kernel_times *out) {
   if (!c) return fail3(LBM_E_INVALID, "null context");
-  if (n < 1 || !ms || !cells) return fail3(LBM_E_INVALID, "n >= 1, ms and cells required");
-  double total = 0.0;
+  if (n < 1 || !out) return fail3(LBM_E_INVALID, "n >= 1 and out required");
+  double lean = 0.0, gen = 0.0, step = 0.0;
   for (int64_t k = 0; k < n; ++k) {
+    const void *fin = c->fbuf[c->cur];
+    void *fout = c->fbuf[c->cur ^ 1];
     HIP3_TRY(hipEventRecord(c->ev[0], c->stream));
-    const int rc = launch(c, c->fbuf[c->cur], c->fbuf[c->cur ^ 1], nullptr, 0);
+    int rc = launch_list(c, false, c->d_lean.p, c->n_lean, fin, fout, nullptr, 0);
     if (rc) return rc;
     HIP3_TRY(hipEventRecord(c->ev[1], c->stream));
-    HIP3_TRY(hipEventSynchronize(c->ev[1]));
-    float t_ms = 0.f;
-    HIP3_TRY(hipEventElapsedTime(&t_ms, c->ev[0], c->ev[1]));
-    total += t_ms;
+    rc = launch_list(c, true, c->d_general.p, c->n_general, fin, fout, nullptr, 0);
+    if (rc) return rc;
+    HIP3_TRY(hipEventRecord(c->ev[2], c->stream));
+    HIP3_TRY(hipEventSynchronize(c->ev[2]));
+    float a = 0.f, b = 0.f;
+    HIP3_TRY(hipEventElapsedTime(&a, c->ev[0], c->ev[1]));
+    HIP3_TRY(hipEventElapsedTime(&b, c->ev[1], c->ev[2]));
+    lean += a;
+    gen += b;
+    step += a + b;
     c->cur ^= 1;
     c->t += 1;
   }
-  *ms = total / (double)n;
-  *cells = (int64_t)c->nx * c->ny * c->nz;
+  out->steps = n;
+  out->lean_ms = c->n_lean ? lean / (double)n : 0.0;
+  out->general_ms = c->n_general ? gen / (double)n : 0.0;
+  out->lean_cells = c->lean_cells;
+  out->general_cells = c->general_cells;
+  out->step_ms = step / (double)n;
   return LBM_OK;
 }
 
 int lbm3_moments(lbm3_ctx *c, void *out10) {
   if (!c || !out10) return fail3(LBM_E_INVALID, "context and out10 required");
-  return launch(c, c->fbuf[c->cur], nullptr, out10, 1);
+  return launch_list(c, true, c->d_all.p, c->n_all, c->fbuf[c->cur], nullptr, out10, 1);
 }
 
 int lbm3_get_time(const lbm3_ctx *c, int64_t *t) {
@@ -423,7 +564,7 @@ int lbm3_set_tile(lbm3_ctx *c, int32_t rows_y, int32_t planes_z) {
   if (planes_z < 0) return fail3(LBM_E_INVALID, "planes_z must be >= 0 (0: default)");
   c->rows_y = rows_y;
   c->planes_z = planes_z == 0 ? default_planes(c, rows_y) : std::min(planes_z, c->nz);
-  return LBM_OK;
+  return build_tiles(c);
 }
 
 int lbm3_get_tile(const lbm3_ctx *c, int32_t *rows_y, int32_t *planes_z) {
@@ -444,8 +585,17 @@ int lbm3_destroy(lbm3_ctx *c) {
   c->d_rec_x.release();
   c->d_rec_id.release();
   c->d_xyz.release();
+  c->d_lean.release();
+  c->d_general.release();
+  c->d_all.release();
   for (auto &e : c->ev)
     if (e) hipEventDestroy(e);
+  if (c->fork) hipEventDestroy(c->fork);
+  if (c->join) hipEventDestroy(c->join);
+  if (c->side) {
+    hipStreamSynchronize(c->side);
+    hipStreamDestroy(c->side);
+  }
   delete c;
   return LBM_OK;
 }

@@ -42,12 +42,22 @@ struct Vol3Dev {
   int32_t nrec, comp_mask;
 };
 
+// One workgroup's work: columns [x0, x0 + 64) and rows [y0, y0 + rows_y) of
+// the volume (clipped to it), planes [z0, z1).
+struct Tile3Dev {
+  int32_t x0, y0, z0, z1;
+};
+
 // Launchers return the hipError_t of the launch (0 on success).
 
-// Launch of one pass over the volume. mode 0: a step (fin -> fout); mode 1:
-// the macroscopic fields of fin's time into out10 (dense [10][nz][ny][nx]).
-int launch_step3(bool f64, int rows_y, int planes_z, const void *fin, void *fout, void *out10,
-                 const Vol3Dev &v, int64_t t, int mode, hipStream_t s);
+// Launch of one pass over the tiles of a list. mode 0: a step (fin -> fout);
+// mode 1: the macroscopic fields of fin's time into out10 (dense
+// [10][nz][ny][nx]). general = false: the lean kernel, for tiles none of whose
+// pulled cells lies on a non-periodic face and which hold no source or
+// receiver cell; general = true: the kernel with every rule (mode 1 always).
+int launch_step3(bool f64, bool general, int rows_y, const Tile3Dev *tiles, int ntiles,
+                 const void *fin, void *fout, void *out10, const Vol3Dev &v, int64_t t, int mode,
+                 hipStream_t s);
 
 // kappa = b^2 (mu - lambda) / mu into the kappa plane. The count of cells
 // outside 0 <= nu < 1/2, mu > 0, rho > 0 (NaN included) is added to *bad

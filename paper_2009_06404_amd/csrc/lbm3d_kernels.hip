@@ -136,14 +136,16 @@ __device__ __forceinline__ real apply_faces(const Vol3Dev &v, rsrc_t R0, rsrc_t 
     const int kind = v.face[kz0 == kLinkFree ? kFaceTop : kFaceBottom];
     const real wb = kind == kFree ? real(1.5) : real(1), wi = kind == kFree ? real(-0.5) : real(0);
     const rsrc_t Rin = kz0 == kLinkFree ? R2 : R0;
-#pragma unroll
+    // rolled: few loads in flight on this rare path (free-surface planes)
+#pragma unroll 1
     for (int i = 0; i < kQ; ++i) {
       real g = wb * Buf<real>::load(R1, own, (uint32_t)i * run);
       if (kind == kFree) g += wi * Buf<real>::load(Rin, own, (uint32_t)i * run);
       rho_air += g;
-      if (cxv(i) != 0) pxx += g;
-      if (cyv(i) != 0) pyy += g;
-      if (cxv(i) * cyv(i) != 0) pxy += real(cxv(i) * cyv(i)) * g;
+      const int cx = cxv(i), cy = cyv(i);
+      if (cx != 0) pxx += g;
+      if (cy != 0) pyy += g;
+      pxy += real(cx * cy) * g;
     }
   }
   const real b2 = real(1) / real(3);
@@ -173,25 +175,26 @@ __device__ __forceinline__ real apply_faces(const Vol3Dev &v, rsrc_t R0, rsrc_t 
   return rho;
 }
 
-template <typename real, int TY, int MODE>
+// GENERAL = false: the lean kernel (no face rules, sources or receivers; the
+// host gives it only tiles that need none). MODE 1 (fields) is general only.
+template <typename real, int TY, int MODE, bool GENERAL>
 __global__ void __launch_bounds__(64 * (TY + 2))
 step3_kernel(const real *__restrict__ fin, real *__restrict__ fout, real *__restrict__ out10,
-             const Vol3Dev v, int64_t t, int ntx, int nty, int nseg, int planes_z, int nblocks) {
+             const Vol3Dev v, int64_t t, const Tile3Dev *__restrict__ tiles, int ntiles) {
   __shared__ real srho[2][TY + 2][66];
 
-  // die-aware order: workgroup b runs on die b % 8; give each die a
-  // contiguous run of tiles so the tiles sharing halo rows share an L2
-  const int per_die = (nblocks + 7) / 8;
+  // die-aware order: workgroup b runs on die b % 8; each die takes a
+  // contiguous run of the list (ordered by plane segment, row, column), so
+  // the tiles sharing halo rows and planes share an L2
+  const int per_die = (ntiles + 7) / 8;
   const int lin = (int)(blockIdx.x % 8) * per_die + (int)(blockIdx.x / 8);
-  if (lin >= nblocks) return;
-  const int tx = lin % ntx;
-  const int ty = (lin / ntx) % nty;
-  const int seg = lin / (ntx * nty);
+  if (lin >= ntiles) return;
+  const Tile3Dev tile = tiles[lin];
 
   const int nx = v.nx, ny = v.ny, nz = v.nz, pitch = v.pitch;
-  const int x0 = tx * 64, y0 = ty * TY;
+  const int x0 = tile.x0, y0 = tile.y0;
   const int w = min(64, nx - x0), h = min(TY, ny - y0);
-  const int zb = seg * planes_z, ze = min(zb + planes_z, nz);
+  const int zb = tile.z0, ze = tile.z1;
   const bool zper = v.face[kFaceTop] == kPeriodic;
   const bool xper = v.face[kFaceLeft] == kPeriodic, yper = v.face[kFaceFront] == kPeriodic;
 
@@ -224,8 +227,7 @@ step3_kernel(const real *__restrict__ fin, real *__restrict__ fout, real *__rest
       bcol = top ? 0 : w + 1;
     }
   }
-  const Task TA = make_task<real>(v, hasA ? ax : 0, hasA ? ay : 0);
-  const Task TB = make_task<real>(v, hasB ? bx : 0, hasB ? by : 0);
+  const int tax = hasA ? ax : 0, tay = hasA ? ay : 0, tbx = hasB ? bx : 0, tby = hasB ? by : 0;
 
   const real *__restrict__ kap = reinterpret_cast<const real *>(v.kappa);
   const real *__restrict__ damp = reinterpret_cast<const real *>(v.damp);
@@ -244,10 +246,12 @@ step3_kernel(const real *__restrict__ fin, real *__restrict__ fout, real *__rest
     const rsrc_t R1 = lbm::dev::tile_rsrc(fin + (int64_t)p * v.zplane);
     const rsrc_t R2 = lbm::dev::tile_rsrc(fin + (int64_t)zp * v.zplane);
     real rho = pull_inner<real>(R0, R1, R2, T.xb, T.rb, run, f);
-    const int kz0 = p == 0 ? face_link_kind(v.face[kFaceTop]) : kIn;
-    const int kz2 = p == nz - 1 ? face_link_kind(v.face[kFaceBottom]) : kIn;
-    if ((T.kx0 | T.kx2 | T.ky0 | T.ky2 | kz0 | kz2) != kIn)
-      rho = apply_faces<real>(v, R0, R1, R2, T, kz0, kz2, run, f);
+    if (GENERAL) {
+      const int kz0 = p == 0 ? face_link_kind(v.face[kFaceTop]) : kIn;
+      const int kz2 = p == nz - 1 ? face_link_kind(v.face[kFaceBottom]) : kIn;
+      if ((T.kx0 | T.kx2 | T.ky0 | T.ky2 | kz0 | kz2) != kIn)
+        rho = apply_faces<real>(v, R0, R1, R2, T, kz0, kz2, run, f);
+    }
     return rho;
   };
 
@@ -266,9 +270,19 @@ step3_kernel(const real *__restrict__ fin, real *__restrict__ fout, real *__rest
     const int pw = p < 0 ? p + nz : (p >= nz ? p - nz : p);
     const int nslot = p & 1, slot = zl & 1;
     rn = real(0);
-    if (hasA && inside && p <= ze) rn = pull_task(TA, pw, nxt);
+    if (hasA && inside && p <= ze) {
+      // rebuilt every plane: a few integer operations instead of a dozen
+      // registers held across the loop
+      int cx_ = tax, cy_ = tay;
+      asm volatile("" : "+v"(cx_), "+v"(cy_));
+      rn = pull_task(make_task<real>(v, cx_, cy_), pw, nxt);
+    }
     if (!active && hasA && p >= zb && p < ze) srho[nslot][arow][acol] = rn;
-    if (hasB && p >= zb && p < ze) srho[nslot][brow][bcol] = pull_task(TB, pw, nxt);
+    if (hasB && p >= zb && p < ze) {
+      int cx_ = tbx, cy_ = tby;
+      asm volatile("" : "+v"(cx_), "+v"(cy_));
+      srho[nslot][brow][bcol] = pull_task(make_task<real>(v, cx_, cy_), pw, nxt);
+    }
 
     if (active && zl >= zb) {
       const int z = zl;
@@ -299,7 +313,7 @@ step3_kernel(const real *__restrict__ fin, real *__restrict__ fout, real *__rest
       // source G = kappa grad(rho) + F (eq. S, Sec. 5)
       const real kap_c = v.kcells ? kap[((int64_t)z * ny + y) * pitch + x] : real(v.kscalar);
       real Gx = kap_c * gx, Gy = kap_c * gy, Gz = kap_c * gz;
-      for (int s = 0; s < v.nsrc; ++s) {
+      for (int s = 0; s < (GENERAL ? v.nsrc : 0); ++s) {
         const Src3Dev sd = v.src[s];
         const double dz = min_image((double)z - sd.z, nz, zper);
         const double cut = 81.0 * sd.sigma * sd.sigma;
@@ -321,7 +335,7 @@ step3_kernel(const real *__restrict__ fin, real *__restrict__ fout, real *__rest
       const real jx = (mx + real(0.5) * Gx) * inv, jy = (my + real(0.5) * Gy) * inv,
                  jz = (mz + real(0.5) * Gz) * inv;
 
-      if (MODE == 0 && v.rec_row && v.rec_plane[z]) {
+      if (GENERAL && MODE == 0 && v.rec_row && v.rec_plane[z]) {
         const int64_t row = t - v.trace_t0;
         if (row >= 0 && row < v.trace_max) {
           const int rb = v.rec_row[z * ny + y], re = v.rec_row[z * ny + y + 1];
@@ -451,42 +465,44 @@ __global__ void pack3_kernel(const real *__restrict__ src, real *__restrict__ ds
 }
 
 template <typename real, int TY>
-void launch_tile(int planes_z, const void *fin, void *fout, void *out10, const Vol3Dev &v,
-                 int64_t t, int mode, hipStream_t s) {
-  const int ntx = (v.nx + 63) / 64, nty = (v.ny + TY - 1) / TY;
-  const int nseg = (v.nz + planes_z - 1) / planes_z;
-  const int nblocks = ntx * nty * nseg;
-  const int grid = (nblocks + 7) / 8 * 8;
-  const dim3 block(64 * (TY + 2));
-  if (mode == 0)
-    hipLaunchKernelGGL((step3_kernel<real, TY, 0>), dim3(grid), block, 0, s,
-                       reinterpret_cast<const real *>(fin), reinterpret_cast<real *>(fout),
-                       static_cast<real *>(nullptr), v, t, ntx, nty, nseg, planes_z, nblocks);
+void launch_tile(bool general, const Tile3Dev *tiles, int ntiles, const void *fin, void *fout,
+                 void *out10, const Vol3Dev &v, int64_t t, int mode, hipStream_t s) {
+  if (ntiles <= 0) return;
+  const dim3 grid((ntiles + 7) / 8 * 8), block(64 * (TY + 2));
+  const real *in = reinterpret_cast<const real *>(fin);
+  real *out = reinterpret_cast<real *>(fout);
+  real *o10 = reinterpret_cast<real *>(out10);
+  if (mode == 1)
+    hipLaunchKernelGGL((step3_kernel<real, TY, 1, true>), grid, block, 0, s, in, out, o10, v, t,
+                       tiles, ntiles);
+  else if (general)
+    hipLaunchKernelGGL((step3_kernel<real, TY, 0, true>), grid, block, 0, s, in, out, o10, v, t,
+                       tiles, ntiles);
   else
-    hipLaunchKernelGGL((step3_kernel<real, TY, 1>), dim3(grid), block, 0, s,
-                       reinterpret_cast<const real *>(fin), static_cast<real *>(nullptr),
-                       reinterpret_cast<real *>(out10), v, t, ntx, nty, nseg, planes_z, nblocks);
+    hipLaunchKernelGGL((step3_kernel<real, TY, 0, false>), grid, block, 0, s, in, out, o10, v, t,
+                       tiles, ntiles);
 }
 
 template <typename real>
-void launch_rows(int rows_y, int planes_z, const void *fin, void *fout, void *out10,
-                 const Vol3Dev &v, int64_t t, int mode, hipStream_t s) {
+void launch_rows(bool general, int rows_y, const Tile3Dev *tiles, int ntiles, const void *fin,
+                 void *fout, void *out10, const Vol3Dev &v, int64_t t, int mode, hipStream_t s) {
   if (rows_y == 2)
-    launch_tile<real, 2>(planes_z, fin, fout, out10, v, t, mode, s);
+    launch_tile<real, 2>(general, tiles, ntiles, fin, fout, out10, v, t, mode, s);
   else if (rows_y == 14)
-    launch_tile<real, 14>(planes_z, fin, fout, out10, v, t, mode, s);
+    launch_tile<real, 14>(general, tiles, ntiles, fin, fout, out10, v, t, mode, s);
   else
-    launch_tile<real, 6>(planes_z, fin, fout, out10, v, t, mode, s);
+    launch_tile<real, 6>(general, tiles, ntiles, fin, fout, out10, v, t, mode, s);
 }
 
 }  // namespace
 
-int launch_step3(bool f64, int rows_y, int planes_z, const void *fin, void *fout, void *out10,
-                 const Vol3Dev &v, int64_t t, int mode, hipStream_t s) {
+int launch_step3(bool f64, bool general, int rows_y, const Tile3Dev *tiles, int ntiles,
+                 const void *fin, void *fout, void *out10, const Vol3Dev &v, int64_t t, int mode,
+                 hipStream_t s) {
   if (f64)
-    launch_rows<double>(rows_y, planes_z, fin, fout, out10, v, t, mode, s);
+    launch_rows<double>(general, rows_y, tiles, ntiles, fin, fout, out10, v, t, mode, s);
   else
-    launch_rows<float>(rows_y, planes_z, fin, fout, out10, v, t, mode, s);
+    launch_rows<float>(general, rows_y, tiles, ntiles, fin, fout, out10, v, t, mode, s);
   return (int)hipGetLastError();
 }
 

@@ -58,8 +58,8 @@ class Solver3:
     def step(self, n: int) -> None:
         L3.lbm3_step(self.ctx, n)
 
-    def step_timed(self, n: int):
-        """(mean kernel ms per step, cells per launch)."""
+    def step_timed(self, n: int) -> dict:
+        """Mean durations and cells of the lean and general launches of a step."""
         return L3.lbm3_step_timed(self.ctx, n)
 
     def moments(self) -> torch.Tensor:

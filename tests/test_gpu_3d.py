@@ -173,3 +173,28 @@ def test_full_size_half_space_against_the_oracle():
     err = np.abs(got["fstar"] - ref["fstar"]).max() / np.abs(ref["fstar"]).max()
     print(f"[3d] 256^3 f32: worst rel L2 {w:.2e}, max rel {err:.2e}, tile {got['tile']}", flush=True)
     assert err < 1e-4
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_timed_steps_equal_overlapped_steps(dtype):
+    """lbm3_step (general kernel on the second stream beside the lean one)
+    and lbm3_step_timed (one after the other) give the same bits; the timing
+    reports both kernels and their cells add up to the volume."""
+    import torch
+    from paper_2009_06404_amd.solver3d import Solver3
+    p = volume_half_space(n=96, nz=70, sponge=8, src_depth=9, stride=3)
+    outs = []
+    for timed in (False, True):
+        s = Solver3(p, dtype=dtype, trace_steps=30)
+        try:
+            s.step(5)
+            kt = s.step_timed(25) if timed else s.step(25)
+            outs.append((s.state().double().cpu().numpy(), s.trace.double().cpu().numpy()))
+            torch.cuda.synchronize()
+        finally:
+            s.close()
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert kt["steps"] == 25 and kt["lean_ms"] > 0 and kt["general_ms"] > 0
+    assert kt["lean_cells"] + kt["general_cells"] == p.cells
+    assert kt["lean_cells"] > kt["general_cells"]
