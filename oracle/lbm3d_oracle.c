@@ -1,8 +1,9 @@
 /*
  * lbm3d_oracle.c -- plain FP64 reference implementation of the elastic-wave
- * lattice Boltzmann step on the regular three-dimensional D3Q19 lattice, the
- * extension the paper's Chapman-Enskog analysis covers for regular lattices
- * (Sec. 3: the isotropy conditions hold for D2Q9, D3Q15, D3Q19 and D3Q27).
+ * lattice Boltzmann step on the regular three-dimensional D3Q19 and D3Q27
+ * lattices, the extension the paper's Chapman-Enskog analysis covers for
+ * regular lattices (Sec. 3: the isotropy conditions hold for D2Q9, D3Q15,
+ * D3Q19 and D3Q27).
  *
  * TEST INFRASTRUCTURE. This file is the oracle against which the GPU library's
  * three-dimensional path is checked. It shares no code, header, table or
@@ -18,11 +19,14 @@
  * splits each phase's loop.
  *
  * Conventions (readings of the paper in three dimensions):
- *  - lattice: D3Q19, the rest vector, the 6 axis vectors and the 12 edge
- *    vectors (+-1 on two axes), weights 1/3, 1/18, 1/36, b^2 = 1/3; the
- *    order is the rest vector, then the pairs (+x,-x), (+y,-y), (+z,-z),
- *    (x+y), (-x-y), (x-y), (-x+y), (x+z), (-x-z), (x-z), (-x+z), (y+z),
- *    (-y-z), (y-z), (-y+z), so that the opposite of vector 2k-1 is 2k;
+ *  - lattices: D3Q19, the rest vector, the 6 axis vectors and the 12 edge
+ *    vectors (+-1 on two axes), weights 1/3, 1/18, 1/36; D3Q27, those and
+ *    the 8 corner vectors (+-1 on every axis), weights 8/27, 2/27, 1/54,
+ *    1/216; b^2 = 1/3 for both. The order is the rest vector, then the pairs
+ *    (+x,-x), (+y,-y), (+z,-z), (x+y), (-x-y), (x-y), (-x+y), (x+z), (-x-z),
+ *    (x-z), (-x+z), (y+z), (-y-z), (y-z), (-y+z), and for D3Q27 (x+y+z),
+ *    (-x-y-z), (x+y-z), (-x-y+z), (x-y+z), (-x+y-z), (-x+y+z), (x-y-z), so
+ *    that the opposite of vector 2k-1 is 2k;
  *  - volume: x fastest, then y, then z; z = 0 is the top face and z grows
  *    with depth; cell (x, y, z) of plane i is f[i*N + (z*ny + y)*nx + x];
  *  - populations are perturbations about the rest state f = 0;
@@ -61,24 +65,29 @@
 enum { F3_PERIODIC = 0, F3_FREE = 1, F3_RIGID = 2, F3_FREE0 = 3 };
 enum { F3_TOP = 0, F3_BOTTOM = 1, F3_LEFT = 2, F3_RIGHT = 3, F3_FRONT = 4, F3_BACK = 5 };
 
-#define Q3 19
+#define Q3 27 /* the largest velocity set; D3Q19 is its first 19 vectors */
 
-/* D3Q19 velocity set (Sec. 3, regular lattices). */
+/* D3Q19 and D3Q27 velocity sets (Sec. 3, regular lattices). */
 static const int V3[Q3][3] = {
     {0, 0, 0},
     {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
     {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
     {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
-    {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+    {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1},
+    {1, 1, 1},  {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1},
+    {1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1}};
 static const double B2_3 = 1.0 / 3.0;
 
-static double weight3(int i) {
+/* Weight of vector i of the q-velocity set, by its number of nonzero
+ * components (its speed class). */
+static double weight3(int q, int i) {
   const int n = abs(V3[i][0]) + abs(V3[i][1]) + abs(V3[i][2]);
-  return n == 0 ? 1.0 / 3.0 : (n == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+  if (q == 19) return n == 0 ? 1.0 / 3.0 : (n == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+  return n == 0 ? 8.0 / 27.0 : (n == 1 ? 2.0 / 27.0 : (n == 2 ? 1.0 / 54.0 : 1.0 / 216.0));
 }
 
-static int opposite3(int i) {
-  for (int k = 0; k < Q3; ++k)
+static int opposite3(int q, int i) {
+  for (int k = 0; k < q; ++k)
     if (V3[k][0] == -V3[i][0] && V3[k][1] == -V3[i][1] && V3[k][2] == -V3[i][2]) return k;
   return -1;
 }
@@ -94,19 +103,25 @@ typedef struct {
   int32_t nrec;
   int32_t comp_mask;      /* bit 0: v_x, bit 1: v_y, bit 2: v_z */
   const int32_t *rec_xyz; /* nrec x 3: x, y, z */
+  int32_t q;              /* 19 or 27 */
+  int32_t pad_;
 } oracle3_cfg;
 
-void oracle3_lattice(int32_t *c, double *w, int32_t *opp) {
-  for (int i = 0; i < Q3; ++i) {
+/* Velocities, weights and opposites of the q-velocity set (q = 19 or 27);
+ * returns q, or -1 for another q. */
+int oracle3_lattice(int32_t q, int32_t *c, double *w, int32_t *opp) {
+  if (q != 19 && q != 27) return -1;
+  for (int i = 0; i < q; ++i) {
     for (int a = 0; a < 3; ++a) c[3 * i + a] = V3[i][a];
-    w[i] = weight3(i);
-    opp[i] = opposite3(i);
+    w[i] = weight3(q, i);
+    opp[i] = opposite3(q, i);
   }
+  return q;
 }
 
 /* Elastic equilibrium (eqs. equilibrium-solid and Pn) on D3Q19.
  * P = (P_xx, P_xy, P_xz, P_yy, P_yz, P_zz). */
-void oracle3_equilibrium(double rho, const double j[3], const double P[6], double feq[Q3]) {
+void oracle3_equilibrium(int32_t q, double rho, const double j[3], const double P[6], double *feq) {
   double pn[3][3];
   pn[0][0] = P[0] - rho * B2_3;
   pn[0][1] = pn[1][0] = P[1];
@@ -114,21 +129,21 @@ void oracle3_equilibrium(double rho, const double j[3], const double P[6], doubl
   pn[1][1] = P[3] - rho * B2_3;
   pn[1][2] = pn[2][1] = P[4];
   pn[2][2] = P[5] - rho * B2_3;
-  for (int i = 0; i < Q3; ++i) {
+  for (int i = 0; i < q; ++i) {
     double jc = 0.0, pnq = 0.0;
     for (int a = 0; a < 3; ++a) {
       jc += j[a] * V3[i][a];
       for (int b = 0; b < 3; ++b)
         pnq += pn[a][b] * ((double)V3[i][a] * V3[i][b] - (a == b ? B2_3 : 0.0));
     }
-    feq[i] = weight3(i) * (rho + jc / B2_3 + pnq / (2.0 * B2_3 * B2_3));
+    feq[i] = weight3(q, i) * (rho + jc / B2_3 + pnq / (2.0 * B2_3 * B2_3));
   }
 }
 
 /* Moments of one cell: rho, the first moment m and P. */
-static void cell_moments(const double f[Q3], double *rho, double m[3], double P[6]) {
+static void cell_moments(int q, const double *f, double *rho, double m[3], double P[6]) {
   double r = 0.0, mm[3] = {0, 0, 0}, pp[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  for (int i = 0; i < Q3; ++i) {
+  for (int i = 0; i < q; ++i) {
     r += f[i];
     for (int a = 0; a < 3; ++a) {
       mm[a] += f[i] * V3[i][a];
@@ -143,19 +158,19 @@ static void cell_moments(const double f[Q3], double *rho, double m[3], double P[
 
 /* One cell of the collision (eqs. MomentsFeq, Si, LBGK, MomentChainAbsorbing).
  * G: source without the sponge; A: sponge damping. Returns f*, and j and S. */
-void oracle3_collide_cell(const double f[Q3], const double G[3], double A, double tau,
-                          double fstar[Q3], double j_out[3], double S_out[3]) {
+void oracle3_collide_cell(int32_t q, const double *f, const double G[3], double A, double tau,
+                          double *fstar, double j_out[3], double S_out[3]) {
   double rho, m[3], P[6];
-  cell_moments(f, &rho, m, P);
+  cell_moments(q, f, &rho, m, P);
   double j[3], S[3];
   for (int a = 0; a < 3; ++a) {
     j[a] = (m[a] + 0.5 * G[a]) / (1.0 + 0.5 * A);
     S[a] = G[a] - A * j[a];
   }
   double feq[Q3];
-  oracle3_equilibrium(rho, j, P, feq);
-  for (int i = 0; i < Q3; ++i) {
-    const double Si = weight3(i) * (V3[i][0] * S[0] + V3[i][1] * S[1] + V3[i][2] * S[2]) / B2_3;
+  oracle3_equilibrium(q, rho, j, P, feq);
+  for (int i = 0; i < q; ++i) {
+    const double Si = weight3(q, i) * (V3[i][0] * S[0] + V3[i][1] * S[1] + V3[i][2] * S[2]) / B2_3;
     fstar[i] = f[i] - (f[i] - feq[i]) / tau + (1.0 - 1.0 / (2.0 * tau)) * Si;
   }
   if (j_out) for (int a = 0; a < 3; ++a) j_out[a] = j[a];
@@ -169,6 +184,7 @@ static double ricker3(double t, double period, double t0) {
 
 typedef struct {
   const oracle3_cfg *c;
+  int q;              /* velocities */
   int n[3];           /* nx, ny, nz */
   size_t N;
   double *kappa, *A, *inv_rho0_rec;
@@ -210,9 +226,9 @@ static void phase3_moments(grid3 *g, const double *f) {
 #pragma omp parallel for schedule(static)
   for (size_t k = 0; k < g->N; ++k) {
     double fc[Q3], P[6];
-    for (int i = 0; i < Q3; ++i) fc[i] = f[i * g->N + k];
+    for (int i = 0; i < g->q; ++i) fc[i] = f[i * g->N + k];
     double m[3];
-    cell_moments(fc, &g->rho[k], m, P);
+    cell_moments(g->q, fc, &g->rho[k], m, P);
     for (int a = 0; a < 3; ++a) g->m[a][k] = m[a];
     for (int q = 0; q < 6; ++q) g->P[q][k] = P[q];
   }
@@ -290,10 +306,10 @@ static void phase3_collide(grid3 *g, const double *f, double *fstar) {
 #pragma omp parallel for schedule(static)
   for (size_t k = 0; k < g->N; ++k) {
     double fc[Q3], fs[Q3], j[3];
-    for (int i = 0; i < Q3; ++i) fc[i] = f[i * g->N + k];
+    for (int i = 0; i < g->q; ++i) fc[i] = f[i * g->N + k];
     const double G[3] = {g->G[0][k], g->G[1][k], g->G[2][k]};
-    oracle3_collide_cell(fc, G, g->A[k], tau, fs, j, NULL);
-    for (int i = 0; i < Q3; ++i) fstar[i * g->N + k] = fs[i];
+    oracle3_collide_cell(g->q, fc, G, g->A[k], tau, fs, j, NULL);
+    for (int i = 0; i < g->q; ++i) fstar[i * g->N + k] = fs[i];
     for (int a = 0; a < 3; ++a) g->j[a][k] = j[a];
   }
 }
@@ -327,7 +343,7 @@ static double free_value3(const grid3 *g, size_t kb, size_t kin, int i, int orde
   /* w_i (rho + P^n : Q / (2 b^4)) is the equilibrium at zero flux */
   const double jz[3] = {0, 0, 0};
   double feq[Q3];
-  oracle3_equilibrium(rho_air, jz, pair, feq);
+  oracle3_equilibrium(g->q, rho_air, jz, pair, feq);
   return -fs + 2.0 * feq[i];
 }
 
@@ -341,7 +357,7 @@ static void phase3_stream(grid3 *g, const double *fstar, double *fnext) {
       for (int x = 0; x < g->n[0]; ++x) {
         const int p[3] = {x, y, z};
         const size_t k = idx3(g, x, y, z);
-        for (int i = 0; i < Q3; ++i) {
+        for (int i = 0; i < g->q; ++i) {
           int d[3], rigid = 0, free_nz = 0, order = 0;
           for (int ax = 0; ax < 3; ++ax) {
             d[ax] = p[ax] + V3[i][ax];
@@ -358,7 +374,7 @@ static void phase3_stream(grid3 *g, const double *fstar, double *fnext) {
             }
           }
           const double fs = fstar[i * N + k];
-          const int o = opposite3(i);
+          const int o = opposite3(g->q, i);
           if (rigid) {
             fnext[o * N + k] = fs;
           } else if (free_nz != 0) {
@@ -384,6 +400,7 @@ static int grid3_alloc(grid3 *g, const oracle3_cfg *c, const double *lam, const 
                        const double *rho0) {
   memset(g, 0, sizeof(*g));
   g->c = c;
+  g->q = c->q;
   g->n[0] = c->nx; g->n[1] = c->ny; g->n[2] = c->nz;
   g->N = (size_t)c->nx * c->ny * c->nz;
   double **planes[] = {&g->kappa, &g->A, &g->rho, &g->m[0], &g->m[1], &g->m[2],
@@ -405,8 +422,8 @@ static int grid3_alloc(grid3 *g, const oracle3_cfg *c, const double *lam, const 
   return 0;
 }
 
-/* Run nsteps steps from time t0.
- *   init: 19 planes of populations or NULL (rest state); init_kind 0: the
+/* Run nsteps steps from time t0 on the lattice c->q (19 or 27).
+ *   init: q planes of populations or NULL (rest state); init_kind 0: the
  *     post-collision populations of step t0-1, 1: the pre-collision
  *     populations at t0;
  *   fstar_out: post-collision populations of step t0+nsteps-1 (or NULL);
@@ -414,24 +431,27 @@ static int grid3_alloc(grid3 *g, const oracle3_cfg *c, const double *lam, const 
  *   mom_out: [10][N] rho, j_x, j_y, j_z, P_xx, P_xy, P_xz, P_yy, P_yz, P_zz
  *     at t0+nsteps (or NULL);
  *   trace: [nsteps][nrec][ncomp] (or NULL).
- * Returns 0, or -2 when memory runs out. */
+ * Returns 0, -1 for a lattice other than 19 or 27, or -2 when memory runs
+ * out. */
 int oracle3_run(const oracle3_cfg *c, const double *lam, const double *mu, const double *rho0,
                 const double *init, int32_t init_kind, int64_t t0, int64_t nsteps,
                 double *fstar_out, double *f_out, double *mom_out, double *trace) {
+  if (c->q != 19 && c->q != 27) return -1;
   grid3 g;
   if (grid3_alloc(&g, c, lam, mu, rho0) != 0) { grid3_free(&g); return -2; }
   const size_t N = g.N;
-  double *f = (double *)calloc(Q3 * N, sizeof(double));
-  double *fs = (double *)calloc(Q3 * N, sizeof(double));
+  const size_t Q = (size_t)c->q;
+  double *f = (double *)calloc(Q * N, sizeof(double));
+  double *fs = (double *)calloc(Q * N, sizeof(double));
   if (!f || !fs) { free(f); free(fs); grid3_free(&g); return -2; }
   int ncomp = 0;
   for (int a = 0; a < 3; ++a) ncomp += (c->comp_mask >> a) & 1;
   if (init && init_kind == 0) {
-    memcpy(fs, init, Q3 * N * sizeof(double));
+    memcpy(fs, init, Q * N * sizeof(double));
     phase3_moments(&g, fs);
     phase3_stream(&g, fs, f);
   } else if (init) {
-    memcpy(f, init, Q3 * N * sizeof(double));
+    memcpy(f, init, Q * N * sizeof(double));
   }
   for (int64_t n = 0; n < nsteps; ++n) {
     phase3_moments(&g, f);
@@ -441,8 +461,8 @@ int oracle3_run(const oracle3_cfg *c, const double *lam, const double *mu, const
     if (trace && c->nrec > 0) phase3_receivers(&g, trace + (size_t)n * c->nrec * ncomp);
     phase3_stream(&g, fs, f);
   }
-  if (fstar_out) memcpy(fstar_out, fs, Q3 * N * sizeof(double));
-  if (f_out) memcpy(f_out, f, Q3 * N * sizeof(double));
+  if (fstar_out) memcpy(fstar_out, fs, Q * N * sizeof(double));
+  if (f_out) memcpy(f_out, f, Q * N * sizeof(double));
   if (mom_out) {
     phase3_moments(&g, f);
     phase3_gradient(&g);

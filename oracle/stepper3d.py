@@ -1,8 +1,8 @@
 """ctypes front end of the D3Q19 oracle (test infrastructure, see ``oracle/__init__``).
 
 ``run(problem, ...)`` executes the three-dimensional form of the paper's
-scheme in FP64 on the CPU and returns the populations, the macroscopic fields
-and the receiver traces.
+scheme (D3Q19 or D3Q27, ``problem.q``) in FP64 on the CPU and returns the
+populations, the macroscopic fields and the receiver traces.
 """
 from __future__ import annotations
 
@@ -16,7 +16,7 @@ from .stepper import lib
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
 
-Q = 19
+LATTICES = (19, 27)
 
 
 class Oracle3Cfg(C.Structure):
@@ -30,6 +30,7 @@ class Oracle3Cfg(C.Structure):
         ("src", _dp),
         ("nrec", C.c_int32), ("comp_mask", C.c_int32),
         ("rec_xyz", _ip),
+        ("q", C.c_int32), ("pad_", C.c_int32),
     ]
 
 
@@ -44,11 +45,11 @@ def _lib():
         L.oracle3_run.argtypes = [C.POINTER(Oracle3Cfg), _dp, _dp, _dp, _dp, C.c_int32,
                                   C.c_int64, C.c_int64, _dp, _dp, _dp, _dp]
         L.oracle3_collide_cell.restype = None
-        L.oracle3_collide_cell.argtypes = [_dp, _dp, C.c_double, C.c_double, _dp, _dp, _dp]
+        L.oracle3_collide_cell.argtypes = [C.c_int32, _dp, _dp, C.c_double, C.c_double, _dp, _dp, _dp]
         L.oracle3_equilibrium.restype = None
-        L.oracle3_equilibrium.argtypes = [C.c_double, _dp, _dp, _dp]
-        L.oracle3_lattice.restype = None
-        L.oracle3_lattice.argtypes = [_ip, _dp, _ip]
+        L.oracle3_equilibrium.argtypes = [C.c_int32, C.c_double, _dp, _dp, _dp]
+        L.oracle3_lattice.restype = C.c_int
+        L.oracle3_lattice.argtypes = [C.c_int32, _ip, _dp, _ip]
         _bound = True
     return L
 
@@ -59,31 +60,33 @@ def _ptr(a, ct=_dp):
     return a.ctypes.data_as(ct)
 
 
-def lattice():
-    """(c (19, 3) int, w (19,), opp (19,)) of the oracle's D3Q19 table."""
-    c = np.zeros((Q, 3), np.int32)
-    w = np.zeros(Q)
-    opp = np.zeros(Q, np.int32)
-    _lib().oracle3_lattice(_ptr(c, _ip), _ptr(w), _ptr(opp, _ip))
+def lattice(q: int = 19):
+    """(c (q, 3) int, w (q,), opp (q,)) of the oracle's D3Q19 / D3Q27 table."""
+    c = np.zeros((q, 3), np.int32)
+    w = np.zeros(q)
+    opp = np.zeros(q, np.int32)
+    if _lib().oracle3_lattice(q, _ptr(c, _ip), _ptr(w), _ptr(opp, _ip)) != q:
+        raise ValueError("lattice must be 19 or 27")
     return c, w, opp
 
 
-def equilibrium(rho: float, j, P):
+def equilibrium(rho: float, j, P, q: int = 19):
     """P = (P_xx, P_xy, P_xz, P_yy, P_yz, P_zz)."""
     j = np.ascontiguousarray(j, dtype=np.float64)
     P = np.ascontiguousarray(P, dtype=np.float64)
-    out = np.zeros(Q)
-    _lib().oracle3_equilibrium(float(rho), _ptr(j), _ptr(P), _ptr(out))
+    out = np.zeros(q)
+    _lib().oracle3_equilibrium(q, float(rho), _ptr(j), _ptr(P), _ptr(out))
     return out
 
 
 def collide_cell(f, G, A: float, tau: float):
     f = np.ascontiguousarray(f, dtype=np.float64)
+    q = f.size
     G = np.ascontiguousarray(G, dtype=np.float64)
-    fs = np.zeros(Q)
+    fs = np.zeros(q)
     j = np.zeros(3)
     S = np.zeros(3)
-    _lib().oracle3_collide_cell(_ptr(f), _ptr(G), float(A), float(tau), _ptr(fs), _ptr(j), _ptr(S))
+    _lib().oracle3_collide_cell(q, _ptr(f), _ptr(G), float(A), float(tau), _ptr(fs), _ptr(j), _ptr(S))
     return fs, j, S
 
 
@@ -111,6 +114,7 @@ def _cfg(p):
     cfg.nrec = int(rec.shape[0])
     cfg.comp_mask = int(p.comp_mask)
     cfg.rec_xyz = _ptr(rec_buf, _ip)
+    cfg.q = int(getattr(p, "q", 19))
     return cfg, keep
 
 
@@ -119,7 +123,7 @@ def run(p, nsteps: Optional[int] = None, t0: int = 0,
         want_trace: bool = True):
     """Run the D3Q19 oracle on ``p`` for ``nsteps`` steps from time ``t0``.
 
-    fstar_init: post-collision state at t0-1, shape (19, nz, ny, nx); or
+    fstar_init: post-collision state at t0-1, shape (q, nz, ny, nx); or
     f_init: pre-collision state at t0; neither: the rest state. Returns a dict
     with ``fstar`` (t0+n-1), ``f`` (t0+n), ``mom`` (10, nz, ny, nx) = rho, j,
     P_xx, P_xy, P_xz, P_yy, P_yz, P_zz at t0+n, and ``trace`` (n, nrec, ncomp).
@@ -127,7 +131,7 @@ def run(p, nsteps: Optional[int] = None, t0: int = 0,
     n = p.nsteps if nsteps is None else int(nsteps)
     lam, mu, rho0 = p.full()
     cfg, keep = _cfg(p)
-    shape = (Q,) + p.shape
+    shape = (cfg.q,) + p.shape
     fs_out = np.zeros(shape)
     f_out = np.zeros(shape)
     mom = np.zeros((10,) + p.shape)

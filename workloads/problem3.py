@@ -56,6 +56,7 @@ class Problem3:
     comp_mask: int = 7                        # bit0 v_x, bit1 v_y, bit2 v_z
     nsteps: int = 0
     name: str = ""
+    q: int = 19                               # lattice: D3Q19 or D3Q27
 
     @property
     def shape(self) -> Tuple[int, int, int]:
@@ -103,7 +104,7 @@ def surface_receivers(nx: int, ny: int, stride: int = 1, z: int = 0) -> np.ndarr
 
 def volume_half_space(n: int = 256, nz: Optional[int] = None, nsteps: int = 2000,
                       nu: float = 0.25, sponge: int = 24, src_depth: int = 12,
-                      top: int = BC_FREE0, stride: int = 4) -> Problem3:
+                      top: int = BC_FREE0, stride: int = 4, q: int = 19) -> Problem3:
     """The plain workload in three dimensions: an n x n x nz half-space with a
     free surface on top, sponges on the bottom (rigid behind it) and the four
     sides (periodic behind them), homogeneous solid, a vertical Ricker source
@@ -120,11 +121,11 @@ def volume_half_space(n: int = 256, nz: Optional[int] = None, nsteps: int = 2000
         sponge_profiles=(None, prof, prof, prof, prof, prof),
         sources=[Source3(n / 2.0, n / 2.0, float(src_depth), 3.0, 0.0, 0.0, 1.0, 1.0, 40.0, 60.0)],
         receivers=surface_receivers(n, n, stride), comp_mask=4, nsteps=nsteps,
-        name="volume_half_space")
+        name="volume_half_space", q=q)
 
 
 def volume_field(nx: int = 72, ny: int = 40, nz: int = 34, seed: int = 5, nsteps: int = 40,
-                 faces=(BC_PERIODIC,) * 6, tau: float = 0.9) -> Problem3:
+                 faces=(BC_PERIODIC,) * 6, tau: float = 0.9, q: int = 19) -> Problem3:
     """A cell-wise random solid (mu in [0.036, 0.044], nu in [0.1, 0.3]) with
     an oblique source and scattered receivers recording all three components."""
     rng = np.random.default_rng(seed)
@@ -140,7 +141,7 @@ def volume_field(nx: int = 72, ny: int = 40, nz: int = 34, seed: int = 5, nsteps
     return Problem3(nx=nx, ny=ny, nz=nz, faces=tuple(faces), lam=lam, mu=mu, rho0=rho0,
                     tau=tau, sources=[Source3(nx * 0.4, ny * 0.55, nz * 0.45, 2.5, d[0], d[1], d[2],
                                               1.0, 10.0, 12.0)],
-                    receivers=rec, comp_mask=7, nsteps=nsteps, name="volume_field")
+                    receivers=rec, comp_mask=7, nsteps=nsteps, name="volume_field", q=q)
 
 
 __all__ = ["FACES", "Source3", "Problem3", "surface_receivers", "volume_half_space",
