@@ -142,13 +142,15 @@ def bench_filter(torch, w, Solver, steps_ms: float, passes: int = 20) -> dict:
             "vs_one_step": round(ms / steps_ms, 3)}
 
 
-def bench_volume(torch, dtype: str = "f32", n: int = 256, steps: int = 400, warmup: int = 20) -> dict:
-    """The three-dimensional (D3Q19) step on the 256^3 half-space (free
-    surface, sponges, source, 4096 surface receivers): one kernel launch per
-    step, 2 x 19 population words per cell (152 B in FP32)."""
+def bench_volume(torch, dtype: str = "f32", n: int = 256, steps: int = 400, warmup: int = 20,
+                 q: int = 19) -> dict:
+    """The three-dimensional step (D3Q19 or D3Q27) on the 256^3 half-space
+    (free surface, sponges, source, 4096 surface receivers): a lean and a
+    general launch per step, 2 x q population words per cell (152 B / 216 B
+    in FP32)."""
     from workloads.problem3 import volume_half_space
     from paper_2009_06404_amd.solver3d import Solver3
-    p = volume_half_space(n=n, nsteps=warmup + steps)
+    p = volume_half_space(n=n, nsteps=warmup + steps, q=q)
     s = Solver3(p, dtype=dtype, trace_steps=warmup + steps + 50)
     s.step(warmup)
     torch.cuda.synchronize()
@@ -163,10 +165,10 @@ def bench_volume(torch, dtype: str = "f32", n: int = 256, steps: int = 400, warm
     tile = s.tile()
     s.close()
     esize = 4 if dtype == "f32" else 8
-    per_cell = 38 * esize
+    per_cell = 2 * q * esize
     kms, kcells = kt["lean_ms"], kt["lean_cells"]
     gbps = per_cell * kcells / (kms / 1e3) / 1e9
-    return {"workload": f"volume_half_space {n}^3 {dtype.upper()} (D3Q19): free surface top, "
+    return {"workload": f"volume_half_space {n}^3 {dtype.upper()} (D3Q{q}): free surface top, "
                         f"24-cell sponges (rigid bottom, periodic sides), nu=0.25, vertical Ricker "
                         f"source at depth 12, {p.nrec} surface receivers",
             "GLUPS": round(p.cells / ms / 1e6, 3), "ms_per_step": round(ms, 4), "steps": steps,
@@ -294,7 +296,8 @@ def main():
                     help="steps of the per-kernel event-timing pass after the timed region")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the HBM-scale, batched and adjoint measurements")
-    ap.add_argument("--only", choices=["hbm_scale", "batched", "adjoint", "filter", "volume"],
+    ap.add_argument("--only", choices=["hbm_scale", "batched", "adjoint", "filter", "volume",
+                                       "volume27"],
                     help="run only this one of the extra measurements and print it")
     ap.add_argument("--adjoint-steps", type=int, default=5000)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -339,7 +342,8 @@ def main():
               "adjoint": lambda: bench_adjoint(torch, w, Solver, float("nan"),
                                                nsteps=args.adjoint_steps),
               "filter": lambda: bench_filter(torch, w, Solver, float("nan")),
-              "volume": lambda: bench_volume(torch, args.dtype)}[args.only]
+              "volume": lambda: bench_volume(torch, args.dtype),
+              "volume27": lambda: bench_volume(torch, args.dtype, q=27)}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
     p = w.plain_large(n=args.n, dtype=args.dtype)
@@ -414,7 +418,8 @@ def main():
                          ("batched", lambda: bench_batched(torch, w, Solver, glups)),
                          ("adjoint", lambda: bench_adjoint(torch, w, Solver, glups)),
                          ("filter", lambda: bench_filter(torch, w, Solver, ms_step)),
-                         ("volume_d3q19", lambda: bench_volume(torch))):
+                         ("volume_d3q19", lambda: bench_volume(torch)),
+                         ("volume_d3q27", lambda: bench_volume(torch, q=27))):
             print(f"[bench] {name} ...", file=sys.stderr, flush=True)
             extras[name] = fn()
             torch.cuda.empty_cache()

@@ -1,9 +1,9 @@
 /*
- * lbm3d.h -- C ABI of the three-dimensional (D3Q19) elastic-wave lattice
- * Boltzmann step of liblbm.so on MI355X (gfx950).
+ * lbm3d.h -- C ABI of the three-dimensional (D3Q19 / D3Q27) elastic-wave
+ * lattice Boltzmann step of liblbm.so on MI355X (gfx950).
  *
- * The step is the one of lbm.h carried to the regular D3Q19 lattice, which the
- * paper's Chapman-Enskog analysis covers (Escande, Kolluru, Cleon & Sagaut,
+ * The step is the one of lbm.h carried to the regular D3Q19 and D3Q27
+ * lattices, which the paper's Chapman-Enskog analysis covers (Escande, Kolluru, Cleon & Sagaut,
  * arXiv 2009.06404, Sec. 3: the isotropy conditions of D2Q9, D3Q15, D3Q19 and
  * D3Q27): BGK collision toward the elastic equilibrium (eqs. equilibrium-solid
  * and Pn with the full 3 x 3 second moment), the source of eq. S (elastic force
@@ -19,10 +19,14 @@
  *    grows with depth.
  *  - Directions: the rest vector, then (+x,-x), (+y,-y), (+z,-z), (x+y),
  *    (-x-y), (x-y), (-x+y), (x+z), (-x-z), (x-z), (-x+z), (y+z), (-y-z),
- *    (y-z), (-y+z); weights 1/3, 1/18 (axes), 1/36 (edges); b^2 = 1/3.
+ *    (y-z), (-y+z) -- D3Q19, weights 1/3, 1/18 (axes), 1/36 (edges) -- and
+ *    for D3Q27 also (x+y+z), (-x-y-z), (x+y-z), (-x-y+z), (x-y+z), (-x+y-z),
+ *    (-x+y+z), (x-y-z), weights 8/27, 2/27, 1/54, 1/216 (corners); the
+ *    opposite of direction 2k-1 is 2k; b^2 = 1/3.
  *  - One volume per context; kappa = b^2 (mu - lambda) / mu per cell.
  *  - Free surfaces (top and bottom faces only): anti-bounce-back toward the
- *    air state whose density and tangential stress (P_xx, P_xy, P_yy) are the
+ *    air state whose density and tangential stress (P_xx, P_xy, P_yy; P_xy
+ *    enters through D3Q27's corner links only) are the
  *    boundary cell's (LBM_FREE0) or extrapolated half a cell out (LBM_FREE),
  *    with the stress rows along the normal zero (P_air n = 0, Sec. 6.2). A link
  *    that leaves through several faces bounces back as rigid if any of them is
@@ -46,6 +50,8 @@ extern "C" {
 
 typedef struct lbm3_ctx lbm3_ctx; /* opaque, owned by the library */
 
+enum { LBM3_D3Q19 = 19, LBM3_D3Q27 = 27 }; /* velocity sets */
+
 enum { LBM3_FACE_TOP = 0, LBM3_FACE_BOTTOM = 1, LBM3_FACE_LEFT = 2, LBM3_FACE_RIGHT = 3,
        LBM3_FACE_FRONT = 4, LBM3_FACE_BACK = 5 };
 
@@ -67,14 +73,17 @@ typedef struct {
   double x, y, z, sigma, dir_x, dir_y, dir_z, amp, period, t0;
 } lbm3_source;
 
-/* Bytes of device workspace lbm3_init needs: two population buffers of
- * 19 x pitch x ny x nz elements (pitch = nx rounded up to 64) and one
- * pitch x ny x nz plane of kappa. Synchronous, host only. Returns LBM_OK or
- * LBM_E_INVALID (a side < 3, a bad dtype, more than 2^31 cells, or one z
- * plane of populations, 19 x pitch x ny elements, of 2 GiB or more). */
-int lbm3_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t dtype, size_t *bytes);
+/* Bytes of device workspace lbm3_init needs for the q-velocity set (q =
+ * LBM3_D3Q19 or LBM3_D3Q27): two population buffers of q x pitch x ny x nz
+ * elements (pitch = nx rounded up to 64) and one pitch x ny x nz plane of
+ * kappa. Synchronous, host only. Returns LBM_OK or LBM_E_INVALID (a side < 3,
+ * another q, a bad dtype, more than 2^31 cells, or one z plane of
+ * populations, q x pitch x ny elements, of 2 GiB or more). */
+int lbm3_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t q, int32_t dtype,
+                         size_t *bytes);
 
-/* Create a context for one nx x ny x nz volume at time t = 0, rest state.
+/* Create a context for one nx x ny x nz volume on the q-velocity set
+ * (LBM3_D3Q19 or LBM3_D3Q27) at time t = 0, rest state.
  *  lam, mu, rho: DEVICE arrays of dtype, [nz][ny][nx]; 0 <= nu < 1/2 and
  *    mu, rho > 0 per cell (checked on the device).
  *  tau > 1/2. bc: host struct as above.
@@ -82,7 +91,7 @@ int lbm3_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t dtype, size
  *    owned by the caller and used only by this context.
  *  hip_stream: the hipStream_t all work goes to (NULL = default stream).
  * Synchronous. Returns LBM_OK, LBM_E_INVALID, LBM_E_NOMEM or LBM_E_DEVICE. */
-int lbm3_init(lbm3_ctx **ctx, int32_t nx, int32_t ny, int32_t nz, int32_t dtype,
+int lbm3_init(lbm3_ctx **ctx, int32_t nx, int32_t ny, int32_t nz, int32_t q, int32_t dtype,
               const void *lam, const void *mu, const void *rho, double tau,
               const lbm3_bc *bc, void *workspace, size_t ws_bytes, void *hip_stream);
 
@@ -129,7 +138,7 @@ int lbm3_moments(lbm3_ctx *ctx, void *out10);
 int lbm3_get_time(const lbm3_ctx *ctx, int64_t *t);
 
 /* Copy the state (post-collision populations of step t-1, DEVICE
- * [19][nz][ny][nx] of dtype, direction order above) out of / into the
+ * [q][nz][ny][nx] of dtype, direction order above) out of / into the
  * context; set_state makes t the context time and restarts the receiver
  * trace at row 0 when t differs from it. Asynchronous. */
 int lbm3_get_state(lbm3_ctx *ctx, void *dst);

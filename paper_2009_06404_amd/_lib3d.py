@@ -1,4 +1,4 @@
-"""ctypes binding of the three-dimensional (D3Q19) entry points of liblbm.so
+"""ctypes binding of the three-dimensional (D3Q19 / D3Q27) entry points of liblbm.so
 (include/lbm3d.h): argument marshalling only, one wrapper per entry point with
 the C name. Errors raise :class:`LBMError` with the library's message."""
 from __future__ import annotations
@@ -14,6 +14,7 @@ ENTRY_POINTS = (
 )
 
 FACE_TOP, FACE_BOTTOM, FACE_LEFT, FACE_RIGHT, FACE_FRONT, FACE_BACK = range(6)
+D3Q19, D3Q27 = 19, 27
 
 _dp = C.POINTER(C.c_double)
 
@@ -42,8 +43,8 @@ def lib():
         vp = C.c_void_p
         i32, i64 = C.c_int32, C.c_int64
         sig = {
-            "lbm3_workspace_bytes": ([i32, i32, i32, i32, C.POINTER(C.c_size_t)], C.c_int),
-            "lbm3_init": ([C.POINTER(vp), i32, i32, i32, i32, vp, vp, vp, C.c_double,
+            "lbm3_workspace_bytes": ([i32, i32, i32, i32, i32, C.POINTER(C.c_size_t)], C.c_int),
+            "lbm3_init": ([C.POINTER(vp), i32, i32, i32, i32, i32, vp, vp, vp, C.c_double,
                            C.POINTER(lbm3_bc), vp, C.c_size_t, vp], C.c_int),
             "lbm3_set_sources": ([vp, C.POINTER(lbm3_source), i32], C.c_int),
             "lbm3_set_receivers": ([vp, C.POINTER(C.c_int32), i32, i32, vp, i64], C.c_int),
@@ -65,9 +66,9 @@ def lib():
     return L
 
 
-def lbm3_workspace_bytes(nx: int, ny: int, nz: int, dtype: int) -> int:
+def lbm3_workspace_bytes(nx: int, ny: int, nz: int, q: int, dtype: int) -> int:
     out = C.c_size_t(0)
-    check(lib().lbm3_workspace_bytes(nx, ny, nz, dtype, C.byref(out)))
+    check(lib().lbm3_workspace_bytes(nx, ny, nz, q, dtype, C.byref(out)))
     return out.value
 
 
@@ -85,9 +86,9 @@ def make_bc(faces, thick=(0,) * 6, profiles=(None,) * 6):
     return bc, keep
 
 
-def lbm3_init(nx, ny, nz, dtype, lam_ptr, mu_ptr, rho_ptr, tau, bc, ws_ptr, ws_bytes, stream_ptr):
+def lbm3_init(nx, ny, nz, q, dtype, lam_ptr, mu_ptr, rho_ptr, tau, bc, ws_ptr, ws_bytes, stream_ptr):
     ctx = C.c_void_p()
-    check(lib().lbm3_init(C.byref(ctx), nx, ny, nz, dtype, lam_ptr, mu_ptr, rho_ptr, float(tau),
+    check(lib().lbm3_init(C.byref(ctx), nx, ny, nz, q, dtype, lam_ptr, mu_ptr, rho_ptr, float(tau),
                           C.byref(bc), ws_ptr, ws_bytes, stream_ptr))
     return ctx
 

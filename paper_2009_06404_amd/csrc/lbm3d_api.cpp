@@ -1,4 +1,4 @@
-// C ABI of the three-dimensional (D3Q19) step of liblbm.so: argument
+// C ABI of the three-dimensional (D3Q19 / D3Q27) step of liblbm.so: argument
 // validation, workspace layout, device tables (sponge damping, sources,
 // receivers), launches. The kernels are in lbm3d_kernels.hip.
 #include <hip/hip_runtime.h>
@@ -34,6 +34,7 @@ int fail3(int code, const std::string &msg) { return lbm::report_error(code, msg
 int64_t up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 struct Layout3 {
+  int32_t q = 19;
   int32_t pitch = 0;
   int64_t zplane = 0;    // elements per z plane of populations
   int64_t f_elems = 0;   // one population buffer
@@ -43,14 +44,16 @@ struct Layout3 {
   size_t bytes() const { return 2 * f_bytes() + (size_t)up(k_elems * (int64_t)esize, 256) + 256; }
 };
 
-int make_layout3(int32_t nx, int32_t ny, int32_t nz, int32_t dtype, Layout3 *L) {
+int make_layout3(int32_t nx, int32_t ny, int32_t nz, int32_t q, int32_t dtype, Layout3 *L) {
   if (dtype != LBM_F32 && dtype != LBM_F64) return fail3(LBM_E_INVALID, "dtype must be LBM_F32 or LBM_F64");
+  if (q != kQ19 && q != kQ27) return fail3(LBM_E_INVALID, "lattice must be LBM3_D3Q19 or LBM3_D3Q27");
   if (nx < 3 || ny < 3 || nz < 3) return fail3(LBM_E_INVALID, "nx, ny and nz must be >= 3");
   if ((int64_t)nx * ny * nz > (int64_t)INT32_MAX)
     return fail3(LBM_E_INVALID, "volume larger than 2^31 cells");
   L->esize = dtype == LBM_F64 ? 8 : 4;
   L->pitch = (int32_t)up(nx, 64);
-  L->zplane = (int64_t)ny * kQ * L->pitch;
+  L->q = q;
+  L->zplane = (int64_t)ny * q * L->pitch;
   // the kernels address a plane of populations with 32-bit byte offsets
   // behind a buffer descriptor of 2^31 - 1 bytes
   if (L->zplane * (int64_t)L->esize > (int64_t)INT32_MAX)
@@ -302,22 +305,23 @@ std::vector<char> damp_table(const lbm3_ctx *c) {
 
 extern "C" {
 
-int lbm3_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t dtype, size_t *bytes) {
+int lbm3_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t q, int32_t dtype,
+                         size_t *bytes) {
   if (!bytes) return fail3(LBM_E_INVALID, "bytes required");
   Layout3 L;
-  const int rc = make_layout3(nx, ny, nz, dtype, &L);
+  const int rc = make_layout3(nx, ny, nz, q, dtype, &L);
   if (rc) return rc;
   *bytes = L.bytes();
   return LBM_OK;
 }
 
-int lbm3_init(lbm3_ctx **ctx, int32_t nx, int32_t ny, int32_t nz, int32_t dtype, const void *lam,
-              const void *mu, const void *rho, double tau, const lbm3_bc *bc, void *workspace,
-              size_t ws_bytes, void *hip_stream) {
+int lbm3_init(lbm3_ctx **ctx, int32_t nx, int32_t ny, int32_t nz, int32_t q, int32_t dtype,
+              const void *lam, const void *mu, const void *rho, double tau, const lbm3_bc *bc,
+              void *workspace, size_t ws_bytes, void *hip_stream) {
   if (!ctx) return fail3(LBM_E_INVALID, "ctx required");
   *ctx = nullptr;
   Layout3 L;
-  int rc = make_layout3(nx, ny, nz, dtype, &L);
+  int rc = make_layout3(nx, ny, nz, q, dtype, &L);
   if (rc) return rc;
   if (!(tau > 0.5) || !std::isfinite(tau)) return fail3(LBM_E_INVALID, "tau must be > 1/2");
   if (!bc) return fail3(LBM_E_INVALID, "bc required");
@@ -388,6 +392,7 @@ int lbm3_init(lbm3_ctx **ctx, int32_t nx, int32_t ny, int32_t nz, int32_t dtype,
 
   Vol3Dev &v = c->v;
   v.nx = nx; v.ny = ny; v.nz = nz; v.pitch = L.pitch;
+  v.q = q;
   for (int f = 0; f < 6; ++f) v.face[f] = bc->face[f];
   v.kcells = kmin != kmax;
   v.kscalar = kmin;
@@ -543,7 +548,8 @@ int lbm3_get_time(const lbm3_ctx *c, int64_t *t) {
 
 int lbm3_get_state(lbm3_ctx *c, void *dst) {
   if (!c || !dst) return fail3(LBM_E_INVALID, "context and dst required");
-  if (launch_pack3(f64(c), c->fbuf[c->cur], dst, c->nx, c->ny, c->nz, c->L.pitch, false, c->stream))
+  if (launch_pack3(f64(c), c->L.q, c->fbuf[c->cur], dst, c->nx, c->ny, c->nz, c->L.pitch, false,
+                   c->stream))
     return fail3(LBM_E_DEVICE, "state copy failed");
   return LBM_OK;
 }
@@ -551,7 +557,8 @@ int lbm3_get_state(lbm3_ctx *c, void *dst) {
 int lbm3_set_state(lbm3_ctx *c, const void *src, int64_t t) {
   if (!c || !src) return fail3(LBM_E_INVALID, "context and src required");
   if (t < 0) return fail3(LBM_E_INVALID, "t must be >= 0");
-  if (launch_pack3(f64(c), src, c->fbuf[c->cur], c->nx, c->ny, c->nz, c->L.pitch, true, c->stream))
+  if (launch_pack3(f64(c), c->L.q, src, c->fbuf[c->cur], c->nx, c->ny, c->nz, c->L.pitch, true,
+                   c->stream))
     return fail3(LBM_E_DEVICE, "state copy failed");
   if (t != c->t) c->v.trace_t0 = t;
   c->t = t;

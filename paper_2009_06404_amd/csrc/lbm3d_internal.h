@@ -1,5 +1,5 @@
-// Internal descriptors of the three-dimensional (D3Q19) step, shared by its
-// kernels and its host API. Not part of the public ABI.
+// Internal descriptors of the three-dimensional (D3Q19 / D3Q27) step, shared
+// by its kernels and its host API. Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -7,7 +7,7 @@
 
 namespace lbm3 {
 
-constexpr int kQ = 19;
+constexpr int kQ19 = 19, kQ27 = 27;   // the two velocity sets
 constexpr int kFaceTop = 0, kFaceBottom = 1, kFaceLeft = 2, kFaceRight = 3, kFaceFront = 4,
               kFaceBack = 5;
 constexpr int kPeriodic = 0, kFree = 1, kRigid = 2, kFree0 = 3;
@@ -17,17 +17,18 @@ struct Src3Dev {
   double x, y, z, sigma, dir_x, dir_y, dir_z, amp, period, t0;
 };
 
-// One volume. Populations: population i of cell (x, y, z) at
-// z * zplane + (y * 19 + i) * pitch + x of a population buffer; kappa of the
-// cell at (z * ny + y) * pitch + x of the kappa plane.
+// One volume on the q-velocity set. Populations: population i of cell
+// (x, y, z) at z * zplane + (y * q + i) * pitch + x of a population buffer;
+// kappa of the cell at (z * ny + y) * pitch + x of the kappa plane.
 struct Vol3Dev {
   int32_t nx, ny, nz, pitch;
+  int32_t q;               // 19 or 27
   int32_t face[6];
   int32_t kcells;          // 1: kappa per cell, 0: kscalar
   int32_t nsrc;
   double kscalar;
   double omega;            // 1 / tau
-  int64_t zplane;          // ny * 19 * pitch
+  int64_t zplane;          // ny * q * pitch
   const void *kappa;       // real plane (kcells)
   const void *damp;        // real [nx + ny + nz]: sponge damping per x, then y, then z
   const Src3Dev *src;
@@ -72,8 +73,8 @@ int launch_kappa3(bool f64, const void *lam, const void *mu, const void *rho, vo
 int launch_gather_inv3(bool f64, const void *rho, const int32_t *xyz, int n, int nx, int ny,
                        void *out, hipStream_t s);
 
-// Dense [19][nz][ny][nx] <-> pitched population buffer.
-int launch_pack3(bool f64, const void *src, void *dst, int nx, int ny, int nz, int pitch,
+// Dense [q][nz][ny][nx] <-> pitched population buffer.
+int launch_pack3(bool f64, int q, const void *src, void *dst, int nx, int ny, int nz, int pitch,
                  bool to_pitched, hipStream_t s);
 
 }  // namespace lbm3

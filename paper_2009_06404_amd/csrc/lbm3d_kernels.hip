@@ -1,5 +1,6 @@
-// D3Q19 elastic-wave step on gfx950: one kernel per step (or per evaluation
-// of the macroscopic fields), HBM-bound at 2 x 19 population words per cell.
+// D3Q19 / D3Q27 elastic-wave step on gfx950: one kernel per step (or per
+// evaluation of the macroscopic fields), HBM-bound at 2 x Q population words
+// per cell. Q, the velocity set, is a template parameter of every kernel.
 //
 // Work decomposition. A workgroup owns a tile of 64 columns by TY rows and a
 // segment of planes in z, and marches the segment plane by plane. It runs
@@ -23,17 +24,21 @@
 namespace lbm3 {
 namespace {
 
-// D3Q19 velocities in the order of the public header; weights by speed class.
+// Velocities in the order of the public header: D3Q19 is the first 19 of
+// D3Q27's. Weights by speed class.
 __host__ __device__ constexpr int cxv(int i) {
-  constexpr int t[kQ] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+  constexpr int t[kQ27] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0,
+                           1, -1, 1, -1, 1, -1, -1, 1};
   return t[i];
 }
 __host__ __device__ constexpr int cyv(int i) {
-  constexpr int t[kQ] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+  constexpr int t[kQ27] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1,
+                           1, -1, 1, -1, -1, 1, 1, -1};
   return t[i];
 }
 __host__ __device__ constexpr int czv(int i) {
-  constexpr int t[kQ] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+  constexpr int t[kQ27] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1,
+                           1, -1, -1, 1, 1, -1, 1, -1};
   return t[i];
 }
 __host__ __device__ constexpr int oppv(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
@@ -41,9 +46,13 @@ __host__ __device__ constexpr int speed2(int i) {
   return cxv(i) * cxv(i) + cyv(i) * cyv(i) + czv(i) * czv(i);
 }
 
-template <typename real>
+template <typename real, int Q>
 __device__ __forceinline__ real wgt(int i) {
-  return speed2(i) == 0 ? real(1) / real(3) : (speed2(i) == 1 ? real(1) / real(18) : real(1) / real(36));
+  if (Q == kQ19)
+    return speed2(i) == 0 ? real(1) / real(3) : (speed2(i) == 1 ? real(1) / real(18) : real(1) / real(36));
+  return speed2(i) == 0 ? real(8) / real(27)
+                        : (speed2(i) == 1 ? real(2) / real(27)
+                                          : (speed2(i) == 2 ? real(1) / real(54) : real(1) / real(216)));
 }
 
 // Link kinds, ordered by precedence: a link that leaves through a rigid face
@@ -75,12 +84,12 @@ __device__ __forceinline__ double min_image(double d, int n, bool periodic) {
 using lbm::dev::Buf;
 using rsrc_t = __amdgpu_buffer_rsrc_t;
 
-template <typename real>
+template <typename real, int Q>
 __device__ __forceinline__ real pull_inner(rsrc_t R0, rsrc_t R1, rsrc_t R2, const uint32_t (&xb)[3],
-                                           const uint32_t (&rb)[3], uint32_t run, real (&f)[kQ]) {
+                                           const uint32_t (&rb)[3], uint32_t run, real (&f)[Q]) {
   real rho = real(0);
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) {
+  for (int i = 0; i < Q; ++i) {
     const int dx = 1 - cxv(i), dy = 1 - cyv(i), dz = 1 - czv(i);
     const rsrc_t R = dz == 0 ? R0 : (dz == 1 ? R1 : R2);
     f[i] = Buf<real>::load(R, rb[dy] + xb[dx], (uint32_t)i * run);
@@ -99,11 +108,11 @@ struct Task {
   int kx0, kx2, ky0, ky2;
 };
 
-template <typename real>
+template <typename real, int Q>
 __device__ __forceinline__ Task make_task(const Vol3Dev &v, int x, int y) {
   Task k;
   const int nx = v.nx, ny = v.ny;
-  const uint32_t es = sizeof(real), rp = (uint32_t)(kQ * v.pitch) * es;
+  const uint32_t es = sizeof(real), rp = (uint32_t)(Q * v.pitch) * es;
   k.xb[0] = (uint32_t)(x > 0 ? x - 1 : nx - 1) * es;
   k.xb[1] = (uint32_t)x * es;
   k.xb[2] = (uint32_t)(x < nx - 1 ? x + 1 : 0) * es;
@@ -126,10 +135,10 @@ __device__ __forceinline__ Task make_task(const Vol3Dev &v, int x, int y) {
 // tangential stress (P_xx, P_xy, P_yy) are the cell's (FREE0) or 3/2 the
 // cell's - 1/2 the inner neighbour's (FREE): moments of the post-collision
 // populations, which the collision leaves unchanged. Returns the new rho.
-template <typename real>
+template <typename real, int Q>
 __device__ __forceinline__ real apply_faces(const Vol3Dev &v, rsrc_t R0, rsrc_t R1, rsrc_t R2,
                                             const Task &T, int kz0, int kz2, uint32_t run,
-                                            real (&f)[kQ]) {
+                                            real (&f)[Q]) {
   const uint32_t own = T.rb[1] + T.xb[1];
   real rho_air = real(0), pxx = real(0), pxy = real(0), pyy = real(0);
   if (kz0 == kLinkFree || kz2 == kLinkFree) {
@@ -138,7 +147,7 @@ __device__ __forceinline__ real apply_faces(const Vol3Dev &v, rsrc_t R0, rsrc_t 
     const rsrc_t Rin = kz0 == kLinkFree ? R2 : R0;
     // rolled: few loads in flight on this rare path (free-surface planes)
 #pragma unroll 1
-    for (int i = 0; i < kQ; ++i) {
+    for (int i = 0; i < Q; ++i) {
       real g = wb * Buf<real>::load(R1, own, (uint32_t)i * run);
       if (kind == kFree) g += wi * Buf<real>::load(Rin, own, (uint32_t)i * run);
       rho_air += g;
@@ -152,7 +161,7 @@ __device__ __forceinline__ real apply_faces(const Vol3Dev &v, rsrc_t R0, rsrc_t 
   const real pn_xx = pxx - b2 * rho_air, pn_yy = pyy - b2 * rho_air, pn_zz = -b2 * rho_air;
   real rho = real(0);
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) {
+  for (int i = 0; i < Q; ++i) {
     // the population arrives from x - c_i
     const int kxi = cxv(i) > 0 ? T.kx0 : (cxv(i) < 0 ? T.kx2 : kIn);
     const int kyi = cyv(i) > 0 ? T.ky0 : (cyv(i) < 0 ? T.ky2 : kIn);
@@ -167,7 +176,7 @@ __device__ __forceinline__ real apply_faces(const Vol3Dev &v, rsrc_t R0, rsrc_t 
         const real cx = real(cxv(i)), cy = real(cyv(i)), cz = real(czv(i));
         const real q = pn_xx * (cx * cx - b2) + pn_yy * (cy * cy - b2) + pn_zz * (cz * cz - b2) +
                        real(2) * pxy * cx * cy;
-        f[i] = -back + real(2) * wgt<real>(i) * (rho_air + real(4.5) * q);
+        f[i] = -back + real(2) * wgt<real, Q>(i) * (rho_air + real(4.5) * q);
       }
     }
     rho += f[i];
@@ -177,7 +186,7 @@ __device__ __forceinline__ real apply_faces(const Vol3Dev &v, rsrc_t R0, rsrc_t 
 
 // GENERAL = false: the lean kernel (no face rules, sources or receivers; the
 // host gives it only tiles that need none). MODE 1 (fields) is general only.
-template <typename real, int TY, int MODE, bool GENERAL>
+template <typename real, int Q, int TY, int MODE, bool GENERAL>
 __global__ void __launch_bounds__(64 * (TY + 2))
 step3_kernel(const real *__restrict__ fin, real *__restrict__ fout, real *__restrict__ out10,
              const Vol3Dev v, int64_t t, const Tile3Dev *__restrict__ tiles, int ntiles) {
@@ -239,26 +248,26 @@ step3_kernel(const real *__restrict__ fin, real *__restrict__ fout, real *__rest
 
   const uint32_t run = (uint32_t)pitch * (uint32_t)sizeof(real);   // bytes of one population run
   // pull of task T at plane p (0 <= p < nz)
-  auto pull_task = [&](const Task &T, int p, real(&f)[kQ]) -> real {
+  auto pull_task = [&](const Task &T, int p, real(&f)[Q]) -> real {
     const int zm = p > 0 ? p - 1 : nz - 1;
     const int zp = p < nz - 1 ? p + 1 : 0;
     const rsrc_t R0 = lbm::dev::tile_rsrc(fin + (int64_t)zm * v.zplane);
     const rsrc_t R1 = lbm::dev::tile_rsrc(fin + (int64_t)p * v.zplane);
     const rsrc_t R2 = lbm::dev::tile_rsrc(fin + (int64_t)zp * v.zplane);
-    real rho = pull_inner<real>(R0, R1, R2, T.xb, T.rb, run, f);
+    real rho = pull_inner<real, Q>(R0, R1, R2, T.xb, T.rb, run, f);
     if (GENERAL) {
       const int kz0 = p == 0 ? face_link_kind(v.face[kFaceTop]) : kIn;
       const int kz2 = p == nz - 1 ? face_link_kind(v.face[kFaceBottom]) : kIn;
       if ((T.kx0 | T.kx2 | T.ky0 | T.ky2 | kz0 | kz2) != kIn)
-        rho = apply_faces<real>(v, R0, R1, R2, T, kz0, kz2, run, f);
+        rho = apply_faces<real, Q>(v, R0, R1, R2, T, kz0, kz2, run, f);
     }
     return rho;
   };
 
   const real om = real(v.omega), src_w = real(1) - real(0.5) * om;
-  real cur[kQ], nxt[kQ];
+  real cur[Q], nxt[Q];
 #pragma unroll
-  for (int i = 0; i < kQ; ++i) cur[i] = real(0);
+  for (int i = 0; i < Q; ++i) cur[i] = real(0);
   real rp = real(0), rc = real(0), rn = real(0);
 
   // Plane zl + 1 is pulled while plane zl is updated: task A from plane
@@ -275,13 +284,13 @@ step3_kernel(const real *__restrict__ fin, real *__restrict__ fout, real *__rest
       // registers held across the loop
       int cx_ = tax, cy_ = tay;
       asm volatile("" : "+v"(cx_), "+v"(cy_));
-      rn = pull_task(make_task<real>(v, cx_, cy_), pw, nxt);
+      rn = pull_task(make_task<real, Q>(v, cx_, cy_), pw, nxt);
     }
     if (!active && hasA && p >= zb && p < ze) srho[nslot][arow][acol] = rn;
     if (hasB && p >= zb && p < ze) {
       int cx_ = tbx, cy_ = tby;
       asm volatile("" : "+v"(cx_), "+v"(cy_));
-      srho[nslot][brow][bcol] = pull_task(make_task<real>(v, cx_, cy_), pw, nxt);
+      srho[nslot][brow][bcol] = pull_task(make_task<real, Q>(v, cx_, cy_), pw, nxt);
     }
 
     if (active && zl >= zb) {
@@ -301,7 +310,7 @@ step3_kernel(const real *__restrict__ fin, real *__restrict__ fout, real *__rest
       // moments of the pulled populations
       real mx = 0, my = 0, mz = 0, pxx = 0, pxy = 0, pxz = 0, pyy = 0, pyz = 0, pzz = 0;
 #pragma unroll
-      for (int i = 0; i < kQ; ++i) {
+      for (int i = 0; i < Q; ++i) {
         const real f = cur[i];
         if (cxv(i) != 0) { mx += real(cxv(i)) * f; pxx += f; }
         if (cyv(i) != 0) { my += real(cyv(i)) * f; pyy += f; }
@@ -373,15 +382,15 @@ step3_kernel(const real *__restrict__ fin, real *__restrict__ fout, real *__rest
         const real nxx = pxx - b2 * rc, nyy = pyy - b2 * rc, nzz = pzz - b2 * rc;
         const real btr = b2 * (nxx + nyy + nzz);
         const rsrc_t O = lbm::dev::tile_rsrc(fout + (int64_t)z * v.zplane);
-        const uint32_t own = (uint32_t)(y * kQ * pitch + x) * (uint32_t)sizeof(real);
+        const uint32_t own = (uint32_t)(y * Q * pitch + x) * (uint32_t)sizeof(real);
 #pragma unroll
-        for (int i = 0; i < kQ; ++i) {
+        for (int i = 0; i < Q; ++i) {
           const real cx = real(cxv(i)), cy = real(cyv(i)), cz = real(czv(i));
           const real q = nxx * cx * cx + nyy * cy * cy + nzz * cz * cz +
                          real(2) * (pxy * cx * cy + pxz * cx * cz + pyz * cy * cz) - btr;
           const real jc = jx * cx + jy * cy + jz * cz;
           const real sc = Sx * cx + Sy * cy + Sz * cz;
-          const real wi = wgt<real>(i);
+          const real wi = wgt<real, Q>(i);
           // equilibrium (eq. equilibrium-solid): w (rho + j.c / b^2 + P^n:Q / (2 b^4))
           const real feq = wi * (rc + real(3) * jc + real(4.5) * q);
           // BGK (eq. LBGK) with the source of eq. Si
@@ -392,7 +401,7 @@ step3_kernel(const real *__restrict__ fin, real *__restrict__ fout, real *__rest
     }
     if (active && p >= zb && p < ze) srho[nslot][ly][lx + 1] = rn;
 #pragma unroll
-    for (int i = 0; i < kQ; ++i) cur[i] = nxt[i];
+    for (int i = 0; i < Q; ++i) cur[i] = nxt[i];
     rp = rc;
     rc = rn;
     __syncthreads();
@@ -445,17 +454,17 @@ __global__ void gather_inv3_kernel(const real *__restrict__ rho, const int32_t *
 }
 
 template <typename real>
-__global__ void pack3_kernel(const real *__restrict__ src, real *__restrict__ dst, int nx, int ny,
-                             int nz, int pitch, int to_pitched) {
+__global__ void pack3_kernel(const real *__restrict__ src, real *__restrict__ dst, int q, int nx,
+                             int ny, int nz, int pitch, int to_pitched) {
   // one row (i, z, y) per block.y index, columns over threads
   const int64_t rowid = blockIdx.y + (int64_t)blockIdx.z * 65535;
-  const int64_t nrows = (int64_t)kQ * nz * ny;
+  const int64_t nrows = (int64_t)q * nz * ny;
   if (rowid >= nrows) return;
   const int i = (int)(rowid / ((int64_t)nz * ny));
   const int64_t zy = rowid % ((int64_t)nz * ny);
   const int z = (int)(zy / ny), y = (int)(zy % ny);
   const int64_t d = (int64_t)i * nz * ny * nx + zy * nx;
-  const int64_t p = (int64_t)z * ny * kQ * pitch + ((int64_t)y * kQ + i) * pitch;
+  const int64_t p = (int64_t)z * ny * q * pitch + ((int64_t)y * q + i) * pitch;
   for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < nx; x += gridDim.x * blockDim.x) {
     if (to_pitched)
       dst[p + x] = src[d + x];
@@ -464,7 +473,7 @@ __global__ void pack3_kernel(const real *__restrict__ src, real *__restrict__ ds
   }
 }
 
-template <typename real, int TY>
+template <typename real, int Q, int TY>
 void launch_tile(bool general, const Tile3Dev *tiles, int ntiles, const void *fin, void *fout,
                  void *out10, const Vol3Dev &v, int64_t t, int mode, hipStream_t s) {
   if (ntiles <= 0) return;
@@ -473,25 +482,34 @@ void launch_tile(bool general, const Tile3Dev *tiles, int ntiles, const void *fi
   real *out = reinterpret_cast<real *>(fout);
   real *o10 = reinterpret_cast<real *>(out10);
   if (mode == 1)
-    hipLaunchKernelGGL((step3_kernel<real, TY, 1, true>), grid, block, 0, s, in, out, o10, v, t,
+    hipLaunchKernelGGL((step3_kernel<real, Q, TY, 1, true>), grid, block, 0, s, in, out, o10, v, t,
                        tiles, ntiles);
   else if (general)
-    hipLaunchKernelGGL((step3_kernel<real, TY, 0, true>), grid, block, 0, s, in, out, o10, v, t,
+    hipLaunchKernelGGL((step3_kernel<real, Q, TY, 0, true>), grid, block, 0, s, in, out, o10, v, t,
                        tiles, ntiles);
   else
-    hipLaunchKernelGGL((step3_kernel<real, TY, 0, false>), grid, block, 0, s, in, out, o10, v, t,
+    hipLaunchKernelGGL((step3_kernel<real, Q, TY, 0, false>), grid, block, 0, s, in, out, o10, v, t,
                        tiles, ntiles);
 }
 
-template <typename real>
+template <typename real, int Q>
 void launch_rows(bool general, int rows_y, const Tile3Dev *tiles, int ntiles, const void *fin,
                  void *fout, void *out10, const Vol3Dev &v, int64_t t, int mode, hipStream_t s) {
   if (rows_y == 2)
-    launch_tile<real, 2>(general, tiles, ntiles, fin, fout, out10, v, t, mode, s);
+    launch_tile<real, Q, 2>(general, tiles, ntiles, fin, fout, out10, v, t, mode, s);
   else if (rows_y == 14)
-    launch_tile<real, 14>(general, tiles, ntiles, fin, fout, out10, v, t, mode, s);
+    launch_tile<real, Q, 14>(general, tiles, ntiles, fin, fout, out10, v, t, mode, s);
   else
-    launch_tile<real, 6>(general, tiles, ntiles, fin, fout, out10, v, t, mode, s);
+    launch_tile<real, Q, 6>(general, tiles, ntiles, fin, fout, out10, v, t, mode, s);
+}
+
+template <typename real>
+void launch_lattice(bool general, int rows_y, const Tile3Dev *tiles, int ntiles, const void *fin,
+                    void *fout, void *out10, const Vol3Dev &v, int64_t t, int mode, hipStream_t s) {
+  if (v.q == kQ27)
+    launch_rows<real, kQ27>(general, rows_y, tiles, ntiles, fin, fout, out10, v, t, mode, s);
+  else
+    launch_rows<real, kQ19>(general, rows_y, tiles, ntiles, fin, fout, out10, v, t, mode, s);
 }
 
 }  // namespace
@@ -500,9 +518,9 @@ int launch_step3(bool f64, bool general, int rows_y, const Tile3Dev *tiles, int 
                  const void *fin, void *fout, void *out10, const Vol3Dev &v, int64_t t, int mode,
                  hipStream_t s) {
   if (f64)
-    launch_rows<double>(general, rows_y, tiles, ntiles, fin, fout, out10, v, t, mode, s);
+    launch_lattice<double>(general, rows_y, tiles, ntiles, fin, fout, out10, v, t, mode, s);
   else
-    launch_rows<float>(general, rows_y, tiles, ntiles, fin, fout, out10, v, t, mode, s);
+    launch_lattice<float>(general, rows_y, tiles, ntiles, fin, fout, out10, v, t, mode, s);
   return (int)hipGetLastError();
 }
 
@@ -538,18 +556,18 @@ int launch_gather_inv3(bool f64, const void *rho, const int32_t *xyz, int n, int
   return (int)hipGetLastError();
 }
 
-int launch_pack3(bool f64, const void *src, void *dst, int nx, int ny, int nz, int pitch,
+int launch_pack3(bool f64, int q, const void *src, void *dst, int nx, int ny, int nz, int pitch,
                  bool to_pitched, hipStream_t s) {
-  const int64_t nrows = (int64_t)kQ * nz * ny;
+  const int64_t nrows = (int64_t)q * nz * ny;
   const dim3 grid((nx + 255) / 256 < 4 ? (nx + 255) / 256 : 4, 65535,
                   (unsigned)((nrows + 65534) / 65535));
   const dim3 g2(grid.x, nrows < 65535 ? (unsigned)nrows : 65535u, grid.z);
   if (f64)
     hipLaunchKernelGGL(pack3_kernel<double>, g2, dim3(256), 0, s, static_cast<const double *>(src),
-                       static_cast<double *>(dst), nx, ny, nz, pitch, to_pitched ? 1 : 0);
+                       static_cast<double *>(dst), q, nx, ny, nz, pitch, to_pitched ? 1 : 0);
   else
     hipLaunchKernelGGL(pack3_kernel<float>, g2, dim3(256), 0, s, static_cast<const float *>(src),
-                       static_cast<float *>(dst), nx, ny, nz, pitch, to_pitched ? 1 : 0);
+                       static_cast<float *>(dst), q, nx, ny, nz, pitch, to_pitched ? 1 : 0);
   return (int)hipGetLastError();
 }
 

@@ -17,7 +17,7 @@ _DT = {"f32": (L.LBM_F32, torch.float32), "f64": (L.LBM_F64, torch.float64)}
 
 class Solver3:
     """One context for one volume. ``problem`` has the attributes of
-    ``workloads.problem3.Problem3`` (nx, ny, nz, faces, full(), tau,
+    ``workloads.problem3.Problem3`` (nx, ny, nz, q, faces, full(), tau,
     sponge_thick, profile(f), sources, receivers, comp_mask)."""
 
     def __init__(self, problem, dtype: str = "f32", device: str = "cuda",
@@ -32,11 +32,12 @@ class Solver3:
         self.lam = torch.as_tensor(lam, dtype=self.tdtype, device=self.device).contiguous()
         self.mu = torch.as_tensor(mu, dtype=self.tdtype, device=self.device).contiguous()
         self.rho = torch.as_tensor(rho, dtype=self.tdtype, device=self.device).contiguous()
-        self.ws_bytes = L3.lbm3_workspace_bytes(p.nx, p.ny, p.nz, self.code)
+        self.q = int(getattr(p, "q", 19))
+        self.ws_bytes = L3.lbm3_workspace_bytes(p.nx, p.ny, p.nz, self.q, self.code)
         self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.current_stream(self.device)
         bc, keep = L3.make_bc(p.faces, p.sponge_thick, [p.profile(f) for f in range(6)])
-        self.ctx = L3.lbm3_init(p.nx, p.ny, p.nz, self.code, self.lam.data_ptr(),
+        self.ctx = L3.lbm3_init(p.nx, p.ny, p.nz, self.q, self.code, self.lam.data_ptr(),
                                 self.mu.data_ptr(), self.rho.data_ptr(), p.tau, bc,
                                 self.workspace.data_ptr(), self.ws_bytes, self.stream.cuda_stream)
         del keep
@@ -70,15 +71,15 @@ class Solver3:
 
     def state(self) -> torch.Tensor:
         p = self.problem
-        out = torch.empty((19, p.nz, p.ny, p.nx), dtype=self.tdtype, device=self.device)
+        out = torch.empty((self.q, p.nz, p.ny, p.nx), dtype=self.tdtype, device=self.device)
         L3.lbm3_get_state(self.ctx, out.data_ptr())
         return out
 
     def set_state(self, src: torch.Tensor, t: int) -> None:
         p = self.problem
         src = src.to(device=self.device, dtype=self.tdtype).contiguous()
-        if tuple(src.shape) != (19, p.nz, p.ny, p.nx):
-            raise ValueError("state must have shape (19, nz, ny, nx)")
+        if tuple(src.shape) != (self.q, p.nz, p.ny, p.nx):
+            raise ValueError("state must have shape (q, nz, ny, nx)")
         self._state_in = src       # kept until the asynchronous copy has run
         L3.lbm3_set_state(self.ctx, src.data_ptr(), t)
 

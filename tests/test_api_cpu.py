@@ -41,7 +41,7 @@ def _init3(**kw):
     bc, keep = L3.make_bc(faces, thick, prof)
     shape = kw.get("shape", (16, 16, 16))
     fake = 0x2000
-    return L3.lbm3_init(*shape, L.LBM_F32, fake, fake, fake, kw.get("tau", 1.0), bc,
+    return L3.lbm3_init(*shape, kw.get("q", 19), L.LBM_F32, fake, fake, fake, kw.get("tau", 1.0), bc,
                         kw.get("ws", 0x1000), kw.get("ws_bytes", 1 << 34), None)
 
 
@@ -57,6 +57,7 @@ def _init3(**kw):
     (dict(ws=0), "workspace"),
     (dict(ws=0x1004), "aligned"),
     (dict(ws_bytes=100), "too small"),
+    (dict(q=15), "lattice"),
 ])
 def test_init3_rejects_invalid_arguments(kw, msg):
     from paper_2009_06404_amd import _lib as L
@@ -69,14 +70,16 @@ def test_workspace3_size_and_null_context():
     import ctypes as C
     from paper_2009_06404_amd import _lib as L
     from paper_2009_06404_amd import _lib3d as L3
-    b32 = L3.lbm3_workspace_bytes(100, 20, 10, L.LBM_F32)
+    b32 = L3.lbm3_workspace_bytes(100, 20, 10, 19, L.LBM_F32)
     assert b32 >= 2 * 19 * 128 * 20 * 10 * 4 + 128 * 20 * 10 * 4
-    assert L3.lbm3_workspace_bytes(100, 20, 10, L.LBM_F64) > b32
-    for bad in ((2, 5, 5), (5, 5, 2)):
+    assert L3.lbm3_workspace_bytes(100, 20, 10, 19, L.LBM_F64) > b32
+    b27 = L3.lbm3_workspace_bytes(100, 20, 10, 27, L.LBM_F32)
+    assert b27 >= 2 * 27 * 128 * 20 * 10 * 4 + 128 * 20 * 10 * 4 and b27 > b32
+    for bad in ((2, 5, 5, 19), (5, 5, 2, 19), (5, 5, 5, 15)):
         with pytest.raises(L.LBMError):
             L3.lbm3_workspace_bytes(*bad, L.LBM_F32)
     with pytest.raises(L.LBMError):
-        L3.lbm3_workspace_bytes(2048, 2048, 1024, L.LBM_F32)   # > 2^31 cells
+        L3.lbm3_workspace_bytes(2048, 2048, 1024, 19, L.LBM_F32)   # > 2^31 cells
     lib = L3.lib()
     assert lib.lbm3_step(None, 1) == L.LBM_E_INVALID
     assert lib.lbm3_moments(None, None) == L.LBM_E_INVALID
