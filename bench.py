@@ -94,6 +94,19 @@ def cpu_baseline(problem, target_s: float = 15.0):
                       f"state, FP64, OpenMP over rows ({el:.1f} s incl. setup)"}
 
 
+def cpu_baseline3(problem, steps: int = 2):
+    """The FP64 three-dimensional oracle as it stands, on this host's cores,
+    on the first steps of the same volume from the rest state."""
+    from oracle import stepper, stepper3d
+    t = time.perf_counter()
+    stepper3d.run(problem, nsteps=steps, want_trace=False)
+    el = time.perf_counter() - t
+    return {"value": problem.cells * steps / el / 1e9, "unit": "GLUPS", "cores": stepper.num_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} steps of the full {problem.nx}x{problem.ny}x{problem.nz} volume "
+                      f"(D3Q{problem.q}) from the rest state, FP64, OpenMP ({el:.1f} s incl. setup)"}
+
+
 def _timed_steps(s, steps: int, warmup: int, torch) -> float:
     """ms per step over `steps` steps after `warmup`, HIP events on the stream."""
     s.step(warmup)
@@ -143,7 +156,7 @@ def bench_filter(torch, w, Solver, steps_ms: float, passes: int = 20) -> dict:
 
 
 def bench_volume(torch, dtype: str = "f32", n: int = 256, steps: int = 400, warmup: int = 20,
-                 q: int = 19) -> dict:
+                 q: int = 19, cpu: bool = False) -> dict:
     """The three-dimensional step (D3Q19 or D3Q27) on the 256^3 half-space
     (free surface, sponges, source, 4096 surface receivers): a lean and a
     general launch per step, 2 x q population words per cell (152 B / 216 B
@@ -177,7 +190,8 @@ def bench_volume(torch, dtype: str = "f32", n: int = 256, steps: int = 400, warm
             "kernel_GBps": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBS, 4),
             "general_kernel": {"cells_per_launch": kt["general_cells"],
                                "ms_per_launch": round(kt["general_ms"], 5)},
-            "tile": list(tile), "state_finite": ok}
+            "tile": list(tile), "state_finite": ok,
+            **({"cpu_baseline": cpu_baseline3(p)} if cpu else {})}
 
 
 def bench_hbm_scale(torch, w, Solver, steps: int = 200, warmup: int = 20) -> dict:
@@ -342,8 +356,9 @@ def main():
               "adjoint": lambda: bench_adjoint(torch, w, Solver, float("nan"),
                                                nsteps=args.adjoint_steps),
               "filter": lambda: bench_filter(torch, w, Solver, float("nan")),
-              "volume": lambda: bench_volume(torch, args.dtype),
-              "volume27": lambda: bench_volume(torch, args.dtype, q=27)}[args.only]
+              "volume": lambda: bench_volume(torch, args.dtype, cpu=not args.no_cpu_baseline),
+              "volume27": lambda: bench_volume(torch, args.dtype, q=27,
+                                               cpu=not args.no_cpu_baseline)}[args.only]
         print(json.dumps({args.only: fn()}), flush=True)
         return
     p = w.plain_large(n=args.n, dtype=args.dtype)
@@ -418,8 +433,8 @@ def main():
                          ("batched", lambda: bench_batched(torch, w, Solver, glups)),
                          ("adjoint", lambda: bench_adjoint(torch, w, Solver, glups)),
                          ("filter", lambda: bench_filter(torch, w, Solver, ms_step)),
-                         ("volume_d3q19", lambda: bench_volume(torch)),
-                         ("volume_d3q27", lambda: bench_volume(torch, q=27))):
+                         ("volume_d3q19", lambda: bench_volume(torch, cpu=not args.no_cpu_baseline)),
+                         ("volume_d3q27", lambda: bench_volume(torch, q=27, cpu=not args.no_cpu_baseline))):
             print(f"[bench] {name} ...", file=sys.stderr, flush=True)
             extras[name] = fn()
             torch.cuda.empty_cache()
