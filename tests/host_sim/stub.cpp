@@ -29,6 +29,8 @@ static void check_range(const void *p, size_t n, const char *what) {
   }
 }
 
+extern "C" void sim_check_range(const void *p, size_t n, const char *what) { check_range(p, n, what); }
+
 hipError_t hipMalloc(void **p, size_t n) { *p = malloc(n ? n : 1); g_alloc[(uintptr_t)*p] = n ? n : 1; return hipSuccess; }
 hipError_t hipFree(void *p) { if (p) { g_alloc.erase((uintptr_t)p); free(p); } return hipSuccess; }
 hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, hipMemcpyKind k, hipStream_t) {
