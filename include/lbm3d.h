@@ -90,7 +90,11 @@ int lbm3_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t q, int32_t 
  *  workspace: DEVICE memory of at least lbm3_workspace_bytes, 256-B aligned,
  *    owned by the caller and used only by this context.
  *  hip_stream: the hipStream_t all work goes to (NULL = default stream).
- * Synchronous. Returns LBM_OK, LBM_E_INVALID, LBM_E_NOMEM or LBM_E_DEVICE. */
+ * Synchronous. Returns LBM_OK, LBM_E_INVALID, LBM_E_NOMEM, LBM_E_DEVICE, or
+ * LBM_WARN_UNSTABLE (the context is created and usable) when a bulk mode
+ * grows for the medium's Poisson ratios at tau (the factor of lbm3_vn_growth
+ * on 9 points per axis at the extreme and middle ratios) or a face uses
+ * LBM_FREE, with the reason in lbm_last_error. */
 int lbm3_init(lbm3_ctx **ctx, int32_t nx, int32_t ny, int32_t nz, int32_t q, int32_t dtype,
               const void *lam, const void *mu, const void *rho, double tau,
               const lbm3_bc *bc, void *workspace, size_t ws_bytes, void *hip_stream);
@@ -150,6 +154,17 @@ int lbm3_set_state(lbm3_ctx *ctx, const void *src, int64_t t);
  * Returns LBM_OK or LBM_E_INVALID. Host only. */
 int lbm3_set_tile(lbm3_ctx *ctx, int32_t rows_y, int32_t planes_z);
 int lbm3_get_tile(const lbm3_ctx *ctx, int32_t *rows_y, int32_t *planes_z);
+
+/* Largest von Neumann amplification factor of one bulk step (periodic, no
+ * sponge, no source; Sec. 4's analysis carried to the q-velocity set) over an
+ * nk x nk x nk grid of wavenumbers in [0, pi]^3: > 1 means some plane wave
+ * grows. 0 <= nu < 1/2, tau > 1/2, 2 <= nk <= 129. Synchronous, host only.
+ * Returns LBM_OK or LBM_E_INVALID. */
+int lbm3_vn_growth(int32_t q, double nu, double tau, int32_t nk, double *growth);
+
+/* The factor lbm3_init computed for this context; returns LBM_OK, or
+ * LBM_WARN_UNSTABLE as lbm3_init did. Host only. */
+int lbm3_stability(const lbm3_ctx *ctx, double *growth);
 
 /* Free the context's own device tables; the workspace stays the caller's.
  * Synchronous. NULL is accepted. */

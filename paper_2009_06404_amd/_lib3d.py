@@ -4,13 +4,15 @@ the C name. Errors raise :class:`LBMError` with the library's message."""
 from __future__ import annotations
 
 import ctypes as C
+import warnings
 
-from ._lib import LBMError, check, lib as _lib2d  # noqa: F401  (LBMError re-exported)
+from ._lib import LBM_WARN_UNSTABLE, LBMError, check, last_error, lib as _lib2d  # noqa: F401
 
 ENTRY_POINTS = (
     "lbm3_workspace_bytes", "lbm3_init", "lbm3_set_sources", "lbm3_set_receivers",
     "lbm3_step", "lbm3_step_timed", "lbm3_moments", "lbm3_get_time", "lbm3_get_state",
-    "lbm3_set_state", "lbm3_set_tile", "lbm3_get_tile", "lbm3_destroy",
+    "lbm3_set_state", "lbm3_set_tile", "lbm3_get_tile", "lbm3_destroy", "lbm3_vn_growth",
+    "lbm3_stability",
 )
 
 FACE_TOP, FACE_BOTTOM, FACE_LEFT, FACE_RIGHT, FACE_FRONT, FACE_BACK = range(6)
@@ -57,6 +59,8 @@ def lib():
             "lbm3_set_tile": ([vp, i32, i32], C.c_int),
             "lbm3_get_tile": ([vp, C.POINTER(i32), C.POINTER(i32)], C.c_int),
             "lbm3_destroy": ([vp], C.c_int),
+            "lbm3_vn_growth": ([i32, C.c_double, C.c_double, i32, C.POINTER(C.c_double)], C.c_int),
+            "lbm3_stability": ([vp, C.POINTER(C.c_double)], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -87,10 +91,26 @@ def make_bc(faces, thick=(0,) * 6, profiles=(None,) * 6):
 
 
 def lbm3_init(nx, ny, nz, q, dtype, lam_ptr, mu_ptr, rho_ptr, tau, bc, ws_ptr, ws_bytes, stream_ptr):
+    """The context; a RuntimeWarning when the library reports LBM_WARN_UNSTABLE."""
     ctx = C.c_void_p()
-    check(lib().lbm3_init(C.byref(ctx), nx, ny, nz, q, dtype, lam_ptr, mu_ptr, rho_ptr, float(tau),
-                          C.byref(bc), ws_ptr, ws_bytes, stream_ptr))
+    rc = check(lib().lbm3_init(C.byref(ctx), nx, ny, nz, q, dtype, lam_ptr, mu_ptr, rho_ptr, float(tau),
+                               C.byref(bc), ws_ptr, ws_bytes, stream_ptr))
+    if rc == LBM_WARN_UNSTABLE:
+        warnings.warn(last_error(), RuntimeWarning, stacklevel=2)
     return ctx
+
+
+def lbm3_vn_growth(q: int, nu: float, tau: float, nk: int = 13) -> float:
+    g = C.c_double(0)
+    check(lib().lbm3_vn_growth(q, nu, tau, nk, C.byref(g)))
+    return g.value
+
+
+def lbm3_stability(ctx):
+    """(largest von Neumann factor, stable) of the context."""
+    g = C.c_double(0)
+    rc = check(lib().lbm3_stability(ctx, C.byref(g)))
+    return g.value, rc == 0
 
 
 def lbm3_set_sources(ctx, sources) -> None:

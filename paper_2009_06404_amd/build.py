@@ -8,7 +8,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblbm.so")
 SOURCES = ["lbm_kernels.hip", "lbm_adjoint.hip", "lbm_util.hip", "lbm_filter.hip", "lbm3d_kernels.hip",
-           "lbm_api.cpp", "lbm3d_api.cpp", "lbm_stability.cpp"]
+           "lbm_api.cpp", "lbm3d_api.cpp", "lbm_stability.cpp", "lbm3d_stability.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -116,6 +116,8 @@ struct lbm3_ctx {
   // the general kernel runs on a second stream, beside the lean one
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, join = nullptr;
+  double vn_growth = 0.0;           // largest von Neumann factor over the media's nu
+  bool free_printed = false;        // a face uses LBM_FREE
 };
 
 namespace {
@@ -301,9 +303,55 @@ std::vector<char> damp_table(const lbm3_ctx *c) {
   return b;
 }
 
+// Poisson ratio of a cell from its kappa = b^2 (1 - lambda/mu).
+double nu_of_kappa3(double kappa) {
+  const double r = 1.0 - 3.0 * kappa;   // lambda / mu
+  return r / (2.0 * (1.0 + r));
+}
+
+// The init-time stability verdict: the factor at the extreme Poisson ratios
+// of the medium (and the middle one) on a 9-point grid per axis, and the
+// printed free surface, which lets short surface modes grow.
+int stability_verdict3(lbm3_ctx *c, double kmin, double kmax) {
+  double g = 0.0;
+  const double nus[3] = {nu_of_kappa3(kmin), nu_of_kappa3(kmax), nu_of_kappa3(0.5 * (kmin + kmax))};
+  for (int s = 0; s < (kmin == kmax ? 1 : 3); ++s) g = std::max(g, vn_growth3(c->L.q, nus[s], c->tau, 9));
+  c->vn_growth = g;
+  c->free_printed = c->bc.face[LBM3_FACE_TOP] == LBM_FREE || c->bc.face[LBM3_FACE_BOTTOM] == LBM_FREE;
+  if (g > 1.0 + 1e-6) {
+    char buf[200];
+    snprintf(buf, sizeof buf, "bulk modes grow by up to %.6f per step for these Poisson ratios at tau = %g",
+             g, c->tau);
+    lbm::report_error(LBM_WARN_UNSTABLE, buf);
+    return LBM_WARN_UNSTABLE;
+  }
+  if (c->free_printed) {
+    lbm::report_error(LBM_WARN_UNSTABLE,
+                      "LBM_FREE (linear extrapolation) lets short surface modes grow; LBM_FREE0 is the stable variant");
+    return LBM_WARN_UNSTABLE;
+  }
+  return LBM_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+int lbm3_vn_growth(int32_t q, double nu, double tau, int32_t nk, double *growth) {
+  if (!growth) return fail3(LBM_E_INVALID, "growth required");
+  if (q != kQ19 && q != kQ27) return fail3(LBM_E_INVALID, "lattice must be LBM3_D3Q19 or LBM3_D3Q27");
+  if (!(nu >= 0.0 && nu < 0.5) || !(tau > 0.5) || !std::isfinite(tau) || nk < 2 || nk > 129)
+    return fail3(LBM_E_INVALID, "0 <= nu < 1/2, tau > 1/2 and 2 <= nk <= 129 required");
+  *growth = vn_growth3(q, nu, tau, nk);
+  return LBM_OK;
+}
+
+int lbm3_stability(const lbm3_ctx *c, double *growth) {
+  if (!c || !growth) return fail3(LBM_E_INVALID, "context and growth required");
+  *growth = c->vn_growth;
+  if (c->vn_growth > 1.0 + 1e-6 || c->free_printed) return LBM_WARN_UNSTABLE;
+  return LBM_OK;
+}
 
 int lbm3_workspace_bytes(int32_t nx, int32_t ny, int32_t nz, int32_t q, int32_t dtype,
                          size_t *bytes) {
@@ -408,7 +456,7 @@ int lbm3_init(lbm3_ctx **ctx, int32_t nx, int32_t ny, int32_t nz, int32_t q, int
   for (int f = 0; f < 6; ++f) c->bc.profile[f] = nullptr;
   if ((rc = build_tiles(c))) return bail(rc);
   *ctx = c;
-  return LBM_OK;
+  return stability_verdict3(c, kmin, kmax);
 }
 
 int lbm3_set_sources(lbm3_ctx *c, const lbm3_source *src, int32_t n) {

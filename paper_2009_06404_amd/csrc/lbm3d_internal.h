@@ -73,6 +73,10 @@ int launch_kappa3(bool f64, const void *lam, const void *mu, const void *rho, vo
 int launch_gather_inv3(bool f64, const void *rho, const int32_t *xyz, int n, int nx, int ny,
                        void *out, hipStream_t s);
 
+// Largest von Neumann amplification factor of the bulk step on the q-velocity
+// set over an nk^3 grid of wavenumbers in [0, pi]^3 (host code).
+double vn_growth3(int q, double nu, double tau, int nk);
+
 // Dense [q][nz][ny][nx] <-> pitched population buffer.
 int launch_pack3(bool f64, int q, const void *src, void *dst, int nx, int ny, int nz, int pitch,
                  bool to_pitched, hipStream_t s);

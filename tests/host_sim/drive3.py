@@ -8,6 +8,7 @@ tests/test_host_code_cpu.py with the built library's path."""
 import ctypes as C
 import os
 import sys
+import warnings
 
 import numpy as np
 
@@ -31,6 +32,7 @@ from workloads.problem import BC_FREE, BC_FREE0, BC_PERIODIC, BC_RIGID, default_
 from workloads.problem3 import Source3  # noqa: E402
 
 keep = []
+warnings.simplefilter("ignore", RuntimeWarning)   # LBM_WARN_UNSTABLE of unstable media or LBM_FREE
 
 
 def dev(a):
@@ -57,6 +59,10 @@ def run(shape, faces, q, dtype, tile, sources, receivers, thick=(0, 4, 3, 0, 2, 
     bc, kb = L3.make_bc(faces, th, [default_sponge_profile(t) for t in th])
     ctx = L3.lbm3_init(nx, ny, nz, q, code, lam.ctypes.data, mu.ctypes.data, rho.ctypes.data, 0.9,
                        bc, wp, nb, None)
+    g, stable = L3.lbm3_stability(ctx)
+    assert 0.99 < g < 1.5, g
+    if BC_FREE in faces[:2]:
+        assert not stable                    # the printed free surface is always reported
     L3.lbm3_set_sources(ctx, [s.as_tuple() for s in sources])
     T = 12
     rec = np.asarray(receivers, np.int32).reshape(-1, 3)

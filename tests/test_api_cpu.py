@@ -26,7 +26,7 @@ def test_three_dimensional_header_exported():
     from paper_2009_06404_amd import _lib3d as L3
     lib = L3.lib()
     names = _declared3()
-    assert len(names) == len(L3.ENTRY_POINTS) == 13
+    assert len(names) == len(L3.ENTRY_POINTS) == 15
     for name in names:
         assert hasattr(lib, name), name
     assert set(L3.ENTRY_POINTS) == set(names)
@@ -229,3 +229,44 @@ def test_product_code_never_touches_the_oracle():
                     text = fh.read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "lbm_oracle" not in text, f
+
+
+@pytest.mark.parametrize("q,nu,tau", [(19, 0.25, 1.0), (19, 0.35, 1.0), (19, 0.1, 0.6), (27, 0.25, 1.0),
+                                      (27, 0.37, 1.0), (27, 0.3, 0.55)])
+def test_3d_stability_factor_matches_the_oracle_step(q, nu, tau):
+    """lbm3_vn_growth (the library's own plane-wave step on D3Q19 / D3Q27,
+    host code) on the wavenumbers {0, pi/2, pi}^3 against the largest
+    eigenvalue modulus of the oracle's step matrix on those wavenumbers,
+    read off one oracle step of plane waves on a periodic 4^3 volume."""
+    import numpy as np
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from paper_2009_06404_amd import _lib3d as L3
+    from test_oracle_3d import _step_matrix
+    from workloads.configs import lame_from_poisson
+    lam, mu = lame_from_poisson(nu)
+    best = 0.0
+    for mx in range(3):
+        for my in range(mx + 1):
+            for mz in range(my + 1):
+                M = _step_matrix((mx, my, mz), (4, 4, 4), lam, mu, tau, q)
+                best = max(best, float(np.abs(np.linalg.eigvals(M)).max()))
+    g = L3.lbm3_vn_growth(q, nu, tau, 3)
+    assert abs(g - best) < 1e-7, (g, best)
+
+
+def test_3d_stability_factor_window_and_arguments():
+    from paper_2009_06404_amd import _lib as L
+    from paper_2009_06404_amd import _lib3d as L3
+    for q in (19, 27):
+        assert L3.lbm3_vn_growth(q, 0.25, 1.0, 9) <= 1.0 + 1e-6     # nu = 1/4 is stable on both
+        assert L3.lbm3_vn_growth(q, 0.37, 1.0, 9) > 1.01             # nu = 0.37 grows on both
+    # D3Q19 grows from nu ~ 0.32 at tau = 1, where D3Q27 is still stable
+    assert L3.lbm3_vn_growth(19, 0.33, 1.0, 9) > 1.01
+    assert L3.lbm3_vn_growth(27, 0.33, 1.0, 9) <= 1.0 + 1e-6
+    for args in ((15, 0.25, 1.0, 9), (19, 0.5, 1.0, 9), (19, 0.25, 0.5, 9), (19, 0.25, 1.0, 1)):
+        with pytest.raises(L.LBMError):
+            L3.lbm3_vn_growth(*args)
+    import ctypes as C
+    g = C.c_double(0)
+    assert L3.lib().lbm3_stability(None, C.byref(g)) == L.LBM_E_INVALID

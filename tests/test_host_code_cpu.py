@@ -45,6 +45,7 @@ def test_three_dimensional_host_code_and_tile_split(tmp_path):
            os.path.join(ROOT, "paper_2009_06404_amd", "csrc", "lbm_api.cpp"),
            os.path.join(ROOT, "paper_2009_06404_amd", "csrc", "lbm3d_api.cpp"),
            os.path.join(ROOT, "paper_2009_06404_amd", "csrc", "lbm_stability.cpp"),
+           os.path.join(ROOT, "paper_2009_06404_amd", "csrc", "lbm3d_stability.cpp"),
            os.path.join(HERE, "stub.cpp"), os.path.join(HERE, "stub3.cpp"), "-o", lib]
     subprocess.run(cmd, check=True)
     r = subprocess.run([sys.executable, os.path.join(HERE, "drive3.py"), lib],
