@@ -123,9 +123,10 @@ typedef struct {
                          pairs; blocks of 64 x max(waves, 2) columns by up to
                          fuse_rows rows that hold no boundary, receiver or
                          source take two steps in one pass (the intermediate
-                         state stays on chip, apart from the block's border,
-                         kept in a third buffer for the neighbouring blocks);
-                         the other cells take the two steps one at a time.
+                         state stays on chip); the other cells take the two
+                         steps one at a time through a third buffer, together
+                         with the two border rows or columns of the blocks
+                         next to them.
                          Results are bitwise those of single steps. The
                          two-step path launches directly (graph_chunk is not
                          used). The default is set by size: the two-step path

@@ -9,7 +9,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <set>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/lbm.h"
@@ -157,10 +159,11 @@ struct lbm_ctx {
   // two-step path: fused tiles and the general tiles advanced step by step
   DevBuf<FusedTileDev> d_ftiles;
   DevBuf<TileDev> d_gtiles2;
+  DevBuf<TileDev> d_gtiles1;   // first step of a pair: d_gtiles2 plus the two-step blocks' border strips
   // the filter's tiles: 256 columns x kFilterRows rows of every grid
   DevBuf<TileDev> d_filt_tiles;
   int nfilt_tiles = 0;
-  int nftiles = 0, ngtiles2 = 0;
+  int nftiles = 0, ngtiles2 = 0, ngtiles1 = 0;
   int64_t cells_fused = 0, cells_gen2 = 0;
   // second stream and fork/join events for the overlapped general kernel
   hipStream_t side = nullptr;
@@ -519,9 +522,10 @@ int commit(lbm_ctx *c) {
 // A block of an allowed row segment and an allowed column segment runs in
 // the two-step kernel unless a source disk reaches into its reach; every
 // other cell is advanced step by step by the general kernel in
-// one-wavefront tiles of two rows. A two-step block flags the sides next to
-// general cells: the general kernel's second step reads the intermediate
-// state of the two rows or columns there.
+// one-wavefront tiles of two rows. The general kernel's second step reads
+// the intermediate state of the two rows, columns or corner cells of a
+// two-step block next to general cells, so its first step also advances
+// those (the border strips of build_fused_tiles).
 // Two-step blocks are 64 * fused_waves columns wide: the launch's waves
 // (2, 4 or 8; 1 counts as 2).
 int fused_waves(const lbm_ctx *c) { return std::max(2, (int)c->launch.waves); }
@@ -600,10 +604,17 @@ bool source_reaches(const lbm_ctx *c, int g, const Seg &cs, const Seg &rs) {
   return false;
 }
 
+// The general tiles of a pair's second step (general), and of its first step
+// (general1): the same tiles plus, for every two-step block next to general
+// cells, the two rows, columns or corner cells on that side, so that the first
+// general launch leaves f*(t) of every cell the second one reads in the
+// intermediate buffer and the two general launches need nothing from the
+// two-step kernel.
 void build_fused_tiles(const lbm_ctx *c, int rows, std::vector<FusedTileDev> &fused,
-                       std::vector<TileDev> &general, int64_t &fused_cells) {
+                       std::vector<TileDev> &general, std::vector<TileDev> &general1,
+                       int64_t &fused_cells) {
   std::vector<FusedTileDev> lf;
-  std::vector<TileDev> lg;
+  std::vector<TileDev> lg, lh;
   fused_cells = 0;
   for (int g = 0; g < c->nbatch; ++g) {
     const std::vector<Seg> R = fused_row_segments(c, g, rows), C = fused_col_segments(c, g);
@@ -623,17 +634,29 @@ void build_fused_tiles(const lbm_ctx *c, int rows, std::vector<FusedTileDev> &fu
       for (int i = 0; i < nc; ++i) {
         const Seg &rs = R[j], &cs = C[i];
         if (isf[(size_t)j * nc + i]) {
-          int flags = 0;
+          lf.push_back(FusedTileDev{g, cs.lo, cs.hi, rs.lo, rs.hi});
+          fused_cells += (int64_t)(cs.hi - cs.lo) * (rs.hi - rs.lo);
+          // border strips for the first general step: two rows along a
+          // general neighbour above or below, two columns (one 64-column
+          // tile) along one left or right, the 2 x 2 corner (one tile of two
+          // rows) toward a general diagonal neighbour
+          std::set<std::tuple<int, int, int>> strips;
+          const int xl = cs.lo, xr = std::max(cs.lo, cs.hi - 64);
           for (int dj = -1; dj <= 1; ++dj)
             for (int di = -1; di <= 1; ++di) {
               if ((di | dj) == 0 || fused_at(i + di, j + dj) != 0) continue;
-              if (dj < 0) flags |= 1;
-              if (dj > 0) flags |= 2;
-              if (di < 0) flags |= 4;
-              if (di > 0) flags |= 8;
+              const int ya = dj < 0 ? rs.lo : rs.hi - 2;   // the two rows on that side
+              if (di == 0) {
+                for (int xs = cs.lo; xs < cs.hi; xs += 64) strips.emplace(xs, ya, ya + 2);
+              } else if (dj == 0) {
+                for (int ys = rs.lo; ys < rs.hi; ys += kSubRows)
+                  strips.emplace(di < 0 ? xl : xr, ys, std::min(ys + kSubRows, rs.hi));
+              } else {
+                strips.emplace(di < 0 ? xl : xr, ya, ya + 2);
+              }
             }
-          lf.push_back(FusedTileDev{g, cs.lo, cs.hi, rs.lo, rs.hi, flags});
-          fused_cells += (int64_t)(cs.hi - cs.lo) * (rs.hi - rs.lo);
+          for (const auto &st : strips)
+            lh.push_back(TileDev{g, std::get<0>(st), std::get<1>(st), std::get<2>(st)});
         } else {
           for (int ys = rs.lo; ys < rs.hi; ys += kSubRows)
             for (int xs = cs.lo; xs < cs.hi; xs += 64)
@@ -643,12 +666,15 @@ void build_fused_tiles(const lbm_ctx *c, int rows, std::vector<FusedTileDev> &fu
   }
   // die ordering as for the single-step lists
   const int64_t T = (int64_t)lf.size(), per = (T + kXcds - 1) / kXcds;
-  fused.assign((size_t)(per * kXcds), FusedTileDev{-1, 0, 0, 0, 0, 0});
+  fused.assign((size_t)(per * kXcds), FusedTileDev{-1, 0, 0, 0, 0});
   for (int64_t b = 0; b < per * kXcds; ++b) {
     const int64_t jx = b % kXcds, ix = b / kXcds, l = jx * per + ix;
     if (ix < per && l < T) fused[(size_t)b] = lf[(size_t)l];
   }
+  std::vector<TileDev> l1 = lg;
+  l1.insert(l1.end(), lh.begin(), lh.end());
   general = order_for_dies(lg);
+  general1 = order_for_dies(l1);
 }
 
 constexpr int kFilterRows = 32;
@@ -671,17 +697,19 @@ int rebuild_tiles(lbm_ctx *c) {
   c->h_tiles_int = ti;
   c->h_tiles_gen = tg;
   c->adj_tiles_ok = false;
-  c->nftiles = c->ngtiles2 = 0;
+  c->nftiles = c->ngtiles2 = c->ngtiles1 = 0;
   c->cells_fused = c->cells_gen2 = 0;
   if (c->launch.fuse_rows > 0) {
     std::vector<FusedTileDev> tf;
-    std::vector<TileDev> tg2;
-    build_fused_tiles(c, c->launch.fuse_rows, tf, tg2, c->cells_fused);
+    std::vector<TileDev> tg2, tg1;
+    build_fused_tiles(c, c->launch.fuse_rows, tf, tg2, tg1, c->cells_fused);
     c->nftiles = (int)tf.size();
     c->ngtiles2 = (int)tg2.size();
+    c->ngtiles1 = (int)tg1.size();
     c->cells_gen2 = cover(tg2, 64);
     HIP_TRY(c->d_ftiles.upload(tf, c->stream));
     HIP_TRY(c->d_gtiles2.upload(tg2, c->stream));
+    HIP_TRY(c->d_gtiles1.upload(tg1, c->stream));
   }
   HIP_TRY(c->d_tiles_int.upload(ti, c->stream));
   HIP_TRY(c->d_tiles.upload(tg, c->stream));
@@ -744,37 +772,53 @@ hipError_t launch_pair(lbm_ctx *c, hipStream_t s, bool has_int, bool has_gen, Ge
 
 int use_fused(const lbm_ctx *c) { return c->launch.fuse_rows > 0 && c->nftiles > 0; }
 
-// Two steps (t and t+1) on the two-step path: the general kernel advances its
-// tiles to f*(t) in the intermediate buffer while the fused kernel takes its
-// tiles straight to f*(t+1) (and leaves f*(t) of its flagged border cells in
-// the intermediate buffer); then the general kernel takes its tiles from the
-// intermediate buffer to f*(t+1).
-// With stash planes (the adjoint's recompute), the three launches also write
-// rho(t) and rho(t+1) of every cell to rho_t and rho_t1 and skip the receivers.
+// The three launches of a pair of steps (t and t+1) on the two-step path: the
+// general kernel advances its tiles and the two-step blocks' border strips
+// to f*(t) in the intermediate buffer (g1), then its tiles from there to
+// f*(t+1) (g2); the fused kernel takes its tiles straight to f*(t+1) (f2).
+// g1 and g2 need nothing from f2, and f2 nothing from them: they write
+// disjoint cells of the output (the strips' f*(t) goes to the intermediate
+// buffer only, which f2 does not use).
 template <typename real>
-hipError_t launch_two_steps(lbm_ctx *c, StepArgs<real> a, hipStream_t s, real *rho_t = nullptr,
-                            real *rho_t1 = nullptr) {
-  StepArgs<real> g1 = a, f2 = a, g2 = a;
-  const int mode = rho_t ? kModeStash : kModeStep;
-  g1.rho_out = rho_t;
-  f2.rho_out = rho_t;
-  f2.rho_out2 = rho_t1;
-  g2.rho_out = rho_t1;
+void pair_args(lbm_ctx *c, const StepArgs<real> &a, StepArgs<real> &g1, StepArgs<real> &f2,
+               StepArgs<real> &g2) {
+  g1 = f2 = g2 = a;
   g1.fout = reinterpret_cast<real *>(c->fmid);
-  g1.tiles = c->d_gtiles2.p;
+  g1.tiles = c->d_gtiles1.p;
+  g1.fmid = reinterpret_cast<real *>(c->fmid);
   f2.ftiles = c->d_ftiles.p;
   f2.fmid = reinterpret_cast<real *>(c->fmid);
   f2.f_elems = c->L.f_elems;
   g2.fin = reinterpret_cast<const real *>(c->fmid);
   g2.tiles = c->d_gtiles2.p;
+  g2.fmid = reinterpret_cast<real *>(c->fmid);
   g2.t = a.t + 1;
+}
+
+// Two steps on the two-step path: g1 then g2 on the library's second stream,
+// beside f2 on the context's stream (or one after the other without overlap).
+// With stash planes (the adjoint's recompute), the launches also write rho(t)
+// and rho(t+1) of every cell to rho_t and rho_t1 and skip the receivers (g1
+// writes the strips' rho(t) as f2 does, the same values).
+template <typename real>
+hipError_t launch_two_steps(lbm_ctx *c, StepArgs<real> a, hipStream_t s, real *rho_t = nullptr,
+                            real *rho_t1 = nullptr) {
+  StepArgs<real> g1, f2, g2;
+  pair_args<real>(c, a, g1, f2, g2);
+  const int mode = rho_t ? kModeStash : kModeStep;
+  g1.rho_out = rho_t;
+  f2.rho_out = rho_t;
+  f2.rho_out2 = rho_t1;
+  g2.rho_out = rho_t1;
   const int pf = c->launch.prefetch;
-  hipError_t e = launch_pair(
+  return launch_pair(
       c, s, c->nftiles > 0, c->ngtiles2 > 0,
-      [&](hipStream_t q) { return launch_step<real>(g1, 1, pf, c->ngtiles2, mode, q); },
+      [&](hipStream_t q) {
+        hipError_t e = launch_step<real>(g1, 1, pf, c->ngtiles1, mode, q);
+        if (e == hipSuccess) e = launch_step<real>(g2, 1, pf, c->ngtiles2, mode, q);
+        return e;
+      },
       [&](hipStream_t q) { return launch_fused2<real>(f2, fused_waves(c), c->nftiles, q); });
-  if (e == hipSuccess) e = launch_step<real>(g2, 1, pf, c->ngtiles2, mode, s);
-  return e;
 }
 
 template <typename real>
@@ -856,20 +900,13 @@ int step_timed(lbm_ctx *c, int64_t n, lbm_kernel_times *out) {
   if (use_fused(c)) {
     for (; k + 2 <= n && e == hipSuccess; k += 2) {
       const StepArgs<real> a = make_args<real>(c, c->cur);
-      StepArgs<real> g1 = a, f2 = a, g2 = a;
-      g1.fout = reinterpret_cast<real *>(c->fmid);
-      g1.tiles = c->d_gtiles2.p;
-      f2.ftiles = c->d_ftiles.p;
-      f2.fmid = reinterpret_cast<real *>(c->fmid);
-      f2.f_elems = c->L.f_elems;
-      g2.fin = reinterpret_cast<const real *>(c->fmid);
-      g2.tiles = c->d_gtiles2.p;
-      g2.t = a.t + 1;
-      if (c->ngtiles2 > 0)
-        timed(1, [&] { return launch_step<real>(g1, 1, pf, c->ngtiles2, kModeStep, c->stream); });
-      timed(2, [&] { return launch_fused2<real>(f2, fused_waves(c), c->nftiles, c->stream); });
-      if (c->ngtiles2 > 0)
+      StepArgs<real> g1, f2, g2;
+      pair_args<real>(c, a, g1, f2, g2);
+      if (c->ngtiles2 > 0) {
+        timed(1, [&] { return launch_step<real>(g1, 1, pf, c->ngtiles1, kModeStep, c->stream); });
         timed(1, [&] { return launch_step<real>(g2, 1, pf, c->ngtiles2, kModeStep, c->stream); });
+      }
+      timed(2, [&] { return launch_fused2<real>(f2, fused_waves(c), c->nftiles, c->stream); });
       if (e == hipSuccess) {
         c->cur ^= 1;
         c->t += 2;
@@ -1881,6 +1918,7 @@ int lbm_destroy(lbm_ctx *c) {
   c->d_ftiles.release();
   c->d_filt_tiles.release();
   c->d_gtiles2.release();
+  c->d_gtiles1.release();
   c->d_tiles_int.release();
   c->d_krows.release();
   c->d_sponge.release();

@@ -55,12 +55,9 @@ struct TileDev {
 constexpr int kFusedMaxRows = 248;
 
 // A tile of the two-step kernel: grid g, columns [x0, x1) with
-// 0 < x1 - x0 <= 64*NW, rows [y0, y1) with y1 - y0 <= kFusedMaxRows; flags:
-// bit 0/1/2/3 = also write the intermediate state of the tile's two top rows
-// / bottom rows / left columns / right columns (next to cells the general
-// kernel advances step by step).
+// 0 < x1 - x0 <= 64*NW, rows [y0, y1) with y1 - y0 <= kFusedMaxRows.
 struct FusedTileDev {
-  int32_t g, x0, x1, y0, y1, flags;
+  int32_t g, x0, x1, y0, y1;
 };
 
 template <typename real>
@@ -84,8 +81,10 @@ struct StepArgs {
   real *rho_out;         // stash mode: rho(t) of every cell at c_off + y * pitch + x
   real *rho_out2;        // two-step kernel in stash mode: rho(t+1), same layout
   const FusedTileDev *ftiles;  // two-step kernel: its tiles
-  real *fmid;            // two-step kernel: intermediate state f*(t) of the border cells
-  int64_t f_elems;       // elements of one population buffer (bounds of fin/fout/fmid)
+  real *fmid;            // two-step path: the pair's intermediate buffer f*(t), fout of its
+                         // first general launch and fin of its second (set on each launch of
+                         // a pair so the host-side checks can tell them apart; no kernel reads it)
+  int64_t f_elems;       // elements of one population buffer (bounds of fin/fout)
 };
 
 // kModeStash: the step plus the density of every cell written to rho_out,
@@ -137,7 +136,7 @@ hipError_t launch_step(const StepArgs<real> &a, int waves, int prefetch, int nti
                        hipStream_t stream);
 
 // Two steps (t and t+1) of the interior tiles in a.ftiles: reads a.fin =
-// f*(t-1), writes a.fout = f*(t+1) and, for flagged border cells, a.fmid = f*(t);
+// f*(t-1), writes a.fout = f*(t+1) (f*(t) stays on chip);
 // with a.rho_out set also rho(t) and rho(t+1) of its cells to a.rho_out and
 // a.rho_out2.
 template <typename real>

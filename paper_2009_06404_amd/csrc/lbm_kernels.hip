@@ -706,8 +706,7 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t range_rsrc(const void *base, u
 // workgroup marches down the tile's rows with a four-stage pipeline:
 //   A (row r):   pull f(t) from f*(t-1) in HBM (row r+1 already in flight),
 //                rho(t) into an LDS ring;
-//   B (row r-1): density gradient and collision of step t -> f*(t) (and to
-//                HBM for flagged border cells);
+//   B (row r-1): density gradient and collision of step t -> f*(t);
 //   C (row r-2): pull f(t+1) from f*(t) of rows r-3 .. r-1, rho(t+1) into an
 //                LDS ring;
 //   D (row r-3): density gradient and collision of step t+1 -> f*(t+1) to HBM.
@@ -775,7 +774,6 @@ __global__ __launch_bounds__(64 * NW + 64) void fused2_kernel(StepArgs<real> a) 
   const uint64_t rest = (uint64_t)(a.f_elems - base) * esz;
   const __amdgpu_buffer_rsrc_t rin = range_rsrc(a.fin + base, rest);
   const __amdgpu_buffer_rsrc_t rout = range_rsrc(a.fout + base, rest);
-  const __amdgpu_buffer_rsrc_t rmid = range_rsrc(a.fmid + base, rest);
 
   // Per-row look-ups of the tile's rows, read once: the top/bottom sponge
   // pair of the row (combined with the column's pair by the same max/min as
@@ -796,8 +794,6 @@ __global__ __launch_bounds__(64 * NW + 64) void fused2_kernel(StepArgs<real> a) 
   const real kscalar = (real)g.kscalar;
   const real *kcol = a.kappa_cells + g.k_off + col;
   const bool inB = lc >= 1 && lc <= w + 6, inC = lc >= 2 && lc <= w + 5;
-  const int dump = tile.flags;
-  const bool dump_col = (outlane && (((dump & 4) && lc < 6) || ((dump & 8) && lc >= w + 2)));
   __syncthreads();
 
   // Registers carried down the rows, each set rotated with its period:
@@ -828,7 +824,12 @@ __global__ __launch_bounds__(64 * NW + 64) void fused2_kernel(StepArgs<real> a) 
     real &rC_n = RC[P % 3], &rC_c = RC[(P + 2) % 3], &rC_m = RC[(P + 1) % 3];
     real kn = real(0);
     if (live && r + 1 >= y0 - 3 && r + 1 <= rlast) {
-      pull_fast(rin, ybase, r + 1, rowb, qb, o0, ol, orr, fc);
+      // the row index and the store offset below go through an empty asm:
+      // otherwise the compiler keeps every population's offset of every
+      // unrolled row as its own scalar induction variable and spills them
+      int rn = r + 1;
+      asm volatile("" : "+s"(rn));
+      pull_fast(rin, ybase, rn, rowb, qb, o0, ol, orr, fc);
       if (kcells) kn = kcol[(int64_t)(r + 1) * pitch];
     }
     // Stage A: row r of step t.
@@ -858,12 +859,6 @@ __global__ __launch_bounds__(64 * NW + 64) void fused2_kernel(StepArgs<real> a) 
       p0 = s1[0];
       p2 = s1[2];
       p4 = s1[4];
-      if (dump && outlane && rb >= y0 && rb < y1 &&
-          (dump_col || ((dump & 1) && rb < y0 + 2) || ((dump & 2) && rb >= y1 - 2))) {
-        const uint32_t rs = (uint32_t)(rb - ybase) * rowb;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) Buf<real>::store_nt(s1[i], rmid, o0, rs + i * qb);
-      }
     }
     __syncthreads();
     // Stage C: row r-2 of step t+1, pulled from f*(t) of rows r-3 .. r-1.
@@ -894,7 +889,8 @@ __global__ __launch_bounds__(64 * NW + 64) void fused2_kernel(StepArgs<real> a) 
       const CellState<real> cs = cell_state(gc, rC_c, kap * dx, kap * dy, A, inv);
       real s2[9];
       collide(gc, cs, omega, cforce, s2);
-      const uint32_t rs = (uint32_t)(rd - ybase) * rowb;
+      uint32_t rs = (uint32_t)(rd - ybase) * rowb;
+      asm volatile("" : "+s"(rs));
 #pragma unroll
       for (int i = 0; i < 9; ++i) Buf<real>::store_nt(s2[i], rout, o0, rs + i * qb);
     }

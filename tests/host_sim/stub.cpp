@@ -79,19 +79,19 @@ static void check_pop(const real *base, const GridDev &g, const char *what) {
   check_range(base + g.f_off, sizeof(real) * 9 * (size_t)g.pitch * g.ny, what);
 }
 // Two-step path bookkeeping. Each launch gets a sequence number and stamps
-// the cells it writes in its output buffer. A pair is general step t into the
-// intermediate buffer, the two-step kernel (seq s) and general step t+1 out of
-// the intermediate buffer: the first general launch runs just before or just
-// after the two-step kernel (seq s-1 or s+1), so the last must find every
-// cell it may read (within two cells of its tiles) stamped s-1 or later, and
-// the two-step kernel plus the second general launch must write every cell of
-// every grid exactly once.
-static int64_t g_seq = 0, g_fused_seq = -10;
+// the cells it writes in its output buffer. A pair is: the general kernel's
+// first step (g1: its tiles and the two-step blocks' border strips, into the
+// intermediate buffer), its second step (g2: out of the intermediate buffer)
+// and the two-step kernel (f2), which needs nothing from g1 or g2. So g2 must
+// find every cell it may read (within two cells of its tiles) stamped by the
+// g1 launched just before it, and f2 plus g2 must write every cell of every
+// grid exactly once, in either order.
+static int64_t g_seq = 0, g_g1_seq = -10;
 static const void *g_fmid = nullptr, *g_pair_out = nullptr;
 static std::map<const void *, std::map<int, std::vector<int64_t>>> g_stamps;
 static std::map<int, std::vector<int>> g_cov;   // per grid and cell: writes of the pending pair
 static int g_ngrids = 0;
-static bool g_pending = false;
+static bool g_seen_f2 = false, g_seen_g2 = false;
 static int64_t g_pairs_checked = 0;
 
 static std::vector<int64_t> &stamps(const void *buf, int g, const GridDev &G) {
@@ -99,8 +99,13 @@ static std::vector<int64_t> &stamps(const void *buf, int g, const GridDev &G) {
   if (v.empty()) v.assign((size_t)G.nx * G.ny, -100);
   return v;
 }
+static void pair_start(const void *out) {
+  if (g_seen_f2 || g_seen_g2) return;   // the pair has begun
+  g_pair_out = out;
+  g_cov.clear();
+}
 static void pair_check_done() {
-  if (!g_pending) return;
+  if (!(g_seen_f2 && g_seen_g2)) return;
   for (int g = 0; g < g_ngrids; ++g) {
     const std::vector<int> &v = g_cov[g];
     for (size_t i = 0; i < v.size(); ++i)
@@ -109,10 +114,15 @@ static void pair_check_done() {
         abort();
       }
   }
-  g_pending = false;
+  g_seen_f2 = g_seen_g2 = false;
   ++g_pairs_checked;
 }
 extern "C" int64_t sim_pairs_checked() { pair_check_done(); return g_pairs_checked; }
+static std::vector<int> &cov(int g, const GridDev &G) {
+  std::vector<int> &v = g_cov[g];
+  if (v.empty()) v.assign((size_t)G.nx * G.ny, 0);
+  return v;
+}
 
 template <typename real>
 hipError_t launch_step(const StepArgs<real> &a, int waves, int, int ntiles, int mode, hipStream_t) {
@@ -120,7 +130,15 @@ hipError_t launch_step(const StepArgs<real> &a, int waves, int, int ntiles, int 
   check_tiles<real>(a.tiles, ntiles, a.grids, 64 * waves, false, "step tiles");
   const int64_t seq = g_seq++;
   const int W = 64 * waves;
+  if (a.fmid) g_fmid = a.fmid;
+  const bool first = g_fmid && (const void *)a.fout == g_fmid;
   const bool second = g_fmid && (const void *)a.fin == g_fmid;
+  if (first) g_g1_seq = seq;
+  if (second) {
+    if (g_seen_g2) { fprintf(stderr, "two second general steps in one pair\n"); abort(); }
+    pair_start(a.fout);
+    if ((const void *)a.fout != g_pair_out) { fprintf(stderr, "second general step writes another buffer than its pair\n"); abort(); }
+  }
   for (int i = 0; i < ntiles && mode != kModeMoments; ++i) {
     const TileDev t = a.tiles[i];
     if (t.g < 0) continue;
@@ -128,22 +146,18 @@ hipError_t launch_step(const StepArgs<real> &a, int waves, int, int ntiles, int 
     const bool px = g.bc[kEdgeLeft] == kPeriodic, py = g.bc[kEdgeTop] == kPeriodic;
     std::vector<int64_t> &out = stamps(a.fout, t.g, g);
     std::vector<int64_t> *mid = second ? &stamps(g_fmid, t.g, g) : nullptr;
-    if (second && (!g_pending || (const void *)a.fout != g_pair_out)) {
-      fprintf(stderr, "second general step without its two-step launch\n");
-      abort();
-    }
     for (int y = t.y0; y < t.y1; ++y)
       for (int x = t.x0; x < t.x0 + W && x < g.nx; ++x) {
         out[(size_t)y * g.nx + x] = seq;
         if (!second) continue;
-        g_cov[t.g][(size_t)y * g.nx + x] += 1;
+        cov(t.g, g)[(size_t)y * g.nx + x] += 1;
         for (int dy = -2; dy <= 2; ++dy)
           for (int dx = -2; dx <= 2; ++dx) {
             int xx = x + dx, yy = y + dy;
             if (xx < 0 || xx >= g.nx) { if (!px) continue; xx = (xx + g.nx) % g.nx; }
             if (yy < 0 || yy >= g.ny) { if (!py) continue; yy = (yy + g.ny) % g.ny; }
-            if ((*mid)[(size_t)yy * g.nx + xx] < g_fused_seq - 1) {
-              fprintf(stderr, "second general step reads stale intermediate cell g=%d (%d,%d) from (%d,%d)\n",
+            if ((*mid)[(size_t)yy * g.nx + xx] < g_g1_seq) {
+              fprintf(stderr, "second general step reads a cell the first did not write: g=%d (%d,%d) from (%d,%d)\n",
                       t.g, xx, yy, x, y);
               abort();
             }
@@ -156,6 +170,10 @@ hipError_t launch_step(const StepArgs<real> &a, int waves, int, int ntiles, int 
     check_pop(a.fin, g, "step fin");
     if (mode != kModeMoments) check_pop(a.fout, g, "step fout");
     if (mode == kModeStash) check_range(a.rho_out + g.c_off, sizeof(real) * (size_t)g.pitch * g.ny, "stash out");
+  }
+  if (second) {
+    g_seen_g2 = true;
+    pair_check_done();
   }
   return hipSuccess;
 }
@@ -177,18 +195,16 @@ hipError_t launch_fused2(const StepArgs<real> &a, int waves, int ntiles, hipStre
   if (ntiles <= 0) return hipSuccess;
   const int W = 64 * waves;
   check_range(a.ftiles, sizeof(FusedTileDev) * ntiles, "fused tiles");
-  pair_check_done();
   // every grid's population block lies inside f_elems: count the grids
   g_ngrids = 0;
   for (int64_t fe = 0; fe < a.f_elems; ++g_ngrids)
     fe = a.grids[g_ngrids].f_off + 9 * (int64_t)a.grids[g_ngrids].pitch * a.grids[g_ngrids].ny;
   const int64_t seq = g_seq++;
-  g_fused_seq = seq;
   g_fmid = a.fmid;
-  g_pair_out = a.fout;
-  g_pending = true;
-  g_cov.clear();
-  for (int g = 0; g < g_ngrids; ++g) g_cov[g].assign((size_t)a.grids[g].nx * a.grids[g].ny, 0);
+  if (g_seen_f2) { fprintf(stderr, "two two-step launches in one pair\n"); abort(); }
+  pair_start(a.fout);
+  if ((const void *)a.fout != g_pair_out) { fprintf(stderr, "two-step launch writes another buffer than its pair\n"); abort(); }
+  for (int g = 0; g < g_ngrids; ++g) cov(g, a.grids[g]);
   for (int i = 0; i < ntiles; ++i) {
     const FusedTileDev t = a.ftiles[i];
     if (t.g < 0) continue;
@@ -201,7 +217,6 @@ hipError_t launch_fused2(const StepArgs<real> &a, int waves, int ntiles, hipStre
     }
     check_pop(a.fin, g, "fused fin");
     check_pop(a.fout, g, "fused fout");
-    check_pop(a.fmid, g, "fused fmid");
     if (a.rho_out) {
       check_range(a.rho_out + g.c_off, sizeof(real) * (size_t)g.pitch * g.ny, "fused stash t");
       check_range(a.rho_out2 + g.c_off, sizeof(real) * (size_t)g.pitch * g.ny, "fused stash t+1");
@@ -226,20 +241,16 @@ hipError_t launch_fused2(const StepArgs<real> &a, int waves, int ntiles, hipStre
     if (g.nrec > 0)
       for (int y = t.y0; y < t.y1; ++y)
         if (a.itab[g.rowtab_off + y] >= 0) { fprintf(stderr, "receiver row %d in a fused tile\n", y); abort(); }
-    std::vector<int64_t> &mid = stamps(a.fmid, t.g, g);
     std::vector<int64_t> &out = stamps(a.fout, t.g, g);
-    const int w = t.x1 - t.x0;
     for (int y = t.y0; y < t.y1; ++y)
       for (int x = t.x0; x < t.x1; ++x) {
         const size_t c = (size_t)y * g.nx + x;
         g_cov[t.g][c] += 1;
         out[c] = seq;
-        const int lx = x - t.x0;
-        const bool dump = ((t.flags & 4) && lx < 2) || ((t.flags & 8) && lx >= w - 2) ||
-                          ((t.flags & 1) && y < t.y0 + 2) || ((t.flags & 2) && y >= t.y1 - 2);
-        if (dump) mid[c] = seq;
       }
   }
+  g_seen_f2 = true;
+  pair_check_done();
   return hipSuccess;
 }
 template <typename real>
