@@ -124,6 +124,12 @@ namespace {
 
 bool f64(const lbm3_ctx *c) { return c->dtype == LBM_F64; }
 
+// General tiles are cut into z chunks of at most this many planes: more,
+// shorter workgroups, which hide beside the lean launch better than a few
+// that march a whole segment (256^3 half-space, FP32: D3Q19 0.625 against
+// 0.631 ms per step, D3Q27 0.897 against 0.930, with the general launch first).
+constexpr int kGeneralPlanes = 4;
+
 int default_planes(const lbm3_ctx *c, int rows_y) {
   // segments of 16 planes (each re-pulls one plane before and after it: 1/8
   // more reads, from L2), shorter when the volume has too few tiles per plane
@@ -201,7 +207,8 @@ int build_tiles(lbm3_ctx *c) {
         const int64_t cells = (int64_t)w * h * (z1 - z0);
         all.push_back(t);
         if (general) {
-          gen.push_back(t);
+          for (int zs = z0; zs < z1; zs += kGeneralPlanes)
+            gen.push_back(Tile3Dev{x0, y0, zs, std::min(zs + kGeneralPlanes, z1)});
           gen_cells += cells;
         } else {
           lean.push_back(t);
@@ -231,23 +238,26 @@ int launch_list(lbm3_ctx *c, bool general, const Tile3Dev *tiles, int n, const v
   return LBM_OK;
 }
 
-// One step: the general tiles on the library's second stream, forked from and
-// joined back to the context's stream, beside the lean tiles on the context's
-// stream. The two read the same state and write disjoint cells.
+// One step: the general tiles on the context's stream, the lean tiles beside
+// them on the library's second stream, forked from the context's stream
+// before the general launch and joined back after it. The two read the same
+// state and write disjoint cells. The general launch goes first so that its
+// few, slower workgroups start before the lean ones fill the chip (the fork's
+// wait delays the lean launch by a few microseconds).
 int launch_step(lbm3_ctx *c) {
   const void *fin = c->fbuf[c->cur];
   void *fout = c->fbuf[c->cur ^ 1];
   if (c->n_general > 0 && c->n_lean > 0) {
     HIP3_TRY(hipEventRecord(c->fork, c->stream));
+    int rc = launch_list(c, true, c->d_general.p, c->n_general, fin, fout, nullptr, 0);
+    if (rc) return rc;
     HIP3_TRY(hipStreamWaitEvent(c->side, c->fork, 0));
     hipStream_t main = c->stream;
     c->stream = c->side;
-    int rc = launch_list(c, true, c->d_general.p, c->n_general, fin, fout, nullptr, 0);
+    rc = launch_list(c, false, c->d_lean.p, c->n_lean, fin, fout, nullptr, 0);
     c->stream = main;
     if (rc) return rc;
     HIP3_TRY(hipEventRecord(c->join, c->side));
-    rc = launch_list(c, false, c->d_lean.p, c->n_lean, fin, fout, nullptr, 0);
-    if (rc) return rc;
     HIP3_TRY(hipStreamWaitEvent(c->stream, c->join, 0));
     return LBM_OK;
   }
