@@ -359,8 +359,9 @@ void build_tiles(const lbm_ctx *c, int waves, int rows, bool split, std::vector<
 // tiles where the grid would otherwise give too few workgroups to fill 256
 // compute units.
 // Launch shape by size (measured on MI355X): large contexts take the two-step
-// path, with taller blocks on very tall grids and in FP64 (where the halo
-// rows cost twice the bytes); small ones single steps in smaller tiles.
+// path, with wider and taller blocks on very large FP32 grids and shorter
+// ones in FP64 at 4096^2 (72.6 GLUPS at 16 rows against 71.1 at 32); small
+// ones single steps in smaller tiles.
 lbm_launch default_launch(const lbm_ctx *c) {
   int64_t cells = 0;
   int max_ny = 0;
@@ -371,9 +372,10 @@ lbm_launch default_launch(const lbm_ctx *c) {
   lbm_launch l{8, c->dtype == LBM_F64 ? 4 : 8, 0, 1, 1, 0, 1, 0};
   // two-step blocks: 128 columns (more workgroups per CU hide the row loop's
   // barriers), 256 on very tall grids; taller blocks where there are enough
-  // of them to fill the chip, and in FP64
+  // of them to fill the chip
+  const bool huge = cells >= (int64_t)8192 * 8192;
   l.waves = max_ny >= 8192 ? 4 : 2;
-  l.fuse_rows = (c->dtype == LBM_F32 && cells >= (int64_t)8192 * 8192) ? 64 : 32;
+  l.fuse_rows = c->dtype == LBM_F32 ? (huge ? 64 : 32) : (huge ? 32 : 16);
   if (cells < 2048 * 2048) {
     l.waves = 4;
     l.rows = 4;
