@@ -212,7 +212,7 @@ def bench_hbm_scale(torch, w, Solver, steps: int = 200, warmup: int = 20) -> dic
             "launch": launch, "state_finite": bool(ok)}
 
 
-BATCHED_LAUNCH = {"waves": 2, "rows": 8, "fuse_rows": 64}
+BATCHED_LAUNCH = {"waves": 2, "rows": 8, "fuse_rows": 32}
 # 1024-column grids: narrow, short tiles for the adjoint kernels; the recorded
 # forward and the recompute run on the two-step path (128-column blocks)
 ADJOINT_LAUNCH = {"waves": 2, "rows": 4, "fuse_rows": 32}

@@ -359,9 +359,11 @@ void build_tiles(const lbm_ctx *c, int waves, int rows, bool split, std::vector<
 // tiles where the grid would otherwise give too few workgroups to fill 256
 // compute units.
 // Launch shape by size (measured on MI355X): large contexts take the two-step
-// path, with wider and taller blocks on very large FP32 grids and shorter
-// ones in FP64 at 4096^2 (72.6 GLUPS at 16 rows against 71.1 at 32); small
-// ones single steps in smaller tiles.
+// path, with wider and taller blocks on very tall grids (16384^2 FP32: 142.3
+// GLUPS at 256 x 64 against 139.0 at 256 x 32), 128 x 32 blocks otherwise in
+// FP32 (512 batched grids of side 256..2048: 132.9 GLUPS against 126.4 at
+// 128 x 64) and 128 x 16 in FP64 (4096^2: 72.6 against 71.1 at 128 x 32);
+// small ones single steps in smaller tiles.
 lbm_launch default_launch(const lbm_ctx *c) {
   int64_t cells = 0;
   int max_ny = 0;
@@ -371,11 +373,10 @@ lbm_launch default_launch(const lbm_ctx *c) {
   }
   lbm_launch l{8, c->dtype == LBM_F64 ? 4 : 8, 0, 1, 1, 0, 1, 0};
   // two-step blocks: 128 columns (more workgroups per CU hide the row loop's
-  // barriers), 256 on very tall grids; taller blocks where there are enough
-  // of them to fill the chip
-  const bool huge = cells >= (int64_t)8192 * 8192;
-  l.waves = max_ny >= 8192 ? 4 : 2;
-  l.fuse_rows = c->dtype == LBM_F32 ? (huge ? 64 : 32) : (huge ? 32 : 16);
+  // barriers); 256 columns and taller blocks on very tall grids
+  const bool tall = max_ny >= 8192;
+  l.waves = tall ? 4 : 2;
+  l.fuse_rows = c->dtype == LBM_F32 ? (tall ? 64 : 32) : (tall ? 32 : 16);
   if (cells < 2048 * 2048) {
     l.waves = 4;
     l.rows = 4;
