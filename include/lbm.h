@@ -263,8 +263,22 @@ int lbm_get_launch(const lbm_ctx *ctx, lbm_launch *out);
 int lbm_set_launch(lbm_ctx *ctx, const lbm_launch *cfg);
 
 /* Time each candidate launch configuration on the live context (the state is
- * saved and restored) and keep the fastest. steps: timed steps per candidate.
- * Synchronous. */
+ * saved and restored, the time unchanged) and keep the fastest. On the
+ * two-step path (fuse_rows > 0) the candidates are its block widths (waves
+ * 2, 4, 8) and heights (fuse_rows 16 .. 64); otherwise the single-step tile
+ * widths, heights, prefetch depths and column pairing. graph_chunk, split
+ * and overlap stay as set. steps: timed steps per candidate (rounded up to
+ * even on the two-step path); 0 takes the cached result for this context's
+ * key if there is one, else tunes with 10 steps. Results are cached per GPU
+ * architecture, dtype, boundary class (edge kinds, internal rigid row,
+ * sources, receivers), powers of two of the total cells, tallest grid and
+ * grid count, and path, for the process and, when the environment variable
+ * LBM_TUNE_CACHE names a file, in that file (one line per result, appended).
+ * The tuning runs record receiver rows of the times they reach, with the
+ * values those steps produce. Synchronous; allocates a copy of the state
+ * while it runs. Returns LBM_OK,
+ * LBM_E_INVALID (steps < 0) or LBM_E_DEVICE (a HIP call failed, the copy's
+ * allocation included; the previous configuration is reinstalled). */
 int lbm_autotune(lbm_ctx *ctx, int32_t steps, lbm_launch *chosen);
 
 /* ---- Discrete adjoint: gradients of a receiver misfit ------------------

@@ -8,7 +8,10 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <set>
 #include <string>
 #include <tuple>
@@ -681,6 +684,10 @@ void build_fused_tiles(const lbm_ctx *c, int rows, std::vector<FusedTileDev> &fu
 }
 
 constexpr int kFilterRows = 32;
+
+// Timed steps per autotuning candidate when the caller passes 0 and nothing is
+// cached for the context.
+constexpr int kDefaultTuneSteps = 10;
 
 int rebuild_tiles(lbm_ctx *c) {
   std::vector<TileDev> ti, tg;
@@ -1691,12 +1698,146 @@ int lbm_set_launch(lbm_ctx *c, const lbm_launch *cfg) {
   return LBM_OK;
 }
 
+namespace {
+
+// Tuning results per (GPU architecture, dtype, boundary class, size class,
+// path), kept for the life of the process and, when the environment variable
+// LBM_TUNE_CACHE names a file, across processes: one line
+// "key|waves rows prefetch pair fuse_rows" per result, read the first time
+// the file is named and appended to after each tuning run (the last line of a
+// key wins). Lines that do not parse or hold an invalid launch are skipped.
+struct TuneCache {
+  std::mutex mu;
+  std::map<std::string, lbm_launch> map;
+  std::set<std::string> files_read;
+};
+
+TuneCache &tune_cache() {
+  static TuneCache tc;
+  return tc;
+}
+
+bool tuned_launch_ok(const lbm_launch &l) {
+  return (l.waves == 1 || l.waves == 2 || l.waves == 4 || l.waves == 8) && l.rows >= 1 &&
+         l.rows <= 4096 && l.prefetch >= 1 && l.prefetch <= 2 && (l.pair == 0 || l.pair == 1) &&
+         (l.fuse_rows == 0 || (l.fuse_rows >= 4 && l.fuse_rows <= kFusedMaxRows));
+}
+
+int floor_log2(int64_t v) {
+  int k = 0;
+  while (k < 62 && ((int64_t)1 << (k + 1)) <= v) ++k;
+  return k;
+}
+
+// The key: the architecture name without its feature suffix, the dtype, the
+// distinct boundary classes of the grids (edge kinds, internal rigid row,
+// sources, receivers), powers of two of the total cells, of the tallest grid
+// and of the number of grids, and the path (pairs of steps or single steps).
+std::string tune_key(const lbm_ctx *c) {
+  std::string arch = "unknown";
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+  }
+  int64_t cells = 0;
+  int max_ny = 0;
+  std::set<std::string> cls;
+  for (int g = 0; g < c->nbatch; ++g) {
+    cells += (int64_t)c->grids[g].nx * c->grids[g].ny;
+    max_ny = std::max(max_ny, c->grids[g].ny);
+    const lbm_bc &b = c->bc[g];
+    char buf[64];
+    snprintf(buf, sizeof buf, "%d%d%d%d%c%c%c", b.edge[0], b.edge[1], b.edge[2], b.edge[3],
+             b.rigid_row > 0 ? 'r' : '-', c->sources[g].empty() ? '-' : 's',
+             c->recs[g].xy.empty() ? '-' : 'v');
+    cls.insert(buf);
+  }
+  std::string key = arch + (c->dtype == LBM_F64 ? " f64 " : " f32 ");
+  for (const std::string &k : cls) key += k + ",";
+  key += " cells 2^" + std::to_string(floor_log2(cells)) + " rows 2^" +
+         std::to_string(floor_log2(max_ny)) + " grids 2^" + std::to_string(floor_log2(c->nbatch)) +
+         (c->launch.fuse_rows > 0 ? " pairs" : " single");
+  return key;
+}
+
+// Reads the file LBM_TUNE_CACHE names, once per file name. Caller holds mu.
+void tune_cache_load(TuneCache &tc) {
+  const char *path = std::getenv("LBM_TUNE_CACHE");
+  if (!path || !*path || tc.files_read.count(path)) return;
+  tc.files_read.insert(path);
+  FILE *f = std::fopen(path, "r");
+  if (!f) return;
+  char line[1024];
+  while (std::fgets(line, sizeof line, f)) {
+    const char *bar = std::strrchr(line, '|');
+    if (!bar) continue;
+    lbm_launch l{};
+    if (std::sscanf(bar + 1, "%d %d %d %d %d", &l.waves, &l.rows, &l.prefetch, &l.pair,
+                    &l.fuse_rows) != 5 || !tuned_launch_ok(l))
+      continue;
+    tc.map[std::string(line, bar - line)] = l;
+  }
+  std::fclose(f);
+}
+
+// Records a result in the process and appends it to the named file, if any.
+// Caller holds mu.
+void tune_cache_store(TuneCache &tc, const std::string &key, const lbm_launch &l) {
+  tc.map[key] = l;
+  const char *path = std::getenv("LBM_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE *f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s|%d %d %d %d %d\n", key.c_str(), l.waves, l.rows, l.prefetch, l.pair,
+               l.fuse_rows);
+  std::fclose(f);
+}
+
+// Installs the shape fields of l (the caller's graph chunk, split and overlap
+// are kept).
+int apply_tuned(lbm_ctx *c, const lbm_launch &l, lbm_launch *chosen) {
+  lbm_launch next = c->launch;
+  next.waves = l.waves;
+  next.rows = l.rows;
+  next.prefetch = l.prefetch;
+  next.pair = l.pair;
+  next.fuse_rows = l.fuse_rows;
+  c->launch = next;
+  const int rc = rebuild_tiles(c);
+  if (rc) return rc;
+  if (chosen) *chosen = next;
+  return LBM_OK;
+}
+
+}  // namespace
+
 int lbm_autotune(lbm_ctx *c, int32_t steps, lbm_launch *chosen) {
   int rc = check_ctx(c);
   if (rc) return rc;
-  if (steps < 1) return fail(LBM_E_INVALID, "steps must be >= 1");
+  if (steps < 0) return fail(LBM_E_INVALID, "steps must be >= 0");
   rc = commit(c);
   if (rc) return rc;
+  const std::string key = tune_key(c);
+  TuneCache &tc = tune_cache();
+  if (steps == 0) {
+    lbm_launch hit{};
+    bool found = false;
+    {
+      std::lock_guard<std::mutex> lock(tc.mu);
+      tune_cache_load(tc);
+      auto it = tc.map.find(key);
+      if (it != tc.map.end()) {
+        hit = it->second;
+        found = true;
+      }
+    }
+    if (found) return apply_tuned(c, hit, chosen);
+    steps = kDefaultTuneSteps;
+  }
+  const bool pairs = c->launch.fuse_rows > 0;
+  if (pairs) steps += steps % 2;   // whole pairs
   // Save the state; every candidate restarts from it.
   const size_t bytes = (size_t)c->L.f_elems * c->L.esize;
   void *save = nullptr;
@@ -1710,42 +1851,57 @@ int lbm_autotune(lbm_ctx *c, int32_t steps, lbm_launch *chosen) {
   if (e == hipSuccess) e = hipEventCreate(&ev1);
   int64_t cells = 0;
   for (auto &g : c->grids) cells += (int64_t)g.nx * g.ny;
+  // Candidates. On the two-step path: the block width (waves) and height
+  // (fuse_rows), the single-step shape kept for odd last steps. Otherwise the
+  // single-step tile width, height, prefetch depth and column pairing.
+  std::vector<lbm_launch> cands;
+  if (pairs) {
+    for (int w : {2, 4, 8})
+      for (int fr : {16, 24, 29, 32, 44, 48, 64}) {
+        lbm_launch cand = keep;
+        cand.waves = w;
+        cand.fuse_rows = fr;
+        cands.push_back(cand);
+      }
+  } else {
+    bool even = true;
+    for (auto &g : c->grids) even = even && (g.nx % 2 == 0);
+    for (int pair = 0; pair <= (even ? 1 : 0); ++pair)
+      for (int pf = 1; pf <= 2; ++pf)
+        for (int w : {1, 2, 4, 8})
+          for (int r : {2, 4, 8, 16, 32, 64}) {
+            lbm_launch cand{w, r, 0, pf, keep.split, pair, keep.overlap, 0};
+            if (pair && w == 1) continue;
+            const int64_t tiles = cells / ((int64_t)64 * w * r);
+            if (tiles < 512 && !(w == 1 && r == 4)) continue;
+            cands.push_back(cand);
+          }
+  }
   lbm_launch best = keep;
   float best_ms = 1e30f;
-  const int waves_c[4] = {1, 2, 4, 8};
-  const int rows_c[6] = {2, 4, 8, 16, 32, 64};
-  bool even = true;
-  for (auto &g : c->grids) even = even && (g.nx % 2 == 0);
-  for (int pair = 0; pair <= (even ? 1 : 0); ++pair)
-  for (int pf = 1; pf <= 2; ++pf)
-  for (int wi = 0; wi < 4 && e == hipSuccess && rc == LBM_OK; ++wi)
-    for (int ri = 0; ri < 6 && e == hipSuccess && rc == LBM_OK; ++ri) {
-      lbm_launch cand{waves_c[wi], rows_c[ri], 0, pf, keep.split, pair, keep.overlap, 0};
-      if (pair && cand.waves == 1) continue;
-      const int64_t tiles = cells / ((int64_t)64 * cand.waves * cand.rows);
-      if (tiles < 512 && !(cand.waves == 1 && cand.rows == 4)) continue;
-      c->launch = cand;
-      rc = rebuild_tiles(c);
-      if (rc) break;
-      c->cur = cur0;
-      c->t = t0;
-      e = hipMemcpyAsync(c->fbuf[cur0], save, bytes, hipMemcpyDeviceToDevice, c->stream);
-      if (e != hipSuccess) break;
-      rc = c->dtype == LBM_F64 ? step_direct<double>(c, 2) : step_direct<float>(c, 2);  // warm-up
-      if (rc) break;
-      e = hipEventRecord(ev0, c->stream);
-      if (e != hipSuccess) break;
-      rc = c->dtype == LBM_F64 ? step_direct<double>(c, steps) : step_direct<float>(c, steps);
-      if (rc) break;
-      e = hipEventRecord(ev1, c->stream);
-      if (e == hipSuccess) e = hipEventSynchronize(ev1);
-      float ms = 0;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
-      if (e == hipSuccess && ms < best_ms) {
-        best_ms = ms;
-        best = cand;
-      }
+  for (size_t k = 0; k < cands.size() && e == hipSuccess && rc == LBM_OK; ++k) {
+    c->launch = cands[k];
+    rc = rebuild_tiles(c);
+    if (rc) break;
+    c->cur = cur0;
+    c->t = t0;
+    e = hipMemcpyAsync(c->fbuf[cur0], save, bytes, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) break;
+    rc = c->dtype == LBM_F64 ? step_direct<double>(c, 2) : step_direct<float>(c, 2);  // warm-up
+    if (rc) break;
+    e = hipEventRecord(ev0, c->stream);
+    if (e != hipSuccess) break;
+    rc = c->dtype == LBM_F64 ? step_direct<double>(c, steps) : step_direct<float>(c, steps);
+    if (rc) break;
+    e = hipEventRecord(ev1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ev1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev0, ev1);
+    if (e == hipSuccess && ms < best_ms) {
+      best_ms = ms;
+      best = cands[k];
     }
+  }
   // Restore the state and install the winner (keeping the graph chunk).
   c->cur = cur0;
   c->t = t0;
@@ -1754,15 +1910,21 @@ int lbm_autotune(lbm_ctx *c, int32_t steps, lbm_launch *chosen) {
   hipFree(save);
   if (ev0) hipEventDestroy(ev0);
   if (ev1) hipEventDestroy(ev1);
-  if (rc) return rc;
-  if (e != hipSuccess) return fail(LBM_E_DEVICE, hipGetErrorString(e));
-  best.graph_chunk = keep.graph_chunk;
-  best.fuse_rows = keep.fuse_rows;
-  c->launch = best;
-  rc = rebuild_tiles(c);
-  if (rc) return rc;
-  if (chosen) *chosen = best;
-  return LBM_OK;
+  c->launch = keep;
+  if (rc) {
+    rebuild_tiles(c);
+    return rc;
+  }
+  if (e != hipSuccess) {
+    rebuild_tiles(c);
+    return fail(LBM_E_DEVICE, hipGetErrorString(e));
+  }
+  {
+    std::lock_guard<std::mutex> lock(tc.mu);
+    tune_cache_load(tc);
+    tune_cache_store(tc, key, best);
+  }
+  return apply_tuned(c, best, chosen);
 }
 
 

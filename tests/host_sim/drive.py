@@ -93,9 +93,11 @@ def run(probs, T, seg, dtype, launch=None, chunks=None):
 sim.sim_pairs_checked.restype = C.c_int64
 
 
-def run_forward(probs, T, launch, steps=(5, 1, 8)):
+def run_forward(probs, T, launch, steps=(5, 1, 8), tune=None):
     """Forward steps only, with the given launch (two-step path when
-    fuse_rows > 0): odd and even step counts, graphs, timed steps."""
+    fuse_rows > 0): odd and even step counts, graphs, timed steps. With tune,
+    lbm_autotune first runs every candidate shape for that many steps, and a
+    second call with steps = 0 must return the cached choice."""
     code, npdt = (L.LBM_F32, np.float32)
     grids = [(p.nx, p.ny) for p in probs]
     fields = [np.concatenate([p.medium.full(p.ny, p.nx)[k].ravel() for p in probs]).astype(npdt)
@@ -116,6 +118,10 @@ def run_forward(probs, T, launch, steps=(5, 1, 8)):
     lc = L.lbm_get_launch(ctx)
     lc.update(launch)
     L.lbm_set_launch(ctx, **lc)
+    if tune is not None:
+        chosen = L.lbm_autotune(ctx, tune)
+        assert L.lbm_autotune(ctx, 0) == chosen == L.lbm_get_launch(ctx), chosen
+        assert (chosen["fuse_rows"] > 0) == (lc["fuse_rows"] > 0), (chosen, lc)
     before = sim.sim_pairs_checked()
     for n in steps:
         L.lbm_step(ctx, n)
@@ -162,4 +168,17 @@ for name, bc, rr, nx, ny in FUSED:
 pairs, kt = run_forward([problem(FUSED[1][1], 40, 530, 90, 6), problem(FUSED[0][1], -1, 300, 64, 7),
                          problem(FUSED[2][1], -1, 1100, 50, 8)], 0, dict(waves=2, rows=4, fuse_rows=6))
 assert pairs > 0, pairs
+# autotuning: every candidate shape of either path runs through the checks
+# above, and each result lands in the cache file LBM_TUNE_CACHE names
+cache = os.path.join(os.path.dirname(sys.argv[1]), "tune_cache.txt")
+os.environ["LBM_TUNE_CACHE"] = cache
+tp = problem(FUSED[1][1], 61, 530, 150, 9, sources=[Source(300.0, 75.0, 2.0, 0.3, 0.9, 1.0, 12.0, 16.0)],
+             receivers=[(x, 0) for x in range(0, 530, 5)])
+for fr in (6, 0):
+    pairs, kt = run_forward([tp], 0, dict(waves=4, rows=8, fuse_rows=fr), tune=3)
+    assert (pairs > 0) == (fr > 0), (fr, pairs)
+lines = open(cache).read().splitlines()
+assert len(lines) == 2 and lines[0].startswith("sim f32 ") and " pairs|" in lines[0], lines
+assert " single|" in lines[1], lines
+print("ok autotune", flush=True)
 print("ALL OK", flush=True)

@@ -58,6 +58,12 @@ hipError_t hipGraphInstantiate(hipGraphExec_t *e, hipGraph_t, hipGraphNode_t *, 
 hipError_t hipGraphDestroy(hipGraph_t g) { free(g); return hipSuccess; }
 hipError_t hipGraphExecDestroy(hipGraphExec_t e) { free(e); return hipSuccess; }
 hipError_t hipGraphLaunch(hipGraphExec_t, hipStream_t) { return hipSuccess; }
+hipError_t hipGetDevice(int *d) { *d = 0; return hipSuccess; }
+hipError_t hipGetDeviceProperties(hipDeviceProp_t *p, int) {
+  memset(p, 0, sizeof *p);
+  strcpy(p->gcnArchName, "sim:feature");
+  return hipSuccess;
+}
 
 namespace lbm {
 template <typename real>
