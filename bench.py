@@ -76,15 +76,26 @@ def measured_traffic(path: str, cells=None):
         return None
 
 
+def _sample_steps(run, target_s: float, cap: int) -> int:
+    """Steps for a sample of about target_s seconds: a run of 1 step and one
+    of 3 separate the per-step time from the fixed setup time."""
+    t = time.perf_counter()
+    run(1)
+    t1 = time.perf_counter() - t
+    t = time.perf_counter()
+    run(3)
+    t3 = time.perf_counter() - t
+    per = max((t3 - t1) / 2, 1e-3)
+    setup = max(t1 - per, 0.0)
+    return max(1, min(cap, int((target_s - setup) / per)))
+
+
 def cpu_baseline(problem, target_s: float = 15.0):
     """The FP64 oracle as it stands, on this host's cores, on the first steps
     of the same workload; steps chosen so the sample takes ~target_s."""
     from oracle import stepper
     cells = problem.nx * problem.ny
-    t = time.perf_counter()
-    stepper.run(problem, nsteps=1, want_trace=False)
-    one = max(time.perf_counter() - t, 1e-3)
-    n = max(1, min(200, int(target_s / one)))
+    n = _sample_steps(lambda k: stepper.run(problem, nsteps=k, want_trace=False), target_s, 400)
     t = time.perf_counter()
     stepper.run(problem, nsteps=n, want_trace=False)
     el = time.perf_counter() - t
@@ -94,10 +105,12 @@ def cpu_baseline(problem, target_s: float = 15.0):
                       f"state, FP64, OpenMP over rows ({el:.1f} s incl. setup)"}
 
 
-def cpu_baseline3(problem, steps: int = 2):
+def cpu_baseline3(problem, target_s: float = 10.0):
     """The FP64 three-dimensional oracle as it stands, on this host's cores,
-    on the first steps of the same volume from the rest state."""
+    on the first steps of the same volume from the rest state; steps chosen
+    so the sample takes ~target_s."""
     from oracle import stepper, stepper3d
+    steps = _sample_steps(lambda k: stepper3d.run(problem, nsteps=k, want_trace=False), target_s, 40)
     t = time.perf_counter()
     stepper3d.run(problem, nsteps=steps, want_trace=False)
     el = time.perf_counter() - t
