@@ -99,10 +99,21 @@ def cpu_baseline(problem, target_s: float = 15.0):
     t = time.perf_counter()
     stepper.run(problem, nsteps=n, want_trace=False)
     el = time.perf_counter() - t
-    return {"value": cells * n / el / 1e9, "unit": "GLUPS", "cores": stepper.num_threads(),
+    cores = stepper.num_threads()
+    # the same oracle on one thread, over 2 steps (setup included)
+    stepper.set_num_threads(1)
+    try:
+        t = time.perf_counter()
+        stepper.run(problem, nsteps=2, want_trace=False)
+        el1 = time.perf_counter() - t
+    finally:
+        stepper.set_num_threads(cores)
+    return {"value": cells * n / el / 1e9, "unit": "GLUPS", "cores": cores,
             "kind": "oracle",
             "sample": f"{n} steps of the full {problem.nx}x{problem.ny} grid from the rest "
-                      f"state, FP64, OpenMP over rows ({el:.1f} s incl. setup)"}
+                      f"state, FP64, OpenMP over rows ({el:.1f} s incl. setup)",
+            "one_thread": {"value": cells * 2 / el1 / 1e9, "unit": "GLUPS",
+                           "sample": f"2 steps of the same grid on 1 thread ({el1:.1f} s incl. setup)"}}
 
 
 def cpu_baseline3(problem, target_s: float = 10.0):

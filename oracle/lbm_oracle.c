@@ -87,6 +87,15 @@ int oracle_num_threads(void) {
 #endif
 }
 
+/* Threads of the following parallel regions (both oracles); n < 1 is ignored. */
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 void oracle_lattice(int32_t *cx, int32_t *cy, double *w, int32_t *opp) {
   for (int i = 0; i < 9; ++i) {
     cx[i] = CX[i];

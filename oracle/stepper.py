@@ -56,6 +56,8 @@ def lib():
         L.oracle_lattice.restype = None
         L.oracle_lattice.argtypes = [_ip, _ip, _dp, _ip]
         L.oracle_num_threads.restype = C.c_int
+        L.oracle_set_num_threads.restype = None
+        L.oracle_set_num_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -95,6 +97,11 @@ def collide_cell(f, G, A: float, tau: float):
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP regions from here on."""
+    lib().oracle_set_num_threads(int(n))
 
 
 def _cfg(p):
