@@ -116,6 +116,50 @@ def cpu_baseline(problem, target_s: float = 15.0):
                            "sample": f"2 steps of the same grid on 1 thread ({el1:.1f} s incl. setup)"}}
 
 
+# hipDeviceAttribute_t values of the HIP runtime's enum (ROCm 7 headers)
+_HIP_ATTR = {"clock_khz": 5, "mem_bus_bits": 59, "mem_clock_khz": 60, "compute_units": 63}
+
+
+def device_report(torch) -> dict:
+    """What the device reports (hipDeviceGetAttribute) and a measured plain
+    copy of one population buffer's size (9 x 4096^2 FP32): the published
+    peaks the roofline uses are checked against both."""
+    import ctypes as C
+    out = {"name": torch.cuda.get_device_name(0)}
+    try:
+        hip = C.CDLL("libamdhip64.so")
+        for k, a in _HIP_ATTR.items():
+            v = C.c_int(0)
+            if hip.hipDeviceGetAttribute(C.byref(v), a, 0) == 0:
+                out[k] = v.value
+        if "mem_clock_khz" in out and "mem_bus_bits" in out:
+            # HBM3E moves four bits per pin and reported memory clock (2 GHz
+            # reported, 8 Gb/s per pin)
+            out["hbm_peak_from_attributes_GBps"] = round(
+                4 * out["mem_clock_khz"] * 1e3 * out["mem_bus_bits"] / 8 / 1e9, 1)
+            out["hbm_peak_note"] = "4 transfers per reported memory clock x bus width"
+    except OSError:
+        pass
+    src = torch.ones(9 * 4096 * 4096, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    out["copy_GBps"] = round(2 * src.numel() * 4 / (ms / 1e3) / 1e9, 1)
+    out["copy_note"] = "torch copy of 604 MB, read + write bytes per second"
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline3(problem, target_s: float = 10.0):
     """The FP64 three-dimensional oracle as it stands, on this host's cores,
     on the first steps of the same volume from the rest state; steps chosen
@@ -463,6 +507,7 @@ def main():
             extras[name] = fn()
             torch.cuda.empty_cache()
         out["extras"] = extras
+    out["device"] = device_report(torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)
