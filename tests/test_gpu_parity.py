@@ -349,3 +349,39 @@ def test_init_reports_the_stability_window():
     finally:
         s.close()
     assert not stable and g >= T.max_growth(float(nu_f.max()), 1.0, n=33) - 1e-3
+
+
+def test_batched_full_size_sampled_grids():
+    """The batched configuration at full size (512 grids of side 256..2048,
+    860 M cells, FP32) in the launch the benchmark times, 8 steps (four pairs
+    on the two-step path). The 8 smallest and the 2 largest grids start from
+    random states, the others from rest. The grids are independent, so each
+    sampled grid must match the oracle run on that grid alone: fields and
+    state. Every grid's state stays finite."""
+    import torch
+    import bench
+    from paper_2009_06404_amd import Solver
+    probs = w.batched_shots()
+    order = np.argsort([p.nx for p in probs], kind="stable")
+    pick = [int(g) for g in list(order[:8]) + list(order[-2:])]
+    starts = {}
+    s = Solver(probs, dtype="f32", trace_steps=1, launch=dict(bench.BATCHED_LAUNCH))
+    try:
+        assert s.launch()["fuse_rows"] > 0
+        for g in pick:
+            p = probs[g]
+            rng = np.random.default_rng(100 + g)
+            f0 = rng.standard_normal(size=(9, p.ny, p.nx), dtype=np.float32)
+            starts[g] = f0.astype(np.float64) * 1e-3
+            s.set_state(g, torch.as_tensor(starts[g], dtype=torch.float32), 0)
+        s.step(8)
+        got = {g: {"mom": s.moments(g).double().cpu().numpy(),
+                   "fstar": s.state(g).double().cpu().numpy(), "trace": None} for g in pick}
+        assert s.check_finite()
+    finally:
+        s.close()
+    worst = 0.0
+    for g in pick:
+        ref = stepper.run(probs[g], nsteps=8, fstar_init=starts[g], want_trace=False)
+        worst = max(worst, compare(got[g], ref, TOL["f32"], f"batched grid {g} ({probs[g].nx}^2)"))
+    _print("batched_shots full size, 10 sampled grids, 8 steps", worst)
