@@ -264,3 +264,43 @@ def test_autograd_shot_traces():
     assert rel_l2(lam.grad.cpu().numpy(), ref_gl) <= 1e-11
     assert rel_l2(mu.grad.cpu().numpy(), ref_gm) <= 1e-11
     assert rel_l2(amp.grad.cpu().numpy(), np.array(ref_ga)) <= 1e-11
+
+
+def test_full_size_adjoint_one_shot_against_the_oracle():
+    """The adjoint workload on its full grid (16 shots of 1024^2, FP32,
+    cell-wise moduli, checkpoints every 100 steps) in the launch the benchmark
+    times, over 200 steps. Shot 0 takes its residual against the observed
+    data of the homogeneous background (computed by the oracle) and is
+    compared with the FP64 oracle adjoint: dL/dkappa, dL/damp and the adjoint
+    state at t = 0. The other 15 shots take zero observed data and must give
+    finite gradients."""
+    import torch
+    import bench
+    from paper_2009_06404_amd import Solver
+    n, shots, T = 1024, 16, 200
+    probs = [p.replace(nsteps=T) for p in w.adjoint_shots(n=n, shots=shots, nsteps=T)]
+    bg0 = w.adjoint_shots(n=n, shots=shots, nsteps=T, homogeneous=True)[0]
+    d0 = stepper.run(bg0, nsteps=T)["trace"]
+    _, e0 = stepper.misfit(stepper.run(probs[0], nsteps=T)["trace"], d0)
+    ref = stepper.adjoint(probs[0], nsteps=T, residual=e0)
+    print("[adjoint] oracle done for shot 0 at 1024^2", flush=True)
+    s = Solver(probs, dtype="f32", trace_steps=T, launch=dict(bench.ADJOINT_LAUNCH))
+    try:
+        assert s.launch()["fuse_rows"] > 0
+        s.adjoint_begin(T, 100)
+        s.step(T)
+        gk = torch.zeros((shots, n, n), dtype=torch.float64, device=s.device)
+        ga = torch.zeros((shots, 1), dtype=torch.float64, device=s.device)
+        keep = []
+        for g in range(shots):
+            d = torch.as_tensor(d0) if g == 0 else torch.zeros_like(s.traces[g])
+            _, res = s.misfit(g, d)
+            keep.append(res)
+            s.adjoint_set_io(g, res, gk[g], ga[g])
+        s.adjoint_step(T)
+        got = {"adj": s.adjoint_state(0).double().cpu().numpy(), "grad_kappa": gk[0].cpu().numpy(),
+               "grad_amp": ga[0].cpu().numpy()}
+        assert bool(torch.isfinite(gk).all()) and bool(torch.isfinite(ga).all())
+    finally:
+        s.close()
+    _compare(got, ref, TOL["f32"], "full-size shot 0 (1024^2, 200 steps, 16 shots batched)")
