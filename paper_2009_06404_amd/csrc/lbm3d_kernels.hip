@@ -351,8 +351,15 @@ step3_kernel(const real *__restrict__ fin, real *__restrict__ fout, real *__rest
           const real *sc = reinterpret_cast<const real *>(v.rec_scale);
           real *tr = reinterpret_cast<real *>(v.trace);
           const int nc = __builtin_popcount(v.comp_mask);
-          for (int r = rb; r < re; ++r) {
-            if (v.rec_x[r] != x) continue;
+          // the row's receivers are sorted by x: binary search for the first
+          // at or after this column, then take every one at it
+          int lo = rb, hi = re;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (v.rec_x[mid] < x) lo = mid + 1;
+            else hi = mid;
+          }
+          for (int r = lo; r < re && v.rec_x[r] == x; ++r) {
             real *o = tr + (row * v.nrec + v.rec_id[r]) * nc;
             int k = 0;
             if (v.comp_mask & 1) o[k++] = jx * sc[r];
