@@ -124,6 +124,12 @@ namespace {
 
 bool f64(const lbm3_ctx *c) { return c->dtype == LBM_F64; }
 
+// Rows per tile of the general kernel (the general lists and the field
+// launch): the launch's rows, except that 14-row tiles are cut into 2-row
+// ones. The general kernel with 14 rows per tile needs more than the 128
+// VGPRs its 1024-lane workgroup allows and spills to scratch.
+int general_rows(const lbm3_ctx *c) { return c->rows_y == 14 ? 2 : c->rows_y; }
+
 // General tiles are cut into z chunks of at most this many planes: more,
 // shorter workgroups, which hide beside the lean launch better than a few
 // that march a whole segment (256^3 half-space, FP32: D3Q19 0.625 against
@@ -205,10 +211,12 @@ int build_tiles(lbm3_ctx *c) {
         }
         const Tile3Dev t{x0, y0, z0, z1};
         const int64_t cells = (int64_t)w * h * (z1 - z0);
-        all.push_back(t);
+        const int gr = general_rows(c);
+        for (int ys = y0; ys < y0 + h; ys += gr) all.push_back(Tile3Dev{x0, ys, z0, z1});
         if (general) {
-          for (int zs = z0; zs < z1; zs += kGeneralPlanes)
-            gen.push_back(Tile3Dev{x0, y0, zs, std::min(zs + kGeneralPlanes, z1)});
+          for (int ys = y0; ys < y0 + h; ys += gr)
+            for (int zs = z0; zs < z1; zs += kGeneralPlanes)
+              gen.push_back(Tile3Dev{x0, ys, zs, std::min(zs + kGeneralPlanes, z1)});
           gen_cells += cells;
         } else {
           lean.push_back(t);
@@ -232,8 +240,8 @@ int launch_list(lbm3_ctx *c, bool general, const Tile3Dev *tiles, int n, const v
                 void *fout, void *out10, int mode) {
   if (n <= 0) return LBM_OK;
   c->v.omega = 1.0 / c->tau;
-  const int rc = launch_step3(f64(c), general, c->rows_y, tiles, n, fin, fout, out10, c->v, c->t,
-                              mode, c->stream);
+  const int rc = launch_step3(f64(c), general, general ? general_rows(c) : c->rows_y, tiles, n, fin,
+                              fout, out10, c->v, c->t, mode, c->stream);
   if (rc != 0) return fail3(LBM_E_DEVICE, std::string("step launch: ") + hipGetErrorString((hipError_t)rc));
   return LBM_OK;
 }

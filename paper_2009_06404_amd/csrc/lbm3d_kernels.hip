@@ -481,42 +481,49 @@ __global__ void pack3_kernel(const real *__restrict__ src, real *__restrict__ ds
 }
 
 template <typename real, int Q, int TY>
-void launch_tile(bool general, const Tile3Dev *tiles, int ntiles, const void *fin, void *fout,
+hipError_t launch_tile(bool general, const Tile3Dev *tiles, int ntiles, const void *fin, void *fout,
                  void *out10, const Vol3Dev &v, int64_t t, int mode, hipStream_t s) {
-  if (ntiles <= 0) return;
+  if (ntiles <= 0) return hipSuccess;
+  // general tiles of 14 rows are never built (the host cuts them to 2 rows):
+  // that kernel would spill
+  if constexpr (TY == 14) {
+    if (general || mode == 1) return hipErrorInvalidValue;
+  }
   const dim3 grid((ntiles + 7) / 8 * 8), block(64 * (TY + 2));
   const real *in = reinterpret_cast<const real *>(fin);
   real *out = reinterpret_cast<real *>(fout);
   real *o10 = reinterpret_cast<real *>(out10);
-  if (mode == 1)
-    hipLaunchKernelGGL((step3_kernel<real, Q, TY, 1, true>), grid, block, 0, s, in, out, o10, v, t,
-                       tiles, ntiles);
-  else if (general)
-    hipLaunchKernelGGL((step3_kernel<real, Q, TY, 0, true>), grid, block, 0, s, in, out, o10, v, t,
-                       tiles, ntiles);
-  else
-    hipLaunchKernelGGL((step3_kernel<real, Q, TY, 0, false>), grid, block, 0, s, in, out, o10, v, t,
-                       tiles, ntiles);
+  if constexpr (TY != 14) {
+    if (mode == 1) {
+      hipLaunchKernelGGL((step3_kernel<real, Q, TY, 1, true>), grid, block, 0, s, in, out, o10, v, t,
+                         tiles, ntiles);
+      return hipSuccess;
+    }
+    if (general) {
+      hipLaunchKernelGGL((step3_kernel<real, Q, TY, 0, true>), grid, block, 0, s, in, out, o10, v, t,
+                         tiles, ntiles);
+      return hipSuccess;
+    }
+  }
+  hipLaunchKernelGGL((step3_kernel<real, Q, TY, 0, false>), grid, block, 0, s, in, out, o10, v, t,
+                     tiles, ntiles);
+  return hipSuccess;
 }
 
 template <typename real, int Q>
-void launch_rows(bool general, int rows_y, const Tile3Dev *tiles, int ntiles, const void *fin,
-                 void *fout, void *out10, const Vol3Dev &v, int64_t t, int mode, hipStream_t s) {
-  if (rows_y == 2)
-    launch_tile<real, Q, 2>(general, tiles, ntiles, fin, fout, out10, v, t, mode, s);
-  else if (rows_y == 14)
-    launch_tile<real, Q, 14>(general, tiles, ntiles, fin, fout, out10, v, t, mode, s);
-  else
-    launch_tile<real, Q, 6>(general, tiles, ntiles, fin, fout, out10, v, t, mode, s);
+hipError_t launch_rows(bool general, int rows_y, const Tile3Dev *tiles, int ntiles, const void *fin,
+                       void *fout, void *out10, const Vol3Dev &v, int64_t t, int mode, hipStream_t s) {
+  if (rows_y == 2) return launch_tile<real, Q, 2>(general, tiles, ntiles, fin, fout, out10, v, t, mode, s);
+  if (rows_y == 14) return launch_tile<real, Q, 14>(general, tiles, ntiles, fin, fout, out10, v, t, mode, s);
+  return launch_tile<real, Q, 6>(general, tiles, ntiles, fin, fout, out10, v, t, mode, s);
 }
 
 template <typename real>
-void launch_lattice(bool general, int rows_y, const Tile3Dev *tiles, int ntiles, const void *fin,
-                    void *fout, void *out10, const Vol3Dev &v, int64_t t, int mode, hipStream_t s) {
+hipError_t launch_lattice(bool general, int rows_y, const Tile3Dev *tiles, int ntiles, const void *fin,
+                          void *fout, void *out10, const Vol3Dev &v, int64_t t, int mode, hipStream_t s) {
   if (v.q == kQ27)
-    launch_rows<real, kQ27>(general, rows_y, tiles, ntiles, fin, fout, out10, v, t, mode, s);
-  else
-    launch_rows<real, kQ19>(general, rows_y, tiles, ntiles, fin, fout, out10, v, t, mode, s);
+    return launch_rows<real, kQ27>(general, rows_y, tiles, ntiles, fin, fout, out10, v, t, mode, s);
+  return launch_rows<real, kQ19>(general, rows_y, tiles, ntiles, fin, fout, out10, v, t, mode, s);
 }
 
 }  // namespace
@@ -524,10 +531,9 @@ void launch_lattice(bool general, int rows_y, const Tile3Dev *tiles, int ntiles,
 int launch_step3(bool f64, bool general, int rows_y, const Tile3Dev *tiles, int ntiles,
                  const void *fin, void *fout, void *out10, const Vol3Dev &v, int64_t t, int mode,
                  hipStream_t s) {
-  if (f64)
-    launch_lattice<double>(general, rows_y, tiles, ntiles, fin, fout, out10, v, t, mode, s);
-  else
-    launch_lattice<float>(general, rows_y, tiles, ntiles, fin, fout, out10, v, t, mode, s);
+  const hipError_t e = f64 ? launch_lattice<double>(general, rows_y, tiles, ntiles, fin, fout, out10, v, t, mode, s)
+                          : launch_lattice<float>(general, rows_y, tiles, ntiles, fin, fout, out10, v, t, mode, s);
+  if (e != hipSuccess) return (int)e;
   return (int)hipGetLastError();
 }
 

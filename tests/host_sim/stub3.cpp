@@ -66,6 +66,7 @@ int launch_step3(bool f64, bool general, int rows_y, const Tile3Dev *tiles, int 
                  hipStream_t) {
   if (ntiles <= 0) return 0;
   if (rows_y != 2 && rows_y != 6 && rows_y != 14) fail("rows_y");
+  if (rows_y == 14 && (general || mode == 1)) fail("general or field tiles of 14 rows");
   if (v.q != kQ19 && v.q != kQ27) fail("lattice");
   const size_t es = f64 ? 8 : 4;
   const int nx = v.nx, ny = v.ny, nz = v.nz;
