@@ -57,7 +57,7 @@ int make_layout3(int32_t nx, int32_t ny, int32_t nz, int32_t q, int32_t dtype, L
   // the kernels address a plane of populations with 32-bit byte offsets
   // behind a buffer descriptor of 2^31 - 1 bytes
   if (L->zplane * (int64_t)L->esize > (int64_t)INT32_MAX)
-    return fail3(LBM_E_INVALID, "a plane of 19 x ny x nx populations must stay below 2 GiB");
+    return fail3(LBM_E_INVALID, "one z plane of q x ny x pitch populations must stay below 2 GiB");
   L->f_elems = L->zplane * nz;
   L->k_elems = (int64_t)L->pitch * ny * nz;
   return LBM_OK;

@@ -80,6 +80,13 @@ def test_workspace3_size_and_null_context():
             L3.lbm3_workspace_bytes(*bad, L.LBM_F32)
     with pytest.raises(L.LBMError):
         L3.lbm3_workspace_bytes(2048, 2048, 1024, 19, L.LBM_F32)   # > 2^31 cells
+    # one z plane of populations must stay below 2 GiB (32-bit byte offsets):
+    # 19 x 1024 x 27584 x 4 B fits, one more row of 64-column pitch does not
+    assert L3.lbm3_workspace_bytes(27584, 1024, 4, 19, L.LBM_F32) > 0
+    with pytest.raises(L.LBMError, match="2 GiB"):
+        L3.lbm3_workspace_bytes(27648, 1024, 4, 19, L.LBM_F32)
+    with pytest.raises(L.LBMError, match="2 GiB"):
+        L3.lbm3_workspace_bytes(16384, 1024, 4, 27, L.LBM_F64)
     lib = L3.lib()
     assert lib.lbm3_step(None, 1) == L.LBM_E_INVALID
     assert lib.lbm3_moments(None, None) == L.LBM_E_INVALID
