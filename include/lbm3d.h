@@ -151,6 +151,8 @@ int lbm3_set_state(lbm3_ctx *ctx, const void *src, int64_t t);
 /* Workgroup tile: 64 columns by rows_y (2, 6 or 14) rows, marching planes_z
  * planes (>= 1) in z. Defaults: rows_y 6 and planes_z 16 (fewer when a plane
  * has too few tiles for 2048 workgroups); planes_z = 0 selects the default.
+ * The tiles near faces, sources and receivers run in chunks of at most 4
+ * planes, and of 2 rows when rows_y is 14. No tile shape changes the results.
  * Returns LBM_OK or LBM_E_INVALID. Host only. */
 int lbm3_set_tile(lbm3_ctx *ctx, int32_t rows_y, int32_t planes_z);
 int lbm3_get_tile(const lbm3_ctx *ctx, int32_t *rows_y, int32_t *planes_z);
