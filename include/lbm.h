@@ -137,7 +137,10 @@ typedef struct {
  * sizes and dtype: three population buffers of 9 x pitch x ny elements per
  * grid (the state, the next state and the intermediate state of the two-step
  * path; pitch = nx rounded up to 64) and one x pitch x ny plane of cell
- * moduli. Synchronous, host only. Returns LBM_OK or LBM_E_INVALID. */
+ * moduli. Synchronous, host only. Returns LBM_OK or LBM_E_INVALID (a side
+ * below 3, or a grid too wide for the kernels' 32-bit row addressing: 8 rows
+ * of nine population runs, 8 x 9 x pitch x 4 (FP32) or x 8 (FP64) bytes, must
+ * stay below 2^31 bytes; lbm_init refuses such grids as well). */
 int lbm_workspace_bytes(const lbm_grid *grids, int32_t nbatch, int32_t dtype,
                         size_t *bytes);
 
@@ -257,7 +260,12 @@ int lbm_check_finite(lbm_ctx *ctx);
 /* Launch configuration in use, and a way to set it (waves in {1,2,4,8},
  * rows >= 1, graph_chunk >= 0, prefetch in {1,2} (0 means 1), split, pair and
  * overlap in {0,1}, fuse_rows 0 or in [4, 248]). An odd graph_chunk is
- * rounded up to keep the ping-pong parity.
+ * rounded up to keep the ping-pong parity. The kernels reach a tile's rows
+ * through one buffer descriptor with 32-bit byte offsets, so for every grid
+ * (max(rows, 2) + 6) rows of nine population runs (9 x pitch x element size
+ * bytes each) must stay within 2^31 - 1 bytes and, when fuse_rows > 0,
+ * (fuse_rows + 8) rows within 2^32 - 1 bytes; the default launch and the
+ * autotuner keep to this on their own.
  * Returns LBM_OK or LBM_E_INVALID (the configuration in use is kept). */
 int lbm_get_launch(const lbm_ctx *ctx, lbm_launch *out);
 int lbm_set_launch(lbm_ctx *ctx, const lbm_launch *cfg);

@@ -210,7 +210,50 @@ void drop_graphs(lbm_ctx *c) {
   c->gchunk = 0;
 }
 
-int validate_grid(const lbm_grid &g, const lbm_bc &b, const lbm_sponge *sp, int idx) {
+// The step kernels reach a tile's rows through one buffer descriptor based
+// two rows above the tile, with 32-bit byte offsets: row k of nine population
+// runs from the base lies k * 9 * pitch * esize bytes in. The single-step
+// kernels (descriptor range 2^31 - 1 bytes) reach at most kSingleReach rows
+// beyond a tile's own (two above, the row pulled below and the prefetched
+// rows); the two-step kernel (range up to 2^32 - 1) reaches kFusedReach rows
+// beyond its block (four above, four below). A launch whose tiles could reach
+// further would read zeros and drop stores, so it is refused. The tile height
+// is taken as asked (not clipped to the grid), which errs on the safe side.
+constexpr int64_t kSingleReach = 6;
+constexpr int64_t kFusedReach = 8;
+constexpr int kMinTileRows = 2;   // the general kernel's sub-tiles
+
+int64_t row_bytes(int32_t nx, int dtype) {
+  return 9 * round_up(nx, kPitchAlign) * (dtype == LBM_F64 ? 8 : 4);
+}
+
+// Empty when every grid's tiles of `rows` rows (single steps) and blocks of
+// `fuse_rows` rows (two-step path, 0 = off) stay inside the descriptors'
+// ranges; else the reason.
+std::string reach_error(const std::vector<lbm_grid> &grids, int dtype, int rows, int fuse_rows) {
+  for (size_t g = 0; g < grids.size(); ++g) {
+    const int64_t rb = row_bytes(grids[g].nx, dtype);
+    char buf[256];
+    if ((std::max(rows, kMinTileRows) + kSingleReach) * rb > (int64_t)INT32_MAX) {
+      snprintf(buf, sizeof buf,
+               "grid %zu: %d-row tiles would address %lld bytes of populations from one "
+               "descriptor (limit 2^31 - 1): use fewer rows",
+               g, std::max(rows, kMinTileRows),
+               (long long)((std::max(rows, kMinTileRows) + kSingleReach) * rb));
+      return buf;
+    }
+    if (fuse_rows > 0 && (fuse_rows + kFusedReach) * rb > (int64_t)UINT32_MAX) {
+      snprintf(buf, sizeof buf,
+               "grid %zu: %d-row two-step blocks would address %lld bytes of populations "
+               "from one descriptor (limit 2^32 - 1): use fewer fuse_rows",
+               g, fuse_rows, (long long)((fuse_rows + kFusedReach) * rb));
+      return buf;
+    }
+  }
+  return std::string();
+}
+
+int validate_grid(const lbm_grid &g, const lbm_bc &b, const lbm_sponge *sp, int idx, int dtype) {
   char buf[256];
   if (g.nx < 3 || g.ny < 3) {
     snprintf(buf, sizeof buf, "grid %d: nx and ny must be >= 3 (got %d x %d)", idx, g.nx, g.ny);
@@ -218,6 +261,13 @@ int validate_grid(const lbm_grid &g, const lbm_bc &b, const lbm_sponge *sp, int 
   }
   if ((int64_t)g.nx * g.ny > (int64_t)1 << 31) {
     snprintf(buf, sizeof buf, "grid %d: more than 2^31 cells", idx);
+    return fail(LBM_E_INVALID, buf);
+  }
+  if (!reach_error({g}, dtype, kMinTileRows, 0).empty()) {
+    snprintf(buf, sizeof buf,
+             "grid %d: too wide: %d rows of nine population runs of %d columns must stay "
+             "below 2 GiB",
+             idx, (int)(kMinTileRows + kSingleReach), g.nx);
     return fail(LBM_E_INVALID, buf);
   }
   for (int e = 0; e < 4; ++e)
@@ -389,6 +439,13 @@ lbm_launch default_launch(const lbm_ctx *c) {
     l.waves = 1;
     l.rows = 4;
   }
+  // very wide grids: shorter tiles and blocks so that no tile reaches past
+  // its descriptor (the grids passed validation, so 2-row tiles fit)
+  while (l.rows > 1 && !reach_error(c->grids, c->dtype, l.rows, 0).empty()) l.rows /= 2;
+  while (l.fuse_rows >= 8 && !reach_error(c->grids, c->dtype, l.rows, l.fuse_rows).empty())
+    l.fuse_rows /= 2;
+  if (l.fuse_rows > 0 && !reach_error(c->grids, c->dtype, l.rows, l.fuse_rows).empty())
+    l.fuse_rows = 0;
   return l;
 }
 
@@ -1348,8 +1405,11 @@ const char *lbm_last_error(void) { return g_err.c_str(); }
 int lbm_workspace_bytes(const lbm_grid *grids, int32_t nbatch, int32_t dtype, size_t *bytes) {
   if (!grids || nbatch <= 0 || !bytes) return fail(LBM_E_INVALID, "grids, nbatch > 0 and bytes required");
   if (dtype != LBM_F32 && dtype != LBM_F64) return fail(LBM_E_INVALID, "dtype must be LBM_F32 or LBM_F64");
-  for (int g = 0; g < nbatch; ++g)
+  for (int g = 0; g < nbatch; ++g) {
     if (grids[g].nx < 3 || grids[g].ny < 3) return fail(LBM_E_INVALID, "nx and ny must be >= 3");
+    if (!reach_error({grids[g]}, dtype, kMinTileRows, 0).empty())
+      return fail(LBM_E_INVALID, "grid too wide: 8 rows of nine population runs must stay below 2 GiB");
+  }
   *bytes = make_layout(grids, nbatch, dtype).bytes();
   return LBM_OK;
 }
@@ -1366,7 +1426,7 @@ int lbm_init(lbm_ctx **out, const lbm_grid *grids, int32_t nbatch, int32_t dtype
   if (!(tau > 0.5) || !std::isfinite(tau)) return fail(LBM_E_INVALID, "tau must be > 1/2");
   if (!bc) return fail(LBM_E_INVALID, "bc array is null");
   for (int g = 0; g < nbatch; ++g) {
-    int rc = validate_grid(grids[g], bc[g], sponge ? &sponge[g] : nullptr, g);
+    int rc = validate_grid(grids[g], bc[g], sponge ? &sponge[g] : nullptr, g, dtype);
     if (rc) return rc;
   }
   Layout L = make_layout(grids, nbatch, dtype);
@@ -1682,6 +1742,10 @@ int lbm_set_launch(lbm_ctx *c, const lbm_launch *cfg) {
   if (cfg->prefetch < 0 || cfg->prefetch > 2) return fail(LBM_E_INVALID, "prefetch must be 1 or 2");
   if (cfg->fuse_rows != 0 && (cfg->fuse_rows < 4 || cfg->fuse_rows > kFusedMaxRows))
     return fail(LBM_E_INVALID, "fuse_rows must be 0 or in [4, 248]");
+  {
+    const std::string why = reach_error(c->grids, c->dtype, cfg->rows, cfg->fuse_rows);
+    if (!why.empty()) return fail(LBM_E_INVALID, why);
+  }
   const bool retile = cfg->waves != c->launch.waves || cfg->rows != c->launch.rows ||
                       cfg->split != c->launch.split || cfg->fuse_rows != c->launch.fuse_rows;
   if (cfg->split < 0 || cfg->split > 1 || cfg->pair < 0 || cfg->pair > 1 || cfg->overlap < 0 ||
@@ -1697,6 +1761,8 @@ int lbm_set_launch(lbm_ctx *c, const lbm_launch *cfg) {
   if (c->gchunk != c->launch.graph_chunk) drop_graphs(c);
   return LBM_OK;
 }
+
+}  // extern "C"
 
 namespace {
 
@@ -1813,6 +1879,8 @@ int apply_tuned(lbm_ctx *c, const lbm_launch &l, lbm_launch *chosen) {
 
 }  // namespace
 
+extern "C" {
+
 int lbm_autotune(lbm_ctx *c, int32_t steps, lbm_launch *chosen) {
   int rc = check_ctx(c);
   if (rc) return rc;
@@ -1833,7 +1901,8 @@ int lbm_autotune(lbm_ctx *c, int32_t steps, lbm_launch *chosen) {
         found = true;
       }
     }
-    if (found) return apply_tuned(c, hit, chosen);
+    if (found && reach_error(c->grids, c->dtype, hit.rows, hit.fuse_rows).empty())
+      return apply_tuned(c, hit, chosen);
     steps = kDefaultTuneSteps;
   }
   const bool pairs = c->launch.fuse_rows > 0;
@@ -1861,7 +1930,7 @@ int lbm_autotune(lbm_ctx *c, int32_t steps, lbm_launch *chosen) {
         lbm_launch cand = keep;
         cand.waves = w;
         cand.fuse_rows = fr;
-        cands.push_back(cand);
+        if (reach_error(c->grids, c->dtype, cand.rows, fr).empty()) cands.push_back(cand);
       }
   } else {
     bool even = true;
@@ -1874,6 +1943,7 @@ int lbm_autotune(lbm_ctx *c, int32_t steps, lbm_launch *chosen) {
             if (pair && w == 1) continue;
             const int64_t tiles = cells / ((int64_t)64 * w * r);
             if (tiles < 512 && !(w == 1 && r == 4)) continue;
+            if (!reach_error(c->grids, c->dtype, r, 0).empty()) continue;
             cands.push_back(cand);
           }
   }

@@ -181,4 +181,47 @@ lines = open(cache).read().splitlines()
 assert len(lines) == 2 and lines[0].startswith("sim f32 ") and " pairs|" in lines[0], lines
 assert " single|" in lines[1], lines
 print("ok autotune", flush=True)
+
+
+def init_only(nx, ny, code, npdt):
+    """A context on one homogeneous nx x ny grid (no steps)."""
+    lam = dev(np.full(nx * ny, 0.03, npdt))
+    mu = dev(np.full(nx * ny, 0.04, npdt))
+    rho = dev(np.ones(nx * ny, npdt))
+    nb = L.lbm_workspace_bytes([(nx, ny)], code)
+    ws = dev(np.zeros(nb + 512, np.uint8))
+    wp = (ws.ctypes.data + 255) // 256 * 256
+    sps = [((0, 0, 0, 0), tuple(np.zeros(0) for _ in range(4)))]
+    return L.lbm_init([(nx, ny)], code, lam.ctypes.data, mu.ctypes.data, rho.ctypes.data, 1.0,
+                      [(BC_FREE0, BC_RIGID, BC_PERIODIC, BC_PERIODIC, -1)], sps, wp, nb, 0)
+
+
+def refused(ctx, **kw):
+    before = L.lbm_get_launch(ctx)
+    lc = dict(before, **kw)
+    try:
+        L.lbm_set_launch(ctx, **lc)
+    except L.LBMError as e:
+        assert "descriptor" in str(e), str(e)
+        assert L.lbm_get_launch(ctx) == before
+        return True
+    return False
+
+
+# descriptor reach: a tile's rows (plus 6) and a two-step block's rows (plus
+# 8) of nine population runs must stay within 2^31 - 1 and 2^32 - 1 bytes
+ctx = init_only(4096, 40, L.LBM_F64, np.float64)          # 294912 B per row
+assert not refused(ctx, rows=7275) and refused(ctx, rows=7276)
+L.lbm_destroy(ctx)
+ctx = init_only(828544, 3, L.LBM_F64, np.float64)         # 59655168 B per row
+assert not refused(ctx, rows=29, fuse_rows=63)
+assert refused(ctx, rows=30) and refused(ctx, rows=8, fuse_rows=64)
+L.lbm_destroy(ctx)
+# the widest FP32 grid: the default launch takes 2-row tiles and 8-row blocks
+ctx = init_only(7456512, 3, L.LBM_F32, np.float32)
+lc = L.lbm_get_launch(ctx)
+assert lc["rows"] == 2 and lc["fuse_rows"] == 8, lc
+assert refused(ctx, rows=3) and refused(ctx, fuse_rows=9)
+L.lbm_destroy(ctx)
+print("ok descriptor reach", flush=True)
 print("ALL OK", flush=True)

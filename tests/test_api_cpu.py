@@ -125,6 +125,17 @@ def test_workspace_size_and_validation():
         L.lbm_workspace_bytes([(10, 10)], 7)
 
 
+def test_workspace_refuses_grids_too_wide_for_the_kernels_descriptors():
+    """The step kernels address 2-row tiles plus 6 rows of nine population
+    runs from one descriptor of 2^31 - 1 bytes: the widest grid has a pitch
+    (nx rounded up to 64) of 3728256 columns in FP64, 7456512 in FP32."""
+    from paper_2009_06404_amd import _lib as L
+    for code, widest in ((L.LBM_F64, 3728256), (L.LBM_F32, 7456512)):
+        assert L.lbm_workspace_bytes([(widest, 3)], code) > 0
+        with pytest.raises(L.LBMError, match="too wide"):
+            L.lbm_workspace_bytes([(widest + 1, 3)], code)
+
+
 def _init(**kw):
     from paper_2009_06404_amd import _lib as L
     grids = kw.get("grids", [(16, 16)])
