@@ -31,13 +31,16 @@ PROFILE_STEP = int(PV["rayleigh_profile_step"])
 END = 2400
 
 
-def problems():
-    """(phase 1 with side layers, phase 2 with periodic sides)."""
+def problems(tau=1.0, free=BC_FREE0):
+    """(phase 1 with side layers, phase 2 with periodic sides). The paper
+    does not print the experiment's tau or which extrapolation its free
+    surface used; the defaults are tau = 1 and the zero-order surface, and
+    (0.55, BC_FREE) is the printed rule at the tau of the bulk-wave tests."""
     prof = w.default_sponge_profile(L)
     med = Medium("homogeneous", 0.04 * T.lame_ratio(NU), 0.04, 1.0)
     rec = np.array([[x, 0] for x in range(NX)], np.int32)
-    p1 = Problem(nx=NX, ny=NY, bc=(BC_FREE0, BC_RIGID, BC_PERIODIC, BC_PERIODIC), medium=med,
-                 tau=1.0, sponge_thick=(0, L, L, L), sponge_profiles=(None, prof, prof, prof),
+    p1 = Problem(nx=NX, ny=NY, bc=(free, BC_RIGID, BC_PERIODIC, BC_PERIODIC), medium=med,
+                 tau=tau, sponge_thick=(0, L, L, L), sponge_profiles=(None, prof, prof, prof),
                  sources=[Source(45.0, 3.0, 2.0, 0.0, 1.0, 1.0, 40.0, 60.0)],
                  receivers=rec, comp_mask=2, name="rayleigh")
     p2 = p1.replace(sponge_thick=(0, L, 0, 0), sponge_profiles=(None, prof, None, None))

@@ -218,12 +218,13 @@ def test_minimal_grid_and_zero_steps():
                 sources=[Source(1.0, 1.0, 1.0, 1.0, 0.0, 1.0, 4.0, 2.0)],
                 receivers=np.array([[1, 1]], np.int32), comp_mask=3, dtype="f64")
     g = run_gpu(p, 9, "f64")
-    compare(g, _oracle(p, 9), TOL["f64"], "3x3")
+    # P_xy is odd in y about the source row and 4e-6 of the largest field here
+    compare(g, _oracle(p, 9), TOL["f64"], "3x3", near_zero=("P_xy",))
     # zero steps: the state is the rest state; the fields at t = 0 already
     # carry the source's half-step contribution to j (j = m + S/2)
     g0 = run_gpu(p, 0, "f64")
     assert np.all(g0["fstar"] == 0)
-    compare(g0, _oracle(p, 0), TOL["f64"], "3x3 t=0")
+    compare(g0, _oracle(p, 0), TOL["f64"], "3x3 t=0", near_zero=("P_xy",))
 
 
 def test_restart_and_graph_are_bitwise():
