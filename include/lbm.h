@@ -127,10 +127,12 @@ typedef struct {
                          steps one at a time through a third buffer, together
                          with the two border rows or columns of the blocks
                          next to them.
-                         Results are bitwise those of single steps. The
-                         two-step path launches directly (graph_chunk is not
-                         used). The default is set by size: the two-step path
-                         on contexts of 2048^2 cells and more. */
+                         Results are bitwise those of single steps. With
+                         graph_chunk > 0 a chunk is graph_chunk / 2 pairs in
+                         one captured graph (three kernels per pair, the fork
+                         and join as graph edges). The default is set by
+                         size: the two-step path with graph_chunk 20 on
+                         contexts of 2048^2 cells and more. */
 } lbm_launch;
 
 /* Bytes of device workspace lbm_init needs for nbatch grids of the given

@@ -5,9 +5,11 @@ The two-step kernel performs the single-step kernels' per-cell operations in
 the same order, so a run on the two-step path must equal the single-step run
 bit for bit: state and traces, for odd and even step counts, with and without
 the general kernel on the second stream, for several block widths and
-heights, boundary mixes, media and a batch of uneven grids (a graph_chunk in
-the launch is ignored on this path, which launches directly). One run per
-case is also compared with the oracle.
+heights, boundary mixes, media and a batch of uneven grids, launched directly
+and as captured HIP graphs (graph_chunk / 2 pairs per graph, replayed several
+times, with chunks of an even and an odd number of pairs and direct steps
+after the last whole chunk). One run per case is also compared with the
+oracle.
 """
 import numpy as np
 import pytest
@@ -61,7 +63,8 @@ FUSED = [
     dict(waves=4, rows=8, fuse_rows=8),
     dict(waves=4, rows=8, fuse_rows=4, overlap=0),
     dict(waves=2, rows=4, fuse_rows=13, graph_chunk=8),
-    dict(waves=8, rows=8, fuse_rows=32, graph_chunk=12, overlap=0),
+    dict(waves=8, rows=8, fuse_rows=32, graph_chunk=14, overlap=0),
+    dict(waves=2, rows=4, fuse_rows=16, graph_chunk=6),
 ]
 
 
@@ -94,7 +97,8 @@ def test_two_step_path_batched_uneven_grids(dtype):
     probs = [_field_periodic(nx=560, ny=120, seed=12, tau=1.0), _rigid_sides(nx=600, ny=96, tau=1.0),
              w.hbm_scale(n=300, nsteps=NSTEPS, sponge=16), w.plain_small(n=96, nsteps=NSTEPS).replace(tau=1.0)]
     ref = run_gpu(probs, NSTEPS, dtype, launch=dict(waves=2, rows=4))
-    for launch in (dict(waves=2, rows=4, fuse_rows=6), dict(waves=4, rows=8, fuse_rows=16, graph_chunk=8)):
+    for launch in (dict(waves=2, rows=4, fuse_rows=6), dict(waves=4, rows=8, fuse_rows=16, graph_chunk=8),
+                   dict(waves=2, rows=8, fuse_rows=32, graph_chunk=10)):
         got = run_gpu(probs, NSTEPS, dtype, launch=launch)
         for g, (a, b) in enumerate(zip(ref, got)):
             assert np.array_equal(a["fstar"], b["fstar"]), (g, launch)
