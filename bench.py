@@ -41,8 +41,10 @@ FUSED_KERNEL = "fused2_kernel"
 INTERIOR_KERNEL = "interior_kernel"
 
 
-def traffic_file(kernel: str, n: int, dtype: str) -> str:
-    return os.path.join(ROOT, "profiles", f"traffic_{kernel}_plain_large_{n}_{dtype}.txt")
+def traffic_file(kernel: str, workload: str, dtype: str) -> str:
+    """profiles/traffic_<kernel>_<workload>_<dtype>.txt, e.g. workload
+    plain_large_4096 or hbm_scale_16384."""
+    return os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}_{dtype}.txt")
 
 
 def kernel_hash() -> str:
@@ -77,8 +79,10 @@ def measured_traffic(path: str, cells=None):
 
 
 def _sample_steps(run, target_s: float, cap: int) -> int:
-    """Steps for a sample of about target_s seconds: a run of 1 step and one
-    of 3 separate the per-step time from the fixed setup time."""
+    """Steps for a sample of about target_s seconds: after one untimed run
+    (first-touch and library loading), a run of 1 step and one of 3 separate
+    the per-step time from the fixed setup time."""
+    run(1)
     t = time.perf_counter()
     run(1)
     t1 = time.perf_counter() - t
@@ -188,6 +192,43 @@ def _timed_steps(s, steps: int, warmup: int, torch) -> float:
     return e0.elapsed_time(e1) / steps
 
 
+def roofline_block(kt: dict, esize: int, workload: str, dtype: str) -> dict:
+    """The HBM roofline of the dominant kernel (the one covering most cells)
+    from its per-launch event timing kt (lbm_step_timed). Algorithmic bytes
+    per launch: each population word of each cell the launch covers read once
+    from its input state and written once to its output state, 18 words per
+    cell (72 B in FP32). The two-step kernel does this once for two steps, so
+    its `frac` is per pass; `per_update` counts the same launch at 18 words
+    per cell update (the survey's per-update figure), which on the two-step
+    path exceeds the HBM peak because half the updates never touch HBM."""
+    if kt["fused_cells"] > 0:
+        kname, kcells, kms, ksteps = FUSED_KERNEL, kt["fused_cells"], kt["fused_ms"], 2
+    elif kt["interior_cells"] > 0:
+        kname, kcells, kms, ksteps = INTERIOR_KERNEL, kt["interior_cells"], kt["interior_ms"], 1
+    else:
+        kname, kcells, kms, ksteps = "step_kernel", kt["general_cells"], kt["general_ms"], 1
+    per_cell = 18 * esize
+    alg_bytes = per_cell * kcells
+    achieved = alg_bytes / (kms / 1e3) / 1e9 if kms > 0 else float("nan")
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "traffic": measured_traffic(traffic_file(kname, workload, dtype), kcells),
+           "kernel": kname, "bytes_per_launch": alg_bytes, "cells_per_launch": kcells,
+           "steps_per_launch": ksteps, "ms_per_launch": round(kms, 5), "timed_steps": kt["steps"],
+           "general_kernel": {"cells_per_launch": kt["general_cells"],
+                              "ms_per_launch": round(kt["general_ms"], 5)}}
+    if ksteps == 2:
+        out["counting"] = ("frac per two-step pass: 18 population words per cell per launch, "
+                           "the launch advancing its cells by two steps")
+        out["per_update"] = {"achieved": round(2 * achieved, 1),
+                             "frac": round(2 * achieved / HBM_PEAK_GBS, 4),
+                             "counting": "18 population words per cell update, two updates per "
+                                         "cell and launch"}
+    else:
+        out["counting"] = "18 population words per cell update, one update per cell and launch"
+    return out
+
+
 def _dominant_gbps(kt: dict, esize: int) -> dict:
     """Algorithmic GB/s of the kernel covering most cells (72 B per cell and
     launch in FP32; the two-step kernel moves them once per two steps)."""
@@ -196,6 +237,31 @@ def _dominant_gbps(kt: dict, esize: int) -> dict:
     else:
         name, cells, ms = INTERIOR_KERNEL, kt["interior_cells"], kt["interior_ms"]
     return {"kernel": name, "GBps": round(18 * esize * cells / ms / 1e6, 1) if ms > 0 else None}
+
+
+def bench_plain_variant(torch, w, Solver, dtype: str, launch_over: dict, label: str,
+                        steps: int = 600, warmup: int = 20) -> dict:
+    """The plain 4096^2 workload in another dtype or launch (the single-step
+    path, FP64): GLUPS over `steps` steps and the roofline of its dominant
+    kernel."""
+    p = w.plain_large(dtype=dtype)
+    s = Solver(p, dtype=dtype, trace_steps=warmup + steps + 64)
+    launch = s.launch()
+    launch.update(launch_over)
+    launch["graph_chunk"] = 0 if launch.get("fuse_rows", 0) else 100
+    s.set_launch(**launch)
+    ms = _timed_steps(s, steps, warmup, torch)
+    kt = s.step_timed(40)
+    ok = s.check_finite()
+    launch = s.launch()
+    s.close()
+    cells = p.nx * p.ny
+    esize = 4 if dtype == "f32" else 8
+    return {"workload": f"plain_large {p.nx}x{p.ny} {dtype.upper()} ({label})",
+            "GLUPS": round(cells / ms / 1e6, 3), "ms_per_step": round(ms, 5), "steps": steps,
+            "warmup": warmup,
+            "roofline": roofline_block(kt, esize, f"plain_large_{p.nx}", dtype),
+            "launch": launch, "state_finite": bool(ok)}
 
 
 def bench_filter(torch, w, Solver, steps_ms: float, passes: int = 20) -> dict:
@@ -262,9 +328,26 @@ def bench_volume(torch, dtype: str = "f32", n: int = 256, steps: int = 400, warm
             **({"cpu_baseline": cpu_baseline3(p)} if cpu else {})}
 
 
-def bench_hbm_scale(torch, w, Solver, steps: int = 200, warmup: int = 20) -> dict:
+def hbm_scale_band(p, rows: int = 2048):
+    """The top `rows` rows of the HBM-scale grid as a grid of their own (free
+    surface, the side sponges, the first layer's medium, the sources in the
+    band), closed by a rigid edge: the oracle's per-cell work is that of the
+    full grid, on 1/8 of its cells."""
+    import numpy as np
+    lam, mu, rho = p.medium.rows(p.ny)
+    from workloads import BC_RIGID, Medium
+    return p.replace(ny=rows, medium=Medium("layered", lam[:rows], mu[:rows], rho[:rows]),
+                     rigid_row=-1, bc=(p.bc[0], BC_RIGID, p.bc[2], p.bc[3]),
+                     sponge_thick=(p.sponge_thick[0], 0, p.sponge_thick[2], p.sponge_thick[3]),
+                     sources=[q for q in p.sources if q.y < rows - 40],
+                     receivers=np.zeros((0, 2), np.int32))
+
+
+def bench_hbm_scale(torch, w, Solver, steps: int = 200, warmup: int = 20,
+                    cpu: bool = False) -> dict:
     """16384^2 FP32, 8 layers, rigid interface, 3 sources (the HBM-scale
-    configuration), timed over a window of its 4000 steps."""
+    configuration), timed over a window of its 4000 steps, with the roofline
+    of its dominant kernel and the oracle timed on a band of the grid."""
     p = w.hbm_scale()
     s = Solver(p, dtype="f32", trace_steps=1)
     ms = _timed_steps(s, steps, warmup, torch)
@@ -273,37 +356,59 @@ def bench_hbm_scale(torch, w, Solver, steps: int = 200, warmup: int = 20) -> dic
     launch = s.launch()
     s.close()
     cells = p.nx * p.ny
-    return {"workload": f"hbm_scale {p.nx}x{p.ny} FP32, 8 layers, rigid interface at row "
-                        f"{p.rigid_row}, 3 sources", "GLUPS": round(cells / ms / 1e6, 3),
-            "ms_per_step": round(ms, 4), "steps": steps, "warmup": warmup,
-            "dominant_kernel_GBps": _dominant_gbps(kt, 4),
-            "launch": launch, "state_finite": bool(ok)}
+    out = {"workload": f"hbm_scale {p.nx}x{p.ny} FP32, 8 layers, rigid interface at row "
+                       f"{p.rigid_row}, 3 sources", "GLUPS": round(cells / ms / 1e6, 3),
+           "ms_per_step": round(ms, 4), "steps": steps, "warmup": warmup,
+           "roofline": roofline_block(kt, 4, f"hbm_scale_{p.nx}", "f32"),
+           "launch": launch, "state_finite": bool(ok)}
+    if cpu:
+        band = hbm_scale_band(p)
+        cb = cpu_baseline(band, target_s=10.0)
+        cb["sample"] = (f"top {band.ny} rows of the {p.nx}x{p.ny} grid as a grid of their own "
+                        f"(free surface, side sponges, first layer, rigid edge below): " + cb["sample"])
+        out["cpu_baseline"] = cb
+    return out
 
 
-BATCHED_LAUNCH = {"waves": 2, "rows": 8, "fuse_rows": 32}
+# pairs of steps on the two-step path, 10 pairs per captured HIP graph
+BATCHED_LAUNCH = {"waves": 2, "rows": 8, "fuse_rows": 32, "graph_chunk": 20}
 # 1024-column grids: narrow, short tiles for the adjoint kernels; the recorded
-# forward and the recompute run on the two-step path (128-column blocks)
-ADJOINT_LAUNCH = {"waves": 2, "rows": 4, "fuse_rows": 32}
+# forward (captured graphs of 10 pairs) and the recompute run on the two-step
+# path (128-column blocks)
+ADJOINT_LAUNCH = {"waves": 2, "rows": 4, "fuse_rows": 32, "graph_chunk": 20}
 
 
 def bench_batched(torch, w, Solver, plain_glups: float, steps: int = 60,
-                  warmup: int = 10, launch=None) -> dict:
+                  warmup: int = 20, launch=None) -> dict:
     """512 grids of uneven side (256..2048) in one context, one launch of each
-    kernel per step (or pair of steps) over the flat tile lists."""
+    kernel per pair of steps over the flat tile lists, the time loop captured
+    in HIP graphs of 10 pairs; the same launched directly beside it."""
     probs = w.batched_shots()
-    t0 = time.perf_counter()
-    s = Solver(probs, dtype="f32", trace_steps=1, launch=dict(launch or BATCHED_LAUNCH))
-    setup = time.perf_counter() - t0
-    ms = _timed_steps(s, steps, warmup, torch)
-    ok = s.check_finite()
-    launch = s.launch()
-    s.close()
     cells = sum(p.nx * p.ny for p in probs)
-    g = cells / ms / 1e6
+    out = {}
+    for name, gc in (("graph", None), ("direct", 0)):
+        lc = dict(launch or BATCHED_LAUNCH)
+        if gc is not None:
+            lc["graph_chunk"] = gc
+        t0 = time.perf_counter()
+        s = Solver(probs, dtype="f32", trace_steps=1, launch=lc)
+        setup = time.perf_counter() - t0
+        ms = _timed_steps(s, steps, warmup, torch)
+        ok = s.check_finite()
+        lc = s.launch()
+        s.close()
+        out[name] = {"GLUPS": round(cells / ms / 1e6, 3), "ms_per_step": round(ms, 4),
+                     "setup_s": round(setup, 1), "launch": lc, "state_finite": bool(ok)}
+        torch.cuda.empty_cache()
+    g = out["graph"]["GLUPS"]
     return {"workload": f"batched_shots: {len(probs)} grids, sides 256..2048, {cells} cells, FP32",
-            "GLUPS": round(g, 3), "ms_per_step": round(ms, 4), "steps": steps,
-            "warmup": warmup, "vs_plain": round(g / plain_glups, 4), "setup_s": round(setup, 1),
-            "launch": launch, "state_finite": bool(ok)}
+            "GLUPS": g, "ms_per_step": out["graph"]["ms_per_step"], "steps": steps,
+            "warmup": warmup, "vs_plain": round(g / plain_glups, 4),
+            "setup_s": out["graph"]["setup_s"], "launch": out["graph"]["launch"],
+            "state_finite": out["graph"]["state_finite"],
+            "direct_launches": {k: out["direct"][k] for k in ("GLUPS", "ms_per_step", "launch",
+                                                             "state_finite")},
+            "graph_vs_direct": round(g / out["direct"]["GLUPS"], 4)}
 
 
 def bench_adjoint(torch, w, Solver, plain_glups: float, nsteps: int = 5000,
@@ -378,8 +483,8 @@ def main():
                     help="steps of the per-kernel event-timing pass after the timed region")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the HBM-scale, batched and adjoint measurements")
-    ap.add_argument("--only", choices=["hbm_scale", "batched", "adjoint", "filter", "volume",
-                                       "volume27"],
+    ap.add_argument("--only", choices=["hbm_scale", "single_step", "plain_f64", "batched",
+                                       "adjoint", "filter", "volume", "volume27"],
                     help="run only this one of the extra measurements and print it")
     ap.add_argument("--adjoint-steps", type=int, default=5000)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -419,7 +524,11 @@ def main():
                           "copy_GBps": round(2 * src.numel() * 4 / (ms / 1e3) / 1e9, 1)}), flush=True)
         return
     if args.only:
-        fn = {"hbm_scale": lambda: bench_hbm_scale(torch, w, Solver),
+        fn = {"hbm_scale": lambda: bench_hbm_scale(torch, w, Solver, cpu=not args.no_cpu_baseline),
+              "single_step": lambda: bench_plain_variant(torch, w, Solver, "f32", {"fuse_rows": 0},
+                                                         "single-step path"),
+              "plain_f64": lambda: bench_plain_variant(torch, w, Solver, "f64", {},
+                                                       "FP64, default launch"),
               "batched": lambda: bench_batched(torch, w, Solver, float("nan")),
               "adjoint": lambda: bench_adjoint(torch, w, Solver, float("nan"),
                                                nsteps=args.adjoint_steps),
@@ -459,20 +568,11 @@ def main():
     esize = 4 if args.dtype == "f32" else 8
     ms_step = ms / args.steps
     glups = cells * args.steps / (ms / 1e3) / 1e9
-    # Algorithmic bytes of a launch: each population word of each cell it
-    # covers read once from the input state and written once to the output
-    # state -- for the two-step kernel, once per launch of two steps.
-    per_cell = 18 * esize
-    if kt["fused_cells"] > 0:
-        kname, kcells, kms, ksteps = FUSED_KERNEL, kt["fused_cells"], kt["fused_ms"], 2
-    elif kt["interior_cells"] > 0:
-        kname, kcells, kms, ksteps = INTERIOR_KERNEL, kt["interior_cells"], kt["interior_ms"], 1
-    else:
-        kname, kcells, kms, ksteps = "step_kernel", kt["general_cells"], kt["general_ms"], 1
-    alg_bytes = per_cell * kcells                  # per launch of the dominant kernel
-    achieved = alg_bytes / (kms / 1e3) / 1e9       # GB/s
-    step_gbs = per_cell * cells / (ms_step / 1e3) / 1e9
-    traffic = measured_traffic(traffic_file(kname, args.n, args.dtype), kcells)
+    rl = roofline_block(kt, esize, f"plain_large_{args.n}", args.dtype)
+    step_gbs = 18 * esize * cells / (ms_step / 1e3) / 1e9
+    rl["whole_step_GBps"] = round(step_gbs, 1)
+    rl["note"] = ("whole_step_GBps: 18 population words per cell and step over the timed "
+                  "steps -- above the HBM peak when two steps share one pass")
     out = {
         "metric": METRIC, "value": round(glups, 3), "unit": "GLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
@@ -483,21 +583,16 @@ def main():
                                f"vertical Ricker source at depth 20, {p.nx} surface receivers",
                    "nx": p.nx, "ny": p.ny, "tau": p.tau, "launch": launch,
                    "state_finite": bool(ok)},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": kname,
-                     "bytes_per_launch": alg_bytes, "cells_per_launch": kcells,
-                     "steps_per_launch": ksteps, "ms_per_launch": round(kms, 5),
-                     "timed_steps": kt["steps"],
-                     "general_kernel": {"cells_per_launch": kt["general_cells"],
-                                        "ms_per_launch": round(kt["general_ms"], 5)},
-                     "whole_step_GBps": round(step_gbs, 1),
-                     "note": "whole_step_GBps: 18 population words per cell and step over "
-                             "the timed steps -- above the HBM peak when two steps share one pass"},
+        "roofline": rl,
     }
     if not args.no_extras and args.n == 4096 and args.dtype == "f32":
         extras = {}
-        for name, fn in (("hbm_scale", lambda: bench_hbm_scale(torch, w, Solver)),
+        for name, fn in (("hbm_scale", lambda: bench_hbm_scale(torch, w, Solver,
+                                                               cpu=not args.no_cpu_baseline)),
+                         ("single_step", lambda: bench_plain_variant(
+                             torch, w, Solver, "f32", {"fuse_rows": 0}, "single-step path")),
+                         ("plain_f64", lambda: bench_plain_variant(
+                             torch, w, Solver, "f64", {}, "FP64, default launch")),
                          ("batched", lambda: bench_batched(torch, w, Solver, glups)),
                          ("adjoint", lambda: bench_adjoint(torch, w, Solver, glups)),
                          ("filter", lambda: bench_filter(torch, w, Solver, ms_step)),
