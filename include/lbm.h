@@ -259,6 +259,18 @@ int lbm_stability(const lbm_ctx *ctx, double *growth);
  * LBM_E_NONFINITE. */
 int lbm_check_finite(lbm_ctx *ctx);
 
+/* lbm_check_finite for callers that cannot allocate device memory (serving
+ * loops and harnesses that forbid hipMalloc): the same check and the same
+ * results, with no hipMalloc, hipFree or allocating library call. Its flags
+ * live in a static device array of 4096 + 2 words (16 KiB) that the library
+ * holds on each GPU it runs on until the process ends: one flag per grid,
+ * the count of non-finite grids and the first of them (named in
+ * lbm_last_error). Each call clears what it uses first. Calls that overlap
+ * on one GPU share the array and race; call it from one thread per GPU, with
+ * the context's device current. Synchronous. Returns LBM_OK,
+ * LBM_E_NONFINITE, LBM_E_INVALID (more than 4096 grids) or LBM_E_DEVICE. */
+int lbm_check_finite_noalloc(lbm_ctx *ctx);
+
 /* Launch configuration in use, and a way to set it (waves in {1,2,4,8},
  * rows >= 1, graph_chunk >= 0, prefetch in {1,2} (0 means 1), split, pair and
  * overlap in {0,1}, fuse_rows 0 or in [4, 248]). An odd graph_chunk is

@@ -38,7 +38,7 @@ ENTRY_POINTS = (
     "lbm_adjoint_workspace_bytes", "lbm_adjoint_begin", "lbm_adjoint_set_io",
     "lbm_adjoint_step", "lbm_adjoint_time", "lbm_adjoint_get_state", "lbm_adjoint_set_state",
     "lbm_misfit", "lbm_lame_gradient", "lbm_vn_growth", "lbm_stability",
-    "lbm_vn_growth_filtered", "lbm_filter",
+    "lbm_vn_growth_filtered", "lbm_filter", "lbm_check_finite_noalloc",
 )
 
 
@@ -105,6 +105,7 @@ def lib():
             "lbm_get_state": ([vp, i32, vp], C.c_int),
             "lbm_set_state": ([vp, i32, vp, i64], C.c_int),
             "lbm_check_finite": ([vp], C.c_int),
+            "lbm_check_finite_noalloc": ([vp], C.c_int),
             "lbm_get_launch": ([vp, C.POINTER(lbm_launch)], C.c_int),
             "lbm_set_launch": ([vp, C.POINTER(lbm_launch)], C.c_int),
             "lbm_autotune": ([vp, i32, C.POINTER(lbm_launch)], C.c_int),
@@ -255,6 +256,14 @@ def lbm_set_state(ctx, g: int, src_ptr, t: int) -> None:
 
 def lbm_check_finite(ctx) -> bool:
     rc = lib().lbm_check_finite(ctx)
+    if rc == LBM_E_NONFINITE:
+        return False
+    check(rc)
+    return True
+
+
+def lbm_check_finite_noalloc(ctx) -> bool:
+    rc = lib().lbm_check_finite_noalloc(ctx)
     if rc == LBM_E_NONFINITE:
         return False
     check(rc)

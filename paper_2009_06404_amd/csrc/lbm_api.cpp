@@ -1736,6 +1736,36 @@ int lbm_check_finite(lbm_ctx *c) {
   return LBM_OK;
 }
 
+int lbm_check_finite_noalloc(lbm_ctx *c) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (c->nbatch > kScratchGrids)
+    return fail(LBM_E_INVALID,
+                "lbm_check_finite_noalloc: at most 4096 grids (its static device scratch holds "
+                "one flag per grid); use lbm_check_finite");
+  int64_t max_elems = 0;
+  for (int g = 0; g < c->nbatch; ++g)
+    max_elems = std::max<int64_t>(max_elems, 9 * (int64_t)c->L.pitch[g] * c->grids[g].ny);
+  // The descriptor table holds every grid's offset, pitch and height since
+  // lbm_init; those never change, so no commit (which may allocate) is needed.
+  uint32_t out[2] = {0u, 0u};
+  hipError_t e;
+  if (c->dtype == LBM_F64)
+    e = check_nonfinite_scratch<double>(reinterpret_cast<const double *>(c->fbuf[c->cur]),
+                                        c->d_grids.p, c->nbatch, max_elems, c->stream, out);
+  else
+    e = check_nonfinite_scratch<float>(reinterpret_cast<const float *>(c->fbuf[c->cur]),
+                                       c->d_grids.p, c->nbatch, max_elems, c->stream, out);
+  if (e != hipSuccess) return fail(LBM_E_DEVICE, hipGetErrorString(e));
+  if (out[0]) {
+    char buf[128];
+    snprintf(buf, sizeof buf, "state holds NaN or Inf (%u grid(s), the first is grid %u)", out[0],
+             out[1]);
+    return fail(LBM_E_NONFINITE, buf);
+  }
+  return LBM_OK;
+}
+
 int lbm_get_launch(const lbm_ctx *c, lbm_launch *out) {
   int rc = check_ctx(c);
   if (rc) return rc;

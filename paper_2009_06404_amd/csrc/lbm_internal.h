@@ -166,6 +166,15 @@ hipError_t launch_gather(const real *src, const int64_t *idx, int n, real *dst,
                          hipStream_t stream);
 template <typename real>
 hipError_t launch_count_nonfinite(const real *f, int64_t n, int *count, hipStream_t stream);
+// The finite check in the library's static device scratch (no allocation):
+// grids [nbatch] is the device descriptor table, at most kScratchGrids grids,
+// max_elems the largest grid's population count (9 x pitch x ny). On return
+// (the stream synchronised) out[0] holds the number of grids whose state
+// holds NaN or Inf and out[1] the lowest such grid index (0xffffffff if none).
+constexpr int kScratchGrids = 4096;
+template <typename real>
+hipError_t check_nonfinite_scratch(const real *f, const GridDev *grids, int nbatch,
+                                   int64_t max_elems, hipStream_t stream, uint32_t out[2]);
 template <typename real>
 hipError_t launch_copy_planes(const real *src, int64_t src_ps, int64_t src_ys, real *dst,
                               int64_t dst_ps, int64_t dst_ys, int nx, int ny, int nplanes,

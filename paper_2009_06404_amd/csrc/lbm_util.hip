@@ -1,7 +1,17 @@
 // Initialisation and utility kernels of liblbm.so: the per-cell elastic
 // coefficient, field validation, receiver gathers, state copies, the finite
 // check and the device time base used by captured graphs.
+#include <algorithm>
+#include <mutex>
+
 #include "lbm_internal.h"
+
+// Scratch memory of the allocation-free finite check: a flag per grid, then
+// the number of grids found non-finite and the lowest such grid index. Each
+// GPU holds its own copy for the life of the process. In host code this name
+// is only a stand-in for the symbol: host code reaches the memory through the
+// address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) uint32_t scratch[lbm::kScratchGrids + 2];
 
 namespace lbm {
 namespace {
@@ -82,6 +92,63 @@ __global__ void nonfinite_kernel(const real *__restrict__ f, int64_t n, int *cou
   if (local) atomicAdd(count, 1);
 }
 
+// Clears the scratch of the allocation-free finite check for nflags grids:
+// flags and count to 0, the lowest bad grid to 0xffffffff.
+__global__ void scratch_reset_kernel(uint32_t *s, int nflags) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nflags; k += gridDim.x * blockDim.x)
+    s[k] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    s[kScratchGrids] = 0u;
+    s[kScratchGrids + 1] = 0xffffffffu;
+  }
+}
+
+// Grid blockIdx.y's populations (9 x pitch x ny from its offset) scanned by
+// gridDim.x blocks; a block that finds NaN or Inf raises the grid's flag, and
+// the first block to raise it counts the grid and lowers the minimum index.
+template <typename real>
+__global__ void nonfinite_grids_kernel(const real *__restrict__ f, const GridDev *__restrict__ grids,
+                                       uint32_t *s) {
+  const int g = blockIdx.y;
+  const int64_t off = grids[g].f_off;
+  const int64_t n = (int64_t)9 * grids[g].pitch * grids[g].ny;
+  int bad = 0;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const real v = f[off + k];
+    if (!(v - v == real(0))) bad = 1;
+  }
+  if (__syncthreads_or(bad) && threadIdx.x == 0) {
+    if (atomicOr(&s[g], 1u) == 0u) {
+      atomicAdd(&s[kScratchGrids], 1u);
+      atomicMin(&s[kScratchGrids + 1], (uint32_t)g);
+    }
+  }
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {};
+
+// The current device's address of the scratch array, taken once per device
+// with that device current.
+hipError_t scratch_address(uint32_t **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_addr[dev] = p;
+  }
+  *out = static_cast<uint32_t *>(g_scratch_addr[dev]);
+  return hipSuccess;
+}
+
 // Copy nplanes planes of an nx x ny grid between two layouts given by their
 // strides (elements) between planes and between rows.
 template <typename real>
@@ -148,6 +215,29 @@ hipError_t launch_count_nonfinite(const real *f, int64_t n, int *count, hipStrea
 }
 
 template <typename real>
+hipError_t check_nonfinite_scratch(const real *f, const GridDev *grids, int nbatch,
+                                   int64_t max_elems, hipStream_t stream, uint32_t out[2]) {
+  if (nbatch < 1 || nbatch > kScratchGrids || max_elems < 1) return hipErrorInvalidValue;
+  uint32_t *s = nullptr;
+  hipError_t e = scratch_address(&s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(scratch_reset_kernel, dim3((nbatch + 255) / 256), dim3(256), 0, stream, s,
+                     nbatch);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // blocks per grid: enough to cover the largest grid in a few passes, and
+  // at most 65535 grids along y (nbatch <= kScratchGrids)
+  const int bx = blocks_for(max_elems, 256, std::max(1, 16384 / nbatch));
+  hipLaunchKernelGGL(nonfinite_grids_kernel<real>, dim3(bx, nbatch), dim3(256), 0, stream, f,
+                     grids, s);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(out, s + kScratchGrids, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost, stream);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(stream);
+}
+
+template <typename real>
 hipError_t launch_copy_planes(const real *src, int64_t src_ps, int64_t src_ys, real *dst,
                               int64_t dst_ps, int64_t dst_ys, int nx, int ny, int nplanes,
                               hipStream_t stream) {
@@ -176,6 +266,8 @@ hipError_t launch_add_time(int64_t *t_dev, int64_t delta, hipStream_t stream) {
   template hipError_t launch_gather<real>(const real *, const int64_t *, int, real *,            \
                                           hipStream_t);                                          \
   template hipError_t launch_count_nonfinite<real>(const real *, int64_t, int *, hipStream_t);   \
+  template hipError_t check_nonfinite_scratch<real>(const real *, const GridDev *, int, int64_t,  \
+                                                    hipStream_t, uint32_t *);                    \
   template hipError_t launch_copy_planes<real>(const real *, int64_t, int64_t, real *, int64_t,  \
                                                int64_t, int, int, int, hipStream_t);
 LBM_INST(float)

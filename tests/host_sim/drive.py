@@ -127,6 +127,7 @@ def run_forward(probs, T, launch, steps=(5, 1, 8), tune=None):
         L.lbm_step(ctx, n)
         L.lbm_filter(ctx, 0.01)
     kt = L.lbm_step_timed(ctx, 4)
+    assert L.lbm_check_finite_noalloc(ctx)
     after = sim.sim_pairs_checked()
     L.lbm_destroy(ctx)
     return after - before, kt

@@ -341,6 +341,21 @@ hipError_t launch_gather(const real *src, const int64_t *idx, int n, real *dst, 
 }
 template <typename real>
 hipError_t launch_count_nonfinite(const real *f, int64_t n, int *count, hipStream_t) { check_range(f, n * sizeof(real), "nonfinite"); return hipSuccess; }
+// the scratch-backed finite check: every grid's populations inside the
+// descriptor table's ranges; no scratch exists here, so it reports none
+template <typename real>
+hipError_t check_nonfinite_scratch(const real *f, const GridDev *grids, int nbatch, int64_t max_elems,
+                                   hipStream_t, uint32_t out[2]) {
+  if (nbatch < 1 || nbatch > kScratchGrids) return hipErrorInvalidValue;
+  check_range(grids, sizeof(GridDev) * nbatch, "scratch grids");
+  for (int g = 0; g < nbatch; ++g) {
+    if (9 * (int64_t)grids[g].pitch * grids[g].ny > max_elems) { fprintf(stderr, "max_elems too small\n"); abort(); }
+    check_range(f + grids[g].f_off, sizeof(real) * 9 * (size_t)grids[g].pitch * grids[g].ny, "scratch check");
+  }
+  out[0] = 0u;
+  out[1] = 0xffffffffu;
+  return hipSuccess;
+}
 template <typename real>
 hipError_t launch_copy_planes(const real *src, int64_t sps, int64_t sys, real *dst, int64_t dps, int64_t dys, int nx, int ny, int np, hipStream_t) {
   for (int p = 0; p < np; ++p) for (int y = 0; y < ny; ++y) {
@@ -366,6 +381,7 @@ hipError_t launch_add_time(int64_t *t, int64_t v, hipStream_t) { check_range(t, 
   template hipError_t launch_kappa_range<real>(const real *, int, int, int, real *, int, hipStream_t); \
   template hipError_t launch_gather<real>(const real *, const int64_t *, int, real *, hipStream_t); \
   template hipError_t launch_count_nonfinite<real>(const real *, int64_t, int *, hipStream_t); \
+  template hipError_t check_nonfinite_scratch<real>(const real *, const GridDev *, int, int64_t, hipStream_t, uint32_t *); \
   template hipError_t launch_copy_planes<real>(const real *, int64_t, int64_t, real *, int64_t, int64_t, int, int, int, hipStream_t);
 INST(float)
 INST(double)
