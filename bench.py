@@ -382,33 +382,31 @@ def bench_batched(torch, w, Solver, plain_glups: float, steps: int = 60,
                   warmup: int = 20, launch=None) -> dict:
     """512 grids of uneven side (256..2048) in one context, one launch of each
     kernel per pair of steps over the flat tile lists, the time loop captured
-    in HIP graphs of 10 pairs; the same launched directly beside it."""
+    in HIP graphs of 10 pairs; then the same context launched directly (the
+    same workspace: its placement in HBM moves the rate by several percent
+    between allocations, so both forms are timed on one)."""
     probs = w.batched_shots()
     cells = sum(p.nx * p.ny for p in probs)
-    out = {}
-    for name, gc in (("graph", None), ("direct", 0)):
-        lc = dict(launch or BATCHED_LAUNCH)
-        if gc is not None:
-            lc["graph_chunk"] = gc
-        t0 = time.perf_counter()
-        s = Solver(probs, dtype="f32", trace_steps=1, launch=lc)
-        setup = time.perf_counter() - t0
-        ms = _timed_steps(s, steps, warmup, torch)
-        ok = s.check_finite()
-        lc = s.launch()
-        s.close()
-        out[name] = {"GLUPS": round(cells / ms / 1e6, 3), "ms_per_step": round(ms, 4),
-                     "setup_s": round(setup, 1), "launch": lc, "state_finite": bool(ok)}
-        torch.cuda.empty_cache()
-    g = out["graph"]["GLUPS"]
+    lc = dict(launch or BATCHED_LAUNCH)
+    t0 = time.perf_counter()
+    s = Solver(probs, dtype="f32", trace_steps=1, launch=lc)
+    setup = time.perf_counter() - t0
+    ms = _timed_steps(s, steps, warmup, torch)
+    graph_launch = s.launch()
+    direct = dict(graph_launch)
+    direct["graph_chunk"] = 0
+    s.set_launch(**direct)
+    ms_direct = _timed_steps(s, steps, warmup, torch)
+    ok = s.check_finite()
+    s.close()
+    g = cells / ms / 1e6
+    gd = cells / ms_direct / 1e6
     return {"workload": f"batched_shots: {len(probs)} grids, sides 256..2048, {cells} cells, FP32",
-            "GLUPS": g, "ms_per_step": out["graph"]["ms_per_step"], "steps": steps,
-            "warmup": warmup, "vs_plain": round(g / plain_glups, 4),
-            "setup_s": out["graph"]["setup_s"], "launch": out["graph"]["launch"],
-            "state_finite": out["graph"]["state_finite"],
-            "direct_launches": {k: out["direct"][k] for k in ("GLUPS", "ms_per_step", "launch",
-                                                             "state_finite")},
-            "graph_vs_direct": round(g / out["direct"]["GLUPS"], 4)}
+            "GLUPS": round(g, 3), "ms_per_step": round(ms, 4), "steps": steps,
+            "warmup": warmup, "vs_plain": round(g / plain_glups, 4), "setup_s": round(setup, 1),
+            "launch": graph_launch, "state_finite": bool(ok),
+            "direct_launches": {"GLUPS": round(gd, 3), "ms_per_step": round(ms_direct, 4)},
+            "graph_vs_direct": round(g / gd, 4)}
 
 
 def bench_adjoint(torch, w, Solver, plain_glups: float, nsteps: int = 5000,
@@ -525,7 +523,8 @@ def main():
         return
     if args.only:
         fn = {"hbm_scale": lambda: bench_hbm_scale(torch, w, Solver, cpu=not args.no_cpu_baseline),
-              "single_step": lambda: bench_plain_variant(torch, w, Solver, "f32", {"fuse_rows": 0},
+              "single_step": lambda: bench_plain_variant(torch, w, Solver, "f32",
+                                                         {"fuse_rows": 0, "waves": 8, "rows": 8},
                                                          "single-step path"),
               "plain_f64": lambda: bench_plain_variant(torch, w, Solver, "f64", {},
                                                        "FP64, default launch"),
@@ -590,7 +589,8 @@ def main():
         for name, fn in (("hbm_scale", lambda: bench_hbm_scale(torch, w, Solver,
                                                                cpu=not args.no_cpu_baseline)),
                          ("single_step", lambda: bench_plain_variant(
-                             torch, w, Solver, "f32", {"fuse_rows": 0}, "single-step path")),
+                             torch, w, Solver, "f32", {"fuse_rows": 0, "waves": 8, "rows": 8},
+                             "single-step path")),
                          ("plain_f64", lambda: bench_plain_variant(
                              torch, w, Solver, "f64", {}, "FP64, default launch")),
                          ("batched", lambda: bench_batched(torch, w, Solver, glups)),
