@@ -259,6 +259,25 @@ int lbm_stability(const lbm_ctx *ctx, double *growth);
  * LBM_E_NONFINITE. */
 int lbm_check_finite(lbm_ctx *ctx);
 
+/* Periodic finite check (numerical blow-up: the paper's instability of
+ * nu != 1/4 at high wavenumbers, Sec. 4, or the printed free surface). With
+ * every > 0, lbm_step checks every grid's state each time the context time
+ * reaches a multiple of `every` (a read of the whole state, asynchronous on
+ * the stream; steps run in segments ending there, so captured graphs serve
+ * chunks that fit between checks) and records the first time whose state
+ * holds NaN or Inf. Once that check has run, lbm_step returns
+ * LBM_E_NONFINITE without stepping, with the time in lbm_last_error; the
+ * recorded failure is cleared by lbm_set_state and by calling this again.
+ * every = 0 (the default) turns it off. Synchronous (waits for the stream,
+ * allocates 8 bytes of pinned host memory the first time). Returns LBM_OK,
+ * LBM_E_INVALID (every < 0) or LBM_E_DEVICE. */
+int lbm_set_finite_check(lbm_ctx *ctx, int64_t every);
+
+/* Wait for the context's stream and report the periodic check: LBM_OK, or
+ * LBM_E_NONFINITE with *t_bad (host, may be NULL) the first checked time
+ * whose state held NaN or Inf (-1 when none). Synchronous. */
+int lbm_finite_status(lbm_ctx *ctx, int64_t *t_bad);
+
 /* lbm_check_finite for callers that cannot allocate device memory (serving
  * loops and harnesses that forbid hipMalloc): the same check and the same
  * results, with no hipMalloc, hipFree or allocating library call. Its flags

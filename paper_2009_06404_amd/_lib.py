@@ -39,6 +39,7 @@ ENTRY_POINTS = (
     "lbm_adjoint_step", "lbm_adjoint_time", "lbm_adjoint_get_state", "lbm_adjoint_set_state",
     "lbm_misfit", "lbm_lame_gradient", "lbm_vn_growth", "lbm_stability",
     "lbm_vn_growth_filtered", "lbm_filter", "lbm_check_finite_noalloc",
+    "lbm_set_finite_check", "lbm_finite_status",
 )
 
 
@@ -106,6 +107,8 @@ def lib():
             "lbm_set_state": ([vp, i32, vp, i64], C.c_int),
             "lbm_check_finite": ([vp], C.c_int),
             "lbm_check_finite_noalloc": ([vp], C.c_int),
+            "lbm_set_finite_check": ([vp, i64], C.c_int),
+            "lbm_finite_status": ([vp, C.POINTER(i64)], C.c_int),
             "lbm_get_launch": ([vp, C.POINTER(lbm_launch)], C.c_int),
             "lbm_set_launch": ([vp, C.POINTER(lbm_launch)], C.c_int),
             "lbm_autotune": ([vp, i32, C.POINTER(lbm_launch)], C.c_int),
@@ -260,6 +263,21 @@ def lbm_check_finite(ctx) -> bool:
         return False
     check(rc)
     return True
+
+
+def lbm_set_finite_check(ctx, every: int) -> None:
+    check(lib().lbm_set_finite_check(ctx, int(every)))
+
+
+def lbm_finite_status(ctx):
+    """(ok, t_bad): t_bad is the first checked time whose state held NaN or
+    Inf, -1 when none."""
+    t = C.c_int64(-1)
+    rc = lib().lbm_finite_status(ctx, C.byref(t))
+    if rc == LBM_E_NONFINITE:
+        return False, t.value
+    check(rc)
+    return True, t.value
 
 
 def lbm_check_finite_noalloc(ctx) -> bool:

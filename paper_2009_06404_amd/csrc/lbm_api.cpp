@@ -171,6 +171,12 @@ struct lbm_ctx {
   // second stream and fork/join events for the overlapped general kernel
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // periodic finite check (lbm_set_finite_check): every `watch_every` steps
+  // of time, the state is checked; the first failing time lands in pinned
+  // host memory the check kernel writes through its device mapping
+  int64_t watch_every = 0;
+  int64_t *watch_host = nullptr;   // hipHostMalloc'd, -1 while no failure
+  int64_t *watch_dev = nullptr;    // its device address
   int ntiles = 0, ntiles_int = 0;
   int gen_waves = 1;                             // tile width (x64) of the general list
   int64_t cells_int = 0, cells_gen = 0;          // cells each kernel's tile list covers
@@ -1058,8 +1064,38 @@ int build_graphs(lbm_ctx *c, int chunk) {
   return LBM_OK;
 }
 
+// Enqueue the finite check of the current state (time c->t).
+template <typename real>
+int watch_state(lbm_ctx *c) {
+  HIP_TRY(launch_finite_watch<real>(reinterpret_cast<const real *>(c->fbuf[c->cur]), c->L.f_elems,
+                                    c->t, c->watch_dev, c->stream));
+  return LBM_OK;
+}
+
+template <typename real>
+int step_run(lbm_ctx *c, int64_t n);
+
+// With the finite check on, steps run in segments that end on multiples of
+// watch_every, each followed by the check of the state reached.
 template <typename real>
 int step_impl(lbm_ctx *c, int64_t n) {
+  if (c->watch_every <= 0) return step_run<real>(c, n);
+  while (n > 0) {
+    const int64_t to_next = c->watch_every - (c->t % c->watch_every);
+    const int64_t m = std::min(n, to_next);
+    int rc = step_run<real>(c, m);
+    if (rc) return rc;
+    n -= m;
+    if (c->t % c->watch_every == 0) {
+      rc = watch_state<real>(c);
+      if (rc) return rc;
+    }
+  }
+  return LBM_OK;
+}
+
+template <typename real>
+int step_run(lbm_ctx *c, int64_t n) {
   int rc = commit(c);
   if (rc) return rc;
   // graph_chunk > 0: whole chunks run as captured graphs, one per buffer
@@ -1575,10 +1611,24 @@ int lbm_set_receivers(lbm_ctx *c, int32_t g, const int32_t *xy, int32_t n, int32
   return LBM_OK;
 }
 
+// A failure the periodic finite check has recorded (visible once the check
+// has run), or LBM_OK.
+int watch_verdict(const lbm_ctx *c) {
+  if (!c->watch_host) return LBM_OK;
+  const int64_t bad = *static_cast<volatile int64_t *>(c->watch_host);
+  if (bad < 0) return LBM_OK;
+  char buf[160];
+  snprintf(buf, sizeof buf, "the periodic finite check found NaN or Inf in the state at t = %lld",
+           (long long)bad);
+  return fail(LBM_E_NONFINITE, buf);
+}
+
 int lbm_step(lbm_ctx *c, int64_t n) {
   int rc = check_ctx(c);
   if (rc) return rc;
   if (n < 0) return fail(LBM_E_INVALID, "n must be >= 0");
+  rc = watch_verdict(c);
+  if (rc) return rc;
   if (n == 0) return LBM_OK;
   if (c->adj.begun && c->adj.taken < c->adj.nseg) {
     rc = commit(c);
@@ -1661,6 +1711,10 @@ int lbm_set_state(lbm_ctx *c, int32_t g, const void *src, int64_t t) {
   if (g < 0 || g >= c->nbatch || !src) return fail(LBM_E_INVALID, "bad grid index or src");
   if (t < 0) return fail(LBM_E_INVALID, "t must be >= 0");
   c->adj.begun = false;   // the recorded forward run no longer describes the state
+  if (c->watch_host) {     // a new state: a recorded failure no longer applies
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    *static_cast<volatile int64_t *>(c->watch_host) = -1;
+  }
   const lbm_grid &G = c->grids[g];
   const int64_t n = (int64_t)G.nx * G.ny;
   const int64_t ps = c->L.pitch[g], ys = 9 * (int64_t)c->L.pitch[g];
@@ -1734,6 +1788,38 @@ int lbm_check_finite(lbm_ctx *c) {
   if (e != hipSuccess) return fail(LBM_E_DEVICE, hipGetErrorString(e));
   if (h) return fail(LBM_E_NONFINITE, "state holds NaN or Inf");
   return LBM_OK;
+}
+
+int lbm_set_finite_check(lbm_ctx *c, int64_t every) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (every < 0) return fail(LBM_E_INVALID, "every must be >= 0");
+  if (every > 0 && !c->watch_host) {
+    void *h = nullptr;
+    HIP_TRY(hipHostMalloc(&h, sizeof(int64_t), hipHostMallocMapped));
+    void *d = nullptr;
+    hipError_t e = hipHostGetDevicePointer(&d, h, 0);
+    if (e != hipSuccess) {
+      hipHostFree(h);
+      return fail(LBM_E_DEVICE, std::string("hipHostGetDevicePointer: ") + hipGetErrorString(e));
+    }
+    c->watch_host = static_cast<int64_t *>(h);
+    c->watch_dev = static_cast<int64_t *>(d);
+  }
+  // re-arm: work already enqueued may still record into the flag
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (c->watch_host) *static_cast<volatile int64_t *>(c->watch_host) = -1;
+  c->watch_every = every;
+  return LBM_OK;
+}
+
+int lbm_finite_status(lbm_ctx *c, int64_t *t_bad) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const int64_t bad = c->watch_host ? *static_cast<volatile int64_t *>(c->watch_host) : -1;
+  if (t_bad) *t_bad = bad;
+  return watch_verdict(c);
 }
 
 int lbm_check_finite_noalloc(lbm_ctx *c) {
@@ -2188,6 +2274,10 @@ int lbm_destroy(lbm_ctx *c) {
   }
   if (c->ev_fork) hipEventDestroy(c->ev_fork);
   if (c->ev_join) hipEventDestroy(c->ev_join);
+  if (c->watch_host) {
+    hipStreamSynchronize(c->stream);
+    hipHostFree(c->watch_host);
+  }
   c->d_adj_io.release();
   c->d_adj_int.release();
   c->d_adj_gen.release();

@@ -166,6 +166,12 @@ hipError_t launch_gather(const real *src, const int64_t *idx, int n, real *dst,
                          hipStream_t stream);
 template <typename real>
 hipError_t launch_count_nonfinite(const real *f, int64_t n, int *count, hipStream_t stream);
+// The periodic finite check of lbm_step: records t in *first_bad (mapped host
+// memory, -1 while none) when the n values at f hold NaN or Inf and no time
+// is recorded yet.
+template <typename real>
+hipError_t launch_finite_watch(const real *f, int64_t n, int64_t t, int64_t *first_bad,
+                               hipStream_t stream);
 // The finite check in the library's static device scratch (no allocation):
 // grids [nbatch] is the device descriptor table, at most kScratchGrids grids,
 // max_elems the largest grid's population count (9 x pitch x ny). On return

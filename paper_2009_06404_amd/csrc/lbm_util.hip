@@ -92,6 +92,23 @@ __global__ void nonfinite_kernel(const real *__restrict__ f, int64_t n, int *cou
   if (local) atomicAdd(count, 1);
 }
 
+// The watch of lbm_set_finite_check: if any of the n values at f is NaN or
+// Inf and no earlier check has recorded a time, record t in *first_bad
+// (host memory mapped into the device; -1 until then). Every writer of one
+// launch writes the same t.
+template <typename real>
+__global__ void finite_watch_kernel(const real *__restrict__ f, int64_t n, int64_t t,
+                                    volatile int64_t *first_bad) {
+  int bad = 0;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const real v = f[k];
+    if (!(v - v == real(0))) bad = 1;
+  }
+  // only blocks that found one touch the host word (one read, one write)
+  if (__syncthreads_or(bad) && threadIdx.x == 0 && *first_bad < 0) *first_bad = t;
+}
+
 // Clears the scratch of the allocation-free finite check for nflags grids:
 // flags and count to 0, the lowest bad grid to 0xffffffff.
 __global__ void scratch_reset_kernel(uint32_t *s, int nflags) {
@@ -215,6 +232,14 @@ hipError_t launch_count_nonfinite(const real *f, int64_t n, int *count, hipStrea
 }
 
 template <typename real>
+hipError_t launch_finite_watch(const real *f, int64_t n, int64_t t, int64_t *first_bad,
+                               hipStream_t stream) {
+  hipLaunchKernelGGL(finite_watch_kernel<real>, dim3(blocks_for(n, 256, 2048)), dim3(256), 0,
+                     stream, f, n, t, first_bad);
+  return hipGetLastError();
+}
+
+template <typename real>
 hipError_t check_nonfinite_scratch(const real *f, const GridDev *grids, int nbatch,
                                    int64_t max_elems, hipStream_t stream, uint32_t out[2]) {
   if (nbatch < 1 || nbatch > kScratchGrids || max_elems < 1) return hipErrorInvalidValue;
@@ -266,6 +291,8 @@ hipError_t launch_add_time(int64_t *t_dev, int64_t delta, hipStream_t stream) {
   template hipError_t launch_gather<real>(const real *, const int64_t *, int, real *,            \
                                           hipStream_t);                                          \
   template hipError_t launch_count_nonfinite<real>(const real *, int64_t, int *, hipStream_t);   \
+  template hipError_t launch_finite_watch<real>(const real *, int64_t, int64_t, int64_t *,      \
+                                                hipStream_t);                                    \
   template hipError_t check_nonfinite_scratch<real>(const real *, const GridDev *, int, int64_t,  \
                                                     hipStream_t, uint32_t *);                    \
   template hipError_t launch_copy_planes<real>(const real *, int64_t, int64_t, real *, int64_t,  \

@@ -123,11 +123,14 @@ def run_forward(probs, T, launch, steps=(5, 1, 8), tune=None):
         assert L.lbm_autotune(ctx, 0) == chosen == L.lbm_get_launch(ctx), chosen
         assert (chosen["fuse_rows"] > 0) == (lc["fuse_rows"] > 0), (chosen, lc)
     before = sim.sim_pairs_checked()
+    L.lbm_set_finite_check(ctx, 4)
     for n in steps:
         L.lbm_step(ctx, n)
         L.lbm_filter(ctx, 0.01)
     kt = L.lbm_step_timed(ctx, 4)
     assert L.lbm_check_finite_noalloc(ctx)
+    assert L.lbm_finite_status(ctx) == (True, -1)
+    L.lbm_set_finite_check(ctx, 0)
     after = sim.sim_pairs_checked()
     L.lbm_destroy(ctx)
     return after - before, kt

@@ -41,6 +41,9 @@ hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, hipMemcpyKind k, hip
 }
 hipError_t hipMemsetAsync(void *d, int v, size_t n, hipStream_t) { check_range(d, n, "memset"); memset(d, v, n); return hipSuccess; }
 hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+hipError_t hipHostMalloc(void **p, size_t n, unsigned int) { *p = malloc(n ? n : 1); g_alloc[(uintptr_t)*p] = n ? n : 1; return hipSuccess; }
+hipError_t hipHostGetDevicePointer(void **d, void *h, unsigned int) { *d = h; return hipSuccess; }
+hipError_t hipHostFree(void *p) { g_alloc.erase((uintptr_t)p); free(p); return hipSuccess; }
 const char *hipGetErrorString(hipError_t) { return "sim error"; }
 hipError_t hipGetLastError() { return hipSuccess; }
 hipError_t hipEventCreate(hipEvent_t *e) { *e = (hipEvent_t)malloc(8); return hipSuccess; }
@@ -341,6 +344,12 @@ hipError_t launch_gather(const real *src, const int64_t *idx, int n, real *dst, 
 }
 template <typename real>
 hipError_t launch_count_nonfinite(const real *f, int64_t n, int *count, hipStream_t) { check_range(f, n * sizeof(real), "nonfinite"); return hipSuccess; }
+template <typename real>
+hipError_t launch_finite_watch(const real *f, int64_t n, int64_t, int64_t *first_bad, hipStream_t) {
+  check_range(f, n * sizeof(real), "finite watch");
+  if (!first_bad) { fprintf(stderr, "finite watch without a flag\n"); abort(); }
+  return hipSuccess;
+}
 // the scratch-backed finite check: every grid's populations inside the
 // descriptor table's ranges; no scratch exists here, so it reports none
 template <typename real>
@@ -382,6 +391,7 @@ hipError_t launch_add_time(int64_t *t, int64_t v, hipStream_t) { check_range(t, 
   template hipError_t launch_gather<real>(const real *, const int64_t *, int, real *, hipStream_t); \
   template hipError_t launch_count_nonfinite<real>(const real *, int64_t, int *, hipStream_t); \
   template hipError_t check_nonfinite_scratch<real>(const real *, const GridDev *, int, int64_t, hipStream_t, uint32_t *); \
+  template hipError_t launch_finite_watch<real>(const real *, int64_t, int64_t, int64_t *, hipStream_t); \
   template hipError_t launch_copy_planes<real>(const real *, int64_t, int64_t, real *, int64_t, int64_t, int, int, int, hipStream_t);
 INST(float)
 INST(double)
