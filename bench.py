@@ -371,7 +371,7 @@ def bench_hbm_scale(torch, w, Solver, steps: int = 200, warmup: int = 20,
 
 
 # pairs of steps on the two-step path, 10 pairs per captured HIP graph
-BATCHED_LAUNCH = {"waves": 2, "rows": 8, "fuse_rows": 32, "graph_chunk": 20}
+BATCHED_LAUNCH = {"waves": 2, "rows": 8, "fuse_rows": 16, "graph_chunk": 20}
 # 1024-column grids: narrow, short tiles for the adjoint kernels; the recorded
 # forward (captured graphs of 10 pairs) and the recompute run on the two-step
 # path (128-column blocks)

@@ -418,11 +418,11 @@ void build_tiles(const lbm_ctx *c, int waves, int rows, bool split, std::vector<
 // tiles where the grid would otherwise give too few workgroups to fill 256
 // compute units.
 // Launch shape by size (measured on MI355X): large contexts take the two-step
-// path, with wider and taller blocks on very tall grids (16384^2 FP32: 142.3
-// GLUPS at 256 x 64 against 139.0 at 256 x 32), 128 x 32 blocks otherwise in
-// FP32 (512 batched grids of side 256..2048: 132.9 GLUPS against 126.4 at
-// 128 x 64) and 128 x 16 in FP64 (4096^2: 72.6 against 71.1 at 128 x 32);
-// small ones single steps in smaller tiles.
+// path in blocks of 128 columns x 16 rows (4096^2 FP32: 133.5 GLUPS against
+// 132.0 at 32 rows and 124-126 at 40-64; the 512 batched grids of side
+// 256..2048: +0.9% against 32 rows; FP64 4096^2: 74.9 against 73.9), and in
+// blocks of 256 x 32 on very tall grids (16384^2 FP32: 149.4 GLUPS against
+// 148.5 at 64 rows); small ones single steps in smaller tiles.
 lbm_launch default_launch(const lbm_ctx *c) {
   int64_t cells = 0;
   int max_ny = 0;
@@ -435,7 +435,7 @@ lbm_launch default_launch(const lbm_ctx *c) {
   // barriers); 256 columns and taller blocks on very tall grids
   const bool tall = max_ny >= 8192;
   l.waves = tall ? 4 : 2;
-  l.fuse_rows = c->dtype == LBM_F32 ? (tall ? 64 : 32) : (tall ? 32 : 16);
+  l.fuse_rows = tall ? 32 : 16;
   // pairs run as captured graphs of 10 pairs: on MI355X as fast as direct
   // launches (within 0.2% on the same workspace, 512 batched grids and
   // 4096^2 FP32), with one host call per 20 steps

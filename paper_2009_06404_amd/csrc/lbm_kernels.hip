@@ -731,7 +731,9 @@ struct Phase {
 };
 
 template <typename real, int NW, bool STASH>
-__global__ __launch_bounds__(64 * NW + 64) void fused2_kernel(StepArgs<real> a) {
+__global__ __launch_bounds__(64 * NW + 64, sizeof(real) == 4 ? (STASH ? 4 : 5) : (STASH ? 2 : 3))
+    void fused2_kernel(
+    StepArgs<real> a) {
   constexpr int W = 64 * NW;
   constexpr int LW = W + 8;                 // LDS columns: tile plus 4 each side
   constexpr int RT = kFusedMaxRows + 8;     // per-row table: rows y0-4 .. y1+3
@@ -813,7 +815,9 @@ __global__ __launch_bounds__(64 * NW + 64) void fused2_kernel(StepArgs<real> a) 
   // rounded up to whole unrolled rounds by starting earlier
   const int r0 = rlast + 1 - (rlast - (y0 - 4) + 1 + 5) / 6 * 6;
 
-  auto iter = [&](const int r, auto ph) {
+  // first: the loop's first round of six rows, whose early rows (before
+  // y0-3, run only to fill the pipeline) load nothing.
+  auto iter = [&](const int r, auto ph, auto first) {
     constexpr int P = decltype(ph)::value;
     real(&fa)[9] = F[P % 3];
     real(&fb)[9] = F[(P + 1) % 3];
@@ -823,14 +827,25 @@ __global__ __launch_bounds__(64 * NW + 64) void fused2_kernel(StepArgs<real> a) 
     real &rA_n = RA[P % 3], &rA_c = RA[(P + 2) % 3], &rA_m = RA[(P + 1) % 3];
     real &rC_n = RC[P % 3], &rC_c = RC[(P + 2) % 3], &rC_m = RC[(P + 1) % 3];
     real kn = real(0);
-    if (live && r + 1 >= y0 - 3 && r + 1 <= rlast) {
-      // the row index and the store offset below go through an empty asm:
-      // otherwise the compiler keeps every population's offset of every
-      // unrolled row as its own scalar induction variable and spills them
-      int rn = r + 1;
+    // The row index and the store offset below go through an empty asm:
+    // otherwise the compiler keeps every population's offset of every
+    // unrolled row as its own scalar induction variable and spills them.
+    if (decltype(first)::value) {
+      if (live && r + 1 >= y0 - 3) {
+        int rn = r + 1;
+        asm volatile("" : "+s"(rn));
+        pull_fast(rin, ybase, rn, rowb, qb, o0, ol, orr, fc);
+        if (kcells) kn = kcol[(int64_t)rn * pitch];
+      }
+    } else {
+      // After the first round every lane loads a row on every iteration
+      // (the row past rlast clamped to rlast, loaded again and not used), so
+      // that every path through the loop issues the same loads and the waits
+      // of stage A leave this prefetch in flight.
+      int rn = min(r + 1, rlast);
       asm volatile("" : "+s"(rn));
       pull_fast(rin, ybase, rn, rowb, qb, o0, ol, orr, fc);
-      if (kcells) kn = kcol[(int64_t)(r + 1) * pitch];
+      if (kcells) kn = kcol[(int64_t)rn * pitch];
     }
     // Stage A: row r of step t.
     rA_n = real(0);
@@ -900,13 +915,22 @@ __global__ __launch_bounds__(64 * NW + 64) void fused2_kernel(StepArgs<real> a) 
     k3 = k2; k2 = k1; k1 = kq; kq = kn;
   };
 
-  for (int r = r0; r <= rlast; r += 6) {
-    iter(r, Phase<0>{});
-    iter(r + 1, Phase<1>{});
-    iter(r + 2, Phase<2>{});
-    iter(r + 3, Phase<3>{});
-    iter(r + 4, Phase<4>{});
-    iter(r + 5, Phase<5>{});
+  // at least one round: rlast - r0 + 1 is a positive multiple of six
+  using First = std::true_type;
+  using Steady = std::false_type;
+  iter(r0, Phase<0>{}, First{});
+  iter(r0 + 1, Phase<1>{}, First{});
+  iter(r0 + 2, Phase<2>{}, First{});
+  iter(r0 + 3, Phase<3>{}, First{});
+  iter(r0 + 4, Phase<4>{}, First{});
+  iter(r0 + 5, Phase<5>{}, First{});
+  for (int r = r0 + 6; r <= rlast; r += 6) {
+    iter(r, Phase<0>{}, Steady{});
+    iter(r + 1, Phase<1>{}, Steady{});
+    iter(r + 2, Phase<2>{}, Steady{});
+    iter(r + 3, Phase<3>{}, Steady{});
+    iter(r + 4, Phase<4>{}, Steady{});
+    iter(r + 5, Phase<5>{}, Steady{});
   }
 }
 
