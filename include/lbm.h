@@ -362,8 +362,25 @@ int lbm_adjoint_set_io(lbm_ctx *ctx, int32_t g, const void *residual, double *gr
 /* n adjoint steps from the adjoint time t_a down to t_a - n (>= t0), for all
  * grids. The recorded forward run must have reached t0 + nsteps. Calls that
  * overlap on one stream are ordered; the gradient buffers must stay valid
- * until the work completes. Asynchronous. */
+ * until the work completes. With fuse_rows > 0 the steps go in pairs (t,
+ * t-1) inside each checkpoint segment, like the forward's: the general
+ * adjoint kernel takes step t of its tiles and of the two-step blocks'
+ * border strips, the two-step adjoint kernel both steps of its blocks (no
+ * receiver within three rows of their own rows) in one pass, the general
+ * kernel step t-1 of its tiles; a step left alone at a segment's start runs
+ * as a single step. Asynchronous. */
 int lbm_adjoint_step(lbm_ctx *ctx, int64_t n);
+
+/* lbm_adjoint_step with direct launches and a HIP event pair on the
+ * context's stream around every adjoint-kernel launch: the mean launch
+ * durations and cells covered go to *out (host; interior = the single-step
+ * interior adjoint kernel, general = the general adjoint kernel, on the pair
+ * path its tiles of one pair's step, fused = the two-step adjoint kernel,
+ * whose cells advance two steps a launch). The recompute of a segment runs
+ * untimed. The adjoint state and dL/dkappa equal those of lbm_adjoint_step
+ * bit for bit (dL/damp up to the order of its FP64 atomic sums). Synchronous.
+ * Errors as lbm_adjoint_step, and LBM_E_INVALID for a null out. */
+int lbm_adjoint_step_timed(lbm_ctx *ctx, int64_t n, lbm_kernel_times *out);
 
 int lbm_adjoint_time(const lbm_ctx *ctx, int64_t *t);
 

@@ -36,7 +36,8 @@ ENTRY_POINTS = (
     "lbm_get_time", "lbm_get_state", "lbm_set_state", "lbm_check_finite",
     "lbm_get_launch", "lbm_set_launch", "lbm_autotune", "lbm_destroy",
     "lbm_adjoint_workspace_bytes", "lbm_adjoint_begin", "lbm_adjoint_set_io",
-    "lbm_adjoint_step", "lbm_adjoint_time", "lbm_adjoint_get_state", "lbm_adjoint_set_state",
+    "lbm_adjoint_step", "lbm_adjoint_step_timed", "lbm_adjoint_time", "lbm_adjoint_get_state",
+    "lbm_adjoint_set_state",
     "lbm_misfit", "lbm_lame_gradient", "lbm_vn_growth", "lbm_stability",
     "lbm_vn_growth_filtered", "lbm_filter", "lbm_check_finite_noalloc",
     "lbm_set_finite_check", "lbm_finite_status",
@@ -117,6 +118,7 @@ def lib():
             "lbm_adjoint_begin": ([vp, i32, i64, vp, C.c_size_t], C.c_int),
             "lbm_adjoint_set_io": ([vp, i32, vp, vp, vp], C.c_int),
             "lbm_adjoint_step": ([vp, i64], C.c_int),
+            "lbm_adjoint_step_timed": ([vp, i64, C.POINTER(lbm_kernel_times)], C.c_int),
             "lbm_adjoint_time": ([vp, C.POINTER(i64)], C.c_int),
             "lbm_adjoint_get_state": ([vp, i32, vp], C.c_int),
             "lbm_adjoint_set_state": ([vp, i32, vp], C.c_int),
@@ -327,6 +329,12 @@ def lbm_adjoint_set_io(ctx, g: int, residual_ptr, grad_kappa_ptr, grad_amp_ptr) 
 
 def lbm_adjoint_step(ctx, n: int) -> None:
     check(lib().lbm_adjoint_step(ctx, int(n)))
+
+
+def lbm_adjoint_step_timed(ctx, n: int) -> dict:
+    out = lbm_kernel_times()
+    check(lib().lbm_adjoint_step_timed(ctx, int(n), C.byref(out)))
+    return {k: getattr(out, k) for k, _ in lbm_kernel_times._fields_}
 
 
 def lbm_adjoint_time(ctx) -> int:

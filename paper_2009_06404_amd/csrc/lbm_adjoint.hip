@@ -29,6 +29,8 @@
 //      with grad(rho)(t) from the density stash of the forward recompute, and
 //      dL/damp_s += Gh . d_s gauss_s(x) ricker_s(t), reduced over each
 //      wavefront and the workgroup before one atomic add per source.
+#include <type_traits>
+
 #include "lbm_device.h"
 
 namespace lbm {
@@ -117,6 +119,39 @@ __device__ __forceinline__ void adj_abb(real fa, real fd1, real fd2, real &r, re
   p = div36(real(6) * d - real(12) * fa);
 }
 
+// kappa times a component of Gh, rounded on its own and never fused into the
+// add or subtract that uses it: every adjoint kernel then forms the same
+// transposed gradient for a cell away from walls, 1/2 ((q_l - q_r) + (q_u -
+// q_d)), and the launch shape (tile lists, the two-step path) does not change
+// the result.
+template <typename real>
+__device__ __forceinline__ real kmul(real k, real gh) {
+#pragma clang fp contract(off)
+  return k * gh;
+}
+
+// x / 2 rounded on its own: exact unless x is denormal, and then only the
+// same in every kernel if it is never fused into the add that uses it.
+template <typename real>
+__device__ __forceinline__ real halve(real x) {
+#pragma clang fp contract(off)
+  return real(0.5) * x;
+}
+
+// Step 5's dL/dkappa term Gh . grad(rho) of one cell and step, and its
+// accumulation, in FP64 with every product and sum rounded on its own, so
+// that all kernels (the two-step one forms a step's term before it reads
+// the sum) give the same bits.
+template <typename real>
+__device__ __forceinline__ double gk_term(real gx, real gy, real dx, real dy) {
+#pragma clang fp contract(off)
+  return (double)gx * (double)dx + (double)gy * (double)dy;
+}
+__device__ __forceinline__ double gk_add(double acc, double term) {
+#pragma clang fp contract(off)
+  return acc + term;
+}
+
 template <typename real, int NW>
 __global__ __launch_bounds__(64 * NW) void adjoint_kernel(AdjArgs<real> a) {
   constexpr int W = 64 * NW;
@@ -125,8 +160,15 @@ __global__ __launch_bounds__(64 * NW) void adjoint_kernel(AdjArgs<real> a) {
 
   const TileDev tile = a.tiles[blockIdx.x];
   if (tile.g < 0) return;
-  const GridDev &g = a.grids[tile.g];
-  const AdjGridDev io = a.io[tile.g];
+  // a border strip of a two-step block advances the state only
+  const bool strip = (tile.g & kStripTile) != 0;
+  const int gi = tile.g & ~kStripTile;
+  const GridDev &g = a.grids[gi];
+  AdjGridDev io = a.io[gi];
+  if (strip) {
+    io.grad_kappa = nullptr;
+    io.grad_amp = nullptr;
+  }
   const real *__restrict__ fin = a.fin + g.f_off;
   real *__restrict__ fout = a.fout + g.f_off;
   const int nx = g.nx, ny = g.ny, pitch = g.pitch;
@@ -158,11 +200,12 @@ __global__ __launch_bounds__(64 * NW) void adjoint_kernel(AdjArgs<real> a) {
   const int nsrc = io.grad_amp ? min(g.nsrc, kMaxAdjSources) : 0;
   if (lane < kMaxAdjSources) samp[lane] = 0.0;
 
-  // Weights of the transposed gradient from the x-neighbours: 1/2, or 1 from
-  // a neighbour on a rigid side edge (its one-sided difference).
+  // Twice the weights of the transposed gradient from the x-neighbours: 1
+  // (weight 1/2), or 2 from a neighbour on a rigid side edge (its one-sided
+  // difference, weight 1).
   const bool rigid_l = g.bc[kEdgeLeft] == kRigid, rigid_r = g.bc[kEdgeRight] == kRigid;
-  const real wxl = (rigid_l && col.xl == 0) ? real(1) : real(0.5);
-  const real wxr = (rigid_r && col.xr == nx - 1) ? real(1) : real(0.5);
+  const real wxl = (rigid_l && col.xl == 0) ? real(2) : real(1);
+  const real wxr = (rigid_r && col.xr == nx - 1) ? real(2) : real(1);
 
   // Steps 1-2 for the cell (xc, r.y) of column c.
   auto cell = [&](const Row &r, const Col &c, int xc, real as[9], real &Gx, real &Gy, real &mx,
@@ -194,26 +237,26 @@ __global__ __launch_bounds__(64 * NW) void adjoint_kernel(AdjArgs<real> a) {
 
   const int y0 = tile.y0, y1 = tile.y1;
   Row rc = make_row(g, y0);
-  // The row above the tile, when connected: its kappa * Gh_y and whether it
-  // is a top-boundary row (one-sided difference, weight 1).
-  real qy_m = real(0), wy_m = real(0.5);
+  // The row above the tile, when connected: its kappa * Gh_y and twice its
+  // weight (2 for a top-boundary row with its one-sided difference, else 1).
+  real qy_m = real(0), wy_m = real(1);
   if (rc.wall_up == 0) {
     const Row ru = make_row(g, rc.up);
     real as_[9], gx_, gy_, mx_, my_;
     cell(ru, col, xa, as_, gx_, gy_, mx_, my_);
-    qy_m = cell_kappa(a.kappa_rows, a.kappa_cells, g, ru.y, xa) * gy_;
-    wy_m = ru.wall_up != 0 ? real(1) : real(0.5);
+    qy_m = kmul(cell_kappa(a.kappa_rows, a.kappa_cells, g, ru.y, xa), gy_);
+    wy_m = ru.wall_up != 0 ? real(2) : real(1);
   }
   real as_c[9], gx_c, gy_c, mx_c, my_c;
   cell(rc, col, xa, as_c, gx_c, gy_c, mx_c, my_c);
   real kap_c = cell_kappa(a.kappa_rows, a.kappa_cells, g, y0, xa);
-  sq[0][lane + 1] = kap_c * gx_c;
+  sq[0][lane + 1] = kmul(kap_c, gx_c);
   if (lane < 2) {
     real hq = real(0);
     if (hlane) {
       real as_[9], gx_, gy_, mx_, my_;
       cell(rc, hcol, hx, as_, gx_, gy_, mx_, my_);
-      hq = cell_kappa(a.kappa_rows, a.kappa_cells, g, y0, hx) * gx_;
+      hq = kmul(cell_kappa(a.kappa_rows, a.kappa_cells, g, y0, hx), gx_);
     }
     sq[0][hslot] = hq;
   }
@@ -237,7 +280,7 @@ __global__ __launch_bounds__(64 * NW) void adjoint_kernel(AdjArgs<real> a) {
       if (in_tile && hlane) {
         real as_[9], gx_, gy_, mx_, my_;
         cell(rn, hcol, hx, as_, gx_, gy_, mx_, my_);
-        hq_n = cell_kappa(a.kappa_rows, a.kappa_cells, g, yn, hx) * gx_;
+        hq_n = kmul(cell_kappa(a.kappa_rows, a.kappa_cells, g, yn, hx), gx_);
       }
     }
 
@@ -245,22 +288,21 @@ __global__ __launch_bounds__(64 * NW) void adjoint_kernel(AdjArgs<real> a) {
     const real qx_l = sq[s][lane];
     const real qx_r = (xa == x_last) ? sq[s][W + 1] : sq[s][lane + 2];
     if (in_tile) {
-      sq[s ^ 1][lane + 1] = kap_n * gx_n;
+      sq[s ^ 1][lane + 1] = kmul(kap_n, gx_n);
       if (lane < 2) sq[s ^ 1][hslot] = hq_n;
     }
 
-    // Step 3: transposed density gradient.
-    const real qx_c = kap_c * gx_c, qy_c = kap_c * gy_c;
+    // Step 3: transposed density gradient, 1/2 of the x and y parts with
+    // twice their weights (2 q of the cell itself at a wall): away from
+    // walls 1/2 ((q_l - q_r) + (q_u - q_d)), the operations of the other
+    // adjoint kernels, denormal values included.
+    const real qx_c = kmul(kap_c, gx_c), qy_c = kmul(kap_c, gy_c);
     const bool lo_y = rc.wall_up != 0, hi_y = rc.wall_dn != 0;
-    real rD = real(0);
-    if (col.wl) rD -= qx_c;
-    else rD += wxl * qx_l;
-    if (col.wr) rD += qx_c;
-    else rD -= wxr * qx_r;
-    if (lo_y) rD -= qy_c;
-    else rD += wy_m * qy_m;
-    if (hi_y) rD += qy_c;
-    else rD -= (rn.wall_dn != 0 ? real(1) : real(0.5)) * (kap_n * gy_n);
+    const real wy_n = rn.wall_dn != 0 ? real(2) : real(1);
+    const real qx2 = qx_c + qx_c, qy2 = qy_c + qy_c;
+    const real rx = (col.wl ? -qx2 : wxl * qx_l) - (col.wr ? -qx2 : wxr * qx_r);
+    const real ry = (lo_y ? -qy2 : wy_m * qy_m) - (hi_y ? -qy2 : wy_n * kmul(kap_n, gy_n));
+    const real rD = halve(rx + ry);
 
     // Free-surface moment adjoints: the boundary row (extrapolation weight
     // 1.5 as printed, 1 for the zero-order rule) and the row inside it (-0.5).
@@ -317,11 +359,12 @@ __global__ __launch_bounds__(64 * NW) void adjoint_kernel(AdjArgs<real> a) {
       real dx, dy;
       if (col.wl) dx = rs[(int64_t)y * pitch + col.xr] - rho_c;
       else if (col.wr) dx = rho_c - rs[(int64_t)y * pitch + col.xl];
-      else dx = real(0.5) * (rs[(int64_t)y * pitch + col.xr] - rs[(int64_t)y * pitch + col.xl]);
+      else dx = halve(rs[(int64_t)y * pitch + col.xr] - rs[(int64_t)y * pitch + col.xl]);
       if (lo_y) dy = rs[(int64_t)(y + 1) * pitch + x] - rho_c;
       else if (hi_y) dy = rho_c - rs[(int64_t)(y - 1) * pitch + x];
-      else dy = real(0.5) * (rs[(int64_t)rc.dn * pitch + x] - rs[(int64_t)rc.up * pitch + x]);
-      io.grad_kappa[(int64_t)y * nx + x] += (double)gx_c * (double)dx + (double)gy_c * (double)dy;
+      else dy = halve(rs[(int64_t)rc.dn * pitch + x] - rs[(int64_t)rc.up * pitch + x]);
+      double &cell = io.grad_kappa[(int64_t)y * nx + x];
+      cell = gk_add(cell, gk_term(gx_c, gy_c, dx, dy));
     }
     for (int si = 0; si < nsrc; ++si) {
       const SourceDev sd = a.sources[g.src_off + si];
@@ -341,7 +384,7 @@ __global__ __launch_bounds__(64 * NW) void adjoint_kernel(AdjArgs<real> a) {
     // March: row y+1 becomes current.
     __syncthreads();
     qy_m = qy_c;
-    wy_m = lo_y ? real(1) : real(0.5);
+    wy_m = lo_y ? real(2) : real(1);
     if (need_n) {
 #pragma unroll
       for (int i = 0; i < 9; ++i) as_c[i] = as_n[i];
@@ -432,15 +475,15 @@ __global__ __launch_bounds__(64 * NW) void adjoint_interior_kernel(AdjArgs<real>
   {
     real t_[9], gx_, gy_, mx_, my_;
     cell(y0 - 1, false, t_, gx_, gy_, mx_, my_);
-    qy_m = cell_kappa(a.kappa_rows, a.kappa_cells, g, y0 - 1, xa) * gy_;
+    qy_m = kmul(cell_kappa(a.kappa_rows, a.kappa_cells, g, y0 - 1, xa), gy_);
   }
   cell(y0, false, as_c, gx_c, gy_c, mx_c, my_c);
   real kap_c = cell_kappa(a.kappa_rows, a.kappa_cells, g, y0, xa);
-  sq[0][lane + 1] = kap_c * gx_c;
+  sq[0][lane + 1] = kmul(kap_c, gx_c);
   if (lane < 2) {
     real t_[9], gx_, gy_, mx_, my_;
     cell(y0, true, t_, gx_, gy_, mx_, my_);
-    sq[0][hslot] = cell_kappa(a.kappa_rows, a.kappa_cells, g, y0, hx) * gx_;
+    sq[0][hslot] = kmul(cell_kappa(a.kappa_rows, a.kappa_cells, g, y0, hx), gx_);
   }
   __syncthreads();
 
@@ -452,16 +495,16 @@ __global__ __launch_bounds__(64 * NW) void adjoint_interior_kernel(AdjArgs<real>
     if (lane < 2) {
       real t_[9], gx_, gy_, mx_, my_;
       cell(y + 1, true, t_, gx_, gy_, mx_, my_);
-      hq_n = cell_kappa(a.kappa_rows, a.kappa_cells, g, y + 1, hx) * gx_;
+      hq_n = kmul(cell_kappa(a.kappa_rows, a.kappa_cells, g, y + 1, hx), gx_);
     }
     const int s = k & 1;
     const real qx_l = sq[s][lane];
     const real qx_r = (xa == x_last) ? sq[s][W + 1] : sq[s][lane + 2];
-    sq[s ^ 1][lane + 1] = kap_n * gx_n;
+    sq[s ^ 1][lane + 1] = kmul(kap_n, gx_n);
     if (lane < 2) sq[s ^ 1][hslot] = hq_n;
 
     // Step 3 (centred differences only) and step 4.
-    const real rD = real(0.5) * ((qx_l - qx_r) + (qy_m - kap_n * gy_n));
+    const real rD = halve((qx_l - qx_r) + (qy_m - kmul(kap_n, gy_n)));
     if (active) {
       real fh[9];
       adj_finish(as_c, omega, rD, mx_c, my_c, real(0), fh);
@@ -470,13 +513,13 @@ __global__ __launch_bounds__(64 * NW) void adjoint_interior_kernel(AdjArgs<real>
       for (int i = 0; i < 9; ++i) Buf<real>::store_nt(fh[i], rout, o0, rs + i * qb);
       // Step 5: dL/dkappa += Gh . grad(rho)(t).
       const uint32_t pr = (uint32_t)(y - ybase) * qb;
-      const real dx = real(0.5) * (Buf<real>::load(rrho, orr, pr) - Buf<real>::load(rrho, ol, pr));
-      const real dy = real(0.5) * (Buf<real>::load(rrho, o0, pr + qb) - Buf<real>::load(rrho, o0, pr - qb));
-      if (gk) gk[(int64_t)y * nx + x] += (double)gx_c * (double)dx + (double)gy_c * (double)dy;
+      const real dx = halve(Buf<real>::load(rrho, orr, pr) - Buf<real>::load(rrho, ol, pr));
+      const real dy = halve(Buf<real>::load(rrho, o0, pr + qb) - Buf<real>::load(rrho, o0, pr - qb));
+      if (gk) gk[(int64_t)y * nx + x] = gk_add(gk[(int64_t)y * nx + x], gk_term(gx_c, gy_c, dx, dy));
     }
 
     __syncthreads();
-    qy_m = kap_c * gy_c;
+    qy_m = kmul(kap_c, gy_c);
 #pragma unroll
     for (int i = 0; i < 9; ++i) as_c[i] = as_n[i];
     gx_c = gx_n;
@@ -484,6 +527,292 @@ __global__ __launch_bounds__(64 * NW) void adjoint_interior_kernel(AdjArgs<real>
     mx_c = mx_n;
     my_c = my_n;
     kap_c = kap_n;
+  }
+}
+
+template <int N>
+using AdjPhase = std::integral_constant<int, N>;
+
+// Two adjoint steps of a block in one pass: from fh(t+1) in HBM to fh(t-1)
+// in HBM, fh(t) staying on chip, over blocks clear of walls, of the y-wrap,
+// of source disks and of receivers within three rows (the blocks of the
+// forward's two-step path, the rows near receivers taken out). The row loop
+// is the forward two-step kernel's with every arrow reversed:
+//   A (row r):   transposed pull of ah(t) from fh(t+1) (row r+1 in flight),
+//                the local transpose (Gh, mh); kappa Gh_x into an LDS ring;
+//   B (row r-1): transposed gradient and moments -> fh(t) of row r-1, and
+//                step t's dL/dkappa contribution Gh . grad(rho)(t);
+//   C (row r-2): transposed pull of ah(t-1) from fh(t) of rows r-3 .. r-1
+//                (on chip), the local transpose; kappa Gh_x into a ring;
+//   D (row r-3): -> fh(t-1) of row r-3 to HBM; dL/dkappa += step t's then
+//                step t-1's contribution (one FP64 read and write, in the
+//                order of two single steps).
+// The transposed pull takes population k from row y + c_ky: of fh(t), the
+// populations with c_y = +1 (2, 5, 6) come from the newest row, those with
+// c_y = 0 (0, 1, 3) from one row before, those with c_y = -1 (4, 7, 8) from
+// two rows before; the six with c_x != 0 pass through LDS rings of those
+// depths, the three with c_x = 0 stay in registers. The per-cell operations
+// are the interior adjoint kernel's, in the same order. Lanes as in the
+// forward kernel: the block's 64 * NW columns plus a wavefront for the four
+// halo columns on each side; stage B runs on three halo columns, C on two.
+// The density stashes reach the gradient terms through register rings (the
+// rows above and below, each lane its own column, loaded one row ahead) and
+// LDS (the row's neighbours in x); dL/dkappa is read one row ahead too, so
+// that no stage waits on a load issued in it.
+template <typename real, int NW>
+__global__ __launch_bounds__(64 * NW + 64, sizeof(real) == 4 ? 4 : 2) void adjoint_fused2_kernel(
+    AdjArgs<real> a) {
+  constexpr int W = 64 * NW;
+  constexpr int LW = W + 8;
+  constexpr int RT = kFusedMaxRows + 8;
+  __shared__ real sQA[2][LW];               // kappa Gh_x(t) of rows r-1, r
+  __shared__ real sQC[2][LW];               // kappa Gh_x(t-1) of rows r-3, r-2
+  __shared__ real s56[2][LW];               // fh(t) populations 5, 6 of row r-1
+  __shared__ real s13[2][2][LW];            // populations 1, 3 of rows r-2, r-1
+  __shared__ real s78[3][2][LW];            // populations 7, 8 of rows r-3 .. r-1
+  __shared__ real sRt[LW], sRt1[LW];        // rho(t) of row r-1, rho(t-1) of row r-3
+  __shared__ real sRowA[RT], sRowI[RT], sRowK[RT];
+
+  const FusedTileDev tile = a.ftiles[blockIdx.x];
+  if (tile.g < 0) return;
+  const GridDev g = uniform_lookup_fields(a.grids[tile.g]);
+  const double *gk = a.io[tile.g].grad_kappa;
+  const int pitch = g.pitch, nx = g.nx;
+  const int w = tile.x1 - tile.x0;
+  const int tid = threadIdx.x;
+  const int hl = tid - W;
+  int lc = -1;
+  if (tid < W) lc = tid + 4;
+  else if (hl < 4) lc = hl;
+  else if (hl < 8) lc = W + hl;
+  const bool live = lc >= 0 && lc < w + 8;
+  const bool outlane = tid < w;
+  auto wrapx = [&](int c) { return c < 0 ? c + nx : (c >= nx ? c - nx : c); };
+  const int col = live ? wrapx(tile.x0 - 4 + lc) : 0;
+  const uint32_t esz = sizeof(real);
+  const uint32_t o0 = (uint32_t)col * esz;
+  const uint32_t ol = (uint32_t)wrapx(col - 1) * esz;
+  const uint32_t orr = (uint32_t)wrapx(col + 1) * esz;
+
+  const real omega = a.omega, cforce = a.cforce;
+  const int y0 = tile.y0, y1 = tile.y1;
+  const int ybase = y0 - 4;
+  const uint32_t qb = (uint32_t)pitch * esz;
+  const uint32_t rowb = 9 * qb;
+  const int64_t base = g.f_off + (int64_t)ybase * 9 * pitch;
+  const uint64_t rest = (uint64_t)(a.f_elems - base) * esz;
+  const __amdgpu_buffer_rsrc_t rin = range_rsrc(a.fin + base, rest);
+  const __amdgpu_buffer_rsrc_t rout = range_rsrc(a.fout + base, rest);
+  // the density stash of steps t and t-1, rows from ybase on
+  const __amdgpu_buffer_rsrc_t rt = tile_rsrc(a.rho + g.c_off + (int64_t)ybase * pitch);
+  const __amdgpu_buffer_rsrc_t rt1 = tile_rsrc(a.rho2 + g.c_off + (int64_t)ybase * pitch);
+  // dL/dkappa from row ybase on; without it (no gradient asked) an empty
+  // range, through which loads return 0 and stores are dropped
+  const __amdgpu_buffer_rsrc_t rgk = range_rsrc(
+      gk ? gk + (int64_t)ybase * nx : gk, gk ? (uint64_t)(g.ny - ybase) * nx * sizeof(double) : 0);
+  const uint32_t og = (uint32_t)col * sizeof(double), gkrow = (uint32_t)nx * sizeof(double);
+
+  const int nrows = y1 - y0 + 8;
+  for (int k = tid; k < nrows; k += W + 64) {
+    real Ay = real(0), Iy = real(1);
+    sponge_y(a.sponge, g, ybase + k, Ay, Iy);
+    sRowA[k] = Ay;
+    sRowI[k] = Iy;
+    sRowK[k] = g.kmode == kKappaRows ? a.kappa_rows[g.k_off + ybase + k] : real(0);
+  }
+  real A_x, inv_x;
+  sponge_x(a.sponge, g, col, A_x, inv_x);
+  const bool kcells = g.kmode == kKappaCells;
+  const real kscalar = (real)g.kscalar;
+  // the cell-wise moduli from row ybase on (an empty range for the other
+  // kinds of medium: their loads return 0, with no branch around them)
+  const __amdgpu_buffer_rsrc_t rk = range_rsrc(
+      a.kappa_cells + (kcells ? g.k_off + (int64_t)ybase * pitch : 0),
+      kcells ? (uint64_t)(g.ny - ybase) * pitch * sizeof(real) : 0);
+  const bool inB = lc >= 1 && lc <= w + 6, inC = lc >= 2 && lc <= w + 5;
+  __syncthreads();
+
+  // Registers carried down the rows: F the pulled ah(t) of rows r-1, r and
+  // r+1 (in flight); MA the (mh_x, mh_y, Gh_x, Gh_y) of rows r-1, r; QA
+  // kappa Gh_y(t) of rows r-2, r-1, r; G the pulled ah(t-1) of rows r-3,
+  // r-2 and MC, QC their moments as for step t; D0 / E4 populations 0 and 4
+  // of fh(t) waiting one and two rows for stage C; CT step t's dL/dkappa
+  // contributions of rows r-3 .. r-1; kq, k0, k1 the cell-wise modulus of
+  // rows r, r-1, r-2 (row r+1 in flight). Indexed by row modulo 6 (the
+  // unrolled round): RH rho(t) of rows r-2 .. r+1 (in flight), R1 rho(t-1)
+  // of rows r-4 .. r-1 (in flight), GK dL/dkappa of rows r-3, r-2 (in
+  // flight), at this lane's column.
+  real F[3][9], G[2][9], MA[2][4], MC[2][4], QA[3], QC[3], D0[2], E4[3], RH[6], R1[6];
+  double CT[3], GK[6];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) { F[0][i] = F[1][i] = F[2][i] = G[0][i] = G[1][i] = real(0); }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) { MA[0][i] = MA[1][i] = MC[0][i] = MC[1][i] = real(0); }
+  QA[0] = QA[1] = QA[2] = QC[0] = QC[1] = QC[2] = real(0);
+  D0[0] = D0[1] = E4[0] = E4[1] = E4[2] = real(0);
+  CT[0] = CT[1] = CT[2] = 0.0;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    RH[i] = R1[i] = real(0);
+    GK[i] = 0.0;
+  }
+  real kq = real(0), k0 = real(0), k1 = real(0);
+
+  const int rlast = y1 + 2;
+  const int r0 = rlast + 1 - (rlast - (y0 - 4) + 1 + 5) / 6 * 6;
+
+  auto kap_row = [&](int row, real kc) {
+    return kcells ? kc : (g.kmode == kKappaRows ? sRowK[row - ybase] : kscalar);
+  };
+
+  auto iter = [&](const int r, auto ph, auto first) {
+    constexpr int P = decltype(ph)::value;
+    real(&fb)[9] = F[(P + 1) % 3];          // row r (stage A)
+    real(&fc)[9] = F[(P + 2) % 3];          // row r+1 (loads)
+    real(&fa)[9] = F[P % 3];                // row r-1 (stage B)
+    real(&gn)[9] = G[(P + 1) % 2];          // row r-2 (stage C)
+    real(&gc)[9] = G[P % 2];                // row r-3 (stage D)
+    real(&ma_n)[4] = MA[P % 2];             // row r
+    real(&ma_c)[4] = MA[(P + 1) % 2];       // row r-1
+    real(&mc_n)[4] = MC[P % 2];             // row r-2
+    real(&mc_c)[4] = MC[(P + 1) % 2];       // row r-3
+    real &qA_n = QA[P % 3], &qA_m = QA[(P + 1) % 3];   // rows r, r-2
+    real &qC_n = QC[P % 3], &qC_m = QC[(P + 1) % 3];   // rows r-2, r-4
+    double &ct_b = CT[P % 3], &ct_d = CT[(P + 1) % 3];
+    real kn = real(0);
+    // row y's slot in RH, R1 and GK: (P + y - r) mod 6
+    constexpr int S_P1 = (P + 1) % 6, S_M1 = (P + 5) % 6, S_M2 = (P + 4) % 6;
+    constexpr int S_M3 = (P + 3) % 6, S_M4 = (P + 2) % 6, S_0 = P;
+    // dL/dkappa of row r-2 (clamped to the block's first row, in range)
+    {
+      const uint32_t sg = sreg((int32_t)((uint32_t)(max(r - 2, y0) - ybase) * gkrow));
+      GK[S_M2] = Buf<double>::load(rgk, og, sg);
+    }
+    // The row index and the offsets below go through an empty asm: otherwise
+    // the compiler keeps every population's offset of every unrolled row as
+    // its own scalar induction variable. After the first round every lane
+    // loads on every iteration (past rlast: rlast again, not used), so the
+    // waits of stage A leave this prefetch in flight.
+    // The densities: rho(t) of row r+1, rho(t-1) of row r-1.
+    if (decltype(first)::value) {
+      if (live && r + 1 >= y0 - 3) {
+        int rn = r + 1;
+        asm volatile("" : "+s"(rn));
+        adj_pull_fast(rin, ybase, rn, rowb, qb, o0, ol, orr, fc);
+        const uint32_t sr = sreg((int32_t)((uint32_t)(rn - ybase) * qb));
+        kn = Buf<real>::load(rk, o0, sr);
+        RH[S_P1] = Buf<real>::load(rt, o0, sr);
+      }
+      if (live && r - 1 >= y0 - 1)
+        R1[S_M1] = Buf<real>::load(rt1, o0, sreg((int32_t)((uint32_t)(r - 1 - ybase) * qb)));
+    } else {
+      int rn = min(r + 1, rlast);
+      asm volatile("" : "+s"(rn));
+      adj_pull_fast(rin, ybase, rn, rowb, qb, o0, ol, orr, fc);
+      kn = Buf<real>::load(rk, o0, sreg((int32_t)((uint32_t)(rn - ybase) * qb)));
+      RH[S_P1] = Buf<real>::load(rt, o0, sreg((int32_t)((uint32_t)(r + 1 - ybase) * qb)));
+      R1[S_M1] = Buf<real>::load(rt1, o0, sreg((int32_t)((uint32_t)(r - 1 - ybase) * qb)));
+    }
+    // Stage A: row r of step t.
+    qA_n = real(0);
+    if (live && r >= y0 - 3) {
+      const real A = max(A_x, sRowA[r - ybase]), inv = min(inv_x, sRowI[r - ybase]);
+      adj_local(fb, real(0), real(0), A, inv, omega, cforce, ma_n[2], ma_n[3], ma_n[0], ma_n[1]);
+      const real kap = kap_row(r, kq);
+      sQA[r & 1][lc] = kmul(kap, ma_n[2]);
+      qA_n = kmul(kap, ma_n[3]);
+    }
+    if (live) sRt[lc] = RH[S_M1];
+    __syncthreads();
+    // Stage B: row r-1 of step t.
+    const int rb = r - 1;
+    real p0 = real(0), p2 = real(0), p4 = real(0);
+    if (rb >= y0 - 2 && inB) {
+      const real qx_l = sQA[rb & 1][lc - 1], qx_r = sQA[rb & 1][lc + 1];
+      const real rD = halve((qx_l - qx_r) + (qA_m - qA_n));
+      real fh[9];
+      adj_finish(fa, omega, rD, ma_c[0], ma_c[1], real(0), fh);
+      s56[0][lc] = fh[5];
+      s56[1][lc] = fh[6];
+      s13[rb & 1][0][lc] = fh[1];
+      s13[rb & 1][1][lc] = fh[3];
+      s78[rb % 3][0][lc] = fh[7];
+      s78[rb % 3][1][lc] = fh[8];
+      p0 = fh[0];
+      p2 = fh[2];
+      p4 = fh[4];
+      if (gk && outlane && rb >= y0 && rb < y1) {
+        const real dx = halve(sRt[lc + 1] - sRt[lc - 1]);
+        const real dy = halve(RH[S_0] - RH[S_M2]);
+        ct_b = gk_term(ma_c[2], ma_c[3], dx, dy);
+      }
+    }
+    __syncthreads();
+    // Stage C: row r-2 of step t-1, pulled from fh(t) of rows r-3 .. r-1.
+    const int rc = r - 2;
+    qC_n = real(0);
+    if (rc >= y0 - 1 && inC) {
+      const int s13i = rc & 1, s78i = (rc + 2) % 3;   // rows rc and rc-1
+      gn[0] = D0[P % 2];                             // row rc, this column
+      gn[1] = s13[s13i][0][lc + 1];                  // ( 1, 0) from (x+1, rc)
+      gn[2] = p2;                                    // ( 0, 1) from (x, rc+1)
+      gn[3] = s13[s13i][1][lc - 1];                  // (-1, 0) from (x-1, rc)
+      gn[4] = E4[P % 3];                             // ( 0,-1) from (x, rc-1)
+      gn[5] = s56[0][lc + 1];                        // ( 1, 1) from (x+1, rc+1)
+      gn[6] = s56[1][lc - 1];                        // (-1, 1) from (x-1, rc+1)
+      gn[7] = s78[s78i][0][lc - 1];                  // (-1,-1) from (x-1, rc-1)
+      gn[8] = s78[s78i][1][lc + 1];                  // ( 1,-1) from (x+1, rc-1)
+      const real A = max(A_x, sRowA[rc - ybase]), inv = min(inv_x, sRowI[rc - ybase]);
+      adj_local(gn, real(0), real(0), A, inv, omega, cforce, mc_n[2], mc_n[3], mc_n[0], mc_n[1]);
+      const real kap = kap_row(rc, k1);
+      sQC[rc & 1][lc] = kmul(kap, mc_n[2]);
+      qC_n = kmul(kap, mc_n[3]);
+    }
+    if (live) sRt1[lc] = R1[S_M3];
+    __syncthreads();
+    // Stage D: row r-3 of step t-1.
+    const int rd = r - 3;
+    // (uniform offsets, moved to scalar registers before the branch; rows
+    // before y0 give values that are not used)
+    const uint32_t rs = sreg((int32_t)((uint32_t)(rd - ybase) * rowb));
+    const uint32_t sg = sreg((int32_t)((uint32_t)(rd - ybase) * gkrow));
+    if (rd >= y0 && outlane) {
+      const real qx_l = sQC[rd & 1][lc - 1], qx_r = sQC[rd & 1][lc + 1];
+      const real rD = halve((qx_l - qx_r) + (qC_m - qC_n));
+      real fh[9];
+      adj_finish(gc, omega, rD, mc_c[0], mc_c[1], real(0), fh);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Buf<real>::store_nt(fh[i], rout, o0, rs + i * qb);
+      if (gk) {
+        const real dx = halve(sRt1[lc + 1] - sRt1[lc - 1]);
+        const real dy = halve(R1[S_M2] - R1[S_M4]);
+        const double sum = gk_add(gk_add(GK[S_M3], ct_d), gk_term(mc_c[2], mc_c[3], dx, dy));
+        Buf<double>::store_nt(sum, rgk, og, sg);
+      }
+    }
+    __syncthreads();
+    D0[(P + 1) % 2] = p0;
+    E4[(P + 2) % 3] = p4;
+    k1 = k0;
+    k0 = kq;
+    kq = kn;
+  };
+
+  using First = std::true_type;
+  using Steady = std::false_type;
+  iter(r0, AdjPhase<0>{}, First{});
+  iter(r0 + 1, AdjPhase<1>{}, First{});
+  iter(r0 + 2, AdjPhase<2>{}, First{});
+  iter(r0 + 3, AdjPhase<3>{}, First{});
+  iter(r0 + 4, AdjPhase<4>{}, First{});
+  iter(r0 + 5, AdjPhase<5>{}, First{});
+  for (int r = r0 + 6; r <= rlast; r += 6) {
+    iter(r, AdjPhase<0>{}, Steady{});
+    iter(r + 1, AdjPhase<1>{}, Steady{});
+    iter(r + 2, AdjPhase<2>{}, Steady{});
+    iter(r + 3, AdjPhase<3>{}, Steady{});
+    iter(r + 4, AdjPhase<4>{}, Steady{});
+    iter(r + 5, AdjPhase<5>{}, Steady{});
   }
 }
 
@@ -555,6 +884,17 @@ hipError_t launch_adjoint_interior(const AdjArgs<real> &a, int waves, int ntiles
 }
 
 template <typename real>
+hipError_t launch_adjoint_fused2(const AdjArgs<real> &a, int waves, int ntiles, hipStream_t stream) {
+  if (ntiles <= 0) return hipSuccess;
+  dim3 grid(ntiles), block(64 * waves + 64);
+  if (waves == 2) hipLaunchKernelGGL((adjoint_fused2_kernel<real, 2>), grid, block, 0, stream, a);
+  else if (waves == 4) hipLaunchKernelGGL((adjoint_fused2_kernel<real, 4>), grid, block, 0, stream, a);
+  else if (waves == 8) hipLaunchKernelGGL((adjoint_fused2_kernel<real, 8>), grid, block, 0, stream, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <typename real>
 hipError_t launch_misfit(const real *trace, const real *d_obs, real *residual, int64_t n,
                          double *misfit, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
@@ -576,6 +916,7 @@ hipError_t launch_lame_gradient(const real *lam, const real *mu, const double *g
   template hipError_t launch_adjoint<real>(const AdjArgs<real> &, int, int, hipStream_t);     \
   template hipError_t launch_adjoint_interior<real>(const AdjArgs<real> &, int, int,          \
                                                     hipStream_t);                             \
+  template hipError_t launch_adjoint_fused2<real>(const AdjArgs<real> &, int, int, hipStream_t); \
   template hipError_t launch_misfit<real>(const real *, const real *, real *, int64_t, double *, \
                                           hipStream_t);                                       \
   template hipError_t launch_lame_gradient<real>(const real *, const real *, const double *,  \

@@ -185,6 +185,13 @@ struct lbm_ctx {
   // and the rest (rebuilt after every retiling)
   DevBuf<TileDev> d_adj_int, d_adj_gen;
   int n_adj_int = 0, n_adj_gen = 0;
+  // adjoint pairs on the two-step path: two-step blocks with no receiver
+  // within three rows, the general tiles of the pair's second step (g2) and
+  // of its first (g1: g2's plus the blocks' border strips, flagged)
+  DevBuf<FusedTileDev> d_adj_ftiles;
+  DevBuf<TileDev> d_adj_g2, d_adj_g1;
+  int n_adj_f = 0, n_adj_g2 = 0, n_adj_g1 = 0, adj_fwaves = 2;
+  int64_t cells_adj_int = 0, cells_adj_gen = 0, cells_adj_f = 0, cells_adj_g2 = 0;
   bool adj_tiles_ok = false;
   // graph of graph_chunk steps for each starting buffer parity
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -609,12 +616,17 @@ struct Seg {
   bool ok;       // may hold two-step blocks
 };
 
-std::vector<Seg> fused_row_segments(const lbm_ctx *c, int g, int rows) {
+// rec_reach: a row with a receiver within rec_reach rows is no own row of a
+// block (0 for the forward; the adjoint's blocks, whose receivers add to the
+// adjoint state of every row their two steps form, take 3).
+std::vector<Seg> fused_row_segments(const lbm_ctx *c, int g, int rows, int rec_reach) {
   const int ny = c->grids[g].ny, rr = c->bc[g].rigid_row;
   std::vector<char> allowed((size_t)ny, 0);
   std::vector<char> has_rec((size_t)ny, 0);
   const std::vector<int32_t> &xy = c->recs[g].xy;
-  for (size_t r = 1; r < xy.size(); r += 2) has_rec[(size_t)xy[r]] = 1;
+  for (size_t r = 1; r < xy.size(); r += 2)
+    for (int y = std::max(0, xy[r] - rec_reach); y <= std::min(ny - 1, xy[r] + rec_reach); ++y)
+      has_rec[(size_t)y] = 1;
   for (int y = 0; y < ny; ++y) {
     // the first step pulls rows y-3 .. y+3 (reading y-4 .. y+4): inside the
     // grid without the wrap, and off rows 0 and ny-1 where walls cut links
@@ -643,8 +655,8 @@ std::vector<Seg> fused_row_segments(const lbm_ctx *c, int g, int rows) {
   return segs;
 }
 
-std::vector<Seg> fused_col_segments(const lbm_ctx *c, int g) {
-  const int nx = c->grids[g].nx, bw = 64 * fused_waves(c);
+std::vector<Seg> fused_col_segments(const lbm_ctx *c, int g, int waves) {
+  const int nx = c->grids[g].nx, bw = 64 * waves;
   const bool px = c->bc[g].edge[LBM_EDGE_LEFT] == LBM_PERIODIC;
   // allowed columns [a, b): with x-wrap all; without, x-5 >= 0 and x+4 <= nx-1
   // for every own column x
@@ -683,15 +695,20 @@ bool source_reaches(const lbm_ctx *c, int g, const Seg &cs, const Seg &rs) {
 // cells, the two rows, columns or corner cells on that side, so that the first
 // general launch leaves f*(t) of every cell the second one reads in the
 // intermediate buffer and the two general launches need nothing from the
-// two-step kernel.
-void build_fused_tiles(const lbm_ctx *c, int rows, std::vector<FusedTileDev> &fused,
-                       std::vector<TileDev> &general, std::vector<TileDev> &general1,
-                       int64_t &fused_cells) {
+// two-step kernel. The adjoint builds its own lists the same way (blocks of
+// `waves` x 64 columns, no receiver within rec_reach rows of an own row) and
+// flags the strips with strip_bit in their grid index. The general kernels
+// reach two rows and columns beyond a cell in both directions, the adjoint's
+// as the forward's, so the same strips serve both.
+void build_fused_tiles(const lbm_ctx *c, int rows, int waves, int rec_reach, int32_t strip_bit,
+                       std::vector<FusedTileDev> &fused, std::vector<TileDev> &general,
+                       std::vector<TileDev> &general1, int64_t &fused_cells) {
   std::vector<FusedTileDev> lf;
   std::vector<TileDev> lg, lh;
   fused_cells = 0;
   for (int g = 0; g < c->nbatch; ++g) {
-    const std::vector<Seg> R = fused_row_segments(c, g, rows), C = fused_col_segments(c, g);
+    const std::vector<Seg> R = fused_row_segments(c, g, rows, rec_reach),
+                           C = fused_col_segments(c, g, waves);
     const int nr = (int)R.size(), nc = (int)C.size();
     const bool px = c->bc[g].edge[LBM_EDGE_LEFT] == LBM_PERIODIC;
     const bool py = c->bc[g].edge[LBM_EDGE_TOP] == LBM_PERIODIC;
@@ -730,7 +747,7 @@ void build_fused_tiles(const lbm_ctx *c, int rows, std::vector<FusedTileDev> &fu
               }
             }
           for (const auto &st : strips)
-            lh.push_back(TileDev{g, std::get<0>(st), std::get<1>(st), std::get<2>(st)});
+            lh.push_back(TileDev{g | strip_bit, std::get<0>(st), std::get<1>(st), std::get<2>(st)});
         } else {
           for (int ys = rs.lo; ys < rs.hi; ys += kSubRows)
             for (int xs = cs.lo; xs < cs.hi; xs += 64)
@@ -780,7 +797,7 @@ int rebuild_tiles(lbm_ctx *c) {
   if (c->launch.fuse_rows > 0) {
     std::vector<FusedTileDev> tf;
     std::vector<TileDev> tg2, tg1;
-    build_fused_tiles(c, c->launch.fuse_rows, tf, tg2, tg1, c->cells_fused);
+    build_fused_tiles(c, c->launch.fuse_rows, fused_waves(c), 0, 0, tf, tg2, tg1, c->cells_fused);
     c->nftiles = (int)tf.size();
     c->ngtiles2 = (int)tg2.size();
     c->ngtiles1 = (int)tg1.size();
@@ -1333,6 +1350,12 @@ int recompute_segment(lbm_ctx *c, int64_t m) {
   return LBM_OK;
 }
 
+// Rows from a two-step adjoint block's own rows to the farthest row whose
+// adjoint state its first step forms (three: the second step's gradient
+// reads rows one out, whose pulls read fh(t) two out, whose gradient reads
+// the first step's rows three out).
+constexpr int kAdjRecReach = 3;
+
 // The adjoint's tile lists: the forward's interior tiles whose rows y0-1 and
 // y1 also hold no receiver, and every other tile. Built from the real tiles
 // of the two (die-ordered, padded) forward lists in their logical order
@@ -1359,18 +1382,84 @@ int build_adjoint_tiles(lbm_ctx *c) {
   };
   std::sort(li.begin(), li.end(), logical);
   std::sort(lg.begin(), lg.end(), logical);
+  auto cover = [&](const std::vector<TileDev> &v, int W) {
+    int64_t n = 0;
+    for (const auto &t : v)
+      if (t.g >= 0) n += (int64_t)std::min(W, c->grids[t.g & ~kStripTile].nx - t.x0) * (t.y1 - t.y0);
+    return n;
+  };
+  c->cells_adj_int = cover(li, 64 * c->launch.waves);
+  c->cells_adj_gen = cover(lg, 64 * c->gen_waves);
   const std::vector<TileDev> ai = order_for_dies(li), ag = order_for_dies(lg);
   c->n_adj_int = (int)ai.size();
   c->n_adj_gen = (int)ag.size();
   HIP_TRY(c->d_adj_int.upload(ai, c->stream));
   HIP_TRY(c->d_adj_gen.upload(ag, c->stream));
+  c->n_adj_f = c->n_adj_g2 = c->n_adj_g1 = 0;
+  c->cells_adj_f = c->cells_adj_g2 = 0;
+  if (c->launch.fuse_rows > 0) {
+    // FP64 blocks of 512 columns would need more than the 168 registers a
+    // lane has at three waves per SIMD: 256 columns
+    c->adj_fwaves = c->dtype == LBM_F64 ? std::min(fused_waves(c), 4) : fused_waves(c);
+    std::vector<FusedTileDev> tf;
+    std::vector<TileDev> tg2, tg1;
+    int64_t cells = 0;
+    build_fused_tiles(c, c->launch.fuse_rows, c->adj_fwaves, kAdjRecReach, kStripTile, tf, tg2,
+                      tg1, cells);
+    if (cells > 0) {
+      c->cells_adj_f = cells;
+      c->cells_adj_g2 = cover(tg2, 64);
+      c->n_adj_f = (int)tf.size();
+      c->n_adj_g2 = (int)tg2.size();
+      c->n_adj_g1 = (int)tg1.size();
+      HIP_TRY(c->d_adj_ftiles.upload(tf, c->stream));
+      HIP_TRY(c->d_adj_g2.upload(tg2, c->stream));
+      HIP_TRY(c->d_adj_g1.upload(tg1, c->stream));
+    }
+  }
   c->adj_tiles_ok = true;
   return LBM_OK;
 }
 
+// With `out`, every adjoint-kernel launch goes directly to the context's
+// stream between a HIP event pair and the mean durations land in *out (the
+// recompute of a segment runs as without, untimed); the adjoint state and
+// dL/dkappa are the same bit for bit.
 template <typename real>
-int adjoint_impl(lbm_ctx *c, int64_t n) {
+int adjoint_impl(lbm_ctx *c, int64_t n, lbm_kernel_times *out = nullptr) {
   auto &A = c->adj;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  double sum[3] = {0.0, 0.0, 0.0};   // interior, general, two-step
+  int64_t cnt[3] = {0, 0, 0};
+  struct EvGuard {
+    hipEvent_t *ev;
+    ~EvGuard() {
+      for (int i = 0; i < 2; ++i)
+        if (ev[i]) hipEventDestroy(ev[i]);
+    }
+  } guard{ev};
+  if (out)
+    for (int i = 0; i < 2; ++i) HIP_TRY(hipEventCreate(&ev[i]));
+  auto timed = [&](int kind, auto &&launch) -> hipError_t {
+    hipError_t e = hipEventRecord(ev[0], c->stream);
+    if (e == hipSuccess) e = launch(c->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+    if (e == hipSuccess) {
+      sum[kind] += ms;
+      cnt[kind] += 1;
+    }
+    return e;
+  };
+  // the two kernels of one launch: overlapped as in a step, or timed in turn
+  auto run = [&](bool has_int, bool has_gen, int kind_int, auto &&general, auto &&interior) {
+    if (!out) return launch_pair(c, c->stream, has_int, has_gen, general, interior);
+    hipError_t e = has_int ? timed(kind_int, interior) : hipSuccess;
+    if (e == hipSuccess && has_gen) e = general(c->stream);
+    return e;
+  };
   if (!c->adj_tiles_ok) {
     int rc = build_adjoint_tiles(c);
     if (rc) return rc;
@@ -1379,7 +1468,8 @@ int adjoint_impl(lbm_ctx *c, int64_t n) {
     HIP_TRY(c->d_adj_io.upload(A.io, c->stream));
     A.io_dirty = false;
   }
-  for (int64_t k = 0; k < n; ++k) {
+  auto stash = [&](int64_t s) { return reinterpret_cast<const real *>(A.stash + (size_t)s * A.cbytes); };
+  for (int64_t k = 0; k < n;) {
     const int64_t t = A.t_adj - 1;
     const int64_t m = (t - A.t_begin) / A.seg;
     if (A.stash_seg != m) {
@@ -1399,19 +1489,64 @@ int adjoint_impl(lbm_ctx *c, int64_t n) {
     a.sources = c->d_src.p;
     a.itab = c->d_itab.p;
     a.rtab = reinterpret_cast<const real *>(c->d_rtab.p);
-    a.rho = reinterpret_cast<const real *>(A.stash + (size_t)(t - tm) * A.cbytes);
+    a.rho = stash(t - tm);
     a.t = t;
     a.omega = (real)(1.0 / c->tau);
     a.cforce = (real)(1.0 - 0.5 / c->tau);
+    if (c->n_adj_f > 0 && n - k >= 2 && t - 1 >= tm) {
+      // Steps t and t-1 of one recomputed segment: g1 takes the general
+      // tiles and the blocks' border strips to fh(t) in the recompute's
+      // first buffer (free until the next segment is recomputed), g2 the
+      // general tiles from there to fh(t-1); the two-step kernel takes its
+      // blocks from fh(t+1) to fh(t-1) directly.
+      real *mid = reinterpret_cast<real *>(A.rbuf[0]);
+      AdjArgs<real> g1 = a, f2 = a, g2 = a;
+      g1.fout = mid;
+      g1.tiles = c->d_adj_g1.p;
+      f2.ftiles = c->d_adj_ftiles.p;
+      f2.rho2 = stash(t - 1 - tm);
+      f2.f_elems = c->L.f_elems;
+      g2.fin = mid;
+      g2.tiles = c->d_adj_g2.p;
+      g2.t = t - 1;
+      g2.rho = stash(t - 1 - tm);
+      HIP_TRY(run(
+          true, c->n_adj_g1 > 0, 2,
+          [&](hipStream_t q) {
+            auto l1 = [&](hipStream_t r) { return launch_adjoint<real>(g1, 1, c->n_adj_g1, r); };
+            auto l2 = [&](hipStream_t r) { return launch_adjoint<real>(g2, 1, c->n_adj_g2, r); };
+            hipError_t e = out ? timed(1, l1) : l1(q);
+            if (e == hipSuccess && c->n_adj_g2 > 0) e = out ? timed(1, l2) : l2(q);
+            return e;
+          },
+          [&](hipStream_t q) { return launch_adjoint_fused2<real>(f2, c->adj_fwaves, c->n_adj_f, q); }));
+      A.cur ^= 1;
+      A.t_adj = t - 1;
+      k += 2;
+      continue;
+    }
     AdjArgs<real> ag = a;
     a.tiles = c->d_adj_int.p;
     ag.tiles = c->d_adj_gen.p;
-    HIP_TRY(launch_pair(
-        c, c->stream, c->n_adj_int > 0, c->n_adj_gen > 0,
-        [&](hipStream_t q) { return launch_adjoint<real>(ag, c->gen_waves, c->n_adj_gen, q); },
+    HIP_TRY(run(
+        c->n_adj_int > 0, c->n_adj_gen > 0, 0,
+        [&](hipStream_t q) {
+          auto lg = [&](hipStream_t r) { return launch_adjoint<real>(ag, c->gen_waves, c->n_adj_gen, r); };
+          return out ? timed(1, lg) : lg(q);
+        },
         [&](hipStream_t q) { return launch_adjoint_interior<real>(a, c->launch.waves, c->n_adj_int, q); }));
     A.cur ^= 1;
     A.t_adj = t;
+    k += 1;
+  }
+  if (out) {
+    out->steps = n;
+    out->interior_ms = cnt[0] ? sum[0] / (double)cnt[0] : 0.0;
+    out->general_ms = cnt[1] ? sum[1] / (double)cnt[1] : 0.0;
+    out->fused_ms = cnt[2] ? sum[2] / (double)cnt[2] : 0.0;
+    out->interior_cells = c->cells_adj_int;
+    out->general_cells = cnt[2] ? c->cells_adj_g2 : c->cells_adj_gen;
+    out->fused_cells = cnt[2] ? c->cells_adj_f : 0;
   }
   return LBM_OK;
 }
@@ -2195,6 +2330,24 @@ int lbm_adjoint_step(lbm_ctx *c, int64_t n) {
   rc = commit(c);
   if (rc) return rc;
   return c->dtype == LBM_F64 ? adjoint_impl<double>(c, n) : adjoint_impl<float>(c, n);
+}
+
+int lbm_adjoint_step_timed(lbm_ctx *c, int64_t n, lbm_kernel_times *out) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!out) return fail(LBM_E_INVALID, "out is null");
+  auto &A = c->adj;
+  if (!A.begun) return fail(LBM_E_STATE, "call lbm_adjoint_begin first");
+  if (A.taken < A.nseg || c->t < A.t_begin + A.nsteps)
+    return fail(LBM_E_STATE, "the recorded forward run has not reached its last step yet");
+  if (n < 0 || n > A.t_adj - A.t_begin) return fail(LBM_E_INVALID, "n must be in [0, adjoint time - start time]");
+  rc = commit(c);
+  if (rc) return rc;
+  if (n == 0) {
+    *out = lbm_kernel_times{};
+    return LBM_OK;
+  }
+  return c->dtype == LBM_F64 ? adjoint_impl<double>(c, n, out) : adjoint_impl<float>(c, n, out);
 }
 
 int lbm_adjoint_time(const lbm_ctx *c, int64_t *t) {

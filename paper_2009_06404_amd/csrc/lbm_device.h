@@ -129,6 +129,13 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t tile_rsrc(const void *base) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, 0x7fffffff, 0x00020000);
 }
 
+// Buffer descriptor covering [base, base + bytes) (capped at 4 GiB - 1):
+// accesses past the end read zero and drop their stores instead of faulting.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t range_rsrc(const void *base, uint64_t bytes) {
+  const uint32_t n = bytes > 0xffffffffull ? 0xffffffffu : (uint32_t)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)n, 0x00020000);
+}
+
 template <typename real>
 struct Buf;
 

@@ -116,6 +116,11 @@ struct AdjArgs {
   const real *rho;        // rho(t) of every cell (stash layout), for the gradient
   int64_t t;
   real omega, cforce;
+  // two adjoint steps per pass (adjoint_fused2_kernel): its blocks, rho(t-1)
+  // of every cell, and the size of one population buffer (elements)
+  const FusedTileDev *ftiles;
+  const real *rho2;
+  int64_t f_elems;
 };
 
 template <typename real>
@@ -124,6 +129,17 @@ hipError_t launch_adjoint(const AdjArgs<real> &a, int waves, int ntiles, hipStre
 template <typename real>
 hipError_t launch_adjoint_interior(const AdjArgs<real> &a, int waves, int ntiles,
                                    hipStream_t stream);
+// Two adjoint steps (t and t-1) of the blocks a.ftiles in one pass, from
+// fh(t+1) in a.fin to fh(t-1) in a.fout, with rho(t) in a.rho and rho(t-1)
+// in a.rho2; blocks of 64 * waves columns (waves 2, 4 or 8).
+template <typename real>
+hipError_t launch_adjoint_fused2(const AdjArgs<real> &a, int waves, int ntiles,
+                                 hipStream_t stream);
+// Tiles of the first general launch of an adjoint pair that are border
+// strips of two-step blocks carry this bit in their grid index: they advance
+// the adjoint state only, the gradients of their cells being the two-step
+// kernel's.
+constexpr int32_t kStripTile = 1 << 30;
 template <typename real>
 hipError_t launch_misfit(const real *trace, const real *d_obs, real *residual, int64_t n,
                          double *misfit, hipStream_t stream);

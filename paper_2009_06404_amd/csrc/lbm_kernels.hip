@@ -695,13 +695,6 @@ __global__ __launch_bounds__(64 * NW) void interior2_kernel(StepArgs<real> a) {
 }
 
 
-// Buffer descriptor covering [base, base + bytes) (capped at 4 GiB - 1):
-// accesses past the end read zero and drop their stores instead of faulting.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t range_rsrc(const void *base, uint64_t bytes) {
-  const uint32_t n = bytes > 0xffffffffull ? 0xffffffffu : (uint32_t)bytes;
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)n, 0x00020000);
-}
-
 // Two time steps of an interior tile in one pass (temporal blocking). The
 // workgroup marches down the tile's rows with a four-stage pipeline:
 //   A (row r):   pull f(t) from f*(t-1) in HBM (row r+1 already in flight),
@@ -794,7 +787,12 @@ __global__ __launch_bounds__(64 * NW + 64, sizeof(real) == 4 ? (STASH ? 4 : 5) :
   sponge_x(a.sponge, g, col, A_x, inv_x);
   const bool kcells = g.kmode == kKappaCells;
   const real kscalar = (real)g.kscalar;
-  const real *kcol = a.kappa_cells + g.k_off + col;
+  // the cell-wise moduli from row ybase on (an empty range for the other
+  // kinds of medium: their loads return 0, with no branch around them, which
+  // would end in a wait for every load in flight)
+  const __amdgpu_buffer_rsrc_t rk = range_rsrc(
+      a.kappa_cells + (kcells ? g.k_off + (int64_t)ybase * pitch : 0),
+      kcells ? (uint64_t)(g.ny - ybase) * pitch * sizeof(real) : 0);
   const bool inB = lc >= 1 && lc <= w + 6, inC = lc >= 2 && lc <= w + 5;
   __syncthreads();
 
@@ -835,7 +833,7 @@ __global__ __launch_bounds__(64 * NW + 64, sizeof(real) == 4 ? (STASH ? 4 : 5) :
         int rn = r + 1;
         asm volatile("" : "+s"(rn));
         pull_fast(rin, ybase, rn, rowb, qb, o0, ol, orr, fc);
-        if (kcells) kn = kcol[(int64_t)rn * pitch];
+        kn = Buf<real>::load(rk, o0, (uint32_t)(rn - ybase) * qb);
       }
     } else {
       // After the first round every lane loads a row on every iteration
@@ -845,7 +843,7 @@ __global__ __launch_bounds__(64 * NW + 64, sizeof(real) == 4 ? (STASH ? 4 : 5) :
       int rn = min(r + 1, rlast);
       asm volatile("" : "+s"(rn));
       pull_fast(rin, ybase, rn, rowb, qb, o0, ol, orr, fc);
-      if (kcells) kn = kcol[(int64_t)rn * pitch];
+      kn = Buf<real>::load(rk, o0, (uint32_t)(rn - ybase) * qb);
     }
     // Stage A: row r of step t.
     rA_n = real(0);

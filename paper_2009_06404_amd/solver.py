@@ -176,6 +176,10 @@ class Solver:
     def adjoint_step(self, n: int) -> None:
         L.lbm_adjoint_step(self.ctx, n)
 
+    def adjoint_step_timed(self, n: int) -> dict:
+        """n adjoint steps with per-kernel event timing (synchronous)."""
+        return L.lbm_adjoint_step_timed(self.ctx, n)
+
     @property
     def adjoint_time(self) -> int:
         return L.lbm_adjoint_time(self.ctx)

@@ -71,6 +71,7 @@ def run(probs, T, seg, dtype, launch=None, chunks=None):
         lc.update(launch)
         L.lbm_set_launch(ctx, **lc)
     ab = L.lbm_adjoint_workspace_bytes(ctx, seg, T)
+    adj_before = sim.sim_adjoint_pairs_checked()
     aws = dev(np.zeros(ab + 512, np.uint8))
     L.lbm_adjoint_begin(ctx, seg, T, (aws.ctypes.data + 255) // 256 * 256, ab)
     L.lbm_step(ctx, T)
@@ -79,8 +80,12 @@ def run(probs, T, seg, dtype, launch=None, chunks=None):
         gk = dev(np.zeros((p.ny, p.nx)))
         ga = dev(np.zeros(max(len(p.sources), 1)))
         L.lbm_adjoint_set_io(ctx, g, res.ctypes.data, gk.ctypes.data, ga.ctypes.data)
-    for n in (chunks or [T]):
-        L.lbm_adjoint_step(ctx, n)
+    for i, n in enumerate(chunks or [T]):
+        if i % 2:
+            kt = L.lbm_adjoint_step_timed(ctx, n)
+            assert kt["steps"] == n, kt
+        else:
+            L.lbm_adjoint_step(ctx, n)
     for g, p in enumerate(probs):
         out = dev(np.zeros((9, p.ny, p.nx), npdt))
         L.lbm_adjoint_get_state(ctx, g, out.ctypes.data)
@@ -88,9 +93,11 @@ def run(probs, T, seg, dtype, launch=None, chunks=None):
         L.lbm_moments(ctx, g, mom.ctypes.data)
         L.lbm_get_state(ctx, g, out.ctypes.data)
     L.lbm_destroy(ctx)
+    return sim.sim_adjoint_pairs_checked() - adj_before
 
 
 sim.sim_pairs_checked.restype = C.c_int64
+sim.sim_adjoint_pairs_checked.restype = C.c_int64
 
 
 def run_forward(probs, T, launch, steps=(5, 1, 8), tune=None):
@@ -150,7 +157,9 @@ for dtype in ("f64", "f32"):
                       receivers=[(x, 0) for x in range(0, 300, 5)] + [(x, 101) for x in range(3, 300, 11)])
         for launch in (dict(waves=1, rows=4), dict(waves=2, rows=8), dict(waves=8, rows=2),
                        dict(waves=2, rows=8, fuse_rows=6)):
-            run([big], 20, 8, dtype, launch=launch)
+            apairs = run([big], 20, 8, dtype, launch=launch)
+            # adjoint pairs on the two-step path: in every segment of 8 steps
+            assert (apairs > 0) == ("fuse_rows" in launch), (launch, apairs)
         print("ok", name, dtype, flush=True)
     run([problem(CASES[1][1], 20, 150, 37, 3), problem(CASES[3][1], -1, 64, 65, 4)], 18, 5, dtype,
         launch=dict(waves=2, rows=4), chunks=[7, 11])
@@ -185,6 +194,24 @@ lines = open(cache).read().splitlines()
 assert len(lines) == 2 and lines[0].startswith("sim f32 ") and " pairs|" in lines[0], lines
 assert " single|" in lines[1], lines
 print("ok autotune", flush=True)
+
+# adjoint pairs: blocks of 128, 256 and 512 columns (256 in FP64), segments of
+# odd and even lengths (a pair never spans two), adjoint steps taken in odd
+# chunks, batched grids; every pair writes each cell once and its second
+# general step reads only cells its first wrote
+for dtype in ("f32", "f64"):
+    for name, bc, rr, nx, ny in FUSED:
+        p = problem(bc, rr, nx, ny, 11, sources=[Source(nx * 0.7, ny * 0.5, 2.0, 0.3, 0.9, 1.0, 12.0, 16.0)],
+                    receivers=[(x, 0) for x in range(0, nx, 5)] + [(x, 77) for x in range(3, nx, 11)])
+        for fr, waves, seg, chunks in ((4, 2, 7, [5, 3, 9, 4]), (13, 4, 8, [21]), (8, 8, 5, [1, 2, 18])):
+            apairs = run([p], 21, seg, dtype, launch=dict(waves=waves, rows=8, fuse_rows=fr),
+                         chunks=chunks)
+            assert apairs > 0, (name, dtype, fr, waves, apairs)
+    apairs = run([problem(FUSED[1][1], 40, 530, 90, 6), problem(FUSED[0][1], -1, 300, 64, 7),
+                  problem(FUSED[2][1], -1, 1100, 50, 8)], 16, 6, dtype,
+                 launch=dict(waves=2, rows=4, fuse_rows=6, overlap=0), chunks=[3, 13])
+    assert apairs > 0, apairs
+    print("ok adjoint pairs", dtype, flush=True)
 
 
 def init_only(nx, ny, code, npdt):

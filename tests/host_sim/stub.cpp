@@ -74,8 +74,9 @@ static void check_tiles(const TileDev *tiles, int ntiles, const GridDev *grids, 
                         const char *what) {
   check_range(tiles, sizeof(TileDev) * ntiles, what);
   for (int i = 0; i < ntiles; ++i) {
-    const TileDev t = tiles[i];
+    TileDev t = tiles[i];
     if (t.g < 0) continue;   // padding entries: the kernels return at once
+    t.g &= ~kStripTile;      // the adjoint's border strips
     check_range(&grids[t.g], sizeof(GridDev), "grid desc");
     const GridDev &g = grids[t.g];
     if (t.x0 < 0 || t.x0 >= g.nx || t.y0 < 0 || t.y1 > g.ny || t.y0 >= t.y1) { fprintf(stderr, "bad tile %s\n", what); abort(); }
@@ -274,13 +275,57 @@ hipError_t launch_filter(const real *fin, real *fout, const GridDev *grids, cons
   }
   return hipSuccess;
 }
+// Adjoint pairs, checked as the forward's: the general kernel's first step
+// (g1, its tile list holding the blocks' border strips) writes the
+// intermediate buffer, its second (g2) reads only cells within two of its
+// tiles that g1 wrote, and the two-step kernel (f2) plus g2 write every cell
+// of every grid exactly once.
+static int64_t g_adj_g1_seq = -10;
+static const void *g_adj_mid = nullptr;
+static bool g_adj_seen_f2 = false, g_adj_seen_g2 = false;
+static std::map<int, std::vector<int>> g_adj_cov;
+static int g_adj_ngrids = 0;
+static int64_t g_adj_pairs_checked = 0;
+static std::vector<int> &adj_cov(int g, const GridDev &G) {
+  std::vector<int> &v = g_adj_cov[g];
+  if (v.empty()) v.assign((size_t)G.nx * G.ny, 0);
+  return v;
+}
+static void adj_pair_check_done() {
+  if (!(g_adj_seen_f2 && g_adj_seen_g2)) return;
+  for (int g = 0; g < g_adj_ngrids; ++g) {
+    const std::vector<int> &v = g_adj_cov[g];
+    for (size_t i = 0; i < v.size(); ++i)
+      if (v[i] != 1) {
+        fprintf(stderr, "adjoint pair wrote cell %zu of grid %d %d times\n", i, g, v[i]);
+        abort();
+      }
+  }
+  g_adj_cov.clear();
+  g_adj_seen_f2 = g_adj_seen_g2 = false;
+  ++g_adj_pairs_checked;
+}
+extern "C" int64_t sim_adjoint_pairs_checked() { adj_pair_check_done(); return g_adj_pairs_checked; }
+
 template <typename real>
 static hipError_t adj_common(const AdjArgs<real> &a, int waves, int ntiles, bool interior) {
   if (ntiles <= 0) return hipSuccess;
   check_tiles<real>(a.tiles, ntiles, a.grids, 64 * waves, interior, interior ? "adj int tiles" : "adj gen tiles");
+  const int64_t seq = g_seq++;
+  bool strips = false;
+  for (int i = 0; i < ntiles; ++i) strips = strips || (a.tiles[i].g >= 0 && (a.tiles[i].g & kStripTile));
+  if (strips && interior) { fprintf(stderr, "border strips in the interior adjoint list\n"); abort(); }
+  if (strips) {
+    g_adj_g1_seq = seq;
+    g_adj_mid = a.fout;
+  }
+  const bool second = !interior && g_adj_mid && (const void *)a.fin == g_adj_mid;
+  if (second && g_adj_seen_g2) { fprintf(stderr, "two second adjoint steps in one pair\n"); abort(); }
+  const int W = 64 * waves;
   for (int i = 0; i < ntiles; ++i) {
-    const TileDev t = a.tiles[i];
+    TileDev t = a.tiles[i];
     if (t.g < 0) continue;
+    t.g &= ~kStripTile;
     const GridDev &g = a.grids[t.g];
     check_range(&a.io[t.g], sizeof(AdjGridDev), "adj io");
     const AdjGridDev io = a.io[t.g];
@@ -290,6 +335,30 @@ static hipError_t adj_common(const AdjArgs<real> &a, int waves, int ntiles, bool
     if (io.grad_kappa) check_range(io.grad_kappa, sizeof(double) * (size_t)g.nx * g.ny, "grad_kappa");
     if (io.grad_amp && g.nsrc) check_range(io.grad_amp, sizeof(double) * (g.nsrc < kMaxAdjSources ? g.nsrc : kMaxAdjSources), "grad_amp");
     if (io.residual && g.nrec) check_range(io.residual, sizeof(real) * (size_t)g.trace_max * g.nrec * g.ncomp, "residual");
+    std::vector<int64_t> &out = stamps(a.fout, t.g, g);
+    std::vector<int64_t> *mid = second ? &stamps(g_adj_mid, t.g, g) : nullptr;
+    const bool px = g.bc[kEdgeLeft] == kPeriodic, py = g.bc[kEdgeTop] == kPeriodic;
+    for (int y = t.y0; y < t.y1; ++y)
+      for (int x = t.x0; x < t.x0 + W && x < g.nx; ++x) {
+        out[(size_t)y * g.nx + x] = seq;
+        if (!second) continue;
+        adj_cov(t.g, g)[(size_t)y * g.nx + x] += 1;
+        for (int dy = -2; dy <= 2; ++dy)
+          for (int dx = -2; dx <= 2; ++dx) {
+            int xx = x + dx, yy = y + dy;
+            if (xx < 0 || xx >= g.nx) { if (!px) continue; xx = (xx + g.nx) % g.nx; }
+            if (yy < 0 || yy >= g.ny) { if (!py) continue; yy = (yy + g.ny) % g.ny; }
+            if ((*mid)[(size_t)yy * g.nx + xx] < g_adj_g1_seq) {
+              fprintf(stderr, "second adjoint step reads a cell the first did not write: g=%d (%d,%d) from (%d,%d)\n",
+                      t.g, xx, yy, x, y);
+              abort();
+            }
+          }
+      }
+  }
+  if (second) {
+    g_adj_seen_g2 = true;
+    adj_pair_check_done();
   }
   return hipSuccess;
 }
@@ -297,6 +366,66 @@ template <typename real>
 hipError_t launch_adjoint(const AdjArgs<real> &a, int waves, int ntiles, hipStream_t) { return adj_common(a, waves, ntiles, false); }
 template <typename real>
 hipError_t launch_adjoint_interior(const AdjArgs<real> &a, int waves, int ntiles, hipStream_t) { return adj_common(a, waves, ntiles, true); }
+template <typename real>
+hipError_t launch_adjoint_fused2(const AdjArgs<real> &a, int waves, int ntiles, hipStream_t) {
+  if (ntiles <= 0) return hipSuccess;
+  if (waves != 2 && waves != 4 && waves != 8) { fprintf(stderr, "adjoint two-step waves %d\n", waves); abort(); }
+  if (sizeof(real) == 8 && waves == 8) { fprintf(stderr, "FP64 adjoint two-step blocks of 512 columns\n"); abort(); }
+  const int W = 64 * waves;
+  check_range(a.ftiles, sizeof(FusedTileDev) * ntiles, "adjoint fused tiles");
+  g_adj_ngrids = 0;
+  for (int64_t fe = 0; fe < a.f_elems; ++g_adj_ngrids)
+    fe = a.grids[g_adj_ngrids].f_off + 9 * (int64_t)a.grids[g_adj_ngrids].pitch * a.grids[g_adj_ngrids].ny;
+  if (g_adj_seen_f2) { fprintf(stderr, "two adjoint two-step launches in one pair\n"); abort(); }
+  const int64_t seq = g_seq++;
+  for (int g = 0; g < g_adj_ngrids; ++g) adj_cov(g, a.grids[g]);
+  for (int i = 0; i < ntiles; ++i) {
+    const FusedTileDev t = a.ftiles[i];
+    if (t.g < 0) continue;
+    if (t.g >= g_adj_ngrids) { fprintf(stderr, "adjoint fused tile grid %d out of range\n", t.g); abort(); }
+    const GridDev &g = a.grids[t.g];
+    if (t.x0 < 0 || t.x1 > g.nx || t.x1 <= t.x0 || t.x1 - t.x0 > W || t.y0 - 4 < 0 ||
+        t.y1 + 3 > g.ny - 1 || t.y0 >= t.y1 || t.y1 - t.y0 > kFusedMaxRows) {
+      fprintf(stderr, "bad adjoint fused tile g=%d x0=%d x1=%d y0=%d y1=%d\n", t.g, t.x0, t.x1, t.y0, t.y1);
+      abort();
+    }
+    check_pop(a.fin, g, "adj fused fin");
+    check_pop(a.fout, g, "adj fused fout");
+    check_range(a.rho + g.c_off, sizeof(real) * (size_t)g.pitch * g.ny, "adj fused rho(t)");
+    check_range(a.rho2 + g.c_off, sizeof(real) * (size_t)g.pitch * g.ny, "adj fused rho(t-1)");
+    check_range(&a.io[t.g], sizeof(AdjGridDev), "adj io");
+    if (a.io[t.g].grad_kappa) check_range(a.io[t.g].grad_kappa, sizeof(double) * (size_t)g.nx * g.ny, "grad_kappa");
+    // what the kernel does not handle lies outside its reach: walls and the
+    // rigid row among the pulled rows and columns, receivers within three
+    // rows of an own row, source disks over its own cells
+    const int rr = g.rigid_row;
+    if (rr > 0 && t.y0 - 3 <= rr && t.y1 + 2 >= rr - 1) { fprintf(stderr, "adjoint fused tile pulls across the rigid row\n"); abort(); }
+    const bool px = g.bc[kEdgeLeft] == kPeriodic, py = g.bc[kEdgeTop] == kPeriodic;
+    if (!px && (t.x0 - 5 < 0 || t.x1 + 4 > g.nx - 1)) { fprintf(stderr, "adjoint fused tile pulls across a side wall\n"); abort(); }
+    if (g.nrec > 0)
+      for (int y = t.y0 - 3; y <= t.y1 + 2; ++y)
+        if (a.itab[g.rowtab_off + y] >= 0) { fprintf(stderr, "receiver row %d within reach of an adjoint fused tile\n", y); abort(); }
+    for (int si = 0; si < g.nsrc; ++si) {
+      const SourceDev q = a.sources[g.src_off + si];
+      for (int y = t.y0; y < t.y1; ++y)
+        for (int x = t.x0; x < t.x1; ++x) {
+          double dx = x - q.x, dy = y - q.y;
+          if (px) { if (dx > 0.5 * g.nx) dx -= g.nx; else if (dx < -0.5 * g.nx) dx += g.nx; }
+          if (py) { if (dy > 0.5 * g.ny) dy -= g.ny; else if (dy < -0.5 * g.ny) dy += g.ny; }
+          if (dx * dx + dy * dy <= 81.0 * q.sigma * q.sigma) { fprintf(stderr, "source reaches an adjoint fused tile\n"); abort(); }
+        }
+    }
+    std::vector<int64_t> &out = stamps(a.fout, t.g, g);
+    for (int y = t.y0; y < t.y1; ++y)
+      for (int x = t.x0; x < t.x1; ++x) {
+        adj_cov(t.g, g)[(size_t)y * g.nx + x] += 1;
+        out[(size_t)y * g.nx + x] = seq;
+      }
+  }
+  g_adj_seen_f2 = true;
+  adj_pair_check_done();
+  return hipSuccess;
+}
 template <typename real>
 hipError_t launch_misfit(const real *tr, const real *d, real *r, int64_t n, double *m, hipStream_t) {
   check_range(tr, n * sizeof(real), "misfit tr"); check_range(d, n * sizeof(real), "misfit d");
@@ -383,6 +512,7 @@ hipError_t launch_add_time(int64_t *t, int64_t v, hipStream_t) { check_range(t, 
   template hipError_t launch_filter<real>(const real *, real *, const GridDev *, const TileDev *, int, real, hipStream_t); \
   template hipError_t launch_adjoint<real>(const AdjArgs<real> &, int, int, hipStream_t); \
   template hipError_t launch_adjoint_interior<real>(const AdjArgs<real> &, int, int, hipStream_t); \
+  template hipError_t launch_adjoint_fused2<real>(const AdjArgs<real> &, int, int, hipStream_t); \
   template hipError_t launch_misfit<real>(const real *, const real *, real *, int64_t, double *, hipStream_t); \
   template hipError_t launch_lame_gradient<real>(const real *, const real *, const double *, double *, double *, int64_t, hipStream_t); \
   template hipError_t launch_kappa<real>(const real *, const real *, const real *, int, int, int, real *, int *, int *, hipStream_t); \

@@ -136,11 +136,11 @@ def test_two_step_timed_steps_equal_plain_steps(dtype):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_adjoint_with_two_step_forward(dtype):
-    """The adjoint's recorded forward and its recompute may run on the
-    two-step path (pairs, and single steps up to each checkpoint; the
-    recompute also stashes rho of both steps of a pair): the checkpoints,
-    traces, adjoint state and dL/dkappa equal those of single steps bit for
-    bit."""
+    """The adjoint's recorded forward, its recompute and the adjoint steps
+    themselves may run on the two-step path (pairs, and single steps up to
+    each checkpoint; the recompute also stashes rho of both steps of a pair):
+    the checkpoints, traces, adjoint state and dL/dkappa equal those of
+    single steps bit for bit."""
     from test_gpu_adjoint import _gpu_adjoint, _problem
     p = _problem((BC_FREE0, BC_RIGID, BC_PERIODIC, BC_PERIODIC), -1, nx=600, ny=90, seed=5)
     T = 31
