@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 METRIC = "GLUPS (D2Q9 cell updates/s) and % HBM roofline; batched & adjoint vs plain"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_2009_06404_amd/csrc/lbm_kernels.hip",
+                  "paper_2009_06404_amd/csrc/lbm_adjoint.hip",
                   "paper_2009_06404_amd/csrc/lbm_device.h",
                   "paper_2009_06404_amd/csrc/lbm_internal.h")
 FUSED_KERNEL = "fused2_kernel"
@@ -453,6 +454,7 @@ def bench_adjoint(torch, w, Solver, plain_glups: float, nsteps: int = 5000,
     t_all = e0.elapsed_time(e2)
     ok = bool(torch.isfinite(gl).all().item() and torch.isfinite(gm).all().item())
     misfit = float(sum(m.item() for m in mis))
+    kernels = adjoint_kernel_roofline(torch, s, seg)
     s.close()
     cells = G * n * n
     g_rate = cells * nsteps / (t_all / 1e3) / 1e9
@@ -460,9 +462,53 @@ def bench_adjoint(torch, w, Solver, plain_glups: float, nsteps: int = 5000,
                         f"checkpoints every {seg}", "gradient_GLUPS": round(g_rate, 3),
             "ms_total": round(t_all, 1), "ms_forward_recorded": round(t_fwd, 1),
             "vs_plain": round(g_rate / plain_glups, 4), "misfit": misfit,
-            "gradients_finite": ok,
+            "gradients_finite": ok, "adjoint_kernels": kernels,
             "note": "gradient_GLUPS = cell-steps of the forward per second of forward + "
                     "misfit + adjoint (with recompute) + Lame gradients"}
+
+
+# Algorithmic bytes per cell and launch of the adjoint kernels (FP32, cell-wise
+# moduli, dL/dkappa asked): the two-step kernel reads fh(t+1) and writes
+# fh(t-1) (9 + 9 words), reads rho(t), rho(t-1) and kappa (3 words) and
+# reads and writes dL/dkappa (FP64, 16 B); the single-step interior kernel
+# reads fh(t+1), writes fh(t) (18 words), reads rho(t) and kappa (2 words)
+# and dL/dkappa (16 B).
+ADJ_FUSED_BYTES = 21 * 4 + 16
+ADJ_INTERIOR_BYTES = 20 * 4 + 16
+
+
+def adjoint_kernel_roofline(torch, s, seg: int, nsteps: int = 400, timed: int = 200) -> dict:
+    """Per-launch event timing of the adjoint kernels (lbm_adjoint_step_timed)
+    over the last `timed` adjoint steps of a fresh recording of `nsteps` steps
+    on the same context, and their HBM roofline on algorithmic bytes."""
+    n_g = len(s.problems)
+    gk = [torch.zeros((p.ny, p.nx), dtype=torch.float64, device="cuda") for p in s.problems]
+    s.adjoint_begin(nsteps, seg)
+    s.step(nsteps)
+    for g in range(n_g):
+        r = torch.randn_like(s.traces[g])
+        s.adjoint_set_io(g, r, gk[g], None)
+    s.adjoint_step(nsteps - timed)
+    torch.cuda.synchronize()
+    kt = s.adjoint_step_timed(timed)
+    out = {"timed_steps": kt["steps"]}
+    for name, cells, ms, per_cell, steps in (
+            ("adjoint_fused2_kernel", kt["fused_cells"], kt["fused_ms"], ADJ_FUSED_BYTES, 2),
+            ("adjoint_interior_kernel", kt["interior_cells"], kt["interior_ms"],
+             ADJ_INTERIOR_BYTES, 1)):
+        if cells <= 0 or ms <= 0:
+            continue
+        achieved = per_cell * cells / (ms / 1e3) / 1e9
+        n = s.problems[0].nx
+        out[name] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(traffic_file(name, f"adjoint_shots_{n}", "f32"),
+                                                 cells),
+                     "bytes_per_cell": per_cell, "cells_per_launch": cells,
+                     "steps_per_launch": steps, "ms_per_launch": round(ms, 5)}
+    out["adjoint_kernel_general"] = {"cells_per_launch": kt["general_cells"],
+                                     "ms_per_launch": round(kt["general_ms"], 5)}
+    return out
 
 
 def main():

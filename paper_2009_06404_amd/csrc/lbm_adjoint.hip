@@ -156,7 +156,7 @@ template <typename real, int NW>
 __global__ __launch_bounds__(64 * NW) void adjoint_kernel(AdjArgs<real> a) {
   constexpr int W = 64 * NW;
   __shared__ real sq[2][W + 2];
-  __shared__ double samp[kMaxAdjSources];
+  __shared__ double samp[NW][kMaxAdjSources];   // each wavefront's dL/damp sums
 
   const TileDev tile = a.tiles[blockIdx.x];
   if (tile.g < 0) return;
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(64 * NW) void adjoint_kernel(AdjArgs<real> a) {
   const real omega = a.omega, cforce = a.cforce;
   const bool px = g.bc[kEdgeLeft] == kPeriodic, py = g.bc[kEdgeTop] == kPeriodic;
   const int nsrc = io.grad_amp ? min(g.nsrc, kMaxAdjSources) : 0;
-  if (lane < kMaxAdjSources) samp[lane] = 0.0;
+  if ((lane & 63) < kMaxAdjSources) samp[lane >> 6][lane & 63] = 0.0;
 
   // Twice the weights of the transposed gradient from the x-neighbours: 1
   // (weight 1/2), or 2 from a neighbour on a rigid side edge (its one-sided
@@ -378,7 +378,7 @@ __global__ __launch_bounds__(64 * NW) void adjoint_kernel(AdjArgs<real> a) {
         v = exp(-r2 / (2.0 * sd.sigma * sd.sigma)) * ricker((double)t, sd.period, sd.t0) *
             ((double)gx_c * sd.dir_x + (double)gy_c * sd.dir_y);
       for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-      if ((lane & 63) == 0) atomicAdd(&samp[si], v);
+      if ((lane & 63) == 0) samp[lane >> 6][si] += v;
     }
 
     // March: row y+1 becomes current.
@@ -396,7 +396,16 @@ __global__ __launch_bounds__(64 * NW) void adjoint_kernel(AdjArgs<real> a) {
     }
     rc = rn;
   }
-  if (lane < nsrc && samp[lane] != 0.0) atomicAdd(io.grad_amp + lane, samp[lane]);
+  // The workgroup's dL/damp of this step, wavefronts summed in order, to its
+  // slot of the partial sums (added to dL/damp in a fixed order by
+  // amp_reduce_kernel: no atomics, so the result does not depend on the
+  // order in which workgroups finish).
+  if (lane < nsrc) {
+    double sum = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) sum += samp[w][lane];
+    a.amp_part[(int64_t)blockIdx.x * kMaxAdjSources + lane] = sum;
+  }
 }
 
 // Transposed pull of an interior row (no wall, no wrap in y): ah_k(x) =
@@ -588,7 +597,10 @@ __global__ __launch_bounds__(64 * NW + 64, sizeof(real) == 4 ? 4 : 2) void adjoi
   const bool live = lc >= 0 && lc < w + 8;
   const bool outlane = tid < w;
   auto wrapx = [&](int c) { return c < 0 ? c + nx : (c >= nx ? c - nx : c); };
-  const int col = live ? wrapx(tile.x0 - 4 + lc) : 0;
+  // the lanes outside the block's columns (the halo wavefront's last 56, the
+  // lanes past a narrow block) load a live lane's column: their unconditional
+  // loads then touch no line the block does not need
+  const int col = wrapx(tile.x0 - 4 + min(max(lc, 0), w + 7));
   const uint32_t esz = sizeof(real);
   const uint32_t o0 = (uint32_t)col * esz;
   const uint32_t ol = (uint32_t)wrapx(col - 1) * esz;
@@ -816,13 +828,45 @@ __global__ __launch_bounds__(64 * NW + 64, sizeof(real) == 4 ? 4 : 2) void adjoi
   }
 }
 
+// Sum of v over a 256-thread workgroup in a fixed order (wavefront shuffles,
+// then the four wavefronts' sums in order); the result in thread 0.
+__device__ __forceinline__ double block_sum_256(double v, double *s4) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0) s4[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return ((s4[0] + s4[1]) + s4[2]) + s4[3];
+}
+
+// dL/damp of one (grid, source) per workgroup: the partial sums of the
+// general kernel's workgroups that cover the grid (their slots listed in
+// tiles[off[k] .. off[k+1])), added in that order.
+__global__ __launch_bounds__(256) void amp_reduce_kernel(const double *__restrict__ part,
+                                                         const int32_t *__restrict__ tiles,
+                                                         const int32_t *__restrict__ off,
+                                                         const int32_t *__restrict__ pairs,
+                                                         const AdjGridDev *__restrict__ io) {
+  __shared__ double s4[4];
+  const int k = blockIdx.x;
+  const int g = pairs[2 * k], si = pairs[2 * k + 1];
+  double *out = io[g].grad_amp;
+  if (!out) return;
+  double v = 0.0;
+  for (int i = off[k] + (int)threadIdx.x; i < off[k + 1]; i += 256)
+    v += part[(int64_t)tiles[i] * kMaxAdjSources + si];
+  v = block_sum_256(v, s4);
+  if (threadIdx.x == 0) out[si] += v;
+}
+
 // Residual e = v - d of one grid's traces and the misfit L += 1/2 sum e^2,
-// accumulated in FP64: wavefront shuffles, then one atomic add per wavefront.
+// accumulated in FP64 in a fixed order: each workgroup's sum to part[], then
+// misfit_sum_kernel adds them in order (no atomics, so the result does not
+// depend on the order in which workgroups finish).
 template <typename real>
 __global__ __launch_bounds__(256) void misfit_kernel(const real *__restrict__ trace,
                                                      const real *__restrict__ d_obs,
                                                      real *__restrict__ residual, int64_t n,
-                                                     double *misfit) {
+                                                     double *__restrict__ part) {
+  __shared__ double s4[4];
   double acc = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
@@ -830,8 +874,17 @@ __global__ __launch_bounds__(256) void misfit_kernel(const real *__restrict__ tr
     if (residual) residual[i] = e;
     acc += (double)e * (double)e;
   }
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if ((threadIdx.x & 63) == 0 && acc != 0.0) atomicAdd(misfit, 0.5 * acc);
+  acc = block_sum_256(acc, s4);
+  if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+__global__ __launch_bounds__(256) void misfit_sum_kernel(const double *__restrict__ part, int nb,
+                                                         double *misfit) {
+  __shared__ double s4[4];
+  double v = 0.0;
+  for (int i = (int)threadIdx.x; i < nb; i += 256) v += part[i];
+  v = block_sum_256(v, s4);
+  if (threadIdx.x == 0) *misfit += 0.5 * v;
 }
 
 // dL/dlambda and dL/dmu from dL/dkappa with kappa = b^2 (mu - lambda)/mu
@@ -894,12 +947,23 @@ hipError_t launch_adjoint_fused2(const AdjArgs<real> &a, int waves, int ntiles, 
   return hipGetLastError();
 }
 
+hipError_t launch_amp_reduce(const double *part, const int32_t *tiles, const int32_t *off,
+                             const int32_t *pairs, int npairs, const AdjGridDev *io,
+                             hipStream_t stream) {
+  if (npairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(amp_reduce_kernel, dim3(npairs), dim3(256), 0, stream, part, tiles, off,
+                     pairs, io);
+  return hipGetLastError();
+}
+
 template <typename real>
 hipError_t launch_misfit(const real *trace, const real *d_obs, real *residual, int64_t n,
-                         double *misfit, hipStream_t stream) {
+                         double *misfit, double *part, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(misfit_kernel<real>, dim3(blocks_for(n)), dim3(256), 0, stream, trace, d_obs,
-                     residual, n, misfit);
+  const int nb = blocks_for(n);
+  hipLaunchKernelGGL(misfit_kernel<real>, dim3(nb), dim3(256), 0, stream, trace, d_obs, residual,
+                     n, part);
+  hipLaunchKernelGGL(misfit_sum_kernel, dim3(1), dim3(256), 0, stream, part, nb, misfit);
   return hipGetLastError();
 }
 
@@ -918,7 +982,7 @@ hipError_t launch_lame_gradient(const real *lam, const real *mu, const double *g
                                                     hipStream_t);                             \
   template hipError_t launch_adjoint_fused2<real>(const AdjArgs<real> &, int, int, hipStream_t); \
   template hipError_t launch_misfit<real>(const real *, const real *, real *, int64_t, double *, \
-                                          hipStream_t);                                       \
+                                          double *, hipStream_t);                             \
   template hipError_t launch_lame_gradient<real>(const real *, const real *, const double *,  \
                                                  double *, double *, int64_t, hipStream_t);
 LBM_INST(float)

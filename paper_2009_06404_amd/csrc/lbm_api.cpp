@@ -105,6 +105,15 @@ struct DevBuf {
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(s);
   }
+  // room for at least `count` elements, contents undefined
+  hipError_t reserve(size_t count) {
+    if (count <= n && p) return hipSuccess;
+    release();
+    hipError_t e = hipMalloc((void **)&p, std::max<size_t>(count, 1) * sizeof(T));
+    if (e != hipSuccess) return e;
+    n = std::max<size_t>(count, 1);
+    return hipSuccess;
+  }
   void release() {
     if (p) hipFree(p);
     p = nullptr;
@@ -192,6 +201,16 @@ struct lbm_ctx {
   DevBuf<TileDev> d_adj_g2, d_adj_g1;
   int n_adj_f = 0, n_adj_g2 = 0, n_adj_g1 = 0, adj_fwaves = 2;
   int64_t cells_adj_int = 0, cells_adj_gen = 0, cells_adj_f = 0, cells_adj_g2 = 0;
+  // dL/damp in a fixed order: the general adjoint kernel's per-workgroup
+  // partial sums, and for a single step (its list) and for a pair (g1's
+  // workgroups, then g2's, whose slots follow g1's) the workgroups that cover
+  // each (grid, source) pair
+  DevBuf<double> d_amp_part;
+  struct AmpPlan {
+    DevBuf<int32_t> tiles, off, pairs;
+    int npairs = 0;
+  } amp_single, amp_pair;
+  DevBuf<double> d_misfit_part;   // the misfit's per-workgroup sums
   bool adj_tiles_ok = false;
   // graph of graph_chunk steps for each starting buffer parity
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
@@ -1356,6 +1375,40 @@ int recompute_segment(lbm_ctx *c, int64_t m) {
 // the first step's rows three out).
 constexpr int kAdjRecReach = 3;
 
+// The order of the dL/damp sums over the general adjoint kernel's workgroups
+// for one launch or a pair of launches (lists, their slots one after the
+// other): for each grid with sources and each of its first kMaxAdjSources
+// sources, every workgroup of a tile of that grid that is not a border strip,
+// in list order.
+int build_amp_plan(lbm_ctx *c, std::initializer_list<const std::vector<TileDev> *> lists,
+                   lbm_ctx::AmpPlan &plan) {
+  std::vector<std::vector<int32_t>> per_grid(c->nbatch);
+  int32_t base = 0;
+  for (const std::vector<TileDev> *l : lists) {
+    for (size_t i = 0; i < l->size(); ++i) {
+      const TileDev &t = (*l)[i];
+      if (t.g < 0 || (t.g & kStripTile)) continue;
+      per_grid[t.g].push_back(base + (int32_t)i);
+    }
+    base += (int32_t)l->size();
+  }
+  std::vector<int32_t> tiles, off{0}, pairs;
+  for (int g = 0; g < c->nbatch; ++g) {
+    const int ns = std::min((int)c->sources[g].size(), kMaxAdjSources);
+    for (int si = 0; si < ns && !per_grid[g].empty(); ++si) {
+      tiles.insert(tiles.end(), per_grid[g].begin(), per_grid[g].end());
+      off.push_back((int32_t)tiles.size());
+      pairs.push_back(g);
+      pairs.push_back(si);
+    }
+  }
+  plan.npairs = (int)pairs.size() / 2;
+  HIP_TRY(plan.tiles.upload(tiles, c->stream));
+  HIP_TRY(plan.off.upload(off, c->stream));
+  HIP_TRY(plan.pairs.upload(pairs, c->stream));
+  return LBM_OK;
+}
+
 // The adjoint's tile lists: the forward's interior tiles whose rows y0-1 and
 // y1 also hold no receiver, and every other tile. Built from the real tiles
 // of the two (die-ordered, padded) forward lists in their logical order
@@ -1395,8 +1448,12 @@ int build_adjoint_tiles(lbm_ctx *c) {
   c->n_adj_gen = (int)ag.size();
   HIP_TRY(c->d_adj_int.upload(ai, c->stream));
   HIP_TRY(c->d_adj_gen.upload(ag, c->stream));
+  int rc = build_amp_plan(c, {&ag}, c->amp_single);
+  if (rc) return rc;
+  size_t part_slots = ag.size();
   c->n_adj_f = c->n_adj_g2 = c->n_adj_g1 = 0;
   c->cells_adj_f = c->cells_adj_g2 = 0;
+  c->amp_pair.npairs = 0;
   if (c->launch.fuse_rows > 0) {
     // FP64 blocks of 512 columns would need more than the 168 registers a
     // lane has at three waves per SIMD: 256 columns
@@ -1415,8 +1472,12 @@ int build_adjoint_tiles(lbm_ctx *c) {
       HIP_TRY(c->d_adj_ftiles.upload(tf, c->stream));
       HIP_TRY(c->d_adj_g2.upload(tg2, c->stream));
       HIP_TRY(c->d_adj_g1.upload(tg1, c->stream));
+      rc = build_amp_plan(c, {&tg1, &tg2}, c->amp_pair);
+      if (rc) return rc;
+      part_slots = std::max(part_slots, tg1.size() + tg2.size());
     }
   }
+  HIP_TRY(c->d_amp_part.reserve(part_slots * kMaxAdjSources));
   c->adj_tiles_ok = true;
   return LBM_OK;
 }
@@ -1452,6 +1513,11 @@ int adjoint_impl(lbm_ctx *c, int64_t n, lbm_kernel_times *out = nullptr) {
       cnt[kind] += 1;
     }
     return e;
+  };
+  // dL/damp of the launches just queued, after them on the context's stream
+  auto reduce_amp = [&](const lbm_ctx::AmpPlan &p) {
+    return launch_amp_reduce(c->d_amp_part.p, p.tiles.p, p.off.p, p.pairs.p, p.npairs,
+                             c->d_adj_io.p, c->stream);
   };
   // the two kernels of one launch: overlapped as in a step, or timed in turn
   auto run = [&](bool has_int, bool has_gen, int kind_int, auto &&general, auto &&interior) {
@@ -1510,6 +1576,8 @@ int adjoint_impl(lbm_ctx *c, int64_t n, lbm_kernel_times *out = nullptr) {
       g2.tiles = c->d_adj_g2.p;
       g2.t = t - 1;
       g2.rho = stash(t - 1 - tm);
+      g1.amp_part = c->d_amp_part.p;
+      g2.amp_part = c->d_amp_part.p + (size_t)c->n_adj_g1 * kMaxAdjSources;
       HIP_TRY(run(
           true, c->n_adj_g1 > 0, 2,
           [&](hipStream_t q) {
@@ -1520,6 +1588,7 @@ int adjoint_impl(lbm_ctx *c, int64_t n, lbm_kernel_times *out = nullptr) {
             return e;
           },
           [&](hipStream_t q) { return launch_adjoint_fused2<real>(f2, c->adj_fwaves, c->n_adj_f, q); }));
+      HIP_TRY(reduce_amp(c->amp_pair));
       A.cur ^= 1;
       A.t_adj = t - 1;
       k += 2;
@@ -1528,6 +1597,7 @@ int adjoint_impl(lbm_ctx *c, int64_t n, lbm_kernel_times *out = nullptr) {
     AdjArgs<real> ag = a;
     a.tiles = c->d_adj_int.p;
     ag.tiles = c->d_adj_gen.p;
+    ag.amp_part = c->d_amp_part.p;
     HIP_TRY(run(
         c->n_adj_int > 0, c->n_adj_gen > 0, 0,
         [&](hipStream_t q) {
@@ -1535,6 +1605,7 @@ int adjoint_impl(lbm_ctx *c, int64_t n, lbm_kernel_times *out = nullptr) {
           return out ? timed(1, lg) : lg(q);
         },
         [&](hipStream_t q) { return launch_adjoint_interior<real>(a, c->launch.waves, c->n_adj_int, q); }));
+    HIP_TRY(reduce_amp(c->amp_single));
     A.cur ^= 1;
     A.t_adj = t;
     k += 1;
@@ -2393,12 +2464,13 @@ int lbm_misfit(lbm_ctx *c, int32_t g, const void *d_obs, void *residual, int64_t
   if (nrows < 0 || nrows > R.max_steps) return fail(LBM_E_INVALID, "nrows must be in [0, max_steps]");
   const int ncomp = (R.comp_mask & 1) + ((R.comp_mask >> 1) & 1);
   const int64_t n = nrows * (int64_t)(R.xy.size() / 2) * ncomp;
+  HIP_TRY(c->d_misfit_part.reserve(kMisfitParts));
   if (c->dtype == LBM_F64)
     HIP_TRY(launch_misfit<double>(reinterpret_cast<const double *>(R.trace), reinterpret_cast<const double *>(d_obs),
-                                  reinterpret_cast<double *>(residual), n, misfit, c->stream));
+                                  reinterpret_cast<double *>(residual), n, misfit, c->d_misfit_part.p, c->stream));
   else
     HIP_TRY(launch_misfit<float>(reinterpret_cast<const float *>(R.trace), reinterpret_cast<const float *>(d_obs),
-                                 reinterpret_cast<float *>(residual), n, misfit, c->stream));
+                                 reinterpret_cast<float *>(residual), n, misfit, c->d_misfit_part.p, c->stream));
   return LBM_OK;
 }
 
@@ -2434,6 +2506,16 @@ int lbm_destroy(lbm_ctx *c) {
   c->d_adj_io.release();
   c->d_adj_int.release();
   c->d_adj_gen.release();
+  c->d_adj_ftiles.release();
+  c->d_adj_g2.release();
+  c->d_adj_g1.release();
+  c->d_amp_part.release();
+  for (lbm_ctx::AmpPlan *p : {&c->amp_single, &c->amp_pair}) {
+    p->tiles.release();
+    p->off.release();
+    p->pairs.release();
+  }
+  c->d_misfit_part.release();
   c->d_grids.release();
   c->d_tiles.release();
   c->d_ftiles.release();

@@ -121,6 +121,9 @@ struct AdjArgs {
   const FusedTileDev *ftiles;
   const real *rho2;
   int64_t f_elems;
+  // the general kernel's per-workgroup dL/damp sums: kMaxAdjSources doubles
+  // at the workgroup's index (read by launch_amp_reduce)
+  double *amp_part;
 };
 
 template <typename real>
@@ -140,9 +143,18 @@ hipError_t launch_adjoint_fused2(const AdjArgs<real> &a, int waves, int ntiles,
 // the adjoint state only, the gradients of their cells being the two-step
 // kernel's.
 constexpr int32_t kStripTile = 1 << 30;
+// Adds to grad_amp of each listed (grid, source) pair (pairs: g, si) the
+// partial sums part[tiles[i] * kMaxAdjSources + si], i in off[k] .. off[k+1],
+// in that order.
+hipError_t launch_amp_reduce(const double *part, const int32_t *tiles, const int32_t *off,
+                             const int32_t *pairs, int npairs, const AdjGridDev *io,
+                             hipStream_t stream);
+// The misfit's per-workgroup sums go to part (at least kMisfitParts doubles)
+// and are then added to *misfit in order.
+constexpr int kMisfitParts = 4096;
 template <typename real>
 hipError_t launch_misfit(const real *trace, const real *d_obs, real *residual, int64_t n,
-                         double *misfit, hipStream_t stream);
+                         double *misfit, double *part, hipStream_t stream);
 template <typename real>
 hipError_t launch_lame_gradient(const real *lam, const real *mu, const double *grad_kappa,
                                 double *grad_lam, double *grad_mu, int64_t n, hipStream_t stream);

@@ -754,7 +754,10 @@ __global__ __launch_bounds__(64 * NW + 64, sizeof(real) == 4 ? (STASH ? 4 : 5) :
   const bool live = lc >= 0 && lc < w + 8;
   const bool outlane = tid < w;
   auto wrapx = [&](int c) { return c < 0 ? c + nx : (c >= nx ? c - nx : c); };
-  const int col = live ? wrapx(tile.x0 - 4 + lc) : 0;
+  // the lanes outside the block's columns (the halo wavefront's last 56, the
+  // lanes past a narrow block) load a live lane's column: their unconditional
+  // loads then touch no line the block does not need
+  const int col = wrapx(tile.x0 - 4 + min(max(lc, 0), w + 7));
   const uint32_t esz = sizeof(real);
   const uint32_t o0 = (uint32_t)col * esz;
   const uint32_t ol = (uint32_t)wrapx(col - 1) * esz;

@@ -286,6 +286,8 @@ static bool g_adj_seen_f2 = false, g_adj_seen_g2 = false;
 static std::map<int, std::vector<int>> g_adj_cov;
 static int g_adj_ngrids = 0;
 static int64_t g_adj_pairs_checked = 0;
+static std::map<const double *, int64_t> g_amp_slot;   // partial-sum slot -> launch that wrote it
+static int64_t g_amp_reduced = 0;                      // launches before the last reduction
 static std::vector<int> &adj_cov(int g, const GridDev &G) {
   std::vector<int> &v = g_adj_cov[g];
   if (v.empty()) v.assign((size_t)G.nx * G.ny, 0);
@@ -334,6 +336,10 @@ static hipError_t adj_common(const AdjArgs<real> &a, int waves, int ntiles, bool
     check_range(a.rho + g.c_off, sizeof(real) * (size_t)g.pitch * g.ny, "adj rho");
     if (io.grad_kappa) check_range(io.grad_kappa, sizeof(double) * (size_t)g.nx * g.ny, "grad_kappa");
     if (io.grad_amp && g.nsrc) check_range(io.grad_amp, sizeof(double) * (g.nsrc < kMaxAdjSources ? g.nsrc : kMaxAdjSources), "grad_amp");
+    if (!interior && io.grad_amp && g.nsrc && !(a.tiles[i].g & kStripTile)) {
+      check_range(a.amp_part + (size_t)i * kMaxAdjSources, sizeof(double) * kMaxAdjSources, "dL/damp partial sums");
+      g_amp_slot[a.amp_part + (size_t)i * kMaxAdjSources] = g_seq;   // written by this launch
+    }
     if (io.residual && g.nrec) check_range(io.residual, sizeof(real) * (size_t)g.trace_max * g.nrec * g.ncomp, "residual");
     std::vector<int64_t> &out = stamps(a.fout, t.g, g);
     std::vector<int64_t> *mid = second ? &stamps(g_adj_mid, t.g, g) : nullptr;
@@ -364,6 +370,29 @@ static hipError_t adj_common(const AdjArgs<real> &a, int waves, int ntiles, bool
 }
 template <typename real>
 hipError_t launch_adjoint(const AdjArgs<real> &a, int waves, int ntiles, hipStream_t) { return adj_common(a, waves, ntiles, false); }
+// every slot the reduction reads was written by a general launch since the
+// previous reduction
+hipError_t launch_amp_reduce(const double *part, const int32_t *tiles, const int32_t *off,
+                             const int32_t *pairs, int npairs, const AdjGridDev *io, hipStream_t) {
+  if (npairs <= 0) return hipSuccess;
+  check_range(off, sizeof(int32_t) * (npairs + 1), "amp plan offsets");
+  check_range(pairs, sizeof(int32_t) * 2 * npairs, "amp plan pairs");
+  for (int k = 0; k < npairs; ++k) {
+    check_range(&io[pairs[2 * k]], sizeof(AdjGridDev), "amp io");
+    if (!io[pairs[2 * k]].grad_amp) continue;
+    check_range(tiles + off[k], sizeof(int32_t) * (off[k + 1] - off[k]), "amp plan tiles");
+    for (int i = off[k]; i < off[k + 1]; ++i) {
+      const double *slot = part + (size_t)tiles[i] * kMaxAdjSources;
+      auto it = g_amp_slot.find(slot);
+      if (it == g_amp_slot.end() || it->second <= g_amp_reduced) {
+        fprintf(stderr, "dL/damp reduction reads a slot no general launch wrote since the last one\n");
+        abort();
+      }
+    }
+  }
+  g_amp_reduced = g_seq;
+  return hipSuccess;
+}
 template <typename real>
 hipError_t launch_adjoint_interior(const AdjArgs<real> &a, int waves, int ntiles, hipStream_t) { return adj_common(a, waves, ntiles, true); }
 template <typename real>
@@ -427,9 +456,12 @@ hipError_t launch_adjoint_fused2(const AdjArgs<real> &a, int waves, int ntiles, 
   return hipSuccess;
 }
 template <typename real>
-hipError_t launch_misfit(const real *tr, const real *d, real *r, int64_t n, double *m, hipStream_t) {
+hipError_t launch_misfit(const real *tr, const real *d, real *r, int64_t n, double *m, double *part, hipStream_t) {
   check_range(tr, n * sizeof(real), "misfit tr"); check_range(d, n * sizeof(real), "misfit d");
   if (r) check_range(r, n * sizeof(real), "misfit r");
+  int64_t nb = (n + 255) / 256;
+  nb = nb < 1 ? 1 : (nb > 4096 ? 4096 : nb);
+  check_range(part, nb * sizeof(double), "misfit partial sums");
   check_range(m, 8, "misfit m"); return hipSuccess;
 }
 template <typename real>
@@ -513,7 +545,7 @@ hipError_t launch_add_time(int64_t *t, int64_t v, hipStream_t) { check_range(t, 
   template hipError_t launch_adjoint<real>(const AdjArgs<real> &, int, int, hipStream_t); \
   template hipError_t launch_adjoint_interior<real>(const AdjArgs<real> &, int, int, hipStream_t); \
   template hipError_t launch_adjoint_fused2<real>(const AdjArgs<real> &, int, int, hipStream_t); \
-  template hipError_t launch_misfit<real>(const real *, const real *, real *, int64_t, double *, hipStream_t); \
+  template hipError_t launch_misfit<real>(const real *, const real *, real *, int64_t, double *, double *, hipStream_t); \
   template hipError_t launch_lame_gradient<real>(const real *, const real *, const double *, double *, double *, int64_t, hipStream_t); \
   template hipError_t launch_kappa<real>(const real *, const real *, const real *, int, int, int, real *, int *, int *, hipStream_t); \
   template hipError_t launch_kappa_rows<real>(const real *, int, int, real *, hipStream_t); \

@@ -127,17 +127,16 @@ def test_adjoint_interior_tiles_match_oracle(bc, dtype):
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_adjoint_chunks_and_segments_are_neutral(dtype):
     """Stepping the adjoint back in uneven pieces, and any checkpoint
-    spacing, gives bitwise the same state and dL/dkappa; dL/damp is summed
-    across workgroups with FP64 atomics, so only its rounding order varies."""
+    spacing, gives bitwise the same state, dL/dkappa and dL/damp (each step's
+    dL/damp is summed over workgroups in a fixed order, with no atomics)."""
     p = _problem((BC_FREE0, BC_RIGID, BC_PERIODIC, BC_PERIODIC), -1, nx=90, ny=33, seed=3)
     T = 30
     res = np.random.default_rng(2).standard_normal((T, p.nrec, p.ncomp))
     a = _gpu_adjoint([p], T, 30, dtype, [res])[0]
     for seg, chunks in ((1, [30]), (4, [13, 17]), (11, [1, 28, 1]), (64, [29, 1])):
         b = _gpu_adjoint([p], T, seg, dtype, [res], chunks=chunks)[0]
-        for k in ("adj", "grad_kappa"):
+        for k in ("adj", "grad_kappa", "grad_amp"):
             assert np.array_equal(a[k], b[k]), (seg, chunks, k)
-        assert np.allclose(a["grad_amp"], b["grad_amp"], rtol=1e-13, atol=0), (seg, chunks)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -152,6 +151,38 @@ def test_batched_adjoint_matches_oracle(dtype):
     g1, g2 = _gpu_adjoint([p1, p2], T, seg, dtype, [r1, r2], launch=dict(waves=2, rows=4))
     _compare(g1, stepper.adjoint(p1, nsteps=T, residual=r1), TOL[dtype], f"batched grid 0 {dtype}")
     _compare(g2, stepper.adjoint(p2, nsteps=T, residual=r2), TOL[dtype], f"batched grid 1 {dtype}")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_gradients_and_misfit_are_reproducible(dtype):
+    """The same run twice, on the two-step path with pairs and single steps
+    mixed: the adjoint state, dL/dkappa, dL/damp and the misfit agree bit for
+    bit (their sums over workgroups run in a fixed order, with no atomics)."""
+    import torch
+    from paper_2009_06404_amd import Solver
+    p = _problem((BC_FREE, BC_RIGID, BC_PERIODIC, BC_PERIODIC), 20, nx=300, ny=90, seed=8)
+    T = 26
+    d_obs = np.random.default_rng(4).standard_normal((T, p.nrec, p.ncomp)) * 1e-3
+    runs = []
+    for _ in range(2):
+        s = Solver(p, dtype=dtype, trace_steps=T, launch=dict(waves=2, rows=4, fuse_rows=8))
+        try:
+            s.adjoint_begin(T, 9)
+            s.step(T)
+            mis, res = s.misfit(0, torch.as_tensor(d_obs))
+            gk = torch.zeros((p.ny, p.nx), dtype=torch.float64, device=s.device)
+            ga = torch.zeros(len(p.sources), dtype=torch.float64, device=s.device)
+            s.adjoint_set_io(0, res, gk, ga)
+            s.adjoint_step(5)
+            s.adjoint_step(T - 5)
+            runs.append([mis.cpu().numpy(), s.adjoint_state(0).cpu().numpy(), gk.cpu().numpy(),
+                         ga.cpu().numpy()])
+            torch.cuda.synchronize()
+        finally:
+            s.close()
+    assert np.abs(runs[0][3]).max() > 0
+    for a, b, what in zip(runs[0], runs[1], ("misfit", "state", "grad_kappa", "grad_amp")):
+        assert np.array_equal(a, b), what
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
