@@ -410,12 +410,29 @@ def bench_batched(torch, w, Solver, plain_glups: float, steps: int = 60,
             "graph_vs_direct": round(g / gd, 4)}
 
 
+def kept_density_steps(torch, s, seg: int, nsteps: int, margin_gib: float = 16.0) -> int:
+    """Steps whose densities an adjoint recording of nsteps steps can keep in
+    the HBM left free, `margin_gib` GiB held back."""
+    from paper_2009_06404_amd import _lib as L
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    base = L.lbm_adjoint_workspace_bytes(s.ctx, seg, nsteps)
+    plane = (L.lbm_adjoint_workspace_bytes_resident(s.ctx, seg, nsteps, nsteps) - base) / nsteps
+    avail = free - base - margin_gib * 2 ** 30
+    return int(max(0, min(nsteps, avail // plane)))
+
+
 def bench_adjoint(torch, w, Solver, plain_glups: float, nsteps: int = 5000,
                   seg: int = 100, launch=None) -> dict:
     """16 shots of 1024^2 FP32 through the perturbed medium, 5000 steps,
     checkpoints every 100: the full gradient (recorded forward, misfit,
-    adjoint with recompute, Lame gradients) timed end to end, against the
-    observed data of the homogeneous background (computed beforehand)."""
+    adjoint, Lame gradients) timed end to end, against the observed data of
+    the homogeneous background (computed beforehand). Timed twice: with the
+    densities of as many trailing segments as the free HBM holds kept from
+    the recorded forward (no recompute there), and with every segment
+    recomputed from its checkpoint; the gradients agree bit for bit except
+    dL/damp, to rounding."""
     shots = w.adjoint_shots(nsteps=nsteps)
     bg = w.adjoint_shots(nsteps=nsteps, homogeneous=True)
     sb = Solver(bg, dtype="f32", trace_steps=nsteps)
@@ -430,41 +447,58 @@ def bench_adjoint(torch, w, Solver, plain_glups: float, nsteps: int = 5000,
     ga = torch.zeros((G, 1), dtype=torch.float64, device="cuda")
     gl = torch.zeros((n, n), dtype=torch.float64, device="cuda")
     gm = torch.zeros_like(gl)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e2 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    s.adjoint_begin(nsteps, seg)
-    s.step(nsteps)
-    e1.record()
-    mis = []
-    res = []
-    for g in range(G):
-        m, r = s.misfit(g, d_obs[g])
-        mis.append(m)
-        res.append(r)
-        s.adjoint_set_io(g, r, gk[g], ga[g])
-    s.adjoint_step(nsteps)
-    for g in range(G):
-        s.lame_gradient(g, gk[g], gl, gm)
-    e2.record()
-    torch.cuda.synchronize()
-    t_fwd = e0.elapsed_time(e1)
-    t_all = e0.elapsed_time(e2)
-    ok = bool(torch.isfinite(gl).all().item() and torch.isfinite(gm).all().item())
-    misfit = float(sum(m.item() for m in mis))
+    cells = G * n * n
+
+    init = [s.state(g).clone() for g in range(G)]   # the rest state at t = 0
+
+    def gradient(kept: int) -> dict:
+        for t_ in (gk, ga, gl, gm):
+            t_.zero_()
+        for g in range(G):
+            s.set_state(g, init[g], 0)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e2 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.adjoint_begin(nsteps, seg, resident_steps=kept)
+        s.step(nsteps)
+        e1.record()
+        mis = []
+        for g in range(G):
+            m, r = s.misfit(g, d_obs[g])
+            mis.append(m)
+            s.adjoint_set_io(g, r, gk[g], ga[g])
+        s.adjoint_step(nsteps)
+        for g in range(G):
+            s.lame_gradient(g, gk[g], gl, gm)
+        e2.record()
+        torch.cuda.synchronize()
+        t_all = e0.elapsed_time(e2)
+        return {"gradient_GLUPS": round(cells * nsteps / (t_all / 1e3) / 1e9, 3),
+                "ms_total": round(t_all, 1), "ms_forward_recorded": round(e0.elapsed_time(e1), 1),
+                "misfit": float(sum(m.item() for m in mis)),
+                "gradients_finite": bool(torch.isfinite(gl).all().item()
+                                         and torch.isfinite(gm).all().item()),
+                "gl": gl.clone()}
+
+    kept = kept_density_steps(torch, s, seg, nsteps)
+    with_kept = gradient(kept)
+    recompute = gradient(0)
+    same = bool(torch.equal(with_kept.pop("gl"), recompute.pop("gl")))
+    del init
     kernels = adjoint_kernel_roofline(torch, s, seg)
     s.close()
-    cells = G * n * n
-    g_rate = cells * nsteps / (t_all / 1e3) / 1e9
+    plane_gb = cells * 4 / 1e9
     return {"workload": f"adjoint_shots: {G} shots of {n}x{n} FP32, {nsteps} steps, "
-                        f"checkpoints every {seg}", "gradient_GLUPS": round(g_rate, 3),
-            "ms_total": round(t_all, 1), "ms_forward_recorded": round(t_fwd, 1),
-            "vs_plain": round(g_rate / plain_glups, 4), "misfit": misfit,
-            "gradients_finite": ok, "adjoint_kernels": kernels,
+                        f"checkpoints every {seg}",
+            **with_kept, "vs_plain": round(with_kept["gradient_GLUPS"] / plain_glups, 4),
+            "kept_density_steps": kept, "kept_density_GB": round(kept * plane_gb, 1),
+            "recompute_every_segment": recompute, "dL_dlambda_bitwise_equal": same,
+            "adjoint_kernels": kernels,
             "note": "gradient_GLUPS = cell-steps of the forward per second of forward + "
-                    "misfit + adjoint (with recompute) + Lame gradients"}
+                    "misfit + adjoint (kept densities for the last kept_density_steps steps, "
+                    "recompute from checkpoints for the others) + Lame gradients"}
 
 
 # Algorithmic bytes per cell and launch of the adjoint kernels (FP32, cell-wise

@@ -345,11 +345,24 @@ int lbm_autotune(lbm_ctx *ctx, int32_t steps, lbm_launch *chosen);
 int lbm_adjoint_workspace_bytes(const lbm_ctx *ctx, int32_t seg_steps, int64_t nsteps,
                                 size_t *bytes);
 
+/* Workspace of an adjoint run that also keeps in HBM the densities of its
+ * last resident_steps steps, rounded down to whole trailing segments (the
+ * last segment may be short): one plane of the grids' cells per step, written
+ * by the recorded forward run. Those segments then need no recompute in
+ * lbm_adjoint_step; the results are the same bit for bit. resident_steps = 0
+ * gives lbm_adjoint_workspace_bytes. Host only. */
+int lbm_adjoint_workspace_bytes_resident(const lbm_ctx *ctx, int32_t seg_steps, int64_t nsteps,
+                                         int64_t resident_steps, size_t *bytes);
+
 /* Open a recording of the forward run from the current time t0 for nsteps
  * steps. ws: caller-owned DEVICE memory, 256-B aligned, at least
  * lbm_adjoint_workspace_bytes, used exclusively by this context until the
- * next lbm_adjoint_begin or lbm_destroy. The adjoint state starts at
- * t0 + nsteps with fh = 0. At most 16 sources per grid. Asynchronous. */
+ * next lbm_adjoint_begin or lbm_destroy; room beyond that minimum keeps the
+ * densities of as many whole trailing segments as fit (see
+ * lbm_adjoint_workspace_bytes_resident). The adjoint state starts at
+ * t0 + nsteps with fh = 0. At most 16 sources per grid. The recording stays
+ * open until the forward run reaches t0 + nsteps; meanwhile lbm_step_timed
+ * and lbm_filter are refused. Asynchronous. */
 int lbm_adjoint_begin(lbm_ctx *ctx, int32_t seg_steps, int64_t nsteps, void *ws, size_t ws_bytes);
 
 /* Per-grid adjoint inputs and outputs (DEVICE pointers, caller-owned, any may

@@ -35,7 +35,8 @@ ENTRY_POINTS = (
     "lbm_set_sources", "lbm_set_receivers", "lbm_step", "lbm_step_timed", "lbm_moments",
     "lbm_get_time", "lbm_get_state", "lbm_set_state", "lbm_check_finite",
     "lbm_get_launch", "lbm_set_launch", "lbm_autotune", "lbm_destroy",
-    "lbm_adjoint_workspace_bytes", "lbm_adjoint_begin", "lbm_adjoint_set_io",
+    "lbm_adjoint_workspace_bytes", "lbm_adjoint_workspace_bytes_resident", "lbm_adjoint_begin",
+    "lbm_adjoint_set_io",
     "lbm_adjoint_step", "lbm_adjoint_step_timed", "lbm_adjoint_time", "lbm_adjoint_get_state",
     "lbm_adjoint_set_state",
     "lbm_misfit", "lbm_lame_gradient", "lbm_vn_growth", "lbm_stability",
@@ -115,6 +116,8 @@ def lib():
             "lbm_autotune": ([vp, i32, C.POINTER(lbm_launch)], C.c_int),
             "lbm_destroy": ([vp], C.c_int),
             "lbm_adjoint_workspace_bytes": ([vp, i32, i64, C.POINTER(C.c_size_t)], C.c_int),
+            "lbm_adjoint_workspace_bytes_resident": ([vp, i32, i64, i64, C.POINTER(C.c_size_t)],
+                                                     C.c_int),
             "lbm_adjoint_begin": ([vp, i32, i64, vp, C.c_size_t], C.c_int),
             "lbm_adjoint_set_io": ([vp, i32, vp, vp, vp], C.c_int),
             "lbm_adjoint_step": ([vp, i64], C.c_int),
@@ -317,6 +320,14 @@ def lbm_adjoint_workspace_bytes(ctx, seg_steps: int, nsteps: int) -> int:
     out = C.c_size_t(0)
     check(lib().lbm_adjoint_workspace_bytes(ctx, int(seg_steps), int(nsteps), C.byref(out)))
     return int(out.value)
+
+
+def lbm_adjoint_workspace_bytes_resident(ctx, seg_steps: int, nsteps: int,
+                                         resident_steps: int) -> int:
+    out = C.c_size_t()
+    check(lib().lbm_adjoint_workspace_bytes_resident(ctx, int(seg_steps), int(nsteps),
+                                                     int(resident_steps), C.byref(out)))
+    return out.value
 
 
 def lbm_adjoint_begin(ctx, seg_steps: int, nsteps: int, ws_ptr, ws_bytes: int) -> None:

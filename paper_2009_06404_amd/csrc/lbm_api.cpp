@@ -224,6 +224,10 @@ struct lbm_ctx {
     char *ckpt = nullptr, *rbuf[2] = {nullptr, nullptr}, *abuf[2] = {nullptr, nullptr};
     char *stash = nullptr;
     int64_t t_adj = 0, stash_seg = -1;
+    // densities kept from the recorded forward for the steps res_t0 ..
+    // res_t0 + res_steps - 1 (whole trailing segments): no recompute there
+    char *res = nullptr;
+    int64_t res_t0 = 0, res_steps = 0;
     int cur = 0;
     std::vector<AdjGridDev> io;
     bool io_dirty = true;
@@ -911,15 +915,16 @@ void pair_args(lbm_ctx *c, const StepArgs<real> &a, StepArgs<real> &g1, StepArgs
 
 // Two steps on the two-step path: g1 then g2 on the library's second stream,
 // beside f2 on the context's stream (or one after the other without overlap).
-// With stash planes (the adjoint's recompute), the launches also write rho(t)
-// and rho(t+1) of every cell to rho_t and rho_t1 and skip the receivers (g1
-// writes the strips' rho(t) as f2 does, the same values).
+// With stash planes, the launches also write rho(t) and rho(t+1) of every
+// cell to rho_t and rho_t1 (g1 writes the strips' rho(t) as f2 does, the same
+// values) and skip the receivers, unless `receivers` (a recorded forward
+// step that keeps its densities).
 template <typename real>
 hipError_t launch_two_steps(lbm_ctx *c, StepArgs<real> a, hipStream_t s, real *rho_t = nullptr,
-                            real *rho_t1 = nullptr) {
+                            real *rho_t1 = nullptr, bool receivers = false) {
   StepArgs<real> g1, f2, g2;
   pair_args<real>(c, a, g1, f2, g2);
-  const int mode = rho_t ? kModeStash : kModeStep;
+  const int mode = rho_t && !receivers ? kModeStash : kModeStep;
   g1.rho_out = rho_t;
   f2.rho_out = rho_t;
   f2.rho_out2 = rho_t1;
@@ -1131,9 +1136,61 @@ int step_impl(lbm_ctx *c, int64_t n) {
 }
 
 template <typename real>
+int step_chunks(lbm_ctx *c, int64_t n);
+
+// Recorded forward steps whose densities the adjoint keeps: direct launches
+// that also write rho(t) of every cell to the step's plane, receivers included.
+template <typename real>
+int step_keep_densities(lbm_ctx *c, int64_t n) {
+  auto &A = c->adj;
+  auto plane = [&](int64_t t) {
+    return reinterpret_cast<real *>(A.res + (size_t)(t - A.res_t0) * A.cbytes);
+  };
+  if (use_fused(c)) {
+    for (; n >= 2; n -= 2) {
+      HIP_TRY(launch_two_steps<real>(c, make_args<real>(c, c->cur), c->stream, plane(c->t),
+                                     plane(c->t + 1), true));
+      c->cur ^= 1;
+      c->t += 2;
+    }
+  }
+  for (; n > 0; --n) {
+    StepArgs<real> a = make_args<real>(c, c->cur);
+    a.rho_out = plane(c->t);
+    HIP_TRY(launch_one_step<real>(c, a, c->stream));
+    c->cur ^= 1;
+    c->t += 1;
+  }
+  return LBM_OK;
+}
+
+template <typename real>
 int step_run(lbm_ctx *c, int64_t n) {
   int rc = commit(c);
   if (rc) return rc;
+  // the steps of an open recording whose densities are kept run apart
+  auto &A = c->adj;
+  if (A.begun && A.res_steps > 0) {
+    const int64_t r0 = A.res_t0, r1 = A.res_t0 + A.res_steps;
+    if (c->t < r1 && c->t + n > r0) {
+      if (c->t < r0) {
+        const int64_t m = r0 - c->t;
+        rc = step_chunks<real>(c, m);
+        if (rc) return rc;
+        n -= m;
+      }
+      const int64_t m = std::min(n, r1 - c->t);
+      rc = step_keep_densities<real>(c, m);
+      if (rc) return rc;
+      n -= m;
+    }
+  }
+  return step_chunks<real>(c, n);
+}
+
+template <typename real>
+int step_chunks(lbm_ctx *c, int64_t n) {
+  int rc = LBM_OK;
   // graph_chunk > 0: whole chunks run as captured graphs, one per buffer
   // parity. A single step swaps the ping-pong buffers once, a pair of steps
   // on the two-step path once per pair: after an even chunk of single steps
@@ -1299,6 +1356,21 @@ size_t adj_cbytes(const lbm_ctx *c) { return (size_t)round_up(c->L.k_elems * (in
 size_t adj_ws_bytes(const lbm_ctx *c, int32_t seg, int64_t nsteps) {
   const int64_t nseg = (nsteps + seg - 1) / seg;
   return (size_t)nseg * adj_fbytes(c) + 4 * adj_fbytes(c) + (size_t)seg * adj_cbytes(c) + 256;
+}
+
+// Steps of the last r segments of a recording (the last one may be short).
+int64_t trailing_steps(int32_t seg, int64_t nsteps, int64_t r) {
+  const int64_t nseg = (nsteps + seg - 1) / seg;
+  r = std::min(r, nseg);
+  return r <= 0 ? 0 : nsteps - (nseg - r) * seg;
+}
+
+// The most whole trailing segments whose steps fit in `steps` density planes.
+int64_t resident_segments(int32_t seg, int64_t nsteps, int64_t steps) {
+  const int64_t nseg = (nsteps + seg - 1) / seg;
+  int64_t r = 0;
+  while (r < nseg && trailing_steps(seg, nsteps, r + 1) <= steps) ++r;
+  return r;
 }
 
 // Forward steps while an adjoint recording is open: the state at every
@@ -1535,14 +1607,20 @@ int adjoint_impl(lbm_ctx *c, int64_t n, lbm_kernel_times *out = nullptr) {
     A.io_dirty = false;
   }
   auto stash = [&](int64_t s) { return reinterpret_cast<const real *>(A.stash + (size_t)s * A.cbytes); };
+  // rho(s): kept from the recorded forward, or from the segment's recompute
+  auto kept = [&](int64_t s) { return A.res_steps > 0 && s >= A.res_t0; };
   for (int64_t k = 0; k < n;) {
     const int64_t t = A.t_adj - 1;
     const int64_t m = (t - A.t_begin) / A.seg;
-    if (A.stash_seg != m) {
+    if (!kept(t) && A.stash_seg != m) {
       int rc = recompute_segment<real>(c, m);
       if (rc) return rc;
     }
     const int64_t tm = A.t_begin + m * A.seg;
+    auto rho_at = [&](int64_t s) {
+      return kept(s) ? reinterpret_cast<const real *>(A.res + (size_t)(s - A.res_t0) * A.cbytes)
+                     : stash(s - tm);
+    };
     AdjArgs<real> a;
     memset(&a, 0, sizeof a);
     a.fin = reinterpret_cast<const real *>(A.abuf[A.cur]);
@@ -1555,11 +1633,11 @@ int adjoint_impl(lbm_ctx *c, int64_t n, lbm_kernel_times *out = nullptr) {
     a.sources = c->d_src.p;
     a.itab = c->d_itab.p;
     a.rtab = reinterpret_cast<const real *>(c->d_rtab.p);
-    a.rho = stash(t - tm);
+    a.rho = rho_at(t);
     a.t = t;
     a.omega = (real)(1.0 / c->tau);
     a.cforce = (real)(1.0 - 0.5 / c->tau);
-    if (c->n_adj_f > 0 && n - k >= 2 && t - 1 >= tm) {
+    if (c->n_adj_f > 0 && n - k >= 2 && (t - 1 >= tm || (kept(t) && kept(t - 1)))) {
       // Steps t and t-1 of one recomputed segment: g1 takes the general
       // tiles and the blocks' border strips to fh(t) in the recompute's
       // first buffer (free until the next segment is recomputed), g2 the
@@ -1570,12 +1648,12 @@ int adjoint_impl(lbm_ctx *c, int64_t n, lbm_kernel_times *out = nullptr) {
       g1.fout = mid;
       g1.tiles = c->d_adj_g1.p;
       f2.ftiles = c->d_adj_ftiles.p;
-      f2.rho2 = stash(t - 1 - tm);
+      f2.rho2 = rho_at(t - 1);
       f2.f_elems = c->L.f_elems;
       g2.fin = mid;
       g2.tiles = c->d_adj_g2.p;
       g2.t = t - 1;
-      g2.rho = stash(t - 1 - tm);
+      g2.rho = rho_at(t - 1);
       g1.amp_part = c->d_amp_part.p;
       g2.amp_part = c->d_amp_part.p + (size_t)c->n_adj_g1 * kMaxAdjSources;
       HIP_TRY(run(
@@ -1829,6 +1907,14 @@ int watch_verdict(const lbm_ctx *c) {
   return fail(LBM_E_NONFINITE, buf);
 }
 
+// A recording is open until its forward run has taken every checkpoint and
+// reached its last step: until then steps must go through it (checkpoints,
+// kept densities).
+static bool recording_open(const lbm_ctx *c) {
+  const auto &A = c->adj;
+  return A.begun && (A.taken < A.nseg || c->t < A.t_begin + A.nsteps);
+}
+
 int lbm_step(lbm_ctx *c, int64_t n) {
   int rc = check_ctx(c);
   if (rc) return rc;
@@ -1836,7 +1922,7 @@ int lbm_step(lbm_ctx *c, int64_t n) {
   rc = watch_verdict(c);
   if (rc) return rc;
   if (n == 0) return LBM_OK;
-  if (c->adj.begun && c->adj.taken < c->adj.nseg) {
+  if (recording_open(c)) {
     rc = commit(c);
     if (rc) return rc;
     return step_recording(c, n);
@@ -1849,7 +1935,7 @@ int lbm_step_timed(lbm_ctx *c, int64_t n, lbm_kernel_times *out) {
   if (rc) return rc;
   if (n < 0) return fail(LBM_E_INVALID, "n must be >= 0");
   if (!out) return fail(LBM_E_INVALID, "out is null");
-  if (c->adj.begun && c->adj.taken < c->adj.nseg)
+  if (recording_open(c))
     return fail(LBM_E_STATE, "an adjoint recording is open: advance it with lbm_step");
   rc = commit(c);
   if (rc) return rc;
@@ -1947,7 +2033,7 @@ int lbm_filter(lbm_ctx *c, double sigma) {
   int rc = check_ctx(c);
   if (rc) return rc;
   if (!(sigma > 0.0 && sigma <= 1.0 / 16.0)) return fail(LBM_E_INVALID, "sigma must be in (0, 1/16]");
-  if (c->adj.begun && c->adj.taken < c->adj.nseg)
+  if (recording_open(c))
     return fail(LBM_E_STATE, "an adjoint recording is open: it assumes unfiltered steps");
   rc = commit(c);
   if (rc) return rc;
@@ -2341,6 +2427,18 @@ int lbm_adjoint_workspace_bytes(const lbm_ctx *c, int32_t seg_steps, int64_t nst
   return LBM_OK;
 }
 
+int lbm_adjoint_workspace_bytes_resident(const lbm_ctx *c, int32_t seg_steps, int64_t nsteps,
+                                         int64_t resident_steps, size_t *bytes) {
+  int rc = check_ctx(c);
+  if (rc) return rc;
+  if (!bytes) return fail(LBM_E_INVALID, "bytes is null");
+  if (seg_steps < 1 || nsteps < 1 || resident_steps < 0)
+    return fail(LBM_E_INVALID, "need seg_steps >= 1, nsteps >= 1 and resident_steps >= 0");
+  const int64_t kept = trailing_steps(seg_steps, nsteps, resident_segments(seg_steps, nsteps, resident_steps));
+  *bytes = adj_ws_bytes(c, seg_steps, nsteps) + (size_t)kept * adj_cbytes(c);
+  return LBM_OK;
+}
+
 int lbm_adjoint_begin(lbm_ctx *c, int32_t seg_steps, int64_t nsteps, void *ws, size_t ws_bytes) {
   int rc = check_ctx(c);
   if (rc) return rc;
@@ -2364,6 +2462,13 @@ int lbm_adjoint_begin(lbm_ctx *c, int32_t seg_steps, int64_t nsteps, void *ws, s
   for (int i = 0; i < 2; ++i) { A.rbuf[i] = p; p += A.fbytes; }
   for (int i = 0; i < 2; ++i) { A.abuf[i] = p; p += A.fbytes; }
   A.stash = p;
+  p += (size_t)seg_steps * A.cbytes;
+  // room beyond the minimum keeps the densities of whole trailing segments
+  const size_t used = (size_t)(p - reinterpret_cast<char *>(ws));
+  const int64_t planes = ws_bytes > used ? (int64_t)((ws_bytes - used) / A.cbytes) : 0;
+  A.res_steps = trailing_steps(seg_steps, nsteps, resident_segments(seg_steps, nsteps, planes));
+  A.res = A.res_steps > 0 ? p : nullptr;
+  A.res_t0 = c->t + nsteps - A.res_steps;
   A.t_begin = c->t;
   A.t_adj = c->t + nsteps;
   A.taken = 0;

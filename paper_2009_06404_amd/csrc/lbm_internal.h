@@ -88,7 +88,9 @@ struct StepArgs {
 };
 
 // kModeStash: the step plus the density of every cell written to rho_out,
-// without the receivers (the forward recompute of the adjoint).
+// without the receivers (the forward recompute of the adjoint). kModeStep
+// with rho_out set writes the densities too, receivers included (a recorded
+// forward step whose densities the adjoint keeps).
 enum Mode { kModeStep = 0, kModeMoments = 1, kModeStash = 2 };
 
 // The adjoint's per-grid inputs and outputs (device pointers, caller-owned).

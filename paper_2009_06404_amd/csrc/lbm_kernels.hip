@@ -376,7 +376,9 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepArgs<real> a) {
         a.mom[5 * n + o] = pyy;
       }
     } else {
-      if (MODE == kModeStash && active) a.rho_out[g.c_off + (int64_t)y * pitch + x] = rho;
+      // the density of the step: the adjoint's recompute (kModeStash), or a
+      // recorded forward step that keeps it (kModeStep with rho_out set)
+      if (a.rho_out && active) a.rho_out[g.c_off + (int64_t)y * pitch + x] = rho;
       // Receivers on this row.
       if (MODE == kModeStep && g.nrec > 0) {
         const int slot = a.itab[g.rowtab_off + y];

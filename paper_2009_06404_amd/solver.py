@@ -148,9 +148,13 @@ class Solver:
         return L.lbm_autotune(self.ctx, steps)
 
     # -- adjoint ---------------------------------------------------------
-    def adjoint_begin(self, nsteps: int, seg_steps: int = 100) -> None:
-        """Record the next nsteps forward steps (checkpoints every seg_steps)."""
-        nbytes = L.lbm_adjoint_workspace_bytes(self.ctx, seg_steps, nsteps)
+    def adjoint_begin(self, nsteps: int, seg_steps: int = 100, resident_steps: int = 0) -> None:
+        """Record the next nsteps forward steps (checkpoints every seg_steps),
+        keeping the densities of the last resident_steps steps (whole trailing
+        segments) in HBM: those segments need no recompute."""
+        nbytes = L.lbm_adjoint_workspace_bytes_resident(self.ctx, seg_steps, nsteps,
+                                                        resident_steps)
+        self.adj_ws = None           # a previous recording's workspace goes first
         self.adj_ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         L.lbm_adjoint_begin(self.ctx, seg_steps, nsteps, self.adj_ws.data_ptr(), nbytes)
         self._adj_keep = {}

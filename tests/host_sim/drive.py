@@ -49,7 +49,7 @@ def problem(bc, rr, nx, ny, seed, sources=None, receivers=None):
                    receivers=np.asarray(rec, np.int32), comp_mask=3)
 
 
-def run(probs, T, seg, dtype, launch=None, chunks=None):
+def run(probs, T, seg, dtype, launch=None, chunks=None, resident=0):
     code, npdt = (L.LBM_F32, np.float32) if dtype == "f32" else (L.LBM_F64, np.float64)
     grids = [(p.nx, p.ny) for p in probs]
     fields = [np.concatenate([p.medium.full(p.ny, p.nx)[k].ravel() for p in probs]).astype(npdt)
@@ -70,11 +70,14 @@ def run(probs, T, seg, dtype, launch=None, chunks=None):
         lc = L.lbm_get_launch(ctx)
         lc.update(launch)
         L.lbm_set_launch(ctx, **lc)
-    ab = L.lbm_adjoint_workspace_bytes(ctx, seg, T)
+    ab = L.lbm_adjoint_workspace_bytes_resident(ctx, seg, T, resident)
+    assert (ab == L.lbm_adjoint_workspace_bytes(ctx, seg, T)) == (resident < T - (T - 1) // seg * seg)
     adj_before = sim.sim_adjoint_pairs_checked()
     aws = dev(np.zeros(ab + 512, np.uint8))
     L.lbm_adjoint_begin(ctx, seg, T, (aws.ctypes.data + 255) // 256 * 256, ab)
-    L.lbm_step(ctx, T)
+    # the forward in pieces that cross the checkpoints and the kept range
+    for n in (3, T // 2 - 3, T - T // 2):
+        L.lbm_step(ctx, n)
     for g, p in enumerate(probs):
         res = dev(np.ones((T, p.nrec, p.ncomp), npdt))
         gk = dev(np.zeros((p.ny, p.nx)))
@@ -194,6 +197,17 @@ lines = open(cache).read().splitlines()
 assert len(lines) == 2 and lines[0].startswith("sim f32 ") and " pairs|" in lines[0], lines
 assert " single|" in lines[1], lines
 print("ok autotune", flush=True)
+
+# densities kept from the recorded forward: none, the last (short) segment,
+# a few whole segments, all of them; every plane the adjoint reads must hold
+# the density of the time it reads it for
+for dtype in ("f32", "f64"):
+    p = problem(FUSED[1][1], 61, 530, 150, 12, sources=[Source(300.0, 75.0, 2.0, 0.3, 0.9, 1.0, 12.0, 16.0)],
+                receivers=[(x, 0) for x in range(0, 530, 5)] + [(x, 77) for x in range(3, 530, 11)])
+    for launch in (dict(waves=2, rows=8, fuse_rows=8), dict(waves=2, rows=8)):
+        for resident, chunks in ((0, [23]), (2, [5, 18]), (12, [1, 22]), (23, [23]), (1000, [4, 19])):
+            run([p], 23, 7, dtype, launch=launch, chunks=chunks, resident=resident)
+    print("ok kept densities", dtype, flush=True)
 
 # adjoint pairs: blocks of 128, 256 and 512 columns (256 in FP64), segments of
 # odd and even lengths (a pair never spans two), adjoint steps taken in odd

@@ -100,6 +100,18 @@ static int64_t g_seq = 0, g_g1_seq = -10;
 static const void *g_fmid = nullptr, *g_pair_out = nullptr;
 static std::map<const void *, std::map<int, std::vector<int64_t>>> g_stamps;
 static std::map<int, std::vector<int>> g_cov;   // per grid and cell: writes of the pending pair
+// Density planes: the time whose rho a forward launch last wrote to each
+// plane (by base address), checked against the time the adjoint reads it for.
+static std::map<const void *, int64_t> g_plane_t;
+static void plane_written(const void *p, int64_t t) { g_plane_t[p] = t; }
+static void plane_read(const void *p, int64_t t, const char *what) {
+  auto it = g_plane_t.find(p);
+  if (it == g_plane_t.end() || it->second != t) {
+    fprintf(stderr, "%s: density plane %p read for time %lld holds %s%lld\n", what, p, (long long)t,
+            it == g_plane_t.end() ? "nothing " : "time ", it == g_plane_t.end() ? 0LL : (long long)it->second);
+    abort();
+  }
+}
 static int g_ngrids = 0;
 static bool g_seen_f2 = false, g_seen_g2 = false;
 static int64_t g_pairs_checked = 0;
@@ -179,8 +191,9 @@ hipError_t launch_step(const StepArgs<real> &a, int waves, int, int ntiles, int 
     const GridDev &g = a.grids[a.tiles[i].g];
     check_pop(a.fin, g, "step fin");
     if (mode != kModeMoments) check_pop(a.fout, g, "step fout");
-    if (mode == kModeStash) check_range(a.rho_out + g.c_off, sizeof(real) * (size_t)g.pitch * g.ny, "stash out");
+    if (a.rho_out) check_range(a.rho_out + g.c_off, sizeof(real) * (size_t)g.pitch * g.ny, "stash out");
   }
+  if (a.rho_out && mode != kModeMoments) plane_written(a.rho_out, a.t);
   if (second) {
     g_seen_g2 = true;
     pair_check_done();
@@ -198,6 +211,7 @@ hipError_t launch_interior(const StepArgs<real> &a, int waves, int, int ntiles, 
     check_pop(a.fout, g, "int fout");
     if (a.rho_out) check_range(a.rho_out + g.c_off, sizeof(real) * (size_t)g.pitch * g.ny, "int stash out");
   }
+  if (a.rho_out) plane_written(a.rho_out, a.t);
   return hipSuccess;
 }
 template <typename real>
@@ -258,6 +272,10 @@ hipError_t launch_fused2(const StepArgs<real> &a, int waves, int ntiles, hipStre
         g_cov[t.g][c] += 1;
         out[c] = seq;
       }
+  }
+  if (a.rho_out) {
+    plane_written(a.rho_out, a.t);
+    plane_written(a.rho_out2, a.t + 1);
   }
   g_seen_f2 = true;
   pair_check_done();
@@ -322,6 +340,7 @@ static hipError_t adj_common(const AdjArgs<real> &a, int waves, int ntiles, bool
     g_adj_mid = a.fout;
   }
   const bool second = !interior && g_adj_mid && (const void *)a.fin == g_adj_mid;
+  plane_read(a.rho, a.t, interior ? "adjoint interior launch" : "adjoint general launch");
   if (second && g_adj_seen_g2) { fprintf(stderr, "two second adjoint steps in one pair\n"); abort(); }
   const int W = 64 * waves;
   for (int i = 0; i < ntiles; ++i) {
@@ -406,6 +425,8 @@ hipError_t launch_adjoint_fused2(const AdjArgs<real> &a, int waves, int ntiles, 
   for (int64_t fe = 0; fe < a.f_elems; ++g_adj_ngrids)
     fe = a.grids[g_adj_ngrids].f_off + 9 * (int64_t)a.grids[g_adj_ngrids].pitch * a.grids[g_adj_ngrids].ny;
   if (g_adj_seen_f2) { fprintf(stderr, "two adjoint two-step launches in one pair\n"); abort(); }
+  plane_read(a.rho, a.t, "adjoint two-step launch, rho(t)");
+  plane_read(a.rho2, a.t - 1, "adjoint two-step launch, rho(t-1)");
   const int64_t seq = g_seq++;
   for (int g = 0; g < g_adj_ngrids; ++g) adj_cov(g, a.grids[g]);
   for (int i = 0; i < ntiles; ++i) {

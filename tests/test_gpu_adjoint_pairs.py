@@ -52,7 +52,7 @@ def _problem(bc, rr, nx, ny, seed, medium="field", tau=0.9, sponge=6, rec_rows=(
                    sources=src, receivers=np.asarray(rec, np.int32), comp_mask=3, nsteps=0)
 
 
-def _gpu_adjoint(probs, T, seg, dtype, residuals, launch, chunks):
+def _gpu_adjoint(probs, T, seg, dtype, residuals, launch, chunks, resident=0):
     """The adjoint through the C ABI; every other chunk through the timed
     adjoint step, whose kernel counts come back with the results."""
     import torch
@@ -60,7 +60,7 @@ def _gpu_adjoint(probs, T, seg, dtype, residuals, launch, chunks):
     s = Solver(probs, dtype=dtype, trace_steps=T, launch=launch)
     fused_launches = 0
     try:
-        s.adjoint_begin(T, seg)
+        s.adjoint_begin(T, seg, resident_steps=resident)
         s.step(T)
         keep = []
         for g, p in enumerate(probs):
@@ -80,7 +80,8 @@ def _gpu_adjoint(probs, T, seg, dtype, residuals, launch, chunks):
         assert s.adjoint_time == 0
         out = [{"adj": s.adjoint_state(g).double().cpu().numpy(),
                 "grad_kappa": keep[g][1].cpu().numpy(),
-                "grad_amp": keep[g][2].cpu().numpy()[:len(p.sources)]}
+                "grad_amp": keep[g][2].cpu().numpy()[:len(p.sources)],
+                "trace": s.traces[g].double().cpu().numpy()}
                for g, p in enumerate(probs)]
         torch.cuda.synchronize()
     finally:
@@ -168,3 +169,27 @@ def test_batched_adjoint_pairs_and_partial_blocks(dtype):
     for g, p in enumerate(probs):
         ref = stepper.adjoint(p, nsteps=T, residual=res[g])
         _check(f"batched grid {g} ({p.nx}x{p.ny}) {dtype}", dtype, got[g], ref, one[g])
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("fuse_rows", [8, 0], ids=["pairs", "single_steps"])
+def test_kept_densities_equal_the_recompute(fuse_rows, dtype):
+    """A workspace beyond the minimum keeps the densities of the last
+    segments from the recorded forward run (written as it goes, receivers
+    recorded as usual), and the adjoint skips their recompute: traces, adjoint
+    state and dL/dkappa are those of the run that recomputes every segment,
+    bit for bit; dL/damp to rounding (pairs may then span two kept segments).
+    Kept: none, the last (short) segment, three segments, all."""
+    p = _problem((BC_FREE, BC_RIGID, BC_PERIODIC, BC_PERIODIC), 150, 300, 200, seed=21)
+    T, seg = 40, 7
+    res = np.random.default_rng(8).standard_normal((T, p.nrec, p.ncomp))
+    launch = dict(waves=2, rows=8, fuse_rows=fuse_rows)
+    base, _ = _gpu_adjoint([p], T, seg, dtype, [res], launch, [3, 37])
+    for resident in (5, 19, T):
+        got, _ = _gpu_adjoint([p], T, seg, dtype, [res], launch, [3, 37], resident=resident)
+        for k in ("trace", "adj", "grad_kappa"):
+            assert np.array_equal(got[0][k], base[0][k]), (resident, k)
+        e = rel_l2(got[0]["grad_amp"], base[0]["grad_amp"])
+        print(f"[kept densities] {dtype} fuse_rows={fuse_rows} resident={resident}: bitwise; "
+              f"dL/damp {e:.1e}", flush=True)
+        assert e <= 1e-12, (resident, e)
