@@ -456,6 +456,9 @@ def bench_adjoint(torch, w, Solver, plain_glups: float, nsteps: int = 5000,
             t_.zero_()
         for g in range(G):
             s.set_state(g, init[g], 0)
+        # the workspace is allocated once, outside the timed region (a 245 GB
+        # allocation can take seconds after other workloads freed theirs)
+        s.adjoint_reserve(nsteps, seg, kept)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)

@@ -148,14 +148,23 @@ class Solver:
         return L.lbm_autotune(self.ctx, steps)
 
     # -- adjoint ---------------------------------------------------------
+    def adjoint_reserve(self, nsteps: int, seg_steps: int = 100, resident_steps: int = 0) -> int:
+        """Allocate (or keep, when large enough) the adjoint workspace for a
+        recording of nsteps steps; returns its byte count. A workspace kept
+        across recordings spares each one a device allocation."""
+        nbytes = L.lbm_adjoint_workspace_bytes_resident(self.ctx, seg_steps, nsteps,
+                                                        resident_steps)
+        ws = getattr(self, "adj_ws", None)
+        if ws is None or ws.numel() < nbytes:
+            self.adj_ws = None       # the previous workspace goes first
+            self.adj_ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return nbytes
+
     def adjoint_begin(self, nsteps: int, seg_steps: int = 100, resident_steps: int = 0) -> None:
         """Record the next nsteps forward steps (checkpoints every seg_steps),
         keeping the densities of the last resident_steps steps (whole trailing
         segments) in HBM: those segments need no recompute."""
-        nbytes = L.lbm_adjoint_workspace_bytes_resident(self.ctx, seg_steps, nsteps,
-                                                        resident_steps)
-        self.adj_ws = None           # a previous recording's workspace goes first
-        self.adj_ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        nbytes = self.adjoint_reserve(nsteps, seg_steps, resident_steps)
         L.lbm_adjoint_begin(self.ctx, seg_steps, nsteps, self.adj_ws.data_ptr(), nbytes)
         self._adj_keep = {}
 
