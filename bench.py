@@ -457,8 +457,17 @@ def bench_adjoint(torch, w, Solver, plain_glups: float, nsteps: int = 5000,
         for g in range(G):
             s.set_state(g, init[g], 0)
         # the workspace is allocated once, outside the timed region (a 245 GB
-        # allocation can take seconds after other workloads freed theirs)
-        s.adjoint_reserve(nsteps, seg, kept)
+        # allocation can take seconds after other workloads freed theirs);
+        # fewer kept steps if the device refuses it
+        while True:
+            try:
+                s.adjoint_reserve(nsteps, seg, kept)
+                break
+            except torch.cuda.OutOfMemoryError:
+                if kept == 0:
+                    raise
+                kept //= 2
+                torch.cuda.empty_cache()
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -478,16 +487,18 @@ def bench_adjoint(torch, w, Solver, plain_glups: float, nsteps: int = 5000,
         e2.record()
         torch.cuda.synchronize()
         t_all = e0.elapsed_time(e2)
-        return {"gradient_GLUPS": round(cells * nsteps / (t_all / 1e3) / 1e9, 3),
+        return {"kept_density_steps": kept,
+                "gradient_GLUPS": round(cells * nsteps / (t_all / 1e3) / 1e9, 3),
                 "ms_total": round(t_all, 1), "ms_forward_recorded": round(e0.elapsed_time(e1), 1),
                 "misfit": float(sum(m.item() for m in mis)),
                 "gradients_finite": bool(torch.isfinite(gl).all().item()
                                          and torch.isfinite(gm).all().item()),
                 "gl": gl.clone()}
 
-    kept = kept_density_steps(torch, s, seg, nsteps)
-    with_kept = gradient(kept)
+    with_kept = gradient(kept_density_steps(torch, s, seg, nsteps))
+    kept = with_kept.pop("kept_density_steps")
     recompute = gradient(0)
+    recompute.pop("kept_density_steps")
     same = bool(torch.equal(with_kept.pop("gl"), recompute.pop("gl")))
     del init
     kernels = adjoint_kernel_roofline(torch, s, seg)
