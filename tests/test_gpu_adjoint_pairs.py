@@ -193,3 +193,62 @@ def test_kept_densities_equal_the_recompute(fuse_rows, dtype):
         print(f"[kept densities] {dtype} fuse_rows={fuse_rows} resident={resident}: bitwise; "
               f"dL/damp {e:.1e}", flush=True)
         assert e <= 1e-12, (resident, e)
+
+
+def test_gradient_matches_central_differences_of_the_gpu_misfit():
+    """dL/dlambda and dL/dmu of the GPU adjoint (two-step path, FP64) against
+    central differences of the GPU forward's own misfit, at six cells within
+    the wavefield's reach: beside the sources, under the free surface, near
+    the receiver row through the grid. Independent of the oracle: both sides
+    come from the kernels."""
+    import torch
+    from paper_2009_06404_amd import Solver
+    p = _problem((BC_FREE0, BC_RIGID, BC_PERIODIC, BC_PERIODIC), -1, 300, 100, seed=31,
+                 rec_rows=(0, 50))
+    T, seg = 60, 13
+    launch = dict(waves=2, rows=8, fuse_rows=8)
+    lam, mu, rho = p.medium.full(p.ny, p.nx)
+    d_obs = np.random.default_rng(2).standard_normal((T, p.nrec, p.ncomp)) * 1e-3
+
+    def misfit(lam_, mu_):
+        q = p.replace(medium=Medium("field", lam_, mu_, rho))
+        s = Solver(q, dtype="f64", trace_steps=T, launch=launch)
+        try:
+            s.step(T)
+            m, _ = s.misfit(0, torch.as_tensor(d_obs))
+            return float(m.item())
+        finally:
+            s.close()
+
+    s = Solver(p, dtype="f64", trace_steps=T, launch=launch)
+    try:
+        s.adjoint_begin(T, seg)
+        s.step(T)
+        _, res = s.misfit(0, torch.as_tensor(d_obs))
+        gk = torch.zeros((p.ny, p.nx), dtype=torch.float64, device=s.device)
+        s.adjoint_set_io(0, res, gk, None)
+        kt = s.adjoint_step_timed(T)
+        assert kt["fused_cells"] > 0
+        gl = torch.zeros_like(gk)
+        gm = torch.zeros_like(gk)
+        s.lame_gradient(0, gk, gl, gm)
+        gl, gm = gl.cpu().numpy(), gm.cpu().numpy()
+    finally:
+        s.close()
+    # within the wavefield's reach over 60 steps: near the sources (45, 20)
+    # and (240, 75), under the surface, beside the receiver row 50, in a block
+    cells = [(45, 22), (30, 6), (60, 42), (230, 80), (246, 68), (240, 56)]
+    for x, y in cells:
+        for name, field, g in (("lambda", lam, gl), ("mu", mu, gm)):
+            h = 1e-5 * field[y, x]
+            plus, minus = field.copy(), field.copy()
+            plus[y, x] += h
+            minus[y, x] -= h
+            if name == "lambda":
+                fd = (misfit(plus, mu) - misfit(minus, mu)) / (2 * h)
+            else:
+                fd = (misfit(lam, plus) - misfit(lam, minus)) / (2 * h)
+            e = abs(g[y, x] - fd) / max(abs(fd), 1e-30)
+            print(f"[central differences] dL/d{name} at ({x},{y}): adjoint {g[y, x]:.6e}, "
+                  f"differences {fd:.6e}, rel {e:.1e}", flush=True)
+            assert abs(fd) > 0 and e <= 1e-5, (name, x, y, g[y, x], fd)
