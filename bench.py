@@ -311,6 +311,7 @@ def bench_volume(torch, dtype: str = "f32", n: int = 256, steps: int = 400, warm
     kt = s.step_timed(50)
     ok = bool(torch.isfinite(s.state()).all().item())
     tile = s.tile()
+    width = s.lean_width
     s.close()
     esize = 4 if dtype == "f32" else 8
     per_cell = 2 * q * esize
@@ -325,7 +326,7 @@ def bench_volume(torch, dtype: str = "f32", n: int = 256, steps: int = 400, warm
             "kernel_GBps": round(gbps, 1), "frac": round(gbps / HBM_PEAK_GBS, 4),
             "general_kernel": {"cells_per_launch": kt["general_cells"],
                                "ms_per_launch": round(kt["general_ms"], 5)},
-            "tile": list(tile), "state_finite": ok,
+            "tile": list(tile), "lean_tile_columns": width, "state_finite": ok,
             **({"cpu_baseline": cpu_baseline3(p)} if cpu else {})}
 
 

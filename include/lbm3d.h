@@ -148,14 +148,27 @@ int lbm3_get_time(const lbm3_ctx *ctx, int64_t *t);
 int lbm3_get_state(lbm3_ctx *ctx, void *dst);
 int lbm3_set_state(lbm3_ctx *ctx, const void *src, int64_t t);
 
-/* Workgroup tile: 64 columns by rows_y (2, 6 or 14) rows, marching planes_z
- * planes (>= 1) in z. Defaults: rows_y 6 and planes_z 16 (fewer when a plane
- * has too few tiles for 2048 workgroups); planes_z = 0 selects the default.
- * The tiles near faces, sources and receivers run in chunks of at most 4
- * planes, and of 2 rows when rows_y is 14. No tile shape changes the results.
- * Returns LBM_OK or LBM_E_INVALID. Host only. */
+/* Workgroup tile: 64 columns (128 for the lean tiles of an FP32 context by
+ * default, below) by rows_y (2, 6 or 14) rows, marching planes_z planes
+ * (>= 1) in z. Defaults: rows_y 6 and planes_z 16 (12 with 128-column
+ * tiles; fewer when a plane has too few tiles for 2048 workgroups, 1536 with
+ * 128-column tiles); planes_z = 0
+ * selects the default. The tiles near faces, sources and receivers run in
+ * 64-column chunks of at most 4 planes, and of 2 rows when rows_y is 14. No
+ * tile shape changes the results. Returns LBM_OK or LBM_E_INVALID. Host
+ * only. */
 int lbm3_set_tile(lbm3_ctx *ctx, int32_t rows_y, int32_t planes_z);
 int lbm3_get_tile(const lbm3_ctx *ctx, int32_t *rows_y, int32_t *planes_z);
+
+/* Width in columns of the tiles clear of faces, sources and receivers (the
+ * bulk of the streaming and collision of eq. LBGK, Sec. 2): 64, or 128 (two
+ * wavefronts per row of a tile, each population row read as 512 contiguous
+ * bytes). 128 needs an FP32 context and is its default (LBM_E_INVALID for
+ * FP64); rows_y 14 always runs 64. The results do not depend on it. get
+ * reports the width the next step uses; planes_z keeps its value (pass
+ * planes_z = 0 to lbm3_set_tile for the default of the new width). Host only. */
+int lbm3_set_lean_width(lbm3_ctx *ctx, int32_t columns);
+int lbm3_get_lean_width(const lbm3_ctx *ctx, int32_t *columns);
 
 /* Largest von Neumann amplification factor of one bulk step (periodic, no
  * sponge, no source; Sec. 4's analysis carried to the q-velocity set) over an

@@ -11,8 +11,8 @@ from ._lib import LBM_WARN_UNSTABLE, LBMError, check, last_error, lib as _lib2d 
 ENTRY_POINTS = (
     "lbm3_workspace_bytes", "lbm3_init", "lbm3_set_sources", "lbm3_set_receivers",
     "lbm3_step", "lbm3_step_timed", "lbm3_moments", "lbm3_get_time", "lbm3_get_state",
-    "lbm3_set_state", "lbm3_set_tile", "lbm3_get_tile", "lbm3_destroy", "lbm3_vn_growth",
-    "lbm3_stability",
+    "lbm3_set_state", "lbm3_set_tile", "lbm3_get_tile", "lbm3_set_lean_width",
+    "lbm3_get_lean_width", "lbm3_destroy", "lbm3_vn_growth", "lbm3_stability",
 )
 
 FACE_TOP, FACE_BOTTOM, FACE_LEFT, FACE_RIGHT, FACE_FRONT, FACE_BACK = range(6)
@@ -58,6 +58,8 @@ def lib():
             "lbm3_set_state": ([vp, vp, i64], C.c_int),
             "lbm3_set_tile": ([vp, i32, i32], C.c_int),
             "lbm3_get_tile": ([vp, C.POINTER(i32), C.POINTER(i32)], C.c_int),
+            "lbm3_set_lean_width": ([vp, i32], C.c_int),
+            "lbm3_get_lean_width": ([vp, C.POINTER(i32)], C.c_int),
             "lbm3_destroy": ([vp], C.c_int),
             "lbm3_vn_growth": ([i32, C.c_double, C.c_double, i32, C.POINTER(C.c_double)], C.c_int),
             "lbm3_stability": ([vp, C.POINTER(C.c_double)], C.c_int),
@@ -164,6 +166,16 @@ def lbm3_get_tile(ctx):
     p = C.c_int32(0)
     check(lib().lbm3_get_tile(ctx, C.byref(r), C.byref(p)))
     return r.value, p.value
+
+
+def lbm3_set_lean_width(ctx, columns: int) -> None:
+    check(lib().lbm3_set_lean_width(ctx, columns))
+
+
+def lbm3_get_lean_width(ctx) -> int:
+    c = C.c_int32(0)
+    check(lib().lbm3_get_lean_width(ctx, C.byref(c)))
+    return c.value
 
 
 def lbm3_destroy(ctx) -> None:

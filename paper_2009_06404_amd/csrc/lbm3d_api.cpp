@@ -102,6 +102,7 @@ struct lbm3_ctx {
   int64_t t = 0;
   const void *rho0 = nullptr;       // caller's density field (receiver scales)
   int32_t rows_y = 6, planes_z = 0;
+  int32_t lean_width = 64;          // columns of a lean tile asked for (64 or 128)
   Vol3Dev v{};
   DBuf<char> d_damp, d_rec_scale;
   DBuf<Src3Dev> d_src;
@@ -130,19 +131,31 @@ bool f64(const lbm3_ctx *c) { return c->dtype == LBM_F64; }
 // VGPRs its 1024-lane workgroup allows and spills to scratch.
 int general_rows(const lbm3_ctx *c) { return c->rows_y == 14 ? 2 : c->rows_y; }
 
+// Width of the lean tiles: 128 columns (two wavefronts per row, so each
+// population row a workgroup reads is 512 contiguous bytes in FP32) where the
+// setting asks for it and the kernel exists (FP32, tiles of 2 or 6 rows: the
+// FP64 kernel needs more registers than a 1024-lane workgroup allows), else
+// 64. The general and field tiles are always 64 columns wide.
+bool wide_ok(const lbm3_ctx *c) { return c->dtype == LBM_F32; }
+int lean_tx(const lbm3_ctx *c) { return c->lean_width == 128 && wide_ok(c) && c->rows_y != 14 ? 128 : 64; }
+
 // General tiles are cut into z chunks of at most this many planes: more,
 // shorter workgroups, which hide beside the lean launch better than a few
 // that march a whole segment (256^3 half-space, FP32: D3Q19 0.625 against
 // 0.631 ms per step, D3Q27 0.897 against 0.930, with the general launch first).
 constexpr int kGeneralPlanes = 4;
 
-int default_planes(const lbm3_ctx *c, int rows_y) {
-  // segments of 16 planes (each re-pulls one plane before and after it: 1/8
-  // more reads, from L2), shorter when the volume has too few tiles per plane
-  // for 2048 workgroups (8 per CU)
-  const int64_t tiles = (int64_t)((c->nx + 63) / 64) * ((c->ny + rows_y - 1) / rows_y);
-  const int64_t nseg = std::max<int64_t>(1, (2048 + tiles - 1) / tiles);
-  const int64_t pz = std::max<int64_t>(4, std::min<int64_t>(16, (c->nz + nseg - 1) / nseg));
+int default_planes(const lbm3_ctx *c, int rows_y, int tx) {
+  // segments of 16 planes (12 with 128-column tiles; each re-pulls one plane
+  // before and after it, mostly from L2), shorter when the volume has too few
+  // tiles per plane for 2048 workgroups (8 per CU; 1536 of the 1024-lane
+  // workgroups of 128-column tiles, one per CU at a time). 256^3 half-space,
+  // FP32, 128-column tiles, whole step: D3Q19 28.3 GLUPS at 12 planes, 28.1
+  // at 8, 26.8 at 6; D3Q27 20.4, 20.0 and 19.4.
+  const int64_t tiles = (int64_t)((c->nx + tx - 1) / tx) * ((c->ny + rows_y - 1) / rows_y);
+  const int64_t target = tx == 128 ? 1536 : 2048, cap = tx == 128 ? 12 : 16;
+  const int64_t nseg = std::max<int64_t>(1, (target + tiles - 1) / tiles);
+  const int64_t pz = std::max<int64_t>(4, std::min<int64_t>(cap, (c->nz + nseg - 1) / nseg));
   return (int)std::min<int64_t>(pz, c->nz);
 }
 
@@ -177,18 +190,19 @@ double axis_gap(double s, int a, int b, int n, bool periodic) {
 // no source within 9 sigma of a cell, no receiver) and the general list.
 int build_tiles(lbm3_ctx *c) {
   const int nx = c->nx, ny = c->ny, nz = c->nz, ty = c->rows_y;
+  const int tw = lean_tx(c);   // tile width of the lean and general split
   const bool xper = c->bc.face[LBM3_FACE_LEFT] == LBM_PERIODIC;
   const bool yper = c->bc.face[LBM3_FACE_FRONT] == LBM_PERIODIC;
   const bool zper = c->bc.face[LBM3_FACE_TOP] == LBM_PERIODIC;
   const auto segs = z_segments(c);
-  const int ntx = (nx + 63) / 64, nty = (ny + ty - 1) / ty, ns = (int)segs.size();
+  const int ntx = (nx + tw - 1) / tw, nty = (ny + ty - 1) / ty, ns = (int)segs.size();
   std::vector<char> rec(static_cast<size_t>(ntx) * nty * ns, 0);
   std::vector<int> seg_of(nz);
   for (int k = 0; k < ns; ++k)
     for (int z = segs[k].first; z < segs[k].second; ++z) seg_of[z] = k;
   for (size_t r = 0; r + 2 < c->rec_xyz.size(); r += 3) {
     const int x = c->rec_xyz[r], y = c->rec_xyz[r + 1], z = c->rec_xyz[r + 2];
-    rec[((size_t)seg_of[z] * nty + y / ty) * ntx + x / 64] = 1;
+    rec[((size_t)seg_of[z] * nty + y / ty) * ntx + x / tw] = 1;
   }
   std::vector<Tile3Dev> lean, gen, all;
   int64_t lean_cells = 0, gen_cells = 0;
@@ -197,7 +211,7 @@ int build_tiles(lbm3_ctx *c) {
     for (int j = 0; j < nty; ++j) {
       const int y0 = j * ty, h = std::min(ty, ny - y0);
       for (int i = 0; i < ntx; ++i) {
-        const int x0 = i * 64, w = std::min(64, nx - x0);
+        const int x0 = i * tw, w = std::min(tw, nx - x0);
         bool general = rec[((size_t)k * nty + j) * ntx + i] != 0;
         // pulled cells: [x0-1, x0+w] x [y0-1, y0+h] x [z0-1, z1]
         if (!xper && (x0 - 1 <= 0 || x0 + w >= nx - 1)) general = true;
@@ -212,11 +226,14 @@ int build_tiles(lbm3_ctx *c) {
         const Tile3Dev t{x0, y0, z0, z1};
         const int64_t cells = (int64_t)w * h * (z1 - z0);
         const int gr = general_rows(c);
-        for (int ys = y0; ys < y0 + h; ys += gr) all.push_back(Tile3Dev{x0, ys, z0, z1});
+        // the general and field kernels take 64-column tiles
+        for (int xs = x0; xs < x0 + w; xs += 64)
+          for (int ys = y0; ys < y0 + h; ys += gr) all.push_back(Tile3Dev{xs, ys, z0, z1});
         if (general) {
-          for (int ys = y0; ys < y0 + h; ys += gr)
-            for (int zs = z0; zs < z1; zs += kGeneralPlanes)
-              gen.push_back(Tile3Dev{x0, ys, zs, std::min(zs + kGeneralPlanes, z1)});
+          for (int xs = x0; xs < x0 + w; xs += 64)
+            for (int ys = y0; ys < y0 + h; ys += gr)
+              for (int zs = z0; zs < z1; zs += kGeneralPlanes)
+                gen.push_back(Tile3Dev{xs, ys, zs, std::min(zs + kGeneralPlanes, z1)});
           gen_cells += cells;
         } else {
           lean.push_back(t);
@@ -240,8 +257,9 @@ int launch_list(lbm3_ctx *c, bool general, const Tile3Dev *tiles, int n, const v
                 void *fout, void *out10, int mode) {
   if (n <= 0) return LBM_OK;
   c->v.omega = 1.0 / c->tau;
-  const int rc = launch_step3(f64(c), general, general ? general_rows(c) : c->rows_y, tiles, n, fin,
-                              fout, out10, c->v, c->t, mode, c->stream);
+  const int rc = launch_step3(f64(c), general, general ? general_rows(c) : c->rows_y,
+                              general ? 64 : lean_tx(c), tiles, n, fin, fout, out10, c->v, c->t,
+                              mode, c->stream);
   if (rc != 0) return fail3(LBM_E_DEVICE, std::string("step launch: ") + hipGetErrorString((hipError_t)rc));
   return LBM_OK;
 }
@@ -469,7 +487,8 @@ int lbm3_init(lbm3_ctx **ctx, int32_t nx, int32_t ny, int32_t nz, int32_t q, int
   v.damp = c->d_damp.p;
   v.src = c->d_src.p;
   v.rec_row = nullptr;
-  c->planes_z = default_planes(c, c->rows_y);
+  c->lean_width = wide_ok(c) ? 128 : 64;
+  c->planes_z = default_planes(c, c->rows_y, lean_tx(c));
   // the profiles were only needed for the damping table
   for (int f = 0; f < 6; ++f) c->bc.profile[f] = nullptr;
   if ((rc = build_tiles(c))) return bail(rc);
@@ -636,8 +655,22 @@ int lbm3_set_tile(lbm3_ctx *c, int32_t rows_y, int32_t planes_z) {
   if (rows_y != 2 && rows_y != 6 && rows_y != 14) return fail3(LBM_E_INVALID, "rows_y must be 2, 6 or 14");
   if (planes_z < 0) return fail3(LBM_E_INVALID, "planes_z must be >= 0 (0: default)");
   c->rows_y = rows_y;
-  c->planes_z = planes_z == 0 ? default_planes(c, rows_y) : std::min(planes_z, c->nz);
+  c->planes_z = planes_z == 0 ? default_planes(c, rows_y, lean_tx(c)) : std::min(planes_z, c->nz);
   return build_tiles(c);
+}
+
+int lbm3_set_lean_width(lbm3_ctx *c, int32_t columns) {
+  if (!c) return fail3(LBM_E_INVALID, "null context");
+  if (columns != 64 && columns != 128) return fail3(LBM_E_INVALID, "columns must be 64 or 128");
+  if (columns == 128 && !wide_ok(c)) return fail3(LBM_E_INVALID, "128-column tiles need an FP32 context");
+  c->lean_width = columns;
+  return build_tiles(c);
+}
+
+int lbm3_get_lean_width(const lbm3_ctx *c, int32_t *columns) {
+  if (!c || !columns) return fail3(LBM_E_INVALID, "context and columns required");
+  *columns = lean_tx(c);
+  return LBM_OK;
 }
 
 int lbm3_get_tile(const lbm3_ctx *c, int32_t *rows_y, int32_t *planes_z) {

@@ -43,8 +43,9 @@ struct Vol3Dev {
   int32_t nrec, comp_mask;
 };
 
-// One workgroup's work: columns [x0, x0 + 64) and rows [y0, y0 + rows_y) of
-// the volume (clipped to it), planes [z0, z1).
+// One workgroup's work: columns [x0, x0 + tx) (tx = 64, or 128 for wide lean
+// tiles) and rows [y0, y0 + rows_y) of the volume (clipped to it), planes
+// [z0, z1).
 struct Tile3Dev {
   int32_t x0, y0, z0, z1;
 };
@@ -56,7 +57,9 @@ struct Tile3Dev {
 // [10][nz][ny][nx]). general = false: the lean kernel, for tiles none of whose
 // pulled cells lies on a non-periodic face and which hold no source or
 // receiver cell; general = true: the kernel with every rule (mode 1 always).
-int launch_step3(bool f64, bool general, int rows_y, const Tile3Dev *tiles, int ntiles,
+// tx: tile width, 64, or 128 for the lean FP32 steps in tiles of 2 or 6 rows
+// (hipErrorInvalidValue otherwise).
+int launch_step3(bool f64, bool general, int rows_y, int tx, const Tile3Dev *tiles, int ntiles,
                  const void *fin, void *fout, void *out10, const Vol3Dev &v, int64_t t, int mode,
                  hipStream_t s);
 

@@ -2,14 +2,15 @@
 // evaluation of the macroscopic fields), HBM-bound at 2 x Q population words
 // per cell. Q, the velocity set, is a template parameter of every kernel.
 //
-// Work decomposition. A workgroup owns a tile of 64 columns by TY rows and a
-// segment of planes in z, and marches the segment plane by plane. It runs
-// 64 x (TY + 2) lanes: lane (lx, ly) with 1 <= ly <= TY owns cell
-// (x0 + lx, y0 + ly - 1); the rows ly = 0 and TY + 1 are halo lanes that
-// compute the density of the rows just outside the tile (and, in their first
-// TY lanes, of the columns just left and right of it). The density of each
-// plane is gathered in a (TY + 2) x 66 LDS tile, double-buffered by plane
-// parity, for the x and y differences of eq. FDrho; the z difference uses the
+// Work decomposition. A workgroup owns a tile of TX columns (64, or 128 for
+// the wide FP32 lean tiles) by TY rows and a segment of planes in z, and
+// marches the segment plane by plane. It runs TX x (TY + 2) lanes: lane
+// (lx, ly) with 1 <= ly <= TY owns cell (x0 + lx, y0 + ly - 1); the rows
+// ly = 0 and TY + 1 are halo lanes that compute the density of the rows just
+// outside the tile (and, in their first TY lanes, of the columns just left
+// and right of it). The density of each plane is gathered in a
+// (TY + 2) x (TX + 2) LDS tile, double-buffered by plane parity, for the x
+// and y differences of eq. FDrho; the z difference uses the
 // density of the planes before and after, kept in registers. Each lane pulls
 // the populations of plane z + 1 (streaming of eq. LBGK, with the face rules)
 // while the tile's LDS holds plane z, so one barrier per plane suffices.
@@ -184,13 +185,114 @@ __device__ __forceinline__ real apply_faces(const Vol3Dev &v, rsrc_t R0, rsrc_t 
   return rho;
 }
 
+// Moments of a cell's pulled populations: the first (m) and the second (P).
+template <typename real>
+struct Mom3 {
+  real mx, my, mz, pxx, pxy, pxz, pyy, pyz, pzz;
+};
+
+template <typename real, int Q>
+__device__ __forceinline__ Mom3<real> moments3(const real (&f)[Q]) {
+  Mom3<real> m;
+  m.mx = m.my = m.mz = m.pxx = m.pxy = m.pxz = m.pyy = m.pyz = m.pzz = real(0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const real fi = f[i];
+    if (cxv(i) != 0) { m.mx += real(cxv(i)) * fi; m.pxx += fi; }
+    if (cyv(i) != 0) { m.my += real(cyv(i)) * fi; m.pyy += fi; }
+    if (czv(i) != 0) { m.mz += real(czv(i)) * fi; m.pzz += fi; }
+    if (cxv(i) * cyv(i) != 0) m.pxy += real(cxv(i) * cyv(i)) * fi;
+    if (cxv(i) * czv(i) != 0) m.pxz += real(cxv(i) * czv(i)) * fi;
+    if (cyv(i) * czv(i) != 0) m.pyz += real(cyv(i) * czv(i)) * fi;
+  }
+  return m;
+}
+
+// Flux with the implicit sponge (eq. MomentChainAbsorbing): j = (m + G/2) / (1 + A/2).
+template <typename real>
+__device__ __forceinline__ void flux3(const Mom3<real> &m, real Gx, real Gy, real Gz, real A, real &jx,
+                                      real &jy, real &jz) {
+  const real inv = real(1) / (real(1) + real(0.5) * A);
+  jx = (m.mx + real(0.5) * Gx) * inv;
+  jy = (m.my + real(0.5) * Gy) * inv;
+  jz = (m.mz + real(0.5) * Gz) * inv;
+}
+
+// What the collision of a cell needs besides its populations: rho, j, the
+// source S = G - A j, and P^n = P - rho b^2 I (eq. Pn) with its trace part.
+template <typename real>
+struct Coll3 {
+  real rc, jx, jy, jz, Sx, Sy, Sz, nxx, nyy, nzz, pxy, pxz, pyz, btr;
+};
+
+template <typename real>
+__device__ __forceinline__ Coll3<real> coll3(const Mom3<real> &m, real rc, real jx, real jy, real jz,
+                                             real Gx, real Gy, real Gz, real A) {
+  Coll3<real> c;
+  c.rc = rc;
+  c.jx = jx;
+  c.jy = jy;
+  c.jz = jz;
+  c.Sx = Gx - A * jx;
+  c.Sy = Gy - A * jy;
+  c.Sz = Gz - A * jz;
+  const real b2 = real(1) / real(3);
+  c.nxx = m.pxx - b2 * rc;
+  c.nyy = m.pyy - b2 * rc;
+  c.nzz = m.pzz - b2 * rc;
+  c.btr = b2 * (c.nxx + c.nyy + c.nzz);
+  c.pxy = m.pxy;
+  c.pxz = m.pxz;
+  c.pyz = m.pyz;
+  return c;
+}
+
+// Post-collision population i: BGK (eq. LBGK) toward the equilibrium of eq.
+// equilibrium-solid, w (rho + j.c / b^2 + P^n:(c c - b^2 I) / (2 b^4)), with
+// the source of eq. Si. The products with a zero velocity component are left
+// out of the sums (they would add exact zeros): the nonzero terms are summed
+// in the order of the full expressions.
+template <typename real>
+__device__ __forceinline__ void sum_in(real &acc, bool &any, real t) {
+  acc = any ? acc + t : t;
+  any = true;
+}
+
+template <typename real, int Q>
+__device__ __forceinline__ real post3(int i, real f, const Coll3<real> &c, real om, real src_w) {
+  const int ix = cxv(i), iy = cyv(i), iz = czv(i);
+  const real cx = real(ix), cy = real(iy), cz = real(iz);
+  // P^n : (c c - b^2 I) = sum of P^n_ab c_a c_b - b^2 tr P^n
+  real d = real(0), o = real(0);
+  bool hd = false, ho = false;
+  if (ix != 0) sum_in(d, hd, c.nxx * cx * cx);
+  if (iy != 0) sum_in(d, hd, c.nyy * cy * cy);
+  if (iz != 0) sum_in(d, hd, c.nzz * cz * cz);
+  if (ix * iy != 0) sum_in(o, ho, c.pxy * cx * cy);
+  if (ix * iz != 0) sum_in(o, ho, c.pxz * cx * cz);
+  if (iy * iz != 0) sum_in(o, ho, c.pyz * cy * cz);
+  if (ho) d = d + real(2) * o;
+  const real q = hd ? d - c.btr : -c.btr;
+  real jc = real(0), sc = real(0);
+  bool hj = false, hs = false;
+  if (ix != 0) { sum_in(jc, hj, c.jx * cx); sum_in(sc, hs, c.Sx * cx); }
+  if (iy != 0) { sum_in(jc, hj, c.jy * cy); sum_in(sc, hs, c.Sy * cy); }
+  if (iz != 0) { sum_in(jc, hj, c.jz * cz); sum_in(sc, hs, c.Sz * cz); }
+  const real wi = wgt<real, Q>(i);
+  const real feq = hj ? wi * (c.rc + real(3) * jc + real(4.5) * q) : wi * (c.rc + real(4.5) * q);
+  const real relaxed = f - om * (f - feq);
+  return hs ? relaxed + src_w * wi * real(3) * sc : relaxed;
+}
+
 // GENERAL = false: the lean kernel (no face rules, sources or receivers; the
 // host gives it only tiles that need none). MODE 1 (fields) is general only.
-template <typename real, int Q, int TY, int MODE, bool GENERAL>
-__global__ void __launch_bounds__(64 * (TY + 2))
+// TX = 128 (lean FP32 tiles only): two wavefronts per row, so a workgroup
+// reads each population row of a plane as 512 contiguous bytes, not 256.
+template <typename real, int Q, int TY, int MODE, bool GENERAL, int TX = 64>
+__global__ void __launch_bounds__(TX * (TY + 2))
 step3_kernel(const real *__restrict__ fin, real *__restrict__ fout, real *__restrict__ out10,
              const Vol3Dev v, int64_t t, const Tile3Dev *__restrict__ tiles, int ntiles) {
-  __shared__ real srho[2][TY + 2][66];
+  __shared__ real srho[2][TY + 2][TX + 2];
 
   // die-aware order: workgroup b runs on die b % 8; each die takes a
   // contiguous run of the list (ordered by plane segment, row, column), so
@@ -202,12 +304,12 @@ step3_kernel(const real *__restrict__ fin, real *__restrict__ fout, real *__rest
 
   const int nx = v.nx, ny = v.ny, nz = v.nz, pitch = v.pitch;
   const int x0 = tile.x0, y0 = tile.y0;
-  const int w = min(64, nx - x0), h = min(TY, ny - y0);
+  const int w = min(TX, nx - x0), h = min(TY, ny - y0);
   const int zb = tile.z0, ze = tile.z1;
   const bool zper = v.face[kFaceTop] == kPeriodic;
   const bool xper = v.face[kFaceLeft] == kPeriodic, yper = v.face[kFaceFront] == kPeriodic;
 
-  const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+  const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
   const bool interior = ly >= 1 && ly <= TY;
   const bool active = interior && lx < w && ly <= h;
   const int x = x0 + lx;
@@ -307,18 +409,7 @@ step3_kernel(const real *__restrict__ fin, real *__restrict__ fout, real *__rest
       if (!zper && z == nz - 1) rzp = real(2) * rc - rzm;
       const real gx = real(0.5) * (rr - rl), gy = real(0.5) * (rd - ru), gz = real(0.5) * (rzp - rzm);
 
-      // moments of the pulled populations
-      real mx = 0, my = 0, mz = 0, pxx = 0, pxy = 0, pxz = 0, pyy = 0, pyz = 0, pzz = 0;
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const real f = cur[i];
-        if (cxv(i) != 0) { mx += real(cxv(i)) * f; pxx += f; }
-        if (cyv(i) != 0) { my += real(cyv(i)) * f; pyy += f; }
-        if (czv(i) != 0) { mz += real(czv(i)) * f; pzz += f; }
-        if (cxv(i) * cyv(i) != 0) pxy += real(cxv(i) * cyv(i)) * f;
-        if (cxv(i) * czv(i) != 0) pxz += real(cxv(i) * czv(i)) * f;
-        if (cyv(i) * czv(i) != 0) pyz += real(cyv(i) * czv(i)) * f;
-      }
+      const Mom3<real> m = moments3<real, Q>(cur);
       // source G = kappa grad(rho) + F (eq. S, Sec. 5)
       const real kap_c = v.kcells ? kap[((int64_t)z * ny + y) * pitch + x] : real(v.kscalar);
       real Gx = kap_c * gx, Gy = kap_c * gy, Gz = kap_c * gz;
@@ -337,12 +428,10 @@ step3_kernel(const real *__restrict__ fin, real *__restrict__ fout, real *__rest
         Gy += real(mag * sd.dir_y);
         Gz += real(mag * sd.dir_z);
       }
-      // flux with the implicit sponge (eq. MomentChainAbsorbing)
       const real az = damp[nx + ny + z];
       const real A = Axy > az ? Axy : az;
-      const real inv = real(1) / (real(1) + real(0.5) * A);
-      const real jx = (mx + real(0.5) * Gx) * inv, jy = (my + real(0.5) * Gy) * inv,
-                 jz = (mz + real(0.5) * Gz) * inv;
+      real jx, jy, jz;
+      flux3(m, Gx, Gy, Gz, A, jx, jy, jz);
 
       if (GENERAL && MODE == 0 && v.rec_row && v.rec_plane[z]) {
         const int64_t row = t - v.trace_t0;
@@ -376,34 +465,19 @@ step3_kernel(const real *__restrict__ fin, real *__restrict__ fout, real *__rest
         o[N] = jx;
         o[2 * N] = jy;
         o[3 * N] = jz;
-        o[4 * N] = pxx;
-        o[5 * N] = pxy;
-        o[6 * N] = pxz;
-        o[7 * N] = pyy;
-        o[8 * N] = pyz;
-        o[9 * N] = pzz;
+        o[4 * N] = m.pxx;
+        o[5 * N] = m.pxy;
+        o[6 * N] = m.pxz;
+        o[7 * N] = m.pyy;
+        o[8 * N] = m.pyz;
+        o[9 * N] = m.pzz;
       } else {
-        const real Sx = Gx - A * jx, Sy = Gy - A * jy, Sz = Gz - A * jz;
-        const real b2 = real(1) / real(3);
-        // P^n = P - rho b^2 I (eq. Pn); its trace part of P^n : (c c - b^2 I)
-        const real nxx = pxx - b2 * rc, nyy = pyy - b2 * rc, nzz = pzz - b2 * rc;
-        const real btr = b2 * (nxx + nyy + nzz);
+        const Coll3<real> c = coll3(m, rc, jx, jy, jz, Gx, Gy, Gz, A);
         const rsrc_t O = lbm::dev::tile_rsrc(fout + (int64_t)z * v.zplane);
         const uint32_t own = (uint32_t)(y * Q * pitch + x) * (uint32_t)sizeof(real);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          const real cx = real(cxv(i)), cy = real(cyv(i)), cz = real(czv(i));
-          const real q = nxx * cx * cx + nyy * cy * cy + nzz * cz * cz +
-                         real(2) * (pxy * cx * cy + pxz * cx * cz + pyz * cy * cz) - btr;
-          const real jc = jx * cx + jy * cy + jz * cz;
-          const real sc = Sx * cx + Sy * cy + Sz * cz;
-          const real wi = wgt<real, Q>(i);
-          // equilibrium (eq. equilibrium-solid): w (rho + j.c / b^2 + P^n:Q / (2 b^4))
-          const real feq = wi * (rc + real(3) * jc + real(4.5) * q);
-          // BGK (eq. LBGK) with the source of eq. Si
-          Buf<real>::store_nt(cur[i] - om * (cur[i] - feq) + src_w * wi * real(3) * sc, O, own,
-                              (uint32_t)i * run);
-        }
+        for (int i = 0; i < Q; ++i)
+          Buf<real>::store_nt(post3<real, Q>(i, cur[i], c, om, src_w), O, own, (uint32_t)i * run);
       }
     }
     if (active && p >= zb && p < ze) srho[nslot][ly][lx + 1] = rn;
@@ -481,9 +555,20 @@ __global__ void pack3_kernel(const real *__restrict__ src, real *__restrict__ ds
 }
 
 template <typename real, int Q, int TY>
-hipError_t launch_tile(bool general, const Tile3Dev *tiles, int ntiles, const void *fin, void *fout,
-                 void *out10, const Vol3Dev &v, int64_t t, int mode, hipStream_t s) {
+hipError_t launch_tile(bool general, int tx, const Tile3Dev *tiles, int ntiles, const void *fin,
+                       void *fout, void *out10, const Vol3Dev &v, int64_t t, int mode, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
+  if (tx == 128) {
+    // wide lean tiles: FP32 steps, 2 or 6 rows (at most 1024 lanes)
+    if constexpr (sizeof(real) == 4 && TY != 14) {
+      if (general || mode != 0) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((step3_kernel<real, Q, TY, 0, false, 128>), dim3((ntiles + 7) / 8 * 8),
+                         dim3(128 * (TY + 2)), 0, s, reinterpret_cast<const real *>(fin),
+                         reinterpret_cast<real *>(fout), nullptr, v, t, tiles, ntiles);
+      return hipSuccess;
+    }
+    return hipErrorInvalidValue;
+  }
   // general tiles of 14 rows are never built (the host cuts them to 2 rows):
   // that kernel would spill
   if constexpr (TY == 14) {
@@ -511,28 +596,33 @@ hipError_t launch_tile(bool general, const Tile3Dev *tiles, int ntiles, const vo
 }
 
 template <typename real, int Q>
-hipError_t launch_rows(bool general, int rows_y, const Tile3Dev *tiles, int ntiles, const void *fin,
-                       void *fout, void *out10, const Vol3Dev &v, int64_t t, int mode, hipStream_t s) {
-  if (rows_y == 2) return launch_tile<real, Q, 2>(general, tiles, ntiles, fin, fout, out10, v, t, mode, s);
-  if (rows_y == 14) return launch_tile<real, Q, 14>(general, tiles, ntiles, fin, fout, out10, v, t, mode, s);
-  return launch_tile<real, Q, 6>(general, tiles, ntiles, fin, fout, out10, v, t, mode, s);
+hipError_t launch_rows(bool general, int rows_y, int tx, const Tile3Dev *tiles, int ntiles,
+                       const void *fin, void *fout, void *out10, const Vol3Dev &v, int64_t t, int mode,
+                       hipStream_t s) {
+  if (rows_y == 2)
+    return launch_tile<real, Q, 2>(general, tx, tiles, ntiles, fin, fout, out10, v, t, mode, s);
+  if (rows_y == 14)
+    return launch_tile<real, Q, 14>(general, tx, tiles, ntiles, fin, fout, out10, v, t, mode, s);
+  return launch_tile<real, Q, 6>(general, tx, tiles, ntiles, fin, fout, out10, v, t, mode, s);
 }
 
 template <typename real>
-hipError_t launch_lattice(bool general, int rows_y, const Tile3Dev *tiles, int ntiles, const void *fin,
-                          void *fout, void *out10, const Vol3Dev &v, int64_t t, int mode, hipStream_t s) {
+hipError_t launch_lattice(bool general, int rows_y, int tx, const Tile3Dev *tiles, int ntiles,
+                          const void *fin, void *fout, void *out10, const Vol3Dev &v, int64_t t,
+                          int mode, hipStream_t s) {
   if (v.q == kQ27)
-    return launch_rows<real, kQ27>(general, rows_y, tiles, ntiles, fin, fout, out10, v, t, mode, s);
-  return launch_rows<real, kQ19>(general, rows_y, tiles, ntiles, fin, fout, out10, v, t, mode, s);
+    return launch_rows<real, kQ27>(general, rows_y, tx, tiles, ntiles, fin, fout, out10, v, t, mode, s);
+  return launch_rows<real, kQ19>(general, rows_y, tx, tiles, ntiles, fin, fout, out10, v, t, mode, s);
 }
 
 }  // namespace
 
-int launch_step3(bool f64, bool general, int rows_y, const Tile3Dev *tiles, int ntiles,
+int launch_step3(bool f64, bool general, int rows_y, int tx, const Tile3Dev *tiles, int ntiles,
                  const void *fin, void *fout, void *out10, const Vol3Dev &v, int64_t t, int mode,
                  hipStream_t s) {
-  const hipError_t e = f64 ? launch_lattice<double>(general, rows_y, tiles, ntiles, fin, fout, out10, v, t, mode, s)
-                          : launch_lattice<float>(general, rows_y, tiles, ntiles, fin, fout, out10, v, t, mode, s);
+  const hipError_t e =
+      f64 ? launch_lattice<double>(general, rows_y, tx, tiles, ntiles, fin, fout, out10, v, t, mode, s)
+          : launch_lattice<float>(general, rows_y, tx, tiles, ntiles, fin, fout, out10, v, t, mode, s);
   if (e != hipSuccess) return (int)e;
   return (int)hipGetLastError();
 }

@@ -519,54 +519,6 @@ __global__ __launch_bounds__(64 * NW) void interior_kernel(StepArgs<real> a) {
   }
 }
 
-// Pair access for the two-column interior kernel: two consecutive elements
-// of one population run (dword-aligned multi-dword buffer accesses).
-template <typename real>
-struct Pair {
-  real a, b;
-};
-
-template <typename real>
-struct Buf2;
-
-template <>
-struct Buf2<float> {
-  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-  static __device__ __forceinline__ Pair<float> load(__amdgpu_buffer_rsrc_t r, uint32_t voff,
-                                                     uint32_t soff) {
-    const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
-    return {__uint_as_float(v.x), __uint_as_float(v.y)};
-  }
-  static __device__ __forceinline__ void store_nt(float a, float b, __amdgpu_buffer_rsrc_t r,
-                                                  uint32_t voff, uint32_t soff) {
-    u32x2 v;
-    v.x = __float_as_uint(a);
-    v.y = __float_as_uint(b);
-    __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 2);
-  }
-};
-
-template <>
-struct Buf2<double> {
-  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-  typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-  static __device__ __forceinline__ Pair<double> load(__amdgpu_buffer_rsrc_t r, uint32_t voff,
-                                                      uint32_t soff) {
-    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
-    u32x2 lo, hi;
-    lo.x = v.x; lo.y = v.y;
-    hi.x = v.z; hi.y = v.w;
-    return {__builtin_bit_cast(double, lo), __builtin_bit_cast(double, hi)};
-  }
-  static __device__ __forceinline__ void store_nt(double a, double b, __amdgpu_buffer_rsrc_t r,
-                                                  uint32_t voff, uint32_t soff) {
-    const u32x2 lo = __builtin_bit_cast(u32x2, a), hi = __builtin_bit_cast(u32x2, b);
-    u32x4 v;
-    v.x = lo.x; v.y = lo.y; v.z = hi.x; v.w = hi.y;
-    __builtin_amdgcn_raw_buffer_store_b128(v, r, voff, soff, 2);
-  }
-};
-
 // Pair of one population run shifted by one column: (x-1, x) for dir = -1,
 // (x+1, x+2) for dir = +1, with the periodic wrap for the pair that straddles
 // the x edge (two single loads there).
@@ -726,7 +678,7 @@ struct Phase {
 };
 
 template <typename real, int NW, bool STASH>
-__global__ __launch_bounds__(64 * NW + 64, sizeof(real) == 4 ? (STASH ? 4 : 5) : (STASH ? 2 : 3))
+__global__ __launch_bounds__(64 * NW + 64, sizeof(real) == 4 ? 5 : 3)
     void fused2_kernel(
     StepArgs<real> a) {
   constexpr int W = 64 * NW;

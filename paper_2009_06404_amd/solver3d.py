@@ -93,6 +93,14 @@ class Solver3:
     def set_tile(self, rows_y: int, planes_z: int = 0) -> None:
         L3.lbm3_set_tile(self.ctx, rows_y, planes_z)
 
+    @property
+    def lean_width(self) -> int:
+        """Columns of the lean tiles (64, or 128 for FP32)."""
+        return L3.lbm3_get_lean_width(self.ctx)
+
+    def set_lean_width(self, columns: int) -> None:
+        L3.lbm3_set_lean_width(self.ctx, columns)
+
     def close(self) -> None:
         if getattr(self, "ctx", None) is not None:
             L3.lbm3_destroy(self.ctx)

@@ -2,7 +2,8 @@
 HIP runtime in this folder, through the call sequences of the GPU tests:
 volumes with ragged tails on both lattices and both dtypes, every face mix,
 sources by and across faces, receivers on face cells, several tile shapes,
-stepping, timed steps, fields, state copies and argument errors. The stub
+stepping, timed steps, 64- and 128-column lean tiles, fields, state copies and
+argument errors. The stub
 checks every launch's tiles (see stub3.cpp). Run as a script by
 tests/test_host_code_cpu.py with the built library's path."""
 import ctypes as C
@@ -27,6 +28,7 @@ sim.sim_register.argtypes = [C.c_void_p, C.c_size_t]
 sim.sim3_steps_checked.restype = C.c_longlong
 sim.sim3_lean_tiles.restype = C.c_longlong
 sim.sim3_general_tiles.restype = C.c_longlong
+sim.sim3_wide_launches.restype = C.c_longlong
 
 from workloads.problem import BC_FREE, BC_FREE0, BC_PERIODIC, BC_RIGID, default_sponge_profile  # noqa: E402
 from workloads.problem3 import Source3  # noqa: E402
@@ -73,6 +75,23 @@ def run(shape, faces, q, dtype, tile, sources, receivers, thick=(0, 4, 3, 0, 2, 
     L3.lbm3_step(ctx, 3)
     kt = L3.lbm3_step_timed(ctx, 2)
     assert kt["lean_cells"] + kt["general_cells"] == nx * ny * nz, kt
+    # width of the lean tiles: 128 columns by default for FP32
+    wide = dtype == "f32"
+    rows = 6 if tile is None else tile[0]
+    assert L3.lbm3_get_lean_width(ctx) == (128 if wide and rows != 14 else 64)
+    L3.lbm3_set_lean_width(ctx, 64)
+    assert L3.lbm3_get_lean_width(ctx) == 64
+    L3.lbm3_step(ctx, 1)
+    if wide:
+        L3.lbm3_set_lean_width(ctx, 128)
+        L3.lbm3_step(ctx, 1)
+    else:
+        try:
+            L3.lbm3_set_lean_width(ctx, 128)
+        except L.LBMError:
+            pass
+        else:
+            raise AssertionError("128-column tiles accepted for FP64")
     out10 = dev(np.zeros((10,) + shape, npdt))
     L3.lbm3_moments(ctx, out10.ctypes.data)
     st = dev(np.zeros((q,) + shape, npdt))
@@ -115,6 +134,6 @@ for si, shape in enumerate(SHAPES):
             run(shape, faces, q, dtype, tile, srcs, recs)
             n += 1
 print(f"volumes {n}, steps checked {sim.sim3_steps_checked()}, lean tiles {sim.sim3_lean_tiles()}, "
-      f"general tiles {sim.sim3_general_tiles()}")
-assert sim.sim3_lean_tiles() > 0 and sim.sim3_general_tiles() > 0
+      f"general tiles {sim.sim3_general_tiles()}, 128-column launches {sim.sim3_wide_launches()}")
+assert sim.sim3_lean_tiles() > 0 and sim.sim3_general_tiles() > 0 and sim.sim3_wide_launches() > 0
 print("ALL OK")

@@ -2,7 +2,8 @@
 // itself is stub.cpp's). The initialisation kernels are evaluated on the host
 // so the host code takes the device's branches; every step launch checks its
 // tile list against the volume and the rules of the lean / general split:
-//  - each tile lies inside the volume and inside the launch's buffers;
+//  - each tile lies inside the volume and inside the launch's buffers, 64
+//    columns wide (128 for wide lean tiles, FP32 steps only);
 //  - a lean tile pulls no cell on a non-periodic face (its cells widened by
 //    one in x and y, and by one plane on either side of its segment), holds
 //    no cell within 9 sigma of a source (minimum image on periodic axes) and
@@ -26,7 +27,7 @@ std::vector<int> g_cov;             // writes per cell of the pending step
 int g_nx = 0, g_ny = 0, g_nz = 0;
 bool g_pending = false;
 const void *g_pending_out = nullptr;
-long long g_steps_checked = 0, g_lean_tiles = 0, g_general_tiles = 0;
+long long g_steps_checked = 0, g_lean_tiles = 0, g_general_tiles = 0, g_wide_launches = 0;
 
 void fail(const char *msg) {
   fprintf(stderr, "stub3: %s\n", msg);
@@ -58,15 +59,20 @@ extern "C" long long sim3_steps_checked() {
 }
 extern "C" long long sim3_lean_tiles() { return g_lean_tiles; }
 extern "C" long long sim3_general_tiles() { return g_general_tiles; }
+extern "C" long long sim3_wide_launches() { return g_wide_launches; }
 
 namespace lbm3 {
 
-int launch_step3(bool f64, bool general, int rows_y, const Tile3Dev *tiles, int ntiles,
+int launch_step3(bool f64, bool general, int rows_y, int tw, const Tile3Dev *tiles, int ntiles,
                  const void *fin, void *fout, void *out10, const Vol3Dev &v, int64_t t, int mode,
                  hipStream_t) {
   if (ntiles <= 0) return 0;
   if (rows_y != 2 && rows_y != 6 && rows_y != 14) fail("rows_y");
   if (rows_y == 14 && (general || mode == 1)) fail("general or field tiles of 14 rows");
+  if (tw != 64 && tw != 128) fail("tile width");
+  if (tw == 128 && (general || mode != 0 || f64 || rows_y == 14))
+    fail("128-column tiles outside lean FP32 steps in 2- or 6-row tiles");
+  if (tw == 128) ++g_wide_launches;
   if (v.q != kQ19 && v.q != kQ27) fail("lattice");
   const size_t es = f64 ? 8 : 4;
   const int nx = v.nx, ny = v.ny, nz = v.nz;
@@ -101,10 +107,10 @@ int launch_step3(bool f64, bool general, int rows_y, const Tile3Dev *tiles, int 
   }
   for (int k = 0; k < ntiles; ++k) {
     const Tile3Dev tl = tiles[k];
-    if (tl.x0 < 0 || tl.x0 >= nx || tl.x0 % 64 || tl.y0 < 0 || tl.y0 >= ny || tl.y0 % rows_y ||
+    if (tl.x0 < 0 || tl.x0 >= nx || tl.x0 % tw || tl.y0 < 0 || tl.y0 >= ny || tl.y0 % rows_y ||
         tl.z0 < 0 || tl.z1 > nz || tl.z0 >= tl.z1)
       fail("tile outside the volume");
-    const int w = std::min(64, nx - tl.x0), h = std::min(rows_y, ny - tl.y0);
+    const int w = std::min(tw, nx - tl.x0), h = std::min(rows_y, ny - tl.y0);
     if (!general) {
       ++g_lean_tiles;
       if (!xper && (tl.x0 - 1 <= 0 || tl.x0 + w >= nx - 1)) fail("lean tile pulls an x-face cell");

@@ -26,7 +26,7 @@ def test_three_dimensional_header_exported():
     from paper_2009_06404_amd import _lib3d as L3
     lib = L3.lib()
     names = _declared3()
-    assert len(names) == len(L3.ENTRY_POINTS) == 15
+    assert len(names) == len(L3.ENTRY_POINTS) == 17
     for name in names:
         assert hasattr(lib, name), name
     assert set(L3.ENTRY_POINTS) == set(names)
@@ -91,6 +91,8 @@ def test_workspace3_size_and_null_context():
     assert lib.lbm3_step(None, 1) == L.LBM_E_INVALID
     assert lib.lbm3_moments(None, None) == L.LBM_E_INVALID
     assert lib.lbm3_set_tile(None, 6, 0) == L.LBM_E_INVALID
+    assert lib.lbm3_set_lean_width(None, 128) == L.LBM_E_INVALID
+    assert lib.lbm3_get_lean_width(None, None) == L.LBM_E_INVALID
     assert lib.lbm3_destroy(None) == L.LBM_OK
     t = C.c_int64(0)
     assert lib.lbm3_get_time(None, C.byref(t)) == L.LBM_E_INVALID

@@ -7,8 +7,8 @@ through the C ABI of include/lbm3d.h.
   kind (periodic, rigid, FREE, FREE0), sponges on every face, uniform and
   cell-wise media, sources and random initial states: FP64 <= 1e-12, FP32
   <= 1e-5 relative L2;
-* the tile shape (rows per workgroup 2 / 6 / 14, planes per segment) does not
-  change a single bit;
+* the tile shape (rows per workgroup 2 / 6 / 14, planes per segment, 64- or
+  128-column lean tiles) does not change a single bit;
 * the smallest volumes (3 cells on an axis) and a volume of one ragged tile;
 * the full 256^3 half-space workload in the launch the benchmark times,
   against the oracle over two steps from a random state.
@@ -34,17 +34,19 @@ def _random_state(p, seed, scale=1e-3):
     return np.random.default_rng(seed).normal(size=(p.q,) + p.shape) * scale
 
 
-def _run_gpu(p, nsteps, dtype, state=None, t0=0, tile=None):
+def _run_gpu(p, nsteps, dtype, state=None, t0=0, tile=None, width=None):
     import torch
     from paper_2009_06404_amd.solver3d import Solver3
     s = Solver3(p, dtype=dtype, trace_steps=max(nsteps, 1), tile=tile)
     try:
+        if width is not None:
+            s.set_lean_width(width)
         if state is not None:
             s.set_state(torch.as_tensor(state), t0)
         s.step(nsteps)
         out = {"fstar": s.state().double().cpu().numpy(), "mom": s.moments().double().cpu().numpy(),
                "trace": s.trace.double().cpu().numpy() if s.trace is not None else None,
-               "time": s.time, "tile": s.tile()}
+               "time": s.time, "tile": s.tile(), "width": s.lean_width}
         torch.cuda.synchronize()
     finally:
         s.close()
@@ -112,7 +114,8 @@ def test_parity_with_the_oracle(case, dtype, q):
     ref = O3.run(p, n, fstar_init=st, t0=3 if random_start else 0)
     got = _run_gpu(p, n, dtype, state=st, t0=3 if random_start else 0)
     worst = _compare(got, ref, TOL[dtype], f"{case} {dtype}")
-    print(f"[3d] D3Q{q} {case} {dtype}: worst rel L2 {worst:.2e}, tile {got['tile']}", flush=True)
+    print(f"[3d] D3Q{q} {case} {dtype}: worst rel L2 {worst:.2e}, tile {got['tile']}, "
+          f"lean width {got['width']}", flush=True)
     assert got["time"] == n + (3 if random_start else 0)
     assert np.linalg.norm(ref["fstar"]) > 0
 
@@ -129,6 +132,27 @@ def test_tile_shape_does_not_change_a_bit(dtype, q):
         assert np.array_equal(g["fstar"], base["fstar"]), tile
         assert np.array_equal(g["mom"], base["mom"]), tile
         assert np.array_equal(g["trace"], base["trace"]), tile
+
+
+@pytest.mark.parametrize("q", Q)
+def test_lean_tile_width_changes_no_bit(q):
+    """FP32 lean tiles of 128 columns (two wavefronts per row) against 64-column
+    ones, bit for bit, on a volume whose last tile is ragged (322 = 2 x 128 +
+    66 columns) with the x wrap inside lean tiles, in 6- and 2-row tiles; and
+    against the oracle."""
+    p = volume_field(nx=322, ny=23, nz=19, seed=31, nsteps=9, q=q)
+    p = p.replace(sources=[], receivers=p.receivers[:3])   # most tiles lean, both x edges among them
+    st = _random_state(p, 7)
+    ref = O3.run(p, 9, fstar_init=st, t0=4)
+    for tile in ((6, 0), (2, 5)):
+        narrow = _run_gpu(p, 9, "f32", state=st, t0=4, tile=tile, width=64)
+        wide = _run_gpu(p, 9, "f32", state=st, t0=4, tile=tile, width=128)
+        assert narrow["width"] == 64 and wide["width"] == 128
+        for k in ("fstar", "mom", "trace"):
+            assert np.array_equal(narrow[k], wide[k]), (tile, k)
+        w = _compare(wide, ref, TOL["f32"], f"128 columns {tile}")
+        print(f"[3d] D3Q{q} 128-column lean tiles, tile {tile}: bitwise equal to 64 columns, "
+              f"worst rel L2 against the oracle {w:.2e}", flush=True)
 
 
 @pytest.mark.parametrize("faces", [(BC_PERIODIC,) * 6, (BC_FREE0, BC_RIGID) + (BC_RIGID,) * 4,
