@@ -17,96 +17,113 @@ namespace {
 
 using namespace dev;
 
-// A workgroup of 256 lanes takes a tile of 256 columns down its rows. Each
-// lane keeps the five rows y-2 .. y+2 of its column in registers and the
-// row two ahead of them in flight; every row also goes into a four-row LDS
-// ring for the x neighbours, with four lanes loading the two halo columns on
-// each side (also a row ahead). One barrier per row.
+// A workgroup takes a tile of 256 columns down its rows: four wavefronts own
+// the tile's columns and a fifth loads the two halo columns on each side
+// (its lanes 0..3; the others load a column of the tile and discard it), so
+// that no load sits under a lane condition. Each lane keeps the five rows
+// y-2 .. y+2 of its column in registers and the two rows after them in flight,
+// and every row also goes into a four-row LDS ring for the x neighbours. One
+// barrier per row. The lanes past a narrow grid's last column load the
+// columns after it (wrapped, or the last column where x is not periodic), so
+// the ring holds the right neighbours of the last column without the halo
+// wavefront. Rows are read and written through per-row buffer descriptors
+// (the row index is the same for the whole workgroup).
 template <typename real>
-__global__ __launch_bounds__(256) void filter_kernel(const real *__restrict__ fin, real *__restrict__ fout,
+__global__ __launch_bounds__(320) void filter_kernel(const real *__restrict__ fin, real *__restrict__ fout,
                                                      const GridDev *__restrict__ grids,
                                                      const TileDev *__restrict__ tiles, real sigma) {
   constexpr int TW = 256;
-  __shared__ real srow[4][9][TW + 4];
+  constexpr int kDummySlot = TW + 4;     // LDS column of the halo wavefront's unused lanes
+  __shared__ real srow[4][9][TW + 5];
   const TileDev t = tiles[blockIdx.x];
   if (t.g < 0) return;
-  const GridDev &g = grids[t.g];
-  const int nx = g.nx, ny = g.ny, rr = g.rigid_row;
+  const GridDev g = uniform_lookup_fields(grids[t.g]);
+  const int nx = g.nx, ny = g.ny, rr = sreg(grids[t.g].rigid_row);
   const int lane = (int)threadIdx.x;
+  const bool main_lane = lane < TW;
   const int x = t.x0 + lane;
-  const bool active = x < nx;
-  const int xa = active ? x : nx - 1;
-  const int x_end = min(t.x0 + TW, nx);          // columns [x0, x_end) of this tile
-  const real *f = fin + g.f_off;
-  real *o = fout + g.f_off;
-  const int64_t pitch = g.pitch;
+  const bool active = main_lane && x < nx;
   const bool px = g.bc[kEdgeLeft] == kPeriodic, py = g.bc[kEdgeTop] == kPeriodic;
-  auto wx = [&](int c) { return c < 0 ? c + nx : (c >= nx ? c - nx : c); };
+  // the column this lane loads and its LDS slot: main lanes their own column
+  // (past the grid: the column after it, wrapped or clamped); halo lanes
+  // 0, 1 columns x0-2, x0-1 (slots 0, 1), 2, 3 columns x0+256, x0+257
+  // (slots 258, 259)
+  int c = x, slot = lane + 2;
+  if (!main_lane) {
+    const int hl = lane - TW;
+    c = hl < 2 ? t.x0 - 2 + hl : (hl < 4 ? t.x0 + TW + hl - 2 : t.x0);
+    slot = hl < 2 ? hl : (hl < 4 ? TW + hl : kDummySlot);
+  }
+  const int cl = px ? ((c % nx) + nx) % nx : min(max(c, 0), nx - 1);
+  const uint32_t esz = sizeof(real);
+  const uint32_t voff = (uint32_t)cl * esz, qb = (uint32_t)g.pitch * esz;
   // rows outside a non-periodic grid are never used (their terms are left
   // out); clamp them to stay in bounds
   auto wy = [&](int r) { return py ? (r < 0 ? r + ny : (r >= ny ? r - ny : r)) : min(max(r, 0), ny - 1); };
-  const bool xs = px ? nx >= 5 : (xa >= 2 && xa <= nx - 3);
-  // halo lanes: 0, 1 -> columns x0-2, x0-1 (slots 0, 1); 2, 3 -> x_end,
-  // x_end+1 (the slots after the tile's last column)
-  int hcol = -1, hslot = 0;
-  if (lane < 2) { hcol = t.x0 - 2 + lane; hslot = lane; }
-  else if (lane < 4) { hcol = x_end + lane - 2; hslot = (x_end - t.x0) + 2 + lane - 2; }
-  const bool hl = lane < 4 && (px || (hcol >= 0 && hcol < nx));
-  const int hc = hl ? wx(hcol) : 0;
+  auto row_in = [&](int r) {
+    return tile_rsrc(fin + g.f_off + (int64_t)sreg(wy(r)) * 9 * g.pitch);
+  };
+  const bool xs = px ? nx >= 5 : (x >= 2 && x <= nx - 3);
 
-  auto at = [&](int i, int r, int c) { return f[((int64_t)r * 9 + i) * pitch + c]; };
-  real win[9][5];   // rows y-2 .. y+2 of this column
-  real pre[9], hpre[9];   // row y+3 of this column and of the halo column (in flight)
-  // prologue: rows y0-2 .. y0+1 into the window, and rows y0, y0+1 into the ring
+  real win[9][5];   // rows y-2 .. y+2 of this lane's column
+  // the two rows after them, in flight: P0 and P1 alternate (row y+2 in the
+  // one of y's parity relative to y0, row y+3 in the other), so no register
+  // move waits on a load
+  real P0[9], P1[9];
+  // prologue: rows y0-2 .. y0+1 into the window, rows y0, y0+1 into the ring
 #pragma unroll
-  for (int i = 0; i < 9; ++i)
+  for (int k = 0; k < 4; ++k) {
+    const __amdgpu_buffer_rsrc_t R = row_in(t.y0 - 2 + k);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) win[i][k + 1] = at(i, wy(t.y0 - 2 + k), xa);
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const int r = t.y0 + k;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      if (active) srow[r & 3][i][lane + 2] = win[i][k + 3];
-      if (hl) srow[r & 3][i][hslot] = at(i, wy(r), hc);
-    }
+    for (int i = 0; i < 9; ++i) win[i][k + 1] = Buf<real>::load(R, voff, (uint32_t)i * qb);
   }
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    pre[i] = at(i, wy(t.y0 + 2), xa);
-    hpre[i] = hl ? at(i, wy(t.y0 + 2), hc) : real(0);
+  for (int k = 0; k < 2; ++k)
+#pragma unroll
+    for (int i = 0; i < 9; ++i) srow[(t.y0 + k) & 3][i][slot] = win[i][k + 3];
+  {
+    const __amdgpu_buffer_rsrc_t R2 = row_in(t.y0 + 2), R3 = row_in(t.y0 + 3);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) P0[i] = Buf<real>::load(R2, voff, (uint32_t)i * qb);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) P1[i] = Buf<real>::load(R3, voff, (uint32_t)i * qb);
   }
 
-  for (int y = t.y0; y < t.y1; ++y) {
-    // row y+2 arrives: into the window and the ring; row y+3 goes in flight
-    const int yn = wy(y + 3);
+  // row y: row y+2 (in P) joins the window and the ring, row y+4 goes into P
+  auto row = [&](int y, real(&P)[9]) {
+    const __amdgpu_buffer_rsrc_t R = row_in(min(y + 4, t.y1 + 2));   // no row past the stencil
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
 #pragma unroll
       for (int k = 0; k < 4; ++k) win[i][k] = win[i][k + 1];
-      win[i][4] = pre[i];
-      if (active) srow[(y + 2) & 3][i][lane + 2] = pre[i];   // (idle lanes would hit the halo slots)
-      if (hl) srow[(y + 2) & 3][i][hslot] = hpre[i];
-      pre[i] = at(i, yn, xa);
-      if (hl) hpre[i] = at(i, yn, hc);
+      win[i][4] = P[i];
+      srow[(y + 2) & 3][i][slot] = P[i];
+      P[i] = Buf<real>::load(R, voff, (uint32_t)i * qb);
     }
     __syncthreads();
     const bool ys = (py ? ny >= 5 : (y >= 2 && y <= ny - 3)) && !(rr > 0 && y >= rr - 2 && y <= rr + 1);
     const int s = y & 3;
     if (active) {
+      const __amdgpu_buffer_rsrc_t O = tile_rsrc(fout + g.f_off + (int64_t)y * 9 * g.pitch);
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        const real c = win[i][2];
+        const real cc = win[i][2];
         real acc = real(0);
         if (xs)
           acc += ((srow[s][i][lane] + srow[s][i][lane + 4]) -
                   real(4) * (srow[s][i][lane + 1] + srow[s][i][lane + 3])) +
-                 real(6) * c;
-        if (ys) acc += ((win[i][0] + win[i][4]) - real(4) * (win[i][1] + win[i][3])) + real(6) * c;
-        o[((int64_t)y * 9 + i) * pitch + x] = c - sigma * acc;
+                 real(6) * cc;
+        if (ys) acc += ((win[i][0] + win[i][4]) - real(4) * (win[i][1] + win[i][3])) + real(6) * cc;
+        Buf<real>::store_nt(cc - sigma * acc, O, (uint32_t)x * esz, (uint32_t)i * qb);
       }
     }
+  };
+  int y = t.y0;
+  for (; y + 1 < t.y1; y += 2) {
+    row(y, P0);
+    row(y + 1, P1);
   }
+  if (y < t.y1) row(y, P0);
 }
 
 }  // namespace
@@ -115,7 +132,7 @@ template <typename real>
 hipError_t launch_filter(const real *fin, real *fout, const GridDev *grids, const TileDev *tiles,
                          int ntiles, real sigma, hipStream_t stream) {
   if (ntiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL((filter_kernel<real>), dim3(ntiles), dim3(256), 0, stream, fin, fout, grids, tiles,
+  hipLaunchKernelGGL((filter_kernel<real>), dim3(ntiles), dim3(320), 0, stream, fin, fout, grids, tiles,
                      sigma);
   return hipGetLastError();
 }
