@@ -145,13 +145,20 @@ def test_tile_shape_does_not_change_a_bit(dtype, q):
 
 
 @pytest.mark.parametrize("q", Q)
-def test_lean_tile_width_changes_no_bit(q):
+@pytest.mark.parametrize("sides", ["periodic", "rigid"])
+def test_lean_tile_width_changes_no_bit(q, sides):
     """FP32 lean tiles of 128 columns (two wavefronts per row) against 64-column
-    ones, bit for bit, on a volume whose last tile is ragged (322 = 2 x 128 +
-    66 columns) with the x wrap inside lean tiles, in 6- and 2-row tiles; and
-    against the oracle."""
-    p = volume_field(nx=322, ny=23, nz=19, seed=31, nsteps=9, q=q)
-    p = p.replace(sources=[], receivers=p.receivers[:3])   # most tiles lean, both x edges among them
+    ones, bit for bit, in 6- and 2-row tiles, and against the oracle: on a
+    periodic volume whose last tile is ragged (322 = 2 x 128 + 66 columns)
+    with the x wrap inside lean tiles, and on a volume with rigid x and y
+    faces (400 columns: the 128-column tiles next to the x faces are general,
+    the two between them lean)."""
+    if sides == "periodic":
+        p = volume_field(nx=322, ny=23, nz=19, seed=31, nsteps=9, q=q)
+    else:
+        p = volume_field(nx=400, ny=23, nz=19, seed=32, nsteps=9, q=q,
+                         faces=(BC_PERIODIC, BC_PERIODIC, BC_RIGID, BC_RIGID, BC_RIGID, BC_RIGID))
+    p = p.replace(sources=[], receivers=p.receivers[:3])   # most tiles lean
     st = _random_state(p, 7)
     ref = O3.run(p, 9, fstar_init=st, t0=4)
     for tile in ((6, 0), (2, 5)):
@@ -161,7 +168,7 @@ def test_lean_tile_width_changes_no_bit(q):
         for k in ("fstar", "mom", "trace"):
             assert np.array_equal(narrow[k], wide[k]), (tile, k)
         w = _compare(wide, ref, TOL["f32"], f"128 columns {tile}")
-        print(f"[3d] D3Q{q} 128-column lean tiles, tile {tile}: bitwise equal to 64 columns, "
+        print(f"[3d] D3Q{q} {sides} 128-column lean tiles, tile {tile}: bitwise equal to 64 columns, "
               f"worst rel L2 against the oracle {w:.2e}", flush=True)
 
 
