@@ -402,7 +402,7 @@ __global__ __launch_bounds__(64 * NW) void step_kernel(StepArgs<real> a) {
         collide(fa, cs, omega, cforce, fs);
         const uint32_t rs = (uint32_t)(y - ybase) * rowb;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) Buf<real>::store_nt(fs[i], rout, o0, rs + i * qb);
+        for (int i = 0; i < 9; ++i) Buf<real>::store_nt_device(fs[i], rout, o0, rs + i * qb);
       }
     }
 
@@ -508,7 +508,7 @@ __global__ __launch_bounds__(64 * NW) void interior_kernel(StepArgs<real> a) {
       collide(fa, cs, omega, cforce, fs);
       const uint32_t rs = (uint32_t)(y - ybase) * rowb;
 #pragma unroll
-      for (int i = 0; i < 9; ++i) Buf<real>::store_nt(fs[i], rout, o0, rs + i * qb);
+      for (int i = 0; i < 9; ++i) Buf<real>::store_nt_device(fs[i], rout, o0, rs + i * qb);
     }
 
     __syncthreads();
@@ -862,7 +862,7 @@ __global__ __launch_bounds__(64 * NW + 64, sizeof(real) == 4 ? 5 : 3)
       uint32_t rs = (uint32_t)(rd - ybase) * rowb;
       asm volatile("" : "+s"(rs));
 #pragma unroll
-      for (int i = 0; i < 9; ++i) Buf<real>::store_nt(s2[i], rout, o0, rs + i * qb);
+      for (int i = 0; i < 9; ++i) Buf<real>::store_nt_device(s2[i], rout, o0, rs + i * qb);
     }
     __syncthreads();
     D0[(P + 1) % 2] = p0;
