@@ -39,6 +39,7 @@ KERNEL_SOURCES = ("paper_2009_06404_amd/csrc/lbm_kernels.hip",
                   "paper_2009_06404_amd/csrc/lbm_device.h",
                   "paper_2009_06404_amd/csrc/lbm_internal.h")
 FUSED_KERNEL = "fused2_kernel"
+FUSED3_KERNEL = "fused3_kernel"
 INTERIOR_KERNEL = "interior_kernel"
 
 
@@ -198,12 +199,15 @@ def roofline_block(kt: dict, esize: int, workload: str, dtype: str) -> dict:
     from its per-launch event timing kt (lbm_step_timed). Algorithmic bytes
     per launch: each population word of each cell the launch covers read once
     from its input state and written once to its output state, 18 words per
-    cell (72 B in FP32). The two-step kernel does this once for two steps, so
-    its `frac` is per pass; `per_update` counts the same launch at 18 words
-    per cell update (the survey's per-update figure), which on the two-step
-    path exceeds the HBM peak because half the updates never touch HBM."""
+    cell (72 B in FP32). The two- and three-step kernels do this once for two
+    or three steps, so their `frac` is per pass; `per_update` counts the same
+    launch at 18 words per cell update (the survey's per-update figure), which
+    on those paths exceeds the HBM peak because the intermediate updates
+    never touch HBM."""
     if kt["fused_cells"] > 0:
-        kname, kcells, kms, ksteps = FUSED_KERNEL, kt["fused_cells"], kt["fused_ms"], 2
+        ksteps = kt.get("fused_steps") or 2
+        kname = FUSED3_KERNEL if ksteps == 3 else FUSED_KERNEL
+        kcells, kms = kt["fused_cells"], kt["fused_ms"]
     elif kt["interior_cells"] > 0:
         kname, kcells, kms, ksteps = INTERIOR_KERNEL, kt["interior_cells"], kt["interior_ms"], 1
     else:
@@ -218,12 +222,13 @@ def roofline_block(kt: dict, esize: int, workload: str, dtype: str) -> dict:
            "steps_per_launch": ksteps, "ms_per_launch": round(kms, 5), "timed_steps": kt["steps"],
            "general_kernel": {"cells_per_launch": kt["general_cells"],
                               "ms_per_launch": round(kt["general_ms"], 5)}}
-    if ksteps == 2:
-        out["counting"] = ("frac per two-step pass: 18 population words per cell per launch, "
-                           "the launch advancing its cells by two steps")
-        out["per_update"] = {"achieved": round(2 * achieved, 1),
-                             "frac": round(2 * achieved / HBM_PEAK_GBS, 4),
-                             "counting": "18 population words per cell update, two updates per "
+    if ksteps > 1:
+        word = {2: "two", 3: "three"}[ksteps]
+        out["counting"] = (f"frac per {word}-step pass: 18 population words per cell per launch, "
+                           f"the launch advancing its cells by {word} steps")
+        out["per_update"] = {"achieved": round(ksteps * achieved, 1),
+                             "frac": round(ksteps * achieved / HBM_PEAK_GBS, 4),
+                             "counting": f"18 population words per cell update, {word} updates per "
                                          "cell and launch"}
     else:
         out["counting"] = "18 population words per cell update, one update per cell and launch"
@@ -234,7 +239,8 @@ def _dominant_gbps(kt: dict, esize: int) -> dict:
     """Algorithmic GB/s of the kernel covering most cells (72 B per cell and
     launch in FP32; the two-step kernel moves them once per two steps)."""
     if kt["fused_cells"] > 0:
-        name, cells, ms = FUSED_KERNEL, kt["fused_cells"], kt["fused_ms"]
+        name = FUSED3_KERNEL if kt.get("fused_steps") == 3 else FUSED_KERNEL
+        cells, ms = kt["fused_cells"], kt["fused_ms"]
     else:
         name, cells, ms = INTERIOR_KERNEL, kt["interior_cells"], kt["interior_ms"]
     return {"kernel": name, "GBps": round(18 * esize * cells / ms / 1e6, 1) if ms > 0 else None}
@@ -372,8 +378,9 @@ def bench_hbm_scale(torch, w, Solver, steps: int = 200, warmup: int = 20,
     return out
 
 
-# pairs of steps on the two-step path, 10 pairs per captured HIP graph
-BATCHED_LAUNCH = {"waves": 2, "rows": 8, "fuse_rows": 16, "graph_chunk": 20}
+# triples of steps on the three-step path (blocks of 32 rows), 10 triples per
+# captured HIP graph
+BATCHED_LAUNCH = {"waves": 2, "rows": 8, "fuse_rows": 32, "fuse_steps": 3, "graph_chunk": 30}
 # 1024-column grids: narrow, short tiles for the adjoint kernels; the recorded
 # forward (captured graphs of 10 pairs) and the recompute run on the two-step
 # path (128-column blocks)
@@ -383,8 +390,8 @@ ADJOINT_LAUNCH = {"waves": 2, "rows": 4, "fuse_rows": 32, "graph_chunk": 20}
 def bench_batched(torch, w, Solver, plain_glups: float, steps: int = 60,
                   warmup: int = 20, launch=None) -> dict:
     """512 grids of uneven side (256..2048) in one context, one launch of each
-    kernel per pair of steps over the flat tile lists, the time loop captured
-    in HIP graphs of 10 pairs; then the same context launched directly (the
+    kernel per triple of steps over the flat tile lists, the time loop captured
+    in HIP graphs of 10 triples; then the same context launched directly (the
     same workspace: its placement in HBM moves the rate by several percent
     between allocations, so both forms are timed on one)."""
     probs = w.batched_shots()

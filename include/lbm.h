@@ -131,8 +131,32 @@ typedef struct {
                          graph_chunk > 0 a chunk is graph_chunk / 2 pairs in
                          one captured graph (three kernels per pair, the fork
                          and join as graph edges). The default is set by
-                         size: the two-step path with graph_chunk 20 on
-                         contexts of 2048^2 cells and more. */
+                         size: the three-step path (fuse_steps 3, 128-column
+                         blocks of 128 rows on grids of 4096 rows and more,
+                         32 rows otherwise) with graph_chunk 30 on contexts
+                         of 2048^2 cells and more. */
+  int32_t fuse_steps; /* steps per pass of the blocks when fuse_rows > 0: 2
+                         (0 means 2) or 3. With 3 the steps run in triples:
+                         blocks of 64 x min(max(waves, 2), 4) columns take
+                         three steps in one pass (the two intermediate states
+                         stay on chip; the blocks keep six rows and columns
+                         clear of walls, the y-wrap, sources and receivers);
+                         the other cells take the three steps one at a time,
+                         the first beside the blocks' pass with the four
+                         border rows or columns next to them, the second
+                         (with two border rows or columns) and the third
+                         after it. Leftover steps run as a pair and a single
+                         step. Results are bitwise those of single steps;
+                         with graph_chunk > 0 (rounded up to a multiple of 3)
+                         a chunk is graph_chunk / 3 triples in one captured
+                         graph. The recorded forward of the adjoint runs in
+                         pairs either way. The path uses a second
+                         intermediate buffer as large as one of the
+                         workspace's population buffers, which the library
+                         allocates itself when the launch is set
+                         (LBM_E_NOMEM if the device cannot hold it) and
+                         frees when fuse_steps changes back or the context is
+                         destroyed. */
 } lbm_launch;
 
 /* Bytes of device workspace lbm_init needs for nbatch grids of the given
@@ -186,7 +210,9 @@ int lbm_step(lbm_ctx *ctx, int64_t n);
  * receivers (when split is on), then the general kernel over the rest. With
  * fuse_rows > 0 the steps go in pairs: the general kernel (step t), the
  * two-step kernel (steps t and t+1 of its blocks), the general kernel (step
- * t+1); an odd last step runs alone as above. */
+ * t+1); an odd last step runs alone as above. With fuse_steps = 3 they go in
+ * triples: the general kernel (step t), the three-step kernel, the general
+ * kernel (steps t+1 and t+2); leftover steps as a pair and a single step. */
 typedef struct {
   int64_t steps;          /* steps timed */
   double interior_ms;     /* mean duration of one interior-kernel launch; 0 if none */
@@ -194,8 +220,10 @@ typedef struct {
   int64_t interior_cells; /* cells one interior-kernel launch updates */
   int64_t general_cells;  /* cells one general-kernel launch updates (of the
                              two-step path's general tiles when fuse_rows > 0) */
-  double fused_ms;        /* mean duration of one two-step-kernel launch; 0 if none */
-  int64_t fused_cells;    /* cells one two-step-kernel launch advances by two steps */
+  double fused_ms;        /* mean duration of one multi-step-kernel launch; 0 if none */
+  int64_t fused_cells;    /* cells one multi-step-kernel launch advances by
+                             fused_steps steps */
+  int32_t fused_steps;    /* steps per multi-step-kernel launch: 2 or 3 (0 if none) */
 } lbm_kernel_times;
 
 /* Advance all grids n >= 0 steps like lbm_step, but with direct launches and

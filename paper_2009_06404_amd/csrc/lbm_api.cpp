@@ -167,7 +167,7 @@ struct lbm_ctx {
   std::vector<int64_t> rscale_off;               // per grid offset into d_rtab
   std::vector<char> rtab_host;
   bool tables_dirty = true;
-  lbm_launch launch{4, 8, 0, 1, 1, 0, 1, 0};
+  lbm_launch launch{4, 8, 0, 1, 1, 0, 1, 0, 2};
   // two-step path: fused tiles and the general tiles advanced step by step
   DevBuf<FusedTileDev> d_ftiles;
   DevBuf<TileDev> d_gtiles2;
@@ -177,6 +177,15 @@ struct lbm_ctx {
   int nfilt_tiles = 0;
   int nftiles = 0, ngtiles2 = 0, ngtiles1 = 0;
   int64_t cells_fused = 0, cells_gen2 = 0;
+  // three-step path (fuse_steps 3): its blocks, and the general tiles of the
+  // triple's steps (d_tgen[k] for step t+k: the general tiles plus the
+  // blocks' border strips 4 - 2k deep)
+  DevBuf<FusedTileDev> d_ttiles;
+  DevBuf<TileDev> d_tgen[3];
+  DevBuf<char> d_fmid2;   // the triple's second intermediate state, f*(t+1) (library-owned)
+  bool launch_set = false;  // the launch was set by the caller (lbm_set_launch, lbm_autotune)
+  int nttiles = 0, ntgen[3] = {0, 0, 0};
+  int64_t cells_tri = 0, cells_tri_gen = 0;
   // second stream and fork/join events for the overlapped general kernel
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -257,6 +266,7 @@ void drop_graphs(lbm_ctx *c) {
 // is taken as asked (not clipped to the grid), which errs on the safe side.
 constexpr int64_t kSingleReach = 6;
 constexpr int64_t kFusedReach = 8;
+constexpr int64_t kFused3Reach = 12;   // the three-step kernel: six above, six below
 constexpr int kMinTileRows = 2;   // the general kernel's sub-tiles
 
 int64_t row_bytes(int32_t nx, int dtype) {
@@ -264,9 +274,11 @@ int64_t row_bytes(int32_t nx, int dtype) {
 }
 
 // Empty when every grid's tiles of `rows` rows (single steps) and blocks of
-// `fuse_rows` rows (two-step path, 0 = off) stay inside the descriptors'
+// `fuse_rows` rows (multi-step path, 0 = off; fuse_steps 2 or 3) stay inside the descriptors'
 // ranges; else the reason.
-std::string reach_error(const std::vector<lbm_grid> &grids, int dtype, int rows, int fuse_rows) {
+std::string reach_error(const std::vector<lbm_grid> &grids, int dtype, int rows, int fuse_rows,
+                        int fuse_steps = 2) {
+  const int64_t freach = fuse_steps == 3 ? kFused3Reach : kFusedReach;
   for (size_t g = 0; g < grids.size(); ++g) {
     const int64_t rb = row_bytes(grids[g].nx, dtype);
     char buf[256];
@@ -278,11 +290,12 @@ std::string reach_error(const std::vector<lbm_grid> &grids, int dtype, int rows,
                (long long)((std::max(rows, kMinTileRows) + kSingleReach) * rb));
       return buf;
     }
-    if (fuse_rows > 0 && (fuse_rows + kFusedReach) * rb > (int64_t)UINT32_MAX) {
+    if (fuse_rows > 0 && (fuse_rows + freach) * rb > (int64_t)UINT32_MAX) {
       snprintf(buf, sizeof buf,
-               "grid %zu: %d-row two-step blocks would address %lld bytes of populations "
+               "grid %zu: %d-row %s-step blocks would address %lld bytes of populations "
                "from one descriptor (limit 2^32 - 1): use fewer fuse_rows",
-               g, fuse_rows, (long long)((fuse_rows + kFusedReach) * rb));
+               g, fuse_rows, fuse_steps == 3 ? "three" : "two",
+               (long long)((fuse_rows + freach) * rb));
       return buf;
     }
   }
@@ -447,12 +460,16 @@ void build_tiles(const lbm_ctx *c, int waves, int rows, bool split, std::vector<
 // fewer halo rows, shorter ones keep the rows in flight compact); narrower
 // tiles where the grid would otherwise give too few workgroups to fill 256
 // compute units.
-// Launch shape by size (measured on MI355X): large contexts take the two-step
-// path in blocks of 128 columns x 16 rows (4096^2 FP32: 133.5 GLUPS against
-// 132.0 at 32 rows and 124-126 at 40-64; the 512 batched grids of side
-// 256..2048: +0.9% against 32 rows; FP64 4096^2: 74.9 against 73.9), and in
-// blocks of 256 x 32 on very tall grids (16384^2 FP32: 149.4 GLUPS against
-// 148.5 at 64 rows); small ones single steps in smaller tiles.
+// Launch shape by size (measured on MI355X): large contexts take the
+// three-step path in blocks of 128 columns, 128 rows high on grids of 4096
+// rows and more (4096^2 FP32: 177 GLUPS against 138 for the two-step path's
+// best shape; 16384^2: 191 against 154; FP64 4096^2: 80.9 against 74.8) and
+// 32 rows on shorter grids (the 512 batched grids of side 256..2048: 162
+// against 155 at 128 rows and 134 for pairs). The block height also sets how
+// many workgroups a launch has: at 96 or 104 rows on 4096^2 the three-step
+// kernel fills every slot of the chip and the general kernel beside it
+// pushes its last blocks into a second round (135 GLUPS). Small contexts run
+// single steps in smaller tiles.
 lbm_launch default_launch(const lbm_ctx *c) {
   int64_t cells = 0;
   int max_ny = 0;
@@ -460,20 +477,20 @@ lbm_launch default_launch(const lbm_ctx *c) {
     cells += (int64_t)g.nx * g.ny;
     max_ny = std::max(max_ny, g.ny);
   }
-  lbm_launch l{8, c->dtype == LBM_F64 ? 4 : 8, 0, 1, 1, 0, 1, 0};
-  // two-step blocks: 128 columns (more workgroups per CU hide the row loop's
-  // barriers); 256 columns and taller blocks on very tall grids
-  const bool tall = max_ny >= 8192;
-  l.waves = tall ? 4 : 2;
-  l.fuse_rows = tall ? 32 : 16;
-  // pairs run as captured graphs of 10 pairs: on MI355X as fast as direct
-  // launches (within 0.2% on the same workspace, 512 batched grids and
-  // 4096^2 FP32), with one host call per 20 steps
-  l.graph_chunk = 20;
+  lbm_launch l{8, c->dtype == LBM_F64 ? 4 : 8, 0, 1, 1, 0, 1, 0, 2};
+  // three-step blocks of 128 columns (more workgroups per CU hide the row
+  // loop's barriers), taller on tall grids
+  l.waves = 2;
+  l.fuse_steps = 3;
+  l.fuse_rows = max_ny >= 4096 ? 128 : 32;
+  // triples run as captured graphs of 10 triples: as fast as direct launches
+  // on MI355X, with one host call per 30 steps
+  l.graph_chunk = 30;
   if (cells < 2048 * 2048) {
     l.waves = 4;
     l.rows = 4;
     l.fuse_rows = 0;
+    l.fuse_steps = 2;
     l.graph_chunk = 0;
   }
   if (cells < 256 * 2048) {
@@ -483,9 +500,13 @@ lbm_launch default_launch(const lbm_ctx *c) {
   // very wide grids: shorter tiles and blocks so that no tile reaches past
   // its descriptor (the grids passed validation, so 2-row tiles fit)
   while (l.rows > 1 && !reach_error(c->grids, c->dtype, l.rows, 0).empty()) l.rows /= 2;
-  while (l.fuse_rows >= 8 && !reach_error(c->grids, c->dtype, l.rows, l.fuse_rows).empty())
+  while (l.fuse_rows >= 8 && !reach_error(c->grids, c->dtype, l.rows, l.fuse_rows, l.fuse_steps).empty())
     l.fuse_rows /= 2;
-  if (l.fuse_rows > 0 && !reach_error(c->grids, c->dtype, l.rows, l.fuse_rows).empty())
+  if (l.fuse_rows > 0 && !reach_error(c->grids, c->dtype, l.rows, l.fuse_rows, l.fuse_steps).empty()) {
+    l.fuse_steps = 2;   // the two-step blocks reach four rows fewer
+    l.graph_chunk = 20;
+  }
+  if (l.fuse_rows > 0 && !reach_error(c->grids, c->dtype, l.rows, l.fuse_rows, l.fuse_steps).empty())
     l.fuse_rows = 0;
   return l;
 }
@@ -633,6 +654,8 @@ int commit(lbm_ctx *c) {
 // Two-step blocks are 64 * fused_waves columns wide: the launch's waves
 // (2, 4 or 8; 1 counts as 2).
 int fused_waves(const lbm_ctx *c) { return std::max(2, (int)c->launch.waves); }
+// Three-step blocks: 128 or 256 columns (8 waves count as 4).
+int tri_waves(const lbm_ctx *c) { return std::min(4, fused_waves(c)); }
 
 struct Seg {
   int lo, hi;    // [lo, hi)
@@ -641,8 +664,12 @@ struct Seg {
 
 // rec_reach: a row with a receiver within rec_reach rows is no own row of a
 // block (0 for the forward; the adjoint's blocks, whose receivers add to the
-// adjoint state of every row their two steps form, take 3).
-std::vector<Seg> fused_row_segments(const lbm_ctx *c, int g, int rows, int rec_reach) {
+// adjoint state of every row their two steps form, take 3). steps: 2 or 3,
+// the steps a block takes per pass; its reach is 2 x steps rows (the first
+// step pulls rows y - 2 steps + 1 .. y + 2 steps - 1), and runs of allowed
+// rows shorter than the border strips (2 x (steps - 1) rows) stay general.
+std::vector<Seg> fused_row_segments(const lbm_ctx *c, int g, int rows, int rec_reach, int steps = 2) {
+  const int R = 2 * steps, depth = 2 * (steps - 1);
   const int ny = c->grids[g].ny, rr = c->bc[g].rigid_row;
   std::vector<char> allowed((size_t)ny, 0);
   std::vector<char> has_rec((size_t)ny, 0);
@@ -651,12 +678,12 @@ std::vector<Seg> fused_row_segments(const lbm_ctx *c, int g, int rows, int rec_r
     for (int y = std::max(0, xy[r] - rec_reach); y <= std::min(ny - 1, xy[r] + rec_reach); ++y)
       has_rec[(size_t)y] = 1;
   for (int y = 0; y < ny; ++y) {
-    // the first step pulls rows y-3 .. y+3 (reading y-4 .. y+4): inside the
-    // grid without the wrap, and off rows 0 and ny-1 where walls cut links
-    bool ok = y - 4 >= 0 && y + 4 <= ny - 1;
+    // the first step pulls rows y-R+1 .. y+R-1 (reading y-R .. y+R): inside
+    // the grid without the wrap, and off rows 0 and ny-1 where walls cut links
+    bool ok = y - R >= 0 && y + R <= ny - 1;
     // rigid-row links cross between rows rr-1 and rr: no pulled row may be
     // either of them
-    if (rr > 0 && y - 3 <= rr && y + 3 >= rr - 1) ok = false;
+    if (rr > 0 && y - (R - 1) <= rr && y + (R - 1) >= rr - 1) ok = false;
     if (has_rec[(size_t)y]) ok = false;
     allowed[(size_t)y] = ok;
   }
@@ -665,7 +692,7 @@ std::vector<Seg> fused_row_segments(const lbm_ctx *c, int g, int rows, int rec_r
     int e = y;
     while (e < ny && allowed[(size_t)e] == allowed[(size_t)y]) ++e;
     const int len = e - y;
-    if (!allowed[(size_t)y] || len < 2) {
+    if (!allowed[(size_t)y] || len < depth) {
       if (!segs.empty() && !segs.back().ok) segs.back().hi = e;
       else segs.push_back(Seg{y, e, false});
     } else {
@@ -678,13 +705,17 @@ std::vector<Seg> fused_row_segments(const lbm_ctx *c, int g, int rows, int rec_r
   return segs;
 }
 
-std::vector<Seg> fused_col_segments(const lbm_ctx *c, int g, int waves) {
-  const int nx = c->grids[g].nx, bw = 64 * waves;
+// The kernels' halo columns: 4 each side for two steps, 5 for three; no halo
+// column may sit on a side wall's column.
+int fused_halo(int steps) { return steps == 3 ? 5 : 4; }
+
+std::vector<Seg> fused_col_segments(const lbm_ctx *c, int g, int waves, int steps = 2) {
+  const int nx = c->grids[g].nx, bw = 64 * waves, h = fused_halo(steps);
   const bool px = c->bc[g].edge[LBM_EDGE_LEFT] == LBM_PERIODIC;
-  // allowed columns [a, b): with x-wrap all; without, x-5 >= 0 and x+4 <= nx-1
-  // for every own column x
-  int a = px ? 0 : 64;                  // first multiple of 64 >= 5
-  const int b = px ? nx : nx - 5;
+  // allowed columns [a, b): with x-wrap all; without, x-h-1 >= 0 and
+  // x+h <= nx-2 for every own column x
+  int a = px ? 0 : 64;                  // first multiple of 64 >= h + 1
+  const int b = px ? nx : nx - h - 1;
   std::vector<Seg> segs;
   if (a > 0) segs.push_back(Seg{0, std::min(a, nx), false});
   for (int x = a; x < nx;) {
@@ -700,46 +731,53 @@ std::vector<Seg> fused_col_segments(const lbm_ctx *c, int g, int waves) {
   return segs;
 }
 
-bool source_reaches(const lbm_ctx *c, int g, const Seg &cs, const Seg &rs) {
+// A source disk reaching any cell the block's kernel computes (its halo
+// columns and the rows of its first stage: h and 2 x steps - 1 beyond the
+// block).
+bool source_reaches(const lbm_ctx *c, int g, const Seg &cs, const Seg &rs, int steps = 2) {
+  const int h = fused_halo(steps), v = 2 * steps - 1;
   const int nx = c->grids[g].nx, ny = c->grids[g].ny;
   const bool px = c->bc[g].edge[LBM_EDGE_LEFT] == LBM_PERIODIC;
   const bool py = c->bc[g].edge[LBM_EDGE_TOP] == LBM_PERIODIC;
   for (const lbm_source &q : c->sources[g]) {
     const double cut = 81.0 * q.sigma * q.sigma;
-    const double dx = dist_to_range(q.x, cs.lo - 4, cs.hi + 3, nx, px);
-    const double dy = dist_to_range(q.y, rs.lo - 3, rs.hi + 2, ny, py);
+    const double dx = dist_to_range(q.x, cs.lo - h, cs.hi + h - 1, nx, px);
+    const double dy = dist_to_range(q.y, rs.lo - v, rs.hi + v - 1, ny, py);
     if (dx * dx + dy * dy <= cut) return true;
   }
   return false;
 }
 
-// The general tiles of a pair's second step (general), and of its first step
-// (general1): the same tiles plus, for every two-step block next to general
-// cells, the two rows, columns or corner cells on that side, so that the first
-// general launch leaves f*(t) of every cell the second one reads in the
-// intermediate buffer and the two general launches need nothing from the
-// two-step kernel. The adjoint builds its own lists the same way (blocks of
-// `waves` x 64 columns, no receiver within rec_reach rows of an own row) and
-// flags the strips with strip_bit in their grid index. The general kernels
-// reach two rows and columns beyond a cell in both directions, the adjoint's
-// as the forward's, so the same strips serve both.
-void build_fused_tiles(const lbm_ctx *c, int rows, int waves, int rec_reach, int32_t strip_bit,
-                       std::vector<FusedTileDev> &fused, std::vector<TileDev> &general,
-                       std::vector<TileDev> &general1, int64_t &fused_cells) {
+// The general tiles of each step of a pass of `steps` steps. gens[steps-1]
+// (the last step's) holds the general tiles; gens[k] for an earlier step adds,
+// for every block next to general cells, the 2 x (steps - 1 - k) rows,
+// columns or corner cells on that side (border strips), so that each general
+// launch leaves the state of every cell the next one reads in its output and
+// the general launches need nothing from the blocks' pass. For a pair:
+// gens[0] with two-deep strips (the first step's list), gens[1] the second's.
+// The adjoint builds its own lists the same way (blocks of `waves` x 64
+// columns, no receiver within rec_reach rows of an own row) and flags the
+// strips with strip_bit in their grid index. The general kernels reach two
+// rows and columns beyond a cell in both directions, the adjoint's as the
+// forward's, so the same strips serve both.
+void build_multi_tiles(const lbm_ctx *c, int rows, int waves, int rec_reach, int32_t strip_bit,
+                       int steps, std::vector<FusedTileDev> &fused,
+                       std::vector<std::vector<TileDev>> &gens, int64_t &fused_cells) {
   std::vector<FusedTileDev> lf;
-  std::vector<TileDev> lg, lh;
+  std::vector<TileDev> lg;
+  std::vector<std::vector<TileDev>> lh((size_t)steps);
   fused_cells = 0;
   for (int g = 0; g < c->nbatch; ++g) {
-    const std::vector<Seg> R = fused_row_segments(c, g, rows, rec_reach),
-                           C = fused_col_segments(c, g, waves);
+    const std::vector<Seg> R = fused_row_segments(c, g, rows, rec_reach, steps),
+                           C = fused_col_segments(c, g, waves, steps);
     const int nr = (int)R.size(), nc = (int)C.size();
     const bool px = c->bc[g].edge[LBM_EDGE_LEFT] == LBM_PERIODIC;
     const bool py = c->bc[g].edge[LBM_EDGE_TOP] == LBM_PERIODIC;
     std::vector<char> isf((size_t)nr * nc, 0);
     for (int j = 0; j < nr; ++j)
       for (int i = 0; i < nc; ++i)
-        isf[(size_t)j * nc + i] = R[j].ok && C[i].ok && !source_reaches(c, g, C[i], R[j]);
-    auto fused_at = [&](int i, int j) -> int {   // 1 two-step, 0 general, -1 outside the grid
+        isf[(size_t)j * nc + i] = R[j].ok && C[i].ok && !source_reaches(c, g, C[i], R[j], steps);
+    auto fused_at = [&](int i, int j) -> int {   // 1 block, 0 general, -1 outside the grid
       if (i < 0 || i >= nc) { if (!px) return -1; i = (i + nc) % nc; }
       if (j < 0 || j >= nr) { if (!py) return -1; j = (j + nr) % nr; }
       return isf[(size_t)j * nc + i];
@@ -750,27 +788,30 @@ void build_fused_tiles(const lbm_ctx *c, int rows, int waves, int rec_reach, int
         if (isf[(size_t)j * nc + i]) {
           lf.push_back(FusedTileDev{g, cs.lo, cs.hi, rs.lo, rs.hi});
           fused_cells += (int64_t)(cs.hi - cs.lo) * (rs.hi - rs.lo);
-          // border strips for the first general step: two rows along a
-          // general neighbour above or below, two columns (one 64-column
-          // tile) along one left or right, the 2 x 2 corner (one tile of two
-          // rows) toward a general diagonal neighbour
-          std::set<std::tuple<int, int, int>> strips;
-          const int xl = cs.lo, xr = std::max(cs.lo, cs.hi - 64);
-          for (int dj = -1; dj <= 1; ++dj)
-            for (int di = -1; di <= 1; ++di) {
-              if ((di | dj) == 0 || fused_at(i + di, j + dj) != 0) continue;
-              const int ya = dj < 0 ? rs.lo : rs.hi - 2;   // the two rows on that side
-              if (di == 0) {
-                for (int xs = cs.lo; xs < cs.hi; xs += 64) strips.emplace(xs, ya, ya + 2);
-              } else if (dj == 0) {
-                for (int ys = rs.lo; ys < rs.hi; ys += kSubRows)
-                  strips.emplace(di < 0 ? xl : xr, ys, std::min(ys + kSubRows, rs.hi));
-              } else {
-                strips.emplace(di < 0 ? xl : xr, ya, ya + 2);
+          // border strips d deep: d rows along a general neighbour above or
+          // below, d columns (one 64-column tile) along one left or right,
+          // the d x d corner (one 64-column tile of d rows) toward a general
+          // diagonal neighbour; rows in tiles of at most kSubRows
+          for (int k = 0; k + 1 < steps; ++k) {
+            const int d = 2 * (steps - 1 - k);
+            std::set<std::tuple<int, int, int>> strips;
+            const int xl = cs.lo, xr = std::max(cs.lo, cs.hi - 64);
+            for (int dj = -1; dj <= 1; ++dj)
+              for (int di = -1; di <= 1; ++di) {
+                if ((di | dj) == 0 || fused_at(i + di, j + dj) != 0) continue;
+                const int ya = dj < 0 ? rs.lo : rs.hi - d;   // the d rows on that side
+                for (int ys = dj == 0 ? rs.lo : ya; ys < (dj == 0 ? rs.hi : ya + d); ys += kSubRows) {
+                  const int ye = std::min(ys + kSubRows, dj == 0 ? rs.hi : ya + d);
+                  if (di == 0) {
+                    for (int xs = cs.lo; xs < cs.hi; xs += 64) strips.emplace(xs, ys, ye);
+                  } else {
+                    strips.emplace(di < 0 ? xl : xr, ys, ye);
+                  }
+                }
               }
-            }
-          for (const auto &st : strips)
-            lh.push_back(TileDev{g | strip_bit, std::get<0>(st), std::get<1>(st), std::get<2>(st)});
+            for (const auto &st : strips)
+              lh[(size_t)k].push_back(TileDev{g | strip_bit, std::get<0>(st), std::get<1>(st), std::get<2>(st)});
+          }
         } else {
           for (int ys = rs.lo; ys < rs.hi; ys += kSubRows)
             for (int xs = cs.lo; xs < cs.hi; xs += 64)
@@ -785,10 +826,23 @@ void build_fused_tiles(const lbm_ctx *c, int rows, int waves, int rec_reach, int
     const int64_t jx = b % kXcds, ix = b / kXcds, l = jx * per + ix;
     if (ix < per && l < T) fused[(size_t)b] = lf[(size_t)l];
   }
-  std::vector<TileDev> l1 = lg;
-  l1.insert(l1.end(), lh.begin(), lh.end());
-  general = order_for_dies(lg);
-  general1 = order_for_dies(l1);
+  gens.assign((size_t)steps, std::vector<TileDev>());
+  for (int k = 0; k < steps; ++k) {
+    std::vector<TileDev> l = lg;
+    l.insert(l.end(), lh[(size_t)k].begin(), lh[(size_t)k].end());
+    gens[(size_t)k] = order_for_dies(l);
+  }
+}
+
+// The two-step path's lists: general (the pair's second step) and general1
+// (its first, with the two-deep border strips).
+void build_fused_tiles(const lbm_ctx *c, int rows, int waves, int rec_reach, int32_t strip_bit,
+                       std::vector<FusedTileDev> &fused, std::vector<TileDev> &general,
+                       std::vector<TileDev> &general1, int64_t &fused_cells) {
+  std::vector<std::vector<TileDev>> gens;
+  build_multi_tiles(c, rows, waves, rec_reach, strip_bit, 2, fused, gens, fused_cells);
+  general1 = gens[0];
+  general = gens[1];
 }
 
 constexpr int kFilterRows = 32;
@@ -828,6 +882,31 @@ int rebuild_tiles(lbm_ctx *c) {
     HIP_TRY(c->d_ftiles.upload(tf, c->stream));
     HIP_TRY(c->d_gtiles2.upload(tg2, c->stream));
     HIP_TRY(c->d_gtiles1.upload(tg1, c->stream));
+  }
+  c->nttiles = c->ntgen[0] = c->ntgen[1] = c->ntgen[2] = 0;
+  c->cells_tri = c->cells_tri_gen = 0;
+  if (c->launch.fuse_rows > 0 && c->launch.fuse_steps == 3) {
+    if (c->d_fmid2.reserve((size_t)round_up(c->L.f_elems * (int64_t)c->L.esize, 256)) != hipSuccess) {
+      hipGetLastError();
+      if (c->launch_set)
+        return fail(LBM_E_NOMEM, "no device memory for the three-step path's second intermediate buffer");
+      // the default launch falls back to pairs
+      c->launch.fuse_steps = 2;
+      c->launch.graph_chunk += c->launch.graph_chunk % 2;
+      return rebuild_tiles(c);
+    }
+    std::vector<FusedTileDev> tf;
+    std::vector<std::vector<TileDev>> gens;
+    build_multi_tiles(c, c->launch.fuse_rows, tri_waves(c), 0, 0, 3, tf, gens, c->cells_tri);
+    c->nttiles = (int)tf.size();
+    c->cells_tri_gen = cover(gens[2], 64);
+    HIP_TRY(c->d_ttiles.upload(tf, c->stream));
+    for (int k = 0; k < 3; ++k) {
+      c->ntgen[k] = (int)gens[(size_t)k].size();
+      HIP_TRY(c->d_tgen[k].upload(gens[(size_t)k], c->stream));
+    }
+  } else {
+    c->d_fmid2.release();
   }
   HIP_TRY(c->d_tiles_int.upload(ti, c->stream));
   HIP_TRY(c->d_tiles.upload(tg, c->stream));
@@ -940,6 +1019,54 @@ hipError_t launch_two_steps(lbm_ctx *c, StepArgs<real> a, hipStream_t s, real *r
       [&](hipStream_t q) { return launch_fused2<real>(f2, fused_waves(c), c->nftiles, q); });
 }
 
+int use_tri(const lbm_ctx *c) {
+  return c->launch.fuse_rows > 0 && c->launch.fuse_steps == 3 && c->nttiles > 0;
+}
+
+// The launches of a triple of steps (t, t+1, t+2) on the three-step path.
+// The three-step kernel (f3) takes its blocks from f*(t-1) in fin straight to
+// f*(t+2) in fout. Beside it, on the second stream, the general kernel
+// advances its tiles and the blocks' four-deep border strips to f*(t) in the
+// intermediate buffer (g1), its tiles and the two-deep strips from there to
+// f*(t+1) in the second intermediate buffer (g2), and its tiles from there
+// to f*(t+2) in fout (g3). The general launches need nothing from f3 and f3
+// nothing from them; f3 and g3 write disjoint cells of fout.
+template <typename real>
+void tri_args(lbm_ctx *c, const StepArgs<real> &a, StepArgs<real> &g1, StepArgs<real> &f3,
+              StepArgs<real> &g2, StepArgs<real> &g3) {
+  g1 = f3 = g2 = g3 = a;
+  g1.fout = reinterpret_cast<real *>(c->fmid);
+  g1.tiles = c->d_tgen[0].p;
+  g1.tri_step = 1;
+  f3.ftiles = c->d_ttiles.p;
+  f3.f_elems = c->L.f_elems;
+  g2.fin = reinterpret_cast<const real *>(c->fmid);
+  g2.fout = reinterpret_cast<real *>(c->d_fmid2.p);
+  g2.tiles = c->d_tgen[1].p;
+  g2.t = a.t + 1;
+  g2.tri_step = 2;
+  g3.fin = reinterpret_cast<const real *>(c->d_fmid2.p);
+  g3.tiles = c->d_tgen[2].p;
+  g3.t = a.t + 2;
+  g3.tri_step = 3;
+}
+
+template <typename real>
+hipError_t launch_three_steps(lbm_ctx *c, StepArgs<real> a, hipStream_t s) {
+  StepArgs<real> g1, f3, g2, g3;
+  tri_args<real>(c, a, g1, f3, g2, g3);
+  const int pf = c->launch.prefetch;
+  return launch_pair(
+      c, s, true, c->ntgen[0] + c->ntgen[1] + c->ntgen[2] > 0,
+      [&](hipStream_t q) {
+        hipError_t e = launch_step<real>(g1, 1, pf, c->ntgen[0], kModeStep, q);
+        if (e == hipSuccess) e = launch_step<real>(g2, 1, pf, c->ntgen[1], kModeStep, q);
+        if (e == hipSuccess) e = launch_step<real>(g3, 1, pf, c->ntgen[2], kModeStep, q);
+        return e;
+      },
+      [&](hipStream_t q) { return launch_fused3<real>(f3, tri_waves(c), c->nttiles, q); });
+}
+
 template <typename real>
 hipError_t launch_one_step(lbm_ctx *c, StepArgs<real> a, hipStream_t s) {
   StepArgs<real> ai = a;
@@ -980,6 +1107,13 @@ StepArgs<real> make_args(lbm_ctx *c, int src_buf) {
 
 template <typename real>
 int step_direct(lbm_ctx *c, int64_t n) {
+  if (use_tri(c)) {
+    for (; n >= 3; n -= 3) {
+      HIP_TRY(launch_three_steps<real>(c, make_args<real>(c, c->cur), c->stream));
+      c->cur ^= 1;
+      c->t += 3;
+    }
+  }
   if (use_fused(c)) {
     for (; n >= 2; n -= 2) {
       HIP_TRY(launch_two_steps<real>(c, make_args<real>(c, c->cur), c->stream));
@@ -1002,8 +1136,8 @@ int step_timed(lbm_ctx *c, int64_t n, lbm_kernel_times *out) {
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipError_t e = hipSuccess;
   for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
-  double sum[3] = {0.0, 0.0, 0.0};   // interior, general, two-step
-  int64_t cnt[3] = {0, 0, 0};
+  double sum[4] = {0.0, 0.0, 0.0, 0.0};   // interior, general, multi-step, leftover pairs
+  int64_t cnt[4] = {0, 0, 0, 0};
   // One launch between an event pair on the context's stream.
   auto timed = [&](int kind, auto &&launch) {
     if (e == hipSuccess) e = hipEventRecord(ev[0], c->stream);
@@ -1016,6 +1150,25 @@ int step_timed(lbm_ctx *c, int64_t n, lbm_kernel_times *out) {
   };
   int64_t k = 0;
   const int pf = c->launch.prefetch;
+  const bool tri = use_tri(c) != 0;
+  if (tri) {
+    for (; k + 3 <= n && e == hipSuccess; k += 3) {
+      const StepArgs<real> a = make_args<real>(c, c->cur);
+      StepArgs<real> g1, f3, g2, g3;
+      tri_args<real>(c, a, g1, f3, g2, g3);
+      if (c->ntgen[0] > 0)
+        timed(1, [&] { return launch_step<real>(g1, 1, pf, c->ntgen[0], kModeStep, c->stream); });
+      timed(2, [&] { return launch_fused3<real>(f3, tri_waves(c), c->nttiles, c->stream); });
+      if (c->ntgen[1] > 0)
+        timed(1, [&] { return launch_step<real>(g2, 1, pf, c->ntgen[1], kModeStep, c->stream); });
+      if (c->ntgen[2] > 0)
+        timed(1, [&] { return launch_step<real>(g3, 1, pf, c->ntgen[2], kModeStep, c->stream); });
+      if (e == hipSuccess) {
+        c->cur ^= 1;
+        c->t += 3;
+      }
+    }
+  }
   if (use_fused(c)) {
     for (; k + 2 <= n && e == hipSuccess; k += 2) {
       const StepArgs<real> a = make_args<real>(c, c->cur);
@@ -1025,7 +1178,9 @@ int step_timed(lbm_ctx *c, int64_t n, lbm_kernel_times *out) {
         timed(1, [&] { return launch_step<real>(g1, 1, pf, c->ngtiles1, kModeStep, c->stream); });
         timed(1, [&] { return launch_step<real>(g2, 1, pf, c->ngtiles2, kModeStep, c->stream); });
       }
-      timed(2, [&] { return launch_fused2<real>(f2, fused_waves(c), c->nftiles, c->stream); });
+      // on the three-step path a leftover pair's two-step launch is timed
+      // apart (not reported)
+      timed(tri ? 3 : 2, [&] { return launch_fused2<real>(f2, fused_waves(c), c->nftiles, c->stream); });
       if (e == hipSuccess) {
         c->cur ^= 1;
         c->t += 2;
@@ -1059,15 +1214,17 @@ int step_timed(lbm_ctx *c, int64_t n, lbm_kernel_times *out) {
   out->general_ms = cnt[1] ? sum[1] / (double)cnt[1] : 0.0;
   out->fused_ms = cnt[2] ? sum[2] / (double)cnt[2] : 0.0;
   out->interior_cells = c->cells_int;
-  out->general_cells = use_fused(c) ? c->cells_gen2 : c->cells_gen;
-  out->fused_cells = use_fused(c) ? c->cells_fused : 0;
+  out->general_cells = tri ? c->cells_tri_gen : use_fused(c) ? c->cells_gen2 : c->cells_gen;
+  out->fused_cells = tri ? c->cells_tri : use_fused(c) ? c->cells_fused : 0;
+  out->fused_steps = tri ? 3 : use_fused(c) ? 2 : 0;
   return LBM_OK;
 }
 
-// Capture graph_chunk (even) steps reading the time from the device counter,
+// Capture graph_chunk steps reading the time from the device counter,
 // followed by a node that advances the counter. On the two-step path the
 // chunk is graph_chunk / 2 pairs, each the three launches of a pair with its
-// fork and join as graph edges.
+// fork and join as graph edges; on the three-step path graph_chunk / 3
+// triples of four launches.
 template <typename real>
 int build_graphs(lbm_ctx *c, int chunk) {
   drop_graphs(c);
@@ -1081,12 +1238,13 @@ int build_graphs(lbm_ctx *c, int chunk) {
       return fail(LBM_E_DEVICE, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
     }
     int buf = parity;
-    const bool pairs = use_fused(c) != 0;
-    for (int k = 0; k < chunk; k += pairs ? 2 : 1) {
+    const int per = use_tri(c) ? 3 : use_fused(c) ? 2 : 1;
+    for (int k = 0; k < chunk; k += per) {
       StepArgs<real> a = make_args<real>(c, buf);
       a.t = k;
       a.t_dev = c->d_time.p;
-      if (pairs) launch_two_steps<real>(c, a, cs);
+      if (per == 3) launch_three_steps<real>(c, a, cs);
+      else if (per == 2) launch_two_steps<real>(c, a, cs);
       else launch_one_step<real>(c, a, cs);
       buf ^= 1;
     }
@@ -1192,17 +1350,17 @@ template <typename real>
 int step_chunks(lbm_ctx *c, int64_t n) {
   int rc = LBM_OK;
   // graph_chunk > 0: whole chunks run as captured graphs, one per buffer
-  // parity. A single step swaps the ping-pong buffers once, a pair of steps
-  // on the two-step path once per pair: after an even chunk of single steps
-  // the state is back in its buffer, after a chunk of an odd number of pairs
-  // in the other one.
+  // parity. A single step swaps the ping-pong buffers once, a pair or a
+  // triple of steps on the multi-step paths once: after an even chunk of
+  // single steps the state is back in its buffer, after a chunk of an odd
+  // number of pairs or triples in the other one.
   const int chunk = c->launch.graph_chunk;
   if (chunk > 0 && n >= chunk) {
     if (c->gchunk != chunk) {
       rc = build_graphs<real>(c, chunk);
       if (rc) return rc;
     }
-    const int swaps = use_fused(c) ? chunk / 2 : chunk;
+    const int swaps = use_tri(c) ? chunk / 3 : use_fused(c) ? chunk / 2 : chunk;
     HIP_TRY(launch_set_time(c->d_time.p, c->t, c->stream));
     while (n >= chunk) {
       HIP_TRY(hipGraphLaunch(c->gexec[c->cur], c->stream));
@@ -1696,6 +1854,7 @@ int adjoint_impl(lbm_ctx *c, int64_t n, lbm_kernel_times *out = nullptr) {
     out->interior_cells = c->cells_adj_int;
     out->general_cells = cnt[2] ? c->cells_adj_g2 : c->cells_adj_gen;
     out->fused_cells = cnt[2] ? c->cells_adj_f : 0;
+    out->fused_steps = cnt[2] ? 2 : 0;
   }
   return LBM_OK;
 }
@@ -2163,22 +2322,40 @@ int lbm_set_launch(lbm_ctx *c, const lbm_launch *cfg) {
   if (cfg->prefetch < 0 || cfg->prefetch > 2) return fail(LBM_E_INVALID, "prefetch must be 1 or 2");
   if (cfg->fuse_rows != 0 && (cfg->fuse_rows < 4 || cfg->fuse_rows > kFusedMaxRows))
     return fail(LBM_E_INVALID, "fuse_rows must be 0 or in [4, 248]");
+  if (cfg->fuse_steps != 0 && cfg->fuse_steps != 2 && cfg->fuse_steps != 3)
+    return fail(LBM_E_INVALID, "fuse_steps must be 2 or 3 (0 means 2)");
+  const int fsteps = cfg->fuse_steps == 3 ? 3 : 2;
   {
-    const std::string why = reach_error(c->grids, c->dtype, cfg->rows, cfg->fuse_rows);
+    const std::string why = reach_error(c->grids, c->dtype, cfg->rows, cfg->fuse_rows, fsteps);
     if (!why.empty()) return fail(LBM_E_INVALID, why);
   }
   const bool retile = cfg->waves != c->launch.waves || cfg->rows != c->launch.rows ||
-                      cfg->split != c->launch.split || cfg->fuse_rows != c->launch.fuse_rows;
+                      cfg->split != c->launch.split || cfg->fuse_rows != c->launch.fuse_rows ||
+                      fsteps != c->launch.fuse_steps;
   if (cfg->split < 0 || cfg->split > 1 || cfg->pair < 0 || cfg->pair > 1 || cfg->overlap < 0 ||
       cfg->overlap > 1)
     return fail(LBM_E_INVALID, "split, pair and overlap must be 0 or 1");
   const bool regraph = retile || cfg->prefetch != c->launch.prefetch || cfg->pair != c->launch.pair ||
                        cfg->overlap != c->launch.overlap;
+  const lbm_launch before = c->launch;
   c->launch = *cfg;
+  c->launch.fuse_steps = fsteps;
+  c->launch_set = true;
   if (c->launch.prefetch == 0) c->launch.prefetch = 1;
   if (regraph) drop_graphs(c);
-  if (c->launch.graph_chunk % 2) c->launch.graph_chunk += 1;   // keep buffer parity
-  if (retile) return rebuild_tiles(c);
+  // whole pairs, or whole triples on the three-step path
+  const int unit = c->launch.fuse_rows > 0 && fsteps == 3 ? 3 : 2;
+  c->launch.graph_chunk = (c->launch.graph_chunk + unit - 1) / unit * unit;
+  if (retile) {
+    const int rc2 = rebuild_tiles(c);
+    if (rc2 != LBM_OK) {   // keep the previous launch
+      const std::string why = g_err;
+      c->launch = before;
+      rebuild_tiles(c);
+      return fail(rc2, why);
+    }
+    return LBM_OK;
+  }
   if (c->gchunk != c->launch.graph_chunk) drop_graphs(c);
   return LBM_OK;
 }
@@ -2219,7 +2396,7 @@ int floor_log2(int64_t v) {
 // The key: the architecture name without its feature suffix, the dtype, the
 // distinct boundary classes of the grids (edge kinds, internal rigid row,
 // sources, receivers), powers of two of the total cells, of the tallest grid
-// and of the number of grids, and the path (pairs of steps or single steps).
+// and of the number of grids, and the path (triples, pairs or single steps).
 std::string tune_key(const lbm_ctx *c) {
   std::string arch = "unknown";
   int dev = 0;
@@ -2245,7 +2422,7 @@ std::string tune_key(const lbm_ctx *c) {
   for (const std::string &k : cls) key += k + ",";
   key += " cells 2^" + std::to_string(floor_log2(cells)) + " rows 2^" +
          std::to_string(floor_log2(max_ny)) + " grids 2^" + std::to_string(floor_log2(c->nbatch)) +
-         (c->launch.fuse_rows > 0 ? " pairs" : " single");
+         (c->launch.fuse_rows > 0 ? (c->launch.fuse_steps == 3 ? " triples" : " pairs") : " single");
   return key;
 }
 
@@ -2292,6 +2469,7 @@ int apply_tuned(lbm_ctx *c, const lbm_launch &l, lbm_launch *chosen) {
   next.pair = l.pair;
   next.fuse_rows = l.fuse_rows;
   c->launch = next;
+  c->launch_set = true;
   const int rc = rebuild_tiles(c);
   if (rc) return rc;
   if (chosen) *chosen = next;
@@ -2322,12 +2500,13 @@ int lbm_autotune(lbm_ctx *c, int32_t steps, lbm_launch *chosen) {
         found = true;
       }
     }
-    if (found && reach_error(c->grids, c->dtype, hit.rows, hit.fuse_rows).empty())
+    if (found && reach_error(c->grids, c->dtype, hit.rows, hit.fuse_rows, c->launch.fuse_steps).empty())
       return apply_tuned(c, hit, chosen);
     steps = kDefaultTuneSteps;
   }
   const bool pairs = c->launch.fuse_rows > 0;
-  if (pairs) steps += steps % 2;   // whole pairs
+  const int unit = pairs ? (c->launch.fuse_steps == 3 ? 3 : 2) : 1;
+  steps = (steps + unit - 1) / unit * unit;   // whole pairs or triples
   // Save the state; every candidate restarts from it.
   const size_t bytes = (size_t)c->L.f_elems * c->L.esize;
   void *save = nullptr;
@@ -2341,17 +2520,20 @@ int lbm_autotune(lbm_ctx *c, int32_t steps, lbm_launch *chosen) {
   if (e == hipSuccess) e = hipEventCreate(&ev1);
   int64_t cells = 0;
   for (auto &g : c->grids) cells += (int64_t)g.nx * g.ny;
-  // Candidates. On the two-step path: the block width (waves) and height
-  // (fuse_rows), the single-step shape kept for odd last steps. Otherwise the
+  // Candidates. On the two- and three-step paths: the block width (waves)
+  // and height (fuse_rows), the single-step shape kept for leftover steps. Otherwise the
   // single-step tile width, height, prefetch depth and column pairing.
   std::vector<lbm_launch> cands;
   if (pairs) {
+    const std::vector<int> heights = unit == 3 ? std::vector<int>{16, 32, 48, 64, 96, 128, 160}
+                                               : std::vector<int>{16, 24, 29, 32, 44, 48, 64};
     for (int w : {2, 4, 8})
-      for (int fr : {16, 24, 29, 32, 44, 48, 64}) {
+      for (int fr : heights) {
+        if (unit == 3 && w == 8) continue;   // three-step blocks are at most 4 waves wide
         lbm_launch cand = keep;
         cand.waves = w;
         cand.fuse_rows = fr;
-        if (reach_error(c->grids, c->dtype, cand.rows, fr).empty()) cands.push_back(cand);
+        if (reach_error(c->grids, c->dtype, cand.rows, fr, keep.fuse_steps).empty()) cands.push_back(cand);
       }
   } else {
     bool even = true;
@@ -2360,7 +2542,7 @@ int lbm_autotune(lbm_ctx *c, int32_t steps, lbm_launch *chosen) {
       for (int pf = 1; pf <= 2; ++pf)
         for (int w : {1, 2, 4, 8})
           for (int r : {2, 4, 8, 16, 32, 64}) {
-            lbm_launch cand{w, r, 0, pf, keep.split, pair, keep.overlap, 0};
+            lbm_launch cand{w, r, 0, pf, keep.split, pair, keep.overlap, 0, keep.fuse_steps};
             if (pair && w == 1) continue;
             const int64_t tiles = cells / ((int64_t)64 * w * r);
             if (tiles < 512 && !(w == 1 && r == 4)) continue;
@@ -2378,7 +2560,7 @@ int lbm_autotune(lbm_ctx *c, int32_t steps, lbm_launch *chosen) {
     c->t = t0;
     e = hipMemcpyAsync(c->fbuf[cur0], save, bytes, hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) break;
-    rc = c->dtype == LBM_F64 ? step_direct<double>(c, 2) : step_direct<float>(c, 2);  // warm-up
+    rc = c->dtype == LBM_F64 ? step_direct<double>(c, std::max(unit, 2)) : step_direct<float>(c, std::max(unit, 2));  // warm-up
     if (rc) break;
     e = hipEventRecord(ev0, c->stream);
     if (e != hipSuccess) break;
@@ -2627,6 +2809,9 @@ int lbm_destroy(lbm_ctx *c) {
   c->d_filt_tiles.release();
   c->d_gtiles2.release();
   c->d_gtiles1.release();
+  c->d_ttiles.release();
+  for (int k = 0; k < 3; ++k) c->d_tgen[k].release();
+  c->d_fmid2.release();
   c->d_tiles_int.release();
   c->d_krows.release();
   c->d_sponge.release();

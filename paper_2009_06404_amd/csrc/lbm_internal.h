@@ -85,6 +85,8 @@ struct StepArgs {
                          // first general launch and fin of its second (set on each launch of
                          // a pair so the host-side checks can tell them apart; no kernel reads it)
   int64_t f_elems;       // elements of one population buffer (bounds of fin/fout)
+  int32_t tri_step;      // three-step path: 1, 2 or 3 on the general kernel's launches of a
+                         // triple, 0 otherwise (for the host-side checks; no kernel reads it)
 };
 
 // kModeStash: the step plus the density of every cell written to rho_out,
@@ -171,6 +173,11 @@ hipError_t launch_step(const StepArgs<real> &a, int waves, int prefetch, int nti
 // a.rho_out2.
 template <typename real>
 hipError_t launch_fused2(const StepArgs<real> &a, int waves, int ntiles, hipStream_t stream);
+
+// Three steps (t, t+1, t+2) of the interior tiles in a.ftiles: reads a.fin =
+// f*(t-1), writes a.fout = f*(t+2); tiles of 64 x waves columns (2 or 4).
+template <typename real>
+hipError_t launch_fused3(const StepArgs<real> &a, int waves, int ntiles, hipStream_t stream);
 
 // The high-wavenumber filter (lbm_filter.hip): fout = fin - sigma (d4x + d4y)
 // fin for the cells of the 256-column tiles in tiles.

@@ -889,6 +889,268 @@ __global__ __launch_bounds__(64 * NW + 64, sizeof(real) == 4 ? 5 : 3)
   }
 }
 
+
+// Three time steps of an interior tile in one pass: the two-step kernel's
+// pipeline with a third pair of stages. At iteration r:
+//   A (row r):   pull f(t) from f*(t-1) in HBM (row r+1 already in flight),
+//                rho(t) into an LDS ring;
+//   B (row r-1): gradient and collision of step t -> f*(t) (LDS rings and
+//                registers, as in the two-step kernel);
+//   C (row r-2): pull f(t+1) from f*(t), rho(t+1) into an LDS ring;
+//   D (row r-3): gradient and collision of step t+1 -> f*(t+1), into a
+//                second set of rings of the same shape;
+//   E (row r-4): pull f(t+2) from f*(t+1), rho(t+2) into an LDS ring;
+//   F (row r-5): gradient and collision of step t+2 -> f*(t+2) to HBM.
+// Each stage runs on one column fewer on each side than the one before:
+// A on the tile plus five halo columns each side, F on the tile's own
+// columns (the halo columns are lanes of an extra wavefront as in the
+// two-step kernel). Rows: output rows [y0, y1) need f*(t-1) on rows
+// y0-6 .. y1+5. Two barriers per iteration suffice: one after B (C reads
+// B's rings) and one after D (E reads D's); the next iteration's A and B
+// touch nothing E and F read, and the ring depths keep every slot a stage
+// reads apart from the slots written before the next barrier. The per-cell
+// arithmetic is the single-step kernels', so three steps here equal three
+// single steps bit for bit. Tiles are clear of walls, the y-wrap, source
+// disks and receivers over that whole reach.
+template <typename real, int NW>
+__global__ __launch_bounds__(64 * NW + 64, sizeof(real) == 4 ? 4 : 2)
+    void fused3_kernel(StepArgs<real> a) {
+  constexpr int W = 64 * NW;
+  constexpr int HC = 5;                     // halo columns each side
+  constexpr int LW = W + 2 * HC;            // LDS columns
+  constexpr int RT = kFusedMaxRows + 12;    // per-row table: rows y0-6 .. y1+5
+  __shared__ real sA[2][LW];                // rho(t)
+  __shared__ real sC[2][LW];                // rho(t+1)
+  __shared__ real sE[2][LW];                // rho(t+2)
+  __shared__ real s78[2][LW], s13[2][2][LW], s56[3][2][LW];   // f*(t) from B
+  __shared__ real u78[2][LW], u13[2][2][LW], u56[3][2][LW];   // f*(t+1) from D
+  __shared__ real sRowA[RT], sRowI[RT], sRowK[RT];
+
+  const FusedTileDev tile = a.ftiles[blockIdx.x];
+  if (tile.g < 0) return;
+  const GridDev g = uniform_lookup_fields(a.grids[tile.g]);
+  const int pitch = g.pitch, nx = g.nx;
+  const int w = tile.x1 - tile.x0;          // 0 < w <= W
+  const int tid = threadIdx.x;
+  const int hl = tid - W;
+  // LDS column lc of column x0 - 5 + lc: 0..4 the left halo (lanes of the
+  // extra wavefront), 5..w+4 the tile, w+5..w+9 the right halo (the next
+  // output lanes, or the extra wavefront's lanes 5..9 past a full tile)
+  int lc = -1;
+  if (tid < W) lc = tid + HC;
+  else if (hl < HC) lc = hl;
+  else if (hl < 2 * HC) lc = W + hl;
+  const bool live = lc >= 0 && lc < w + 2 * HC;
+  const bool outlane = tid < w;
+  auto wrapx = [&](int c) { return c < 0 ? c + nx : (c >= nx ? c - nx : c); };
+  // lanes outside the block's columns load a live lane's column
+  const int col = wrapx(tile.x0 - HC + min(max(lc, 0), w + 2 * HC - 1));
+  const uint32_t esz = sizeof(real);
+  const uint32_t o0 = (uint32_t)col * esz;
+  const uint32_t ol = (uint32_t)wrapx(col - 1) * esz;
+  const uint32_t orr = (uint32_t)wrapx(col + 1) * esz;
+
+  const real omega = a.omega, cforce = a.cforce;
+  const int y0 = tile.y0, y1 = tile.y1;
+  const int ybase = y0 - 6;
+  const uint32_t qb = (uint32_t)pitch * esz;
+  const uint32_t rowb = 9 * qb;
+  const int64_t base = g.f_off + (int64_t)ybase * 9 * pitch;
+  const uint64_t rest = (uint64_t)(a.f_elems - base) * esz;
+  const __amdgpu_buffer_rsrc_t rin = range_rsrc(a.fin + base, rest);
+  const __amdgpu_buffer_rsrc_t rout = range_rsrc(a.fout + base, rest);
+
+  const int nrows = y1 - y0 + 12;
+  for (int k = tid; k < nrows; k += W + 64) {
+    real Ay = real(0), Iy = real(1);
+    sponge_y(a.sponge, g, ybase + k, Ay, Iy);
+    sRowA[k] = Ay;
+    sRowI[k] = Iy;
+    sRowK[k] = g.kmode == kKappaRows ? a.kappa_rows[g.k_off + ybase + k] : real(0);
+  }
+  real A_x, inv_x;
+  sponge_x(a.sponge, g, col, A_x, inv_x);
+  const bool kcells = g.kmode == kKappaCells;
+  const real kscalar = (real)g.kscalar;
+  const __amdgpu_buffer_rsrc_t rk = range_rsrc(
+      a.kappa_cells + (kcells ? g.k_off + (int64_t)ybase * pitch : 0),
+      kcells ? (uint64_t)(g.ny - ybase) * pitch * sizeof(real) : 0);
+  const int lmax = w + 2 * HC - 1;
+  const bool inB = lc >= 1 && lc <= lmax - 1, inC = lc >= 2 && lc <= lmax - 2;
+  const bool inD = lc >= 3 && lc <= lmax - 3, inE = lc >= 4 && lc <= lmax - 4;
+  __syncthreads();
+
+  // Registers carried down the rows: F the pulled f(t) of rows r-1, r, r+1
+  // (in flight); G / H the pulled f(t+1) / f(t+2) of two rows each; RA, RC,
+  // RE rho(t), rho(t+1), rho(t+2) of three rows; D0 / E2 and D0b / E2b
+  // populations 0 and 2 of f*(t) and f*(t+1) waiting one and two rows; the
+  // cell-wise modulus of rows r+1 (in flight) .. r-5.
+  real F[3][9], G[2][9], H[2][9], D0[2], E2[3], D0b[2], E2b[3], RA[3], RC[3], RE[3];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    F[0][i] = F[1][i] = F[2][i] = real(0);
+    G[0][i] = G[1][i] = H[0][i] = H[1][i] = real(0);
+  }
+  D0[0] = D0[1] = D0b[0] = D0b[1] = real(0);
+  E2[0] = E2[1] = E2[2] = E2b[0] = E2b[1] = E2b[2] = real(0);
+  RA[0] = RA[1] = RA[2] = RC[0] = RC[1] = RC[2] = RE[0] = RE[1] = RE[2] = real(0);
+  real kq = real(0), k1 = real(0), k2 = real(0), k3 = real(0), k4 = real(0), k5 = real(0);
+
+  const int rlast = y1 + 4;
+  // iterations from y0-6 (which only starts the loads of row y0-5) to rlast,
+  // rounded up to whole unrolled rounds by starting earlier
+  const int r0 = rlast + 1 - (rlast - (y0 - 6) + 1 + 5) / 6 * 6;
+
+  auto iter = [&](const int r, auto ph, auto first) {
+    constexpr int P = decltype(ph)::value;
+    real(&fa)[9] = F[P % 3];
+    real(&fb)[9] = F[(P + 1) % 3];
+    real(&fc)[9] = F[(P + 2) % 3];
+    real(&gc)[9] = G[P % 2];
+    real(&gn)[9] = G[(P + 1) % 2];
+    real(&hc)[9] = H[P % 2];
+    real(&hn)[9] = H[(P + 1) % 2];
+    real &rA_n = RA[P % 3], &rA_c = RA[(P + 2) % 3], &rA_m = RA[(P + 1) % 3];
+    real &rC_n = RC[P % 3], &rC_c = RC[(P + 2) % 3], &rC_m = RC[(P + 1) % 3];
+    real &rE_n = RE[P % 3], &rE_c = RE[(P + 2) % 3], &rE_m = RE[(P + 1) % 3];
+    real kn = real(0);
+    if (decltype(first)::value) {
+      if (live && r + 1 >= y0 - 5) {
+        int rn = r + 1;
+        asm volatile("" : "+s"(rn));
+        pull_fast(rin, ybase, rn, rowb, qb, o0, ol, orr, fc);
+        kn = Buf<real>::load(rk, o0, (uint32_t)(rn - ybase) * qb);
+      }
+    } else {
+      int rn = min(r + 1, rlast);
+      asm volatile("" : "+s"(rn));
+      pull_fast(rin, ybase, rn, rowb, qb, o0, ol, orr, fc);
+      kn = Buf<real>::load(rk, o0, (uint32_t)(rn - ybase) * qb);
+    }
+    // Stage A: row r of step t.
+    rA_n = real(0);
+    if (live && r >= y0 - 5) {
+      rA_n = sum9(fb);
+      sA[r & 1][lc] = rA_n;
+    }
+    // Stage B: row r-1 of step t.
+    const int rb = r - 1;
+    real p0 = real(0), p2 = real(0), p4 = real(0);
+    if (rb >= y0 - 4 && inB) {
+      const real dx = real(0.5) * (sA[rb & 1][lc + 1] - sA[rb & 1][lc - 1]);
+      const real dy = real(0.5) * (rA_n - rA_m);
+      const real kap = kcells ? k1 : (g.kmode == kKappaRows ? sRowK[rb - ybase] : kscalar);
+      const real A = max(A_x, sRowA[rb - ybase]), inv = min(inv_x, sRowI[rb - ybase]);
+      const CellState<real> cs = cell_state(fa, rA_c, kap * dx, kap * dy, A, inv);
+      real s1[9];
+      collide(fa, cs, omega, cforce, s1);
+      s78[0][lc] = s1[7];
+      s78[1][lc] = s1[8];
+      s13[rb & 1][0][lc] = s1[1];
+      s13[rb & 1][1][lc] = s1[3];
+      s56[rb % 3][0][lc] = s1[5];
+      s56[rb % 3][1][lc] = s1[6];
+      p0 = s1[0];
+      p2 = s1[2];
+      p4 = s1[4];
+    }
+    __syncthreads();
+    // Stage C: row r-2 of step t+1, pulled from f*(t) of rows r-3 .. r-1.
+    const int rc = r - 2;
+    rC_n = real(0);
+    if (rc >= y0 - 3 && inC) {
+      const int s13i = rc & 1, s56i = (rc + 2) % 3;
+      gn[0] = D0[P % 2];
+      gn[1] = s13[s13i][0][lc - 1];
+      gn[2] = E2[P % 3];
+      gn[3] = s13[s13i][1][lc + 1];
+      gn[4] = p4;
+      gn[5] = s56[s56i][0][lc - 1];
+      gn[6] = s56[s56i][1][lc + 1];
+      gn[7] = s78[0][lc + 1];
+      gn[8] = s78[1][lc - 1];
+      rC_n = sum9(gn);
+      sC[rc & 1][lc] = rC_n;
+    }
+    // Stage D: row r-3 of step t+1.
+    const int rd = r - 3;
+    real q0 = real(0), q2 = real(0), q4 = real(0);
+    if (rd >= y0 - 2 && inD) {
+      const real dx = real(0.5) * (sC[rd & 1][lc + 1] - sC[rd & 1][lc - 1]);
+      const real dy = real(0.5) * (rC_n - rC_m);
+      const real kap = kcells ? k3 : (g.kmode == kKappaRows ? sRowK[rd - ybase] : kscalar);
+      const real A = max(A_x, sRowA[rd - ybase]), inv = min(inv_x, sRowI[rd - ybase]);
+      const CellState<real> cs = cell_state(gc, rC_c, kap * dx, kap * dy, A, inv);
+      real s2[9];
+      collide(gc, cs, omega, cforce, s2);
+      u78[0][lc] = s2[7];
+      u78[1][lc] = s2[8];
+      u13[rd & 1][0][lc] = s2[1];
+      u13[rd & 1][1][lc] = s2[3];
+      u56[rd % 3][0][lc] = s2[5];
+      u56[rd % 3][1][lc] = s2[6];
+      q0 = s2[0];
+      q2 = s2[2];
+      q4 = s2[4];
+    }
+    __syncthreads();
+    // Stage E: row r-4 of step t+2, pulled from f*(t+1) of rows r-5 .. r-3.
+    const int re = r - 4;
+    rE_n = real(0);
+    if (re >= y0 - 1 && inE) {
+      const int u13i = re & 1, u56i = (re + 2) % 3;
+      hn[0] = D0b[P % 2];
+      hn[1] = u13[u13i][0][lc - 1];
+      hn[2] = E2b[P % 3];
+      hn[3] = u13[u13i][1][lc + 1];
+      hn[4] = q4;
+      hn[5] = u56[u56i][0][lc - 1];
+      hn[6] = u56[u56i][1][lc + 1];
+      hn[7] = u78[0][lc + 1];
+      hn[8] = u78[1][lc - 1];
+      rE_n = sum9(hn);
+      sE[re & 1][lc] = rE_n;
+    }
+    // Stage F: row r-5 of step t+2 to HBM.
+    const int rf = r - 5;
+    if (rf >= y0 && outlane) {
+      const real dx = real(0.5) * (sE[rf & 1][lc + 1] - sE[rf & 1][lc - 1]);
+      const real dy = real(0.5) * (rE_n - rE_m);
+      const real kap = kcells ? k5 : (g.kmode == kKappaRows ? sRowK[rf - ybase] : kscalar);
+      const real A = max(A_x, sRowA[rf - ybase]), inv = min(inv_x, sRowI[rf - ybase]);
+      const CellState<real> cs = cell_state(hc, rE_c, kap * dx, kap * dy, A, inv);
+      real s3[9];
+      collide(hc, cs, omega, cforce, s3);
+      uint32_t rs = (uint32_t)(rf - ybase) * rowb;
+      asm volatile("" : "+s"(rs));
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Buf<real>::store_nt_device(s3[i], rout, o0, rs + i * qb);
+    }
+    D0[(P + 1) % 2] = p0;
+    E2[(P + 2) % 3] = p2;
+    D0b[(P + 1) % 2] = q0;
+    E2b[(P + 2) % 3] = q2;
+    k5 = k4; k4 = k3; k3 = k2; k2 = k1; k1 = kq; kq = kn;
+  };
+
+  using First = std::true_type;
+  using Steady = std::false_type;
+  iter(r0, Phase<0>{}, First{});
+  iter(r0 + 1, Phase<1>{}, First{});
+  iter(r0 + 2, Phase<2>{}, First{});
+  iter(r0 + 3, Phase<3>{}, First{});
+  iter(r0 + 4, Phase<4>{}, First{});
+  iter(r0 + 5, Phase<5>{}, First{});
+  for (int r = r0 + 6; r <= rlast; r += 6) {
+    iter(r, Phase<0>{}, Steady{});
+    iter(r + 1, Phase<1>{}, Steady{});
+    iter(r + 2, Phase<2>{}, Steady{});
+    iter(r + 3, Phase<3>{}, Steady{});
+    iter(r + 4, Phase<4>{}, Steady{});
+    iter(r + 5, Phase<5>{}, Steady{});
+  }
+}
+
 }  // namespace
 
 template <typename real>
@@ -977,8 +1239,20 @@ hipError_t launch_fused2(const StepArgs<real> &a, int waves, int ntiles, hipStre
   return hipGetLastError();
 }
 
+template <typename real>
+hipError_t launch_fused3(const StepArgs<real> &a, int waves, int ntiles, hipStream_t stream) {
+  if (ntiles <= 0) return hipSuccess;
+  dim3 grid(ntiles), block(64 * waves + 64);
+  if (waves == 2) hipLaunchKernelGGL((fused3_kernel<real, 2>), grid, block, 0, stream, a);
+  else if (waves == 4) hipLaunchKernelGGL((fused3_kernel<real, 4>), grid, block, 0, stream, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 template hipError_t launch_fused2<float>(const StepArgs<float> &, int, int, hipStream_t);
 template hipError_t launch_fused2<double>(const StepArgs<double> &, int, int, hipStream_t);
+template hipError_t launch_fused3<float>(const StepArgs<float> &, int, int, hipStream_t);
+template hipError_t launch_fused3<double>(const StepArgs<double> &, int, int, hipStream_t);
 
 template hipError_t launch_interior<float>(const StepArgs<float> &, int, int, int, hipStream_t);
 template hipError_t launch_interior<double>(const StepArgs<double> &, int, int, int, hipStream_t);

@@ -184,6 +184,28 @@ for name, bc, rr, nx, ny in FUSED:
 pairs, kt = run_forward([problem(FUSED[1][1], 40, 530, 90, 6), problem(FUSED[0][1], -1, 300, 64, 7),
                          problem(FUSED[2][1], -1, 1100, 50, 8)], 0, dict(waves=2, rows=4, fuse_rows=6))
 assert pairs > 0, pairs
+# three-step path: blocks of 128 and 256 columns (8 waves count as 4); the
+# step counts leave a pair and a single step over; every launch reads only
+# cells holding the state of its starting time, and every triple writes each
+# cell once
+sim.sim_triples_checked.restype = C.c_int64
+sim.sim_time_reads.restype = C.c_int64
+for name, bc, rr, nx, ny in FUSED:
+    p = problem(bc, rr, nx, ny, 5, sources=[Source(nx * 0.7, ny * 0.5, 2.0, 0.3, 0.9, 1.0, 12.0, 16.0)],
+                receivers=[(x, 0) for x in range(0, nx, 5)] + [(x, 77) for x in range(3, nx, 11)])
+    for fr in (4, 8, 13):
+        for extra in (dict(), dict(overlap=0), dict(graph_chunk=6), dict(waves=8), dict(waves=2)):
+            t0 = sim.sim_triples_checked()
+            pairs, kt = run_forward([p], 0, dict(dict(waves=4, rows=8, fuse_rows=fr, fuse_steps=3), **extra))
+            assert sim.sim_triples_checked() > t0 and kt["fused_steps"] == 3 and kt["fused_cells"] > 0, \
+                (name, fr, extra, kt)
+    print("ok three-step", name, flush=True)
+t0 = sim.sim_triples_checked()
+pairs, kt = run_forward([problem(FUSED[1][1], 40, 530, 90, 6), problem(FUSED[0][1], -1, 300, 64, 7),
+                         problem(FUSED[2][1], -1, 1100, 50, 8)], 0,
+                        dict(waves=2, rows=4, fuse_rows=6, fuse_steps=3), steps=(3, 7, 12))
+assert sim.sim_triples_checked() > t0, kt
+assert sim.sim_time_reads() > 0
 # autotuning: every candidate shape of either path runs through the checks
 # above, and each result lands in the cache file LBM_TUNE_CACHE names
 cache = os.path.join(os.path.dirname(sys.argv[1]), "tune_cache.txt")
@@ -193,9 +215,12 @@ tp = problem(FUSED[1][1], 61, 530, 150, 9, sources=[Source(300.0, 75.0, 2.0, 0.3
 for fr in (6, 0):
     pairs, kt = run_forward([tp], 0, dict(waves=4, rows=8, fuse_rows=fr), tune=3)
     assert (pairs > 0) == (fr > 0), (fr, pairs)
+t0 = sim.sim_triples_checked()
+pairs, kt = run_forward([tp], 0, dict(waves=4, rows=8, fuse_rows=6, fuse_steps=3), tune=3)
+assert sim.sim_triples_checked() > t0 and kt["fused_steps"] == 3, kt
 lines = open(cache).read().splitlines()
-assert len(lines) == 2 and lines[0].startswith("sim f32 ") and " pairs|" in lines[0], lines
-assert " single|" in lines[1], lines
+assert len(lines) == 3 and lines[0].startswith("sim f32 ") and " pairs|" in lines[0], lines
+assert " single|" in lines[1] and " triples|" in lines[2], lines
 print("ok autotune", flush=True)
 
 # densities kept from the recorded forward: none, the last (short) segment,
@@ -204,7 +229,8 @@ print("ok autotune", flush=True)
 for dtype in ("f32", "f64"):
     p = problem(FUSED[1][1], 61, 530, 150, 12, sources=[Source(300.0, 75.0, 2.0, 0.3, 0.9, 1.0, 12.0, 16.0)],
                 receivers=[(x, 0) for x in range(0, 530, 5)] + [(x, 77) for x in range(3, 530, 11)])
-    for launch in (dict(waves=2, rows=8, fuse_rows=8), dict(waves=2, rows=8)):
+    for launch in (dict(waves=2, rows=8, fuse_rows=8), dict(waves=2, rows=8),
+                   dict(waves=2, rows=8, fuse_rows=8, fuse_steps=3)):
         for resident, chunks in ((0, [23]), (2, [5, 18]), (12, [1, 22]), (23, [23]), (1000, [4, 19])):
             run([p], 23, 7, dtype, launch=launch, chunks=chunks, resident=resident)
     print("ok kept densities", dtype, flush=True)
@@ -254,19 +280,24 @@ def refused(ctx, **kw):
 
 
 # descriptor reach: a tile's rows (plus 6) and a two-step block's rows (plus
-# 8) of nine population runs must stay within 2^31 - 1 and 2^32 - 1 bytes
+# 8; a three-step block's plus 12) of nine population runs must stay within
+# 2^31 - 1 and 2^32 - 1 bytes
 ctx = init_only(4096, 40, L.LBM_F64, np.float64)          # 294912 B per row
 assert not refused(ctx, rows=7275) and refused(ctx, rows=7276)
 L.lbm_destroy(ctx)
 ctx = init_only(828544, 3, L.LBM_F64, np.float64)         # 59655168 B per row
-assert not refused(ctx, rows=29, fuse_rows=63)
-assert refused(ctx, rows=30) and refused(ctx, rows=8, fuse_rows=64)
+assert not refused(ctx, rows=29, fuse_rows=63, fuse_steps=2)
+assert refused(ctx, rows=30) and refused(ctx, rows=8, fuse_rows=64, fuse_steps=2)
+assert not refused(ctx, rows=8, fuse_rows=59, fuse_steps=3)
+assert refused(ctx, rows=8, fuse_rows=60, fuse_steps=3)
 L.lbm_destroy(ctx)
-# the widest FP32 grid: the default launch takes 2-row tiles and 8-row blocks
+# the widest FP32 grid: the default launch takes 2-row tiles and 4-row
+# three-step blocks (8-row blocks on the two-step path)
 ctx = init_only(7456512, 3, L.LBM_F32, np.float32)
 lc = L.lbm_get_launch(ctx)
-assert lc["rows"] == 2 and lc["fuse_rows"] == 8, lc
-assert refused(ctx, rows=3) and refused(ctx, fuse_rows=9)
+assert lc["rows"] == 2 and lc["fuse_rows"] == 4 and lc["fuse_steps"] == 3, lc
+assert refused(ctx, rows=3) and refused(ctx, fuse_rows=5)
+assert not refused(ctx, fuse_rows=8, fuse_steps=2) and refused(ctx, fuse_rows=9, fuse_steps=2)
 L.lbm_destroy(ctx)
 print("ok descriptor reach", flush=True)
 print("ALL OK", flush=True)

@@ -33,13 +33,20 @@ extern "C" void sim_check_range(const void *p, size_t n, const char *what) { che
 
 hipError_t hipMalloc(void **p, size_t n) { *p = malloc(n ? n : 1); g_alloc[(uintptr_t)*p] = n ? n : 1; return hipSuccess; }
 hipError_t hipFree(void *p) { if (p) { g_alloc.erase((uintptr_t)p); free(p); } return hipSuccess; }
+namespace lbm { static void times_forget(const void *p, size_t n); }
 hipError_t hipMemcpyAsync(void *d, const void *s, size_t n, hipMemcpyKind k, hipStream_t) {
   if (k != hipMemcpyHostToDevice) check_range(s, n, "memcpy src");
   if (k != hipMemcpyDeviceToHost) check_range(d, n, "memcpy dst");
+  if (k != hipMemcpyDeviceToHost) lbm::times_forget(d, n);
   memmove(d, s, n);
   return hipSuccess;
 }
-hipError_t hipMemsetAsync(void *d, int v, size_t n, hipStream_t) { check_range(d, n, "memset"); memset(d, v, n); return hipSuccess; }
+hipError_t hipMemsetAsync(void *d, int v, size_t n, hipStream_t) {
+  check_range(d, n, "memset");
+  lbm::times_forget(d, n);
+  memset(d, v, n);
+  return hipSuccess;
+}
 hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
 hipError_t hipHostMalloc(void **p, size_t n, unsigned int) { *p = malloc(n ? n : 1); g_alloc[(uintptr_t)*p] = n ? n : 1; return hipSuccess; }
 hipError_t hipHostGetDevicePointer(void **d, void *h, unsigned int) { *d = h; return hipSuccess; }
@@ -88,6 +95,116 @@ template <typename real>
 static void check_pop(const real *base, const GridDev &g, const char *what) {
   check_range(base + g.f_off, sizeof(real) * 9 * (size_t)g.pitch * g.ny, what);
 }
+// State times: for each population buffer (by base address) and grid, the
+// time of the state every cell holds, -1 where unknown (not written by a step
+// launch since the last copy or fill over it), -2 where poisoned (computed
+// from cells of another time). A launch of S steps from time a.t (fin holding
+// the state of time a.t, fout receiving a.t + S) reads the cells within 2 S
+// of each cell it writes: all must hold time a.t. Only the second general
+// launch of a triple may read others: its 64-column strip tiles compute
+// cells beyond the two-deep strips the third launch reads, from intermediate
+// cells no launch wrote; those cells are poisoned, and a triple's output must
+// hold none.
+struct TimeMap {
+  uintptr_t lo = 0, hi = 0;   // the grid's population bytes in the buffer
+  std::vector<int64_t> t;
+};
+static std::map<const void *, std::map<int, TimeMap>> g_time;
+static int64_t g_time_reads = 0;
+extern "C" int64_t sim_time_reads() { return g_time_reads; }
+static void times_forget(const void *p, size_t n) {
+  const uintptr_t a = (uintptr_t)p, b = a + n;
+  for (auto &kv : g_time)
+    for (auto &gv : kv.second)
+      if (gv.second.lo < b && a < gv.second.hi) std::fill(gv.second.t.begin(), gv.second.t.end(), -1);
+}
+template <typename real>
+static std::vector<int64_t> &times(const real *buf, int gi, const GridDev &g) {
+  TimeMap &m = g_time[(const void *)buf][gi];
+  if (m.t.empty()) {
+    m.t.assign((size_t)g.nx * g.ny, -1);
+    m.lo = (uintptr_t)(buf + g.f_off);
+    m.hi = m.lo + sizeof(real) * 9 * (size_t)g.pitch * g.ny;
+  }
+  return m.t;
+}
+// Check the reads of a launch of `steps` steps writing cell (x, y) of grid gi,
+// then record the cell's new time in fout.
+template <typename real>
+static void time_step_cell(const StepArgs<real> &a, int gi, const GridDev &g, int x, int y, int steps,
+                           const char *what) {
+  const std::vector<int64_t> &in = times(a.fin, gi, g);
+  const bool px = g.bc[kEdgeLeft] == kPeriodic, py = g.bc[kEdgeTop] == kPeriodic;
+  const int R = 2 * steps;
+  for (int dy = -R; dy <= R; ++dy)
+    for (int dx = -R; dx <= R; ++dx) {
+      int xx = x + dx, yy = y + dy;
+      if (xx < 0 || xx >= g.nx) { if (!px) continue; xx = (xx + g.nx) % g.nx; }
+      if (yy < 0 || yy >= g.ny) { if (!py) continue; yy = (yy + g.ny) % g.ny; }
+      const int64_t h = in[(size_t)yy * g.nx + xx];
+      ++g_time_reads;
+      if (h == -2 || (h >= 0 && h != a.t)) {
+        if (a.tri_step == 2) {
+          times(a.fout, gi, g)[(size_t)y * g.nx + x] = -2;
+          return;
+        }
+        fprintf(stderr, "%s of time %lld at g=%d (%d,%d) reads (%d,%d) holding %s %lld\n", what,
+                (long long)a.t, gi, x, y, xx, yy, h == -2 ? "poison" : "time", (long long)h);
+        abort();
+      }
+    }
+  times(a.fout, gi, g)[(size_t)y * g.nx + x] = a.t + steps;
+}
+// A triple: the three-step kernel and the third general launch (in either
+// order) write every cell of the triple's output once, and the output then
+// holds the state of the triple's end everywhere.
+static std::map<int, std::vector<int>> g_tri_cov;
+static const void *g_tri_out = nullptr;
+static bool g_tri_seen_f3 = false, g_tri_seen_g3 = false;
+static int64_t g_tri_end = -1;
+static int64_t g_triples_checked = 0;
+extern "C" int64_t sim_triples_checked() { return g_triples_checked; }
+static int g_ngrids = 0;
+static const GridDev *g_tri_grids = nullptr;
+template <typename real>
+static std::vector<int64_t> &times(const real *buf, int gi, const GridDev &g);
+static void tri_begin(const void *out, int64_t end, const GridDev *grids) {
+  if (!g_tri_seen_f3 && !g_tri_seen_g3) {
+    g_tri_out = out;
+    g_tri_end = end;
+    g_tri_cov.clear();
+  }
+  if (out != g_tri_out || end != g_tri_end) {
+    fprintf(stderr, "three-step launch and third general step of different triples\n");
+    abort();
+  }
+  g_tri_grids = grids;
+}
+template <typename real>
+static void tri_done() {
+  if (!(g_tri_seen_f3 && g_tri_seen_g3)) return;
+  for (int gi = 0; gi < g_ngrids; ++gi) {
+    const GridDev &g = g_tri_grids[gi];
+    const std::vector<int64_t> &tv = times((const real *)g_tri_out, gi, g);
+    for (size_t i = 0; i < tv.size(); ++i)
+      if (tv[i] != g_tri_end) {
+        fprintf(stderr, "triple output cell %zu of grid %d holds time %lld, not %lld\n", i, gi,
+                (long long)tv[i], (long long)g_tri_end);
+        abort();
+      }
+    std::vector<int> &v = g_tri_cov[gi];
+    if (v.size() != (size_t)g.nx * g.ny) { fprintf(stderr, "triple wrote nothing of grid %d\n", gi); abort(); }
+    for (size_t i = 0; i < v.size(); ++i)
+      if (v[i] != 1) {
+        fprintf(stderr, "triple wrote cell %zu of grid %d %d times\n", i, gi, v[i]);
+        abort();
+      }
+  }
+  g_tri_cov.clear();
+  g_tri_out = nullptr;
+  g_tri_seen_f3 = g_tri_seen_g3 = false;
+  ++g_triples_checked;
+}
 // Two-step path bookkeeping. Each launch gets a sequence number and stamps
 // the cells it writes in its output buffer. A pair is: the general kernel's
 // first step (g1: its tiles and the two-step blocks' border strips, into the
@@ -112,7 +229,7 @@ static void plane_read(const void *p, int64_t t, const char *what) {
     abort();
   }
 }
-static int g_ngrids = 0;
+
 static bool g_seen_f2 = false, g_seen_g2 = false;
 static int64_t g_pairs_checked = 0;
 
@@ -153,8 +270,12 @@ hipError_t launch_step(const StepArgs<real> &a, int waves, int, int ntiles, int 
   const int64_t seq = g_seq++;
   const int W = 64 * waves;
   if (a.fmid) g_fmid = a.fmid;
-  const bool first = g_fmid && (const void *)a.fout == g_fmid;
-  const bool second = g_fmid && (const void *)a.fin == g_fmid;
+  const bool first = !a.tri_step && g_fmid && (const void *)a.fout == g_fmid;
+  const bool second = !a.tri_step && g_fmid && (const void *)a.fin == g_fmid;
+  if (a.tri_step == 3) {
+    if (g_tri_seen_g3) { fprintf(stderr, "two third general steps in one triple\n"); abort(); }
+    tri_begin(a.fout, a.t + 1, a.grids);
+  }
   if (first) g_g1_seq = seq;
   if (second) {
     if (g_seen_g2) { fprintf(stderr, "two second general steps in one pair\n"); abort(); }
@@ -171,6 +292,12 @@ hipError_t launch_step(const StepArgs<real> &a, int waves, int, int ntiles, int 
     for (int y = t.y0; y < t.y1; ++y)
       for (int x = t.x0; x < t.x0 + W && x < g.nx; ++x) {
         out[(size_t)y * g.nx + x] = seq;
+        time_step_cell(a, t.g, g, x, y, 1, "general step");
+        if (a.tri_step == 3) {
+          std::vector<int> &v = g_tri_cov[t.g];
+          if (v.empty()) v.assign((size_t)g.nx * g.ny, 0);
+          v[(size_t)y * g.nx + x] += 1;
+        }
         if (!second) continue;
         cov(t.g, g)[(size_t)y * g.nx + x] += 1;
         for (int dy = -2; dy <= 2; ++dy)
@@ -198,6 +325,10 @@ hipError_t launch_step(const StepArgs<real> &a, int waves, int, int ntiles, int 
     g_seen_g2 = true;
     pair_check_done();
   }
+  if (a.tri_step == 3) {
+    g_tri_seen_g3 = true;
+    tri_done<real>();
+  }
   return hipSuccess;
 }
 template <typename real>
@@ -210,6 +341,9 @@ hipError_t launch_interior(const StepArgs<real> &a, int waves, int, int ntiles, 
     check_pop(a.fin, g, "int fin");
     check_pop(a.fout, g, "int fout");
     if (a.rho_out) check_range(a.rho_out + g.c_off, sizeof(real) * (size_t)g.pitch * g.ny, "int stash out");
+    const TileDev t = a.tiles[i];
+    for (int y = t.y0; y < t.y1; ++y)
+      for (int x = t.x0; x < t.x0 + 64 * waves && x < g.nx; ++x) time_step_cell(a, t.g, g, x, y, 1, "interior step");
   }
   if (a.rho_out) plane_written(a.rho_out, a.t);
   return hipSuccess;
@@ -271,6 +405,7 @@ hipError_t launch_fused2(const StepArgs<real> &a, int waves, int ntiles, hipStre
         const size_t c = (size_t)y * g.nx + x;
         g_cov[t.g][c] += 1;
         out[c] = seq;
+        time_step_cell(a, t.g, g, x, y, 2, "two-step block");
       }
   }
   if (a.rho_out) {
@@ -279,6 +414,64 @@ hipError_t launch_fused2(const StepArgs<real> &a, int waves, int ntiles, hipStre
   }
   g_seen_f2 = true;
   pair_check_done();
+  return hipSuccess;
+}
+// The three-step kernel: its blocks inside the grid with six rows and
+// columns of reach clear of walls, the y-wrap, the rigid row, source disks
+// (over the cells its first stages compute: 5 beyond the block) and
+// receivers in its rows; each block's cells read only cells of time a.t
+// within six and become a.t + 3.
+template <typename real>
+hipError_t launch_fused3(const StepArgs<real> &a, int waves, int ntiles, hipStream_t) {
+  if (ntiles <= 0) return hipSuccess;
+  if (waves != 2 && waves != 4) { fprintf(stderr, "three-step waves %d\n", waves); abort(); }
+  if (a.fmid || a.rho_out || a.tri_step) { fprintf(stderr, "three-step launch with pair or stash fields set\n"); abort(); }
+  const int W = 64 * waves;
+  check_range(a.ftiles, sizeof(FusedTileDev) * ntiles, "three-step tiles");
+  g_ngrids = 0;
+  for (int64_t fe = 0; fe < a.f_elems; ++g_ngrids)
+    fe = a.grids[g_ngrids].f_off + 9 * (int64_t)a.grids[g_ngrids].pitch * a.grids[g_ngrids].ny;
+  if (g_tri_seen_f3) { fprintf(stderr, "two three-step launches in one triple\n"); abort(); }
+  tri_begin(a.fout, a.t + 3, a.grids);
+  for (int gi = 0; gi < g_ngrids; ++gi)
+    if (g_tri_cov[gi].empty()) g_tri_cov[gi].assign((size_t)a.grids[gi].nx * a.grids[gi].ny, 0);
+  for (int i = 0; i < ntiles; ++i) {
+    const FusedTileDev t = a.ftiles[i];
+    if (t.g < 0) continue;
+    if (t.g >= g_ngrids) { fprintf(stderr, "three-step tile grid %d out of range\n", t.g); abort(); }
+    const GridDev &g = a.grids[t.g];
+    if (t.x0 < 0 || t.x1 > g.nx || t.x1 <= t.x0 || t.x1 - t.x0 > W || t.y0 - 6 < 0 ||
+        t.y1 + 5 > g.ny - 1 || t.y0 >= t.y1 || t.y1 - t.y0 > kFusedMaxRows) {
+      fprintf(stderr, "bad three-step tile g=%d x0=%d x1=%d y0=%d y1=%d (nx=%d ny=%d)\n", t.g, t.x0, t.x1, t.y0, t.y1, g.nx, g.ny);
+      abort();
+    }
+    check_pop(a.fin, g, "three-step fin");
+    check_pop(a.fout, g, "three-step fout");
+    const int rr = g.rigid_row;
+    if (rr > 0 && t.y0 - 5 <= rr && t.y1 + 4 >= rr - 1) { fprintf(stderr, "three-step tile pulls across the rigid row\n"); abort(); }
+    const bool px = g.bc[kEdgeLeft] == kPeriodic, py = g.bc[kEdgeTop] == kPeriodic;
+    if (!px && (t.x0 - 6 < 0 || t.x1 + 5 > g.nx - 1)) { fprintf(stderr, "three-step tile pulls across a side wall\n"); abort(); }
+    for (int si = 0; si < g.nsrc; ++si) {
+      const SourceDev q = a.sources[g.src_off + si];
+      for (int y = t.y0 - 5; y <= t.y1 + 4; ++y)
+        for (int x = t.x0 - 5; x <= t.x1 + 4; ++x) {
+          double dx = x - q.x, dy = y - q.y;
+          if (px) { if (dx > 0.5 * g.nx) dx -= g.nx; else if (dx < -0.5 * g.nx) dx += g.nx; }
+          if (py) { if (dy > 0.5 * g.ny) dy -= g.ny; else if (dy < -0.5 * g.ny) dy += g.ny; }
+          if (dx * dx + dy * dy <= 81.0 * q.sigma * q.sigma) { fprintf(stderr, "source reaches a three-step tile\n"); abort(); }
+        }
+    }
+    if (g.nrec > 0)
+      for (int y = t.y0; y < t.y1; ++y)
+        if (a.itab[g.rowtab_off + y] >= 0) { fprintf(stderr, "receiver row %d in a three-step tile\n", y); abort(); }
+    for (int y = t.y0; y < t.y1; ++y)
+      for (int x = t.x0; x < t.x1; ++x) {
+        g_tri_cov[t.g][(size_t)y * g.nx + x] += 1;
+        time_step_cell(a, t.g, g, x, y, 3, "three-step block");
+      }
+  }
+  g_tri_seen_f3 = true;
+  tri_done<real>();
   return hipSuccess;
 }
 template <typename real>
@@ -290,6 +483,17 @@ hipError_t launch_filter(const real *fin, real *fout, const GridDev *grids, cons
     if (tiles[i].g < 0) continue;
     check_pop(fin, grids[tiles[i].g], "filter in");
     check_pop(fout, grids[tiles[i].g], "filter out");
+  }
+  // the filter keeps the time: each cell it writes (it reads two cells along
+  // each axis) takes the time of fin's cell
+  for (int i = 0; i < ntiles; ++i) {
+    const TileDev t = tiles[i];
+    if (t.g < 0) continue;
+    const GridDev &g = grids[t.g];
+    const std::vector<int64_t> &in = times(fin, t.g, g);
+    std::vector<int64_t> &out = times(fout, t.g, g);
+    for (int y = t.y0; y < t.y1; ++y)
+      for (int x = t.x0; x < t.x0 + 256 && x < g.nx; ++x) out[(size_t)y * g.nx + x] = in[(size_t)y * g.nx + x];
   }
   return hipSuccess;
 }
@@ -562,6 +766,7 @@ hipError_t launch_add_time(int64_t *t, int64_t v, hipStream_t) { check_range(t, 
   template hipError_t launch_step<real>(const StepArgs<real> &, int, int, int, int, hipStream_t); \
   template hipError_t launch_interior<real>(const StepArgs<real> &, int, int, int, hipStream_t); \
   template hipError_t launch_fused2<real>(const StepArgs<real> &, int, int, hipStream_t); \
+  template hipError_t launch_fused3<real>(const StepArgs<real> &, int, int, hipStream_t); \
   template hipError_t launch_filter<real>(const real *, real *, const GridDev *, const TileDev *, int, real, hipStream_t); \
   template hipError_t launch_adjoint<real>(const AdjArgs<real> &, int, int, hipStream_t); \
   template hipError_t launch_adjoint_interior<real>(const AdjArgs<real> &, int, int, hipStream_t); \
