@@ -673,7 +673,7 @@ def main():
     step_gbs = 18 * esize * cells / (ms_step / 1e3) / 1e9
     rl["whole_step_GBps"] = round(step_gbs, 1)
     rl["note"] = ("whole_step_GBps: 18 population words per cell and step over the timed "
-                  "steps -- above the HBM peak when two steps share one pass")
+                  "steps -- above the HBM peak when several steps share one pass")
     out = {
         "metric": METRIC, "value": round(glups, 3), "unit": "GLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 5),
