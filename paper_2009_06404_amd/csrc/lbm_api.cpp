@@ -1354,13 +1354,18 @@ int step_chunks(lbm_ctx *c, int64_t n) {
   // triple of steps on the multi-step paths once: after an even chunk of
   // single steps the state is back in its buffer, after a chunk of an odd
   // number of pairs or triples in the other one.
+  // A chunk must be a whole number of the path's units (a context on the
+  // three-step path whose grids hold only two-step blocks runs pairs, and a
+  // chunk of an odd multiple of 3 steps is then not whole pairs): otherwise
+  // the steps run launched directly.
   const int chunk = c->launch.graph_chunk;
-  if (chunk > 0 && n >= chunk) {
+  const int unit = use_tri(c) ? 3 : use_fused(c) ? 2 : 1;
+  if (chunk > 0 && n >= chunk && chunk % unit == 0) {
     if (c->gchunk != chunk) {
       rc = build_graphs<real>(c, chunk);
       if (rc) return rc;
     }
-    const int swaps = use_tri(c) ? chunk / 3 : use_fused(c) ? chunk / 2 : chunk;
+    const int swaps = chunk / unit;
     HIP_TRY(launch_set_time(c->d_time.p, c->t, c->stream));
     while (n >= chunk) {
       HIP_TRY(hipGraphLaunch(c->gexec[c->cur], c->stream));

@@ -121,3 +121,33 @@ def test_adjoint_with_three_step_launch(dtype):
     for k in ("trace", "adj", "grad_kappa"):
         assert np.array_equal(a[k], b[k]), k
     assert np.allclose(a["grad_amp"], b["grad_amp"], rtol=1e-13, atol=0)
+
+
+def _short_grid(nx=600, ny=11, tau=0.9):
+    from workloads import BC_FREE0, BC_PERIODIC, BC_RIGID, Medium, Problem, Source
+    from workloads.configs import lame_from_poisson
+    lam, mu = lame_from_poisson(0.25)
+    rec = [(x, 0) for x in range(0, nx, 7)]
+    return Problem(nx=nx, ny=ny, bc=(BC_FREE0, BC_RIGID, BC_PERIODIC, BC_PERIODIC),
+                   medium=Medium("homogeneous", lam, mu, 1.0), tau=tau,
+                   sources=[Source(60.0, 5.0, 1.5, 0.0, 1.0, 1.0, 12.0, 18.0)],
+                   receivers=np.asarray(rec, np.int32), comp_mask=3, nsteps=NSTEPS,
+                   name="short")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_three_step_launch_on_grids_without_three_step_blocks(dtype):
+    """An 11-row grid holds two-step blocks (own rows 4..6) but no three-step
+    blocks (six rows of reach each side): under fuse_steps = 3 it runs pairs.
+    A graph chunk of 9 steps is then not whole pairs and the steps run
+    launched directly; a chunk of 12 runs as graphs of 6 pairs. Both give the
+    single-step bits."""
+    p = _short_grid()
+    launch = dict(waves=2, rows=4, fuse_rows=8, fuse_steps=3, graph_chunk=9)
+    kt = _kernel_times(p, dtype, launch, 2)
+    assert kt["fused_steps"] == 2 and kt["fused_cells"] > 0, kt
+    ref = run_gpu(p, NSTEPS, dtype, launch=dict(waves=2, rows=4))
+    for lc in (launch, dict(launch, graph_chunk=12)):
+        g = run_gpu(p, NSTEPS, dtype, launch=lc)
+        assert np.array_equal(ref["fstar"], g["fstar"]), lc
+        assert np.array_equal(ref["trace"], g["trace"]), lc
