@@ -378,9 +378,10 @@ def bench_hbm_scale(torch, w, Solver, steps: int = 200, warmup: int = 20,
     return out
 
 
-# triples of steps on the three-step path (blocks of 32 rows), 10 triples per
-# captured HIP graph
-BATCHED_LAUNCH = {"waves": 2, "rows": 8, "fuse_rows": 32, "fuse_steps": 3, "graph_chunk": 30}
+# triples of steps on the three-step path (blocks of 192 columns by 32 rows),
+# 10 triples per captured HIP graph
+BATCHED_LAUNCH = {"waves": 2, "rows": 8, "fuse_rows": 32, "fuse_steps": 3, "tri_waves": 3,
+                  "graph_chunk": 30}
 # 1024-column grids: narrow, short tiles for the adjoint kernels; the recorded
 # forward (captured graphs of 10 pairs) and the recompute run on the two-step
 # path (128-column blocks)

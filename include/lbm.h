@@ -137,7 +137,7 @@ typedef struct {
                          of 2048^2 cells and more. */
   int32_t fuse_steps; /* steps per pass of the blocks when fuse_rows > 0: 2
                          (0 means 2) or 3. With 3 the steps run in triples:
-                         blocks of 64 x min(max(waves, 2), 4) columns take
+                         blocks of 64 x tri_waves columns take
                          three steps in one pass (the two intermediate states
                          stay on chip; the blocks keep six rows and columns
                          clear of walls, the y-wrap, sources and receivers);
@@ -157,6 +157,11 @@ typedef struct {
                          (LBM_E_NOMEM if the device cannot hold it) and
                          frees when fuse_steps changes back or the context is
                          destroyed. */
+  int32_t tri_waves;  /* output wavefronts of a three-step block: 2, 3 or 4
+                         (blocks of 128, 192 or 256 columns; each workgroup
+                         has one more wavefront for the halo columns); 0 takes
+                         min(max(waves, 2), 4). Leftover pairs and single
+                         steps keep the widths that waves gives. */
 } lbm_launch;
 
 /* Bytes of device workspace lbm_init needs for nbatch grids of the given

@@ -64,7 +64,8 @@ class lbm_source(C.Structure):
 class lbm_launch(C.Structure):
     _fields_ = [("waves", C.c_int32), ("rows", C.c_int32), ("graph_chunk", C.c_int32),
                 ("prefetch", C.c_int32), ("split", C.c_int32), ("pair", C.c_int32),
-                ("overlap", C.c_int32), ("fuse_rows", C.c_int32), ("fuse_steps", C.c_int32)]
+                ("overlap", C.c_int32), ("fuse_rows", C.c_int32), ("fuse_steps", C.c_int32),
+                ("tri_waves", C.c_int32)]
 
 
 class lbm_kernel_times(C.Structure):
@@ -301,8 +302,9 @@ def lbm_get_launch(ctx):
 
 def lbm_set_launch(ctx, waves: int, rows: int, graph_chunk: int = 0, prefetch: int = 1,
                    split: int = 1, pair: int = 0, overlap: int = 1, fuse_rows: int = 0,
-                   fuse_steps: int = 2) -> None:
-    o = lbm_launch(waves, rows, graph_chunk, prefetch, split, pair, overlap, fuse_rows, fuse_steps)
+                   fuse_steps: int = 2, tri_waves: int = 0) -> None:
+    o = lbm_launch(waves, rows, graph_chunk, prefetch, split, pair, overlap, fuse_rows, fuse_steps,
+                   tri_waves)
     check(lib().lbm_set_launch(ctx, C.byref(o)))
 
 

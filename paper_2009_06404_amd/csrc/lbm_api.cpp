@@ -461,14 +461,15 @@ void build_tiles(const lbm_ctx *c, int waves, int rows, bool split, std::vector<
 // tiles where the grid would otherwise give too few workgroups to fill 256
 // compute units.
 // Launch shape by size (measured on MI355X): large contexts take the
-// three-step path in blocks of 128 columns, 128 rows high on grids of 4096
-// rows and more (4096^2 FP32: 177 GLUPS against 138 for the two-step path's
-// best shape; 16384^2: 191 against 154; FP64 4096^2: 80.9 against 74.8) and
-// 32 rows on shorter grids (the 512 batched grids of side 256..2048: 162
-// against 155 at 128 rows and 134 for pairs). The block height also sets how
-// many workgroups a launch has: at 96 or 104 rows on 4096^2 the three-step
-// kernel fills every slot of the chip and the general kernel beside it
-// pushes its last blocks into a second round (135 GLUPS). Small contexts run
+// three-step path. Blocks of 192 columns (three output wavefronts beside the
+// halo wavefront: one wavefront in four carries the halo instead of one in
+// three) and 96 rows on grids of 4096 rows and more: 16384^2 FP32 203 GLUPS
+// against 191 with 128-column blocks, FP64 4096^2 90.3 against 81.6; 32 rows
+// on shorter grids (the 512 batched grids of side 256..2048: 170 against 162).
+// FP32 grids of 4096..8191 rows keep 128-column blocks of 128 rows (4096^2:
+// 176 GLUPS; 192-column blocks of 96 rows reach 182 launched directly but 141
+// in captured graphs, where the general launches take slots first and the
+// blocks' last workgroups wait for a second round). Small contexts run
 // single steps in smaller tiles.
 lbm_launch default_launch(const lbm_ctx *c) {
   int64_t cells = 0;
@@ -478,11 +479,18 @@ lbm_launch default_launch(const lbm_ctx *c) {
     max_ny = std::max(max_ny, g.ny);
   }
   lbm_launch l{8, c->dtype == LBM_F64 ? 4 : 8, 0, 1, 1, 0, 1, 0, 2};
-  // three-step blocks of 128 columns (more workgroups per CU hide the row
-  // loop's barriers), taller on tall grids
+  // three-step blocks of 192 columns (four wavefronts, one of them for the
+  // halo), 96 rows tall on tall grids and 32 otherwise; FP32 grids of 4096 to
+  // 8191 rows take 128-column blocks of 128 rows, where five such workgroups
+  // per CU fill the chip in one round beside the general launches
   l.waves = 2;
   l.fuse_steps = 3;
-  l.fuse_rows = max_ny >= 4096 ? 128 : 32;
+  l.tri_waves = 3;
+  l.fuse_rows = max_ny >= 4096 ? 96 : 32;
+  if (c->dtype == LBM_F32 && max_ny >= 4096 && max_ny < 8192) {
+    l.tri_waves = 2;
+    l.fuse_rows = 128;
+  }
   // triples run as captured graphs of 10 triples: as fast as direct launches
   // on MI355X, with one host call per 30 steps
   l.graph_chunk = 30;
@@ -654,8 +662,11 @@ int commit(lbm_ctx *c) {
 // Two-step blocks are 64 * fused_waves columns wide: the launch's waves
 // (2, 4 or 8; 1 counts as 2).
 int fused_waves(const lbm_ctx *c) { return std::max(2, (int)c->launch.waves); }
-// Three-step blocks: 128 or 256 columns (8 waves count as 4).
-int tri_waves(const lbm_ctx *c) { return std::min(4, fused_waves(c)); }
+// Three-step blocks: 128, 192 or 256 columns (the launch's tri_waves; 0
+// follows waves, 8 counting as 4).
+int tri_waves(const lbm_ctx *c) {
+  return c->launch.tri_waves ? (int)c->launch.tri_waves : std::min(4, fused_waves(c));
+}
 
 struct Seg {
   int lo, hi;    // [lo, hi)
@@ -2329,6 +2340,8 @@ int lbm_set_launch(lbm_ctx *c, const lbm_launch *cfg) {
     return fail(LBM_E_INVALID, "fuse_rows must be 0 or in [4, 248]");
   if (cfg->fuse_steps != 0 && cfg->fuse_steps != 2 && cfg->fuse_steps != 3)
     return fail(LBM_E_INVALID, "fuse_steps must be 2 or 3 (0 means 2)");
+  if (cfg->tri_waves != 0 && (cfg->tri_waves < 2 || cfg->tri_waves > 4))
+    return fail(LBM_E_INVALID, "tri_waves must be 0, 2, 3 or 4");
   const int fsteps = cfg->fuse_steps == 3 ? 3 : 2;
   {
     const std::string why = reach_error(c->grids, c->dtype, cfg->rows, cfg->fuse_rows, fsteps);
@@ -2336,7 +2349,7 @@ int lbm_set_launch(lbm_ctx *c, const lbm_launch *cfg) {
   }
   const bool retile = cfg->waves != c->launch.waves || cfg->rows != c->launch.rows ||
                       cfg->split != c->launch.split || cfg->fuse_rows != c->launch.fuse_rows ||
-                      fsteps != c->launch.fuse_steps;
+                      fsteps != c->launch.fuse_steps || cfg->tri_waves != c->launch.tri_waves;
   if (cfg->split < 0 || cfg->split > 1 || cfg->pair < 0 || cfg->pair > 1 || cfg->overlap < 0 ||
       cfg->overlap > 1)
     return fail(LBM_E_INVALID, "split, pair and overlap must be 0 or 1");
@@ -2372,7 +2385,8 @@ namespace {
 // Tuning results per (GPU architecture, dtype, boundary class, size class,
 // path), kept for the life of the process and, when the environment variable
 // LBM_TUNE_CACHE names a file, across processes: one line
-// "key|waves rows prefetch pair fuse_rows" per result, read the first time
+// "key|waves rows prefetch pair fuse_rows tri_waves" per result (lines
+// without the last field, from before it existed, read it as 0), read the first time
 // the file is named and appended to after each tuning run (the last line of a
 // key wins). Lines that do not parse or hold an invalid launch are skipped.
 struct TuneCache {
@@ -2389,7 +2403,8 @@ TuneCache &tune_cache() {
 bool tuned_launch_ok(const lbm_launch &l) {
   return (l.waves == 1 || l.waves == 2 || l.waves == 4 || l.waves == 8) && l.rows >= 1 &&
          l.rows <= 4096 && l.prefetch >= 1 && l.prefetch <= 2 && (l.pair == 0 || l.pair == 1) &&
-         (l.fuse_rows == 0 || (l.fuse_rows >= 4 && l.fuse_rows <= kFusedMaxRows));
+         (l.fuse_rows == 0 || (l.fuse_rows >= 4 && l.fuse_rows <= kFusedMaxRows)) &&
+         (l.tri_waves == 0 || (l.tri_waves >= 2 && l.tri_waves <= 4));
 }
 
 int floor_log2(int64_t v) {
@@ -2443,9 +2458,10 @@ void tune_cache_load(TuneCache &tc) {
     const char *bar = std::strrchr(line, '|');
     if (!bar) continue;
     lbm_launch l{};
-    if (std::sscanf(bar + 1, "%d %d %d %d %d", &l.waves, &l.rows, &l.prefetch, &l.pair,
-                    &l.fuse_rows) != 5 || !tuned_launch_ok(l))
-      continue;
+    const int got = std::sscanf(bar + 1, "%d %d %d %d %d %d", &l.waves, &l.rows, &l.prefetch,
+                                &l.pair, &l.fuse_rows, &l.tri_waves);
+    if (got < 5 || !tuned_launch_ok(l)) continue;
+    if (got == 5) l.tri_waves = 0;
     tc.map[std::string(line, bar - line)] = l;
   }
   std::fclose(f);
@@ -2459,8 +2475,8 @@ void tune_cache_store(TuneCache &tc, const std::string &key, const lbm_launch &l
   if (!path || !*path) return;
   FILE *f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s|%d %d %d %d %d\n", key.c_str(), l.waves, l.rows, l.prefetch, l.pair,
-               l.fuse_rows);
+  std::fprintf(f, "%s|%d %d %d %d %d %d\n", key.c_str(), l.waves, l.rows, l.prefetch, l.pair,
+               l.fuse_rows, l.tri_waves);
   std::fclose(f);
 }
 
@@ -2473,6 +2489,7 @@ int apply_tuned(lbm_ctx *c, const lbm_launch &l, lbm_launch *chosen) {
   next.prefetch = l.prefetch;
   next.pair = l.pair;
   next.fuse_rows = l.fuse_rows;
+  next.tri_waves = l.tri_waves;
   c->launch = next;
   c->launch_set = true;
   const int rc = rebuild_tiles(c);
@@ -2525,18 +2542,24 @@ int lbm_autotune(lbm_ctx *c, int32_t steps, lbm_launch *chosen) {
   if (e == hipSuccess) e = hipEventCreate(&ev1);
   int64_t cells = 0;
   for (auto &g : c->grids) cells += (int64_t)g.nx * g.ny;
-  // Candidates. On the two- and three-step paths: the block width (waves)
-  // and height (fuse_rows), the single-step shape kept for leftover steps. Otherwise the
+  // Candidates. On the two- and three-step paths: the block width (waves,
+  // or tri_waves for three-step blocks) and height (fuse_rows), the
+  // single-step shape kept for leftover steps. Otherwise the
   // single-step tile width, height, prefetch depth and column pairing.
   std::vector<lbm_launch> cands;
   if (pairs) {
     const std::vector<int> heights = unit == 3 ? std::vector<int>{16, 32, 48, 64, 96, 128, 160}
                                                : std::vector<int>{16, 24, 29, 32, 44, 48, 64};
-    for (int w : {2, 4, 8})
+    for (int w : {2, 3, 4, 8})
       for (int fr : heights) {
         if (unit == 3 && w == 8) continue;   // three-step blocks are at most 4 waves wide
+        if (unit == 2 && w == 3) continue;   // two-step blocks: 2, 4 or 8
         lbm_launch cand = keep;
-        cand.waves = w;
+        if (unit == 3) {
+          cand.tri_waves = w;
+        } else {
+          cand.waves = w;
+        }
         cand.fuse_rows = fr;
         if (reach_error(c->grids, c->dtype, cand.rows, fr, keep.fuse_steps).empty()) cands.push_back(cand);
       }
@@ -2547,7 +2570,8 @@ int lbm_autotune(lbm_ctx *c, int32_t steps, lbm_launch *chosen) {
       for (int pf = 1; pf <= 2; ++pf)
         for (int w : {1, 2, 4, 8})
           for (int r : {2, 4, 8, 16, 32, 64}) {
-            lbm_launch cand{w, r, 0, pf, keep.split, pair, keep.overlap, 0, keep.fuse_steps};
+            lbm_launch cand{w, r, 0, pf, keep.split, pair, keep.overlap, 0, keep.fuse_steps,
+                            keep.tri_waves};
             if (pair && w == 1) continue;
             const int64_t tiles = cells / ((int64_t)64 * w * r);
             if (tiles < 512 && !(w == 1 && r == 4)) continue;

@@ -1244,6 +1244,7 @@ hipError_t launch_fused3(const StepArgs<real> &a, int waves, int ntiles, hipStre
   if (ntiles <= 0) return hipSuccess;
   dim3 grid(ntiles), block(64 * waves + 64);
   if (waves == 2) hipLaunchKernelGGL((fused3_kernel<real, 2>), grid, block, 0, stream, a);
+  else if (waves == 3) hipLaunchKernelGGL((fused3_kernel<real, 3>), grid, block, 0, stream, a);
   else if (waves == 4) hipLaunchKernelGGL((fused3_kernel<real, 4>), grid, block, 0, stream, a);
   else return hipErrorInvalidValue;
   return hipGetLastError();

@@ -141,9 +141,9 @@ class Solver:
 
     def set_launch(self, waves: int, rows: int, graph_chunk: int = 0, prefetch: int = 1,
                    split: int = 1, pair: int = 0, overlap: int = 1, fuse_rows: int = 0,
-                   fuse_steps: int = 2) -> None:
+                   fuse_steps: int = 2, tri_waves: int = 0) -> None:
         L.lbm_set_launch(self.ctx, waves, rows, graph_chunk, prefetch, split, pair, overlap,
-                         fuse_rows, fuse_steps)
+                         fuse_rows, fuse_steps, tri_waves)
 
     def autotune(self, steps: int = 5) -> dict:
         return L.lbm_autotune(self.ctx, steps)

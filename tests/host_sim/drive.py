@@ -184,7 +184,8 @@ for name, bc, rr, nx, ny in FUSED:
 pairs, kt = run_forward([problem(FUSED[1][1], 40, 530, 90, 6), problem(FUSED[0][1], -1, 300, 64, 7),
                          problem(FUSED[2][1], -1, 1100, 50, 8)], 0, dict(waves=2, rows=4, fuse_rows=6))
 assert pairs > 0, pairs
-# three-step path: blocks of 128 and 256 columns (8 waves count as 4); the
+# three-step path: blocks of 128, 192 and 256 columns (tri_waves, or waves
+# with 8 counting as 4); the
 # step counts leave a pair and a single step over; every launch reads only
 # cells holding the state of its starting time, and every triple writes each
 # cell once
@@ -194,7 +195,8 @@ for name, bc, rr, nx, ny in FUSED:
     p = problem(bc, rr, nx, ny, 5, sources=[Source(nx * 0.7, ny * 0.5, 2.0, 0.3, 0.9, 1.0, 12.0, 16.0)],
                 receivers=[(x, 0) for x in range(0, nx, 5)] + [(x, 77) for x in range(3, nx, 11)])
     for fr in (4, 8, 13):
-        for extra in (dict(), dict(overlap=0), dict(graph_chunk=6), dict(waves=8), dict(waves=2)):
+        for extra in (dict(), dict(overlap=0), dict(graph_chunk=6), dict(waves=8), dict(waves=2),
+                      dict(tri_waves=3), dict(waves=8, tri_waves=3, overlap=0), dict(tri_waves=2)):
             t0 = sim.sim_triples_checked()
             pairs, kt = run_forward([p], 0, dict(dict(waves=4, rows=8, fuse_rows=fr, fuse_steps=3), **extra))
             assert sim.sim_triples_checked() > t0 and kt["fused_steps"] == 3 and kt["fused_cells"] > 0, \
@@ -204,6 +206,11 @@ t0 = sim.sim_triples_checked()
 pairs, kt = run_forward([problem(FUSED[1][1], 40, 530, 90, 6), problem(FUSED[0][1], -1, 300, 64, 7),
                          problem(FUSED[2][1], -1, 1100, 50, 8)], 0,
                         dict(waves=2, rows=4, fuse_rows=6, fuse_steps=3), steps=(3, 7, 12))
+assert sim.sim_triples_checked() > t0, kt
+t0 = sim.sim_triples_checked()
+pairs, kt = run_forward([problem(FUSED[1][1], 40, 530, 90, 6), problem(FUSED[0][1], -1, 300, 64, 7),
+                         problem(FUSED[2][1], -1, 1100, 50, 8)], 0,
+                        dict(waves=1, rows=4, fuse_rows=6, fuse_steps=3, tri_waves=3), steps=(3, 7, 12))
 assert sim.sim_triples_checked() > t0, kt
 assert sim.sim_time_reads() > 0
 # autotuning: every candidate shape of either path runs through the checks
@@ -300,4 +307,17 @@ assert refused(ctx, rows=3) and refused(ctx, fuse_rows=5)
 assert not refused(ctx, fuse_rows=8, fuse_steps=2) and refused(ctx, fuse_rows=9, fuse_steps=2)
 L.lbm_destroy(ctx)
 print("ok descriptor reach", flush=True)
+# three-step block widths: 2, 3 or 4 wavefronts, 0 to follow waves
+ctx = init_only(4096, 40, L.LBM_F32, np.float32)
+for bad in (1, 5, -1):
+    try:
+        L.lbm_set_launch(ctx, **dict(L.lbm_get_launch(ctx), tri_waves=bad))
+        raise AssertionError(f"tri_waves {bad} accepted")
+    except L.LBMError as e:
+        assert "tri_waves" in str(e), str(e)
+for good in (0, 2, 3, 4):
+    L.lbm_set_launch(ctx, **dict(L.lbm_get_launch(ctx), tri_waves=good))
+    assert L.lbm_get_launch(ctx)["tri_waves"] == good
+L.lbm_destroy(ctx)
+print("ok three-step widths", flush=True)
 print("ALL OK", flush=True)

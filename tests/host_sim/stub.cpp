@@ -424,7 +424,7 @@ hipError_t launch_fused2(const StepArgs<real> &a, int waves, int ntiles, hipStre
 template <typename real>
 hipError_t launch_fused3(const StepArgs<real> &a, int waves, int ntiles, hipStream_t) {
   if (ntiles <= 0) return hipSuccess;
-  if (waves != 2 && waves != 4) { fprintf(stderr, "three-step waves %d\n", waves); abort(); }
+  if (waves < 2 || waves > 4) { fprintf(stderr, "three-step waves %d\n", waves); abort(); }
   if (a.fmid || a.rho_out || a.tri_step) { fprintf(stderr, "three-step launch with pair or stash fields set\n"); abort(); }
   const int W = 64 * waves;
   check_range(a.ftiles, sizeof(FusedTileDev) * ntiles, "three-step tiles");

@@ -5,7 +5,8 @@ The three-step kernel performs the single-step kernels' per-cell operations in
 the same order, so a run on the three-step path must equal the single-step
 run bit for bit: state, traces and moments, for step counts that leave a pair
 and a single step over, with and without the general kernel's first step on
-the second stream, for blocks of 128 and 256 columns (8 waves count as 4) and
+the second stream, for blocks of 128, 192 and 256 columns (tri_waves 2, 3 and
+4; without tri_waves the width follows waves, 8 counting as 4) and
 several heights, the boundary mixes and media of the two-step tests and a
 batch of uneven grids, launched directly and as captured HIP graphs
 (graph_chunk / 3 triples per graph, replayed several times, with direct steps
@@ -28,6 +29,9 @@ TRIPLES = [
     dict(waves=2, rows=4, fuse_rows=13, fuse_steps=3, graph_chunk=9),
     dict(waves=8, rows=8, fuse_rows=32, fuse_steps=3, graph_chunk=15, overlap=0),
     dict(waves=4, rows=4, fuse_rows=16, fuse_steps=3, graph_chunk=6),
+    dict(waves=2, rows=4, fuse_rows=7, fuse_steps=3, tri_waves=3),
+    dict(waves=4, rows=8, fuse_rows=24, fuse_steps=3, tri_waves=3, graph_chunk=9, overlap=0),
+    dict(waves=8, rows=8, fuse_rows=10, fuse_steps=3, tri_waves=2),
 ]
 
 
@@ -64,7 +68,9 @@ def test_three_step_path_batched_uneven_grids(dtype):
     ref = run_gpu(probs, NSTEPS, dtype, launch=dict(waves=2, rows=4))
     for launch in (dict(waves=2, rows=4, fuse_rows=6, fuse_steps=3),
                    dict(waves=4, rows=8, fuse_rows=16, fuse_steps=3, graph_chunk=12),
-                   dict(waves=2, rows=8, fuse_rows=32, fuse_steps=3, graph_chunk=9)):
+                   dict(waves=2, rows=8, fuse_rows=32, fuse_steps=3, graph_chunk=9),
+                   dict(waves=2, rows=8, fuse_rows=32, fuse_steps=3, tri_waves=3, graph_chunk=9),
+                   dict(waves=1, rows=4, fuse_rows=5, fuse_steps=3, tri_waves=3)):
         got = run_gpu(probs, NSTEPS, dtype, launch=launch)
         for g, (a, b) in enumerate(zip(ref, got)):
             assert np.array_equal(a["fstar"], b["fstar"]), (g, launch)
