@@ -579,7 +579,8 @@ def main():
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--rows", type=int, default=0)
-    ap.add_argument("--graph-chunk", type=int, default=100)
+    ap.add_argument("--graph-chunk", type=int, default=-1,
+                    help="steps per captured HIP graph; -1 keeps the library's default launch")
     ap.add_argument("--timed-launches", type=int, default=200,
                     help="steps of the per-kernel event-timing pass after the timed region")
     ap.add_argument("--no-extras", action="store_true",
@@ -648,7 +649,8 @@ def main():
     launch = s.launch()
     if args.waves or args.rows:
         launch.update({k: v for k, v in (("waves", args.waves), ("rows", args.rows)) if v})
-    launch["graph_chunk"] = args.graph_chunk
+    if args.graph_chunk >= 0:
+        launch["graph_chunk"] = args.graph_chunk
     s.set_launch(**launch)
     launch = s.launch()
 

@@ -131,12 +131,11 @@ typedef struct {
                          graph_chunk > 0 a chunk is graph_chunk / 2 pairs in
                          one captured graph (three kernels per pair, the fork
                          and join as graph edges). The default is set by
-                         size: the three-step path (fuse_steps 3) with
-                         graph_chunk 30 on contexts of 2048^2 cells and more,
-                         in 192-column blocks (tri_waves 3) of 96 rows on
-                         grids of 4096 rows and more and 32 rows otherwise,
-                         except FP32 grids of 4096..8191 rows, which take
-                         128-column blocks (tri_waves 2) of 128 rows. */
+                         size: on contexts of 2048^2 cells and more the
+                         three-step path (fuse_steps 3) launched directly
+                         (graph_chunk 0), in 192-column blocks (tri_waves 3)
+                         of 96 rows on grids of 4096 rows and more and 32
+                         rows otherwise. */
   int32_t fuse_steps; /* steps per pass of the blocks when fuse_rows > 0: 2
                          (0 means 2) or 3. With 3 the steps run in triples:
                          blocks of 64 x tri_waves columns take

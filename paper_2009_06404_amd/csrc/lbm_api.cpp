@@ -463,13 +463,14 @@ void build_tiles(const lbm_ctx *c, int waves, int rows, bool split, std::vector<
 // Launch shape by size (measured on MI355X): large contexts take the
 // three-step path. Blocks of 192 columns (three output wavefronts beside the
 // halo wavefront: one wavefront in four carries the halo instead of one in
-// three) and 96 rows on grids of 4096 rows and more: 16384^2 FP32 203 GLUPS
-// against 191 with 128-column blocks, FP64 4096^2 90.3 against 81.6; 32 rows
-// on shorter grids (the 512 batched grids of side 256..2048: 170 against 162).
-// FP32 grids of 4096..8191 rows keep 128-column blocks of 128 rows (4096^2:
-// 176 GLUPS; 192-column blocks of 96 rows reach 182 launched directly but 141
-// in captured graphs, where the general launches take slots first and the
-// blocks' last workgroups wait for a second round). Small contexts run
+// three), 96 rows high on grids of 4096 rows and more (4096^2 FP32: 182
+// GLUPS against 176 with 128-column blocks of 128 rows; 16384^2 203 against
+// 191; FP64 4096^2 90.3 against 81.6) and 32 rows on shorter grids (the 512
+// batched grids of side 256..2048: 170 against 162). The triples are
+// launched directly: as fast as captured graphs or faster everywhere
+// measured, and at 4096^2 FP32 the graphs' node scheduling leaves the
+// general launches waiting for compute units the block kernel holds (141
+// GLUPS in captured graphs against 182 direct). Small contexts run
 // single steps in smaller tiles.
 lbm_launch default_launch(const lbm_ctx *c) {
   int64_t cells = 0;
@@ -479,21 +480,11 @@ lbm_launch default_launch(const lbm_ctx *c) {
     max_ny = std::max(max_ny, g.ny);
   }
   lbm_launch l{8, c->dtype == LBM_F64 ? 4 : 8, 0, 1, 1, 0, 1, 0, 2};
-  // three-step blocks of 192 columns (four wavefronts, one of them for the
-  // halo), 96 rows tall on tall grids and 32 otherwise; FP32 grids of 4096 to
-  // 8191 rows take 128-column blocks of 128 rows, where five such workgroups
-  // per CU fill the chip in one round beside the general launches
   l.waves = 2;
   l.fuse_steps = 3;
   l.tri_waves = 3;
   l.fuse_rows = max_ny >= 4096 ? 96 : 32;
-  if (c->dtype == LBM_F32 && max_ny >= 4096 && max_ny < 8192) {
-    l.tri_waves = 2;
-    l.fuse_rows = 128;
-  }
-  // triples run as captured graphs of 10 triples: as fast as direct launches
-  // on MI355X, with one host call per 30 steps
-  l.graph_chunk = 30;
+  l.graph_chunk = 0;
   if (cells < 2048 * 2048) {
     l.waves = 4;
     l.rows = 4;
