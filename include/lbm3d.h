@@ -122,10 +122,13 @@ int lbm3_step(lbm3_ctx *ctx, int64_t n);
  * no source or receiver cell, then the general kernel over the others. */
 typedef struct {
   int64_t steps;         /* steps timed */
-  double lean_ms;        /* mean duration of one lean-kernel launch; 0 if none */
-  double general_ms;     /* mean duration of one general-kernel launch; 0 if none */
-  int64_t lean_cells;    /* cells one lean-kernel launch updates */
-  int64_t general_cells; /* cells one general-kernel launch updates */
+  double lean_ms;        /* mean duration of one lean-kernel launch over the tiles
+                            clear of faces, sources and receivers; 0 if none */
+  double general_ms;     /* mean duration of one step's other launches: the general
+                            kernel, then the lean kernel with sources over the tiles
+                            clear of faces and receivers near a source; 0 if none */
+  int64_t lean_cells;    /* cells the lean launch (without sources) updates */
+  int64_t general_cells; /* cells the other launches update */
   double step_ms;        /* mean duration of a step (both launches) */
 } lbm3_kernel_times;
 

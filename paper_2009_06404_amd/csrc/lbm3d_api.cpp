@@ -109,9 +109,10 @@ struct lbm3_ctx {
   DBuf<int32_t> d_rec_row, d_rec_plane, d_rec_x, d_rec_id, d_xyz;
   std::vector<Src3Dev> sources;
   std::vector<int32_t> rec_xyz;     // receivers (x, y, z), for the tile classification
-  // tile lists: lean, general, and every tile (for the macroscopic fields)
-  DBuf<Tile3Dev> d_lean, d_general, d_all;
-  int n_lean = 0, n_general = 0, n_all = 0;
+  // tile lists: lean, lean with sources, general, and every tile (for the
+  // macroscopic fields)
+  DBuf<Tile3Dev> d_lean, d_lean_src, d_general, d_all;
+  int n_lean = 0, n_lean_src = 0, n_general = 0, n_all = 0;
   int64_t lean_cells = 0, general_cells = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   // the general kernel runs on a second stream, beside the lean one
@@ -187,7 +188,8 @@ double axis_gap(double s, int a, int b, int n, bool periodic) {
 }
 
 // Split the tiles into the lean list (no pulled cell on a non-periodic face,
-// no source within 9 sigma of a cell, no receiver) and the general list.
+// no source within 9 sigma of a cell, no receiver), the lean-with-sources
+// list (the same but a source within reach) and the general list.
 int build_tiles(lbm3_ctx *c) {
   const int nx = c->nx, ny = c->ny, nz = c->nz, ty = c->rows_y;
   const int tw = lean_tx(c);   // tile width of the lean and general split
@@ -204,7 +206,7 @@ int build_tiles(lbm3_ctx *c) {
     const int x = c->rec_xyz[r], y = c->rec_xyz[r + 1], z = c->rec_xyz[r + 2];
     rec[((size_t)seg_of[z] * nty + y / ty) * ntx + x / tw] = 1;
   }
-  std::vector<Tile3Dev> lean, gen, all;
+  std::vector<Tile3Dev> lean, lean_src, gen, all;
   int64_t lean_cells = 0, gen_cells = 0;
   for (int k = 0; k < ns; ++k) {
     const int z0 = segs[k].first, z1 = segs[k].second;
@@ -212,7 +214,7 @@ int build_tiles(lbm3_ctx *c) {
       const int y0 = j * ty, h = std::min(ty, ny - y0);
       for (int i = 0; i < ntx; ++i) {
         const int x0 = i * tw, w = std::min(tw, nx - x0);
-        bool general = rec[((size_t)k * nty + j) * ntx + i] != 0;
+        bool general = rec[((size_t)k * nty + j) * ntx + i] != 0, src = false;
         // pulled cells: [x0-1, x0+w] x [y0-1, y0+h] x [z0-1, z1]
         if (!xper && (x0 - 1 <= 0 || x0 + w >= nx - 1)) general = true;
         if (!yper && (y0 - 1 <= 0 || y0 + h >= ny - 1)) general = true;
@@ -221,7 +223,7 @@ int build_tiles(lbm3_ctx *c) {
           const double cut = 9.0 * q.sigma;
           if (axis_gap(q.x, x0, x0 + w, nx, xper) <= cut && axis_gap(q.y, y0, y0 + h, ny, yper) <= cut &&
               axis_gap(q.z, z0, z1, nz, zper) <= cut)
-            general = true;
+            src = true;
         }
         const Tile3Dev t{x0, y0, z0, z1};
         const int64_t cells = (int64_t)w * h * (z1 - z0);
@@ -236,16 +238,18 @@ int build_tiles(lbm3_ctx *c) {
                 gen.push_back(Tile3Dev{xs, ys, zs, std::min(zs + kGeneralPlanes, z1)});
           gen_cells += cells;
         } else {
-          lean.push_back(t);
-          lean_cells += cells;
+          (src ? lean_src : lean).push_back(t);
+          (src ? gen_cells : lean_cells) += cells;   // timed with the general launch
         }
       }
     }
   }
   HIP3_TRY(c->d_lean.put(lean, c->stream));
+  HIP3_TRY(c->d_lean_src.put(lean_src, c->stream));
   HIP3_TRY(c->d_general.put(gen, c->stream));
   HIP3_TRY(c->d_all.put(all, c->stream));
   c->n_lean = (int)lean.size();
+  c->n_lean_src = (int)lean_src.size();
   c->n_general = (int)gen.size();
   c->n_all = (int)all.size();
   c->lean_cells = lean_cells;
@@ -254,28 +258,30 @@ int build_tiles(lbm3_ctx *c) {
 }
 
 int launch_list(lbm3_ctx *c, bool general, const Tile3Dev *tiles, int n, const void *fin,
-                void *fout, void *out10, int mode) {
+                void *fout, void *out10, int mode, bool src = false) {
   if (n <= 0) return LBM_OK;
   c->v.omega = 1.0 / c->tau;
-  const int rc = launch_step3(f64(c), general, general ? general_rows(c) : c->rows_y,
+  const int rc = launch_step3(f64(c), general, src, general ? general_rows(c) : c->rows_y,
                               general ? 64 : lean_tx(c), tiles, n, fin, fout, out10, c->v, c->t,
                               mode, c->stream);
   if (rc != 0) return fail3(LBM_E_DEVICE, std::string("step launch: ") + hipGetErrorString((hipError_t)rc));
   return LBM_OK;
 }
 
-// One step: the general tiles on the context's stream, the lean tiles beside
-// them on the library's second stream, forked from the context's stream
-// before the general launch and joined back after it. The two read the same
-// state and write disjoint cells. The general launch goes first so that its
-// few, slower workgroups start before the lean ones fill the chip (the fork's
-// wait delays the lean launch by a few microseconds).
+// One step: the general tiles and then the lean tiles near sources on the
+// context's stream, the other lean tiles beside them on the library's second
+// stream, forked from the context's stream before the general launch and
+// joined back after it. They read the same state and write disjoint cells.
+// The general launch goes first so that its few, slower workgroups start
+// before the lean ones fill the chip (the fork's wait delays the lean launch
+// by a few microseconds).
 int launch_step(lbm3_ctx *c) {
   const void *fin = c->fbuf[c->cur];
   void *fout = c->fbuf[c->cur ^ 1];
-  if (c->n_general > 0 && c->n_lean > 0) {
+  if (c->n_general + c->n_lean_src > 0 && c->n_lean > 0) {
     HIP3_TRY(hipEventRecord(c->fork, c->stream));
     int rc = launch_list(c, true, c->d_general.p, c->n_general, fin, fout, nullptr, 0);
+    if (!rc) rc = launch_list(c, false, c->d_lean_src.p, c->n_lean_src, fin, fout, nullptr, 0, true);
     if (rc) return rc;
     HIP3_TRY(hipStreamWaitEvent(c->side, c->fork, 0));
     hipStream_t main = c->stream;
@@ -288,6 +294,7 @@ int launch_step(lbm3_ctx *c) {
     return LBM_OK;
   }
   int rc = launch_list(c, false, c->d_lean.p, c->n_lean, fin, fout, nullptr, 0);
+  if (!rc) rc = launch_list(c, false, c->d_lean_src.p, c->n_lean_src, fin, fout, nullptr, 0, true);
   if (!rc) rc = launch_list(c, true, c->d_general.p, c->n_general, fin, fout, nullptr, 0);
   return rc;
 }
@@ -599,6 +606,7 @@ int lbm3_step_timed(lbm3_ctx *c, int64_t n, lbm3_kernel_times *out) {
     if (rc) return rc;
     HIP3_TRY(hipEventRecord(c->ev[1], c->stream));
     rc = launch_list(c, true, c->d_general.p, c->n_general, fin, fout, nullptr, 0);
+    if (!rc) rc = launch_list(c, false, c->d_lean_src.p, c->n_lean_src, fin, fout, nullptr, 0, true);
     if (rc) return rc;
     HIP3_TRY(hipEventRecord(c->ev[2], c->stream));
     HIP3_TRY(hipEventSynchronize(c->ev[2]));
@@ -613,7 +621,7 @@ int lbm3_step_timed(lbm3_ctx *c, int64_t n, lbm3_kernel_times *out) {
   }
   out->steps = n;
   out->lean_ms = c->n_lean ? lean / (double)n : 0.0;
-  out->general_ms = c->n_general ? gen / (double)n : 0.0;
+  out->general_ms = c->n_general + c->n_lean_src ? gen / (double)n : 0.0;
   out->lean_cells = c->lean_cells;
   out->general_cells = c->general_cells;
   out->step_ms = step / (double)n;
@@ -692,6 +700,7 @@ int lbm3_destroy(lbm3_ctx *c) {
   c->d_rec_id.release();
   c->d_xyz.release();
   c->d_lean.release();
+  c->d_lean_src.release();
   c->d_general.release();
   c->d_all.release();
   for (auto &e : c->ev)

@@ -55,13 +55,15 @@ struct Tile3Dev {
 // Launch of one pass over the tiles of a list. mode 0: a step (fin -> fout);
 // mode 1: the macroscopic fields of fin's time into out10 (dense
 // [10][nz][ny][nx]). general = false: the lean kernel, for tiles none of whose
-// pulled cells lies on a non-periodic face and which hold no source or
-// receiver cell; general = true: the kernel with every rule (mode 1 always).
-// tx: tile width, 64, or 128 for the lean FP32 steps in tiles of 2 or 6 rows
-// (hipErrorInvalidValue otherwise).
-int launch_step3(bool f64, bool general, int rows_y, int tx, const Tile3Dev *tiles, int ntiles,
-                 const void *fin, void *fout, void *out10, const Vol3Dev &v, int64_t t, int mode,
-                 hipStream_t s);
+// pulled cells lies on a non-periodic face and which hold no receiver cell;
+// with src = false their cells are also beyond every source's reach, with
+// src = true (mode 0 only) the lean kernel adds the sources' body force.
+// general = true: the kernel with every rule (mode 1 always; src must be
+// false). tx: tile width, 64, or 128 for the lean FP32 steps in tiles of 2 or
+// 6 rows (hipErrorInvalidValue otherwise).
+int launch_step3(bool f64, bool general, bool src, int rows_y, int tx, const Tile3Dev *tiles,
+                 int ntiles, const void *fin, void *fout, void *out10, const Vol3Dev &v, int64_t t,
+                 int mode, hipStream_t s);
 
 // kappa = b^2 (mu - lambda) / mu into the kappa plane. The count of cells
 // outside 0 <= nu < 1/2, mu > 0, rho > 0 (NaN included) is added to *bad

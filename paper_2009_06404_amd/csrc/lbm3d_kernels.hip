@@ -285,10 +285,12 @@ __device__ __forceinline__ real post3(int i, real f, const Coll3<real> &c, real 
 }
 
 // GENERAL = false: the lean kernel (no face rules, sources or receivers; the
-// host gives it only tiles that need none). MODE 1 (fields) is general only.
+// host gives it only tiles that need none); with SRC it adds the body force of
+// the sources (tiles clear of faces and receivers but near a source). MODE 1
+// (fields) is general only.
 // TX = 128 (lean FP32 tiles only): two wavefronts per row, so a workgroup
 // reads each population row of a plane as 512 contiguous bytes, not 256.
-template <typename real, int Q, int TY, int MODE, bool GENERAL, int TX = 64>
+template <typename real, int Q, int TY, int MODE, bool GENERAL, int TX = 64, bool SRC = GENERAL>
 __global__ void __launch_bounds__(TX * (TY + 2))
 step3_kernel(const real *__restrict__ fin, real *__restrict__ fout, real *__restrict__ out10,
              const Vol3Dev v, int64_t t, const Tile3Dev *__restrict__ tiles, int ntiles) {
@@ -413,7 +415,7 @@ step3_kernel(const real *__restrict__ fin, real *__restrict__ fout, real *__rest
       // source G = kappa grad(rho) + F (eq. S, Sec. 5)
       const real kap_c = v.kcells ? kap[((int64_t)z * ny + y) * pitch + x] : real(v.kscalar);
       real Gx = kap_c * gx, Gy = kap_c * gy, Gz = kap_c * gz;
-      for (int s = 0; s < (GENERAL ? v.nsrc : 0); ++s) {
+      for (int s = 0; s < (SRC ? v.nsrc : 0); ++s) {
         const Src3Dev sd = v.src[s];
         const double dz = min_image((double)z - sd.z, nz, zper);
         const double cut = 81.0 * sd.sigma * sd.sigma;
@@ -555,16 +557,23 @@ __global__ void pack3_kernel(const real *__restrict__ src, real *__restrict__ ds
 }
 
 template <typename real, int Q, int TY>
-hipError_t launch_tile(bool general, int tx, const Tile3Dev *tiles, int ntiles, const void *fin,
-                       void *fout, void *out10, const Vol3Dev &v, int64_t t, int mode, hipStream_t s) {
+hipError_t launch_tile(bool general, bool src, int tx, const Tile3Dev *tiles, int ntiles,
+                       const void *fin, void *fout, void *out10, const Vol3Dev &v, int64_t t,
+                       int mode, hipStream_t s) {
   if (ntiles <= 0) return hipSuccess;
+  if (general && src) return hipErrorInvalidValue;   // the general kernel always adds sources
   if (tx == 128) {
     // wide lean tiles: FP32 steps, 2 or 6 rows (at most 1024 lanes)
     if constexpr (sizeof(real) == 4 && TY != 14) {
       if (general || mode != 0) return hipErrorInvalidValue;
-      hipLaunchKernelGGL((step3_kernel<real, Q, TY, 0, false, 128>), dim3((ntiles + 7) / 8 * 8),
-                         dim3(128 * (TY + 2)), 0, s, reinterpret_cast<const real *>(fin),
-                         reinterpret_cast<real *>(fout), nullptr, v, t, tiles, ntiles);
+      if (src)
+        hipLaunchKernelGGL((step3_kernel<real, Q, TY, 0, false, 128, true>), dim3((ntiles + 7) / 8 * 8),
+                           dim3(128 * (TY + 2)), 0, s, reinterpret_cast<const real *>(fin),
+                           reinterpret_cast<real *>(fout), nullptr, v, t, tiles, ntiles);
+      else
+        hipLaunchKernelGGL((step3_kernel<real, Q, TY, 0, false, 128>), dim3((ntiles + 7) / 8 * 8),
+                           dim3(128 * (TY + 2)), 0, s, reinterpret_cast<const real *>(fin),
+                           reinterpret_cast<real *>(fout), nullptr, v, t, tiles, ntiles);
       return hipSuccess;
     }
     return hipErrorInvalidValue;
@@ -590,39 +599,48 @@ hipError_t launch_tile(bool general, int tx, const Tile3Dev *tiles, int ntiles, 
       return hipSuccess;
     }
   }
-  hipLaunchKernelGGL((step3_kernel<real, Q, TY, 0, false>), grid, block, 0, s, in, out, o10, v, t,
-                     tiles, ntiles);
+  if (mode != 0) return hipErrorInvalidValue;
+  if (src)
+    hipLaunchKernelGGL((step3_kernel<real, Q, TY, 0, false, 64, true>), grid, block, 0, s, in, out, o10,
+                       v, t, tiles, ntiles);
+  else
+    hipLaunchKernelGGL((step3_kernel<real, Q, TY, 0, false>), grid, block, 0, s, in, out, o10, v, t,
+                       tiles, ntiles);
   return hipSuccess;
 }
 
 template <typename real, int Q>
-hipError_t launch_rows(bool general, int rows_y, int tx, const Tile3Dev *tiles, int ntiles,
+hipError_t launch_rows(bool general, bool src, int rows_y, int tx, const Tile3Dev *tiles, int ntiles,
                        const void *fin, void *fout, void *out10, const Vol3Dev &v, int64_t t, int mode,
                        hipStream_t s) {
   if (rows_y == 2)
-    return launch_tile<real, Q, 2>(general, tx, tiles, ntiles, fin, fout, out10, v, t, mode, s);
+    return launch_tile<real, Q, 2>(general, src, tx, tiles, ntiles, fin, fout, out10, v, t, mode, s);
   if (rows_y == 14)
-    return launch_tile<real, Q, 14>(general, tx, tiles, ntiles, fin, fout, out10, v, t, mode, s);
-  return launch_tile<real, Q, 6>(general, tx, tiles, ntiles, fin, fout, out10, v, t, mode, s);
+    return launch_tile<real, Q, 14>(general, src, tx, tiles, ntiles, fin, fout, out10, v, t, mode, s);
+  return launch_tile<real, Q, 6>(general, src, tx, tiles, ntiles, fin, fout, out10, v, t, mode, s);
 }
 
 template <typename real>
-hipError_t launch_lattice(bool general, int rows_y, int tx, const Tile3Dev *tiles, int ntiles,
-                          const void *fin, void *fout, void *out10, const Vol3Dev &v, int64_t t,
-                          int mode, hipStream_t s) {
+hipError_t launch_lattice(bool general, bool src, int rows_y, int tx, const Tile3Dev *tiles,
+                          int ntiles, const void *fin, void *fout, void *out10, const Vol3Dev &v,
+                          int64_t t, int mode, hipStream_t s) {
   if (v.q == kQ27)
-    return launch_rows<real, kQ27>(general, rows_y, tx, tiles, ntiles, fin, fout, out10, v, t, mode, s);
-  return launch_rows<real, kQ19>(general, rows_y, tx, tiles, ntiles, fin, fout, out10, v, t, mode, s);
+    return launch_rows<real, kQ27>(general, src, rows_y, tx, tiles, ntiles, fin, fout, out10, v, t,
+                                   mode, s);
+  return launch_rows<real, kQ19>(general, src, rows_y, tx, tiles, ntiles, fin, fout, out10, v, t,
+                                 mode, s);
 }
 
 }  // namespace
 
-int launch_step3(bool f64, bool general, int rows_y, int tx, const Tile3Dev *tiles, int ntiles,
-                 const void *fin, void *fout, void *out10, const Vol3Dev &v, int64_t t, int mode,
-                 hipStream_t s) {
+int launch_step3(bool f64, bool general, bool src, int rows_y, int tx, const Tile3Dev *tiles,
+                 int ntiles, const void *fin, void *fout, void *out10, const Vol3Dev &v, int64_t t,
+                 int mode, hipStream_t s) {
   const hipError_t e =
-      f64 ? launch_lattice<double>(general, rows_y, tx, tiles, ntiles, fin, fout, out10, v, t, mode, s)
-          : launch_lattice<float>(general, rows_y, tx, tiles, ntiles, fin, fout, out10, v, t, mode, s);
+      f64 ? launch_lattice<double>(general, src, rows_y, tx, tiles, ntiles, fin, fout, out10, v, t,
+                                   mode, s)
+          : launch_lattice<float>(general, src, rows_y, tx, tiles, ntiles, fin, fout, out10, v, t,
+                                  mode, s);
   if (e != hipSuccess) return (int)e;
   return (int)hipGetLastError();
 }

@@ -29,6 +29,7 @@ sim.sim3_steps_checked.restype = C.c_longlong
 sim.sim3_lean_tiles.restype = C.c_longlong
 sim.sim3_general_tiles.restype = C.c_longlong
 sim.sim3_wide_launches.restype = C.c_longlong
+sim.sim3_lean_src_tiles.restype = C.c_longlong
 
 from workloads.problem import BC_FREE, BC_FREE0, BC_PERIODIC, BC_RIGID, default_sponge_profile  # noqa: E402
 from workloads.problem3 import Source3  # noqa: E402
@@ -134,6 +135,8 @@ for si, shape in enumerate(SHAPES):
             run(shape, faces, q, dtype, tile, srcs, recs)
             n += 1
 print(f"volumes {n}, steps checked {sim.sim3_steps_checked()}, lean tiles {sim.sim3_lean_tiles()}, "
-      f"general tiles {sim.sim3_general_tiles()}, 128-column launches {sim.sim3_wide_launches()}")
+      f"general tiles {sim.sim3_general_tiles()}, 128-column launches {sim.sim3_wide_launches()}, "
+      f"lean tiles near sources {sim.sim3_lean_src_tiles()}")
 assert sim.sim3_lean_tiles() > 0 and sim.sim3_general_tiles() > 0 and sim.sim3_wide_launches() > 0
+assert sim.sim3_lean_src_tiles() > 0, "no lean tile near a source was launched"
 print("ALL OK")

@@ -27,7 +27,8 @@ std::vector<int> g_cov;             // writes per cell of the pending step
 int g_nx = 0, g_ny = 0, g_nz = 0;
 bool g_pending = false;
 const void *g_pending_out = nullptr;
-long long g_steps_checked = 0, g_lean_tiles = 0, g_general_tiles = 0, g_wide_launches = 0;
+long long g_steps_checked = 0, g_lean_tiles = 0, g_general_tiles = 0, g_wide_launches = 0,
+          g_lean_src_tiles = 0;
 
 void fail(const char *msg) {
   fprintf(stderr, "stub3: %s\n", msg);
@@ -60,13 +61,15 @@ extern "C" long long sim3_steps_checked() {
 extern "C" long long sim3_lean_tiles() { return g_lean_tiles; }
 extern "C" long long sim3_general_tiles() { return g_general_tiles; }
 extern "C" long long sim3_wide_launches() { return g_wide_launches; }
+extern "C" long long sim3_lean_src_tiles() { return g_lean_src_tiles; }
 
 namespace lbm3 {
 
-int launch_step3(bool f64, bool general, int rows_y, int tw, const Tile3Dev *tiles, int ntiles,
-                 const void *fin, void *fout, void *out10, const Vol3Dev &v, int64_t t, int mode,
-                 hipStream_t) {
+int launch_step3(bool f64, bool general, bool src, int rows_y, int tw, const Tile3Dev *tiles,
+                 int ntiles, const void *fin, void *fout, void *out10, const Vol3Dev &v, int64_t t,
+                 int mode, hipStream_t) {
   if (ntiles <= 0) return 0;
+  if (src && (general || mode != 0)) fail("lean source launch outside lean steps");
   if (rows_y != 2 && rows_y != 6 && rows_y != 14) fail("rows_y");
   if (rows_y == 14 && (general || mode == 1)) fail("general or field tiles of 14 rows");
   if (tw != 64 && tw != 128) fail("tile width");
@@ -113,6 +116,7 @@ int launch_step3(bool f64, bool general, int rows_y, int tw, const Tile3Dev *til
     const int w = std::min(tw, nx - tl.x0), h = std::min(rows_y, ny - tl.y0);
     if (!general) {
       ++g_lean_tiles;
+      if (src) ++g_lean_src_tiles;
       if (!xper && (tl.x0 - 1 <= 0 || tl.x0 + w >= nx - 1)) fail("lean tile pulls an x-face cell");
       if (!yper && (tl.y0 - 1 <= 0 || tl.y0 + h >= ny - 1)) fail("lean tile pulls a y-face cell");
       if (!zper && (tl.z0 - 1 <= 0 || tl.z1 >= nz - 1)) fail("lean tile pulls a z-face cell");
@@ -121,7 +125,7 @@ int launch_step3(bool f64, bool general, int rows_y, int tw, const Tile3Dev *til
         const double c = 9.0 * q.sigma;
         const double gx = gap(q.x, tl.x0, tl.x0 + w, nx, xper), gy = gap(q.y, tl.y0, tl.y0 + h, ny, yper),
                      gz = gap(q.z, tl.z0, tl.z1, nz, zper);
-        if (gx * gx + gy * gy + gz * gz <= c * c) fail("lean tile within 9 sigma of a source");
+        if (!src && gx * gx + gy * gy + gz * gz <= c * c) fail("lean tile within 9 sigma of a source");
       }
       if (v.rec_row)
         for (int z = tl.z0; z < tl.z1; ++z)
