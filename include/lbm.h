@@ -134,8 +134,8 @@ typedef struct {
                          size: on contexts of 2048^2 cells and more the
                          three-step path (fuse_steps 3) launched directly
                          (graph_chunk 0), in 192-column blocks (tri_waves 3)
-                         of 96 rows on grids of 4096 rows and more and 32
-                         rows otherwise. */
+                         of 96 rows (92 in FP64) on grids of 4096 rows and
+                         more and 32 rows otherwise. */
   int32_t fuse_steps; /* steps per pass of the blocks when fuse_rows > 0: 2
                          (0 means 2) or 3. With 3 the steps run in triples:
                          blocks of 64 x tri_waves columns take

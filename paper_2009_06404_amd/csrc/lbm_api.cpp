@@ -463,9 +463,9 @@ void build_tiles(const lbm_ctx *c, int waves, int rows, bool split, std::vector<
 // Launch shape by size (measured on MI355X): large contexts take the
 // three-step path. Blocks of 192 columns (three output wavefronts beside the
 // halo wavefront: one wavefront in four carries the halo instead of one in
-// three), 96 rows high on grids of 4096 rows and more (4096^2 FP32: 182
-// GLUPS against 176 with 128-column blocks of 128 rows; 16384^2 203 against
-// 191; FP64 4096^2 90.3 against 81.6) and 32 rows on shorter grids (the 512
+// three), 96 rows high on grids of 4096 rows and more, 92 in FP64 (4096^2
+// FP32: 182 GLUPS against 176 with 128-column blocks of 128 rows; 16384^2
+// 203 against 191; FP64 4096^2 93.4 against 81.6) and 32 rows on shorter grids (the 512
 // batched grids of side 256..2048: 170 against 162). The triples are
 // launched directly: as fast as captured graphs or faster everywhere
 // measured, and at 4096^2 FP32 the graphs' node scheduling leaves the
@@ -483,7 +483,7 @@ lbm_launch default_launch(const lbm_ctx *c) {
   l.waves = 2;
   l.fuse_steps = 3;
   l.tri_waves = 3;
-  l.fuse_rows = max_ny >= 4096 ? 96 : 32;
+  l.fuse_rows = max_ny >= 4096 ? (c->dtype == LBM_F64 ? 92 : 96) : 32;
   l.graph_chunk = 0;
   if (cells < 2048 * 2048) {
     l.waves = 4;
